@@ -1,0 +1,1114 @@
+/*
+ * mcdi_oracle.c -- plain, slow, FP64 CPU oracle for the differentiable Monte
+ * Carlo direct-illumination estimator of Hasselgren, Hofmann & Munkberg,
+ * "Shape, Light, and Material Decomposition from Images using Monte Carlo
+ * Rendering and Denoising" (NeurIPS 2022).
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this file.  It shares no code, header,
+ * table or constant generator with the HIP library; the only thing both sides
+ * consume is the seeded synthetic input.
+ *
+ * What it computes, in the paper's order (section 3.1 "Direct Illumination",
+ * section 4.1 "Multiple Importance Sampling", appendix A "Optimization and
+ * Regularization" for the visibility term H, appendix D "Sampling"):
+ *   - the rendering equation restricted to direct light from an environment
+ *     probe, estimated by Monte Carlo with shadow rays (section 3.1);
+ *   - three sampling techniques combined with the balance heuristic: a
+ *     piecewise-constant 2D distribution over the probe, cosine sampling of the
+ *     diffuse lobe and visible-normal sampling of the GGX lobe (section 4.1);
+ *   - detached sampling and detached visibility: gradients flow only through
+ *     the material evaluation (section 3.1 "Shadow gradients", section 4.1);
+ *   - the same random numbers are replayed in the backward pass (section 4.1,
+ *     appendix D);
+ *   - diffuse lighting is returned demodulated, specular is not (section 4.2);
+ *   - shadowed samples are weighted by H = 1 - tau (appendix A).
+ * Readings of points the paper leaves open (probe parameterisation, lobe
+ * selection probability, GGX details, ray offsets, RNG) are listed in the
+ * design notes and are identical on both sides.
+ *
+ * Everything here is FP64 except two discrete decisions that the HIP kernel
+ * takes in FP32 and that the oracle therefore also takes in FP32: the
+ * lobe-selection probability q and the roughness clamp.  The probe's sampling
+ * tables are FP64 sums rounded once to FP32, because the tables themselves are
+ * an output that both sides must agree on bit for bit.
+ *
+ * Parity unpinned: nothing; every function is pinned by a test against a
+ * closed form, a library routine, a quadrature or a brute-force evaluation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based RNG: Philox4x32-10 (Salmon, Moraes, Dror, Shaw; SC 2011).   */
+/* Ten rounds of two 32x32->64 multiplies and a key schedule (Weyl sequence).*/
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 24 high bits of a 32-bit word as a uniform number in [0, 1). Exact. */
+static double u01(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+/* The eight uniforms of sample s of a pixel: two Philox blocks keyed by the
+ * 64-bit seed, with counter (pixel in view, global view id, s, block). */
+static void sample_uniforms(uint64_t seed, uint32_t pix_in_view, uint32_t view_id,
+                            uint32_t s, double xi[8])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t c[4] = {pix_in_view, view_id, s, 0u}, o[4];
+    orc_philox4x32_10(c, key, o);
+    for (int k = 0; k < 4; ++k) xi[k] = u01(o[k]);
+    c[3] = 1u;
+    orc_philox4x32_10(c, key, o);
+    for (int k = 0; k < 4; ++k) xi[4 + k] = u01(o[k]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Piecewise-constant 2D distribution over the lat-long probe (section 4.1,  */
+/* appendix D: light importance sampling).  Row i covers polar angle         */
+/* [i, i+1) * pi/H measured from +Y, column j covers azimuth [j, j+1)*2pi/W. */
+/* Texel weight = luminance (r+g+b)/3 (clamped at 0) times sin(theta) at the */
+/* row centre.                                                               */
+/* ------------------------------------------------------------------------ */
+static double texel_weight(const float* env, int W, int i, int j, double sin_row)
+{
+    const float* t = env + ((size_t)i * W + j) * 3;
+    double y = ((double)t[0] + (double)t[1] + (double)t[2]) / 3.0;
+    if (!(y > 0.0) || !isfinite(y)) y = 0.0;
+    return y * sin_row;
+}
+
+/* Tables: cond [H][W+1] (per-row CDF), marg [H+1] (marginal CDF over rows),
+ * pdf [H][W] = (w_ij / sum w) * W * H, the density in (u, v) of texel (i,j).
+ * Sums run left to right in FP64; each entry is rounded once to FP32.
+ * Returns 1 if the total weight is positive (light sampling enabled). */
+int orc_env_tables(const float* env, int H, int W, float* cond, float* marg, float* pdf,
+                   double* total_out)
+{
+    double* rowsum = (double*)malloc(sizeof(double) * (size_t)H);
+    for (int i = 0; i < H; ++i) {
+        double srow = sin(ORC_PI * ((double)i + 0.5) / (double)H);
+        double run = 0.0;
+        for (int j = 0; j < W; ++j) run += texel_weight(env, W, i, j, srow);
+        rowsum[i] = run;
+        float* c = cond + (size_t)i * (W + 1);
+        double prefix = 0.0;
+        c[0] = 0.0f;
+        for (int j = 0; j + 1 < W; ++j) {
+            prefix += texel_weight(env, W, i, j, srow);
+            c[j + 1] = run > 0.0 ? (float)(prefix / run) : (float)((double)(j + 1) / (double)W);
+        }
+        c[W] = 1.0f;
+    }
+    double total = 0.0;
+    for (int i = 0; i < H; ++i) total += rowsum[i];
+    double prefix = 0.0;
+    marg[0] = 0.0f;
+    for (int i = 0; i + 1 < H; ++i) {
+        prefix += rowsum[i];
+        marg[i + 1] = total > 0.0 ? (float)(prefix / total) : (float)((double)(i + 1) / (double)H);
+    }
+    marg[H] = 1.0f;
+    for (int i = 0; i < H; ++i) {
+        double srow = sin(ORC_PI * ((double)i + 0.5) / (double)H);
+        for (int j = 0; j < W; ++j) {
+            double w = texel_weight(env, W, i, j, srow);
+            pdf[(size_t)i * W + j] = total > 0.0 ? (float)((w / total) * ((double)W * (double)H)) : 0.0f;
+        }
+    }
+    free(rowsum);
+    if (total_out) *total_out = total;
+    return total > 0.0;
+}
+
+/* Largest k in [0, n-1] with cdf[k] <= x (cdf[0] = 0 <= x < 1 = cdf[n]).
+ * Zero-width bins are skipped because a later equal entry also qualifies. */
+static int cdf_search(const float* cdf, int n, double x)
+{
+    int k = 0;
+    for (int i = 1; i < n; ++i)
+        if ((double)cdf[i] <= x) k = i;
+    return k;
+}
+
+typedef struct {
+    int32_t H, W;
+    const float* env;   /* [H][W][3] radiance used for shading */
+    const float* cond;  /* [H][W+1] */
+    const float* marg;  /* [H+1] */
+    const float* pdf;   /* [H][W] */
+    int32_t light_enabled;
+} orc_env;
+
+/* Direction of (u, v) in [0,1)^2: theta = pi v from +Y, phi = 2 pi u. */
+static void dir_of_uv(double u, double v, double w[3])
+{
+    double th = ORC_PI * v, ph = 2.0 * ORC_PI * u;
+    w[0] = sin(th) * cos(ph);
+    w[1] = cos(th);
+    w[2] = sin(th) * sin(ph);
+}
+
+/* Sample the probe: returns texel (i, j), the direction and its solid-angle
+ * density p = pdf_uv / (2 pi^2 sin theta). */
+void orc_sample_light(const orc_env* e, double xi0, double xi1, double w[3], double* p,
+                      int32_t* ti, int32_t* tj)
+{
+    int H = e->H, W = e->W;
+    int i = cdf_search(e->marg, H, xi0);
+    const float* c = e->cond + (size_t)i * (W + 1);
+    int j = cdf_search(c, W, xi1);
+    double dv = (xi0 - (double)e->marg[i]) / ((double)e->marg[i + 1] - (double)e->marg[i]);
+    double du = (xi1 - (double)c[j]) / ((double)c[j + 1] - (double)c[j]);
+    double v = ((double)i + dv) / (double)H, u = ((double)j + du) / (double)W;
+    dir_of_uv(u, v, w);
+    double st = sin(ORC_PI * v);
+    *p = st > 0.0 ? (double)e->pdf[(size_t)i * W + j] / (2.0 * ORC_PI * ORC_PI * st) : 0.0;
+    *ti = i;
+    *tj = j;
+}
+
+/* Texel of a unit direction (nearest lookup) and the angular distance, in
+ * radians of arc, to the closest texel boundary that would change it. */
+static void texel_of_dir(int H, int W, const double w[3], int* ti, int* tj, double* margin)
+{
+    double rho = sqrt(w[0] * w[0] + w[2] * w[2]);
+    double th = atan2(rho, w[1]);
+    double ph = atan2(w[2], w[0]);
+    if (ph < 0.0) ph += 2.0 * ORC_PI;
+    double fi = th * (double)H / ORC_PI, fj = ph * (double)W / (2.0 * ORC_PI);
+    int i = (int)floor(fi), j = (int)floor(fj);
+    if (i > H - 1) i = H - 1;
+    if (i < 0) i = 0;
+    if (j > W - 1) j = W - 1;
+    if (j < 0) j = 0;
+    double m = INFINITY;
+    /* interior row boundaries 1..H-1 */
+    double ri = floor(fi + 0.5);
+    if (ri >= 1.0 && ri <= (double)(H - 1)) m = fmin(m, fabs(fi - ri) * ORC_PI / (double)H);
+    /* column boundaries 0..W (0 and W are the same seam) */
+    double rj = floor(fj + 0.5);
+    m = fmin(m, fabs(fj - rj) * 2.0 * ORC_PI / (double)W * rho);
+    *ti = i;
+    *tj = j;
+    *margin = m;
+}
+
+/* Solid-angle density of the light technique at a direction. */
+double orc_pdf_light(const orc_env* e, const double w[3])
+{
+    if (!e->light_enabled) return 0.0;
+    int i, j;
+    double m;
+    texel_of_dir(e->H, e->W, w, &i, &j, &m);
+    double rho = sqrt(w[0] * w[0] + w[2] * w[2]);
+    return rho > 0.0 ? (double)e->pdf[(size_t)i * e->W + j] / (2.0 * ORC_PI * ORC_PI * rho) : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Vectors                                                                    */
+/* ------------------------------------------------------------------------ */
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double norm3(const double a[3]) { return sqrt(dot3(a, a)); }
+
+/* Orthonormal basis (t, b) around unit n, branch-free construction of Duff
+ * et al. (JCGT 2017).  `sgn` is the sign of n_z as given by the caller. */
+static void onb(const double n[3], double sgn, double t[3], double b[3])
+{
+    double a = -1.0 / (sgn + n[2]);
+    double bb = n[0] * n[1] * a;
+    t[0] = 1.0 + sgn * n[0] * n[0] * a;
+    t[1] = sgn * bb;
+    t[2] = -sgn * n[0];
+    b[0] = bb;
+    b[1] = sgn + n[1] * n[1] * a;
+    b[2] = -n[1];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Material model (section 3): a diffuse term plus an isotropic GGX specular */
+/* lobe (Walter et al. 2007).  alpha = roughness^2, Smith height-correlated  */
+/* masking-shadowing, Schlick Fresnel with F0 = lerp(0.04, kd, metallic).    */
+/* ------------------------------------------------------------------------ */
+
+/* GGX normal distribution written with s2 = |n x h|^2 for 1 - (n.h)^2. */
+double orc_ggx_D(double noh, double s2, double alpha)
+{
+    if (!(noh > 0.0)) return 0.0;
+    double a2 = alpha * alpha;
+    double den = a2 * noh * noh + s2;
+    return a2 / (ORC_PI * den * den);
+}
+
+/* Smith Lambda for GGX at cos = x > 0. */
+double orc_ggx_lambda(double x, double alpha)
+{
+    double t2 = (1.0 - x * x) / (x * x);
+    return 0.5 * (-1.0 + sqrt(1.0 + alpha * alpha * t2));
+}
+
+static double lambda_dalpha(double x, double alpha)
+{
+    double t2 = (1.0 - x * x) / (x * x);
+    return alpha * t2 / (2.0 * sqrt(1.0 + alpha * alpha * t2));
+}
+
+static double lambda_dx(double x, double alpha)
+{
+    double a2 = alpha * alpha;
+    return -a2 / (2.0 * x * x * x * sqrt(1.0 + a2 * (1.0 / (x * x) - 1.0)));
+}
+
+/* Density of visible-normal sampling after reflection about h (Heitz 2018):
+ * G1(wo) D(h) / (4 n.wo), in local coordinates (z = normal). */
+double orc_pdf_ggx_local(const double V[3], const double L[3], double alpha)
+{
+    if (!(V[2] > 0.0)) return 0.0;
+    double h[3] = {V[0] + L[0], V[1] + L[1], V[2] + L[2]};
+    double hl = norm3(h);
+    if (!(hl > 0.0)) return 0.0;
+    for (int k = 0; k < 3; ++k) h[k] /= hl;
+    double s2 = h[0] * h[0] + h[1] * h[1];
+    double D = orc_ggx_D(h[2], s2, alpha);
+    double G1 = 1.0 / (1.0 + orc_ggx_lambda(V[2], alpha));
+    return G1 * D / (4.0 * V[2]);
+}
+
+double orc_pdf_cos_local(const double L[3]) { return L[2] > 0.0 ? L[2] / ORC_PI : 0.0; }
+
+/* Cosine-weighted hemisphere sample, polar mapping. */
+void orc_sample_cos_local(double u1, double u2, double L[3])
+{
+    double r = sqrt(u1), ph = 2.0 * ORC_PI * u2;
+    L[0] = r * cos(ph);
+    L[1] = r * sin(ph);
+    L[2] = sqrt(fmax(0.0, 1.0 - u1));
+}
+
+/* Visible-normal sampling of GGX (Heitz, JCGT 2018): stretch the view vector,
+ * sample the projected visible hemisphere, un-stretch the normal, reflect.
+ * Returns lensq of the stretched view's tangential part (the degenerate-frame
+ * decision). */
+double orc_sample_vndf_local(const double V[3], double alpha, double u1, double u2, double L[3])
+{
+    double vh[3] = {alpha * V[0], alpha * V[1], V[2]};
+    double l = norm3(vh);
+    for (int k = 0; k < 3; ++k) vh[k] /= l;
+    double lensq = vh[0] * vh[0] + vh[1] * vh[1];
+    double T1[3], T2[3];
+    if (lensq > 0.0) {
+        double il = 1.0 / sqrt(lensq);
+        T1[0] = -vh[1] * il;
+        T1[1] = vh[0] * il;
+        T1[2] = 0.0;
+    } else {
+        T1[0] = 1.0; T1[1] = 0.0; T1[2] = 0.0;
+    }
+    cross3(vh, T1, T2);
+    double r = sqrt(u1), ph = 2.0 * ORC_PI * u2;
+    double t1 = r * cos(ph), t2 = r * sin(ph);
+    double s = 0.5 * (1.0 + vh[2]);
+    t2 = (1.0 - s) * sqrt(fmax(0.0, 1.0 - t1 * t1)) + s * t2;
+    double tz = sqrt(fmax(0.0, 1.0 - t1 * t1 - t2 * t2));
+    double nh[3];
+    for (int k = 0; k < 3; ++k) nh[k] = t1 * T1[k] + t2 * T2[k] + tz * vh[k];
+    double ne[3] = {alpha * nh[0], alpha * nh[1], fmax(0.0, nh[2])};
+    double nl = norm3(ne);
+    for (int k = 0; k < 3; ++k) ne[k] /= nl;
+    double vn = dot3(V, ne);
+    for (int k = 0; k < 3; ++k) L[k] = 2.0 * vn * ne[k] - V[k];
+    return lensq;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Shadow-ray visibility (section 3.1): any triangle hit along the ray from  */
+/* o in direction d, t in (0, inf), no back-face culling.  Evaluated in FP64 */
+/* with a margin: each answer is classified as robust (every ray within the  */
+/* tolerance gives the same answer) or undecided.                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double lo[3], hi[3];
+    int32_t left, right; /* children, -1 for a leaf */
+    int32_t start, count;
+} onode;
+
+typedef struct {
+    int64_t ntri;
+    double* v;        /* [ntri][9] vertex coordinates */
+    int32_t* order;   /* triangle order in leaves */
+    onode* nodes;
+    int64_t nnodes;
+    double center[3];
+    double diag;
+} orc_scene;
+
+static void tri_bounds(const double* t, double lo[3], double hi[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = fmin(t[k], fmin(t[3 + k], t[6 + k]));
+        hi[k] = fmax(t[k], fmax(t[3 + k], t[6 + k]));
+    }
+}
+
+static double centroid(const double* t, int axis) { return (t[axis] + t[3 + axis] + t[6 + axis]) / 3.0; }
+
+/* Median-free object partition at the midpoint of the centroid bounds along
+ * the longest axis; a range that cannot be split that way is cut in half. */
+static int32_t build_node(orc_scene* s, int32_t start, int32_t count)
+{
+    int32_t id = (int32_t)s->nnodes++;
+    onode* nd = &s->nodes[id];
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = 0; k < 3; ++k) { nd->lo[k] = INFINITY; nd->hi[k] = -INFINITY; }
+    for (int32_t q = start; q < start + count; ++q) {
+        const double* t = s->v + (size_t)s->order[q] * 9;
+        double lo[3], hi[3];
+        tri_bounds(t, lo, hi);
+        for (int k = 0; k < 3; ++k) {
+            nd->lo[k] = fmin(nd->lo[k], lo[k]);
+            nd->hi[k] = fmax(nd->hi[k], hi[k]);
+            double c = centroid(t, k);
+            clo[k] = fmin(clo[k], c);
+            chi[k] = fmax(chi[k], c);
+        }
+    }
+    if (count <= 4) {
+        nd->left = nd->right = -1;
+        nd->start = start;
+        nd->count = count;
+        return id;
+    }
+    int axis = 0;
+    for (int k = 1; k < 3; ++k)
+        if (chi[k] - clo[k] > chi[axis] - clo[axis]) axis = k;
+    double mid = 0.5 * (clo[axis] + chi[axis]);
+    int32_t i = start, j = start + count - 1;
+    while (i <= j) {
+        if (centroid(s->v + (size_t)s->order[i] * 9, axis) < mid) {
+            ++i;
+        } else {
+            int32_t tmp = s->order[i];
+            s->order[i] = s->order[j];
+            s->order[j] = tmp;
+            --j;
+        }
+    }
+    int32_t nleft = i - start;
+    if (nleft == 0 || nleft == count) nleft = count / 2;
+    int32_t l = build_node(s, start, nleft);
+    int32_t r = build_node(s, start + nleft, count - nleft);
+    nd = &s->nodes[id];
+    nd->left = l;
+    nd->right = r;
+    nd->start = start;
+    nd->count = 0;
+    return id;
+}
+
+orc_scene* orc_scene_build(const float* verts, int64_t nv, const int32_t* tris, int64_t nt)
+{
+    orc_scene* s = (orc_scene*)calloc(1, sizeof(orc_scene));
+    s->ntri = nt;
+    s->v = (double*)malloc(sizeof(double) * 9 * (size_t)(nt > 0 ? nt : 1));
+    s->order = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nt > 0 ? nt : 1));
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t f = 0; f < nt; ++f) {
+        for (int c = 0; c < 3; ++c) {
+            int32_t vi = tris[f * 3 + c];
+            for (int k = 0; k < 3; ++k) {
+                double x = (vi >= 0 && vi < nv) ? (double)verts[(size_t)vi * 3 + k] : 0.0;
+                s->v[f * 9 + c * 3 + k] = x;
+                lo[k] = fmin(lo[k], x);
+                hi[k] = fmax(hi[k], x);
+            }
+        }
+        s->order[f] = (int32_t)f;
+    }
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        s->center[k] = nt > 0 ? 0.5 * (lo[k] + hi[k]) : 0.0;
+        d2 += nt > 0 ? (hi[k] - lo[k]) * (hi[k] - lo[k]) : 0.0;
+    }
+    s->diag = sqrt(d2);
+    s->nodes = (onode*)malloc(sizeof(onode) * (size_t)(2 * (nt > 0 ? nt : 1)));
+    s->nnodes = 0;
+    if (nt > 0) build_node(s, 0, (int32_t)nt);
+    return s;
+}
+
+void orc_scene_free(orc_scene* s)
+{
+    if (!s) return;
+    free(s->v);
+    free(s->order);
+    free(s->nodes);
+    free(s);
+}
+
+enum { TRI_MISS = 0, TRI_HIT = 1, TRI_NEAR = 2 };
+
+/* Distance from the 2D origin to segment a-b. */
+static double seg_dist(const double a[2], const double b[2])
+{
+    double ab[2] = {b[0] - a[0], b[1] - a[1]};
+    double l2 = ab[0] * ab[0] + ab[1] * ab[1];
+    double t = l2 > 0.0 ? -(a[0] * ab[0] + a[1] * ab[1]) / l2 : 0.0;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    double x = a[0] + t * ab[0], y = a[1] + t * ab[1];
+    return sqrt(x * x + y * y);
+}
+
+/* Classify one triangle against the ray (o, d) with basis (e1, e2) spanning
+ * the plane orthogonal to d.  Vertices are projected on that plane; the ray
+ * hits iff the origin lies inside the projected triangle and the hit
+ * distance along d is positive.  delta_abs/delta_rel give the tolerance. */
+static int classify_tri(const double* tv, const double o[3], const double d[3],
+                        const double e1[3], const double e2[3], double delta_abs, double delta_rel)
+{
+    double P[3][2], tk[3];
+    double tmaxabs = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double q[3] = {tv[c * 3] - o[0], tv[c * 3 + 1] - o[1], tv[c * 3 + 2] - o[2]};
+        P[c][0] = dot3(q, e1);
+        P[c][1] = dot3(q, e2);
+        tk[c] = dot3(q, d);
+        tmaxabs = fmax(tmaxabs, fabs(tk[c]));
+    }
+    double delta = delta_abs + delta_rel * tmaxabs;
+    double E0 = P[1][0] * P[2][1] - P[1][1] * P[2][0];
+    double E1 = P[2][0] * P[0][1] - P[2][1] * P[0][0];
+    double E2 = P[0][0] * P[1][1] - P[0][1] * P[1][0];
+    double A = E0 + E1 + E2;
+    int inside = (A > 0.0 && E0 > 0.0 && E1 > 0.0 && E2 > 0.0) ||
+                 (A < 0.0 && E0 < 0.0 && E1 < 0.0 && E2 < 0.0);
+    double bd = fmin(seg_dist(P[0], P[1]), fmin(seg_dist(P[1], P[2]), seg_dist(P[2], P[0])));
+    double tmax = fmax(tk[0], fmax(tk[1], tk[2]));
+    if (inside && bd > delta) {
+        double t = (E0 * tk[0] + E1 * tk[1] + E2 * tk[2]) / A;
+        if (t > delta) return TRI_HIT;
+        if (t < -delta) return TRI_MISS;
+        return TRI_NEAR;
+    }
+    if (!inside && bd > delta) return TRI_MISS;
+    if (tmax < -delta) return TRI_MISS;
+    return TRI_NEAR;
+}
+
+/* Does the whole line o + t d (any t) meet the box grown by pad?  The line,
+ * not the ray, so that the candidate set covers every triangle the
+ * classification can call hit or undecided. */
+static int box_hit_padded(const onode* nd, const double o[3], const double d[3], double pad)
+{
+    double t0 = -INFINITY, t1 = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        double lo = nd->lo[k] - pad, hi = nd->hi[k] + pad;
+        if (fabs(d[k]) < 1e-300) {
+            if (o[k] < lo || o[k] > hi) return 0;
+            continue;
+        }
+        double a = (lo - o[k]) / d[k], b = (hi - o[k]) / d[k];
+        if (a > b) { double x = a; a = b; b = x; }
+        t0 = fmax(t0, a);
+        t1 = fmin(t1, b);
+        if (t0 > t1) return 0;
+    }
+    return 1;
+}
+
+/* Any-hit query.  Returns TRI_HIT if some triangle is hit robustly, TRI_MISS
+ * if every triangle is missed robustly, TRI_NEAR otherwise.  brute != 0 tests
+ * every triangle; otherwise the BVH, with boxes padded by the tolerance at the
+ * farthest distance any scene point can be, so it never skips a triangle the
+ * brute-force loop would classify as hit or near. */
+int orc_anyhit(const orc_scene* s, const double o[3], const double d_in[3], double delta_abs,
+               double delta_rel, int brute)
+{
+    if (s->ntri == 0) return TRI_MISS;
+    double dl = norm3(d_in);
+    double d[3] = {d_in[0] / dl, d_in[1] / dl, d_in[2] / dl};
+    double e1[3], e2[3];
+    onb(d, d[2] >= 0.0 ? 1.0 : -1.0, e1, e2);
+    int near = 0;
+    if (brute) {
+        for (int64_t f = 0; f < s->ntri; ++f) {
+            int r = classify_tri(s->v + f * 9, o, d, e1, e2, delta_abs, delta_rel);
+            if (r == TRI_HIT) return TRI_HIT;
+            if (r == TRI_NEAR) near = 1;
+        }
+        return near ? TRI_NEAR : TRI_MISS;
+    }
+    double oc[3] = {o[0] - s->center[0], o[1] - s->center[1], o[2] - s->center[2]};
+    double tfar = norm3(oc) + 0.5 * s->diag;
+    double pad = delta_abs + delta_rel * tfar;
+    int32_t stack[256];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const onode* nd = &s->nodes[stack[--sp]];
+        if (!box_hit_padded(nd, o, d, pad)) continue;
+        if (nd->left < 0) {
+            for (int32_t q = nd->start; q < nd->start + nd->count; ++q) {
+                int r = classify_tri(s->v + (size_t)s->order[q] * 9, o, d, e1, e2, delta_abs, delta_rel);
+                if (r == TRI_HIT) return TRI_HIT;
+                if (r == TRI_NEAR) near = 1;
+            }
+        } else {
+            stack[sp++] = nd->right;
+            stack[sp++] = nd->left;
+        }
+    }
+    return near ? TRI_NEAR : TRI_MISS;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The estimator                                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_views, height, width, view_base;
+    const float *pos, *nrm, *kd, *korm; /* [3][N] planar; korm = (occlusion, roughness, metallic) */
+    const uint8_t* mask;                /* [N] */
+    const float* eye;                   /* [n_views][3] */
+} orc_gbuffer;
+
+typedef struct {
+    int32_t spp;
+    uint32_t flags;
+    uint64_t seed;
+    double tau;
+    double ray_eps;
+    double delta_vis_abs, delta_vis_rel; /* visibility tolerance (world units, x t) */
+    double delta_ang;                    /* texel-boundary tolerance, radians of arc */
+    double delta_cos;                    /* tolerance on n.v / n.l sign decisions */
+    int32_t brute;                       /* all-triangle visibility instead of the BVH */
+} orc_params;
+
+/* flags: debug techniques (white-furnace style checks) */
+#define ORC_LIGHT_OFF 1u  /* no light sample and p_light == 0 */
+#define ORC_FORCE_COS 2u  /* q = 1: the BSDF technique is pure cosine */
+
+/* decision record flag bits (shared meaning with the HIP debug dump) */
+#define DEC_LOBE_COS   (1u << 0)
+#define DEC_L_CULL     (1u << 1)
+#define DEC_B_CULL     (1u << 2)
+#define DEC_L_TRACED   (1u << 3)
+#define DEC_B_TRACED   (1u << 4)
+#define DEC_L_HIT      (1u << 5)
+#define DEC_B_HIT      (1u << 6)
+#define DEC_NOV_POS    (1u << 7)
+#define DEC_VALID      (1u << 8)
+#define DEC_NONE       0xFFFFFFFFu
+
+#define R_MIN_F 0.08f
+
+typedef struct {
+    int valid;
+    double p[3], n[3], nlen, V[3], NoV;
+    int nov_pos;
+    double t[3], b[3];
+    double kd[3], r, m, alpha, F0[3];
+    float qf;
+    int r_active; /* roughness above the clamp: d alpha / d r = 2 r */
+} pix_setup;
+
+static int setup_pixel(const orc_gbuffer* g, int64_t pix, pix_setup* S, int* nonfinite)
+{
+    int64_t N = (int64_t)g->n_views * g->height * g->width;
+    memset(S, 0, sizeof(*S));
+    *nonfinite = 0;
+    if (!g->mask[pix]) return 0;
+    int v = (int)(pix / ((int64_t)g->height * g->width));
+    float raw[12], eyef[3];
+    for (int k = 0; k < 3; ++k) {
+        raw[k] = g->pos[k * N + pix];
+        raw[3 + k] = g->nrm[k * N + pix];
+        raw[6 + k] = g->kd[k * N + pix];
+        raw[9 + k] = g->korm[k * N + pix];
+        eyef[k] = g->eye[v * 3 + k];
+    }
+    for (int k = 0; k < 12; ++k) if (!isfinite(raw[k])) { *nonfinite = 1; return 0; }
+    for (int k = 0; k < 3; ++k) if (!isfinite(eyef[k])) { *nonfinite = 1; return 0; }
+    if (raw[3] == 0.0f && raw[4] == 0.0f && raw[5] == 0.0f) return 0;
+    double wv[3];
+    for (int k = 0; k < 3; ++k) {
+        S->p[k] = raw[k];
+        wv[k] = (double)eyef[k] - (double)raw[k];
+    }
+    if (wv[0] == 0.0 && wv[1] == 0.0 && wv[2] == 0.0) return 0;
+    double nr[3] = {raw[3], raw[4], raw[5]};
+    S->nlen = norm3(nr);
+    for (int k = 0; k < 3; ++k) S->n[k] = nr[k] / S->nlen;
+    double vl = norm3(wv);
+    for (int k = 0; k < 3; ++k) S->V[k] = wv[k] / vl;
+    S->NoV = dot3(S->n, S->V);
+    S->nov_pos = S->NoV > 0.0;
+    onb(S->n, signbit(raw[5]) ? -1.0 : 1.0, S->t, S->b);
+    for (int k = 0; k < 3; ++k) S->kd[k] = raw[6 + k];
+    S->r = raw[10];
+    S->m = raw[11];
+    S->r_active = raw[10] > R_MIN_F;
+    double rc = S->r_active ? (double)raw[10] : (double)R_MIN_F;
+    S->alpha = rc * rc;
+    for (int k = 0; k < 3; ++k) S->F0[k] = 0.04 * (1.0 - S->m) + S->kd[k] * S->m;
+    S->valid = 1;
+    return 1;
+}
+
+/* Lobe-selection probability, an FP32 decision on both sides. */
+static float lobe_q(const pix_setup* S, float m_f, uint32_t flags)
+{
+    volatile float one_minus = 1.0f - m_f;
+    float q = 0.5f * one_minus;
+    if (q < 0.0f) q = 0.0f;
+    if (q > 1.0f) q = 1.0f;
+    if (!S->nov_pos || (flags & ORC_FORCE_COS)) q = 1.0f;
+    return q;
+}
+
+typedef struct {
+    /* outputs of one pixel */
+    double cd[3], cs[3];
+    double gkd[3], gr, gm, gn[3];
+    uint32_t hitbits[32]; /* 2 bits per sample, spp <= 512 */
+    int n_synced, n_flag, n_hard;
+} pix_out;
+
+typedef struct {
+    int32_t texel;
+    double coef[3];
+    double absc[3];
+} env_contrib;
+
+/* Per-sample evaluation at direction w.  `Ss` drives sampling-side
+ * quantities (P, q, ray origin); `Se` the differentiated integrand. */
+static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, const double w[3],
+                        double pL, const float* Lrad, int spp, double Hv, int grad,
+                        const double* Ud, const double* Us, pix_out* out, env_contrib* ec,
+                        int unit_pdf)
+{
+    double NoL = dot3(Se->n, w);
+    double h[3] = {Se->V[0] + w[0], Se->V[1] + w[1], Se->V[2] + w[2]};
+    double hl = norm3(h);
+    for (int k = 0; k < 3; ++k) h[k] /= hl;
+    /* sampling-side density (detached) */
+    double NoLs = dot3(Ss->n, w);
+    double hs[3] = {Ss->V[0] + w[0], Ss->V[1] + w[1], Ss->V[2] + w[2]};
+    double hsl = norm3(hs);
+    for (int k = 0; k < 3; ++k) hs[k] /= hsl;
+    double nxh[3];
+    cross3(Ss->n, hs, nxh);
+    double q = (double)qf;
+    double pcos = NoLs > 0.0 ? NoLs / ORC_PI : 0.0;
+    double pggx = 0.0;
+    if (Ss->nov_pos) {
+        double Ds = orc_ggx_D(dot3(Ss->n, hs), dot3(nxh, nxh), Ss->alpha);
+        pggx = Ds / (1.0 + orc_ggx_lambda(Ss->NoV, Ss->alpha)) / (4.0 * Ss->NoV);
+    }
+    double P = unit_pdf ? 1.0 : pL + q * pcos + (1.0 - q) * pggx;
+    double K = Hv / (P * (double)spp);
+    /* diffuse, demodulated (kd applied outside): (1-m)/pi * NoL * L */
+    double kdiff = (1.0 - Se->m) / ORC_PI * NoL * K;
+    /* specular: F D G2 / (4 NoV) * L, NoL cancelled */
+    double S = 0.0, Fw = 0.0, dSdr = 0.0, dSdNoV = 0.0, dSdNoL = 0.0, dSdNoH = 0.0;
+    double F[3] = {0, 0, 0};
+    int spec = Ss->nov_pos;
+    if (spec) {
+        double a = Se->alpha, NoV = Se->NoV, NoH = dot3(Se->n, h), VoH = dot3(Se->V, h);
+        cross3(Se->n, h, nxh);
+        double s2 = dot3(nxh, nxh);
+        double D = orc_ggx_D(NoH, s2, a);
+        double LV = orc_ggx_lambda(NoV, a), LL = orc_ggx_lambda(NoL, a);
+        double G2 = 1.0 / (1.0 + LV + LL);
+        S = D * G2 / (4.0 * NoV);
+        double omv = 1.0 - VoH;
+        Fw = omv * omv * omv * omv * omv;
+        for (int c = 0; c < 3; ++c) F[c] = Se->F0[c] + (1.0 - Se->F0[c]) * Fw;
+        if (grad) {
+            double B = a * a * NoH * NoH + s2;
+            double dDda = D * (2.0 / a - 4.0 * a * NoH * NoH / B);
+            double dG2da = -G2 * G2 * (lambda_dalpha(NoV, a) + lambda_dalpha(NoL, a));
+            double dSda = (dDda * G2 + D * dG2da) / (4.0 * NoV);
+            dSdr = Se->r_active ? dSda * 2.0 * Se->r : 0.0;
+            double dDdc = D * 4.0 * (1.0 - a * a) * NoH / B;
+            double dG2dV = -G2 * G2 * lambda_dx(NoV, a);
+            double dG2dL = -G2 * G2 * lambda_dx(NoL, a);
+            dSdNoV = D * dG2dV / (4.0 * NoV) - S / NoV;
+            dSdNoL = D * dG2dL / (4.0 * NoV);
+            dSdNoH = dDdc * G2 / (4.0 * NoV);
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        double L = (double)Lrad[c];
+        out->cd[c] += kdiff * L;
+        out->cs[c] += F[c] * S * L * K;
+    }
+    if (!grad) return;
+    double gnd = 0.0, gns = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double L = (double)Lrad[c];
+        double cdc = kdiff, csc = F[c] * S * K; /* coefficients of L_c */
+        out->gkd[c] += Us[c] * Se->m * (1.0 - Fw) * S * L * K;
+        out->gm += Ud[c] * (-NoL / ORC_PI) * L * K + Us[c] * (Se->kd[c] - 0.04) * (1.0 - Fw) * S * L * K;
+        out->gr += Us[c] * F[c] * L * K * dSdr;
+        gnd += Ud[c] * (1.0 - Se->m) / ORC_PI * L * K;
+        gns += Us[c] * F[c] * L * K;
+        ec->coef[c] = Ud[c] * cdc + Us[c] * csc;
+        ec->absc[c] = fabs(Ud[c] * cdc) + fabs(Us[c] * csc);
+    }
+    for (int k = 0; k < 3; ++k)
+        out->gn[k] += gnd * w[k] + gns * (dSdNoV * Se->V[k] + dSdNoL * w[k] + dSdNoH * h[k]);
+}
+
+typedef struct {
+    const orc_scene* scene;
+    const orc_env* env_s;     /* sampling tables + radiance */
+    const float* env_eval;    /* radiance for the integrand (FD hook) or NULL */
+    const orc_gbuffer* gs;    /* sampling G-buffer */
+    const orc_gbuffer* ge;    /* evaluation G-buffer (FD hook) or NULL */
+    const orc_params* prm;
+    const uint32_t* sync;     /* [npix][spp][3] decisions of the HIP path or NULL */
+    uint32_t* dec_out;        /* [npix][spp][3] or NULL */
+} shade_ctx;
+
+static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, const double* Ud,
+                        const double* Us, pix_out* out, env_contrib* ecs, int64_t* nonfinite)
+{
+    const orc_params* P = C->prm;
+    const orc_env* E = C->env_s;
+    const float* envL = C->env_eval ? C->env_eval : E->env;
+    int spp = P->spp;
+    memset(out, 0, sizeof(*out));
+    for (int s = 0; s < 2 * spp; ++s) ecs[s].texel = -1;
+    pix_setup Ss, Se;
+    int nf = 0;
+    int ok = setup_pixel(C->gs, pix, &Ss, &nf);
+    if (nf) (*nonfinite)++;
+    const uint32_t* sy = C->sync ? C->sync + (size_t)q * spp * 3 : NULL;
+    uint32_t* dq = C->dec_out ? C->dec_out + (size_t)q * spp * 3 : NULL;
+    if (!ok) {
+        if (dq) for (int s = 0; s < spp; ++s) { dq[s * 3] = DEC_NONE; dq[s * 3 + 1] = DEC_NONE; dq[s * 3 + 2] = 0; }
+        if (sy && (sy[2] & DEC_VALID)) out->n_hard++;
+        return;
+    }
+    if (sy && !(sy[2] & DEC_VALID)) out->n_hard++;
+    /* n.v sign: synced when within tolerance */
+    if (fabs(Ss.NoV) < P->delta_cos && sy) {
+        int g = (sy[2] & DEC_NOV_POS) != 0;
+        if (g != Ss.nov_pos) { Ss.nov_pos = g; }
+        out->n_synced++;
+    } else if (sy && (((sy[2] & DEC_NOV_POS) != 0) != Ss.nov_pos)) {
+        out->n_hard++;
+    }
+    if (C->ge) {
+        int nf2 = 0;
+        if (!setup_pixel(C->ge, pix, &Se, &nf2)) Se = Ss;
+        Se.nov_pos = Ss.nov_pos;
+    } else {
+        Se = Ss;
+    }
+    float m_f = C->gs->korm[2 * ((int64_t)C->gs->n_views * C->gs->height * C->gs->width) + pix];
+    float qf = lobe_q(&Ss, m_f, P->flags);
+    int light_on = E->light_enabled && !(P->flags & ORC_LIGHT_OFF);
+    int64_t HW = (int64_t)C->gs->height * C->gs->width;
+    uint32_t view = (uint32_t)(pix / HW), piv = (uint32_t)(pix % HW);
+    double origin[3];
+    for (int k = 0; k < 3; ++k) origin[k] = Ss.p[k] + P->ray_eps * Ss.n[k];
+    double Vl[3] = {dot3(Ss.V, Ss.t), dot3(Ss.V, Ss.b), Ss.NoV};
+    for (int s = 0; s < spp; ++s) {
+        double xi[8];
+        sample_uniforms(P->seed, piv, (uint32_t)C->gs->view_base + view, (uint32_t)s, xi);
+        uint32_t rec0 = DEC_NONE, rec1 = DEC_NONE, rec2 = DEC_VALID | (Ss.nov_pos ? DEC_NOV_POS : 0u);
+        const uint32_t* gsr = sy ? sy + s * 3 : NULL;
+        for (int tech = 0; tech < 2; ++tech) {
+            double w[3], pL = 0.0;
+            int ti = -1, tj = -1;
+            double tex_margin = INFINITY;
+            if (tech == 0) {
+                if (!light_on) continue;
+                int32_t a, b;
+                orc_sample_light(E, xi[0], xi[1], w, &pL, &a, &b);
+                ti = a; tj = b;
+                rec0 = (uint32_t)(ti * E->W + tj);
+                if (gsr && gsr[0] != rec0) out->n_hard++;
+                if (!(pL > 0.0)) { rec2 |= DEC_L_CULL; continue; }
+            } else {
+                double loc[3];
+                int cosl = (float)xi[2] < qf;
+                if (cosl) {
+                    rec2 |= DEC_LOBE_COS;
+                    orc_sample_cos_local(xi[4], xi[5], loc);
+                } else {
+                    double lensq = orc_sample_vndf_local(Vl, Ss.alpha, xi[4], xi[5], loc);
+                    if (lensq < 1e-14) out->n_flag++;
+                }
+                if (gsr && (((gsr[2] & DEC_LOBE_COS) != 0) != cosl)) out->n_hard++;
+                for (int k = 0; k < 3; ++k) w[k] = loc[0] * Ss.t[k] + loc[1] * Ss.b[k] + loc[2] * Ss.n[k];
+                double wl = norm3(w);
+                for (int k = 0; k < 3; ++k) w[k] /= wl;
+                texel_of_dir(E->H, E->W, w, &ti, &tj, &tex_margin);
+                uint32_t mine = (uint32_t)(ti * E->W + tj);
+                if (gsr && gsr[1] != DEC_NONE && gsr[1] != mine) {
+                    if (tex_margin < P->delta_ang) {
+                        ti = (int)(gsr[1] / (uint32_t)E->W);
+                        tj = (int)(gsr[1] % (uint32_t)E->W);
+                        out->n_synced++;
+                    } else {
+                        out->n_hard++;
+                    }
+                }
+                rec1 = (uint32_t)(ti * E->W + tj);
+                if (light_on) {
+                    double rho = sqrt(w[0] * w[0] + w[2] * w[2]);
+                    pL = rho > 0.0 ? (double)E->pdf[(size_t)ti * E->W + tj] / (2.0 * ORC_PI * ORC_PI * rho) : 0.0;
+                }
+            }
+            uint32_t bit_cull = tech ? DEC_B_CULL : DEC_L_CULL;
+            uint32_t bit_tr = tech ? DEC_B_TRACED : DEC_L_TRACED;
+            uint32_t bit_hit = tech ? DEC_B_HIT : DEC_L_HIT;
+            double NoL = dot3(Ss.n, w);
+            int cull = !(NoL > 0.0);
+            if (gsr && fabs(NoL) < P->delta_cos) {
+                int gc = (gsr[2] & bit_cull) != 0;
+                if (gc != cull) { cull = gc; out->n_synced++; }
+            } else if (gsr && (((gsr[2] & bit_cull) != 0) != cull)) {
+                out->n_hard++;
+            }
+            if (cull) { rec2 |= bit_cull; continue; }
+            double Hv = 1.0;
+            if (P->tau != 0.0) {
+                rec2 |= bit_tr;
+                int r = orc_anyhit(C->scene, origin, w, P->delta_vis_abs, P->delta_vis_rel, P->brute);
+                int hit;
+                if (r == TRI_NEAR) {
+                    if (gsr) { hit = (gsr[2] & bit_hit) != 0; out->n_synced++; }
+                    else { hit = 1; out->n_flag++; }
+                } else {
+                    hit = r == TRI_HIT;
+                    if (gsr && (((gsr[2] & bit_hit) != 0) != hit)) out->n_hard++;
+                }
+                if (hit) {
+                    rec2 |= bit_hit;
+                    int bitpos = 2 * s + tech;
+                    out->hitbits[bitpos >> 5] |= 1u << (bitpos & 31);
+                    Hv = 1.0 - P->tau;
+                }
+            }
+            const float* Lrad = envL + ((size_t)ti * E->W + tj) * 3;
+            env_contrib* ec = &ecs[2 * s + tech];
+            eval_sample(&Ss, &Se, qf, w, pL, Lrad, spp, Hv, grad, Ud, Us, out, ec, 0);
+            ec->texel = ti * E->W + tj;
+        }
+        if (dq) { dq[s * 3] = rec0; dq[s * 3 + 1] = rec1; dq[s * 3 + 2] = rec2; }
+    }
+    if (grad) {
+        /* d/dn_raw = (I - n n^T) d/dn / |n_raw| */
+        double nd = dot3(Se.n, out->gn);
+        for (int k = 0; k < 3; ++k) out->gn[k] = (out->gn[k] - nd * Se.n[k]) / Se.nlen;
+    }
+}
+
+/* Forward (grad == 0) or backward (grad == 1) over a list of pixels.
+ * Outputs are [3][npix] in list order.  info = [npix][3]: synced decisions,
+ * unsyncable (flagged) decisions, hard mismatches against `sync`. */
+int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env_eval,
+                  const orc_gbuffer* gs, const orc_gbuffer* ge, const int64_t* pix, int64_t npix,
+                  const orc_params* prm, const uint32_t* sync, int grad, const double* Ud,
+                  const double* Us, double* cd, double* cs, double* gkd, double* gkorm, double* gn,
+                  double* genv, double* senv, uint32_t* hitbits, int32_t hit_words,
+                  uint32_t* dec_out, int32_t* info, int nthreads)
+{
+    shade_ctx C = {scene, env_s, env_eval, gs, ge, prm, sync, dec_out};
+    int spp = prm->spp;
+    if (spp < 1 || spp > 512 || hit_words > 32) return -1;
+    env_contrib* all = NULL;
+    if (grad && genv) all = (env_contrib*)malloc(sizeof(env_contrib) * (size_t)npix * 2 * spp);
+    int64_t nonfinite = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : nonfinite)
+    for (int64_t q = 0; q < npix; ++q) {
+        pix_out o;
+        env_contrib local[2 * 512];
+        env_contrib* ec = all ? all + (size_t)q * 2 * spp : local;
+        double ud[3] = {0, 0, 0}, us[3] = {0, 0, 0};
+        if (grad) for (int c = 0; c < 3; ++c) { ud[c] = Ud[c * npix + q]; us[c] = Us[c * npix + q]; }
+        shade_pixel(&C, q, pix[q], grad, ud, us, &o, ec, &nonfinite);
+        for (int c = 0; c < 3; ++c) {
+            if (cd) cd[c * npix + q] = o.cd[c];
+            if (cs) cs[c * npix + q] = o.cs[c];
+            if (grad) {
+                if (gkd) gkd[c * npix + q] = o.gkd[c];
+                if (gn) gn[c * npix + q] = o.gn[c];
+            }
+        }
+        if (grad && gkorm) {
+            gkorm[0 * npix + q] = 0.0;
+            gkorm[1 * npix + q] = o.gr;
+            gkorm[2 * npix + q] = o.gm;
+        }
+        if (hitbits) for (int k = 0; k < hit_words; ++k) hitbits[(size_t)q * hit_words + k] = o.hitbits[k];
+        if (info) { info[q * 3] = o.n_synced; info[q * 3 + 1] = o.n_flag; info[q * 3 + 2] = o.n_hard; }
+    }
+    if (all) {
+        /* fixed order: pixel list order, then sample, then technique */
+        for (int64_t k = 0; k < npix * 2 * spp; ++k) {
+            if (all[k].texel < 0) continue;
+            for (int c = 0; c < 3; ++c) {
+                genv[(size_t)all[k].texel * 3 + c] += all[k].coef[c];
+                if (senv) senv[(size_t)all[k].texel * 3 + c] += all[k].absc[c];
+            }
+        }
+        free(all);
+    }
+    return nonfinite;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Batched entry points used by the pin tests (plain loops).                 */
+/* ------------------------------------------------------------------------ */
+void orc_batch_philox(int64_t n, const uint32_t* ctr, const uint32_t key[2], uint32_t* out)
+{
+    for (int64_t i = 0; i < n; ++i) orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+void orc_batch_uniforms(int64_t n, uint64_t seed, const uint32_t* pix, const uint32_t* view,
+                        const uint32_t* s, double* xi)
+{
+    for (int64_t i = 0; i < n; ++i) sample_uniforms(seed, pix[i], view[i], s[i], xi + 8 * i);
+}
+
+void orc_batch_sample_light(const orc_env* e, int64_t n, const double* xi0, const double* xi1,
+                            double* w, double* p, int32_t* ti, int32_t* tj)
+{
+    for (int64_t i = 0; i < n; ++i) orc_sample_light(e, xi0[i], xi1[i], w + 3 * i, p + i, ti + i, tj + i);
+}
+
+void orc_batch_pdf_light(const orc_env* e, int64_t n, const double* w, double* p)
+{
+    for (int64_t i = 0; i < n; ++i) p[i] = orc_pdf_light(e, w + 3 * i);
+}
+
+void orc_batch_texel_of_dir(int H, int W, int64_t n, const double* w, int32_t* ti, int32_t* tj,
+                            double* margin)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        int a, b;
+        texel_of_dir(H, W, w + 3 * i, &a, &b, margin + i);
+        ti[i] = a;
+        tj[i] = b;
+    }
+}
+
+void orc_batch_pdf_ggx_local(int64_t n, const double* V, double alpha, const double* L, double* p)
+{
+    for (int64_t i = 0; i < n; ++i) p[i] = orc_pdf_ggx_local(V, L + 3 * i, alpha);
+}
+
+void orc_batch_pdf_cos_local(int64_t n, const double* L, double* p)
+{
+    for (int64_t i = 0; i < n; ++i) p[i] = orc_pdf_cos_local(L + 3 * i);
+}
+
+void orc_batch_sample_vndf_local(int64_t n, const double* V, double alpha, const double* u1,
+                                 const double* u2, double* L)
+{
+    for (int64_t i = 0; i < n; ++i) orc_sample_vndf_local(V, alpha, u1[i], u2[i], L + 3 * i);
+}
+
+void orc_batch_sample_cos_local(int64_t n, const double* u1, const double* u2, double* L)
+{
+    for (int64_t i = 0; i < n; ++i) orc_sample_cos_local(u1[i], u2[i], L + 3 * i);
+}
+
+void orc_batch_ggx(int64_t n, const double* noh, const double* s2, const double* nov,
+                   double alpha, double* D, double* lambda)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        D[i] = orc_ggx_D(noh[i], s2[i], alpha);
+        lambda[i] = orc_ggx_lambda(nov[i], alpha);
+    }
+}
+
+void orc_batch_anyhit(const orc_scene* s, int64_t n, const double* o, const double* d,
+                      double delta_abs, double delta_rel, int brute, int32_t* out)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_anyhit(s, o + 3 * i, d + 3 * i, delta_abs, delta_rel, brute);
+}
+
+/* The integrand of the direct-illumination integral of one pixel at unit
+ * directions w: g_d = (1-m)/pi (n.w) L(w) H(w) and g_s = F D G2/(4 n.v) L(w)
+ * H(w), zero below the horizon, nearest-texel radiance, all-triangle
+ * visibility (an undecided ray counts as hit).  Used by the quadrature pins. */
+void orc_integrand(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g, int64_t pix,
+                   const orc_params* P, int64_t n, const double* w, double* gd, double* gs)
+{
+    pix_setup S;
+    int nf = 0;
+    if (!setup_pixel(g, pix, &S, &nf)) {
+        memset(gd, 0, sizeof(double) * 3 * (size_t)n);
+        memset(gs, 0, sizeof(double) * 3 * (size_t)n);
+        return;
+    }
+    double origin[3];
+    for (int k = 0; k < 3; ++k) origin[k] = S.p[k] + P->ray_eps * S.n[k];
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        const double* wi = w + 3 * i;
+        pix_out o;
+        env_contrib ec;
+        memset(&o, 0, sizeof(o));
+        if (dot3(S.n, wi) > 0.0) {
+            double Hv = 1.0;
+            if (P->tau != 0.0 && orc_anyhit(scene, origin, wi, 0.0, 0.0, P->brute) != TRI_MISS)
+                Hv = 1.0 - P->tau;
+            int ti, tj;
+            double m;
+            texel_of_dir(E->H, E->W, wi, &ti, &tj, &m);
+            eval_sample(&S, &S, 1.0f, wi, 0.0, E->env + ((size_t)ti * E->W + tj) * 3, 1, Hv, 0, NULL,
+                        NULL, &o, &ec, 1);
+        }
+        for (int c = 0; c < 3; ++c) {
+            gd[3 * i + c] = o.cd[c];
+            gs[3 * i + c] = o.cs[c];
+        }
+    }
+}

@@ -1,0 +1,335 @@
+"""Estimator-level pins of the FP64 oracle.
+
+  white furnace      uniform probe, no occluder: E[c_d] = (1 - m) L0, and with
+                     the light technique off and q = 1 every sample equals it;
+  Lambert occluder   uniform probe, a convex polyhedron above a receiver:
+                     E[c_d] = (1 - m) L0 (1 - tau F), F the point-to-polygon
+                     form factor (Lambert's contour formula) summed over the
+                     front-facing faces;
+  quadrature         non-uniform probe and an occluding mesh: the Monte Carlo
+                     mean converges to a dense quadrature of the integrand;
+  finite differences the backward pass equals central differences of the
+                     frozen-sample estimator (samples, pdfs, q and visibility
+                     fixed; paper: detached sampling and visibility);
+  linearity          doubling the probe doubles c_d, c_s bit for bit; tau = 0
+                     equals a scene without triangles bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_workload, from_arrays
+from workloads import meshes
+
+RNG = np.random.Generator(np.random.PCG64(1185))
+
+
+def _unit(v):
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def _empty_mesh():
+    return np.zeros((3, 3), np.float32), np.zeros((0, 3), np.int32)
+
+
+# ---------------------------------------------------------------------------
+# white furnace
+# ---------------------------------------------------------------------------
+def _furnace(n=2048, spp=64, L0=(0.7, 1.0, 1.3)):
+    env = np.ones((8, 16, 3), np.float32) * np.array(L0, np.float32)
+    nrm = _unit(RNG.normal(size=(n, 3)))
+    pos = RNG.normal(size=(n, 3))
+    eye = np.zeros(3)
+    # keep some back-facing pixels (n.v <= 0 path)
+    kd = RNG.random((n, 3))
+    korm = np.stack([np.ones(n), RNG.uniform(0.08, 1, n), RNG.random(n)], 1)
+    v, f = _empty_mesh()
+    w = from_arrays("furnace", v, f, env, pos, nrm, kd, korm, eye=eye, spp=spp)
+    return w, env[0, 0].astype(np.float64)
+
+
+def test_white_furnace_expectation():
+    w, L0 = _furnace()
+    o = oracle.shade(w)
+    m = w.korm[2].astype(np.float64)
+    ratio = o["c_d"] / (1.0 - m)[None, :]
+    # per-channel results are exactly proportional to L0 (same samples)
+    r = ratio / L0[:, None]
+    assert np.allclose(r[0], r[1], rtol=1e-12) and np.allclose(r[0], r[2], rtol=1e-12)
+    mean = r[0].mean()
+    se = r[0].std(ddof=1) / np.sqrt(r.shape[1])
+    assert abs(mean - 1.0) < 4 * se + 1e-12, (mean, se)
+    assert se < 0.01
+
+
+def test_white_furnace_cosine_only_is_exact():
+    w, L0 = _furnace(n=256, spp=8)
+    o = oracle.shade(w, flags=oracle.LIGHT_OFF | oracle.FORCE_COS)
+    m = w.korm[2].astype(np.float64)
+    assert np.allclose(o["c_d"], (1 - m)[None, :] * L0[:, None], rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Lambert: convex polyhedron over a receiver
+# ---------------------------------------------------------------------------
+def lambert_form_factor(p, n, poly):
+    """Point-to-polygon form factor by Lambert's contour integral:
+    F = 1/(2 pi) |sum_k angle(R_k, R_k+1) * (n . unit(R_k x R_k+1))|."""
+    R = poly - p
+    tot = 0.0
+    for k in range(len(R)):
+        a, b = R[k], R[(k + 1) % len(R)]
+        g = np.cross(a, b)
+        gl = np.linalg.norm(g)
+        if gl == 0:
+            continue
+        ang = np.arccos(np.clip(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)), -1, 1))
+        tot += ang * (n @ (g / gl))
+    return abs(tot) / (2 * np.pi)
+
+
+def _occluder_setup(level=4, center=(0.0, 0.2, 0.0), recv=(0.5, -1.0, 0.0)):
+    v, f = meshes.icosphere(level)
+    v = v + np.array(center)
+    p = np.array(recv)
+    n = np.array([0.0, 1.0, 0.0])
+    return v, f, p, n
+
+
+def test_lambert_formula_matches_sphere():
+    """The polygon formula summed over the front faces of a fine icosphere is
+    close to the sphere's closed form (R/d)^2 cos(beta)."""
+    v, f, p, n = _occluder_setup(level=5)
+    tri = v[f]
+    nf = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    front = ((tri[:, 0] - p) * nf).sum(-1) < 0
+    F = sum(lambert_form_factor(p, n, t) for t in tri[front])
+    c = np.array([0.0, 0.2, 0.0])
+    d = np.linalg.norm(c - p)
+    F_sphere = (1.0 / d) ** 2 * ((c - p) @ n / d)
+    assert abs(F - F_sphere) < 0.01 * F_sphere
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.5])
+def test_lambert_occluder_expectation(tau):
+    v, f, p, n = _occluder_setup(level=3)
+    N, spp = 4096, 16
+    eps = 1e-4
+    L0 = np.array([1.0, 2.0, 0.5])
+    env = np.ones((16, 32, 3), np.float32) * L0.astype(np.float32)
+    m = 0.3
+    korm = np.tile([1.0, 0.5, m], (N, 1))
+    w = from_arrays("occluder", v, f, env, np.tile(p, (N, 1)), np.tile(n, (N, 1)),
+                    np.full((N, 3), 0.5), korm, eye=np.array([3.0, 2.0, 1.0]), spp=spp,
+                    ray_eps=eps, tau=tau)
+    o = oracle.shade(w)
+    # form factor of the mesh actually traced, seen from the ray origin
+    origin = (p.astype(np.float32).astype(np.float64) + eps * n)
+    vv = w.verts.astype(np.float64)
+    tri = vv[w.tris]
+    nf = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    front = ((tri[:, 0] - origin) * nf).sum(-1) < 0
+    F = sum(lambert_form_factor(origin, n, t) for t in tri[front])
+    expect = (1 - m) * L0 * (1 - tau * F)
+    est = o["c_d"].mean(1)
+    se = o["c_d"].std(1, ddof=1) / np.sqrt(N)
+    assert np.all(np.abs(est - expect) < 4 * se), (est, expect, se)
+    # rays passing within the tolerance of an edge are undecided: rare
+    assert o["info"][:, 1].sum() < 1e-3 * N * spp
+
+
+# ---------------------------------------------------------------------------
+# quadrature convergence
+# ---------------------------------------------------------------------------
+def _sphere_dirs(H, W, S):
+    """Midpoint nodes S x S per probe texel and their solid-angle weights."""
+    v = (np.arange(H * S) + 0.5) / (H * S)
+    u = (np.arange(W * S) + 0.5) / (W * S)
+    V, U = np.meshgrid(v, u, indexing="ij")
+    th, ph = np.pi * V, 2 * np.pi * U
+    d = np.stack([np.sin(th) * np.cos(ph), np.cos(th), np.sin(th) * np.sin(ph)], -1).reshape(-1, 3)
+    wt = (2 * np.pi ** 2 * np.sin(th) / (H * S * W * S)).reshape(-1)
+    return d, wt
+
+
+@pytest.mark.parametrize("pix_sel", [0, 1, 2])
+def test_mc_converges_to_quadrature(pix_sel):
+    w = make_workload("tiny")
+    valid = np.nonzero((w.mask > 0) & (w.korm[1] > 0.35))[0]
+    pix = valid[[len(valid) // 5, len(valid) // 2, (4 * len(valid)) // 5][pix_sel]]
+    sc = oracle.Scene(w.verts, w.tris)
+    tab = oracle.EnvTables(w.env)
+    d, wt = _sphere_dirs(w.env.shape[0], w.env.shape[1], 24)
+    gd, gs = oracle.integrand(w, pix, d, scene=sc, tables=tab, brute=False)
+    quad_d = (gd * wt[:, None]).sum(0)
+    quad_s = (gs * wt[:, None]).sum(0)
+    # replicate the pixel: independent Philox streams per copy
+    N, spp = 8192, 8
+    col = lambda a: np.tile(a[:, pix], (N, 1))  # noqa: E731
+    rep = from_arrays("rep", w.verts, w.tris, w.env, col(w.pos), col(w.nrm), col(w.kd), col(w.korm),
+                      eye=w.eye[0], spp=spp, ray_eps=w.ray_eps, tau=w.tau)
+    o = oracle.shade(rep, scene=sc, tables=tab)
+    for est, quad in ((o["c_d"], quad_d), (o["c_s"], quad_s)):
+        mean = est.mean(1)
+        se = est.std(1, ddof=1) / np.sqrt(N)
+        assert np.all(np.abs(mean - quad) < 4 * se + 2e-3 * np.abs(quad)), (mean, quad, se)
+        # and the error shrinks like 1/sqrt(N): half the copies, ~sqrt(2) larger SE
+        se_half = est[:, : N // 4].std(1, ddof=1) / np.sqrt(N // 4)
+        assert np.all(se_half > 1.5 * se) and np.all(se_half < 2.6 * se)
+
+
+# ---------------------------------------------------------------------------
+# gradients: analytic backward vs frozen-sample central differences
+# ---------------------------------------------------------------------------
+def _grad_setup():
+    w = make_workload("tiny")
+    valid = np.nonzero((w.mask > 0) & (w.korm[1] > 0.12))[0]
+    pix = RNG.choice(valid, 96, replace=False)
+    n = len(pix)
+    Ud = RNG.normal(size=(3, n))
+    Us = RNG.normal(size=(3, n))
+    return w, pix, Ud, Us
+
+
+def _loss(o, Ud, Us):
+    return (Ud * o["c_d"]).sum(0) + (Us * o["c_s"]).sum(0)
+
+
+@pytest.mark.parametrize("field,ch", [("kd", 0), ("kd", 2), ("korm", 1), ("korm", 2), ("korm", 0),
+                                      ("nrm", 0), ("nrm", 1), ("nrm", 2)])
+def test_backward_matches_frozen_fd(field, ch):
+    w, pix, Ud, Us = _grad_setup()
+    sc = oracle.Scene(w.verts, w.tris)
+    tab = oracle.EnvTables(w.env)
+    g = oracle.shade(w, pixels=pix, scene=sc, tables=tab, grad=True, u_d=Ud, u_s=Us)
+    gkey = {"kd": "g_kd", "korm": "g_korm", "nrm": "g_nrm"}[field]
+    an = g[gkey][ch]
+    eps = 1e-5
+    res = []
+    for sgn in (1, -1):
+        arr = getattr(w, field).astype(np.float64).copy()
+        arr[ch, pix] += sgn * eps
+        # the perturbation is applied on the evaluation side only
+        o = oracle.shade(w, pixels=pix, scene=sc, tables=tab,
+                         eval_override={field: arr.astype(np.float32)})
+        res.append(_loss(o, Ud, Us))
+    # float32 storage of the perturbed input: use the realised step
+    arr_p = getattr(w, field).astype(np.float64).copy()
+    h_p = (arr_p[ch, pix] + eps).astype(np.float32).astype(np.float64) - arr_p[ch, pix]
+    h_m = arr_p[ch, pix] - (arr_p[ch, pix] - eps).astype(np.float32).astype(np.float64)
+    fd = (res[0] - res[1]) / (h_p + h_m)
+    scale = np.abs(an).max() + 1e-12
+    assert np.allclose(an, fd, rtol=2e-3, atol=2e-4 * scale), np.abs(an - fd).max() / scale
+
+
+def test_backward_fd_float64_inputs_tight():
+    """Same check with a float64-exact perturbation path: perturb a roughness
+    value that is exactly representable so the FD step is exact, and ask for
+    1e-6 relative agreement away from kinks."""
+    w, pix, Ud, Us = _grad_setup()
+    sc = oracle.Scene(w.verts, w.tris)
+    tab = oracle.EnvTables(w.env)
+    g = oracle.shade(w, pixels=pix, scene=sc, tables=tab, grad=True, u_d=Ud, u_s=Us)
+    h = 2.0 ** -12
+    res = []
+    for sgn in (1, -1):
+        arr = w.kd.copy()
+        arr[1, pix] = (arr[1, pix] + np.float32(sgn * h)).astype(np.float32)
+        o = oracle.shade(w, pixels=pix, scene=sc, tables=tab, eval_override={"kd": arr})
+        res.append(_loss(o, Ud, Us))
+    step = (w.kd[1, pix].astype(np.float64) + h) - (w.kd[1, pix].astype(np.float64) - h)
+    fd = (res[0] - res[1]) / step
+    # c_s is affine in kd (Schlick), so central differences are exact up to rounding
+    assert np.allclose(g["g_kd"][1], fd, rtol=1e-8, atol=1e-12)
+
+
+def test_env_gradient_matches_fd():
+    """The estimator is linear in each texel under frozen sampling, so the
+    texel gradient equals a finite difference exactly (up to rounding)."""
+    w, pix, Ud, Us = _grad_setup()
+    sc = oracle.Scene(w.verts, w.tris)
+    tab = oracle.EnvTables(w.env)
+    g = oracle.shade(w, pixels=pix, scene=sc, tables=tab, grad=True, u_d=Ud, u_s=Us)
+    ge = g["g_env"]
+    top = np.argsort(-np.abs(ge).reshape(-1))[:12]
+    h = 0.25
+    for flat in top:
+        i, j, c = np.unravel_index(flat, ge.shape)
+        vals, xs = [], []
+        for sgn in (1, -1):
+            e2 = w.env.copy()
+            e2[i, j, c] += np.float32(sgn * h)
+            xs.append(float(e2[i, j, c]))
+            o = oracle.shade(w, pixels=pix, scene=sc, tables=tab, env_eval=e2)
+            vals.append(_loss(o, Ud, Us).sum())
+        fd = (vals[0] - vals[1]) / (xs[0] - xs[1])
+        assert abs(fd - ge[i, j, c]) <= 1e-9 * max(1.0, abs(fd)), (fd, ge[i, j, c])
+    assert np.all(g["s_env"] >= np.abs(ge) - 1e-15)
+
+
+def test_occlusion_channel_has_no_effect():
+    w, pix, Ud, Us = _grad_setup()
+    a = oracle.shade(w, pixels=pix)
+    k2 = w.korm.copy()
+    k2[0] = RNG.random(k2.shape[1])
+    b = oracle.shade(w, pixels=pix, eval_override={"korm": k2})
+    assert np.array_equal(a["c_d"], b["c_d"]) and np.array_equal(a["c_s"], b["c_s"])
+
+
+# ---------------------------------------------------------------------------
+# exact identities
+# ---------------------------------------------------------------------------
+def test_probe_linearity_bitwise():
+    w = make_workload("tiny")
+    a = oracle.shade(w)
+    w2 = make_workload("tiny")
+    w2.env = (w2.env * 2).astype(np.float32)
+    b = oracle.shade(w2)
+    assert np.array_equal(2 * a["c_d"], b["c_d"]) and np.array_equal(2 * a["c_s"], b["c_s"])
+    assert np.array_equal(a["hitbits"], b["hitbits"])
+
+
+def test_tau_zero_equals_empty_scene():
+    w = make_workload("tiny")
+    a = oracle.shade(w, tau=0.0)
+    v, f = _empty_mesh()
+    b = oracle.shade(w, scene=oracle.Scene(v, f), tau=1.0)
+    assert np.array_equal(a["c_d"], b["c_d"]) and np.array_equal(a["c_s"], b["c_s"])
+    assert not a["hitbits"].any()
+
+
+def test_invalid_pixels_are_zero():
+    w = make_workload("tiny")
+    pos = w.pos.copy()
+    nrm = w.nrm.copy()
+    valid = np.nonzero(w.mask)[0]
+    pos[0, valid[0]] = np.nan
+    nrm[:, valid[1]] = 0.0
+    w.pos, w.nrm = pos, nrm
+    o = oracle.shade(w, grad=True, u_d=np.ones((3, w.n_pixels)), u_s=np.ones((3, w.n_pixels)))
+    for k in ("c_d", "c_s", "g_kd", "g_korm", "g_nrm"):
+        assert np.all(o[k][:, w.mask == 0] == 0)
+        assert np.all(o[k][:, valid[:2]] == 0)
+    assert o["nonfinite"] == 1
+
+
+def test_decisions_and_hitbits_consistent():
+    w = make_workload("tiny")
+    o = oracle.shade(w, want_decisions=True)
+    dec = o["decisions"]
+    hb = o["hitbits"][:, 0]
+    for s in range(w.spp):
+        fl = dec[:, s, 2]
+        for tech, bit in ((0, oracle.DEC_L_HIT), (1, oracle.DEC_B_HIT)):
+            assert np.array_equal(((hb >> (2 * s + tech)) & 1) != 0, (fl & bit) != 0)
+    valid = w.mask > 0
+    assert np.all((dec[valid, :, 2] & oracle.DEC_VALID) != 0)
+    assert np.all(dec[~valid, :, 0] == oracle.DEC_NONE)
+
+
+def test_brute_force_equals_bvh_render():
+    w = make_workload("tiny")
+    a = oracle.shade(w)
+    b = oracle.shade(w, brute=True)
+    assert np.array_equal(a["c_d"], b["c_d"]) and np.array_equal(a["hitbits"], b["hitbits"])
