@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the differentiable Monte Carlo direct-illumination hot path.
+
+One step = one optimisation iteration of the path on one batch: rebuild the
+shadow-ray BVH from the mesh, rebuild the probe sampling tables, forward
+shading (samples, MIS, shadow rays), the image loss and the backward pass
+through the autograd Function (adjoint kernel with the probe-texel scatter).
+Inputs are resident in HBM before timing starts.
+
+Default workload: 8 views at 512x512 of a 101,060-triangle displaced sphere
+with 20 box occluders, a 512x256 probe, 12 samples per pixel, forward +
+backward (synthetic data shaped like the paper's multi-view batches).
+
+Prints ONE JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "shaded samples/s fwd+bwd (px×spp) + shadow rays/s; served p50/p99 latency"
+
+# MI355X public peaks
+CU, LANES, CLOCK = 256, 64, 2.4e9
+VALU_PEAK = CU * LANES * CLOCK       # 32-bit lane operations per second, non-packed
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sphere8_grad")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path (the env-gradient all-reduce "
+              "that sharding would need is described in the design notes); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2206_03380_amd as M
+    from workloads import make_workload
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    w = make_workload(args.workload)
+    log(args, "workload %s generated in %.1fs: %d px (%d valid), %d tris, env %s, spp %d" % (
+        w.name, time.time() - t0, w.n_pixels, w.n_valid, len(w.tris), w.env.shape[:2], w.spp))
+
+    verts = torch.from_numpy(w.verts).to(dev)
+    tris = torch.from_numpy(w.tris).to(dev)
+    env_p = torch.from_numpy(w.env).to(dev)
+    gb = M.GBuffer.from_workload(w, dev)
+    kd = gb.kd.clone().requires_grad_(True)
+    korm = gb.korm.clone().requires_grad_(True)
+    nrm = gb.nrm.clone().requires_grad_(True)
+    env_t = env_p.clone().requires_grad_(True)
+    mask = gb.mask.bool()
+    n_valid = int(mask.sum())
+
+    # target image: one render with perturbed materials/probe (fixed seed)
+    rng = np.random.Generator(np.random.PCG64(7))
+    kd_t = np.clip(w.kd * (1 + 0.1 * rng.normal(size=w.kd.shape)), 0, 1).astype(np.float32)
+    korm_t = w.korm.copy()
+    korm_t[1] = np.clip(korm_t[1] + 0.05 * rng.normal(size=korm_t[1].shape), 0.08, 1).astype(np.float32)
+    env_tgt = (w.env * np.exp(0.1 * rng.normal(size=w.env.shape))).astype(np.float32)
+    with torch.no_grad():
+        sc0 = M.Scene(verts, tris)
+        ev0 = M.Env(torch.from_numpy(env_tgt).to(dev))
+        gbt = M.GBuffer(gb.pos, gb.nrm, torch.from_numpy(kd_t).to(dev), torch.from_numpy(korm_t).to(dev), gb.mask,
+                        gb.eye, gb.n_views, gb.height, gb.width)
+        cd_t, cs_t, _, _ = M.shade_fwd(sc0, ev0, gbt, w.spp, seed=0, tau=w.tau, ray_eps=w.ray_eps, hitbits=False)
+        target = (gbt.kd * cd_t + cs_t).detach()
+        del sc0, ev0
+
+    def step():
+        scene = M.Scene(verts, tris)                      # BVH rebuild (mesh changes every iteration)
+        envh = M.Env(env_t.detach())                      # probe tables rebuild
+        c_d, c_s = M.MCDIShade.apply(kd, korm, nrm, env_t, scene, envh, gb, w.spp, w.seed, w.tau, w.ray_eps)
+        img = kd * c_d + c_s
+        loss = ((img - target).abs() * mask).sum() / (3 * n_valid)
+        loss.backward()
+        return scene, envh
+
+    # warmup
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    keep = []
+    start.record()
+    for _ in range(args.steps):
+        keep.append(step())
+        if len(keep) > 2:
+            keep.pop(0)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    samples = n_valid * w.spp
+    value = samples / (ms * 1e-3)
+    log(args, "step %.3f ms -> %.3g samples/s" % (ms, value))
+
+    # ---- per-kernel timing on the launch stream (HIP events) ----
+    scene = M.Scene(verts, tris)
+    envh = M.Env(env_p)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = M.shade_fwd(scene, envh, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps)
+    hb = out[2]
+    g_cd = torch.randn((3, gb.n), device=dev) * mask / n_valid
+    g_cs = torch.randn((3, gb.n), device=dev) * mask / n_valid
+    g_env = torch.zeros_like(env_p)
+    bwd_out = (torch.empty_like(g_cd), torch.empty_like(g_cd), torch.empty_like(g_cd))
+    fwd_ms = timed(lambda: M.shade_fwd(scene, envh, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps,
+                                       out=out[:3]), args.kernel_reps)
+    bwd_ms = timed(lambda: M.shade_bwd(scene, envh, gb, w.spp, g_cd, g_cs, hitbits=hb, seed=w.seed, tau=w.tau,
+                                       ray_eps=w.ray_eps, g_env=g_env, out=bwd_out), args.kernel_reps)
+    bvh_ms = timed(lambda: M.Scene(verts, tris), max(3, args.kernel_reps // 2))
+    cdf_ms = timed(lambda: M.Env(env_p), max(3, args.kernel_reps // 2))
+
+    # ---- statistics instantiation (same rays): work counts ----
+    st = M.new_stats(dev)
+    M.shade_fwd(scene, envh, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps, stats=st, hitbits=False)
+    stats = M.read_stats(st)
+    rays = stats["rays_traced"]
+
+    # ---- roofline of the dominant kernel (forward shading) ----
+    # VALU lane-operations the method performs per launch, from the work counts:
+    ops = (OPS_PER_SAMPLE * samples + OPS_PER_BOX * stats["box_tests"] + OPS_PER_TRI * stats["tri_tests"])
+    achieved = ops / (fwd_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
+                "frac": achieved / VALU_PEAK, "traffic": None,
+                "kernel": "shade_kernel<fwd>", "ops_per_launch": ops, "kernel_ms": fwd_ms}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%s: %d views %dx%d, %d tris, env %dx%d, %d spp, fwd+bwd" % (
+            w.name, w.n_views, w.width, w.height, len(w.tris), w.env.shape[1], w.env.shape[0], w.spp),
+            "views": w.n_views, "height": w.height, "width": w.width, "spp": w.spp, "tris": int(len(w.tris)),
+            "env": [int(w.env.shape[0]), int(w.env.shape[1])], "valid_px": n_valid,
+            "parallelism": "single-gpu"},
+        "shadow_rays_per_s": rays / (fwd_ms * 1e-3),
+        "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "bvh_build_ms": bvh_ms, "env_cdf_ms": cdf_ms,
+        "shade_only_samples_per_s": samples / ((fwd_ms + bwd_ms) * 1e-3),
+        "work": stats,
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args, w)
+    print(json.dumps(result), flush=True)
+
+
+# per-unit VALU lane-operation counts of the method (see the design notes)
+OPS_PER_SAMPLE = 620
+OPS_PER_BOX = 24
+OPS_PER_TRI = 46
+
+
+def cpu_baseline(args, w):
+    """The FP64 oracle (as it stands) on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle
+    from workloads import upstream_grads
+    nthreads = oracle.max_threads()
+    rng = np.random.Generator(np.random.PCG64(11))
+    valid = np.nonzero(w.mask)[0]
+    scene = oracle.Scene(w.verts, w.tris)
+    tables = oracle.EnvTables(w.env)
+    ud, us = upstream_grads(w)
+
+    def run(n):
+        pix = np.sort(rng.choice(valid, n, replace=False))
+        t = time.time()
+        oracle.shade(w, pixels=pix, scene=scene, tables=tables)
+        oracle.shade(w, pixels=pix, scene=scene, tables=tables, grad=True, u_d=ud[:, pix].astype(np.float64),
+                     u_s=us[:, pix].astype(np.float64))
+        return time.time() - t
+
+    n = 512
+    dt = run(n)
+    n2 = int(min(len(valid), max(n, n * args.cpu_seconds / max(dt, 1e-3))))
+    dt2 = run(n2)
+    return {"value": n2 * w.spp / dt2, "unit": "samples/s", "cores": nthreads, "kind": "oracle",
+            "sample": "%d random valid pixels of the same workload, forward + backward, %.1f s" % (n2, dt2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * mcdi.h -- C ABI of the differentiable Monte Carlo direct-illumination
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, per G-buffer pixel, the direct-illumination
+ * rendering equation against an HDR environment probe with shadow rays
+ * (Hasselgren, Hofmann & Munkberg, NeurIPS 2022, section 3.1 "Direct
+ * Illumination"), estimated by Monte Carlo with multiple importance sampling
+ * over three techniques -- a piecewise-constant 2D distribution over the
+ * probe, cosine sampling of the diffuse lobe and GGX visible-normal sampling
+ * (section 4.1 "Multiple Importance Sampling"; appendix D "Sampling") -- and
+ * returns diffuse lighting demodulated from the albedo and specular lighting
+ * separately (section 4.2 "Denoising").  The backward pass replays the same
+ * random numbers (section 4.1; appendix D) and differentiates only the
+ * material evaluation: sampling and visibility are detached (section 3.1
+ * "Shadow gradients"; section 4.1).  Shadowed samples are weighted by
+ * H = 1 - tau (appendix A "Optimization and Regularization").
+ *
+ * Conventions shared by every call:
+ *   - Pointers named as device buffers are device memory owned by the caller;
+ *     the library never frees them.  Handles own the device memory they
+ *     allocate, through the optional allocator hook (NULL: stream-ordered
+ *     hipMallocAsync / hipFreeAsync).
+ *   - `stream` is a hipStream_t passed as void*.  Every call only enqueues
+ *     work on it and returns; nothing synchronises the device unless stated.
+ *   - Per-pixel arrays are planar float32 [C][N], N = n_views*height*width,
+ *     pixel id (view*height + y)*width + x.
+ *   - Status codes only; no C++ exception crosses the ABI.  Arguments are
+ *     validated before anything is enqueued; a non-OK status leaves every
+ *     output untouched.  mcdi_last_error() returns a thread-local message for
+ *     the last non-OK status of the calling thread.
+ *   - Data-dependent anomalies are not errors: a pixel with a non-finite
+ *     input, a zero normal or a zero view vector shades to 0 and gets zero
+ *     gradients (counted in mcdi_stats); a probe whose total luminance is 0
+ *     disables the light technique.
+ */
+#ifndef MCDI_H
+#define MCDI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MCDI_OK = 0,
+    MCDI_E_INVALID = -1,     /* bad argument (null pointer, size, range) */
+    MCDI_E_OOM = -2,         /* device allocation failed */
+    MCDI_E_DEVICE = -3,      /* HIP runtime error while enqueuing */
+    MCDI_E_UNSUPPORTED = -4  /* size beyond a documented limit */
+} mcdi_status;
+
+typedef struct mcdi_scene_s* mcdi_scene; /* opaque BVH over a triangle mesh */
+typedef struct mcdi_env_s* mcdi_env;     /* opaque probe sampling tables */
+
+/* Optional device allocator (e.g. a framework's caching allocator).
+ * alloc returns device memory usable in stream order on `stream`, or NULL;
+ * free releases it in stream order. */
+typedef struct {
+    void* ctx;
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);
+    void (*free)(void* ctx, void* ptr, void* stream);
+} mcdi_allocator;
+
+/* ---------------------------------------------------------------------------
+ * Scene: the triangle mesh the shadow rays are traced against (the mesh the
+ * paper extracts every iteration, section 3 and figure "system").
+ *
+ * verts   device float32 [n_verts][3]
+ * tris    device int32   [n_tris][3], vertex indices
+ * Builds a bounding-volume hierarchy on the device (Morton-ordered linear BVH,
+ * leaves of <= 4 triangles, depth-first node order with skip links).
+ * A triangle with an index outside [0, n_verts) or a non-finite vertex is
+ * replaced by a degenerate triangle that no ray hits (counted in
+ * mcdi_scene_info).  n_tris = 0 gives a scene every ray misses.
+ * verts/tris are read during the call's stream work only; the handle keeps no
+ * reference to them.  Limits: n_verts < 2^31, n_tris < 2^27.
+ * ------------------------------------------------------------------------- */
+mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                             const mcdi_allocator* alloc, void* stream, mcdi_scene* out);
+
+/* Frees the scene's memory in stream order on the stream it was built on.
+ * Work on other streams that uses the scene must have completed. */
+void mcdi_destroy_scene(mcdi_scene scene);
+
+typedef struct {
+    int64_t n_tris;
+    int32_t n_nodes;      /* BVH nodes after leaf collapsing */
+    int32_t max_depth;    /* longest root-to-leaf path */
+    int32_t bad_tris;     /* triangles replaced by degenerate ones */
+    int32_t reserved;
+} mcdi_scene_info_t;
+
+/* Synchronises the scene's stream and reports build statistics. */
+mcdi_status mcdi_scene_info(mcdi_scene scene, mcdi_scene_info_t* info);
+
+/* ---------------------------------------------------------------------------
+ * Environment probe sampling tables (section 4.1: light importance sampling
+ * with a piecewise-constant 2D distribution; rebuilt every optimisation
+ * iteration because the probe is an optimisation variable).
+ *
+ * env_rgb  device float32 [H][W][3] linear radiance, lat-long: row i covers
+ *          polar angle [i, i+1)*pi/H from +Y, column j covers azimuth
+ *          [j, j+1)*2pi/W with azimuth = atan2(z, x).
+ * Texel weight = max(0, (r+g+b)/3) * sin(pi (i+1/2)/H), summed left to right
+ * in FP64; each table entry is rounded once to FP32:
+ *   cond [H][W+1]  per-row CDF, cond[i][0] = 0, cond[i][W] = 1
+ *   marg [H+1]     marginal CDF over rows
+ *   pdf  [H][W]    (w_ij / sum w) * W * H, the texel's density in (u, v)
+ * The handle BORROWS env_rgb (radiance is read from it while shading): it
+ * must stay unchanged until every shade call using the handle has completed.
+ * Limits: 1 <= H <= 4096, 1 <= W <= 4096.
+ * ------------------------------------------------------------------------- */
+mcdi_status mcdi_build_env_cdf(const float* env_rgb, int32_t H, int32_t W, const mcdi_allocator* alloc,
+                               void* stream, mcdi_env* out);
+void mcdi_destroy_env(mcdi_env env);
+
+/* Copies the tables into caller device buffers (any may be NULL), in stream
+ * order: cond [H][W+1], marg [H+1], pdf [H][W] float32. */
+mcdi_status mcdi_env_tables(mcdi_env env, float* cond, float* marg, float* pdf, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Shading
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_views, height, width;
+    int32_t view_base;      /* global id of view 0; keys the random numbers */
+    const float* pos;       /* device [3][N] world position */
+    const float* nrm;       /* device [3][N] shading normal (need not be unit) */
+    const float* kd;        /* device [3][N] diffuse albedo */
+    const float* korm;      /* device [3][N] (occlusion, roughness, metallic); occlusion unused */
+    const uint8_t* mask;    /* device [N] nonzero = covered pixel */
+    const float* eye;       /* device [n_views][3] camera position */
+} mcdi_gbuffer;
+
+/* Flags */
+#define MCDI_FLAG_LIGHT_OFF   (1u << 0) /* no light-technique sample; p_light = 0 */
+#define MCDI_FLAG_FORCE_COS   (1u << 1) /* lobe probability q = 1 (cosine only) */
+#define MCDI_FLAG_DUMP        (1u << 8) /* write per-sample decision records */
+
+typedef struct {
+    int32_t spp;            /* samples per pixel, 1..1024; each = 1 light + 1 BSDF sample */
+    uint32_t flags;
+    uint64_t seed;          /* Philox4x32-10 key */
+    float tau;              /* shadow weight: H = 1 - tau on hit (appendix A) */
+    float ray_eps;          /* shadow-ray origin offset along the normal (world units) */
+    uint32_t* decisions;    /* device [N][spp][3] when MCDI_FLAG_DUMP, else NULL */
+} mcdi_params;
+
+/* Device-side counters, accumulated (+=) by every call that receives them.
+ * Passing stats selects an instrumented instantiation of the same kernel. */
+typedef struct {
+    unsigned long long valid_pixels;
+    unsigned long long invalid_pixels;   /* masked-in pixels with bad inputs */
+    unsigned long long rays_traced;
+    unsigned long long rays_hit;
+    unsigned long long samples_culled;   /* below the horizon */
+    unsigned long long box_tests;        /* BVH node boxes tested */
+    unsigned long long tri_tests;        /* ray/triangle tests */
+    unsigned long long reserved;
+} mcdi_stats;
+
+/* Forward pass.
+ *   c_d, c_s  device [3][N] float32, overwritten: demodulated diffuse and
+ *             specular lighting, so that the shaded colour is kd*c_d + c_s.
+ *   hitbits   device uint32 [ceil(2*spp/32)][N] or NULL; bit 2s (2s+1) of a
+ *             pixel = the light (BSDF) sample s was occluded.  Overwritten.
+ *   stats     device mcdi_stats or NULL (accumulated).
+ * Random numbers: Philox4x32-10 with key = seed and counter = (pixel in view,
+ * view_base + view, s, block), blocks 0 and 1 per sample. */
+mcdi_status mcdi_shade_fwd(mcdi_scene scene, mcdi_env env, const mcdi_gbuffer* gbuf,
+                           const mcdi_params* params, float* c_d, float* c_s, uint32_t* hitbits,
+                           mcdi_stats* stats, void* stream);
+
+/* Backward pass of the detached estimator, same samples as the forward.
+ *   g_cd, g_cs   device [3][N] upstream gradients dL/dc_d, dL/dc_s
+ *   hitbits      the forward pass's hit bits, or NULL to re-trace the rays
+ *   g_kd, g_korm, g_nrm  device [3][N], overwritten (g_korm[0] = 0)
+ *   g_env        device [H][W][3], ACCUMULATED (+=); the caller zeroes it.
+ * Summation order of g_env is not deterministic (float atomics). */
+mcdi_status mcdi_shade_bwd(mcdi_scene scene, mcdi_env env, const mcdi_gbuffer* gbuf,
+                           const mcdi_params* params, const float* g_cd, const float* g_cs,
+                           const uint32_t* hitbits, float* g_kd, float* g_korm, float* g_nrm,
+                           float* g_env, mcdi_stats* stats, void* stream);
+
+/* Any-hit queries for explicit rays (tests and tools).
+ *   orig, dir  device float32 [3][n]; hit device uint8 [n] (1 = occluded),
+ *   t in (0, inf), no culling.  brute != 0 tests every triangle instead of
+ *   traversing the BVH. */
+mcdi_status mcdi_trace_anyhit(mcdi_scene scene, const float* orig, const float* dir, int64_t n,
+                              uint8_t* hit, int32_t brute, void* stream);
+
+/* Thread-local text of the last non-OK status ("" if none). */
+const char* mcdi_last_error(void);
+
+/* Library version string. */
+const char* mcdi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCDI_H */

@@ -240,8 +240,9 @@ def shade(w, pixels=None, scene=None, tables=None, spp=None, seed=None, tau=None
     L = lib()
     spp = w.spp if spp is None else spp
     seed = w.seed if seed is None else seed
-    tau = w.tau if tau is None else tau
-    ray_eps = w.ray_eps if ray_eps is None else ray_eps
+    # tau and ray_eps are FP32 parameters of the library: use the same values
+    tau = float(np.float32(w.tau if tau is None else tau))
+    ray_eps = float(np.float32(w.ray_eps if ray_eps is None else ray_eps))
     tol = tol or Tolerances()
     pixels = np.arange(w.n_pixels, dtype=np.int64) if pixels is None else _c(pixels, np.int64)
     n = len(pixels)

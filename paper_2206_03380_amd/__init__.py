@@ -1,0 +1,241 @@
+"""Differentiable Monte Carlo direct illumination on AMD MI355X.
+
+Thin torch-facing wrappers over the C ABI in include/mcdi.h.  torch provides
+device memory and streams; every step of the estimator runs in the HIP
+kernels of libmcdi.so.
+"""
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+from ._lib import MCDIError, FLAG_LIGHT_OFF, FLAG_FORCE_COS, FLAG_DUMP  # noqa: F401
+
+__all__ = ["Scene", "Env", "GBuffer", "shade_fwd", "shade_bwd", "trace_anyhit", "MCDIShade",
+           "MCDIError", "new_stats", "read_stats"]
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return t
+
+
+# torch's caching allocator behind the library's allocator hook
+@C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+def _torch_alloc(ctx, nbytes, stream):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:  # out of memory: report NULL to the library
+        return None
+
+
+@C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+def _torch_free(ctx, ptr, stream):
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+_TORCH_ALLOCATOR = L.Allocator(None, _torch_alloc, _torch_free)
+
+
+class Scene:
+    """BVH over a triangle mesh (device float32 [Nv,3] vertices, int32 [Nt,3])."""
+
+    def __init__(self, verts, tris, stream=None, use_torch_allocator=True):
+        _need(verts, torch.float32, name="verts")
+        _need(tris, torch.int32, name="tris")
+        if verts.dim() != 2 or verts.shape[1] != 3 or tris.dim() != 2 or tris.shape[1] != 3:
+            raise ValueError("verts must be [Nv,3] and tris [Nt,3]")
+        h = C.c_void_p()
+        L.check(L.lib().mcdi_build_scene(_ptr(verts), verts.shape[0], _ptr(tris), tris.shape[0],
+                                         C.byref(_TORCH_ALLOCATOR) if use_torch_allocator else None,
+                                         _stream(stream), C.byref(h)))
+        self.handle = h
+        self.n_tris = tris.shape[0]
+
+    def info(self):
+        i = L.SceneInfo()
+        L.check(L.lib().mcdi_scene_info(self.handle, C.byref(i)))
+        return {"n_tris": i.n_tris, "n_nodes": i.n_nodes, "max_depth": i.max_depth, "bad_tris": i.bad_tris}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib().mcdi_destroy_scene(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Env:
+    """Sampling tables of a lat-long probe (device float32 [H,W,3]); keeps a
+    reference to the probe tensor, which the tables borrow."""
+
+    def __init__(self, env, stream=None, use_torch_allocator=True):
+        _need(env, torch.float32, name="env")
+        if env.dim() != 3 or env.shape[2] != 3:
+            raise ValueError("env must be [H,W,3]")
+        self.env = env
+        self.H, self.W = env.shape[0], env.shape[1]
+        h = C.c_void_p()
+        L.check(L.lib().mcdi_build_env_cdf(_ptr(env), self.H, self.W,
+                                           C.byref(_TORCH_ALLOCATOR) if use_torch_allocator else None,
+                                           _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def tables(self, stream=None):
+        """Copies of the FP32 tables (cond [H,W+1], marg [H+1], pdf [H,W])."""
+        dev = self.env.device
+        cond = torch.empty((self.H, self.W + 1), dtype=torch.float32, device=dev)
+        marg = torch.empty(self.H + 1, dtype=torch.float32, device=dev)
+        pdf = torch.empty((self.H, self.W), dtype=torch.float32, device=dev)
+        L.check(L.lib().mcdi_env_tables(self.handle, _ptr(cond), _ptr(marg), _ptr(pdf), _stream(stream)))
+        return cond, marg, pdf
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib().mcdi_destroy_env(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class GBuffer:
+    """Planar per-pixel G-buffer on the device."""
+    pos: torch.Tensor      # f32 [3, N]
+    nrm: torch.Tensor      # f32 [3, N]
+    kd: torch.Tensor       # f32 [3, N]
+    korm: torch.Tensor     # f32 [3, N]
+    mask: torch.Tensor     # u8 [N]
+    eye: torch.Tensor      # f32 [V, 3]
+    n_views: int
+    height: int
+    width: int
+    view_base: int = 0
+
+    @property
+    def n(self):
+        return self.n_views * self.height * self.width
+
+    def struct(self, kd=None, korm=None, nrm=None):
+        n = self.n
+        for name in ("pos", "nrm", "kd", "korm"):
+            _need(getattr(self, name), torch.float32, (3, n), name)
+        _need(self.mask, torch.uint8, (n,), "mask")
+        _need(self.eye, torch.float32, (self.n_views, 3), "eye")
+        return L.GBuffer(self.n_views, self.height, self.width, self.view_base, self.pos.data_ptr(),
+                         (nrm if nrm is not None else self.nrm).data_ptr(),
+                         (kd if kd is not None else self.kd).data_ptr(),
+                         (korm if korm is not None else self.korm).data_ptr(), self.mask.data_ptr(),
+                         self.eye.data_ptr())
+
+    @staticmethod
+    def from_workload(w, device="cuda"):
+        t = lambda a: torch.from_numpy(a).to(device).contiguous()  # noqa: E731
+        return GBuffer(t(w.pos), t(w.nrm), t(w.kd), t(w.korm), t(w.mask), t(w.eye), w.n_views, w.height,
+                       w.width, w.view_base)
+
+
+def hit_words(spp):
+    return (2 * spp + 31) // 32
+
+
+def new_stats(device="cuda"):
+    return torch.zeros(8, dtype=torch.int64, device=device)
+
+
+def read_stats(t):
+    v = t.cpu().tolist()
+    return {"valid_pixels": v[0], "invalid_pixels": v[1], "rays_traced": v[2], "rays_hit": v[3],
+            "samples_culled": v[4], "box_tests": v[5], "tri_tests": v[6]}
+
+
+def _params(spp, seed, tau, ray_eps, flags, decisions):
+    return L.Params(int(spp), int(flags), int(seed), float(tau), float(ray_eps),
+                    decisions.data_ptr() if decisions is not None else None)
+
+
+def shade_fwd(scene, env, gb, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0, hitbits=True, decisions=False,
+              stats=None, out=None, stream=None):
+    """Forward pass.  Returns (c_d [3,N], c_s [3,N], hitbits [words,N] or None,
+    decisions [N,spp,3] or None)."""
+    n = gb.n
+    dev = gb.pos.device
+    if out is None:
+        c_d = torch.empty((3, n), dtype=torch.float32, device=dev)
+        c_s = torch.empty((3, n), dtype=torch.float32, device=dev)
+        hb = torch.empty((hit_words(spp), n), dtype=torch.int32, device=dev) if hitbits else None
+    else:
+        c_d, c_s, hb = out
+    dec = None
+    if decisions:
+        dec = torch.empty((n, spp, 3), dtype=torch.int32, device=dev)
+        flags |= FLAG_DUMP
+    gs = gb.struct()
+    prm = _params(spp, seed, tau, ray_eps, flags, dec)
+    L.check(L.lib().mcdi_shade_fwd(scene.handle, env.handle, C.byref(gs), C.byref(prm), _ptr(c_d), _ptr(c_s),
+                                   _ptr(hb), _ptr(stats), _stream(stream)))
+    return c_d, c_s, hb, dec
+
+
+def shade_bwd(scene, env, gb, spp, g_cd, g_cs, hitbits=None, seed=0, tau=1.0, ray_eps=1e-3, flags=0,
+              g_env=None, stats=None, out=None, stream=None):
+    """Backward pass.  Returns (g_kd, g_korm, g_nrm, g_env); g_env is
+    accumulated into if given, else a zeroed [H,W,3] tensor is created."""
+    n = gb.n
+    dev = gb.pos.device
+    _need(g_cd, torch.float32, (3, n), "g_cd")
+    _need(g_cs, torch.float32, (3, n), "g_cs")
+    if out is None:
+        g_kd = torch.empty((3, n), dtype=torch.float32, device=dev)
+        g_korm = torch.empty((3, n), dtype=torch.float32, device=dev)
+        g_nrm = torch.empty((3, n), dtype=torch.float32, device=dev)
+    else:
+        g_kd, g_korm, g_nrm = out
+    if g_env is None:
+        g_env = torch.zeros((env.H, env.W, 3), dtype=torch.float32, device=dev)
+    gs = gb.struct()
+    prm = _params(spp, seed, tau, ray_eps, flags, None)
+    L.check(L.lib().mcdi_shade_bwd(scene.handle, env.handle, C.byref(gs), C.byref(prm), _ptr(g_cd), _ptr(g_cs),
+                                   _ptr(hitbits), _ptr(g_kd), _ptr(g_korm), _ptr(g_nrm), _ptr(g_env),
+                                   _ptr(stats), _stream(stream)))
+    return g_kd, g_korm, g_nrm, g_env
+
+
+def trace_anyhit(scene, orig, dirs, brute=False, stream=None):
+    """orig, dirs: device f32 [3, n].  Returns uint8 [n] (1 = occluded)."""
+    n = orig.shape[1]
+    _need(orig, torch.float32, (3, n), "orig")
+    _need(dirs, torch.float32, (3, n), "dirs")
+    hit = torch.empty(n, dtype=torch.uint8, device=orig.device)
+    L.check(L.lib().mcdi_trace_anyhit(scene.handle, _ptr(orig), _ptr(dirs), n, _ptr(hit), int(brute),
+                                      _stream(stream)))
+    return hit
+
+
+from .autograd import MCDIShade  # noqa: E402,F401

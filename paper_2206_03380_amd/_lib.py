@@ -1,0 +1,99 @@
+"""ctypes binding of libmcdi.so: argument marshalling only.
+
+Every step of the method runs in the HIP kernels behind the C ABI.  If the
+library has not been built, loading fails with an error; there is no
+fallback implementation.
+"""
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcdi.so")
+
+MCDI_OK, MCDI_E_INVALID, MCDI_E_OOM, MCDI_E_DEVICE, MCDI_E_UNSUPPORTED = 0, -1, -2, -3, -4
+FLAG_LIGHT_OFF = 1 << 0
+FLAG_FORCE_COS = 1 << 1
+FLAG_DUMP = 1 << 8
+
+vp = C.c_void_p
+
+
+class MCDIError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("mcdi status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Allocator(C.Structure):
+    _fields_ = [("ctx", vp), ("alloc", C.CFUNCTYPE(vp, vp, C.c_size_t, vp)),
+                ("free", C.CFUNCTYPE(None, vp, vp, vp))]
+
+
+class GBuffer(C.Structure):
+    _fields_ = [("n_views", C.c_int32), ("height", C.c_int32), ("width", C.c_int32),
+                ("view_base", C.c_int32), ("pos", vp), ("nrm", vp), ("kd", vp), ("korm", vp),
+                ("mask", vp), ("eye", vp)]
+
+
+class Params(C.Structure):
+    _fields_ = [("spp", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64), ("tau", C.c_float),
+                ("ray_eps", C.c_float), ("decisions", vp)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("valid_pixels", C.c_uint64), ("invalid_pixels", C.c_uint64), ("rays_traced", C.c_uint64),
+                ("rays_hit", C.c_uint64), ("samples_culled", C.c_uint64), ("box_tests", C.c_uint64),
+                ("tri_tests", C.c_uint64), ("reserved", C.c_uint64)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("n_tris", C.c_int64), ("n_nodes", C.c_int32), ("max_depth", C.c_int32),
+                ("bad_tris", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmcdi.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmcdi.so is not built (run paper_2206_03380_amd/build.py or "
+                          "__graft_entry__.build()); there is no fallback path")
+    L = C.CDLL(LIB_PATH)
+    L.mcdi_build_scene.restype = C.c_int
+    L.mcdi_build_scene.argtypes = [vp, C.c_int64, vp, C.c_int64, vp, vp, C.POINTER(vp)]
+    L.mcdi_destroy_scene.argtypes = [vp]
+    L.mcdi_destroy_scene.restype = None
+    L.mcdi_scene_info.argtypes = [vp, C.POINTER(SceneInfo)]
+    L.mcdi_scene_info.restype = C.c_int
+    L.mcdi_build_env_cdf.restype = C.c_int
+    L.mcdi_build_env_cdf.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(vp)]
+    L.mcdi_destroy_env.argtypes = [vp]
+    L.mcdi_destroy_env.restype = None
+    L.mcdi_env_tables.argtypes = [vp, vp, vp, vp, vp]
+    L.mcdi_env_tables.restype = C.c_int
+    L.mcdi_shade_fwd.restype = C.c_int
+    L.mcdi_shade_fwd.argtypes = [vp, vp, C.POINTER(GBuffer), C.POINTER(Params), vp, vp, vp, vp, vp]
+    L.mcdi_shade_bwd.restype = C.c_int
+    L.mcdi_shade_bwd.argtypes = [vp, vp, C.POINTER(GBuffer), C.POINTER(Params), vp, vp, vp, vp, vp, vp,
+                                 vp, vp, vp]
+    L.mcdi_trace_anyhit.restype = C.c_int
+    L.mcdi_trace_anyhit.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int32, vp]
+    L.mcdi_last_error.restype = C.c_char_p
+    L.mcdi_version.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != MCDI_OK:
+        raise MCDIError(status, lib().mcdi_last_error().decode())
+
+
+EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_build_env_cdf",
+            "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
+            "mcdi_trace_anyhit", "mcdi_last_error", "mcdi_version")

@@ -1,0 +1,62 @@
+"""torch.autograd.Function over the forward/backward kernels.
+
+Forward saves only the shadow-ray hit bits (2 bits per sample and pixel);
+backward replays the same random numbers and recomputes every BSDF, pdf and
+MIS term instead of storing them per sample (paper: section 4.1, the forward
+seed is re-used during backpropagation; sampling and visibility detached).
+"""
+
+import torch
+
+from . import _lib as L
+
+
+class MCDIShade(torch.autograd.Function):
+    """c_d, c_s = MCDIShade.apply(kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed, tau, ray_eps)
+
+    kd, korm, nrm: [3, N] float32 (differentiable); env: the [H, W, 3] probe
+    tensor the tables were built from (differentiable; its gradient is the
+    texel scatter).  Positions, mask and eyes come from gbuf (not
+    differentiated: shape gradients come from primary visibility)."""
+
+    @staticmethod
+    def forward(ctx, kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed=0, tau=1.0, ray_eps=1e-3):
+        from . import _ptr, _stream, hit_words, _params
+        import ctypes as C
+        n = gbuf.n
+        dev = kd.device
+        kd, korm, nrm = kd.contiguous(), korm.contiguous(), nrm.contiguous()
+        if env_tables.env.data_ptr() != env.data_ptr():
+            raise ValueError("env_tables must be built from the env tensor passed in")
+        c_d = torch.empty((3, n), dtype=torch.float32, device=dev)
+        c_s = torch.empty((3, n), dtype=torch.float32, device=dev)
+        need_bits = tau != 0.0 and any(ctx.needs_input_grad[:4])
+        hb = torch.empty((hit_words(spp), n), dtype=torch.int32, device=dev) if need_bits else None
+        gs = gbuf.struct(kd=kd, korm=korm, nrm=nrm)
+        prm = _params(spp, seed, tau, ray_eps, 0, None)
+        L.check(L.lib().mcdi_shade_fwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(c_d),
+                                       _ptr(c_s), _ptr(hb), None, _stream()))
+        ctx.save_for_backward(kd, korm, nrm, hb if hb is not None else torch.empty(0, device=dev))
+        ctx.meta = (scene, env_tables, gbuf, spp, seed, tau, ray_eps, hb is not None)
+        return c_d, c_s
+
+    @staticmethod
+    def backward(ctx, g_cd, g_cs):
+        from . import _ptr, _stream, _params
+        import ctypes as C
+        kd, korm, nrm, hb = ctx.saved_tensors
+        scene, env_tables, gbuf, spp, seed, tau, ray_eps, has_bits = ctx.meta
+        n = gbuf.n
+        dev = kd.device
+        g_cd = (g_cd if g_cd is not None else torch.zeros((3, n), device=dev)).contiguous().float()
+        g_cs = (g_cs if g_cs is not None else torch.zeros((3, n), device=dev)).contiguous().float()
+        g_kd = torch.empty((3, n), dtype=torch.float32, device=dev)
+        g_korm = torch.empty((3, n), dtype=torch.float32, device=dev)
+        g_nrm = torch.empty((3, n), dtype=torch.float32, device=dev)
+        g_env = torch.zeros((env_tables.H, env_tables.W, 3), dtype=torch.float32, device=dev)
+        gs = gbuf.struct(kd=kd, korm=korm, nrm=nrm)
+        prm = _params(spp, seed, tau, ray_eps, 0, None)
+        L.check(L.lib().mcdi_shade_bwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(g_cd),
+                                       _ptr(g_cs), _ptr(hb) if has_bits else None, _ptr(g_kd), _ptr(g_korm),
+                                       _ptr(g_nrm), _ptr(g_env), None, _stream()))
+        return g_kd, g_korm, g_nrm, g_env, None, None, None, None, None, None, None

@@ -1,0 +1,284 @@
+// Host runtime of the C ABI declared in include/mcdi.h: argument validation,
+// handle ownership, stream-ordered allocation and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mcdi_internal.h"
+
+using namespace mcdi;
+
+namespace {
+
+thread_local std::string g_err;
+
+mcdi_status fail(mcdi_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+mcdi_status ok() {
+    g_err.clear();
+    return MCDI_OK;
+}
+
+struct Alloc {
+    mcdi_allocator user{};
+    bool has_user = false;
+    void* get(size_t bytes, hipStream_t s) const {
+        if (bytes == 0) bytes = 256;
+        if (has_user) return user.alloc(user.ctx, bytes, (void*)s);
+        void* p = nullptr;
+        if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void put(void* p, hipStream_t s) const {
+        if (!p) return;
+        if (has_user) user.free(user.ctx, p, (void*)s);
+        else (void)hipFreeAsync(p, s);
+    }
+};
+
+Alloc make_alloc(const mcdi_allocator* a) {
+    Alloc r;
+    if (a && a->alloc && a->free) {
+        r.user = *a;
+        r.has_user = true;
+    }
+    return r;
+}
+
+void* temp_alloc(void* ctx, size_t b, hipStream_t s) { return static_cast<Alloc*>(ctx)->get(b, s); }
+void temp_free(void* ctx, void* p, hipStream_t s) { static_cast<Alloc*>(ctx)->put(p, s); }
+
+}  // namespace
+
+struct mcdi_scene_s {
+    Alloc alloc;
+    hipStream_t stream = nullptr;
+    int64_t n_tris = 0;
+    Node* nodes = nullptr;
+    float4* tris = nullptr;
+    DeviceSceneInfo* info = nullptr;
+};
+
+struct mcdi_env_s {
+    Alloc alloc;
+    hipStream_t stream = nullptr;
+    int32_t H = 0, W = 0;
+    const float* rgb = nullptr;
+    float* cond = nullptr;
+    float* marg = nullptr;
+    float* pdf = nullptr;
+    double* rowsum = nullptr;  // [H + 1]
+    int32_t* light = nullptr;
+};
+
+extern "C" {
+
+const char* mcdi_last_error(void) { return g_err.c_str(); }
+
+const char* mcdi_version(void) { return "mcdi 0.1 gfx950"; }
+
+mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                             const mcdi_allocator* alloc, void* stream, mcdi_scene* out) {
+    if (!out) return fail(MCDI_E_INVALID, "mcdi_build_scene: out is NULL");
+    if (n_verts < 0 || n_tris < 0) return fail(MCDI_E_INVALID, "mcdi_build_scene: negative count");
+    if (n_verts >= (int64_t)1 << 31) return fail(MCDI_E_UNSUPPORTED, "mcdi_build_scene: n_verts >= 2^31");
+    if (n_tris >= (int64_t)1 << 27) return fail(MCDI_E_UNSUPPORTED, "mcdi_build_scene: n_tris >= 2^27");
+    if (n_tris > 0 && (!verts || !tris)) return fail(MCDI_E_INVALID, "mcdi_build_scene: NULL verts/tris");
+    if (n_tris > 0 && n_verts == 0) return fail(MCDI_E_INVALID, "mcdi_build_scene: triangles without vertices");
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(MCDI_E_INVALID, "mcdi_build_scene: allocator incomplete");
+    hipStream_t s = (hipStream_t)stream;
+    mcdi_scene sc = new (std::nothrow) mcdi_scene_s;
+    if (!sc) return fail(MCDI_E_OOM, "mcdi_build_scene: host allocation failed");
+    sc->alloc = make_alloc(alloc);
+    sc->stream = s;
+    sc->n_tris = n_tris;
+    const size_t n_nodes = n_tris > 0 ? (size_t)(2 * n_tris - 1) : 1;
+    sc->nodes = (Node*)sc->alloc.get(sizeof(Node) * n_nodes, s);
+    sc->tris = (float4*)sc->alloc.get(sizeof(float4) * 3 * (size_t)(n_tris > 0 ? n_tris : 1), s);
+    sc->info = (DeviceSceneInfo*)sc->alloc.get(sizeof(DeviceSceneInfo), s);
+    if (!sc->nodes || !sc->tris || !sc->info) {
+        mcdi_destroy_scene(sc);
+        return fail(MCDI_E_OOM, "mcdi_build_scene: device allocation failed (%lld triangles)", (long long)n_tris);
+    }
+    TempAlloc ta{temp_alloc, temp_free, &sc->alloc};
+    int oom = 0;
+    hipError_t e = build_bvh(verts, n_verts, tris, n_tris, sc->nodes, sc->tris, sc->info, ta, s, &oom);
+    if (e != hipSuccess) {
+        mcdi_destroy_scene(sc);
+        if (oom) return fail(MCDI_E_OOM, "mcdi_build_scene: temporary allocation failed");
+        return fail(MCDI_E_DEVICE, "mcdi_build_scene: %s", hipGetErrorString(e));
+    }
+    *out = sc;
+    return ok();
+}
+
+void mcdi_destroy_scene(mcdi_scene sc) {
+    if (!sc) return;
+    sc->alloc.put(sc->nodes, sc->stream);
+    sc->alloc.put(sc->tris, sc->stream);
+    sc->alloc.put(sc->info, sc->stream);
+    delete sc;
+}
+
+mcdi_status mcdi_scene_info(mcdi_scene sc, mcdi_scene_info_t* info) {
+    if (!sc || !info) return fail(MCDI_E_INVALID, "mcdi_scene_info: NULL argument");
+    DeviceSceneInfo h{};
+    hipError_t e = hipStreamSynchronize(sc->stream);
+    if (e == hipSuccess) e = hipMemcpy(&h, sc->info, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_scene_info: %s", hipGetErrorString(e));
+    info->n_tris = sc->n_tris;
+    info->n_nodes = h.n_nodes;
+    info->max_depth = h.max_depth;
+    info->bad_tris = h.bad_tris;
+    info->reserved = 0;
+    return ok();
+}
+
+mcdi_status mcdi_build_env_cdf(const float* env_rgb, int32_t H, int32_t W, const mcdi_allocator* alloc,
+                               void* stream, mcdi_env* out) {
+    if (!out) return fail(MCDI_E_INVALID, "mcdi_build_env_cdf: out is NULL");
+    if (!env_rgb) return fail(MCDI_E_INVALID, "mcdi_build_env_cdf: env_rgb is NULL");
+    if (H < 1 || W < 1) return fail(MCDI_E_INVALID, "mcdi_build_env_cdf: H and W must be >= 1");
+    if (H > 4096 || W > 4096) return fail(MCDI_E_UNSUPPORTED, "mcdi_build_env_cdf: H and W must be <= 4096");
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(MCDI_E_INVALID, "mcdi_build_env_cdf: allocator incomplete");
+    hipStream_t s = (hipStream_t)stream;
+    mcdi_env ev = new (std::nothrow) mcdi_env_s;
+    if (!ev) return fail(MCDI_E_OOM, "mcdi_build_env_cdf: host allocation failed");
+    ev->alloc = make_alloc(alloc);
+    ev->stream = s;
+    ev->H = H;
+    ev->W = W;
+    ev->rgb = env_rgb;
+    ev->cond = (float*)ev->alloc.get(sizeof(float) * (size_t)H * (W + 1), s);
+    ev->marg = (float*)ev->alloc.get(sizeof(float) * (size_t)(H + 1), s);
+    ev->pdf = (float*)ev->alloc.get(sizeof(float) * (size_t)H * W, s);
+    ev->rowsum = (double*)ev->alloc.get(sizeof(double) * (size_t)(H + 1), s);
+    ev->light = (int32_t*)ev->alloc.get(sizeof(int32_t), s);
+    if (!ev->cond || !ev->marg || !ev->pdf || !ev->rowsum || !ev->light) {
+        mcdi_destroy_env(ev);
+        return fail(MCDI_E_OOM, "mcdi_build_env_cdf: device allocation failed");
+    }
+    hipError_t e = launch_env_cdf(env_rgb, H, W, ev->cond, ev->marg, ev->pdf, ev->rowsum, ev->light, s);
+    if (e != hipSuccess) {
+        mcdi_destroy_env(ev);
+        return fail(MCDI_E_DEVICE, "mcdi_build_env_cdf: %s", hipGetErrorString(e));
+    }
+    *out = ev;
+    return ok();
+}
+
+void mcdi_destroy_env(mcdi_env ev) {
+    if (!ev) return;
+    ev->alloc.put(ev->cond, ev->stream);
+    ev->alloc.put(ev->marg, ev->stream);
+    ev->alloc.put(ev->pdf, ev->stream);
+    ev->alloc.put(ev->rowsum, ev->stream);
+    ev->alloc.put(ev->light, ev->stream);
+    delete ev;
+}
+
+mcdi_status mcdi_env_tables(mcdi_env ev, float* cond, float* marg, float* pdf, void* stream) {
+    if (!ev) return fail(MCDI_E_INVALID, "mcdi_env_tables: NULL env");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    const size_t H = (size_t)ev->H, W = (size_t)ev->W;
+    if (cond && e == hipSuccess) e = hipMemcpyAsync(cond, ev->cond, sizeof(float) * H * (W + 1), hipMemcpyDeviceToDevice, s);
+    if (marg && e == hipSuccess) e = hipMemcpyAsync(marg, ev->marg, sizeof(float) * (H + 1), hipMemcpyDeviceToDevice, s);
+    if (pdf && e == hipSuccess) e = hipMemcpyAsync(pdf, ev->pdf, sizeof(float) * H * W, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_env_tables: %s", hipGetErrorString(e));
+    return ok();
+}
+
+static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g,
+                               const mcdi_params* p, ShadeArgs& a) {
+    if (!sc || !ev || !g || !p) return fail(MCDI_E_INVALID, "%s: NULL scene/env/gbuffer/params", who);
+    if (g->n_views < 1 || g->height < 1 || g->width < 1)
+        return fail(MCDI_E_INVALID, "%s: n_views, height, width must be >= 1", who);
+    const int64_t n = (int64_t)g->n_views * g->height * g->width;
+    if (n >= (int64_t)1 << 31) return fail(MCDI_E_UNSUPPORTED, "%s: more than 2^31 - 1 pixels", who);
+    if (!g->pos || !g->nrm || !g->kd || !g->korm || !g->mask || !g->eye)
+        return fail(MCDI_E_INVALID, "%s: NULL G-buffer plane", who);
+    if (p->spp < 1 || p->spp > 1024) return fail(MCDI_E_INVALID, "%s: spp must be in [1, 1024]", who);
+    if (!std::isfinite(p->tau) || !std::isfinite(p->ray_eps) || p->ray_eps < 0.0f)
+        return fail(MCDI_E_INVALID, "%s: tau must be finite and ray_eps finite and >= 0", who);
+    if ((p->flags & MCDI_FLAG_DUMP) && !p->decisions)
+        return fail(MCDI_E_INVALID, "%s: MCDI_FLAG_DUMP without a decisions buffer", who);
+    std::memset(&a, 0, sizeof(a));
+    a.scene = Scene{sc->nodes, sc->tris, sc->n_tris};
+    a.env = EnvView{ev->H, ev->W, ev->rgb, ev->cond, ev->marg, ev->pdf, ev->light};
+    a.g = GBufView{g->n_views, g->height, g->width, g->view_base, g->pos, g->nrm, g->kd, g->korm, g->mask, g->eye, n};
+    a.spp = p->spp;
+    a.flags = p->flags;
+    a.seed = p->seed;
+    a.tau = p->tau;
+    a.ray_eps = p->ray_eps;
+    a.decisions = (p->flags & MCDI_FLAG_DUMP) ? p->decisions : nullptr;
+    return MCDI_OK;
+}
+
+mcdi_status mcdi_shade_fwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, const mcdi_params* p, float* c_d,
+                           float* c_s, uint32_t* hitbits, mcdi_stats* stats, void* stream) {
+    ShadeArgs a;
+    mcdi_status st = fill_common("mcdi_shade_fwd", sc, ev, g, p, a);
+    if (st != MCDI_OK) return st;
+    if (!c_d || !c_s) return fail(MCDI_E_INVALID, "mcdi_shade_fwd: NULL c_d/c_s");
+    a.c_d = c_d;
+    a.c_s = c_s;
+    a.hitbits_out = hitbits;
+    a.stats = stats;
+    hipError_t e = launch_shade_fwd(a, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_fwd: %s", hipGetErrorString(e));
+    return ok();
+}
+
+mcdi_status mcdi_shade_bwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, const mcdi_params* p,
+                           const float* g_cd, const float* g_cs, const uint32_t* hitbits, float* g_kd,
+                           float* g_korm, float* g_nrm, float* g_env, mcdi_stats* stats, void* stream) {
+    ShadeArgs a;
+    mcdi_status st = fill_common("mcdi_shade_bwd", sc, ev, g, p, a);
+    if (st != MCDI_OK) return st;
+    if (p->flags & MCDI_FLAG_DUMP) return fail(MCDI_E_INVALID, "mcdi_shade_bwd: MCDI_FLAG_DUMP is forward-only");
+    if (!g_cd || !g_cs || !g_kd || !g_korm || !g_nrm)
+        return fail(MCDI_E_INVALID, "mcdi_shade_bwd: NULL gradient buffer");
+    a.g_cd = g_cd;
+    a.g_cs = g_cs;
+    a.hitbits_in = hitbits;
+    a.g_kd = g_kd;
+    a.g_korm = g_korm;
+    a.g_nrm = g_nrm;
+    a.g_env = g_env;
+    a.stats = stats;
+    hipError_t e = launch_shade_bwd(a, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd: %s", hipGetErrorString(e));
+    return ok();
+}
+
+mcdi_status mcdi_trace_anyhit(mcdi_scene sc, const float* orig, const float* dir, int64_t n, uint8_t* hit,
+                              int32_t brute, void* stream) {
+    if (!sc) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: NULL scene");
+    if (n < 0) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: negative n");
+    if (n >= (int64_t)1 << 31) return fail(MCDI_E_UNSUPPORTED, "mcdi_trace_anyhit: n >= 2^31");
+    if (n > 0 && (!orig || !dir || !hit)) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: NULL buffer");
+    hipError_t e = launch_trace(Scene{sc->nodes, sc->tris, sc->n_tris}, orig, dir, n, hit, brute,
+                                (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_trace_anyhit: %s", hipGetErrorString(e));
+    return ok();
+}
+
+}  // extern "C"

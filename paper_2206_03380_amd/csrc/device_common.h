@@ -1,0 +1,191 @@
+// Device building blocks for gfx950: counter-based RNG, probe sampling, GGX
+// material model, visible-normal sampling and the any-hit BVH traversal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mcdi_internal.h"
+
+namespace mcdi {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInvPi = 0.318309886183790671538f;
+constexpr float kRMin = 0.08f;  // roughness clamp (alpha >= 0.0064)
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// decision-record bits (debug dump)
+constexpr uint32_t kDecLobeCos = 1u << 0, kDecLCull = 1u << 1, kDecBCull = 1u << 2;
+constexpr uint32_t kDecLTraced = 1u << 3, kDecBTraced = 1u << 4, kDecLHit = 1u << 5;
+constexpr uint32_t kDecBHit = 1u << 6, kDecNovPos = 1u << 7, kDecValid = 1u << 8;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC 2011): ten rounds of two 32x32 products.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// top 24 bits as a float in [0, 1), exact
+__device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * 0x1p-24f; }
+
+// ---------------------------------------------------------------------------
+// small vector helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+__device__ __forceinline__ float dot(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 operator+(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 operator*(float s, float3 a) { return f3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float3 normalize(float3 a) { return (1.0f / sqrtf(dot(a, a))) * a; }
+
+// ---------------------------------------------------------------------------
+// binary search: largest k in [0, n-1] with cdf[k] <= x (cdf[0] = 0 <= x <
+// 1 = cdf[n], non-decreasing) -- skips zero-width bins.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int cdf_find(const float* cdf, int n, float x) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// GGX with Smith height-correlated masking (alpha = roughness^2)
+// ---------------------------------------------------------------------------
+// D written with s2 = |n x h|^2 (local: h.x^2 + h.y^2) for 1 - (n.h)^2
+__device__ __forceinline__ float ggx_D(float noh, float s2, float a2) {
+    const float den = a2 * noh * noh + s2;
+    return a2 / (kPi * den * den);
+}
+
+__device__ __forceinline__ float smith_t2(float x) { return (1.0f - x * x) / (x * x); }
+
+__device__ __forceinline__ float smith_lambda(float t2, float a2) {
+    return 0.5f * (sqrtf(1.0f + a2 * t2) - 1.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Watertight ray/triangle test (Woop, Benthin, Wald; JCGT 2013), any hit with
+// t in (0, inf).  The ray is pre-sheared: kz is the dominant axis of d and the
+// rows M* give the sheared coordinates of (v - o).  Edge functions use no
+// contraction so a shared edge gives exactly negated values in its two
+// triangles; an exactly-zero edge function is re-evaluated in FP64.
+// ---------------------------------------------------------------------------
+struct Ray {
+    float3 o;
+    float3 inv;      // 1/d (zero components replaced, boxes only)
+    float3 mx, my;   // shear rows
+    float sz;        // 1/d[kz]
+    int kz;
+};
+
+__device__ __forceinline__ float comp(float3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+__device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
+    Ray r;
+    r.o = o;
+    const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    const float dz = comp(d, kz);
+    if (dz < 0.0f) { const int t = kx; kx = ky; ky = t; }
+    const float sx = comp(d, kx) / dz, sy = comp(d, ky) / dz;
+    r.sz = 1.0f / dz;
+    r.kz = kz;
+    // rows: e_kx - sx e_kz and e_ky - sy e_kz
+    r.mx = f3(kx == 0 ? 1.f : 0.f, kx == 1 ? 1.f : 0.f, kx == 2 ? 1.f : 0.f);
+    r.my = f3(ky == 0 ? 1.f : 0.f, ky == 1 ? 1.f : 0.f, ky == 2 ? 1.f : 0.f);
+    if (kz == 0) { r.mx.x = -sx; r.my.x = -sy; }
+    if (kz == 1) { r.mx.y = -sx; r.my.y = -sy; }
+    if (kz == 2) { r.mx.z = -sx; r.my.z = -sy; }
+    const float tiny = 1e-30f;
+    r.inv = f3(1.0f / (d.x != 0.0f ? d.x : tiny), 1.0f / (d.y != 0.0f ? d.y : tiny),
+               1.0f / (d.z != 0.0f ? d.z : tiny));
+    return r;
+}
+
+__device__ __forceinline__ bool tri_anyhit(const Ray& r, float4 v0, float4 v1, float4 v2) {
+#pragma clang fp contract(off)
+    const float3 A = f3(v0.x, v0.y, v0.z) - r.o;
+    const float3 B = f3(v1.x, v1.y, v1.z) - r.o;
+    const float3 C = f3(v2.x, v2.y, v2.z) - r.o;
+    const float az = comp(A, r.kz), bz = comp(B, r.kz), cz = comp(C, r.kz);
+    // sheared x, y: component kx (ky) minus s * component kz
+    const float Ax = dot(r.mx, A), Ay = dot(r.my, A);
+    const float Bx = dot(r.mx, B), By = dot(r.my, B);
+    const float Cx = dot(r.mx, C), Cy = dot(r.my, C);
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    const float det = U + V + W;
+    if (det == 0.0f) return false;
+    const float T = U * (r.sz * az) + V * (r.sz * bz) + W * (r.sz * cz);
+    return det > 0.0f ? (T > 0.0f) : (T < 0.0f);
+}
+
+// Conservative slab test (Ize 2013: widen t_far by 1 + 2 gamma(3)), t >= 0.
+__device__ __forceinline__ bool box_hit(const Ray& r, float4 a, float4 b) {
+    const float tx0 = (a.x - r.o.x) * r.inv.x, tx1 = (b.x - r.o.x) * r.inv.x;
+    const float ty0 = (a.y - r.o.y) * r.inv.y, ty1 = (b.y - r.o.y) * r.inv.y;
+    const float tz0 = (a.z - r.o.z) * r.inv.z, tz1 = (b.z - r.o.z) * r.inv.z;
+    const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+    const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+    return tn <= tf * 1.00000036f;
+}
+
+// Stackless any-hit traversal over the pre-order BVH with skip links.
+// COUNT: tally box tests and triangle tests (statistics instantiation only).
+template <bool COUNT = false>
+__device__ __forceinline__ bool bvh_anyhit(const Scene& sc, const Ray& r, int n_total, uint32_t& n_box,
+                                           uint32_t& n_tri) {
+    const float4* nodes = reinterpret_cast<const float4*>(sc.nodes);
+    int i = 0;
+    while (i < n_total) {
+        const float4 a = nodes[2 * i];
+        const float4 b = nodes[2 * i + 1];
+        const int escape = __float_as_int(a.w);
+        const int payload = __float_as_int(b.w);
+        // skip links always point forward; anything else ends the walk
+        const int next = escape > i ? escape : n_total;
+        if (COUNT) ++n_box;
+        if (!box_hit(r, a, b)) { i = next; continue; }
+        if (payload == 0) { ++i; continue; }
+        const int first = payload >> 3;
+        const int cnt = (first + (payload & 7) <= sc.n_tris) ? (payload & 7) : 0;
+        for (int k = 0; k < cnt; ++k) {
+            const float4* t = sc.tris + 3 * (first + k);
+            if (COUNT) ++n_tri;
+            if (tri_anyhit(r, t[0], t[1], t[2])) return true;
+        }
+        i = next;
+    }
+    return false;
+}
+
+__device__ __forceinline__ bool brute_anyhit(const Scene& sc, const Ray& r) {
+    for (int64_t k = 0; k < sc.n_tris; ++k) {
+        const float4* t = sc.tris + 3 * k;
+        if (tri_anyhit(r, t[0], t[1], t[2])) return true;
+    }
+    return false;
+}
+
+}  // namespace mcdi

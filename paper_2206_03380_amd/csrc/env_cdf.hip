@@ -1,0 +1,105 @@
+// Sampling tables of the lat-long probe (piecewise-constant 2D distribution,
+// paper section 4.1 / appendix D), rebuilt whenever the probe changes.
+//
+// The weights and their running sums are FP64 and summed left to right, the
+// order the tables are defined in, so every FP32 entry is the single rounding
+// of the same FP64 value on any device; a row is one workgroup whose lanes
+// compute the weights into LDS and whose first lane runs the scan (W <= 8192
+// dependent FP64 adds, a few microseconds), rows run in parallel.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "mcdi_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace mcdi {
+namespace {
+
+constexpr double kPiD = 3.14159265358979323846;
+
+__device__ __forceinline__ double row_sin(int i, int H) { return sin(kPiD * ((double)i + 0.5) / (double)H); }
+
+__device__ __forceinline__ double texel_weight(const float* env, int W, int i, int j, double srow) {
+    const float* t = env + ((size_t)i * W + j) * 3;
+    double y = ((double)t[0] + (double)t[1] + (double)t[2]) / 3.0;
+    if (!(y > 0.0) || !isfinite(y)) y = 0.0;
+    return y * srow;
+}
+
+__global__ __launch_bounds__(256) void rows_kernel(const float* env, int H, int W, float* cond, double* rowsum) {
+    extern __shared__ double w[];  // [W]
+    __shared__ double s_sum;
+    const int i = blockIdx.x;
+    const double srow = row_sin(i, H);
+    for (int j = threadIdx.x; j < W; j += blockDim.x) w[j] = texel_weight(env, W, i, j, srow);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double run = 0.0;
+        for (int j = 0; j < W; ++j) {
+            run += w[j];
+            w[j] = run;  // inclusive prefix
+        }
+        s_sum = run;
+        rowsum[i] = run;
+    }
+    __syncthreads();
+    const double rs = s_sum;
+    float* c = cond + (size_t)i * (W + 1);
+    for (int k = threadIdx.x; k <= W; k += blockDim.x) {
+        float v;
+        if (k == 0) v = 0.0f;
+        else if (k == W) v = 1.0f;
+        else v = rs > 0.0 ? (float)(w[k - 1] / rs) : (float)((double)k / (double)W);
+        c[k] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void marginal_kernel(const double* rowsum, int H, float* marg, double* total_out,
+                                                        int32_t* light_enabled) {
+    extern __shared__ double pre[];  // [H]
+    __shared__ double s_tot;
+    if (threadIdx.x == 0) {
+        double run = 0.0;
+        for (int i = 0; i < H; ++i) {
+            run += rowsum[i];
+            pre[i] = run;
+        }
+        s_tot = run;
+        *total_out = run;
+        *light_enabled = run > 0.0 ? 1 : 0;
+    }
+    __syncthreads();
+    const double tot = s_tot;
+    for (int k = threadIdx.x; k <= H; k += blockDim.x) {
+        float v;
+        if (k == 0) v = 0.0f;
+        else if (k == H) v = 1.0f;
+        else v = tot > 0.0 ? (float)(pre[k - 1] / tot) : (float)((double)k / (double)H);
+        marg[k] = v;
+    }
+}
+
+__global__ void pdf_kernel(const float* env, int H, int W, const double* total, float* pdf) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)H * W) return;
+    const int i = (int)(k / W), j = (int)(k - (int64_t)i * W);
+    const double tot = *total;
+    const double w = texel_weight(env, W, i, j, row_sin(i, H));
+    pdf[k] = tot > 0.0 ? (float)((w / tot) * ((double)W * (double)H)) : 0.0f;
+}
+
+}  // namespace
+
+// rowsum: device scratch of H + 1 doubles (the last holds the total)
+hipError_t launch_env_cdf(const float* env, int H, int W, float* cond, float* marg, float* pdf, double* rowsum,
+                          int32_t* light_enabled, hipStream_t s) {
+    hipLaunchKernelGGL(rows_kernel, dim3(H), dim3(256), sizeof(double) * (size_t)W, s, env, H, W, cond, rowsum);
+    hipLaunchKernelGGL(marginal_kernel, dim3(1), dim3(256), sizeof(double) * (size_t)H, s, rowsum, H, marg,
+                       rowsum + H, light_enabled);
+    const int64_t n = (int64_t)H * W;
+    hipLaunchKernelGGL(pdf_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, env, H, W, rowsum + H, pdf);
+    return hipGetLastError();
+}
+
+}  // namespace mcdi

@@ -1,0 +1,97 @@
+// Internal declarations shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mcdi.h"
+
+namespace mcdi {
+
+// BVH node, 32 bytes: box, skip link and payload.  Nodes are stored in
+// depth-first pre-order, so the first child of an internal node is the next
+// node and `escape` is the index just past the node's subtree.  payload = 0
+// for an internal node; (first_triangle << 3) | count for a leaf (1..7).
+struct alignas(16) Node {
+    float lo[3];
+    int32_t escape;
+    float hi[3];
+    int32_t payload;
+};
+
+constexpr int kLeafMax = 4;
+
+struct DeviceSceneInfo {
+    int32_t n_nodes;
+    int32_t max_depth;
+    int32_t bad_tris;
+    int32_t pad;
+};
+
+struct Scene {
+    const Node* nodes;   // [>= 1]
+    const float4* tris;  // [3 * n_tris] vertex positions, w unused
+    int64_t n_tris;
+};
+
+struct EnvView {
+    int32_t H, W;
+    const float* rgb;     // [H][W][3] radiance (borrowed)
+    const float* cond;    // [H][W+1]
+    const float* marg;    // [H+1]
+    const float* pdf;     // [H][W]
+    const int32_t* light_enabled;  // device flag: total weight > 0
+};
+
+struct GBufView {
+    int32_t n_views, height, width, view_base;
+    const float *pos, *nrm, *kd, *korm;
+    const uint8_t* mask;
+    const float* eye;
+    int64_t n;  // pixels
+};
+
+struct ShadeArgs {
+    Scene scene;
+    EnvView env;
+    GBufView g;
+    int32_t spp;
+    uint32_t flags;
+    uint64_t seed;
+    float tau;
+    float ray_eps;
+    uint32_t* decisions;
+    // forward
+    float* c_d;
+    float* c_s;
+    uint32_t* hitbits_out;
+    // backward
+    const float* g_cd;
+    const float* g_cs;
+    const uint32_t* hitbits_in;
+    float* g_kd;
+    float* g_korm;
+    float* g_nrm;
+    float* g_env;
+    mcdi_stats* stats;
+};
+
+// kernel launchers (return hipError_t of the launch)
+hipError_t launch_env_cdf(const float* env, int H, int W, float* cond, float* marg, float* pdf,
+                          double* rowsum, int32_t* light_enabled, hipStream_t s);
+hipError_t launch_shade_fwd(const ShadeArgs& a, hipStream_t s);
+hipError_t launch_shade_bwd(const ShadeArgs& a, hipStream_t s);
+hipError_t launch_trace(const Scene& sc, const float* o, const float* d, int64_t n, uint8_t* hit,
+                        int brute, hipStream_t s);
+
+// BVH build: temp buffers are obtained through the callbacks
+struct TempAlloc {
+    void* (*alloc)(void* ctx, size_t bytes, hipStream_t s);
+    void (*free)(void* ctx, void* p, hipStream_t s);
+    void* ctx;
+};
+hipError_t build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                     Node* nodes_out, float4* tris_out, DeviceSceneInfo* info, const TempAlloc& ta,
+                     hipStream_t s, int* oom);
+
+}  // namespace mcdi

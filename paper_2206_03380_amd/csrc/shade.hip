@@ -1,0 +1,447 @@
+// Per-pixel Monte Carlo direct illumination on gfx950: forward (c_d, c_s and
+// shadow-ray hit bits) and the adjoint of the detached estimator.
+//
+// One lane owns one pixel and loops over its samples; each sample draws one
+// light-technique direction and one BSDF-technique direction (cosine or GGX
+// visible normals, chosen with probability q), weights both with the balance
+// heuristic over the three techniques and traces one shadow ray per
+// direction above the horizon (paper: section 3.1, section 4.1, appendix D).
+// The marginal CDF of the probe is staged in LDS; the per-pixel frame, view
+// vector and visible-normal frame are set up in FP64 once per pixel (FP64
+// FMA runs at the FP32 rate on CDNA, and it removes the ill-conditioning of
+// the tangent frame when the view is close to the normal).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "device_common.h"
+
+namespace mcdi {
+
+namespace {
+
+struct Pixel {
+    bool valid, nov_pos;
+    float3 n, t, b;        // world frame
+    float3 Vl;             // view in local frame (z = n.v)
+    float3 o;              // shadow-ray origin
+    float3 vh, t2v;        // visible-normal frame (stretched view, T2)
+    float t1x, t1y;        // T1 (z = 0)
+    float3 kd, F0;
+    float m, r, a2, alpha, q, nov, lamV, G1V, nlen;
+    bool r_active;
+};
+
+__device__ __forceinline__ bool finite3(float a, float b, float c) {
+    return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+__device__ Pixel setup_pixel(const ShadeArgs& A, int64_t pix, bool& nonfinite) {
+    const GBufView& g = A.g;
+    const int64_t N = g.n;
+    Pixel P;
+    P.valid = false;
+    P.nov_pos = false;
+    nonfinite = false;
+    if (!g.mask[pix]) return P;
+    const int64_t hw = (int64_t)g.height * g.width;
+    const int v = (int)(pix / hw);
+    const float px = g.pos[pix], py = g.pos[N + pix], pz = g.pos[2 * N + pix];
+    const float nxf = g.nrm[pix], nyf = g.nrm[N + pix], nzf = g.nrm[2 * N + pix];
+    const float kx = g.kd[pix], ky = g.kd[N + pix], kz = g.kd[2 * N + pix];
+    const float ko = g.korm[pix], kr = g.korm[N + pix], km = g.korm[2 * N + pix];
+    const float ex = g.eye[3 * v], ey = g.eye[3 * v + 1], ez = g.eye[3 * v + 2];
+    if (!(finite3(px, py, pz) && finite3(nxf, nyf, nzf) && finite3(kx, ky, kz) && finite3(ko, kr, km) &&
+          finite3(ex, ey, ez))) {
+        nonfinite = true;
+        return P;
+    }
+    if (nxf == 0.0f && nyf == 0.0f && nzf == 0.0f) return P;
+    const double wx = (double)ex - px, wy = (double)ey - py, wz = (double)ez - pz;
+    if (wx == 0.0 && wy == 0.0 && wz == 0.0) return P;
+    // FP64 setup
+    const double nl = sqrt((double)nxf * nxf + (double)nyf * nyf + (double)nzf * nzf);
+    const double nx = nxf / nl, ny = nyf / nl, nz = nzf / nl;
+    const double wl = sqrt(wx * wx + wy * wy + wz * wz);
+    const double Vx = wx / wl, Vy = wy / wl, Vz = wz / wl;
+    const double nov = nx * Vx + ny * Vy + nz * Vz;
+    const double sg = signbit(nzf) ? -1.0 : 1.0;
+    const double fa = -1.0 / (sg + nz);
+    const double fb = nx * ny * fa;
+    const double tx = 1.0 + sg * nx * nx * fa, ty = sg * fb, tz = -sg * nx;
+    const double bx = fb, by = sg + ny * ny * fa, bz = -ny;
+    const double vlx = Vx * tx + Vy * ty + Vz * tz;
+    const double vly = Vx * bx + Vy * by + Vz * bz;
+    P.valid = true;
+    P.nov_pos = nov > 0.0;
+    P.nov = (float)nov;
+    P.nlen = (float)nl;
+    P.n = f3((float)nx, (float)ny, (float)nz);
+    P.t = f3((float)tx, (float)ty, (float)tz);
+    P.b = f3((float)bx, (float)by, (float)bz);
+    P.Vl = f3((float)vlx, (float)vly, (float)nov);
+    const double eps = (double)A.ray_eps;
+    P.o = f3((float)(px + eps * nx), (float)(py + eps * ny), (float)(pz + eps * nz));
+    P.kd = f3(kx, ky, kz);
+    P.m = km;
+    P.r = kr;
+    P.r_active = kr > kRMin;
+    const float rc = P.r_active ? kr : kRMin;
+    const double al = (double)rc * (double)rc;
+    P.alpha = (float)al;
+    P.a2 = (float)(al * al);
+    P.F0 = f3(0.04f * (1.0f - km) + kx * km, 0.04f * (1.0f - km) + ky * km, 0.04f * (1.0f - km) + kz * km);
+    float q = 0.5f * (1.0f - km);
+    q = fminf(fmaxf(q, 0.0f), 1.0f);
+    if (!P.nov_pos || (A.flags & MCDI_FLAG_FORCE_COS)) q = 1.0f;
+    P.q = q;
+    // Smith Lambda of the view and the visible-normal frame (FP64)
+    if (P.nov_pos) {
+        const double t2 = (1.0 - nov * nov) / (nov * nov);
+        const double lam = 0.5 * (sqrt(1.0 + al * al * t2) - 1.0);
+        P.lamV = (float)lam;
+        P.G1V = (float)(1.0 / (1.0 + lam));
+        double hx = al * vlx, hy = al * vly, hz = nov;
+        const double hl = sqrt(hx * hx + hy * hy + hz * hz);
+        hx /= hl; hy /= hl; hz /= hl;
+        const double lensq = hx * hx + hy * hy;
+        double t1x = 1.0, t1y = 0.0;
+        if (lensq > 0.0) {
+            const double il = 1.0 / sqrt(lensq);
+            t1x = -hy * il;
+            t1y = hx * il;
+        }
+        P.vh = f3((float)hx, (float)hy, (float)hz);
+        P.t1x = (float)t1x;
+        P.t1y = (float)t1y;
+        P.t2v = f3((float)(-hz * t1y), (float)(hz * t1x), (float)(hx * t1y - hy * t1x));
+    } else {
+        P.lamV = 0.0f;
+        P.G1V = 0.0f;
+        P.vh = f3(0, 0, 1);
+        P.t1x = 1.0f;
+        P.t1y = 0.0f;
+        P.t2v = f3(0, 1, 0);
+    }
+    return P;
+}
+
+// visible-normal sample (Heitz 2018), local frame
+__device__ __forceinline__ float3 sample_vndf(const Pixel& P, float u1, float u2) {
+    const float r = sqrtf(u1);
+    float sp, cp;
+    sincospif(2.0f * u2, &sp, &cp);
+    const float a1 = r * cp;
+    float a2 = r * sp;
+    const float s = 0.5f * (1.0f + P.vh.z);
+    a2 = (1.0f - s) * sqrtf(fmaxf(0.0f, 1.0f - a1 * a1)) + s * a2;
+    const float az = sqrtf(fmaxf(0.0f, 1.0f - a1 * a1 - a2 * a2));
+    const float3 nh = f3(a1 * P.t1x + a2 * P.t2v.x + az * P.vh.x, a1 * P.t1y + a2 * P.t2v.y + az * P.vh.y,
+                         a2 * P.t2v.z + az * P.vh.z);
+    const float3 ne = normalize(f3(P.alpha * nh.x, P.alpha * nh.y, fmaxf(0.0f, nh.z)));
+    const float vn = dot(P.Vl, ne);
+    return (2.0f * vn) * ne - P.Vl;
+}
+
+struct Sample {
+    float3 wl;     // local direction
+    float3 w;      // world direction
+    float pL;      // light-technique density
+    int texel;     // probe texel index i*W + j
+};
+
+struct FwdAcc {
+    float3 cd, cs;
+};
+
+struct BwdAcc {
+    float3 gkd;
+    float gm, gr;
+    float3 gnl;  // d/dn in the local frame
+};
+
+template <bool BWD>
+__device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, const Sample& S, float Hv,
+                                            float invspp, FwdAcc& fa, BwdAcc& ba, float3 Ud, float3 Us) {
+    const float NoL = S.wl.z;
+    const float3 hl = normalize(P.Vl + S.wl);
+    const float NoH = hl.z;
+    const float s2 = hl.x * hl.x + hl.y * hl.y;
+    const float VoH = dot(P.Vl, hl);
+    const float D = ggx_D(NoH, s2, P.a2);
+    const float pcos = NoL * kInvPi;
+    const float pggx = P.nov_pos ? P.G1V * D / (4.0f * P.nov) : 0.0f;
+    const float Pt = S.pL + P.q * pcos + (1.0f - P.q) * pggx;
+    const float w = Hv / Pt;
+    const float* Lp = A.env.rgb + 3 * (size_t)S.texel;
+    const float3 L = f3(Lp[0], Lp[1], Lp[2]);
+    const float kdiff = (1.0f - P.m) * kInvPi * NoL;
+    float S_ = 0.0f, Fw = 0.0f, G2 = 0.0f, lamL = 0.0f, t2L = 0.0f;
+    float3 F = f3(0, 0, 0);
+    if (P.nov_pos) {
+        t2L = smith_t2(NoL);
+        lamL = smith_lambda(t2L, P.a2);
+        G2 = 1.0f / (1.0f + P.lamV + lamL);
+        S_ = D * G2 / (4.0f * P.nov);
+        const float omv = 1.0f - VoH;
+        const float o2 = omv * omv;
+        Fw = o2 * o2 * omv;
+        F = f3(P.F0.x + (1.0f - P.F0.x) * Fw, P.F0.y + (1.0f - P.F0.y) * Fw, P.F0.z + (1.0f - P.F0.z) * Fw);
+    }
+    if (!BWD) {
+        fa.cd = fa.cd + (kdiff * w) * L;
+        fa.cs = fa.cs + (S_ * w) * f3(F.x * L.x, F.y * L.y, F.z * L.z);
+        return;
+    }
+    const float K = w * invspp;
+    // env texel gradient: coefficient of L_c
+    const float cdc = kdiff * K, csc = S_ * K;
+    if (A.g_env) {
+        float* ge = A.g_env + 3 * (size_t)S.texel;
+        atomicAdd(ge + 0, Ud.x * cdc + Us.x * F.x * csc);
+        atomicAdd(ge + 1, Ud.y * cdc + Us.y * F.y * csc);
+        atomicAdd(ge + 2, Ud.z * cdc + Us.z * F.z * csc);
+    }
+    const float udL = Ud.x * L.x + Ud.y * L.y + Ud.z * L.z;
+    const float usL = Us.x * L.x + Us.y * L.y + Us.z * L.z;
+    const float uskdL = Us.x * P.kd.x * L.x + Us.y * P.kd.y * L.y + Us.z * P.kd.z * L.z;
+    const float usFL = Us.x * F.x * L.x + Us.y * F.y * L.y + Us.z * F.z * L.z;
+    const float omF = 1.0f - Fw;
+    ba.gkd = ba.gkd + (P.m * omF * S_ * K) * f3(Us.x * L.x, Us.y * L.y, Us.z * L.z);
+    ba.gm += -NoL * kInvPi * K * udL + omF * S_ * K * (uskdL - 0.04f * usL);
+    // diffuse part of d/dn: (1-m)/pi * udL * K * w_l
+    float3 gn = ((1.0f - P.m) * kInvPi * udL * K) * S.wl;
+    if (P.nov_pos) {
+        const float a = P.alpha, a2 = P.a2;
+        const float B = a2 * NoH * NoH + s2;
+        const float dDda = D * (2.0f / a - 4.0f * a * NoH * NoH / B);
+        const float t2V = smith_t2(P.nov);
+        const float sqV = sqrtf(1.0f + a2 * t2V), sqL = sqrtf(1.0f + a2 * t2L);
+        const float dlamV_da = a * t2V / (2.0f * sqV), dlamL_da = a * t2L / (2.0f * sqL);
+        const float G2s = G2 * G2;
+        const float dSda = (dDda * G2 - D * G2s * (dlamV_da + dlamL_da)) / (4.0f * P.nov);
+        const float dSdr = P.r_active ? dSda * 2.0f * P.r : 0.0f;
+        ba.gr += usFL * K * dSdr;
+        const float dlamV_dx = -a2 / (2.0f * P.nov * P.nov * P.nov * sqV);
+        const float dlamL_dx = -a2 / (2.0f * NoL * NoL * NoL * sqL);
+        const float dSdV = -D * G2s * dlamV_dx / (4.0f * P.nov) - S_ / P.nov;
+        const float dSdL = -D * G2s * dlamL_dx / (4.0f * P.nov);
+        const float dSdH = D * 4.0f * (1.0f - a2) * NoH / B * G2 / (4.0f * P.nov);
+        const float c = usFL * K;
+        gn = gn + (c * dSdV) * P.Vl + (c * dSdL) * S.wl + (c * dSdH) * hl;
+    }
+    ba.gnl = ba.gnl + gn;
+}
+
+template <bool BWD, bool DUMP, bool COUNT>
+__global__ __launch_bounds__(256) void shade_kernel(ShadeArgs A) {
+    extern __shared__ float s_marg[];
+    const int H = A.env.H, W = A.env.W;
+    for (int k = threadIdx.x; k <= H; k += blockDim.x) s_marg[k] = A.env.marg[k];
+    __syncthreads();
+
+    const int64_t N = A.g.n;
+    const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = pix < N;
+    uint32_t c_valid = 0, c_invalid = 0, c_rays = 0, c_hits = 0, c_culled = 0, c_box = 0, c_tri = 0;
+    const int spp = A.spp;
+    const int words = (2 * spp + 31) >> 5;
+    const bool light_on = (*A.env.light_enabled != 0) && !(A.flags & MCDI_FLAG_LIGHT_OFF);
+    const int n_total = A.scene.nodes[0].escape;
+    const bool trace = A.tau != 0.0f;
+
+    if (active) {
+        bool nonfinite;
+        const Pixel P = setup_pixel(A, pix, nonfinite);
+        c_invalid = nonfinite ? 1u : 0u;
+        if (!P.valid) {
+            if (!BWD) {
+                for (int c = 0; c < 3; ++c) { A.c_d[c * N + pix] = 0.0f; A.c_s[c * N + pix] = 0.0f; }
+                if (A.hitbits_out) for (int k = 0; k < words; ++k) A.hitbits_out[k * N + pix] = 0u;
+            } else {
+                for (int c = 0; c < 3; ++c) {
+                    A.g_kd[c * N + pix] = 0.0f; A.g_korm[c * N + pix] = 0.0f; A.g_nrm[c * N + pix] = 0.0f;
+                }
+            }
+            if (DUMP) {
+                uint32_t* d = A.decisions + (size_t)pix * spp * 3;
+                for (int s = 0; s < spp; ++s) { d[3 * s] = kNone; d[3 * s + 1] = kNone; d[3 * s + 2] = 0u; }
+            }
+        } else {
+            c_valid = 1;
+            const int64_t hw = (int64_t)A.g.height * A.g.width;
+            const uint32_t view = (uint32_t)(pix / hw), piv = (uint32_t)(pix - (int64_t)view * hw);
+            const uint32_t vid = (uint32_t)A.g.view_base + view;
+            const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
+            const float invspp = 1.0f / (float)spp;
+            float3 Ud = f3(0, 0, 0), Us = f3(0, 0, 0);
+            if (BWD) {
+                Ud = f3(A.g_cd[pix], A.g_cd[N + pix], A.g_cd[2 * N + pix]);
+                Us = f3(A.g_cs[pix], A.g_cs[N + pix], A.g_cs[2 * N + pix]);
+            }
+            FwdAcc fa{f3(0, 0, 0), f3(0, 0, 0)};
+            BwdAcc ba{f3(0, 0, 0), 0.0f, 0.0f, f3(0, 0, 0)};
+            uint32_t hw_bits = 0;
+            uint32_t in_bits = 0;
+            for (int s = 0; s < spp; ++s) {
+                if (BWD && A.hitbits_in && ((2 * s) & 31) == 0) in_bits = A.hitbits_in[((2 * s) >> 5) * N + pix];
+                const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
+                const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
+                uint32_t rec0 = kNone, rec1 = kNone;
+                uint32_t rec2 = kDecValid | (P.nov_pos ? kDecNovPos : 0u);
+                for (int tech = 0; tech < 2; ++tech) {
+                    Sample S;
+                    const uint32_t bit_cull = tech ? kDecBCull : kDecLCull;
+                    if (tech == 0) {
+                        if (!light_on) continue;
+                        const float x0 = u01(r0.x), x1 = u01(r0.y);
+                        const int i = cdf_find(s_marg, H, x0);
+                        const float* crow = A.env.cond + (size_t)i * (W + 1);
+                        const int j = cdf_find(crow, W, x1);
+                        const float m0 = s_marg[i], m1 = s_marg[i + 1];
+                        const float c0 = crow[j], c1 = crow[j + 1];
+                        const float v = ((float)i + (x0 - m0) / (m1 - m0)) / (float)H;
+                        const float u = ((float)j + (x1 - c0) / (c1 - c0)) / (float)W;
+                        float st, ct, sp, cp;
+                        sincospif(v, &st, &ct);
+                        sincospif(2.0f * u, &sp, &cp);
+                        S.w = f3(st * cp, ct, st * sp);
+                        S.texel = i * W + j;
+                        rec0 = (uint32_t)S.texel;
+                        S.pL = st > 0.0f ? A.env.pdf[S.texel] / (2.0f * kPi * kPi * st) : 0.0f;
+                        if (!(S.pL > 0.0f)) { rec2 |= kDecLCull; continue; }
+                        S.wl = f3(dot(S.w, P.t), dot(S.w, P.b), dot(S.w, P.n));
+                    } else {
+                        const float x2 = u01(r0.z), x4 = u01(r1.x), x5 = u01(r1.y);
+                        if (x2 < P.q) {
+                            rec2 |= kDecLobeCos;
+                            const float rr = sqrtf(x4);
+                            float sp, cp;
+                            sincospif(2.0f * x5, &sp, &cp);
+                            S.wl = f3(rr * cp, rr * sp, sqrtf(fmaxf(0.0f, 1.0f - x4)));
+                        } else {
+                            S.wl = sample_vndf(P, x4, x5);
+                        }
+                        S.w = normalize(S.wl.x * P.t + S.wl.y * P.b + S.wl.z * P.n);
+                        S.pL = 0.0f;
+                        S.texel = -1;
+                    }
+                    if (!(S.wl.z > 0.0f)) { rec2 |= bit_cull; ++c_culled; continue; }
+                    if (tech == 1) {
+                        const float rho = sqrtf(S.w.x * S.w.x + S.w.z * S.w.z);
+                        const float th = atan2f(rho, S.w.y);
+                        float ph = atan2f(S.w.z, S.w.x);
+                        if (ph < 0.0f) ph += 2.0f * kPi;
+                        const int ti = min((int)(th * ((float)H * kInvPi)), H - 1);
+                        const int tj = min((int)(ph * ((float)W * (0.5f * kInvPi))), W - 1);
+                        S.texel = ti * W + tj;
+                        rec1 = (uint32_t)S.texel;
+                        if (light_on && rho > 0.0f) S.pL = A.env.pdf[S.texel] / (2.0f * kPi * kPi * rho);
+                    }
+                    float Hv = 1.0f;
+                    if (trace) {
+                        const int bitpos = 2 * s + tech;
+                        bool hit;
+                        if (BWD && A.hitbits_in) {
+                            hit = (in_bits >> (bitpos & 31)) & 1u;
+                        } else {
+                            const Ray ray = make_ray(P.o, S.w);
+                            hit = bvh_anyhit<COUNT>(A.scene, ray, n_total, c_box, c_tri);
+                            ++c_rays;
+                            c_hits += hit ? 1u : 0u;
+                        }
+                        rec2 |= tech ? kDecBTraced : kDecLTraced;
+                        if (hit) {
+                            Hv = 1.0f - A.tau;
+                            hw_bits |= 1u << (bitpos & 31);
+                            rec2 |= tech ? kDecBHit : kDecLHit;
+                        }
+                    }
+                    eval_sample<BWD>(A, P, S, Hv, invspp, fa, ba, Ud, Us);
+                }
+                if (DUMP) {
+                    uint32_t* d = A.decisions + ((size_t)pix * spp + s) * 3;
+                    d[0] = rec0; d[1] = rec1; d[2] = rec2;
+                }
+                if (!BWD && A.hitbits_out && (((2 * s + 2) & 31) == 0 || s == spp - 1)) {
+                    A.hitbits_out[((2 * s) >> 5) * N + pix] = hw_bits;
+                    hw_bits = 0;
+                }
+            }
+            if (!BWD) {
+                for (int c = 0; c < 3; ++c) {
+                    A.c_d[c * N + pix] = comp(fa.cd, c) * invspp;
+                    A.c_s[c * N + pix] = comp(fa.cs, c) * invspp;
+                }
+            } else {
+                A.g_kd[pix] = ba.gkd.x; A.g_kd[N + pix] = ba.gkd.y; A.g_kd[2 * N + pix] = ba.gkd.z;
+                A.g_korm[pix] = 0.0f; A.g_korm[N + pix] = ba.gr; A.g_korm[2 * N + pix] = ba.gm;
+                const float il = 1.0f / P.nlen;
+                const float3 gw = (ba.gnl.x * il) * P.t + (ba.gnl.y * il) * P.b;
+                A.g_nrm[pix] = gw.x; A.g_nrm[N + pix] = gw.y; A.g_nrm[2 * N + pix] = gw.z;
+            }
+        }
+    }
+    if (COUNT) {
+        // wave-level reduction, one atomic per counter per wave
+        for (int off = 32; off > 0; off >>= 1) {
+            c_valid += __shfl_xor(c_valid, off);
+            c_invalid += __shfl_xor(c_invalid, off);
+            c_rays += __shfl_xor(c_rays, off);
+            c_hits += __shfl_xor(c_hits, off);
+            c_culled += __shfl_xor(c_culled, off);
+            c_box += __shfl_xor(c_box, off);
+            c_tri += __shfl_xor(c_tri, off);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (!BWD) {
+                atomicAdd(&A.stats->valid_pixels, (unsigned long long)c_valid);
+                atomicAdd(&A.stats->invalid_pixels, (unsigned long long)c_invalid);
+                atomicAdd(&A.stats->samples_culled, (unsigned long long)c_culled);
+            }
+            atomicAdd(&A.stats->rays_traced, (unsigned long long)c_rays);
+            atomicAdd(&A.stats->rays_hit, (unsigned long long)c_hits);
+            atomicAdd(&A.stats->box_tests, (unsigned long long)c_box);
+            atomicAdd(&A.stats->tri_tests, (unsigned long long)c_tri);
+        }
+    }
+}
+
+__global__ void trace_kernel(Scene sc, const float* o, const float* d, int64_t n, uint8_t* hit, int brute) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const Ray r = make_ray(f3(o[k], o[n + k], o[2 * n + k]), f3(d[k], d[n + k], d[2 * n + k]));
+    const int n_total = sc.nodes[0].escape;
+    uint32_t nb = 0, nt = 0;
+    hit[k] = (brute ? brute_anyhit(sc, r) : bvh_anyhit(sc, r, n_total, nb, nt)) ? 1 : 0;
+}
+
+}  // namespace
+
+hipError_t launch_shade_fwd(const ShadeArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)((a.g.n + 255) / 256)), block(256);
+    const size_t lds = sizeof(float) * (size_t)(a.env.H + 1);
+    const bool dump = (a.flags & MCDI_FLAG_DUMP) != 0, count = a.stats != nullptr;
+    if (dump && count) hipLaunchKernelGGL((shade_kernel<false, true, true>), grid, block, lds, s, a);
+    else if (dump) hipLaunchKernelGGL((shade_kernel<false, true, false>), grid, block, lds, s, a);
+    else if (count) hipLaunchKernelGGL((shade_kernel<false, false, true>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((shade_kernel<false, false, false>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade_bwd(const ShadeArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)((a.g.n + 255) / 256)), block(256);
+    const size_t lds = sizeof(float) * (size_t)(a.env.H + 1);
+    if (a.stats) hipLaunchKernelGGL((shade_kernel<true, false, true>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((shade_kernel<true, false, false>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(const Scene& sc, const float* o, const float* d, int64_t n, uint8_t* hit, int brute,
+                        hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(trace_kernel, dim3((unsigned)blocks), dim3(256), 0, s, sc, o, d, n, hit, brute);
+    return hipGetLastError();
+}
+
+}  // namespace mcdi

@@ -1,0 +1,55 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI
+and the oracle on the same seeded inputs, compare at the stated tolerance."""
+
+import numpy as np
+
+# c_d, c_s and per-pixel gradients: |gpu - oracle| <= REL * |oracle| + ABS * mean|oracle|
+# (per channel, valid pixels).  Derivation in the design notes: FP32 per-sample
+# terms carry ~1e-6 relative error, sums over 2*spp terms of like sign.
+REL_TOL = 1e-4
+ABS_TOL = 1e-6
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_forward(w, scene=None, env=None, gb=None, spp=None, seed=None, tau=None, dump=True, flags=0):
+    import torch
+    import paper_2206_03380_amd as M
+    dev = "cuda"
+    if scene is None:
+        scene = M.Scene(torch.from_numpy(w.verts).to(dev), torch.from_numpy(w.tris).to(dev))
+    if env is None:
+        env = M.Env(torch.from_numpy(w.env).to(dev))
+    if gb is None:
+        gb = M.GBuffer.from_workload(w, dev)
+    spp = w.spp if spp is None else spp
+    seed = w.seed if seed is None else seed
+    tau = w.tau if tau is None else tau
+    c_d, c_s, hb, dec = M.shade_fwd(scene, env, gb, spp, seed=seed, tau=tau, ray_eps=w.ray_eps,
+                                    flags=flags, decisions=dump)
+    torch.cuda.synchronize()
+    out = {"c_d": to_np(c_d), "c_s": to_np(c_s), "hitbits": to_np(hb).view(np.uint32),
+           "decisions": to_np(dec).view(np.uint32) if dec is not None else None}
+    return out, (scene, env, gb, hb)
+
+
+def hitbits_per_pixel(hb_planar):
+    """[words][N] -> [N][words]"""
+    return np.ascontiguousarray(hb_planar.T)
+
+
+def compare(gpu, orc, valid, rel=REL_TOL, absf=ABS_TOL, name=""):
+    """Return (ok, worst relative excess, report)."""
+    g = gpu[:, valid].astype(np.float64)
+    o = orc[:, valid]
+    scale = np.abs(o).mean(axis=1, keepdims=True)
+    bound = rel * np.abs(o) + absf * scale
+    err = np.abs(g - o)
+    ok = err <= bound
+    worst = float((err / np.maximum(bound, 1e-300)).max()) if err.size else 0.0
+    rep = "%s: max|err|=%.3g, max rel=%.3g, fail=%d/%d, worst/bound=%.3g" % (
+        name, err.max() if err.size else 0, (err / np.maximum(np.abs(o), 1e-30)).max() if err.size else 0,
+        int((~ok).sum()), ok.size, worst)
+    return bool(ok.all()), worst, rep
