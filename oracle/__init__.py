@@ -67,7 +67,7 @@ def lib():
         L.orc_env_tables.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
         L.orc_shade.restype = C.c_int64
         L.orc_shade.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, vp, vp, C.c_int, vp, vp, vp, vp,
-                                vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int]
+                                vp, vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int]
         L.orc_batch_philox.argtypes = [C.c_int64, vp, vp, vp]
         L.orc_batch_uniforms.argtypes = [C.c_int64, C.c_uint64, vp, vp, vp, vp]
         L.orc_batch_sample_light.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
@@ -266,12 +266,13 @@ def shade(w, pixels=None, scene=None, tables=None, spp=None, seed=None, tau=None
         ud = _c(u_d, np.float64).reshape(3, n)
         us = _c(u_s, np.float64).reshape(3, n)
         out.update(g_kd=np.zeros((3, n)), g_korm=np.zeros((3, n)), g_nrm=np.zeros((3, n)),
-                   g_env=np.zeros(tables.env.shape), s_env=np.zeros(tables.env.shape))
+                   g_env=np.zeros(tables.env.shape), s_env=np.zeros(tables.env.shape),
+                   c_env=np.zeros(tables.env.shape))
     r = L.orc_shade(scene.ptr, C.byref(tables.struct), _p(env_ev), C.byref(gs),
                     C.byref(ge) if ge is not None else None, _p(pixels), n, C.byref(prm),
                     _p(sync_arr), int(grad), _p(ud), _p(us), _p(out["c_d"]), _p(out["c_s"]),
                     _p(out.get("g_kd")), _p(out.get("g_korm")), _p(out.get("g_nrm")),
-                    _p(out.get("g_env")), _p(out.get("s_env")), _p(out["hitbits"]), hw, _p(dec),
+                    _p(out.get("g_env")), _p(out.get("s_env")), _p(out.get("c_env")), _p(out["hitbits"]), hw, _p(dec),
                     _p(out["info"]), int(threads))
     if r < 0:
         raise ValueError("oracle rejected the parameters (spp must be in [1, 512])")

@@ -705,6 +705,7 @@ typedef struct {
     int32_t texel;
     double coef[3];
     double absc[3];
+    double cond[3]; /* |term| * u / (n.l), u = 2^-24: FP32 conditioning in the cosine */
 } env_contrib;
 
 /* Per-sample evaluation at direction w.  `Ss` drives sampling-side
@@ -782,6 +783,7 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
         gns += Us[c] * F[c] * L * K;
         ec->coef[c] = Ud[c] * cdc + Us[c] * csc;
         ec->absc[c] = fabs(Ud[c] * cdc) + fabs(Us[c] * csc);
+        ec->cond[c] = ec->absc[c] * 0x1p-24 / fmax(fabs(NoL), 1e-30);
     }
     for (int k = 0; k < 3; ++k)
         out->gn[k] += gnd * w[k] + gns * (dSdNoV * Se->V[k] + dSdNoL * w[k] + dSdNoH * h[k]);
@@ -942,7 +944,7 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
                   const orc_gbuffer* gs, const orc_gbuffer* ge, const int64_t* pix, int64_t npix,
                   const orc_params* prm, const uint32_t* sync, int grad, const double* Ud,
                   const double* Us, double* cd, double* cs, double* gkd, double* gkorm, double* gn,
-                  double* genv, double* senv, uint32_t* hitbits, int32_t hit_words,
+                  double* genv, double* senv, double* cenv, uint32_t* hitbits, int32_t hit_words,
                   uint32_t* dec_out, int32_t* info, int nthreads)
 {
     shade_ctx C = {scene, env_s, env_eval, gs, ge, prm, sync, dec_out};
@@ -985,6 +987,7 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
             for (int c = 0; c < 3; ++c) {
                 genv[(size_t)all[k].texel * 3 + c] += all[k].coef[c];
                 if (senv) senv[(size_t)all[k].texel * 3 + c] += all[k].absc[c];
+                if (cenv) cenv[(size_t)all[k].texel * 3 + c] += all[k].cond[c];
             }
         }
         free(all);

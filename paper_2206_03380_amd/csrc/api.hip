@@ -85,6 +85,9 @@ struct mcdi_env_s {
     float* pdf = nullptr;
     double* rowsum = nullptr;  // [H + 1]
     int32_t* light = nullptr;
+    int32_t* hot_slot = nullptr;   // [H*W]
+    int32_t* hot_texel = nullptr;  // [kHotMax]
+    int32_t* n_hot = nullptr;
 };
 
 extern "C" {
@@ -170,11 +173,16 @@ mcdi_status mcdi_build_env_cdf(const float* env_rgb, int32_t H, int32_t W, const
     ev->pdf = (float*)ev->alloc.get(sizeof(float) * (size_t)H * W, s);
     ev->rowsum = (double*)ev->alloc.get(sizeof(double) * (size_t)(H + 1), s);
     ev->light = (int32_t*)ev->alloc.get(sizeof(int32_t), s);
-    if (!ev->cond || !ev->marg || !ev->pdf || !ev->rowsum || !ev->light) {
+    ev->hot_slot = (int32_t*)ev->alloc.get(sizeof(int32_t) * (size_t)H * W, s);
+    ev->hot_texel = (int32_t*)ev->alloc.get(sizeof(int32_t) * kHotMax, s);
+    ev->n_hot = (int32_t*)ev->alloc.get(sizeof(int32_t), s);
+    if (!ev->cond || !ev->marg || !ev->pdf || !ev->rowsum || !ev->light || !ev->hot_slot || !ev->hot_texel ||
+        !ev->n_hot) {
         mcdi_destroy_env(ev);
         return fail(MCDI_E_OOM, "mcdi_build_env_cdf: device allocation failed");
     }
     hipError_t e = launch_env_cdf(env_rgb, H, W, ev->cond, ev->marg, ev->pdf, ev->rowsum, ev->light, s);
+    if (e == hipSuccess) e = launch_env_hot(ev->pdf, H, W, ev->hot_slot, ev->hot_texel, ev->n_hot, s);
     if (e != hipSuccess) {
         mcdi_destroy_env(ev);
         return fail(MCDI_E_DEVICE, "mcdi_build_env_cdf: %s", hipGetErrorString(e));
@@ -190,6 +198,9 @@ void mcdi_destroy_env(mcdi_env ev) {
     ev->alloc.put(ev->pdf, ev->stream);
     ev->alloc.put(ev->rowsum, ev->stream);
     ev->alloc.put(ev->light, ev->stream);
+    ev->alloc.put(ev->hot_slot, ev->stream);
+    ev->alloc.put(ev->hot_texel, ev->stream);
+    ev->alloc.put(ev->n_hot, ev->stream);
     delete ev;
 }
 
@@ -221,7 +232,8 @@ static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, cons
         return fail(MCDI_E_INVALID, "%s: MCDI_FLAG_DUMP without a decisions buffer", who);
     std::memset(&a, 0, sizeof(a));
     a.scene = Scene{sc->nodes, sc->tris, sc->n_tris};
-    a.env = EnvView{ev->H, ev->W, ev->rgb, ev->cond, ev->marg, ev->pdf, ev->light};
+    a.env = EnvView{ev->H, ev->W, ev->rgb, ev->cond, ev->marg, ev->pdf, ev->light, ev->hot_slot, ev->hot_texel,
+                    ev->n_hot};
     a.g = GBufView{g->n_views, g->height, g->width, g->view_base, g->pos, g->nrm, g->kd, g->korm, g->mask, g->eye, n};
     a.spp = p->spp;
     a.flags = p->flags;
@@ -232,17 +244,64 @@ static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, cons
     return MCDI_OK;
 }
 
+// Ray queue workspace of the forward pipeline, from the scene's allocator.
+struct Workspace {
+    const Alloc* alloc = nullptr;
+    hipStream_t s = nullptr;
+    void* base = nullptr;
+    ~Workspace() {
+        if (base) alloc->put(base, s);
+    }
+};
+
+static mcdi_status trace_pipeline(const char* who, mcdi_scene sc, ShadeArgs& a, uint32_t* hitbits, hipStream_t s,
+                                  Workspace& ws, uint32_t** bits_out) {
+    const int64_t n = a.g.n;
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    const size_t words = (size_t)((2 * a.spp + 31) / 32);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t sz_rays = a.tau != 0.0f ? al(sizeof(float4) * (size_t)blocks * 2 * a.spp * kBlock) : 0;
+    const size_t sz_cnt = al(sizeof(int32_t) * (size_t)blocks);
+    const size_t sz_org = al(sizeof(float4) * (size_t)n);
+    const size_t sz_bits = hitbits ? 0 : al(sizeof(uint32_t) * words * (size_t)n);
+    ws.alloc = &sc->alloc;
+    ws.s = s;
+    ws.base = sc->alloc.get(sz_rays + sz_cnt + sz_org + sz_bits, s);
+    if (!ws.base) return fail(MCDI_E_OOM, "%s: workspace allocation failed", who);
+    char* p = (char*)ws.base;
+    a.rays = sz_rays ? (float4*)p : nullptr;
+    p += sz_rays;
+    a.ray_count = (int32_t*)p;
+    p += sz_cnt;
+    a.origins = (float4*)p;
+    p += sz_org;
+    uint32_t* bits = hitbits ? hitbits : (uint32_t*)p;
+    // the generator needs a ray region even when nothing is traced
+    ShadeArgs g = a;
+    if (!g.rays) g.tau = 0.0f;
+    hipError_t e = launch_gen_rays(g, bits, s);
+    if (e == hipSuccess && a.tau != 0.0f) e = launch_trace_rays(a, bits, s);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    *bits_out = bits;
+    return MCDI_OK;
+}
+
 mcdi_status mcdi_shade_fwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, const mcdi_params* p, float* c_d,
                            float* c_s, uint32_t* hitbits, mcdi_stats* stats, void* stream) {
     ShadeArgs a;
     mcdi_status st = fill_common("mcdi_shade_fwd", sc, ev, g, p, a);
     if (st != MCDI_OK) return st;
     if (!c_d || !c_s) return fail(MCDI_E_INVALID, "mcdi_shade_fwd: NULL c_d/c_s");
+    hipStream_t s = (hipStream_t)stream;
     a.c_d = c_d;
     a.c_s = c_s;
-    a.hitbits_out = hitbits;
     a.stats = stats;
-    hipError_t e = launch_shade_fwd(a, (hipStream_t)stream);
+    Workspace ws;
+    uint32_t* bits = nullptr;
+    st = trace_pipeline("mcdi_shade_fwd", sc, a, hitbits, s, ws, &bits);
+    if (st != MCDI_OK) return st;
+    a.hitbits_in = bits;
+    hipError_t e = launch_shade_fwd(a, s);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_fwd: %s", hipGetErrorString(e));
     return ok();
 }
@@ -256,15 +315,25 @@ mcdi_status mcdi_shade_bwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, co
     if (p->flags & MCDI_FLAG_DUMP) return fail(MCDI_E_INVALID, "mcdi_shade_bwd: MCDI_FLAG_DUMP is forward-only");
     if (!g_cd || !g_cs || !g_kd || !g_korm || !g_nrm)
         return fail(MCDI_E_INVALID, "mcdi_shade_bwd: NULL gradient buffer");
+    hipStream_t s = (hipStream_t)stream;
     a.g_cd = g_cd;
     a.g_cs = g_cs;
-    a.hitbits_in = hitbits;
     a.g_kd = g_kd;
     a.g_korm = g_korm;
     a.g_nrm = g_nrm;
     a.g_env = g_env;
     a.stats = stats;
-    hipError_t e = launch_shade_bwd(a, (hipStream_t)stream);
+    Workspace ws;
+    if (hitbits) {
+        a.hitbits_in = hitbits;
+    } else {
+        // re-trace: same rays as the forward pass
+        uint32_t* bits = nullptr;
+        st = trace_pipeline("mcdi_shade_bwd", sc, a, nullptr, s, ws, &bits);
+        if (st != MCDI_OK) return st;
+        a.hitbits_in = bits;
+    }
+    hipError_t e = launch_shade_bwd(a, s);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd: %s", hipGetErrorString(e));
     return ok();
 }

@@ -89,7 +89,36 @@ __global__ void pdf_kernel(const float* env, int H, int W, const double* total, 
     pdf[k] = tot > 0.0 ? (float)((w / tot) * ((double)W * (double)H)) : 0.0f;
 }
 
+// Texels the light technique samples with probability above 1/kHotMax get a
+// slot (at most kHotMax of them, since the probabilities sum to 1): the
+// adjoint accumulates their gradient per workgroup in LDS before one global
+// atomic per slot and workgroup.
+__global__ void hot_init(int32_t* n_hot) { *n_hot = 0; }
+
+__global__ void hot_kernel(const float* pdf, int H, int W, int32_t* hot_slot, int32_t* hot_texel,
+                           int32_t* n_hot) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)H * W) return;
+    const float p = pdf[k] / ((float)W * (float)H);
+    int32_t slot = -1;
+    if (p > 1.0f / (float)kHotMax) {
+        slot = atomicAdd(n_hot, 1);
+        if (slot < kHotMax) hot_texel[slot] = (int32_t)k;
+        else slot = -1;
+    }
+    hot_slot[k] = slot;
+}
+
 }  // namespace
+
+hipError_t launch_env_hot(const float* pdf, int H, int W, int32_t* hot_slot, int32_t* hot_texel, int32_t* n_hot,
+                          hipStream_t s) {
+    const int64_t n = (int64_t)H * W;
+    hipLaunchKernelGGL(hot_init, dim3(1), dim3(1), 0, s, n_hot);
+    hipLaunchKernelGGL(hot_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pdf, H, W, hot_slot,
+                       hot_texel, n_hot);
+    return hipGetLastError();
+}
 
 // rowsum: device scratch of H + 1 doubles (the last holds the total)
 hipError_t launch_env_cdf(const float* env, int H, int W, float* cond, float* marg, float* pdf, double* rowsum,

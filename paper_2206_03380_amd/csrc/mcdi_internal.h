@@ -20,6 +20,8 @@ struct alignas(16) Node {
 };
 
 constexpr int kLeafMax = 4;
+constexpr int kHotMax = 1024;   // probe texels privatised in LDS by the adjoint
+constexpr int kBlock = 256;     // pixels per workgroup in the shading kernels
 
 struct DeviceSceneInfo {
     int32_t n_nodes;
@@ -41,6 +43,9 @@ struct EnvView {
     const float* marg;    // [H+1]
     const float* pdf;     // [H][W]
     const int32_t* light_enabled;  // device flag: total weight > 0
+    const int32_t* hot_slot;       // [H*W] LDS slot of a hot texel or -1
+    const int32_t* hot_texel;      // [kHotMax] texel of each slot
+    const int32_t* n_hot;          // number of hot texels (<= kHotMax)
 };
 
 struct GBufView {
@@ -74,11 +79,21 @@ struct ShadeArgs {
     float* g_nrm;
     float* g_env;
     mcdi_stats* stats;
+    // forward ray queue (one region of 2*spp*kBlock rays per workgroup)
+    float4* rays;          // (direction, local pixel | slot << 8)
+    int32_t* ray_count;    // [blocks]
+    float4* origins;       // [N]
 };
 
 // kernel launchers (return hipError_t of the launch)
 hipError_t launch_env_cdf(const float* env, int H, int W, float* cond, float* marg, float* pdf,
                           double* rowsum, int32_t* light_enabled, hipStream_t s);
+hipError_t launch_env_hot(const float* pdf, int H, int W, int32_t* hot_slot, int32_t* hot_texel, int32_t* n_hot,
+                          hipStream_t s);
+// forward = gen_rays -> trace_rays -> shade; hit bits are produced by the
+// first two and read by the third
+hipError_t launch_gen_rays(const ShadeArgs& a, uint32_t* hitbits, hipStream_t s);
+hipError_t launch_trace_rays(const ShadeArgs& a, uint32_t* hitbits, hipStream_t s);
 hipError_t launch_shade_fwd(const ShadeArgs& a, hipStream_t s);
 hipError_t launch_shade_bwd(const ShadeArgs& a, hipStream_t s);
 hipError_t launch_trace(const Scene& sc, const float* o, const float* d, int64_t n, uint8_t* hit,

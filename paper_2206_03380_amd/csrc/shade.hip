@@ -159,9 +159,64 @@ struct BwdAcc {
     float3 gnl;  // d/dn in the local frame
 };
 
+// Light technique: piecewise-constant 2D distribution over the probe.
+// Returns false when the sample has no density (direction at a pole).
+__device__ __forceinline__ bool draw_light(const ShadeArgs& A, const Pixel& P, const float* s_marg, uint4 r0,
+                                           Sample& S) {
+    const int H = A.env.H, W = A.env.W;
+    const float x0 = u01(r0.x), x1 = u01(r0.y);
+    const int i = cdf_find(s_marg, H, x0);
+    const float* crow = A.env.cond + (size_t)i * (W + 1);
+    const int j = cdf_find(crow, W, x1);
+    const float m0 = s_marg[i], m1 = s_marg[i + 1];
+    const float c0 = crow[j], c1 = crow[j + 1];
+    const float v = ((float)i + (x0 - m0) / (m1 - m0)) / (float)H;
+    const float u = ((float)j + (x1 - c0) / (c1 - c0)) / (float)W;
+    float st, ct, sp, cp;
+    sincospif(v, &st, &ct);
+    sincospif(2.0f * u, &sp, &cp);
+    S.w = f3(st * cp, ct, st * sp);
+    S.texel = i * W + j;
+    S.pL = st > 0.0f ? A.env.pdf[S.texel] / (2.0f * kPi * kPi * st) : 0.0f;
+    S.wl = f3(dot(S.w, P.t), dot(S.w, P.b), dot(S.w, P.n));
+    return S.pL > 0.0f;
+}
+
+// BSDF technique: cosine lobe with probability q, else GGX visible normals.
+__device__ __forceinline__ bool draw_bsdf(const Pixel& P, uint4 r0, uint4 r1, Sample& S) {
+    const float x2 = u01(r0.z), x4 = u01(r1.x), x5 = u01(r1.y);
+    const bool cosl = x2 < P.q;
+    if (cosl) {
+        const float rr = sqrtf(x4);
+        float sp, cp;
+        sincospif(2.0f * x5, &sp, &cp);
+        S.wl = f3(rr * cp, rr * sp, sqrtf(fmaxf(0.0f, 1.0f - x4)));
+    } else {
+        S.wl = sample_vndf(P, x4, x5);
+    }
+    S.w = normalize(S.wl.x * P.t + S.wl.y * P.b + S.wl.z * P.n);
+    S.pL = 0.0f;
+    S.texel = -1;
+    return cosl;
+}
+
+// probe texel (nearest) of a BSDF-sampled direction and its light density
+__device__ __forceinline__ void bsdf_texel(const ShadeArgs& A, bool light_on, Sample& S) {
+    const int H = A.env.H, W = A.env.W;
+    const float rho = sqrtf(S.w.x * S.w.x + S.w.z * S.w.z);
+    const float th = atan2f(rho, S.w.y);
+    float ph = atan2f(S.w.z, S.w.x);
+    if (ph < 0.0f) ph += 2.0f * kPi;
+    const int ti = min((int)(th * ((float)H * kInvPi)), H - 1);
+    const int tj = min((int)(ph * ((float)W * (0.5f * kInvPi))), W - 1);
+    S.texel = ti * W + tj;
+    if (light_on && rho > 0.0f) S.pL = A.env.pdf[S.texel] / (2.0f * kPi * kPi * rho);
+}
+
 template <bool BWD>
 __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, const Sample& S, float Hv,
-                                            float invspp, FwdAcc& fa, BwdAcc& ba, float3 Ud, float3 Us) {
+                                            float invspp, FwdAcc& fa, BwdAcc& ba, float3 Ud, float3 Us,
+                                            float* s_hot) {
     const float NoL = S.wl.z;
     const float3 hl = normalize(P.Vl + S.wl);
     const float NoH = hl.z;
@@ -193,13 +248,24 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
         return;
     }
     const float K = w * invspp;
-    // env texel gradient: coefficient of L_c
+    // probe texel gradient: coefficient of L_c; hot texels go to the
+    // workgroup's LDS copy, the rest straight to global memory
     const float cdc = kdiff * K, csc = S_ * K;
     if (A.g_env) {
-        float* ge = A.g_env + 3 * (size_t)S.texel;
-        atomicAdd(ge + 0, Ud.x * cdc + Us.x * F.x * csc);
-        atomicAdd(ge + 1, Ud.y * cdc + Us.y * F.y * csc);
-        atomicAdd(ge + 2, Ud.z * cdc + Us.z * F.z * csc);
+        const float v0 = Ud.x * cdc + Us.x * F.x * csc;
+        const float v1 = Ud.y * cdc + Us.y * F.y * csc;
+        const float v2 = Ud.z * cdc + Us.z * F.z * csc;
+        const int slot = A.env.hot_slot[S.texel];
+        if (slot >= 0) {
+            atomicAdd(s_hot + 3 * slot + 0, v0);
+            atomicAdd(s_hot + 3 * slot + 1, v1);
+            atomicAdd(s_hot + 3 * slot + 2, v2);
+        } else {
+            float* ge = A.g_env + 3 * (size_t)S.texel;
+            atomicAdd(ge + 0, v0);
+            atomicAdd(ge + 1, v1);
+            atomicAdd(ge + 2, v2);
+        }
     }
     const float udL = Ud.x * L.x + Ud.y * L.y + Ud.z * L.z;
     const float usL = Us.x * L.x + Us.y * L.y + Us.z * L.z;
@@ -232,31 +298,213 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
     ba.gnl = ba.gnl + gn;
 }
 
-template <bool BWD, bool DUMP, bool COUNT>
-__global__ __launch_bounds__(256) void shade_kernel(ShadeArgs A) {
-    extern __shared__ float s_marg[];
-    const int H = A.env.H, W = A.env.W;
-    for (int k = threadIdx.x; k <= H; k += blockDim.x) s_marg[k] = A.env.marg[k];
-    __syncthreads();
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
 
+__device__ __forceinline__ void stage_marg(const ShadeArgs& A, float* s_marg) {
+    for (int k = threadIdx.x; k <= A.env.H; k += blockDim.x) s_marg[k] = A.env.marg[k];
+}
+
+// ---------------------------------------------------------------------------
+// 1) ray generation: the directions of every sample above the horizon,
+//    compacted per workgroup into its own queue region (LDS counter, no
+//    global atomics); hit words of the workgroup's pixels are cleared.
+// ---------------------------------------------------------------------------
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void gen_rays_kernel(ShadeArgs A, uint32_t* hitbits) {
+    extern __shared__ float s_marg[];
+    __shared__ int s_cnt;
+    stage_marg(A, s_marg);
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
     const int64_t N = A.g.n;
-    const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool active = pix < N;
-    uint32_t c_valid = 0, c_invalid = 0, c_rays = 0, c_hits = 0, c_culled = 0, c_box = 0, c_tri = 0;
     const int spp = A.spp;
     const int words = (2 * spp + 31) >> 5;
     const bool light_on = (*A.env.light_enabled != 0) && !(A.flags & MCDI_FLAG_LIGHT_OFF);
-    const int n_total = A.scene.nodes[0].escape;
+    const bool trace = A.tau != 0.0f;
+    bool nonfinite = false;
+    Pixel P;
+    P.valid = false;
+    if (active) {
+        for (int k = 0; k < words; ++k) hitbits[k * N + pix] = 0u;
+        P = setup_pixel(A, pix, nonfinite);
+        if (P.valid) A.origins[pix] = make_float4(P.o.x, P.o.y, P.o.z, 0.0f);
+    }
+    const bool go = P.valid && trace;
+    const int64_t hw = (int64_t)A.g.height * A.g.width;
+    const uint32_t view = active ? (uint32_t)(pix / hw) : 0u;
+    const uint32_t piv = active ? (uint32_t)(pix - (int64_t)view * hw) : 0u;
+    const uint32_t vid = (uint32_t)A.g.view_base + view;
+    const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
+    float4* region = A.rays + (size_t)blockIdx.x * (size_t)(2 * spp * kBlock);
+    const int lane = __lane_id();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t c_rays = 0, c_culled = 0;
+    for (int s = 0; s < spp; ++s) {
+        uint4 r0 = make_uint4(0, 0, 0, 0), r1 = r0;
+        if (go) {
+            r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
+            r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
+        }
+        for (int tech = 0; tech < 2; ++tech) {
+            bool want = false;
+            Sample S;
+            if (go) {
+                bool has = true;
+                if (tech == 0) has = light_on && draw_light(A, P, s_marg, r0, S);
+                else draw_bsdf(P, r0, r1, S);
+                want = has && S.wl.z > 0.0f;
+                if (has && !want) ++c_culled;
+            }
+            const uint64_t bal = __ballot(want);
+            if (bal == 0ull) continue;
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_cnt, (int)__popcll(bal));
+            base = __shfl(base, 0);
+            if (want) {
+                const int slot = 2 * s + tech;
+                const uint32_t tag = (uint32_t)threadIdx.x | ((uint32_t)slot << 8);
+                region[base + (int)__popcll(bal & lt)] = make_float4(S.w.x, S.w.y, S.w.z, __uint_as_float(tag));
+                ++c_rays;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) A.ray_count[blockIdx.x] = s_cnt;
+    if (COUNT) {
+        const uint32_t a = wave_sum(c_rays), b = wave_sum(c_culled);
+        const uint32_t v = wave_sum(P.valid ? 1u : 0u), nf = wave_sum(nonfinite ? 1u : 0u);
+        if (lane == 0) {
+            atomicAdd(&A.stats->rays_traced, (unsigned long long)a);
+            atomicAdd(&A.stats->samples_culled, (unsigned long long)b);
+            atomicAdd(&A.stats->valid_pixels, (unsigned long long)v);
+            atomicAdd(&A.stats->invalid_pixels, (unsigned long long)nf);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2) any-hit traversal of a workgroup's ray queue.  Lanes that finish a ray
+//    take the next one from the queue (one LDS atomic per wave per refill), so
+//    a wave keeps all its lanes busy while its rays have very different
+//    lengths (persistent "while-while" traversal with dynamic fetch).
+// ---------------------------------------------------------------------------
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_t* hitbits) {
+    __shared__ int s_next;
+    if (threadIdx.x == 0) s_next = 0;
+    __syncthreads();
+    const Scene& sc = A.scene;
+    const int64_t N = A.g.n;
+    const int count = A.ray_count[blockIdx.x];
+    const float4* R = A.rays + (size_t)blockIdx.x * (size_t)(2 * A.spp * kBlock);
+    const int64_t base_pix = (int64_t)blockIdx.x * kBlock;
+    const int n_total = sc.nodes[0].escape;
+    const float4* nodes = reinterpret_cast<const float4*>(sc.nodes);
+    const int lane = __lane_id();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool active = false, exhausted = false;
+    Ray ray;
+    int node = 0;
+    int64_t pix = 0;
+    int slot = 0;
+    uint32_t c_hits = 0, c_box = 0, c_tri = 0;
+    while (true) {
+        const uint64_t need = __ballot(!active && !exhausted);
+        if (need) {
+            const int leader = __ffsll((unsigned long long)need) - 1;
+            int b = 0;
+            if (lane == leader) b = atomicAdd(&s_next, (int)__popcll(need));
+            b = __shfl(b, leader);
+            if (!active && !exhausted) {
+                const int idx = b + (int)__popcll(need & lt);
+                if (idx < count) {
+                    const float4 rr = R[idx];
+                    const uint32_t tag = __float_as_uint(rr.w);
+                    pix = base_pix + (tag & 255u);
+                    slot = (int)(tag >> 8);
+                    const float4 o = A.origins[pix];
+                    ray = make_ray(f3(o.x, o.y, o.z), f3(rr.x, rr.y, rr.z));
+                    node = 0;
+                    active = true;
+                } else {
+                    exhausted = true;
+                }
+            }
+        }
+        if (!__any(active)) break;
+        if (active) {
+            bool done = node >= n_total, hit = false;
+            if (!done) {
+                const float4 a = nodes[2 * node];
+                const float4 b = nodes[2 * node + 1];
+                const int escape = __float_as_int(a.w);
+                const int payload = __float_as_int(b.w);
+                const int next = escape > node ? escape : n_total;
+                if (COUNT) ++c_box;
+                if (!box_hit(ray, a, b)) {
+                    node = next;
+                } else if (payload == 0) {
+                    ++node;
+                } else {
+                    const int first = payload >> 3;
+                    const int cnt = (first + (payload & 7) <= sc.n_tris) ? (payload & 7) : 0;
+                    for (int k = 0; k < cnt && !hit; ++k) {
+                        const float4* t = sc.tris + 3 * (first + k);
+                        if (COUNT) ++c_tri;
+                        hit = tri_anyhit(ray, t[0], t[1], t[2]);
+                    }
+                    node = next;
+                }
+                done = hit || node >= n_total;
+            }
+            if (done) {
+                if (hit) {
+                    atomicOr(hitbits + (int64_t)(slot >> 5) * N + pix, 1u << (slot & 31));
+                    ++c_hits;
+                }
+                active = false;
+            }
+        }
+    }
+    if (COUNT) {
+        const uint32_t h = wave_sum(c_hits), bx = wave_sum(c_box), tr = wave_sum(c_tri);
+        if (lane == 0) {
+            atomicAdd(&A.stats->rays_hit, (unsigned long long)h);
+            atomicAdd(&A.stats->box_tests, (unsigned long long)bx);
+            atomicAdd(&A.stats->tri_tests, (unsigned long long)tr);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3) evaluation: forward values or the adjoint, from the hit bits.
+// ---------------------------------------------------------------------------
+template <bool BWD, bool DUMP>
+__global__ __launch_bounds__(kBlock) void shade_kernel(ShadeArgs A) {
+    extern __shared__ float smem[];
+    float* s_marg = smem;
+    float* s_hot = smem + ((A.env.H + 1 + 3) & ~3);
+    stage_marg(A, s_marg);
+    if (BWD) for (int k = threadIdx.x; k < 3 * kHotMax; k += blockDim.x) s_hot[k] = 0.0f;
+    __syncthreads();
+
+    const int64_t N = A.g.n;
+    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int spp = A.spp;
+    const bool light_on = (*A.env.light_enabled != 0) && !(A.flags & MCDI_FLAG_LIGHT_OFF);
     const bool trace = A.tau != 0.0f;
 
-    if (active) {
+    if (pix < N) {
         bool nonfinite;
         const Pixel P = setup_pixel(A, pix, nonfinite);
-        c_invalid = nonfinite ? 1u : 0u;
         if (!P.valid) {
             if (!BWD) {
                 for (int c = 0; c < 3; ++c) { A.c_d[c * N + pix] = 0.0f; A.c_s[c * N + pix] = 0.0f; }
-                if (A.hitbits_out) for (int k = 0; k < words; ++k) A.hitbits_out[k * N + pix] = 0u;
             } else {
                 for (int c = 0; c < 3; ++c) {
                     A.g_kd[c * N + pix] = 0.0f; A.g_korm[c * N + pix] = 0.0f; A.g_nrm[c * N + pix] = 0.0f;
@@ -267,7 +515,6 @@ __global__ __launch_bounds__(256) void shade_kernel(ShadeArgs A) {
                 for (int s = 0; s < spp; ++s) { d[3 * s] = kNone; d[3 * s + 1] = kNone; d[3 * s + 2] = 0u; }
             }
         } else {
-            c_valid = 1;
             const int64_t hw = (int64_t)A.g.height * A.g.width;
             const uint32_t view = (uint32_t)(pix / hw), piv = (uint32_t)(pix - (int64_t)view * hw);
             const uint32_t vid = (uint32_t)A.g.view_base + view;
@@ -280,91 +527,42 @@ __global__ __launch_bounds__(256) void shade_kernel(ShadeArgs A) {
             }
             FwdAcc fa{f3(0, 0, 0), f3(0, 0, 0)};
             BwdAcc ba{f3(0, 0, 0), 0.0f, 0.0f, f3(0, 0, 0)};
-            uint32_t hw_bits = 0;
-            uint32_t in_bits = 0;
+            uint32_t bits = 0;
             for (int s = 0; s < spp; ++s) {
-                if (BWD && A.hitbits_in && ((2 * s) & 31) == 0) in_bits = A.hitbits_in[((2 * s) >> 5) * N + pix];
+                if (((2 * s) & 31) == 0) bits = A.hitbits_in[((2 * s) >> 5) * N + pix];
                 const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
                 const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
                 uint32_t rec0 = kNone, rec1 = kNone;
                 uint32_t rec2 = kDecValid | (P.nov_pos ? kDecNovPos : 0u);
                 for (int tech = 0; tech < 2; ++tech) {
                     Sample S;
-                    const uint32_t bit_cull = tech ? kDecBCull : kDecLCull;
                     if (tech == 0) {
                         if (!light_on) continue;
-                        const float x0 = u01(r0.x), x1 = u01(r0.y);
-                        const int i = cdf_find(s_marg, H, x0);
-                        const float* crow = A.env.cond + (size_t)i * (W + 1);
-                        const int j = cdf_find(crow, W, x1);
-                        const float m0 = s_marg[i], m1 = s_marg[i + 1];
-                        const float c0 = crow[j], c1 = crow[j + 1];
-                        const float v = ((float)i + (x0 - m0) / (m1 - m0)) / (float)H;
-                        const float u = ((float)j + (x1 - c0) / (c1 - c0)) / (float)W;
-                        float st, ct, sp, cp;
-                        sincospif(v, &st, &ct);
-                        sincospif(2.0f * u, &sp, &cp);
-                        S.w = f3(st * cp, ct, st * sp);
-                        S.texel = i * W + j;
+                        const bool has = draw_light(A, P, s_marg, r0, S);
                         rec0 = (uint32_t)S.texel;
-                        S.pL = st > 0.0f ? A.env.pdf[S.texel] / (2.0f * kPi * kPi * st) : 0.0f;
-                        if (!(S.pL > 0.0f)) { rec2 |= kDecLCull; continue; }
-                        S.wl = f3(dot(S.w, P.t), dot(S.w, P.b), dot(S.w, P.n));
+                        if (!has) { rec2 |= kDecLCull; continue; }
                     } else {
-                        const float x2 = u01(r0.z), x4 = u01(r1.x), x5 = u01(r1.y);
-                        if (x2 < P.q) {
-                            rec2 |= kDecLobeCos;
-                            const float rr = sqrtf(x4);
-                            float sp, cp;
-                            sincospif(2.0f * x5, &sp, &cp);
-                            S.wl = f3(rr * cp, rr * sp, sqrtf(fmaxf(0.0f, 1.0f - x4)));
-                        } else {
-                            S.wl = sample_vndf(P, x4, x5);
-                        }
-                        S.w = normalize(S.wl.x * P.t + S.wl.y * P.b + S.wl.z * P.n);
-                        S.pL = 0.0f;
-                        S.texel = -1;
+                        if (draw_bsdf(P, r0, r1, S)) rec2 |= kDecLobeCos;
                     }
-                    if (!(S.wl.z > 0.0f)) { rec2 |= bit_cull; ++c_culled; continue; }
+                    if (!(S.wl.z > 0.0f)) { rec2 |= tech ? kDecBCull : kDecLCull; continue; }
                     if (tech == 1) {
-                        const float rho = sqrtf(S.w.x * S.w.x + S.w.z * S.w.z);
-                        const float th = atan2f(rho, S.w.y);
-                        float ph = atan2f(S.w.z, S.w.x);
-                        if (ph < 0.0f) ph += 2.0f * kPi;
-                        const int ti = min((int)(th * ((float)H * kInvPi)), H - 1);
-                        const int tj = min((int)(ph * ((float)W * (0.5f * kInvPi))), W - 1);
-                        S.texel = ti * W + tj;
+                        bsdf_texel(A, light_on, S);
                         rec1 = (uint32_t)S.texel;
-                        if (light_on && rho > 0.0f) S.pL = A.env.pdf[S.texel] / (2.0f * kPi * kPi * rho);
                     }
                     float Hv = 1.0f;
                     if (trace) {
                         const int bitpos = 2 * s + tech;
-                        bool hit;
-                        if (BWD && A.hitbits_in) {
-                            hit = (in_bits >> (bitpos & 31)) & 1u;
-                        } else {
-                            const Ray ray = make_ray(P.o, S.w);
-                            hit = bvh_anyhit<COUNT>(A.scene, ray, n_total, c_box, c_tri);
-                            ++c_rays;
-                            c_hits += hit ? 1u : 0u;
-                        }
                         rec2 |= tech ? kDecBTraced : kDecLTraced;
-                        if (hit) {
+                        if ((bits >> (bitpos & 31)) & 1u) {
                             Hv = 1.0f - A.tau;
-                            hw_bits |= 1u << (bitpos & 31);
                             rec2 |= tech ? kDecBHit : kDecLHit;
                         }
                     }
-                    eval_sample<BWD>(A, P, S, Hv, invspp, fa, ba, Ud, Us);
+                    eval_sample<BWD>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot);
                 }
                 if (DUMP) {
                     uint32_t* d = A.decisions + ((size_t)pix * spp + s) * 3;
                     d[0] = rec0; d[1] = rec1; d[2] = rec2;
-                }
-                if (!BWD && A.hitbits_out && (((2 * s + 2) & 31) == 0 || s == spp - 1)) {
-                    A.hitbits_out[((2 * s) >> 5) * N + pix] = hw_bits;
-                    hw_bits = 0;
                 }
             }
             if (!BWD) {
@@ -381,27 +579,13 @@ __global__ __launch_bounds__(256) void shade_kernel(ShadeArgs A) {
             }
         }
     }
-    if (COUNT) {
-        // wave-level reduction, one atomic per counter per wave
-        for (int off = 32; off > 0; off >>= 1) {
-            c_valid += __shfl_xor(c_valid, off);
-            c_invalid += __shfl_xor(c_invalid, off);
-            c_rays += __shfl_xor(c_rays, off);
-            c_hits += __shfl_xor(c_hits, off);
-            c_culled += __shfl_xor(c_culled, off);
-            c_box += __shfl_xor(c_box, off);
-            c_tri += __shfl_xor(c_tri, off);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            if (!BWD) {
-                atomicAdd(&A.stats->valid_pixels, (unsigned long long)c_valid);
-                atomicAdd(&A.stats->invalid_pixels, (unsigned long long)c_invalid);
-                atomicAdd(&A.stats->samples_culled, (unsigned long long)c_culled);
-            }
-            atomicAdd(&A.stats->rays_traced, (unsigned long long)c_rays);
-            atomicAdd(&A.stats->rays_hit, (unsigned long long)c_hits);
-            atomicAdd(&A.stats->box_tests, (unsigned long long)c_box);
-            atomicAdd(&A.stats->tri_tests, (unsigned long long)c_tri);
+    if (BWD && A.g_env) {
+        // one global atomic per touched hot slot and workgroup
+        __syncthreads();
+        const int n_hot = min(*A.env.n_hot, kHotMax);
+        for (int k = threadIdx.x; k < 3 * n_hot; k += blockDim.x) {
+            const float v = s_hot[k];
+            if (v != 0.0f) atomicAdd(A.g_env + 3 * (size_t)A.env.hot_texel[k / 3] + (k % 3), v);
         }
     }
 }
@@ -417,22 +601,36 @@ __global__ void trace_kernel(Scene sc, const float* o, const float* d, int64_t n
 
 }  // namespace
 
+static unsigned n_blocks(const ShadeArgs& a) { return (unsigned)((a.g.n + kBlock - 1) / kBlock); }
+static size_t marg_lds(const ShadeArgs& a) { return sizeof(float) * (size_t)((a.env.H + 1 + 3) & ~3); }
+
+hipError_t launch_gen_rays(const ShadeArgs& a, uint32_t* hitbits, hipStream_t s) {
+    if (a.stats)
+        hipLaunchKernelGGL((gen_rays_kernel<true>), dim3(n_blocks(a)), dim3(kBlock), marg_lds(a), s, a, hitbits);
+    else
+        hipLaunchKernelGGL((gen_rays_kernel<false>), dim3(n_blocks(a)), dim3(kBlock), marg_lds(a), s, a, hitbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_rays(const ShadeArgs& a, uint32_t* hitbits, hipStream_t s) {
+    if (a.stats)
+        hipLaunchKernelGGL((trace_rays_kernel<true>), dim3(n_blocks(a)), dim3(kBlock), 0, s, a, hitbits);
+    else
+        hipLaunchKernelGGL((trace_rays_kernel<false>), dim3(n_blocks(a)), dim3(kBlock), 0, s, a, hitbits);
+    return hipGetLastError();
+}
+
 hipError_t launch_shade_fwd(const ShadeArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.g.n + 255) / 256)), block(256);
-    const size_t lds = sizeof(float) * (size_t)(a.env.H + 1);
-    const bool dump = (a.flags & MCDI_FLAG_DUMP) != 0, count = a.stats != nullptr;
-    if (dump && count) hipLaunchKernelGGL((shade_kernel<false, true, true>), grid, block, lds, s, a);
-    else if (dump) hipLaunchKernelGGL((shade_kernel<false, true, false>), grid, block, lds, s, a);
-    else if (count) hipLaunchKernelGGL((shade_kernel<false, false, true>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((shade_kernel<false, false, false>), grid, block, lds, s, a);
+    if (a.flags & MCDI_FLAG_DUMP)
+        hipLaunchKernelGGL((shade_kernel<false, true>), dim3(n_blocks(a)), dim3(kBlock), marg_lds(a), s, a);
+    else
+        hipLaunchKernelGGL((shade_kernel<false, false>), dim3(n_blocks(a)), dim3(kBlock), marg_lds(a), s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_shade_bwd(const ShadeArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.g.n + 255) / 256)), block(256);
-    const size_t lds = sizeof(float) * (size_t)(a.env.H + 1);
-    if (a.stats) hipLaunchKernelGGL((shade_kernel<true, false, true>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((shade_kernel<true, false, false>), grid, block, lds, s, a);
+    const size_t lds = marg_lds(a) + sizeof(float) * 3 * kHotMax;
+    hipLaunchKernelGGL((shade_kernel<true, false>), dim3(n_blocks(a)), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 
