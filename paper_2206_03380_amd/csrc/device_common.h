@@ -92,6 +92,11 @@ struct Ray {
 
 __device__ __forceinline__ float comp(float3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
 
+// Reciprocals use the hardware approximation (<= 1 ulp): the shear constants
+// only need to be the same for every triangle a ray meets, and the box test
+// widens t_far for the extra ulp.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 __device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
     Ray r;
     r.o = o;
@@ -101,8 +106,9 @@ __device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
     int ky = kx == 2 ? 0 : kx + 1;
     const float dz = comp(d, kz);
     if (dz < 0.0f) { const int t = kx; kx = ky; ky = t; }
-    const float sx = comp(d, kx) / dz, sy = comp(d, ky) / dz;
-    r.sz = 1.0f / dz;
+    const float rz = fast_rcp(dz);
+    const float sx = comp(d, kx) * rz, sy = comp(d, ky) * rz;
+    r.sz = rz;
     r.kz = kz;
     // rows: e_kx - sx e_kz and e_ky - sy e_kz
     r.mx = f3(kx == 0 ? 1.f : 0.f, kx == 1 ? 1.f : 0.f, kx == 2 ? 1.f : 0.f);
@@ -111,8 +117,8 @@ __device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
     if (kz == 1) { r.mx.y = -sx; r.my.y = -sy; }
     if (kz == 2) { r.mx.z = -sx; r.my.z = -sy; }
     const float tiny = 1e-30f;
-    r.inv = f3(1.0f / (d.x != 0.0f ? d.x : tiny), 1.0f / (d.y != 0.0f ? d.y : tiny),
-               1.0f / (d.z != 0.0f ? d.z : tiny));
+    r.inv = f3(fast_rcp(d.x != 0.0f ? d.x : tiny), fast_rcp(d.y != 0.0f ? d.y : tiny),
+               fast_rcp(d.z != 0.0f ? d.z : tiny));
     return r;
 }
 
@@ -141,14 +147,16 @@ __device__ __forceinline__ bool tri_anyhit(const Ray& r, float4 v0, float4 v1, f
     return det > 0.0f ? (T > 0.0f) : (T < 0.0f);
 }
 
-// Conservative slab test (Ize 2013: widen t_far by 1 + 2 gamma(3)), t >= 0.
+// Conservative slab test (Ize 2013: widen t_far by 1 + 2 gamma(n)), t >= 0;
+// n = 4 covers the subtraction, the product and the 1-ulp reciprocal, and the
+// factor is rounded up.
 __device__ __forceinline__ bool box_hit(const Ray& r, float4 a, float4 b) {
     const float tx0 = (a.x - r.o.x) * r.inv.x, tx1 = (b.x - r.o.x) * r.inv.x;
     const float ty0 = (a.y - r.o.y) * r.inv.y, ty1 = (b.y - r.o.y) * r.inv.y;
     const float tz0 = (a.z - r.o.z) * r.inv.z, tz1 = (b.z - r.o.z) * r.inv.z;
     const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
     const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
-    return tn <= tf * 1.00000036f;
+    return tn <= tf * 1.000001f;
 }
 
 // Stackless any-hit traversal over the pre-order BVH with skip links.

@@ -410,12 +410,15 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_
     bool active = false, exhausted = false;
     Ray ray;
     int node = 0;
+    int tri = 0, tri_end = 0;   // pending leaf: triangles [tri, tri_end)
     int64_t pix = 0;
     int slot = 0;
     uint32_t c_hits = 0, c_box = 0, c_tri = 0;
     while (true) {
+        // refill when a quarter of the wave is idle, or when nobody is busy
         const uint64_t need = __ballot(!active && !exhausted);
-        if (need) {
+        const uint64_t busy = __ballot(active);
+        if (need && (__popcll(need) >= 16 || busy == 0ull)) {
             const int leader = __ffsll((unsigned long long)need) - 1;
             int b = 0;
             if (lane == leader) b = atomicAdd(&s_next, (int)__popcll(need));
@@ -430,16 +433,26 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_
                     const float4 o = A.origins[pix];
                     ray = make_ray(f3(o.x, o.y, o.z), f3(rr.x, rr.y, rr.z));
                     node = 0;
-                    active = true;
+                    tri = tri_end = 0;
+                    active = n_total > 0;
                 } else {
                     exhausted = true;
                 }
             }
         }
-        if (!__any(active)) break;
-        if (active) {
-            bool done = node >= n_total, hit = false;
-            if (!done) {
+        if (!__any(active)) {
+            if (!__any(!exhausted)) break;
+            continue;
+        }
+        // box phase: lanes without a pending leaf walk the tree until they
+        // reach a leaf whose box the ray enters; it ends once as many lanes
+        // wait on a leaf as are still walking
+        while (true) {
+            const bool walk = active && tri >= tri_end && node < n_total;
+            const uint64_t bw = __ballot(walk);
+            const uint64_t bl = __ballot(active && tri < tri_end);
+            if (bw == 0ull || __popcll(bl) >= __popcll(bw)) break;
+            if (walk) {
                 const float4 a = nodes[2 * node];
                 const float4 b = nodes[2 * node + 1];
                 const int escape = __float_as_int(a.w);
@@ -453,23 +466,30 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_
                 } else {
                     const int first = payload >> 3;
                     const int cnt = (first + (payload & 7) <= sc.n_tris) ? (payload & 7) : 0;
-                    for (int k = 0; k < cnt && !hit; ++k) {
-                        const float4* t = sc.tris + 3 * (first + k);
-                        if (COUNT) ++c_tri;
-                        hit = tri_anyhit(ray, t[0], t[1], t[2]);
-                    }
+                    tri = first;
+                    tri_end = first + cnt;
                     node = next;
                 }
-                done = hit || node >= n_total;
-            }
-            if (done) {
-                if (hit) {
-                    atomicOr(hitbits + (int64_t)(slot >> 5) * N + pix, 1u << (slot & 31));
-                    ++c_hits;
-                }
-                active = false;
             }
         }
+        // triangle phase: every pending leaf, one triangle per iteration
+        while (true) {
+            const bool test = active && tri < tri_end;
+            if (!__any(test)) break;
+            if (test) {
+                const float4* t = sc.tris + 3 * tri;
+                if (COUNT) ++c_tri;
+                if (tri_anyhit(ray, t[0], t[1], t[2])) {
+                    atomicOr(hitbits + (int64_t)(slot >> 5) * N + pix, 1u << (slot & 31));
+                    ++c_hits;
+                    active = false;
+                    tri = tri_end = 0;
+                } else {
+                    ++tri;
+                }
+            }
+        }
+        if (active && tri >= tri_end && node >= n_total) active = false;  // miss
     }
     if (COUNT) {
         const uint32_t h = wave_sum(c_hits), bx = wave_sum(c_box), tr = wave_sum(c_tri);
