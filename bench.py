@@ -38,9 +38,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sphere8_grad")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 512 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -96,7 +98,8 @@ def main():
     def step():
         scene = M.Scene(verts, tris)                      # BVH rebuild (mesh changes every iteration)
         envh = M.Env(env_t.detach())                      # probe tables rebuild
-        c_d, c_s = M.MCDIShade.apply(kd, korm, nrm, env_t, scene, envh, gb, w.spp, w.seed, w.tau, w.ray_eps)
+        c_d, c_s = M.MCDIShade.apply(kd, korm, nrm, env_t, scene, envh, gb, w.spp, w.seed, w.tau, w.ray_eps,
+                                     M.FLAG_TIME_TRACE)
         img = kd * c_d + c_s
         loss = ((img - target).abs() * mask).sum() / (3 * n_valid)
         loss.backward()
@@ -106,19 +109,20 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    M.trace_times()                                       # forget warm-up timings
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    keep = []
     start.record()
     for _ in range(args.steps):
-        keep.append(step())
-        if len(keep) > 2:
-            keep.pop(0)
+        step()
     end.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / args.steps
+    trace_ms_list = M.trace_times()                       # traversal kernel, HIP events on its stream
+    trace_ms = sum(trace_ms_list) / max(len(trace_ms_list), 1)
     samples = n_valid * w.spp
     value = samples / (ms * 1e-3)
-    log(args, "step %.3f ms -> %.3g samples/s" % (ms, value))
+    log(args, "step %.3f ms -> %.3g samples/s; trace kernel %.3f ms (%d launches)" % (
+        ms, value, trace_ms, len(trace_ms_list)))
 
     # ---- per-kernel timing on the launch stream (HIP events) ----
     scene = M.Scene(verts, tris)
@@ -155,13 +159,14 @@ def main():
     stats = M.read_stats(st)
     rays = stats["rays_traced"]
 
-    # ---- roofline of the dominant kernel (forward shading) ----
-    # VALU lane-operations the method performs per launch, from the work counts:
-    ops = (OPS_PER_SAMPLE * samples + OPS_PER_BOX * stats["box_tests"] + OPS_PER_TRI * stats["tri_tests"])
-    achieved = ops / (fwd_ms * 1e-3)
+    # ---- roofline of the dominant kernel (any-hit traversal) ----
+    # VALU lane-operations the method performs per launch, from the work counts
+    ops = OPS_PER_RAY * rays + OPS_PER_BOX * stats["box_tests"] + OPS_PER_TRI * stats["tri_tests"]
+    achieved = ops / (trace_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK, "traffic": None,
-                "kernel": "shade_kernel<fwd>", "ops_per_launch": ops, "kernel_ms": fwd_ms}
+                "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
+                "kernel": "trace_rays_kernel", "ops_per_launch": ops, "kernel_ms": trace_ms,
+                "units": {"rays": rays, "box_tests": stats["box_tests"], "tri_tests": stats["tri_tests"]}}
 
     result = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
@@ -173,21 +178,68 @@ def main():
             "env": [int(w.env.shape[0]), int(w.env.shape[1])], "valid_px": n_valid,
             "parallelism": "single-gpu"},
         "shadow_rays_per_s": rays / (fwd_ms * 1e-3),
-        "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "bvh_build_ms": bvh_ms, "env_cdf_ms": cdf_ms,
+        "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "trace_ms": trace_ms, "bvh_build_ms": bvh_ms, "env_cdf_ms": cdf_ms,
         "shade_only_samples_per_s": samples / ((fwd_ms + bwd_ms) * 1e-3),
         "work": stats,
         "roofline": roofline,
     }
 
+    if args.copy_calibration:
+        result["copy_calibration_bytes"] = copy_calibration(dev)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args, w)
     print(json.dumps(result), flush=True)
 
 
-# per-unit VALU lane-operation counts of the method (see the design notes)
-OPS_PER_SAMPLE = 620
-OPS_PER_BOX = 24
-OPS_PER_TRI = 46
+# per-unit VALU lane-operation counts of the traversal (see the design notes):
+# slab test of one node box, watertight test of one triangle, ray setup
+OPS_PER_BOX = 25
+OPS_PER_TRI = 39
+OPS_PER_RAY = 25
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_rays_sphere8_grad_pmc.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_03380_amd", "csrc", f)
+                  for f in ("shade.hip", "device_common.h", "mcdi_internal.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the traversal kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel calibration;
+    None when the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source-sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic-bytes-per-launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(dev):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+    n = 128 * 1024 * 1024          # 512 MiB of float32
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return 4 * n
 
 
 def cpu_baseline(args, w):

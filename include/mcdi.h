@@ -139,6 +139,7 @@ typedef struct {
 #define MCDI_FLAG_LIGHT_OFF   (1u << 0) /* no light-technique sample; p_light = 0 */
 #define MCDI_FLAG_FORCE_COS   (1u << 1) /* lobe probability q = 1 (cosine only) */
 #define MCDI_FLAG_DUMP        (1u << 8) /* write per-sample decision records */
+#define MCDI_FLAG_TIME_TRACE  (1u << 9) /* bracket the traversal kernel with HIP events */
 
 typedef struct {
     int32_t spp;            /* samples per pixel, 1..1024; each = 1 light + 1 BSDF sample */
@@ -191,6 +192,13 @@ mcdi_status mcdi_shade_bwd(mcdi_scene scene, mcdi_env env, const mcdi_gbuffer* g
  *   traversing the BVH. */
 mcdi_status mcdi_trace_anyhit(mcdi_scene scene, const float* orig, const float* dir, int64_t n,
                               uint8_t* hit, int32_t brute, void* stream);
+
+/* Durations (ms) of the traversal kernels of the calls made with
+ * MCDI_FLAG_TIME_TRACE on this thread since the previous mcdi_trace_times
+ * call, oldest first (at most 1024 are kept).  Synchronises on their end
+ * events, copies at most cap values to out, stores the count in *n and
+ * forgets them. */
+mcdi_status mcdi_trace_times(float* out, int32_t cap, int32_t* n);
 
 /* Thread-local text of the last non-OK status ("" if none). */
 const char* mcdi_last_error(void);

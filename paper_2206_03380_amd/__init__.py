@@ -11,7 +11,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib as L
-from ._lib import MCDIError, FLAG_LIGHT_OFF, FLAG_FORCE_COS, FLAG_DUMP  # noqa: F401
+from ._lib import MCDIError, FLAG_LIGHT_OFF, FLAG_FORCE_COS, FLAG_DUMP, FLAG_TIME_TRACE  # noqa: F401
 
 __all__ = ["Scene", "Env", "GBuffer", "shade_fwd", "shade_bwd", "trace_anyhit", "MCDIShade",
            "MCDIError", "new_stats", "read_stats"]
@@ -225,6 +225,15 @@ def shade_bwd(scene, env, gb, spp, g_cd, g_cs, hitbits=None, seed=0, tau=1.0, ra
                                    _ptr(hitbits), _ptr(g_kd), _ptr(g_korm), _ptr(g_nrm), _ptr(g_env),
                                    _ptr(stats), _stream(stream)))
     return g_kd, g_korm, g_nrm, g_env
+
+
+def trace_times():
+    """Traversal-kernel durations (ms) of the calls made with FLAG_TIME_TRACE
+    since the previous call (HIP events on the launch stream)."""
+    buf = (C.c_float * 1024)()
+    n = C.c_int32()
+    L.check(L.lib().mcdi_trace_times(buf, 1024, C.byref(n)))
+    return [buf[i] for i in range(n.value)]
 
 
 def trace_anyhit(scene, orig, dirs, brute=False, stream=None):

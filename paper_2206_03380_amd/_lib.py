@@ -15,6 +15,7 @@ MCDI_OK, MCDI_E_INVALID, MCDI_E_OOM, MCDI_E_DEVICE, MCDI_E_UNSUPPORTED = 0, -1, 
 FLAG_LIGHT_OFF = 1 << 0
 FLAG_FORCE_COS = 1 << 1
 FLAG_DUMP = 1 << 8
+FLAG_TIME_TRACE = 1 << 9
 
 vp = C.c_void_p
 
@@ -83,6 +84,8 @@ def lib():
                                  vp, vp, vp]
     L.mcdi_trace_anyhit.restype = C.c_int
     L.mcdi_trace_anyhit.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int32, vp]
+    L.mcdi_trace_times.restype = C.c_int
+    L.mcdi_trace_times.argtypes = [C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
     L.mcdi_last_error.restype = C.c_char_p
     L.mcdi_version.restype = C.c_char_p
     _lib = L
@@ -96,4 +99,4 @@ def check(status):
 
 EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_build_env_cdf",
             "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
-            "mcdi_trace_anyhit", "mcdi_last_error", "mcdi_version")
+            "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_last_error", "mcdi_version")

@@ -12,7 +12,7 @@ from . import _lib as L
 
 
 class MCDIShade(torch.autograd.Function):
-    """c_d, c_s = MCDIShade.apply(kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed, tau, ray_eps)
+    """c_d, c_s = MCDIShade.apply(kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed, tau, ray_eps, flags)
 
     kd, korm, nrm: [3, N] float32 (differentiable); env: the [H, W, 3] probe
     tensor the tables were built from (differentiable; its gradient is the
@@ -20,7 +20,7 @@ class MCDIShade(torch.autograd.Function):
     differentiated: shape gradients come from primary visibility)."""
 
     @staticmethod
-    def forward(ctx, kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed=0, tau=1.0, ray_eps=1e-3):
+    def forward(ctx, kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0):
         from . import _ptr, _stream, hit_words, _params
         import ctypes as C
         n = gbuf.n
@@ -33,7 +33,7 @@ class MCDIShade(torch.autograd.Function):
         need_bits = tau != 0.0 and any(ctx.needs_input_grad[:4])
         hb = torch.empty((hit_words(spp), n), dtype=torch.int32, device=dev) if need_bits else None
         gs = gbuf.struct(kd=kd, korm=korm, nrm=nrm)
-        prm = _params(spp, seed, tau, ray_eps, 0, None)
+        prm = _params(spp, seed, tau, ray_eps, flags, None)
         L.check(L.lib().mcdi_shade_fwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(c_d),
                                        _ptr(c_s), _ptr(hb), None, _stream()))
         ctx.save_for_backward(kd, korm, nrm, hb if hb is not None else torch.empty(0, device=dev))
@@ -59,4 +59,4 @@ class MCDIShade(torch.autograd.Function):
         L.check(L.lib().mcdi_shade_bwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(g_cd),
                                        _ptr(g_cs), _ptr(hb) if has_bits else None, _ptr(g_kd), _ptr(g_korm),
                                        _ptr(g_nrm), _ptr(g_env), None, _stream()))
-        return g_kd, g_korm, g_nrm, g_env, None, None, None, None, None, None, None
+        return g_kd, g_korm, g_nrm, g_env, None, None, None, None, None, None, None, None

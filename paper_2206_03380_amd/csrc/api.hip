@@ -8,6 +8,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "mcdi_internal.h"
 
@@ -16,6 +18,35 @@ using namespace mcdi;
 namespace {
 
 thread_local std::string g_err;
+
+// traversal timing (MCDI_FLAG_TIME_TRACE): event pairs recorded around the
+// trace kernel on the caller's stream
+struct TraceTimer {
+    static constexpr int kMax = 1024;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    int used = 0;
+    ~TraceTimer() {
+        for (auto& p : pool) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+    }
+    // next free pair, or nullptr when full
+    std::pair<hipEvent_t, hipEvent_t>* next() {
+        if (used >= kMax) return nullptr;
+        if (used == (int)pool.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return nullptr;
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return nullptr;
+            }
+            pool.emplace_back(a, b);
+        }
+        return &pool[used++];
+    }
+};
+thread_local TraceTimer g_timer;
 
 mcdi_status fail(mcdi_status st, const char* fmt, ...) {
     char buf[512];
@@ -93,6 +124,25 @@ struct mcdi_env_s {
 extern "C" {
 
 const char* mcdi_last_error(void) { return g_err.c_str(); }
+
+mcdi_status mcdi_trace_times(float* out, int32_t cap, int32_t* n) {
+    if (!n || (cap > 0 && !out)) return fail(MCDI_E_INVALID, "mcdi_trace_times: NULL argument");
+    int32_t k = 0;
+    for (int i = 0; i < g_timer.used; ++i) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(g_timer.pool[i].second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_timer.pool[i].first, g_timer.pool[i].second);
+        if (e != hipSuccess) {
+            g_timer.used = 0;
+            return fail(MCDI_E_DEVICE, "mcdi_trace_times: %s", hipGetErrorString(e));
+        }
+        if (k < cap) out[k] = ms;
+        ++k;
+    }
+    g_timer.used = 0;
+    *n = k < cap ? k : cap;
+    return ok();
+}
 
 const char* mcdi_version(void) { return "mcdi 0.1 gfx950"; }
 
@@ -280,7 +330,13 @@ static mcdi_status trace_pipeline(const char* who, mcdi_scene sc, ShadeArgs& a, 
     ShadeArgs g = a;
     if (!g.rays) g.tau = 0.0f;
     hipError_t e = launch_gen_rays(g, bits, s);
+    std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+    if ((a.flags & MCDI_FLAG_TIME_TRACE) && e == hipSuccess && a.tau != 0.0f) {
+        ev = g_timer.next();
+        if (ev) e = hipEventRecord(ev->first, s);
+    }
     if (e == hipSuccess && a.tau != 0.0f) e = launch_trace_rays(a, bits, s);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev->second, s);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "%s: %s", who, hipGetErrorString(e));
     *bits_out = bits;
     return MCDI_OK;

@@ -1,0 +1,60 @@
+"""The C-ABI library loads without a GPU and exports every entry point that
+include/mcdi.h declares (no compute calls)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcdi.h")
+LIB = os.path.join(ROOT, "paper_2206_03380_amd", "libmcdi.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(mcdi_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    names = declared()
+    assert "mcdi_shade_fwd" in names and "mcdi_build_env_cdf" in names and len(names) >= 12
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_version_and_binding_list():
+    lib = ctypes.CDLL(LIB)
+    lib.mcdi_version.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.mcdi_version()
+    from paper_2206_03380_amd import _lib
+    assert set(_lib.EXPORTED) <= set(declared())
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_validation_without_device():
+    """Argument validation runs before any device work: calls with bad
+    arguments return MCDI_E_INVALID / MCDI_E_UNSUPPORTED on a machine without
+    a GPU, and mcdi_last_error names the call."""
+    from paper_2206_03380_amd import _lib as L
+    lib = L.lib()
+    out = ctypes.c_void_p()
+    assert lib.mcdi_build_scene(None, 3, None, 1, None, None, ctypes.byref(out)) == L.MCDI_E_INVALID
+    assert b"mcdi_build_scene" in lib.mcdi_last_error()
+    assert lib.mcdi_build_scene(None, -1, None, 0, None, None, ctypes.byref(out)) == L.MCDI_E_INVALID
+    assert lib.mcdi_build_scene(None, 0, None, 1 << 27, None, None, ctypes.byref(out)) == L.MCDI_E_UNSUPPORTED
+    assert lib.mcdi_build_env_cdf(None, 4, 4, None, None, ctypes.byref(out)) == L.MCDI_E_INVALID
+    assert lib.mcdi_build_env_cdf(ctypes.c_void_p(16), 5000, 4, None, None, ctypes.byref(out)) == L.MCDI_E_UNSUPPORTED
+    assert lib.mcdi_build_env_cdf(ctypes.c_void_p(16), 0, 4, None, None, ctypes.byref(out)) == L.MCDI_E_INVALID
+    g = L.GBuffer()
+    p = L.Params(4, 0, 0, 1.0, 1e-3, None)
+    assert lib.mcdi_shade_fwd(None, None, ctypes.byref(g), ctypes.byref(p), None, None, None, None, None) == L.MCDI_E_INVALID
+    n = ctypes.c_int32()
+    assert lib.mcdi_trace_times(None, 4, ctypes.byref(n)) == L.MCDI_E_INVALID
+    assert lib.mcdi_trace_anyhit(None, None, None, 0, None, 0, None) == L.MCDI_E_INVALID
