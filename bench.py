@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark on the three-scene mix (50k/300k/1M triangles)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-serve", action="store_true", help="skip the short serving run of the default line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 512 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -64,6 +68,9 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.serve:
+        print(json.dumps(serve_full(args, M)), flush=True)
+        return
     t0 = time.time()
     w = make_workload(args.workload)
     log(args, "workload %s generated in %.1fs: %d px (%d valid), %d tris, env %s, spp %d" % (
@@ -184,6 +191,8 @@ def main():
         "roofline": roofline,
     }
 
+    if not args.no_serve:
+        result["serving"] = serve_quick(args, M, w, gb)
     if args.copy_calibration:
         result["copy_calibration_bytes"] = copy_calibration(dev)
     if not args.no_cpu_baseline:
@@ -240,6 +249,122 @@ def copy_calibration(dev):
         dst.copy_(src)
     torch.cuda.synchronize()
     return 4 * n
+
+
+def _serve_run(M, make_system, requests, arrivals):
+    """Drive a serving system with the given arrivals; returns metrics."""
+    import torch
+    from paper_2206_03380_amd.serve import run_arrivals, percentile
+    for r in requests:
+        r.t_done = None
+    sysm = make_system()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = run_arrivals(sysm, requests, arrivals)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = [r.latency * 1e3 for r in done]
+    samples = sum(r._valid * r.spp for r in done)
+    return {"requests": len(done), "wall_s": wall, "samples_per_s": samples / wall,
+            "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99), "launches": sysm.n_launches}
+
+
+def _serving_compare(args, M, resident, requests, label, fracs=(0.7,), warm=10):
+    import numpy as np
+    from paper_2206_03380_amd.serve import Server, PerRequest
+    from workloads.serving import poisson_arrivals
+    mk_srv = lambda: Server(resident, budget_bytes=64 << 30, max_slots=64, spp_max=32)  # noqa: E731
+    mk_base = lambda: PerRequest(resident)  # noqa: E731
+    # warm-up, then the saturated rate: everything arrives at once
+    _serve_run(M, mk_srv, requests[:warm], np.zeros(warm))
+    _serve_run(M, mk_base, requests[:warm], np.zeros(warm))
+    sat = _serve_run(M, mk_srv, requests, np.zeros(len(requests)))
+    rate = sat["requests"] / sat["wall_s"]
+    out = {"workload": label, "saturated_requests_per_s": rate, "saturated_samples_per_s": sat["samples_per_s"],
+           "loads": []}
+    for f in fracs:
+        arr = poisson_arrivals(len(requests), f * rate)
+        srv = _serve_run(M, mk_srv, requests, arr)
+        base = _serve_run(M, mk_base, requests, arr)
+        out["loads"].append({"load": f, "qps": f * rate, "batched": srv, "per_request_launches": base})
+    return out
+
+
+def serve_quick(args, M, w, gb):
+    """Short serving run on the main scene: each request is one 512x512 view
+    with spp in {4, 8, 16, 32}, forward or forward+backward (50/50), Poisson
+    arrivals at 0.7x the batched saturated rate; same requests through plain
+    per-request launches."""
+    import numpy as np
+    import torch
+    from paper_2206_03380_amd.serve import Request
+    from workloads import upstream_grads
+    dev = "cuda:0"
+    resident = {"main": (M.Scene(torch.from_numpy(w.verts).to(dev), torch.from_numpy(w.tris).to(dev)),
+                         M.Env(torch.from_numpy(w.env).to(dev)))}
+    hw = w.height * w.width
+    ud, us = upstream_grads(w)
+    rng = np.random.Generator(np.random.PCG64(5))
+    views = []
+    for v in range(w.n_views):
+        sl = slice(v * hw, (v + 1) * hw)
+        g1 = M.GBuffer(gb.pos[:, sl].contiguous(), gb.nrm[:, sl].contiguous(), gb.kd[:, sl].contiguous(),
+                       gb.korm[:, sl].contiguous(), gb.mask[sl].contiguous(), gb.eye[v:v + 1].contiguous(), 1,
+                       w.height, w.width, v)
+        views.append((g1, torch.from_numpy(np.ascontiguousarray(ud[:, sl])).to(dev),
+                      torch.from_numpy(np.ascontiguousarray(us[:, sl])).to(dev), int(w.mask[sl].sum())))
+    reqs = []
+    for i in range(120):
+        v = int(rng.integers(w.n_views))
+        g1, gd, gs, nv = views[v]
+        r = Request(scene="main", gb=g1, spp=int(rng.choice([4, 8, 16, 32])), seed=i, tau=w.tau,
+                    ray_eps=w.ray_eps)
+        if rng.random() < 0.5:
+            r.g_cd, r.g_cs = gd, gs
+        r._valid = nv
+        reqs.append(r)
+    torch.cuda.synchronize()
+    return _serving_compare(args, M, resident, reqs, "one 512x512 view of the main scene per request")
+
+
+def serve_full(args, M):
+    """Serving mix: resident scenes of ~50k, ~298k and ~1.0M triangles (probes
+    512x256 to 2048x1024); requests draw scene, resolution in {128..1024}^2,
+    spp in {4, 8, 16, 32}, forward or forward+backward; Poisson arrivals at
+    0.5/0.7/0.9 of the saturated request rate."""
+    import torch
+    from paper_2206_03380_amd.serve import Request
+    from workloads import serving, upstream_grads
+    dev = "cuda:0"
+    t0 = time.time()
+    scenes_np = serving.make_scenes(full=True)
+    log(args, "serving scenes generated in %.1fs" % (time.time() - t0))
+    resident = {}
+    gbs = {}
+    for name, views in scenes_np.items():
+        w0 = next(iter(views.values()))
+        resident[name] = (M.Scene(torch.from_numpy(w0.verts).to(dev), torch.from_numpy(w0.tris).to(dev)),
+                          M.Env(torch.from_numpy(w0.env).to(dev)))
+        for res, w in views.items():
+            ud, us = upstream_grads(w)
+            gbs[(name, res)] = (M.GBuffer.from_workload(w, dev), torch.from_numpy(ud).to(dev),
+                                torch.from_numpy(us).to(dev), w.n_valid, w.tau, w.ray_eps)
+    draws = serving.make_requests(scenes_np, args.serve_requests + 50)
+    reqs = []
+    for (name, res, spp, grad, vb) in draws:
+        gb, gd, gs, nv, tau, eps = gbs[(name, res)]
+        g1 = M.GBuffer(gb.pos, gb.nrm, gb.kd, gb.korm, gb.mask, gb.eye, 1, res, res, vb)
+        r = Request(scene=name, gb=g1, spp=spp, seed=0, tau=tau, ray_eps=eps)
+        if grad:
+            r.g_cd, r.g_cs = gd, gs
+        r._valid = nv
+        reqs.append(r)
+    torch.cuda.synchronize()
+    out = _serving_compare(args, M, resident, reqs[50:], "three-scene serving mix (50k/298k/1.0M triangles)",
+                           fracs=(0.5, 0.7, 0.9), warm=50)
+    out["metric"] = METRIC
+    out["tris"] = {n: int(len(next(iter(v.values())).tris)) for n, v in scenes_np.items()}
+    return out
 
 
 def cpu_baseline(args, w):

@@ -193,6 +193,55 @@ mcdi_status mcdi_shade_bwd(mcdi_scene scene, mcdi_env env, const mcdi_gbuffer* g
 mcdi_status mcdi_trace_anyhit(mcdi_scene scene, const float* orig, const float* dir, int64_t n,
                               uint8_t* hit, int32_t brute, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: one persistent launch over the tiles of many requests.
+ *
+ * A tile is 256 consecutive pixels of a request's G-buffer.  Each item gives
+ * one request (scene, probe tables, G-buffer, parameters, outputs) and a
+ * contiguous range of its tiles; a launch may carry several ranges of
+ * different requests, and a request may be spread over several launches.
+ * Every pixel is computed exactly as by mcdi_shade_fwd / mcdi_shade_bwd (the
+ * random numbers depend on the pixel and view_base only), so a request's
+ * per-pixel results do not depend on what else shares its launches.
+ *   hitbits  device uint32 [ceil(2*spp/32)][N] scratch of the request
+ *   origins  device float32 [N][4] scratch of the request
+ *   g_cd     NULL for a forward-only request; otherwise the adjoint also runs
+ *            and g_kd, g_korm, g_nrm (overwritten) and g_env (accumulated)
+ *            must be given.
+ * The server owns the ray queues of its workgroups (n_workgroups regions of
+ * 2*spp_max*256 rays) and a double-buffered item staging area; items of a
+ * launch are copied to the device in stream order.  Calls on one server must
+ * come from one thread and use one stream.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    mcdi_scene scene;
+    mcdi_env env;
+    mcdi_gbuffer gbuf;
+    mcdi_params params;     /* flags: MCDI_FLAG_LIGHT_OFF / FORCE_COS only */
+    float* c_d;
+    float* c_s;
+    uint32_t* hitbits;
+    float* origins;
+    const float* g_cd;
+    const float* g_cs;
+    float* g_kd;
+    float* g_korm;
+    float* g_nrm;
+    float* g_env;
+    int64_t first_tile;     /* tile range [first_tile, first_tile + n_tiles) */
+    int64_t n_tiles;
+} mcdi_serve_item;
+
+typedef struct mcdi_server_s* mcdi_server;
+
+/* spp_max: largest spp any item may use (1..1024); n_workgroups: persistent
+ * grid size (0: 4 per compute unit). */
+mcdi_status mcdi_server_create(int32_t spp_max, int32_t n_workgroups, const mcdi_allocator* alloc, void* stream,
+                               mcdi_server* out);
+mcdi_status mcdi_server_launch(mcdi_server server, const mcdi_serve_item* items, int32_t n_items);
+/* Synchronises the server's stream, then frees its memory. */
+void mcdi_server_destroy(mcdi_server server);
+
 /* Durations (ms) of the traversal kernels of the calls made with
  * MCDI_FLAG_TIME_TRACE on this thread since the previous mcdi_trace_times
  * call, oldest first (at most 1024 are kept).  Synchronises on their end

@@ -42,6 +42,12 @@ class Params(C.Structure):
                 ("ray_eps", C.c_float), ("decisions", vp)]
 
 
+class ServeItem(C.Structure):
+    _fields_ = [("scene", vp), ("env", vp), ("gbuf", GBuffer), ("params", Params), ("c_d", vp), ("c_s", vp),
+                ("hitbits", vp), ("origins", vp), ("g_cd", vp), ("g_cs", vp), ("g_kd", vp), ("g_korm", vp),
+                ("g_nrm", vp), ("g_env", vp), ("first_tile", C.c_int64), ("n_tiles", C.c_int64)]
+
+
 class Stats(C.Structure):
     _fields_ = [("valid_pixels", C.c_uint64), ("invalid_pixels", C.c_uint64), ("rays_traced", C.c_uint64),
                 ("rays_hit", C.c_uint64), ("samples_culled", C.c_uint64), ("box_tests", C.c_uint64),
@@ -86,6 +92,12 @@ def lib():
     L.mcdi_trace_anyhit.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int32, vp]
     L.mcdi_trace_times.restype = C.c_int
     L.mcdi_trace_times.argtypes = [C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
+    L.mcdi_server_create.restype = C.c_int
+    L.mcdi_server_create.argtypes = [C.c_int32, C.c_int32, vp, vp, C.POINTER(vp)]
+    L.mcdi_server_launch.restype = C.c_int
+    L.mcdi_server_launch.argtypes = [vp, vp, C.c_int32]
+    L.mcdi_server_destroy.restype = None
+    L.mcdi_server_destroy.argtypes = [vp]
     L.mcdi_last_error.restype = C.c_char_p
     L.mcdi_version.restype = C.c_char_p
     _lib = L
@@ -99,4 +111,5 @@ def check(status):
 
 EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_build_env_cdf",
             "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
-            "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_last_error", "mcdi_version")
+            "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_server_create", "mcdi_server_launch",
+            "mcdi_server_destroy", "mcdi_last_error", "mcdi_version")

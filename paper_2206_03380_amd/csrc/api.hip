@@ -394,6 +394,150 @@ mcdi_status mcdi_shade_bwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, co
     return ok();
 }
 
+}  // extern "C"
+
+struct mcdi_server_s {
+    Alloc alloc;
+    hipStream_t stream = nullptr;
+    int spp_max = 0;
+    int n_wg = 0;
+    float4* scratch = nullptr;
+    int* counter = nullptr;
+    ServeItem* items_dev = nullptr;
+    int cap = 0;
+    ServeItem* staging[2] = {nullptr, nullptr};  // pinned host
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    int flip = 0;
+};
+
+static void server_free_items(mcdi_server sv) {
+    sv->alloc.put(sv->items_dev, sv->stream);
+    for (int i = 0; i < 2; ++i) {
+        if (sv->copied[i]) (void)hipEventSynchronize(sv->copied[i]);
+        if (sv->staging[i]) (void)hipHostFree(sv->staging[i]);
+        sv->staging[i] = nullptr;
+    }
+    sv->items_dev = nullptr;
+    sv->cap = 0;
+}
+
+static mcdi_status server_reserve(mcdi_server sv, int n) {
+    if (n <= sv->cap) return MCDI_OK;
+    int cap = sv->cap ? sv->cap : 64;
+    while (cap < n) cap *= 2;
+    server_free_items(sv);
+    sv->items_dev = (ServeItem*)sv->alloc.get(sizeof(ServeItem) * (size_t)cap, sv->stream);
+    if (!sv->items_dev) return fail(MCDI_E_OOM, "mcdi_server_launch: item buffer allocation failed");
+    for (int i = 0; i < 2; ++i) {
+        if (hipHostMalloc((void**)&sv->staging[i], sizeof(ServeItem) * (size_t)cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MCDI_E_OOM, "mcdi_server_launch: pinned staging allocation failed");
+        }
+    }
+    sv->cap = cap;
+    return MCDI_OK;
+}
+
+extern "C" {
+
+mcdi_status mcdi_server_create(int32_t spp_max, int32_t n_workgroups, const mcdi_allocator* alloc, void* stream,
+                               mcdi_server* out) {
+    if (!out) return fail(MCDI_E_INVALID, "mcdi_server_create: out is NULL");
+    if (spp_max < 1 || spp_max > 1024) return fail(MCDI_E_INVALID, "mcdi_server_create: spp_max must be in [1, 1024]");
+    if (n_workgroups < 0 || n_workgroups > 65536) return fail(MCDI_E_INVALID, "mcdi_server_create: bad n_workgroups");
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(MCDI_E_INVALID, "mcdi_server_create: allocator incomplete");
+    int n_wg = n_workgroups;
+    if (n_wg == 0) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        n_wg = 4 * cus;
+    }
+    mcdi_server sv = new (std::nothrow) mcdi_server_s;
+    if (!sv) return fail(MCDI_E_OOM, "mcdi_server_create: host allocation failed");
+    sv->alloc = make_alloc(alloc);
+    sv->stream = (hipStream_t)stream;
+    sv->spp_max = spp_max;
+    sv->n_wg = n_wg;
+    sv->scratch = (float4*)sv->alloc.get(sizeof(float4) * (size_t)n_wg * 2 * spp_max * kBlock, sv->stream);
+    sv->counter = (int*)sv->alloc.get(sizeof(int), sv->stream);
+    bool ok_ev = hipEventCreateWithFlags(&sv->copied[0], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&sv->copied[1], hipEventDisableTiming) == hipSuccess;
+    if (!sv->scratch || !sv->counter || !ok_ev) {
+        mcdi_server_destroy(sv);
+        return fail(MCDI_E_OOM, "mcdi_server_create: allocation failed");
+    }
+    *out = sv;
+    return ok();
+}
+
+void mcdi_server_destroy(mcdi_server sv) {
+    if (!sv) return;
+    (void)hipStreamSynchronize(sv->stream);
+    server_free_items(sv);
+    sv->alloc.put(sv->scratch, sv->stream);
+    sv->alloc.put(sv->counter, sv->stream);
+    for (int i = 0; i < 2; ++i)
+        if (sv->copied[i]) (void)hipEventDestroy(sv->copied[i]);
+    delete sv;
+}
+
+mcdi_status mcdi_server_launch(mcdi_server sv, const mcdi_serve_item* items, int32_t n_items) {
+    if (!sv) return fail(MCDI_E_INVALID, "mcdi_server_launch: NULL server");
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(MCDI_E_INVALID, "mcdi_server_launch: bad items");
+    if (n_items == 0) return ok();
+    mcdi_status st = server_reserve(sv, n_items);
+    if (st != MCDI_OK) return st;
+    // staging buffer of this launch: wait until its previous copy completed
+    const int b = sv->flip;
+    sv->flip ^= 1;
+    if (hipEventSynchronize(sv->copied[b]) != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_server_launch: event");
+    ServeItem* h = sv->staging[b];
+    int64_t total = 0;
+    int max_H = 1;
+    for (int i = 0; i < n_items; ++i) {
+        const mcdi_serve_item& it = items[i];
+        ShadeArgs a;
+        st = fill_common("mcdi_server_launch", it.scene, it.env, &it.gbuf, &it.params, a);
+        if (st != MCDI_OK) return st;
+        if (it.params.spp > sv->spp_max) return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d spp > spp_max", i);
+        if (it.params.flags & (MCDI_FLAG_DUMP | MCDI_FLAG_TIME_TRACE))
+            return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d: dump/timing flags are not served", i);
+        if (!it.c_d || !it.c_s || !it.hitbits || !it.origins)
+            return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d: NULL output or scratch", i);
+        if (it.g_cd && (!it.g_cs || !it.g_kd || !it.g_korm || !it.g_nrm))
+            return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d: incomplete gradient buffers", i);
+        const int64_t tiles = (a.g.n + kBlock - 1) / kBlock;
+        if (it.first_tile < 0 || it.n_tiles < 1 || it.first_tile + it.n_tiles > tiles)
+            return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d: tile range outside the request", i);
+        a.c_d = it.c_d;
+        a.c_s = it.c_s;
+        a.hitbits_in = it.hitbits;
+        a.origins = (float4*)it.origins;
+        a.g_cd = it.g_cd;
+        a.g_cs = it.g_cs;
+        a.g_kd = it.g_kd;
+        a.g_korm = it.g_korm;
+        a.g_nrm = it.g_nrm;
+        a.g_env = it.g_env;
+        a.rays = sv->scratch;  // marks tracing available; regions are per workgroup
+        h[i].args = a;
+        h[i].hitbits = it.hitbits;
+        h[i].first_tile = it.first_tile;
+        h[i].first_global = total;
+        total += it.n_tiles;
+        if (a.env.H > max_H) max_H = a.env.H;
+    }
+    if (total >= ((int64_t)1 << 31)) return fail(MCDI_E_UNSUPPORTED, "mcdi_server_launch: too many tiles");
+    hipError_t e = hipMemcpyAsync(sv->items_dev, h, sizeof(ServeItem) * (size_t)n_items, hipMemcpyHostToDevice,
+                                  sv->stream);
+    if (e == hipSuccess) e = hipEventRecord(sv->copied[b], sv->stream);
+    if (e == hipSuccess)
+        e = launch_serve(sv->items_dev, n_items, total, sv->counter, sv->scratch, sv->spp_max, sv->n_wg, max_H,
+                         sv->stream);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_server_launch: %s", hipGetErrorString(e));
+    return ok();
+}
+
 mcdi_status mcdi_trace_anyhit(mcdi_scene sc, const float* orig, const float* dir, int64_t n, uint8_t* hit,
                               int32_t brute, void* stream) {
     if (!sc) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: NULL scene");

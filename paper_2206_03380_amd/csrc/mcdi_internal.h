@@ -85,7 +85,17 @@ struct ShadeArgs {
     float4* origins;       // [N]
 };
 
+// one serving work item: a contiguous range of tiles of one request
+struct ServeItem {
+    ShadeArgs args;        // outputs, upstream gradients (g_cd != null: adjoint too)
+    uint32_t* hitbits;     // [words][N] of the request
+    int64_t first_tile;    // first tile of the range within the request
+    int64_t first_global;  // index of that tile in the launch's tile queue
+};
+
 // kernel launchers (return hipError_t of the launch)
+hipError_t launch_serve(const ServeItem* items_dev, int n_items, int64_t total_tiles, int* tile_counter,
+                        float4* scratch, int spp_max, int n_workgroups, int max_H, hipStream_t s);
 hipError_t launch_env_cdf(const float* env, int H, int W, float* cond, float* marg, float* pdf,
                           double* rowsum, int32_t* light_enabled, hipStream_t s);
 hipError_t launch_env_hot(const float* pdf, int H, int W, int32_t* hot_slot, int32_t* hot_texel, int32_t* n_hot,

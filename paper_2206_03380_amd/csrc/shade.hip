@@ -308,24 +308,25 @@ __device__ __forceinline__ void stage_marg(const ShadeArgs& A, float* s_marg) {
 }
 
 // ---------------------------------------------------------------------------
-// 1) ray generation: the directions of every sample above the horizon,
-//    compacted per workgroup into its own queue region (LDS counter, no
-//    global atomics); hit words of the workgroup's pixels are cleared.
+// The three stages work on one tile of kBlock pixels per workgroup.  The
+// staged kernels run tile = blockIdx.x; the serving kernel pulls tiles of
+// many requests from a queue and runs the stages back to back.
 // ---------------------------------------------------------------------------
+
+// 1) ray generation: the directions of every sample above the horizon,
+//    compacted into the tile's ray region (LDS counter, no global atomics);
+//    hit words of the tile's pixels are cleared; returns the ray count
+//    (valid in thread 0 after the final barrier, in *s_cnt for all).
 template <bool COUNT>
-__global__ __launch_bounds__(kBlock) void gen_rays_kernel(ShadeArgs A, uint32_t* hitbits) {
-    extern __shared__ float s_marg[];
-    __shared__ int s_cnt;
-    stage_marg(A, s_marg);
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
+__device__ __forceinline__ void gen_tile(const ShadeArgs& A, int64_t tile, float4* region, uint32_t* hitbits,
+                                         const float* s_marg, int* s_cnt) {
     const int64_t N = A.g.n;
-    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t pix = tile * kBlock + threadIdx.x;
     const bool active = pix < N;
     const int spp = A.spp;
     const int words = (2 * spp + 31) >> 5;
     const bool light_on = (*A.env.light_enabled != 0) && !(A.flags & MCDI_FLAG_LIGHT_OFF);
-    const bool trace = A.tau != 0.0f;
+    const bool trace = A.tau != 0.0f && region != nullptr;
     bool nonfinite = false;
     Pixel P;
     P.valid = false;
@@ -340,7 +341,6 @@ __global__ __launch_bounds__(kBlock) void gen_rays_kernel(ShadeArgs A, uint32_t*
     const uint32_t piv = active ? (uint32_t)(pix - (int64_t)view * hw) : 0u;
     const uint32_t vid = (uint32_t)A.g.view_base + view;
     const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
-    float4* region = A.rays + (size_t)blockIdx.x * (size_t)(2 * spp * kBlock);
     const int lane = __lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t c_rays = 0, c_culled = 0;
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void gen_rays_kernel(ShadeArgs A, uint32_t*
             const uint64_t bal = __ballot(want);
             if (bal == 0ull) continue;
             int base = 0;
-            if (lane == 0) base = atomicAdd(&s_cnt, (int)__popcll(bal));
+            if (lane == 0) base = atomicAdd(s_cnt, (int)__popcll(bal));
             base = __shfl(base, 0);
             if (want) {
                 const int slot = 2 * s + tech;
@@ -373,8 +373,6 @@ __global__ __launch_bounds__(kBlock) void gen_rays_kernel(ShadeArgs A, uint32_t*
             }
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) A.ray_count[blockIdx.x] = s_cnt;
     if (COUNT) {
         const uint32_t a = wave_sum(c_rays), b = wave_sum(c_culled);
         const uint32_t v = wave_sum(P.valid ? 1u : 0u), nf = wave_sum(nonfinite ? 1u : 0u);
@@ -387,22 +385,16 @@ __global__ __launch_bounds__(kBlock) void gen_rays_kernel(ShadeArgs A, uint32_t*
     }
 }
 
-// ---------------------------------------------------------------------------
-// 2) any-hit traversal of a workgroup's ray queue.  Lanes that finish a ray
-//    take the next one from the queue (one LDS atomic per wave per refill), so
-//    a wave keeps all its lanes busy while its rays have very different
-//    lengths (persistent "while-while" traversal with dynamic fetch).
-// ---------------------------------------------------------------------------
+// 2) any-hit traversal of the tile's ray region.  Lanes that finish a ray
+//    take the next one from the region (one LDS atomic per wave per refill);
+//    box steps and triangle steps run in separate phases so a wave keeps its
+//    lanes on the same code (while-while traversal with dynamic fetch).
 template <bool COUNT>
-__global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_t* hitbits) {
-    __shared__ int s_next;
-    if (threadIdx.x == 0) s_next = 0;
-    __syncthreads();
+__device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, const float4* R, int count,
+                                           uint32_t* hitbits, int* s_next) {
     const Scene& sc = A.scene;
     const int64_t N = A.g.n;
-    const int count = A.ray_count[blockIdx.x];
-    const float4* R = A.rays + (size_t)blockIdx.x * (size_t)(2 * A.spp * kBlock);
-    const int64_t base_pix = (int64_t)blockIdx.x * kBlock;
+    const int64_t base_pix = tile * kBlock;
     const int n_total = sc.nodes[0].escape;
     const float4* nodes = reinterpret_cast<const float4*>(sc.nodes);
     const int lane = __lane_id();
@@ -421,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_
         if (need && (__popcll(need) >= 16 || busy == 0ull)) {
             const int leader = __ffsll((unsigned long long)need) - 1;
             int b = 0;
-            if (lane == leader) b = atomicAdd(&s_next, (int)__popcll(need));
+            if (lane == leader) b = atomicAdd(s_next, (int)__popcll(need));
             b = __shfl(b, leader);
             if (!active && !exhausted) {
                 const int idx = b + (int)__popcll(need & lt);
@@ -501,114 +493,201 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_
     }
 }
 
-// ---------------------------------------------------------------------------
-// 3) evaluation: forward values or the adjoint, from the hit bits.
-// ---------------------------------------------------------------------------
+// 3) evaluation: forward values or the adjoint, from the hit bits.  For the
+//    adjoint, s_hot must be zeroed before and flushed after (hot_flush).
+template <bool BWD, bool DUMP>
+__device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, const float* s_marg, float* s_hot) {
+    const int64_t N = A.g.n;
+    const int64_t pix = tile * kBlock + threadIdx.x;
+    const int spp = A.spp;
+    const bool light_on = (*A.env.light_enabled != 0) && !(A.flags & MCDI_FLAG_LIGHT_OFF);
+    const bool trace = A.tau != 0.0f;
+    if (pix >= N) return;
+    bool nonfinite;
+    const Pixel P = setup_pixel(A, pix, nonfinite);
+    if (!P.valid) {
+        if (!BWD) {
+            for (int c = 0; c < 3; ++c) { A.c_d[c * N + pix] = 0.0f; A.c_s[c * N + pix] = 0.0f; }
+        } else {
+            for (int c = 0; c < 3; ++c) {
+                A.g_kd[c * N + pix] = 0.0f; A.g_korm[c * N + pix] = 0.0f; A.g_nrm[c * N + pix] = 0.0f;
+            }
+        }
+        if (DUMP) {
+            uint32_t* d = A.decisions + (size_t)pix * spp * 3;
+            for (int s = 0; s < spp; ++s) { d[3 * s] = kNone; d[3 * s + 1] = kNone; d[3 * s + 2] = 0u; }
+        }
+        return;
+    }
+    const int64_t hw = (int64_t)A.g.height * A.g.width;
+    const uint32_t view = (uint32_t)(pix / hw), piv = (uint32_t)(pix - (int64_t)view * hw);
+    const uint32_t vid = (uint32_t)A.g.view_base + view;
+    const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
+    const float invspp = 1.0f / (float)spp;
+    float3 Ud = f3(0, 0, 0), Us = f3(0, 0, 0);
+    if (BWD) {
+        Ud = f3(A.g_cd[pix], A.g_cd[N + pix], A.g_cd[2 * N + pix]);
+        Us = f3(A.g_cs[pix], A.g_cs[N + pix], A.g_cs[2 * N + pix]);
+    }
+    FwdAcc fa{f3(0, 0, 0), f3(0, 0, 0)};
+    BwdAcc ba{f3(0, 0, 0), 0.0f, 0.0f, f3(0, 0, 0)};
+    uint32_t bits = 0;
+    for (int s = 0; s < spp; ++s) {
+        if (((2 * s) & 31) == 0) bits = A.hitbits_in[((2 * s) >> 5) * N + pix];
+        const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
+        const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
+        uint32_t rec0 = kNone, rec1 = kNone;
+        uint32_t rec2 = kDecValid | (P.nov_pos ? kDecNovPos : 0u);
+        for (int tech = 0; tech < 2; ++tech) {
+            Sample S;
+            if (tech == 0) {
+                if (!light_on) continue;
+                const bool has = draw_light(A, P, s_marg, r0, S);
+                rec0 = (uint32_t)S.texel;
+                if (!has) { rec2 |= kDecLCull; continue; }
+            } else {
+                if (draw_bsdf(P, r0, r1, S)) rec2 |= kDecLobeCos;
+            }
+            if (!(S.wl.z > 0.0f)) { rec2 |= tech ? kDecBCull : kDecLCull; continue; }
+            if (tech == 1) {
+                bsdf_texel(A, light_on, S);
+                rec1 = (uint32_t)S.texel;
+            }
+            float Hv = 1.0f;
+            if (trace) {
+                const int bitpos = 2 * s + tech;
+                rec2 |= tech ? kDecBTraced : kDecLTraced;
+                if ((bits >> (bitpos & 31)) & 1u) {
+                    Hv = 1.0f - A.tau;
+                    rec2 |= tech ? kDecBHit : kDecLHit;
+                }
+            }
+            eval_sample<BWD>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot);
+        }
+        if (DUMP) {
+            uint32_t* d = A.decisions + ((size_t)pix * spp + s) * 3;
+            d[0] = rec0; d[1] = rec1; d[2] = rec2;
+        }
+    }
+    if (!BWD) {
+        for (int c = 0; c < 3; ++c) {
+            A.c_d[c * N + pix] = comp(fa.cd, c) * invspp;
+            A.c_s[c * N + pix] = comp(fa.cs, c) * invspp;
+        }
+    } else {
+        A.g_kd[pix] = ba.gkd.x; A.g_kd[N + pix] = ba.gkd.y; A.g_kd[2 * N + pix] = ba.gkd.z;
+        A.g_korm[pix] = 0.0f; A.g_korm[N + pix] = ba.gr; A.g_korm[2 * N + pix] = ba.gm;
+        const float il = 1.0f / P.nlen;
+        const float3 gw = (ba.gnl.x * il) * P.t + (ba.gnl.y * il) * P.b;
+        A.g_nrm[pix] = gw.x; A.g_nrm[N + pix] = gw.y; A.g_nrm[2 * N + pix] = gw.z;
+    }
+}
+
+__device__ __forceinline__ void hot_zero(float* s_hot) {
+    for (int k = threadIdx.x; k < 3 * kHotMax; k += blockDim.x) s_hot[k] = 0.0f;
+}
+
+// one global atomic per touched hot slot (call after a barrier)
+__device__ __forceinline__ void hot_flush(const ShadeArgs& A, const float* s_hot) {
+    if (!A.g_env) return;
+    const int n_hot = min(*A.env.n_hot, kHotMax);
+    for (int k = threadIdx.x; k < 3 * n_hot; k += blockDim.x) {
+        const float v = s_hot[k];
+        if (v != 0.0f) atomicAdd(A.g_env + 3 * (size_t)A.env.hot_texel[k / 3] + (k % 3), v);
+    }
+}
+
+__device__ __forceinline__ float4* tile_region(const ShadeArgs& A, int64_t tile) {
+    return A.rays ? A.rays + (size_t)tile * (size_t)(2 * A.spp * kBlock) : nullptr;
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void gen_rays_kernel(ShadeArgs A, uint32_t* hitbits) {
+    extern __shared__ float s_marg[];
+    __shared__ int s_cnt;
+    stage_marg(A, s_marg);
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    gen_tile<COUNT>(A, blockIdx.x, tile_region(A, blockIdx.x), hitbits, s_marg, &s_cnt);
+    __syncthreads();
+    if (threadIdx.x == 0) A.ray_count[blockIdx.x] = s_cnt;
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_t* hitbits) {
+    __shared__ int s_next;
+    if (threadIdx.x == 0) s_next = 0;
+    __syncthreads();
+    trace_tile<COUNT>(A, blockIdx.x, tile_region(A, blockIdx.x), A.ray_count[blockIdx.x], hitbits, &s_next);
+}
+
 template <bool BWD, bool DUMP>
 __global__ __launch_bounds__(kBlock) void shade_kernel(ShadeArgs A) {
     extern __shared__ float smem[];
     float* s_marg = smem;
     float* s_hot = smem + ((A.env.H + 1 + 3) & ~3);
     stage_marg(A, s_marg);
-    if (BWD) for (int k = threadIdx.x; k < 3 * kHotMax; k += blockDim.x) s_hot[k] = 0.0f;
+    if (BWD) hot_zero(s_hot);
     __syncthreads();
-
-    const int64_t N = A.g.n;
-    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int spp = A.spp;
-    const bool light_on = (*A.env.light_enabled != 0) && !(A.flags & MCDI_FLAG_LIGHT_OFF);
-    const bool trace = A.tau != 0.0f;
-
-    if (pix < N) {
-        bool nonfinite;
-        const Pixel P = setup_pixel(A, pix, nonfinite);
-        if (!P.valid) {
-            if (!BWD) {
-                for (int c = 0; c < 3; ++c) { A.c_d[c * N + pix] = 0.0f; A.c_s[c * N + pix] = 0.0f; }
-            } else {
-                for (int c = 0; c < 3; ++c) {
-                    A.g_kd[c * N + pix] = 0.0f; A.g_korm[c * N + pix] = 0.0f; A.g_nrm[c * N + pix] = 0.0f;
-                }
-            }
-            if (DUMP) {
-                uint32_t* d = A.decisions + (size_t)pix * spp * 3;
-                for (int s = 0; s < spp; ++s) { d[3 * s] = kNone; d[3 * s + 1] = kNone; d[3 * s + 2] = 0u; }
-            }
-        } else {
-            const int64_t hw = (int64_t)A.g.height * A.g.width;
-            const uint32_t view = (uint32_t)(pix / hw), piv = (uint32_t)(pix - (int64_t)view * hw);
-            const uint32_t vid = (uint32_t)A.g.view_base + view;
-            const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
-            const float invspp = 1.0f / (float)spp;
-            float3 Ud = f3(0, 0, 0), Us = f3(0, 0, 0);
-            if (BWD) {
-                Ud = f3(A.g_cd[pix], A.g_cd[N + pix], A.g_cd[2 * N + pix]);
-                Us = f3(A.g_cs[pix], A.g_cs[N + pix], A.g_cs[2 * N + pix]);
-            }
-            FwdAcc fa{f3(0, 0, 0), f3(0, 0, 0)};
-            BwdAcc ba{f3(0, 0, 0), 0.0f, 0.0f, f3(0, 0, 0)};
-            uint32_t bits = 0;
-            for (int s = 0; s < spp; ++s) {
-                if (((2 * s) & 31) == 0) bits = A.hitbits_in[((2 * s) >> 5) * N + pix];
-                const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
-                const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
-                uint32_t rec0 = kNone, rec1 = kNone;
-                uint32_t rec2 = kDecValid | (P.nov_pos ? kDecNovPos : 0u);
-                for (int tech = 0; tech < 2; ++tech) {
-                    Sample S;
-                    if (tech == 0) {
-                        if (!light_on) continue;
-                        const bool has = draw_light(A, P, s_marg, r0, S);
-                        rec0 = (uint32_t)S.texel;
-                        if (!has) { rec2 |= kDecLCull; continue; }
-                    } else {
-                        if (draw_bsdf(P, r0, r1, S)) rec2 |= kDecLobeCos;
-                    }
-                    if (!(S.wl.z > 0.0f)) { rec2 |= tech ? kDecBCull : kDecLCull; continue; }
-                    if (tech == 1) {
-                        bsdf_texel(A, light_on, S);
-                        rec1 = (uint32_t)S.texel;
-                    }
-                    float Hv = 1.0f;
-                    if (trace) {
-                        const int bitpos = 2 * s + tech;
-                        rec2 |= tech ? kDecBTraced : kDecLTraced;
-                        if ((bits >> (bitpos & 31)) & 1u) {
-                            Hv = 1.0f - A.tau;
-                            rec2 |= tech ? kDecBHit : kDecLHit;
-                        }
-                    }
-                    eval_sample<BWD>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot);
-                }
-                if (DUMP) {
-                    uint32_t* d = A.decisions + ((size_t)pix * spp + s) * 3;
-                    d[0] = rec0; d[1] = rec1; d[2] = rec2;
-                }
-            }
-            if (!BWD) {
-                for (int c = 0; c < 3; ++c) {
-                    A.c_d[c * N + pix] = comp(fa.cd, c) * invspp;
-                    A.c_s[c * N + pix] = comp(fa.cs, c) * invspp;
-                }
-            } else {
-                A.g_kd[pix] = ba.gkd.x; A.g_kd[N + pix] = ba.gkd.y; A.g_kd[2 * N + pix] = ba.gkd.z;
-                A.g_korm[pix] = 0.0f; A.g_korm[N + pix] = ba.gr; A.g_korm[2 * N + pix] = ba.gm;
-                const float il = 1.0f / P.nlen;
-                const float3 gw = (ba.gnl.x * il) * P.t + (ba.gnl.y * il) * P.b;
-                A.g_nrm[pix] = gw.x; A.g_nrm[N + pix] = gw.y; A.g_nrm[2 * N + pix] = gw.z;
-            }
-        }
-    }
-    if (BWD && A.g_env) {
-        // one global atomic per touched hot slot and workgroup
+    shade_tile<BWD, DUMP>(A, blockIdx.x, s_marg, s_hot);
+    if (BWD) {
         __syncthreads();
-        const int n_hot = min(*A.env.n_hot, kHotMax);
-        for (int k = threadIdx.x; k < 3 * n_hot; k += blockDim.x) {
-            const float v = s_hot[k];
-            if (v != 0.0f) atomicAdd(A.g_env + 3 * (size_t)A.env.hot_texel[k / 3] + (k % 3), v);
-        }
+        hot_flush(A, s_hot);
     }
 }
+
+// ---------------------------------------------------------------------------
+// Serving: one persistent launch over the tiles of many requests.  Every
+// workgroup takes the next tile from a global counter and runs generation,
+// traversal, the forward evaluation and (for gradient requests) the adjoint
+// on it; it stops when the tiles run out, so every wave exits.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void serve_kernel(const ServeItem* items, int n_items, int64_t total_tiles,
+                                                       int* tile_counter, float4* scratch, int spp_max) {
+    extern __shared__ float smem[];
+    __shared__ int s_tile, s_item, s_cnt, s_next;
+    float* s_hot = smem;                     // 3 * kHotMax
+    float* s_marg = smem + 3 * kHotMax;      // H + 1 of the current item
+    float4* region = scratch + (size_t)blockIdx.x * (size_t)(2 * spp_max * kBlock);
+    while (true) {
+        if (threadIdx.x == 0) {
+            const int t = atomicAdd(tile_counter, 1);
+            int lo = 0, hi = n_items;           // item with first_global <= t
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (items[mid].first_global <= t) lo = mid; else hi = mid;
+            }
+            s_tile = t;
+            s_item = lo;
+            s_cnt = 0;
+            s_next = 0;
+        }
+        __syncthreads();
+        const int64_t t = s_tile;
+        if (t >= total_tiles) break;
+        const ServeItem& it = items[s_item];
+        const ShadeArgs& A = it.args;
+        const int64_t tile = it.first_tile + (t - it.first_global);
+        stage_marg(A, s_marg);
+        __syncthreads();
+        float4* reg = A.tau != 0.0f ? region : nullptr;
+        gen_tile<false>(A, tile, reg, it.hitbits, s_marg, &s_cnt);
+        __syncthreads();
+        if (reg) trace_tile<false>(A, tile, reg, s_cnt, it.hitbits, &s_next);
+        __syncthreads();
+        shade_tile<false, false>(A, tile, s_marg, s_hot);
+        if (A.g_cd) {
+            hot_zero(s_hot);
+            __syncthreads();
+            shade_tile<true, false>(A, tile, s_marg, s_hot);
+            __syncthreads();
+            hot_flush(A, s_hot);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void serve_reset(int* tile_counter) { *tile_counter = 0; }
 
 __global__ void trace_kernel(Scene sc, const float* o, const float* d, int64_t n, uint8_t* hit, int brute) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -645,6 +724,15 @@ hipError_t launch_shade_fwd(const ShadeArgs& a, hipStream_t s) {
         hipLaunchKernelGGL((shade_kernel<false, true>), dim3(n_blocks(a)), dim3(kBlock), marg_lds(a), s, a);
     else
         hipLaunchKernelGGL((shade_kernel<false, false>), dim3(n_blocks(a)), dim3(kBlock), marg_lds(a), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_serve(const ServeItem* items_dev, int n_items, int64_t total_tiles, int* tile_counter,
+                        float4* scratch, int spp_max, int n_workgroups, int max_H, hipStream_t s) {
+    hipLaunchKernelGGL(serve_reset, dim3(1), dim3(1), 0, s, tile_counter);
+    const size_t lds = sizeof(float) * (3 * kHotMax + (size_t)max_H + 1);
+    hipLaunchKernelGGL(serve_kernel, dim3(n_workgroups), dim3(kBlock), lds, s, items_dev, n_items, total_tiles,
+                       tile_counter, scratch, spp_max);
     return hipGetLastError();
 }
 

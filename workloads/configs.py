@@ -201,8 +201,11 @@ def sphere_scene(k, freq=71, n_boxes=20, env_hw=(256, 512), env_sigma=1.5):
     return rng, ds, boxes, verts, tris, env, tex_kd, tex_orm
 
 
-def make_sphere8(k=1, H=512, W=512, spp=8, n_views=8, freq=71, views=None):
-    rng, ds, boxes, verts, tris, env, tex_kd, tex_orm = sphere_scene(k, freq=freq)
+def make_sphere8(k=1, H=512, W=512, spp=8, n_views=8, freq=71, views=None, env_hw=(256, 512), scene=None):
+    """scene: a sphere_scene(...) tuple to reuse (same mesh and probe)."""
+    if scene is None:
+        scene = sphere_scene(k, freq=freq, env_hw=env_hw)
+    rng, ds, boxes, verts, tris, env, tex_kd, tex_orm = scene
     surfaces = [ds.intersect] + [
         (lambda c, h, y: (lambda o, d: hit_box(o, d, c, h, y)))(c, h, y) for (c, h, y) in boxes]
     eyes, hv = [], []
