@@ -399,3 +399,40 @@ def test_abi_rejects_bad_arguments():
     assert e.value.status == -4
     with pytest.raises(M.MCDIError):
         M.shade_fwd(scene, env, gb, 4, ray_eps=float("nan"))
+
+
+# ---------------------------------------------------------------------------
+# heavy occlusion: the 1.0M-triangle lattice room, 32 spp, sampled pixels
+# ---------------------------------------------------------------------------
+def test_fwd_bwd_lattice_sampled():
+    _need_gpu()
+    import paper_2206_03380_amd as M
+    w = make_workload("lattice", H=256, W=256, n_views=2)
+    g, (scene, env, gb, hb) = gpu_forward(w)
+    info = scene.info()
+    assert info["n_tris"] > 1_000_000 and info["bad_tris"] == 0
+    r = np.random.Generator(np.random.PCG64(4))
+    pix = np.sort(r.choice(np.nonzero(w.mask)[0], 2500, replace=False))
+    osc = oracle.Scene(w.verts, w.tris)
+    o = oracle.shade(w, pixels=pix, scene=osc, sync=g["decisions"][pix])
+    assert o["info"][:, 2].sum() == 0
+    valid = (w.mask[pix] > 0) & (o["info"][:, 1] == 0)
+    assert valid.mean() > 0.99
+    for key in ("c_d", "c_s"):
+        ok, worst, rep = compare(g[key][:, pix], o[key], valid, name=key)
+        print(rep)
+        assert ok, rep
+    hb_g = hitbits_per_pixel(g["hitbits"])[pix]
+    assert np.array_equal(hb_g, o["hitbits"])
+    hit_frac = np.unpackbits(o["hitbits"].view(np.uint8)).sum() / (len(pix) * 2 * w.spp)
+    assert hit_frac > 0.2     # heavy occlusion
+    ud, us = upstream_grads(w)
+    tud, tus = torch.from_numpy(ud).cuda(), torch.from_numpy(us).cuda()
+    g_kd, g_korm, g_nrm, g_env = M.shade_bwd(scene, env, gb, w.spp, tud, tus, hitbits=hb, seed=w.seed,
+                                             tau=w.tau, ray_eps=w.ray_eps)
+    ob = oracle.shade(w, pixels=pix, scene=osc, sync=g["decisions"][pix], grad=True,
+                      u_d=ud[:, pix].astype(np.float64), u_s=us[:, pix].astype(np.float64))
+    for gpu_t, key in ((g_kd, "g_kd"), (g_korm, "g_korm"), (g_nrm, "g_nrm")):
+        ok, worst, rep = compare(to_np(gpu_t)[:, pix], ob[key], valid, rel=1e-3, absf=1e-5, name=key)
+        print(rep)
+        assert ok, rep
