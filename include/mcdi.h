@@ -194,6 +194,22 @@ mcdi_status mcdi_trace_anyhit(mcdi_scene scene, const float* orig, const float* 
                               uint8_t* hit, int32_t brute, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Image loss on the estimator's outputs (appendix A): composition
+ * c = kd*c_d + c_s (section 4.2), L1 on tonemapped colours with
+ * T(x) = sRGB(log(max(x,0) + 1)), and the light regulariser
+ * |Y(T(c_d + c_s)) - V(T(ref))| with Y = (r+g+b)/3 and V = max(r,g,b).
+ *   L_image = mean over valid pixels and channels, L_light = mean over valid
+ *   pixels, L = L_image + w_light * L_light.
+ *   kd, c_d, c_s, ref  device [3][N]; mask device [N]
+ *   loss               device float [3]: L_image, L_light, L (overwritten)
+ *   g_kd, g_cd, g_cs   device [3][N], dL/d*, overwritten (each may be NULL)
+ * Deterministic (fixed-order FP64 reduction of per-workgroup partial sums).
+ * ------------------------------------------------------------------------- */
+mcdi_status mcdi_image_loss(const float* kd, const float* c_d, const float* c_s, const float* ref,
+                            const uint8_t* mask, int64_t n, float w_light, float* loss, float* g_kd, float* g_cd,
+                            float* g_cs, const mcdi_allocator* alloc, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Serving: one persistent launch over the tiles of many requests.
  *
  * A tile is 256 consecutive pixels of a request's G-buffer.  Each item gives

@@ -236,6 +236,22 @@ def trace_times():
     return [buf[i] for i in range(n.value)]
 
 
+def image_loss(kd, c_d, c_s, ref, mask, w_light=0.15, stream=None):
+    """Loss of the composed image (kd*c_d + c_s) against ref: L1 on tonemapped
+    colours + w_light * light regulariser.  Returns (loss [3] = (L_image,
+    L_light, L), g_kd, g_cd, g_cs), all on the device."""
+    n = mask.shape[0]
+    for name, t in (("kd", kd), ("c_d", c_d), ("c_s", c_s), ("ref", ref)):
+        _need(t, torch.float32, (3, n), name)
+    _need(mask, torch.uint8, (n,), "mask")
+    loss = torch.empty(3, dtype=torch.float32, device=kd.device)
+    g_kd, g_cd, g_cs = (torch.empty((3, n), dtype=torch.float32, device=kd.device) for _ in range(3))
+    L.check(L.lib().mcdi_image_loss(_ptr(kd), _ptr(c_d), _ptr(c_s), _ptr(ref), _ptr(mask), n, float(w_light),
+                                    _ptr(loss), _ptr(g_kd), _ptr(g_cd), _ptr(g_cs), C.byref(_TORCH_ALLOCATOR),
+                                    _stream(stream)))
+    return loss, g_kd, g_cd, g_cs
+
+
 def trace_anyhit(scene, orig, dirs, brute=False, stream=None):
     """orig, dirs: device f32 [3, n].  Returns uint8 [n] (1 = occluded)."""
     n = orig.shape[1]

@@ -98,6 +98,8 @@ def lib():
     L.mcdi_server_launch.argtypes = [vp, vp, C.c_int32]
     L.mcdi_server_destroy.restype = None
     L.mcdi_server_destroy.argtypes = [vp]
+    L.mcdi_image_loss.restype = C.c_int
+    L.mcdi_image_loss.argtypes = [vp, vp, vp, vp, vp, C.c_int64, C.c_float, vp, vp, vp, vp, vp, vp]
     L.mcdi_last_error.restype = C.c_char_p
     L.mcdi_version.restype = C.c_char_p
     _lib = L
@@ -112,4 +114,4 @@ def check(status):
 EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_build_env_cdf",
             "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
             "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_server_create", "mcdi_server_launch",
-            "mcdi_server_destroy", "mcdi_last_error", "mcdi_version")
+            "mcdi_server_destroy", "mcdi_image_loss", "mcdi_last_error", "mcdi_version")

@@ -538,6 +538,25 @@ mcdi_status mcdi_server_launch(mcdi_server sv, const mcdi_serve_item* items, int
     return ok();
 }
 
+mcdi_status mcdi_image_loss(const float* kd, const float* c_d, const float* c_s, const float* ref,
+                            const uint8_t* mask, int64_t n, float w_light, float* loss, float* g_kd, float* g_cd,
+                            float* g_cs, const mcdi_allocator* alloc, void* stream) {
+    if (!kd || !c_d || !c_s || !ref || !mask || !loss) return fail(MCDI_E_INVALID, "mcdi_image_loss: NULL input");
+    if (n < 1) return fail(MCDI_E_INVALID, "mcdi_image_loss: n must be >= 1");
+    if (n >= ((int64_t)1 << 31)) return fail(MCDI_E_UNSUPPORTED, "mcdi_image_loss: n >= 2^31");
+    if (!std::isfinite(w_light)) return fail(MCDI_E_INVALID, "mcdi_image_loss: w_light must be finite");
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(MCDI_E_INVALID, "mcdi_image_loss: allocator incomplete");
+    hipStream_t s = (hipStream_t)stream;
+    Alloc al = make_alloc(alloc);
+    const int64_t nb = (n + 255) / 256;
+    double* scratch = (double*)al.get(sizeof(double) * (size_t)(3 * nb + 1), s);
+    if (!scratch) return fail(MCDI_E_OOM, "mcdi_image_loss: scratch allocation failed");
+    hipError_t e = launch_image_loss(kd, c_d, c_s, ref, mask, n, w_light, loss, g_kd, g_cd, g_cs, scratch, s);
+    al.put(scratch, s);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_image_loss: %s", hipGetErrorString(e));
+    return ok();
+}
+
 mcdi_status mcdi_trace_anyhit(mcdi_scene sc, const float* orig, const float* dir, int64_t n, uint8_t* hit,
                               int32_t brute, void* stream) {
     if (!sc) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: NULL scene");

@@ -109,6 +109,10 @@ hipError_t launch_shade_bwd(const ShadeArgs& a, hipStream_t s);
 hipError_t launch_trace(const Scene& sc, const float* o, const float* d, int64_t n, uint8_t* hit,
                         int brute, hipStream_t s);
 
+hipError_t launch_image_loss(const float* kd, const float* cd, const float* cs, const float* ref,
+                             const uint8_t* mask, int64_t n, float w_light, float* loss, float* g_kd, float* g_cd,
+                             float* g_cs, double* scratch, hipStream_t s);
+
 // BVH build: temp buffers are obtained through the callbacks
 struct TempAlloc {
     void* (*alloc)(void* ctx, size_t bytes, hipStream_t s);
