@@ -210,6 +210,46 @@ mcdi_status mcdi_image_loss(const float* kd, const float* c_d, const float* c_s,
                             float* g_cs, const mcdi_allocator* alloc, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Differentiable cross-bilateral denoiser (appendix B "Bilateral Denoiser"):
+ * the spatial filter of SVGF evaluated densely, applied to the demodulated
+ * diffuse and the specular lighting (section 4.2 "Denoising").
+ *   out(p) = sum_q in(q) w(p,q) / W(p),  W(p) = sum_q w(p,q),
+ *   w(p,q) = exp(-|p-q|^2 / (2 sigma^2))
+ *          * exp(-|z(p) - z(q)| / (sigma_z |grad z(p) . (p-q)| + 1e-5))
+ *          * max(0, n(p) . n(q))^sigma_n
+ * over q in the (2R+1)^2 square around p inside the same view, with
+ * R = mcdi_bilateral_radius(sigma) = clamp(ceil(3 sigma), 1, 8).  grad z is
+ * the central difference of the depth guide over the valid 4-neighbours
+ * (one-sided where one is missing, 0 where both are).  Pixels with mask 0
+ * neither contribute nor receive (their outputs are 0).  The backward pass
+ * propagates to the colours only: g_in(q) = sum_p g_out(p) w(p,q) / W(p).
+ *   depth   device [N] depth guide (mcdi_view_depth gives |pos - eye|)
+ *   nrm     device [3][N] normal guide, normalised by the filter
+ *   in/out  device [n_chan][N], n_chan in {1, 3, 6} (6: c_d and c_s stacked,
+ *           filtered with the same weights); out must not alias in
+ *   wsum    device [N]: W(p), written by the forward (may be NULL there) and
+ *           required by the backward
+ * sigma > 0, sigma_z >= 0, sigma_n > 0, all finite.  Deterministic.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_views, height, width;
+    const float* depth;
+    const float* nrm;
+    const uint8_t* mask;
+    float sigma, sigma_z, sigma_n;
+} mcdi_bilateral_guide;
+
+int32_t mcdi_bilateral_radius(float sigma);
+mcdi_status mcdi_bilateral_fwd(const mcdi_bilateral_guide* guide, int32_t n_chan, const float* in, float* out,
+                               float* wsum, void* stream);
+mcdi_status mcdi_bilateral_bwd(const mcdi_bilateral_guide* guide, int32_t n_chan, const float* g_out,
+                               const float* wsum, float* g_in, void* stream);
+
+/* Depth guide of a G-buffer: depth[p] = |pos(p) - eye(view of p)| for valid
+ * pixels, 0 elsewhere.  depth device float32 [N]. */
+mcdi_status mcdi_view_depth(const mcdi_gbuffer* gbuf, float* depth, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Serving: one persistent launch over the tiles of many requests.
  *
  * A tile is 256 consecutive pixels of a request's G-buffer.  Each item gives

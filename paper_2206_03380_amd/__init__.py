@@ -252,6 +252,79 @@ def image_loss(kd, c_d, c_s, ref, mask, w_light=0.15, stream=None):
     return loss, g_kd, g_cd, g_cs
 
 
+def denoise_sigma(iteration, ramp=1750, lo=1e-4, hi=2.0):
+    """Spatial footprint of the bilateral denoiser during optimisation: linear
+    from lo to hi over the first `ramp` iterations, then hi (appendix B)."""
+    f = min(max(iteration / float(ramp), 0.0), 1.0) if ramp > 0 else 1.0
+    return lo + (hi - lo) * f
+
+
+def bilateral_radius(sigma):
+    """Footprint radius R of the filter for spatial std-dev sigma (pixels)."""
+    return int(L.lib().mcdi_bilateral_radius(float(sigma)))
+
+
+@dataclass
+class BilateralGuide:
+    """Edge-stopping guides of the cross-bilateral denoiser for V views of
+    H x W pixels: depth f32 [N], normal f32 [3, N], mask u8 [N]."""
+    depth: torch.Tensor
+    nrm: torch.Tensor
+    mask: torch.Tensor
+    n_views: int
+    height: int
+    width: int
+    sigma: float = 2.0
+    sigma_z: float = 1.0
+    sigma_n: float = 128.0
+
+    @property
+    def n(self):
+        return self.n_views * self.height * self.width
+
+    def struct(self):
+        n = self.n
+        _need(self.depth, torch.float32, (n,), "depth")
+        _need(self.nrm, torch.float32, (3, n), "nrm")
+        _need(self.mask, torch.uint8, (n,), "mask")
+        return L.BilateralGuide(self.n_views, self.height, self.width, self.depth.data_ptr(), self.nrm.data_ptr(),
+                                self.mask.data_ptr(), float(self.sigma), float(self.sigma_z), float(self.sigma_n))
+
+    @staticmethod
+    def from_gbuffer(gb, sigma=2.0, sigma_z=1.0, sigma_n=128.0, stream=None):
+        return BilateralGuide(view_depth(gb, stream), gb.nrm, gb.mask, gb.n_views, gb.height, gb.width, sigma,
+                              sigma_z, sigma_n)
+
+
+def view_depth(gb, stream=None):
+    """Depth guide |pos - eye| of a G-buffer (0 where mask is 0), f32 [N]."""
+    gs = gb.struct()
+    depth = torch.empty(gb.n, dtype=torch.float32, device=gb.pos.device)
+    L.check(L.lib().mcdi_view_depth(C.byref(gs), _ptr(depth), _stream(stream)))
+    return depth
+
+
+def bilateral_fwd(guide, x, stream=None):
+    """Filter x [C, N] (C in 1, 3, 6).  Returns (out [C, N], wsum [N])."""
+    gs = guide.struct()
+    _need(x, torch.float32, (x.shape[0], guide.n), "x")
+    out = torch.empty_like(x)
+    wsum = torch.empty(guide.n, dtype=torch.float32, device=x.device)
+    L.check(L.lib().mcdi_bilateral_fwd(C.byref(gs), x.shape[0], _ptr(x), _ptr(out), _ptr(wsum), _stream(stream)))
+    return out, wsum
+
+
+def bilateral_bwd(guide, g_out, wsum, stream=None):
+    """Gradient with respect to the filtered colours for upstream g_out [C, N]."""
+    gs = guide.struct()
+    _need(g_out, torch.float32, (g_out.shape[0], guide.n), "g_out")
+    _need(wsum, torch.float32, (guide.n,), "wsum")
+    g_in = torch.empty_like(g_out)
+    L.check(L.lib().mcdi_bilateral_bwd(C.byref(gs), g_out.shape[0], _ptr(g_out), _ptr(wsum), _ptr(g_in),
+                                       _stream(stream)))
+    return g_in
+
+
 def trace_anyhit(scene, orig, dirs, brute=False, stream=None):
     """orig, dirs: device f32 [3, n].  Returns uint8 [n] (1 = occluded)."""
     n = orig.shape[1]
@@ -263,4 +336,4 @@ def trace_anyhit(scene, orig, dirs, brute=False, stream=None):
     return hit
 
 
-from .autograd import MCDIShade  # noqa: E402,F401
+from .autograd import MCDIShade, Bilateral  # noqa: E402,F401

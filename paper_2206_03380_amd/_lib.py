@@ -54,6 +54,12 @@ class Stats(C.Structure):
                 ("tri_tests", C.c_uint64), ("reserved", C.c_uint64)]
 
 
+class BilateralGuide(C.Structure):
+    _fields_ = [("n_views", C.c_int32), ("height", C.c_int32), ("width", C.c_int32), ("depth", C.c_void_p),
+                ("nrm", C.c_void_p), ("mask", C.c_void_p), ("sigma", C.c_float), ("sigma_z", C.c_float),
+                ("sigma_n", C.c_float)]
+
+
 class SceneInfo(C.Structure):
     _fields_ = [("n_tris", C.c_int64), ("n_nodes", C.c_int32), ("max_depth", C.c_int32),
                 ("bad_tris", C.c_int32), ("reserved", C.c_int32)]
@@ -100,6 +106,14 @@ def lib():
     L.mcdi_server_destroy.argtypes = [vp]
     L.mcdi_image_loss.restype = C.c_int
     L.mcdi_image_loss.argtypes = [vp, vp, vp, vp, vp, C.c_int64, C.c_float, vp, vp, vp, vp, vp, vp]
+    L.mcdi_bilateral_radius.restype = C.c_int32
+    L.mcdi_bilateral_radius.argtypes = [C.c_float]
+    L.mcdi_bilateral_fwd.restype = C.c_int
+    L.mcdi_bilateral_fwd.argtypes = [C.POINTER(BilateralGuide), C.c_int32, vp, vp, vp, vp]
+    L.mcdi_bilateral_bwd.restype = C.c_int
+    L.mcdi_bilateral_bwd.argtypes = [C.POINTER(BilateralGuide), C.c_int32, vp, vp, vp, vp]
+    L.mcdi_view_depth.restype = C.c_int
+    L.mcdi_view_depth.argtypes = [C.POINTER(GBuffer), vp, vp]
     L.mcdi_last_error.restype = C.c_char_p
     L.mcdi_version.restype = C.c_char_p
     _lib = L
@@ -114,4 +128,5 @@ def check(status):
 EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_build_env_cdf",
             "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
             "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_server_create", "mcdi_server_launch",
-            "mcdi_server_destroy", "mcdi_image_loss", "mcdi_last_error", "mcdi_version")
+            "mcdi_server_destroy", "mcdi_image_loss", "mcdi_bilateral_radius", "mcdi_bilateral_fwd",
+            "mcdi_bilateral_bwd", "mcdi_view_depth", "mcdi_last_error", "mcdi_version")

@@ -60,3 +60,23 @@ class MCDIShade(torch.autograd.Function):
                                        _ptr(g_cs), _ptr(hb) if has_bits else None, _ptr(g_kd), _ptr(g_korm),
                                        _ptr(g_nrm), _ptr(g_env), None, _stream()))
         return g_kd, g_korm, g_nrm, g_env, None, None, None, None, None, None, None, None
+
+
+class Bilateral(torch.autograd.Function):
+    """out = Bilateral.apply(x, guide): cross-bilateral denoiser on x [C, N]
+    (C in 1, 3, 6) with the guide's depth/normal edge-stopping weights.  The
+    weights are constants: the gradient flows to x only (appendix B)."""
+
+    @staticmethod
+    def forward(ctx, x, guide):
+        from . import bilateral_fwd
+        out, wsum = bilateral_fwd(guide, x.contiguous())
+        ctx.save_for_backward(wsum)
+        ctx.guide = guide
+        return out
+
+    @staticmethod
+    def backward(ctx, g_out):
+        from . import bilateral_bwd
+        (wsum,) = ctx.saved_tensors
+        return bilateral_bwd(ctx.guide, g_out.contiguous().float(), wsum), None

@@ -557,6 +557,65 @@ mcdi_status mcdi_image_loss(const float* kd, const float* c_d, const float* c_s,
     return ok();
 }
 
+static mcdi_status bilat_args(const char* who, const mcdi_bilateral_guide* g, int32_t nc, BilatArgs& a) {
+    if (!g) return fail(MCDI_E_INVALID, "%s: NULL guide", who);
+    if (g->n_views < 0 || g->height < 0 || g->width < 0)
+        return fail(MCDI_E_INVALID, "%s: negative size", who);
+    const int64_t n = (int64_t)g->n_views * g->height * g->width;
+    if (n >= ((int64_t)1 << 31)) return fail(MCDI_E_UNSUPPORTED, "%s: n_views*height*width >= 2^31", who);
+    if (nc != 1 && nc != 3 && nc != 6) return fail(MCDI_E_UNSUPPORTED, "%s: n_chan must be 1, 3 or 6", who);
+    if (!(std::isfinite(g->sigma) && g->sigma > 0.0f)) return fail(MCDI_E_INVALID, "%s: sigma must be > 0", who);
+    if (!(std::isfinite(g->sigma_z) && g->sigma_z >= 0.0f))
+        return fail(MCDI_E_INVALID, "%s: sigma_z must be >= 0", who);
+    if (!(std::isfinite(g->sigma_n) && g->sigma_n > 0.0f))
+        return fail(MCDI_E_INVALID, "%s: sigma_n must be > 0", who);
+    if (n > 0 && (!g->depth || !g->nrm || !g->mask)) return fail(MCDI_E_INVALID, "%s: NULL guide buffer", who);
+    a = BilatArgs{g->n_views, g->height, g->width, n, g->depth, g->nrm, g->mask,
+                  g->sigma, g->sigma_z, g->sigma_n, bilateral_radius(g->sigma), 0, 0};
+    bilateral_tiles(a);
+    if ((int64_t)a.tiles_x * a.tiles_y * a.V >= ((int64_t)1 << 31))
+        return fail(MCDI_E_UNSUPPORTED, "%s: too many tiles", who);
+    return MCDI_OK;
+}
+
+int32_t mcdi_bilateral_radius(float sigma) { return bilateral_radius(sigma); }
+
+mcdi_status mcdi_bilateral_fwd(const mcdi_bilateral_guide* g, int32_t nc, const float* in, float* out,
+                               float* wsum, void* stream) {
+    BilatArgs a;
+    mcdi_status st = bilat_args("mcdi_bilateral_fwd", g, nc, a);
+    if (st != MCDI_OK) return st;
+    if (a.n > 0 && (!in || !out)) return fail(MCDI_E_INVALID, "mcdi_bilateral_fwd: NULL colour buffer");
+    if (a.n > 0 && (const float*)out == in) return fail(MCDI_E_INVALID, "mcdi_bilateral_fwd: out aliases in");
+    hipError_t e = launch_bilateral_fwd(a, nc, in, out, wsum, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_bilateral_fwd: %s", hipGetErrorString(e));
+    return ok();
+}
+
+mcdi_status mcdi_bilateral_bwd(const mcdi_bilateral_guide* g, int32_t nc, const float* g_out, const float* wsum,
+                               float* g_in, void* stream) {
+    BilatArgs a;
+    mcdi_status st = bilat_args("mcdi_bilateral_bwd", g, nc, a);
+    if (st != MCDI_OK) return st;
+    if (a.n > 0 && (!g_out || !wsum || !g_in)) return fail(MCDI_E_INVALID, "mcdi_bilateral_bwd: NULL buffer");
+    if (a.n > 0 && (const float*)g_in == g_out) return fail(MCDI_E_INVALID, "mcdi_bilateral_bwd: g_in aliases g_out");
+    hipError_t e = launch_bilateral_bwd(a, nc, g_out, wsum, g_in, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_bilateral_bwd: %s", hipGetErrorString(e));
+    return ok();
+}
+
+mcdi_status mcdi_view_depth(const mcdi_gbuffer* g, float* depth, void* stream) {
+    if (!g) return fail(MCDI_E_INVALID, "mcdi_view_depth: NULL gbuffer");
+    if (g->n_views < 0 || g->height < 0 || g->width < 0) return fail(MCDI_E_INVALID, "mcdi_view_depth: negative size");
+    const int64_t n = (int64_t)g->n_views * g->height * g->width;
+    if (n >= ((int64_t)1 << 31)) return fail(MCDI_E_UNSUPPORTED, "mcdi_view_depth: n >= 2^31");
+    if (n > 0 && (!g->pos || !g->mask || !g->eye || !depth)) return fail(MCDI_E_INVALID, "mcdi_view_depth: NULL buffer");
+    GBufView v{g->n_views, g->height, g->width, g->view_base, g->pos, g->nrm, g->kd, g->korm, g->mask, g->eye, n};
+    hipError_t e = launch_view_depth(v, depth, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_view_depth: %s", hipGetErrorString(e));
+    return ok();
+}
+
 mcdi_status mcdi_trace_anyhit(mcdi_scene sc, const float* orig, const float* dir, int64_t n, uint8_t* hit,
                               int32_t brute, void* stream) {
     if (!sc) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: NULL scene");

@@ -114,6 +114,26 @@ hipError_t launch_image_loss(const float* kd, const float* cd, const float* cs, 
                              float* g_cs, double* scratch, hipStream_t s);
 
 // BVH build: temp buffers are obtained through the callbacks
+// Cross-bilateral filter over V views of H x W pixels (N = V*H*W).
+constexpr int kBilatMaxR = 8;
+struct BilatArgs {
+    int32_t V, H, W;
+    int64_t n;
+    const float* depth;    // [N]
+    const float* nrm;      // [3][N]
+    const uint8_t* mask;   // [N]
+    float sigma, sigma_z, sigma_n;
+    int32_t R;             // footprint radius
+    int32_t tiles_x, tiles_y;
+};
+int bilateral_radius(float sigma);
+void bilateral_tiles(BilatArgs& a);
+hipError_t launch_bilateral_fwd(const BilatArgs& a, int nc, const float* in, float* out, float* wsum,
+                                hipStream_t s);
+hipError_t launch_bilateral_bwd(const BilatArgs& a, int nc, const float* g_out, const float* wsum, float* g_in,
+                                hipStream_t s);
+hipError_t launch_view_depth(const GBufView& g, float* depth, hipStream_t s);
+
 struct TempAlloc {
     void* (*alloc)(void* ctx, size_t bytes, hipStream_t s);
     void (*free)(void* ctx, void* p, hipStream_t s);

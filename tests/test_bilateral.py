@@ -1,0 +1,493 @@
+"""Cross-bilateral denoiser (appendix B): oracle pins on the CPU, HIP parity
+through the C ABI on the GPU.
+
+Pins tie the FP64 oracle to what the definition fixes without re-deriving
+the weight formula: closed forms of the depth gradient, special cases that
+reduce the filter to a plain normalised convolution (library correlate),
+invariants (constants reproduced, masked pixels ignored), the adjoint
+identity <g, F c> = <F^T g, c>, and the paper's remark that a symmetric
+filter sends the loss gradient through the same filter (section 4.2,
+"Denoising").
+
+GPU tolerance (derived from FP32 arithmetic of one weight): the normal term
+raises a dot product with ~4e-7 error to the power 128 (~5e-5 relative), the
+combined exponent and the hardware exp2/log2 add a few 1e-6, and FP32 sums of
+at most 289 taps add ~2e-5 of the largest colour.  Output error is at most
+about twice the weight error times the largest colour in the footprint, so
+|gpu - oracle| <= 3e-4 * max_footprint|c| + 1e-7; the backward bound uses the
+oracle's backward of |g| as the scale.
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from oracle import bilateral as B
+from workloads import make_workload, noisy_lighting
+
+TOL = 3e-4
+
+
+# ----------------------------------------------------------------------------
+# CPU: oracle pins
+# ----------------------------------------------------------------------------
+
+def _flat(a):
+    return np.asarray(a, np.float64).reshape(a.shape[0], -1) if a.ndim == 4 else np.asarray(a).reshape(-1)
+
+
+def _uniform_guides(V, H, W, z=3.0, n=(0.0, 0.0, 1.0)):
+    depth = np.full(V * H * W, z)
+    nrm = np.tile(np.asarray(n, np.float64)[:, None], (1, V * H * W))
+    mask = np.ones(V * H * W, np.uint8)
+    return depth, nrm, mask
+
+
+def _norm_correlate(c, m, K):
+    """Normalised correlation over valid pixels of each view: the filter with
+    a translation-invariant weight kernel K (zero outside the view)."""
+    out = np.zeros_like(c)
+    for v in range(c.shape[1]):
+        den = ndimage.correlate(m[v].astype(np.float64), K, mode="constant")
+        for ch in range(c.shape[0]):
+            num = ndimage.correlate(c[ch, v] * m[v], K, mode="constant")
+            out[ch, v] = np.where(m[v] > 0, num / np.where(den > 0, den, 1), 0)
+    return out
+
+
+def _gauss(R, sigma):
+    d = np.arange(-R, R + 1)
+    return np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2 * sigma * sigma))
+
+
+def test_radius_rule():
+    assert B.radius(2.0) == 6 and B.radius(1e-4) == 1 and B.radius(0.34) == 2 and B.radius(5.0) == 8
+    assert B.radius(1.0) == 3 and B.radius(2.5) == 8
+
+
+def test_depth_gradient_closed_form():
+    H, W = 5, 7
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    z = (x ** 2 + 3 * y ** 2)[None]
+    m = np.ones_like(z, bool)
+    gx, gy = B.depth_gradient(z, m)
+    # d/dx of x^2 by central differences is 2x; one-sided at the borders
+    ex = np.where(x == 0, 1.0, np.where(x == W - 1, 2 * x - 1, 2 * x))
+    ey = np.where(y == 0, 3.0, np.where(y == H - 1, 3 * (2 * y - 1), 6 * y))
+    assert np.array_equal(gx[0], ex) and np.array_equal(gy[0], ey)
+    # an invalid neighbour turns the central difference one-sided, two give 0
+    m2 = m.copy()
+    m2[0, 2, 3] = False
+    gx2, _ = B.depth_gradient(z, m2)
+    assert gx2[0, 2, 2] == z[0, 2, 2] - z[0, 2, 1] and gx2[0, 2, 4] == z[0, 2, 5] - z[0, 2, 4]
+    m3 = m.copy()
+    m3[0, 1, 2] = m3[0, 1, 4] = False
+    gx3, _ = B.depth_gradient(z, m3)
+    assert gx3[0, 1, 3] == 0.0
+
+
+def test_constant_colour_reproduced():
+    rng = np.random.default_rng(1)
+    V, H, W = 2, 13, 17
+    N = V * H * W
+    depth = 2 + rng.random(N)
+    nrm = np.vstack([rng.normal(0, 0.3, (2, N)), np.ones((1, N))])
+    mask = (rng.random(N) < 0.9).astype(np.uint8)
+    c = np.tile(np.array([[0.25], [7.0], [-3.0]]), (1, N))
+    out, wsum = B.bilateral_fwd(c, depth, nrm, mask, V, H, W, 1.3)
+    ok = (mask > 0) & (wsum > 0)
+    assert np.allclose(out[:, ok], c[:, ok], rtol=1e-13, atol=0)
+    assert np.all(out[:, mask == 0] == 0) and np.all(wsum[mask == 0] == 0)
+
+
+def test_tiny_sigma_is_identity():
+    rng = np.random.default_rng(2)
+    V, H, W = 1, 9, 11
+    N = V * H * W
+    depth = 1 + rng.random(N)
+    nrm = rng.normal(0, 1, (3, N))
+    mask = np.ones(N, np.uint8)
+    c = rng.random((3, N))
+    out, _ = B.bilateral_fwd(c, depth, nrm, mask, V, H, W, 1e-4)
+    assert np.allclose(out, c, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("sigma", [0.7, 2.0, 2.6])
+def test_uniform_guides_are_a_normalised_gaussian(sigma):
+    rng = np.random.default_rng(3)
+    V, H, W = 2, 23, 19
+    depth, nrm, mask = _uniform_guides(V, H, W)
+    mask[rng.random(mask.size) < 0.1] = 0
+    c = rng.random((3, V * H * W))
+    out, _ = B.bilateral_fwd(c, depth, nrm, mask, V, H, W, sigma)
+    R = B.radius(sigma)
+    ref = _norm_correlate(c.reshape(3, V, H, W), mask.reshape(V, H, W), _gauss(R, sigma))
+    assert np.allclose(out, ref.reshape(3, -1), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("angle_deg", [3.0, 10.0, 170.0])
+def test_normal_term_two_regions(angle_deg):
+    # left half faces +z, right half is tilted by `angle` about y; depth flat.
+    V, H, W, sigma = 1, 15, 20, 1.5
+    R = B.radius(sigma)
+    depth, nrm, mask = _uniform_guides(V, H, W)
+    a = math.radians(angle_deg)
+    x = np.tile(np.arange(W), H)
+    right = x >= W // 2
+    nrm[:, right] = np.array([[math.sin(a)], [0.0], [math.cos(a)]])
+    A, Bc = 1.0, 5.0
+    c = np.where(right, Bc, A)[None].repeat(3, 0).astype(np.float64)
+    out, _ = B.bilateral_fwd(c, depth, nrm, mask, V, H, W, sigma, sigma_n=128.0)
+    # weight of a cross-region tap = Gaussian * cos(angle)^128
+    K = _gauss(R, sigma)
+    f = max(0.0, math.cos(a)) ** 128     # facing away: no weight
+    rr = right.reshape(H, W).astype(np.float64)
+    same_r = ndimage.correlate(rr, K, mode="constant")
+    same_l = ndimage.correlate(1 - rr, K, mode="constant")
+    with np.errstate(invalid="ignore"):   # 0/0 only in the branch not taken
+        exp_left = (A * same_l + f * Bc * same_r) / (same_l + f * same_r)
+        exp_right = (Bc * same_r + f * A * same_l) / (same_r + f * same_l)
+    exp = np.where(rr > 0, exp_right, exp_left).reshape(-1)
+    assert np.allclose(out[0], exp, rtol=1e-12)
+
+
+@pytest.mark.parametrize("sigma_z", [1.0, 3.0])
+def test_tilted_plane_depth_term(sigma_z):
+    # z linear in x, y: the linear prediction is exact at every pixel, so the
+    # depth factor of tap (dx, dy) is exp(-|s| / (sigma_z |s| + eps)), s = a dx + b dy
+    V, H, W, sigma = 1, 21, 18, 1.2
+    R = B.radius(sigma)
+    a, b = 0.03, 0.011
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    depth = (2.0 + a * xx + b * yy).reshape(-1)
+    _, nrm, mask = _uniform_guides(V, H, W)
+    rng = np.random.default_rng(4)
+    c = rng.random((3, V * H * W))
+    out, _ = B.bilateral_fwd(c, depth, nrm, mask, V, H, W, sigma, sigma_z=sigma_z)
+    d = np.arange(-R, R + 1)
+    s = np.abs(a * d[None, :] + b * d[:, None])
+    K = _gauss(R, sigma) * np.exp(-s / (sigma_z * s + 1e-5))
+    ref = _norm_correlate(c.reshape(3, V, H, W), mask.reshape(V, H, W), K)
+    assert np.allclose(out, ref.reshape(3, -1), rtol=1e-9, atol=1e-12)
+
+
+def test_depth_step_does_not_mix():
+    V, H, W, sigma = 1, 12, 24, 2.0
+    depth, nrm, mask = _uniform_guides(V, H, W)
+    x = np.tile(np.arange(W), H)
+    far = x >= W // 2
+    depth[far] = 5.0
+    c = np.where(far, 9.0, 2.0)[None].repeat(3, 0).astype(np.float64)
+    out, _ = B.bilateral_fwd(c, depth, nrm, mask, V, H, W, sigma)
+    # pixels two or more columns from the step have zero depth gradient, so a
+    # tap across the step weighs exp(-3 / 1e-5) = 0
+    away = np.abs(x - (W // 2 - 0.5)) >= 2
+    assert np.allclose(out[:, away], c[:, away], rtol=1e-14, atol=0)
+    # next to the step the gradient straddles it and the sides do blend
+    assert not np.allclose(out[:, ~away], c[:, ~away], rtol=1e-3)
+
+
+def _random_case(seed, V=2, H=17, W=23):
+    rng = np.random.default_rng(seed)
+    N = V * H * W
+    depth = 2 + 0.3 * rng.random(N)
+    nrm = np.vstack([rng.normal(0, 0.2, (2, N)), np.ones((1, N))])
+    mask = (rng.random(N) < 0.85).astype(np.uint8)
+    return V, H, W, depth, nrm, mask, rng
+
+
+@pytest.mark.parametrize("sigma", [0.5, 1.0, 2.0])
+def test_adjoint_identity(sigma):
+    V, H, W, depth, nrm, mask, rng = _random_case(5)
+    c = rng.normal(size=(3, V * H * W))
+    g = rng.normal(size=(3, V * H * W))
+    Fc, _ = B.bilateral_fwd(c, depth, nrm, mask, V, H, W, sigma)
+    Ftg = B.bilateral_bwd(g, depth, nrm, mask, V, H, W, sigma)
+    lhs = float((g * Fc).sum())
+    rhs = float((Ftg * c).sum())
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(g).sum() * np.abs(c).max())
+
+
+def test_symmetric_filter_shares_gradient_through_itself():
+    # uniform guides: W(p) is the same for every p farther than R from the
+    # border, and the Gaussian is symmetric, so F^T g = F g there
+    V, H, W, sigma = 1, 40, 44, 2.0
+    R = B.radius(sigma)
+    depth, nrm, mask = _uniform_guides(V, H, W)
+    g = np.random.default_rng(6).normal(size=(3, V * H * W))
+    fg, _ = B.bilateral_fwd(g, depth, nrm, mask, V, H, W, sigma)
+    ftg = B.bilateral_bwd(g, depth, nrm, mask, V, H, W, sigma)
+    yy, xx = np.divmod(np.arange(H * W), W)
+    inner = (yy >= 2 * R) & (yy < H - 2 * R) & (xx >= 2 * R) & (xx < W - 2 * R)
+    assert inner.sum() > 50
+    assert np.allclose(fg[:, inner], ftg[:, inner], rtol=1e-12, atol=1e-14)
+    assert not np.allclose(fg[:, ~inner], ftg[:, ~inner], rtol=1e-6)
+
+
+def test_invalid_pixels_are_ignored():
+    V, H, W, depth, nrm, mask, rng = _random_case(7)
+    c = rng.random((3, V * H * W))
+    out, wsum = B.bilateral_fwd(c, depth, nrm, mask, V, H, W, 1.5)
+    bad = mask == 0
+    c2, d2, n2 = c.copy(), depth.copy(), nrm.copy()
+    c2[:, bad] = np.nan
+    d2[bad] = -1e30
+    n2[:, bad] = 7.0
+    out2, wsum2 = B.bilateral_fwd(c2, d2, n2, mask, V, H, W, 1.5)
+    assert np.array_equal(out, out2) and np.array_equal(wsum, wsum2)
+    assert np.all(out[:, bad] == 0)
+    g = rng.random((3, V * H * W))
+    gb = B.bilateral_bwd(g, depth, nrm, mask, V, H, W, 1.5)
+    g2 = g.copy()
+    g2[:, bad] = np.nan
+    assert np.array_equal(gb, B.bilateral_bwd(g2, d2, n2, mask, V, H, W, 1.5))
+    assert np.all(gb[:, bad] == 0)
+
+
+def test_views_do_not_mix():
+    V, H, W, depth, nrm, mask, rng = _random_case(8)
+    c = rng.random((3, V * H * W))
+    out, _ = B.bilateral_fwd(c, depth, nrm, mask, V, H, W, 2.0)
+    one = H * W
+    o0, _ = B.bilateral_fwd(c[:, :one], depth[:one], nrm[:, :one], mask[:one], 1, H, W, 2.0)
+    assert np.array_equal(out[:, :one], o0)
+
+
+def test_channels_filter_independently():
+    V, H, W, depth, nrm, mask, rng = _random_case(10)
+    c = rng.random((6, V * H * W))
+    o6, w6 = B.bilateral_fwd(c, depth, nrm, mask, V, H, W, 1.0)
+    o1, w1 = B.bilateral_fwd(c[4:5], depth, nrm, mask, V, H, W, 1.0)
+    assert o6.shape == (6, V * H * W) and np.array_equal(o6[4:5], o1) and np.array_equal(w6, w1)
+    g6 = B.bilateral_bwd(c, depth, nrm, mask, V, H, W, 1.0)
+    assert g6.shape == (6, V * H * W) and np.array_equal(g6[:3], B.bilateral_bwd(c[:3], depth, nrm, mask, V, H, W, 1.0))
+
+
+def test_view_depth_is_distance():
+    rng = np.random.default_rng(9)
+    V, H, W = 2, 3, 4
+    eye = rng.normal(size=(V, 3))
+    t = 1 + rng.random(V * H * W)
+    d = rng.normal(size=(3, V * H * W))
+    d /= np.linalg.norm(d, axis=0)
+    pos = eye.repeat(H * W, 0).T + t * d
+    mask = np.ones(V * H * W, np.uint8)
+    mask[3] = 0
+    z = B.view_depth(pos, eye, mask, V, H, W)
+    assert np.allclose(z[mask > 0], t[mask > 0], rtol=1e-14) and z[3] == 0
+
+
+def test_sigma_schedule():
+    import paper_2206_03380_amd as M
+    assert M.denoise_sigma(0) == 1e-4 and M.denoise_sigma(1750) == 2.0 and M.denoise_sigma(5000) == 2.0
+    assert abs(M.denoise_sigma(875) - (1e-4 + 2.0) / 2) < 1e-12
+
+
+def test_abi_validation_without_device():
+    """Argument errors are reported before anything touches the device."""
+    import ctypes as C
+    from paper_2206_03380_amd import _lib as L
+    lib = L.lib()
+    assert lib.mcdi_bilateral_radius(2.0) == 6 and lib.mcdi_bilateral_radius(0.0) == 1
+    g = L.BilateralGuide(1, 4, 4, 1, 1, 1, 2.0, 1.0, 128.0)
+    assert lib.mcdi_bilateral_fwd(C.byref(g), 2, 8, 16, None, None) == -4      # n_chan
+    assert lib.mcdi_bilateral_fwd(None, 3, 8, 16, None, None) == -1
+    for bad in (dict(sigma=0.0), dict(sigma=float("nan")), dict(sigma_n=0.0), dict(sigma_z=-1.0)):
+        gb = L.BilateralGuide(1, 4, 4, 1, 1, 1, bad.get("sigma", 2.0), bad.get("sigma_z", 1.0),
+                              bad.get("sigma_n", 128.0))
+        assert lib.mcdi_bilateral_fwd(C.byref(gb), 3, 8, 16, None, None) == -1, bad
+    assert lib.mcdi_bilateral_fwd(C.byref(g), 3, 8, 8, None, None) == -1        # out aliases in
+    assert lib.mcdi_bilateral_bwd(C.byref(g), 3, 8, None, 16, None) == -1      # wsum required
+    g0 = L.BilateralGuide(1, 4, 4, None, 1, 1, 2.0, 1.0, 128.0)
+    assert lib.mcdi_bilateral_fwd(C.byref(g0), 3, 8, 16, None, None) == -1     # NULL depth
+    big = L.BilateralGuide(4, 32768, 32768, 1, 1, 1, 2.0, 1.0, 128.0)
+    assert lib.mcdi_bilateral_fwd(C.byref(big), 3, 8, 16, None, None) == -4
+
+
+# ----------------------------------------------------------------------------
+# GPU: parity through the C ABI
+# ----------------------------------------------------------------------------
+
+def _footprint_max(a, mask, V, H, W, R):
+    """max over the (2R+1)^2 footprint of |a| (valid pixels), per pixel."""
+    x = np.abs(np.asarray(a, np.float64)).reshape(-1, V, H, W) * (mask.reshape(1, V, H, W) > 0)
+    m = ndimage.maximum_filter(x.max(0), size=(1, 2 * R + 1, 2 * R + 1), mode="constant")
+    return m.reshape(-1)
+
+
+def _gpu_filter(depth, nrm, mask, V, H, W, x, sigma, g_out=None, sigma_z=1.0, sigma_n=128.0):
+    import torch
+    import paper_2206_03380_amd as M
+    t = lambda a, dt=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    guide = M.BilateralGuide(t(depth), t(nrm), t(mask, torch.uint8), V, H, W, sigma, sigma_z, sigma_n)
+    out, wsum = M.bilateral_fwd(guide, t(x))
+    gin = M.bilateral_bwd(guide, t(g_out), wsum) if g_out is not None else None
+    torch.cuda.synchronize()
+    f = lambda a: a.cpu().numpy().astype(np.float64) if a is not None else None  # noqa: E731
+    return f(out), f(wsum), f(gin)
+
+
+def _check_parity(depth, nrm, mask, V, H, W, x, g, sigma, sigma_z=1.0, sigma_n=128.0):
+    sigma = float(np.float32(sigma))
+    out, wsum, gin = _gpu_filter(depth, nrm, mask, V, H, W, x, sigma, g, sigma_z, sigma_n)
+    o_out, o_w = B.bilateral_fwd(x, depth, nrm, mask, V, H, W, sigma, sigma_z, sigma_n)
+    R = B.radius(sigma)
+    bound = TOL * _footprint_max(x, mask, V, H, W, R) + 1e-7
+    err = np.abs(out - o_out).max(0)
+    assert np.all(err <= bound), "fwd: worst %.3g of bound" % (err / bound).max()
+    assert np.all(np.abs(wsum - o_w) <= TOL * o_w + 1e-30)
+    o_g = B.bilateral_bwd(g, depth, nrm, mask, V, H, W, sigma, sigma_z, sigma_n)
+    scale = B.bilateral_bwd(np.abs(g), depth, nrm, mask, V, H, W, sigma, sigma_z, sigma_n)
+    gbound = TOL * scale + 1e-7 * np.abs(o_g).max()
+    gerr = np.abs(gin - o_g)
+    assert np.all(gerr <= gbound), "bwd: worst %.3g of bound" % (gerr / gbound).max()
+    return out, gin
+
+
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("nc", [1, 3, 6])
+@pytest.mark.parametrize("sigma", [1e-4, 0.5, 1.0, 2.0, 2.67])
+def test_bilateral_parity_tiny(nc, sigma):
+    _gpu()
+    w = make_workload("tiny")
+    x = noisy_lighting(w, seed=1, channels=nc)
+    g = noisy_lighting(w, seed=2, channels=nc) - 1.0
+    print("bilateral parity tiny nc=%d sigma=%g" % (nc, sigma), flush=True)
+    _check_parity(w.depth, w.nrm, w.mask, w.n_views, w.height, w.width, x, g, sigma)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("sigma", [0.7, 2.0])
+def test_bilateral_parity_sphere8_ragged(sigma):
+    _gpu()
+    w = make_workload("sphere8", H=60, W=52, n_views=2)
+    x = noisy_lighting(w, seed=3, channels=6)
+    g = noisy_lighting(w, seed=4, channels=6) - 1.0
+    print("bilateral parity sphere8 60x52x2 sigma=%g" % sigma, flush=True)
+    _check_parity(w.depth, w.nrm, w.mask, w.n_views, w.height, w.width, x, g, sigma)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 37), (1, 17, 1), (3, 33, 47), (1, 16, 16)])
+def test_bilateral_edge_shapes(shape):
+    _gpu()
+    V, H, W = shape
+    N = V * H * W
+    rng = np.random.default_rng(11)
+    depth = (2 + rng.random(N)).astype(np.float32)
+    nrm = np.vstack([rng.normal(0, 0.3, (2, N)), np.ones((1, N))]).astype(np.float32)
+    mask = (rng.random(N) < 0.8).astype(np.uint8)
+    x = rng.random((3, N)).astype(np.float32)
+    g = rng.normal(size=(3, N)).astype(np.float32)
+    print("bilateral edge shape", shape, flush=True)
+    _check_parity(depth, nrm, mask, V, H, W, x, g, 2.0)
+
+
+@pytest.mark.gpu
+def test_bilateral_degenerate_inputs():
+    _gpu()
+    import torch
+    import paper_2206_03380_amd as M
+    w = make_workload("tiny")
+    x = noisy_lighting(w, seed=5, channels=3)
+    # all pixels invalid: zeros out, zero weights
+    mask0 = np.zeros_like(w.mask)
+    out, wsum, gin = _gpu_filter(w.depth, w.nrm, mask0, 1, w.height, w.width, x, 2.0, x)
+    assert not out.any() and not wsum.any() and not gin.any()
+    # NaN in every value of the invalid pixels changes nothing
+    bad = w.mask == 0
+    d2, n2, x2 = w.depth.copy(), w.nrm.copy(), x.copy()
+    d2[bad], n2[:, bad], x2[:, bad] = np.nan, np.nan, np.nan
+    a = _gpu_filter(w.depth, w.nrm, w.mask, 1, w.height, w.width, x, 2.0, x)
+    b = _gpu_filter(d2, n2, w.mask, 1, w.height, w.width, x2, 2.0, x2)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    # empty image: nothing to do
+    e = torch.empty(0, device="cuda")
+    guide = M.BilateralGuide(e, e.reshape(3, 0), e.to(torch.uint8), 0, 8, 8, 2.0)
+    o, ws = M.bilateral_fwd(guide, e.reshape(3, 0))
+    assert o.numel() == 0
+    # deterministic: bitwise repeatable
+    c = _gpu_filter(w.depth, w.nrm, w.mask, 1, w.height, w.width, x, 2.0, x)
+    for u, v in zip(a, c):
+        assert np.array_equal(u, v)
+
+
+@pytest.mark.gpu
+def test_view_depth_parity():
+    _gpu()
+    import torch
+    import paper_2206_03380_amd as M
+    w = make_workload("sphere8", H=60, W=52, n_views=2)
+    gb = M.GBuffer.from_workload(w, "cuda")
+    z = M.view_depth(gb).cpu().numpy().astype(np.float64)
+    ref = B.view_depth(w.pos, w.eye, w.mask, w.n_views, w.height, w.width)
+    assert np.allclose(z, ref, rtol=4e-7, atol=0)
+    assert np.all(z[w.mask == 0] == 0)
+    del torch
+
+
+@pytest.mark.gpu
+def test_autograd_bilateral():
+    _gpu()
+    import torch
+    import paper_2206_03380_amd as M
+    w = make_workload("tiny")
+    gb = M.GBuffer.from_workload(w, "cuda")
+    guide = M.BilateralGuide.from_gbuffer(gb, sigma=1.5)
+    x = torch.from_numpy(noisy_lighting(w, seed=6, channels=6)).cuda().requires_grad_(True)
+    g = torch.from_numpy(noisy_lighting(w, seed=7, channels=6)).cuda()
+    y = M.Bilateral.apply(x, guide)
+    (y * g).sum().backward()
+    out, wsum = M.bilateral_fwd(guide, x.detach())
+    assert torch.equal(y, out)
+    assert torch.equal(x.grad, M.bilateral_bwd(guide, g, wsum))
+
+
+def _crop(a, v, y0, y1, x0, x1, V, H, W):
+    a = np.asarray(a)
+    lead = a.shape[:-1]
+    return np.ascontiguousarray(a.reshape(lead + (V, H, W))[..., v, y0:y1, x0:x1].reshape(lead + (-1,)))
+
+
+@pytest.mark.gpu
+def test_bilateral_full_size_sampled():
+    """8 views of 512 x 512 at sigma 2 (R = 6), six channels, the launch the
+    benchmark times: sampled windows against the oracle on crops with enough
+    margin that the crop edge changes nothing inside the window."""
+    _gpu()
+    w = make_workload("sphere8_grad")
+    V, H, W = w.n_views, w.height, w.width
+    x = noisy_lighting(w, seed=8, channels=6)
+    g = noisy_lighting(w, seed=9, channels=6) - 1.0
+    sigma = 2.0
+    R = B.radius(sigma)
+    print("bilateral full size %dx%dx%d" % (V, H, W), flush=True)
+    out, _, gin = _gpu_filter(w.depth, w.nrm, w.mask, V, H, W, x, sigma, g)
+    rng = np.random.default_rng(12)
+    wins = [(0, 0, 0), (V - 1, H - 24, W - 24), (3, 0, W // 2)]
+    wins += [(int(rng.integers(V)), int(rng.integers(H - 24)), int(rng.integers(W - 24))) for _ in range(5)]
+    m = 2 * R + 2
+    for v, y, xw in wins:
+        y0, y1, x0, x1 = max(0, y - m), min(H, y + 24 + m), max(0, xw - m), min(W, xw + 24 + m)
+        ch, cw = y1 - y0, x1 - x0
+        cr = lambda a: _crop(a, v, y0, y1, x0, x1, V, H, W)  # noqa: E731
+        cx, cg, cm = cr(x), cr(g), cr(w.mask)
+        o_out, _ = B.bilateral_fwd(cx, cr(w.depth), cr(w.nrm), cm, 1, ch, cw, sigma)
+        o_g = B.bilateral_bwd(cg, cr(w.depth), cr(w.nrm), cm, 1, ch, cw, sigma)
+        scale = B.bilateral_bwd(np.abs(cg), cr(w.depth), cr(w.nrm), cm, 1, ch, cw, sigma)
+        fmax = _footprint_max(cx, cm, 1, ch, cw, R)
+        inner = np.zeros((ch, cw), bool)
+        inner[y - y0:y - y0 + 24, xw - x0:xw - x0 + 24] = True
+        inner = inner.reshape(-1)
+        go, gg = cr(out)[:, inner], cr(gin)[:, inner]
+        assert np.all(np.abs(go - o_out[:, inner]).max(0) <= TOL * fmax[inner] + 1e-7), (v, y, xw)
+        assert np.all(np.abs(gg - o_g[:, inner]) <= TOL * scale[:, inner] + 1e-7 * np.abs(o_g).max()), (v, y, xw)

@@ -10,4 +10,4 @@ it).
 Every generator is deterministic given its numpy PCG64 seed.
 """
 
-from .configs import Workload, make_workload, from_arrays, upstream_grads, CONFIGS  # noqa: F401
+from .configs import Workload, make_workload, from_arrays, upstream_grads, noisy_lighting, CONFIGS  # noqa: F401

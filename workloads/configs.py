@@ -45,6 +45,7 @@ class Workload:
     ray_eps: float = 1e-3
     view_base: int = 0
     meta: dict = field(default_factory=dict)
+    depth: np.ndarray = None   # f32 [N] primary-ray hit distance (0 where mask is 0)
 
     @property
     def n_pixels(self):
@@ -109,11 +110,13 @@ def _assemble(name, verts, tris, env, eyes, H, W, hits_per_view, materials, spp,
     pos = np.zeros((N, 3))
     nrm = np.zeros((N, 3))
     mask = np.zeros(N, np.uint8)
+    depth = np.zeros(N)
     for v, (p, n, m) in enumerate(hits_per_view):
         sl = slice(v * H * W, (v + 1) * H * W)
         pos[sl] = p
         nrm[sl] = n
         mask[sl] = m
+        depth[sl] = np.where(m > 0, np.linalg.norm(p - np.asarray(eyes[v], np.float64), axis=-1), 0.0)
     kd, korm = materials(pos, mask)
     kd[mask == 0] = 0
     korm[mask == 0] = 0
@@ -122,7 +125,7 @@ def _assemble(name, verts, tris, env, eyes, H, W, hits_per_view, materials, spp,
         name=name, verts=verts32, tris=tris32, env=env, n_views=V, height=H, width=W,
         pos=_planar(pos, N), nrm=_planar(nrm, N), kd=_planar(kd, N), korm=_planar(korm, N),
         mask=mask, eye=np.ascontiguousarray(np.asarray(eyes), dtype=np.float32), spp=spp,
-        ray_eps=_scene_eps(verts32), meta=meta)
+        ray_eps=_scene_eps(verts32), meta=meta, depth=depth.astype(np.float32))
 
 
 def _cast(eye, target, fov, H, W, surfaces):
@@ -258,6 +261,20 @@ def upstream_grads(w, seed=7):
     gcs = (s / nv).astype(np.float32)
     gcd = (w.kd.astype(np.float64) * s / nv).astype(np.float32)
     return np.ascontiguousarray(gcd), np.ascontiguousarray(gcs)
+
+
+def noisy_lighting(w, seed=0, channels=6):
+    """Seeded stand-in for Monte Carlo lighting estimates, f32 [channels][N]:
+    a smooth positive field times heavy-tailed per-pixel noise (lognormal,
+    sigma 1), with occasional fireflies; 0 where mask is 0."""
+    rng = np.random.Generator(np.random.PCG64(5000 + seed))
+    N = w.n_pixels
+    pos = w.pos.astype(np.float64)
+    base = 0.5 + 0.4 * np.sin(3.0 * pos[0] + 1.0)[None] * np.cos(2.0 * pos[2])[None] + 0.2 * np.arange(channels)[:, None] / channels
+    noise = rng.lognormal(0.0, 1.0, size=(channels, N))
+    fire = rng.random((channels, N)) < 1e-3
+    x = base * noise * np.where(fire, 50.0, 1.0)
+    return np.ascontiguousarray(np.where(w.mask[None] > 0, x, 0.0), dtype=np.float32)
 
 
 def from_arrays(name, verts, tris, env, pos, nrm, kd, korm, mask=None, eye=None,

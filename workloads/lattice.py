@@ -186,6 +186,7 @@ def make_lattice(k=3, H=1024, W=1024, spp=32, n_views=4, cells=32, env_hw=(1024,
     pos = np.zeros((N, 3))
     nrm = np.zeros((N, 3))
     mask = np.zeros(N, np.uint8)
+    depth = np.zeros(N)
     for vi, eye in enumerate(eyes):
         d = look_at_rays(eye, [0, 0, 0], 60.0, H, W)
         o = np.broadcast_to(eye, d.shape).copy()
@@ -202,6 +203,7 @@ def make_lattice(k=3, H=1024, W=1024, spp=32, n_views=4, cells=32, env_hw=(1024,
         pos[sl] = np.where(m[:, None], p, 0)
         nrm[sl] = np.where(m[:, None], n_, 0)
         mask[sl] = m
+        depth[sl] = np.where(m, t, 0.0)
     a = spherical_lookup(tex_kd, pos)
     b = spherical_lookup(tex_orm, pos)
     kd = a[:, :3]
@@ -212,4 +214,5 @@ def make_lattice(k=3, H=1024, W=1024, spp=32, n_views=4, cells=32, env_hw=(1024,
     return Workload(name="lattice", verts=verts32, tris=tris32, env=env, n_views=V, height=H, width=W,
                     pos=_planar(pos, N), nrm=_planar(nrm, N), kd=_planar(kd, N), korm=_planar(korm, N),
                     mask=mask, eye=np.ascontiguousarray(np.asarray(eyes), dtype=np.float32), spp=spp,
-                    ray_eps=_scene_eps(verts32), meta={"tris": len(tris), "env": env.shape[:2]})
+                    ray_eps=_scene_eps(verts32), meta={"tris": len(tris), "env": env.shape[:2]},
+                    depth=depth.astype(np.float32))
