@@ -3,9 +3,13 @@
 
 One step = one optimisation iteration of the path on one batch: rebuild the
 shadow-ray BVH from the mesh, rebuild the probe sampling tables, forward
-shading (samples, MIS, shadow rays), the image loss and the backward pass
-through the autograd Function (adjoint kernel with the probe-texel scatter).
-Inputs are resident in HBM before timing starts.
+shading (samples, MIS, shadow rays), the fused image loss (tonemapped L1 +
+light regulariser, value and gradients in one kernel pass) and the backward
+pass through the autograd Function (adjoint kernel with the probe-texel
+scatter); with --denoise the cross-bilateral denoiser (sigma 2) sits between
+shading and loss.  Inputs are resident in HBM before timing starts.  The
+denoiser and the loss kernels are also timed on their own, each with its
+roofline, under "next_rows".
 
 Default workload: 8 views at 512x512 of a 101,060-triangle displaced sphere
 with 20 box occluders, a 512x256 probe, 12 samples per pixel, forward +
@@ -45,6 +49,7 @@ def parse():
                     help="serving benchmark on the three-scene mix (50k/300k/1M triangles)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true", help="skip the short serving run of the default line")
+    ap.add_argument("--denoise", action="store_true", help="cross-bilateral denoiser (sigma 2) inside the step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 512 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -107,8 +112,11 @@ def main():
         envh = M.Env(env_t.detach())                      # probe tables rebuild
         c_d, c_s = M.MCDIShade.apply(kd, korm, nrm, env_t, scene, envh, gb, w.spp, w.seed, w.tau, w.ray_eps,
                                      M.FLAG_TIME_TRACE)
-        img = kd * c_d + c_s
-        loss = ((img - target).abs() * mask).sum() / (3 * n_valid)
+        if args.denoise:
+            guide = M.BilateralGuide.from_gbuffer(gb, sigma=2.0)
+            y = M.Bilateral.apply(torch.cat([c_d, c_s]), guide)
+            c_d, c_s = y[:3], y[3:]
+        loss = M.ImageLoss.apply(kd, c_d, c_s, target, gb.mask, 0.15)
         loss.backward()
         return scene, envh
 
@@ -191,6 +199,7 @@ def main():
         "roofline": roofline,
     }
 
+    result["next_rows"] = next_rows(args, M, gb, out[0], out[1], target, timed)
     if not args.no_serve:
         result["serving"] = serve_quick(args, M, w, gb)
     if args.copy_calibration:
@@ -205,6 +214,58 @@ def main():
 OPS_PER_BOX = 25
 OPS_PER_TRI = 39
 OPS_PER_RAY = 25
+
+# Cross-bilateral denoiser, per footprint tap of a valid pixel with six
+# channels, in single-rate VALU issue slots: 15 FP32 ops (normal dot 3, clamp,
+# depth difference, scale, two exponent FMAs, weight sum, 6 colour FMAs), one
+# FP64->FP32 convert (2), two FP64 FMAs (half rate: 4) and three quarter-rate
+# transcendentals (log2, rcp, exp2: 12).  The adjoint has no weight sum.
+BILAT_OPS_FWD = 33
+BILAT_OPS_BWD = 32
+# Image loss: bytes per pixel that must cross HBM: kd, c_d, c_s, ref in
+# (48), mask twice (count pass and loss pass, 2), three gradients out (36).
+LOSS_BYTES_PER_PX = 86
+
+
+def next_rows(args, M, gb, c_d, c_s, target, timed):
+    """Denoiser and image-loss kernels on the step's own outputs, each timed
+    alone with HIP events on the launch stream."""
+    import torch
+    n = gb.n
+    valid = int(gb.mask.sum())
+    reps = max(args.kernel_reps, 5)
+    sigma = 2.0
+    guide = M.BilateralGuide.from_gbuffer(gb, sigma=sigma)
+    x = torch.cat([c_d, c_s]).contiguous()
+    fo = (torch.empty_like(x), torch.empty(n, dtype=torch.float32, device=x.device))
+    M.bilateral_fwd(guide, x, out=fo)
+    g = torch.randn_like(x) * gb.mask
+    gi = torch.empty_like(x)
+    f_ms = timed(lambda: M.bilateral_fwd(guide, x, out=fo), reps)
+    b_ms = timed(lambda: M.bilateral_bwd(guide, g, fo[1], out=gi), reps)
+    d_ms = timed(lambda: M.view_depth(gb), reps)
+    R = M.bilateral_radius(sigma)
+    taps = valid * (2 * R + 1) ** 2
+
+    def alu(ops, ms):
+        a = ops / (ms * 1e-3)
+        return {"bound": "alu", "achieved": a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
+                "frac": a / VALU_PEAK, "traffic": None}
+
+    lo = (torch.empty(3, dtype=torch.float32, device=x.device),) + tuple(torch.empty_like(c_d) for _ in range(3))
+    l_ms = timed(lambda: M.image_loss(gb.kd, c_d, c_s, target, gb.mask, out=lo), reps)
+    lbytes = LOSS_BYTES_PER_PX * n
+    return {
+        "bilateral": {"sigma": sigma, "radius": R, "channels": 6, "taps": taps,
+                      "fwd_ms": f_ms, "bwd_ms": b_ms, "view_depth_ms": d_ms,
+                      "fwd_roofline": alu(taps * BILAT_OPS_FWD, f_ms),
+                      "bwd_roofline": alu(taps * BILAT_OPS_BWD, b_ms)},
+        "image_loss": {"ms": l_ms, "bytes_per_launch": lbytes,
+                       "roofline": {"bound": "hbm", "achieved": lbytes / (l_ms * 1e-3) / 1e9,
+                                    "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                    "frac": lbytes / (l_ms * 1e-3) / HBM_PEAK, "traffic": None}},
+    }
+
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_rays_sphere8_grad_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_03380_amd", "csrc", f)

@@ -236,16 +236,22 @@ def trace_times():
     return [buf[i] for i in range(n.value)]
 
 
-def image_loss(kd, c_d, c_s, ref, mask, w_light=0.15, stream=None):
+def image_loss(kd, c_d, c_s, ref, mask, w_light=0.15, stream=None, out=None):
     """Loss of the composed image (kd*c_d + c_s) against ref: L1 on tonemapped
     colours + w_light * light regulariser.  Returns (loss [3] = (L_image,
-    L_light, L), g_kd, g_cd, g_cs), all on the device."""
+    L_light, L), g_kd, g_cd, g_cs), all on the device; `out` may pass the
+    four buffers in."""
     n = mask.shape[0]
     for name, t in (("kd", kd), ("c_d", c_d), ("c_s", c_s), ("ref", ref)):
         _need(t, torch.float32, (3, n), name)
     _need(mask, torch.uint8, (n,), "mask")
-    loss = torch.empty(3, dtype=torch.float32, device=kd.device)
-    g_kd, g_cd, g_cs = (torch.empty((3, n), dtype=torch.float32, device=kd.device) for _ in range(3))
+    if out is None:
+        out = (torch.empty(3, dtype=torch.float32, device=kd.device),) + tuple(
+            torch.empty((3, n), dtype=torch.float32, device=kd.device) for _ in range(3))
+    loss, g_kd, g_cd, g_cs = out
+    _need(loss, torch.float32, (3,), "loss")
+    for name, t in (("g_kd", g_kd), ("g_cd", g_cd), ("g_cs", g_cs)):
+        _need(t, torch.float32, (3, n), name)
     L.check(L.lib().mcdi_image_loss(_ptr(kd), _ptr(c_d), _ptr(c_s), _ptr(ref), _ptr(mask), n, float(w_light),
                                     _ptr(loss), _ptr(g_kd), _ptr(g_cd), _ptr(g_cs), C.byref(_TORCH_ALLOCATOR),
                                     _stream(stream)))
@@ -304,22 +310,26 @@ def view_depth(gb, stream=None):
     return depth
 
 
-def bilateral_fwd(guide, x, stream=None):
-    """Filter x [C, N] (C in 1, 3, 6).  Returns (out [C, N], wsum [N])."""
+def bilateral_fwd(guide, x, stream=None, out=None):
+    """Filter x [C, N] (C in 1, 3, 6).  Returns (out [C, N], wsum [N]);
+    `out` may pass both buffers in."""
     gs = guide.struct()
     _need(x, torch.float32, (x.shape[0], guide.n), "x")
-    out = torch.empty_like(x)
-    wsum = torch.empty(guide.n, dtype=torch.float32, device=x.device)
+    if out is None:
+        out = (torch.empty_like(x), torch.empty(guide.n, dtype=torch.float32, device=x.device))
+    out, wsum = out
+    _need(out, torch.float32, tuple(x.shape), "out")
+    _need(wsum, torch.float32, (guide.n,), "wsum")
     L.check(L.lib().mcdi_bilateral_fwd(C.byref(gs), x.shape[0], _ptr(x), _ptr(out), _ptr(wsum), _stream(stream)))
     return out, wsum
 
 
-def bilateral_bwd(guide, g_out, wsum, stream=None):
+def bilateral_bwd(guide, g_out, wsum, stream=None, out=None):
     """Gradient with respect to the filtered colours for upstream g_out [C, N]."""
     gs = guide.struct()
     _need(g_out, torch.float32, (g_out.shape[0], guide.n), "g_out")
     _need(wsum, torch.float32, (guide.n,), "wsum")
-    g_in = torch.empty_like(g_out)
+    g_in = torch.empty_like(g_out) if out is None else _need(out, torch.float32, tuple(g_out.shape), "out")
     L.check(L.lib().mcdi_bilateral_bwd(C.byref(gs), g_out.shape[0], _ptr(g_out), _ptr(wsum), _ptr(g_in),
                                        _stream(stream)))
     return g_in
@@ -336,4 +346,4 @@ def trace_anyhit(scene, orig, dirs, brute=False, stream=None):
     return hit
 
 
-from .autograd import MCDIShade, Bilateral  # noqa: E402,F401
+from .autograd import MCDIShade, Bilateral, ImageLoss  # noqa: E402,F401

@@ -80,3 +80,23 @@ class Bilateral(torch.autograd.Function):
         from . import bilateral_bwd
         (wsum,) = ctx.saved_tensors
         return bilateral_bwd(ctx.guide, g_out.contiguous().float(), wsum), None
+
+
+class ImageLoss(torch.autograd.Function):
+    """L = ImageLoss.apply(kd, c_d, c_s, ref, mask, w_light): tonemapped L1 of
+    the composed image kd*c_d + c_s against ref plus w_light times the light
+    regulariser (appendix A).  One kernel pass computes the loss and its
+    gradients; backward only scales them by the upstream gradient."""
+
+    @staticmethod
+    def forward(ctx, kd, c_d, c_s, ref, mask, w_light=0.15):
+        from . import image_loss
+        loss, g_kd, g_cd, g_cs = image_loss(kd.contiguous(), c_d.contiguous(), c_s.contiguous(),
+                                            ref.contiguous(), mask, w_light)
+        ctx.save_for_backward(g_kd, g_cd, g_cs)
+        return loss[2]
+
+    @staticmethod
+    def backward(ctx, g):
+        g_kd, g_cd, g_cs = ctx.saved_tensors
+        return g_kd * g, g_cd * g, g_cs * g, None, None, None

@@ -1,6 +1,7 @@
 // Host runtime of the C ABI declared in include/mcdi.h: argument validation,
 // handle ownership, stream-ordered allocation and kernel launches.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include <cmath>
 #include <cstdarg>
@@ -389,7 +390,28 @@ mcdi_status mcdi_shade_bwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, co
         if (st != MCDI_OK) return st;
         a.hitbits_in = bits;
     }
-    hipError_t e = launch_shade_bwd(a, s);
+    // probe gradient: per-tile records binned after the adjoint (see
+    // env_scatter.hip); positions in the sorted records are 32-bit
+    Workspace wr;
+    EnvScatter es{};
+    const int64_t tiles = (a.g.n + kBlock - 1) / kBlock;
+    const int64_t region = 2 * (int64_t)a.spp * kBlock;
+    if (g_env && tiles * region <= ((int64_t)1 << 30)) {
+        env_scatter_plan(ev->H, ev->W, tiles, (uint32_t)region, es);
+        wr.alloc = &sc->alloc;
+        wr.s = s;
+        wr.base = sc->alloc.get(env_scatter_bytes(es), s);
+        if (wr.base) {   // without the workspace the adjoint scatters directly
+            env_scatter_carve(wr.base, es);
+            es.g_env = g_env;
+            a.rec = es.rec;
+            a.rec_count = es.tile_count;
+            a.rec_region = es.region;
+        }
+    }
+    hipError_t e = a.rec ? launch_env_scatter_init(es, s) : hipSuccess;
+    if (e == hipSuccess) e = launch_shade_bwd(a, s);
+    if (e == hipSuccess && a.rec) e = launch_env_scatter(es, s);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd: %s", hipGetErrorString(e));
     return ok();
 }
@@ -548,8 +570,7 @@ mcdi_status mcdi_image_loss(const float* kd, const float* c_d, const float* c_s,
     if (alloc && (!alloc->alloc || !alloc->free)) return fail(MCDI_E_INVALID, "mcdi_image_loss: allocator incomplete");
     hipStream_t s = (hipStream_t)stream;
     Alloc al = make_alloc(alloc);
-    const int64_t nb = (n + 255) / 256;
-    double* scratch = (double*)al.get(sizeof(double) * (size_t)(3 * nb + 1), s);
+    void* scratch = al.get(image_loss_scratch_bytes(n), s);
     if (!scratch) return fail(MCDI_E_OOM, "mcdi_image_loss: scratch allocation failed");
     hipError_t e = launch_image_loss(kd, c_d, c_s, ref, mask, n, w_light, loss, g_kd, g_cd, g_cs, scratch, s);
     al.put(scratch, s);

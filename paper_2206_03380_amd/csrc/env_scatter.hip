@@ -1,0 +1,284 @@
+// Probe-gradient scatter of the adjoint (section 3.1: the probe texels are
+// optimisation variables; each light or BSDF sample adds its coefficient times
+// the upstream gradient to the texel its direction falls in).
+//
+// Global float atomics on this chip retire about one 128-byte line per clock
+// per XCD whatever their scope, so an atomic per sample and channel to random
+// texels is bound by line requests, not bandwidth.  Texels outside the
+// per-workgroup LDS hot set therefore go through records instead: the adjoint
+// appends one 16-byte record (texel, three values) per sample to its tile's
+// region (LDS fill counter, one atomic per wave), and this pass sums them:
+//   1. histogram: records per bucket of 4096 consecutive texels, per
+//      workgroup in LDS, kept per workgroup and added to the bucket totals;
+//   2. scan: bucket starts and fill cursors;
+//   3. scatter: counting sort by bucket; each batch of records is sorted in
+//      LDS first so the global writes come out as contiguous runs;
+//   4. accumulate: fixed chunks of the sorted records, each bucket segment
+//      summed in an LDS copy of its texels (LDS float atomics), then one
+//      global add per touched texel channel, consecutive lanes on
+//      consecutive channels (16 per cache line).
+// Each record crosses HBM five times (written, read by the histogram and the
+// scatter, written sorted, read by the accumulation).
+#include <hip/hip_runtime.h>
+
+#include "mcdi_internal.h"
+
+namespace mcdi {
+namespace {
+
+constexpr int kShift = 12;             // 4096 texels per bucket: 48 KB of LDS
+constexpr int kMaxBuckets = 4096;      // 4096 x 4096 texels at most
+constexpr int kGridMax = 2048;
+constexpr int kBatch = 1024;           // records per LDS sort batch
+constexpr uint32_t kChunkMin = 4096;   // sorted records per accumulate workgroup
+
+__device__ __forceinline__ uint32_t rec_texel(const float4& r) { return __float_as_uint(r.x); }
+
+int tile_grid(int64_t n_tiles) { return (int)(n_tiles < kGridMax ? n_tiles : kGridMax); }
+
+__global__ __launch_bounds__(1024) void init_kernel(EnvScatter p) {
+    for (int b = threadIdx.x; b < p.K; b += blockDim.x) p.cursor[b] = 0u;
+}
+
+// Records per bucket over the tiles blockIdx.x, + gridDim.x, ...: kept per
+// workgroup (for the scatter) and added to the bucket totals.
+__global__ __launch_bounds__(256) void hist_kernel(EnvScatter p) {
+    __shared__ uint32_t h[kMaxBuckets];
+    for (int b = threadIdx.x; b < p.K; b += 256) h[b] = 0u;
+    __syncthreads();
+    for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
+        const float4* r = p.rec + (size_t)t * p.region;
+        const uint32_t c = p.tile_count[t];
+        for (uint32_t i = threadIdx.x; i < c; i += 1024) {
+            uint32_t tx[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tx[j] = i + 256 * j < c ? rec_texel(r[i + 256 * j]) : 0xFFFFFFFFu;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (tx[j] != 0xFFFFFFFFu) atomicAdd(&h[tx[j] >> kShift], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t* mine = p.wg_hist + (size_t)blockIdx.x * p.K;
+    for (int b = threadIdx.x; b < p.K; b += 256) {
+        mine[b] = h[b];
+        if (h[b]) atomicAdd(&p.cursor[b], h[b]);
+    }
+}
+
+// exclusive scan of the bucket sizes: one block of 1024 threads, four
+// consecutive buckets per thread
+__global__ __launch_bounds__(1024) void scan_kernel(EnvScatter p) {
+    __shared__ uint32_t s[1024];
+    const int t = threadIdx.x;
+    uint32_t v[4], sum = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int b = 4 * t + j;
+        v[j] = b < p.K ? p.cursor[b] : 0u;
+        sum += v[j];
+    }
+    s[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t a = t >= o ? s[t - o] : 0u;
+        __syncthreads();
+        s[t] += a;
+        __syncthreads();
+    }
+    uint32_t run = s[t] - sum;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int b = 4 * t + j;
+        if (b < p.K) {
+            p.start[b] = run;
+            p.cursor[b] = run;
+        }
+        run += v[j];
+    }
+    if (t == 1023) p.start[p.K] = s[t];
+}
+
+// exclusive scan of a[0..K) in place by 256 threads (ends with a barrier)
+__device__ void block_scan_k(uint32_t* a, int K, uint32_t* s256) {
+    const int per = (K + 255) / 256;
+    const int b0 = threadIdx.x * per;
+    uint32_t sum = 0u;
+    for (int j = 0; j < per; ++j)
+        if (b0 + j < K) sum += a[b0 + j];
+    s256[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)o ? s256[threadIdx.x - o] : 0u;
+        __syncthreads();
+        s256[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = s256[threadIdx.x] - sum;
+    for (int j = 0; j < per; ++j)
+        if (b0 + j < K) {
+            const uint32_t v = a[b0 + j];
+            a[b0 + j] = run;
+            run += v;
+        }
+    __syncthreads();
+}
+
+// Counting-sort scatter over the same tiles as the histogram workgroup.
+// LDS: lh, lofs, dst [K] each, then the batch [kBatch] of sorted records.
+__global__ __launch_bounds__(256) void scatter_kernel(EnvScatter p) {
+    extern __shared__ uint32_t sm[];
+    __shared__ uint32_t s256[256];
+    const int K = p.K;
+    uint32_t* lh = sm;
+    uint32_t* lofs = sm + K;
+    uint32_t* dst = sm + 2 * K;   // next global position of each bucket
+    float4* srt = (float4*)(sm + ((3 * K + 3) & ~3));
+    const uint32_t* mine = p.wg_hist + (size_t)blockIdx.x * K;
+    for (int b = threadIdx.x; b < K; b += 256) dst[b] = mine[b] ? atomicAdd(&p.cursor[b], mine[b]) : 0u;
+    __syncthreads();
+    for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
+        const float4* rr = p.rec + (size_t)t * p.region;
+        const uint32_t c = p.tile_count[t];
+        for (uint32_t b0 = 0; b0 < c; b0 += kBatch) {
+            const int n = (int)min((uint32_t)kBatch, c - b0);
+            float4 r[kBatch / 256];
+            uint32_t rank[kBatch / 256];
+            for (int b = threadIdx.x; b < K; b += 256) lh[b] = 0u;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kBatch / 256; ++j) {
+                const int i = threadIdx.x + 256 * j;
+                if (i < n) r[j] = rr[b0 + i];
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch / 256; ++j) {
+                const int i = threadIdx.x + 256 * j;
+                if (i < n) rank[j] = atomicAdd(&lh[rec_texel(r[j]) >> kShift], 1u);
+            }
+            __syncthreads();
+            for (int b = threadIdx.x; b < K; b += 256) lofs[b] = lh[b];
+            __syncthreads();
+            block_scan_k(lofs, K, s256);
+#pragma unroll
+            for (int j = 0; j < kBatch / 256; ++j) {
+                const int i = threadIdx.x + 256 * j;
+                if (i < n) srt[lofs[rec_texel(r[j]) >> kShift] + rank[j]] = r[j];
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += 256) {
+                const float4 v = srt[i];
+                const uint32_t b = rec_texel(v) >> kShift;
+                p.sorted[dst[b] + ((uint32_t)i - lofs[b])] = v;
+            }
+            __syncthreads();
+            for (int b = threadIdx.x; b < K; b += 256) dst[b] += lh[b];
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void accumulate_kernel(EnvScatter p, uint32_t chunk) {
+    __shared__ float acc[3 << kShift];
+    const uint32_t R = p.start[p.K];
+    const uint64_t lo64 = (uint64_t)blockIdx.x * chunk;
+    if (lo64 >= R) return;
+    const uint32_t lo = (uint32_t)lo64;
+    const uint32_t hi = (uint32_t)(lo64 + chunk < R ? lo64 + chunk : R);
+    const int b0 = (int)(rec_texel(p.sorted[lo]) >> kShift);
+    const int b1 = (int)(rec_texel(p.sorted[hi - 1]) >> kShift);
+    for (int b = b0; b <= b1; ++b) {
+        const uint32_t s = max(lo, p.start[b]), e = min(hi, p.start[b + 1]);
+        if (s >= e) continue;
+        const int first = b << kShift;
+        const int n_tex = min(1 << kShift, p.n_texels - first);
+        for (int k = threadIdx.x; k < 3 * n_tex; k += 256) acc[k] = 0.0f;
+        __syncthreads();
+        for (uint32_t i = s + threadIdx.x; i < e; i += 1024) {
+            float4 r[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r[j] = i + 256 * j < e ? p.sorted[i + 256 * j] : make_float4(0, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (i + 256 * j < e) {
+                    const int k = 3 * (int)(rec_texel(r[j]) - (uint32_t)first);
+                    atomicAdd(&acc[k + 0], r[j].y);
+                    atomicAdd(&acc[k + 1], r[j].z);
+                    atomicAdd(&acc[k + 2], r[j].w);
+                }
+            }
+        }
+        __syncthreads();
+        float* g = p.g_env + 3 * (size_t)first;
+        for (int k = threadIdx.x; k < 3 * n_tex; k += 256) {
+            const float v = acc[k];
+            if (v != 0.0f) atomicAdd(g + k, v);
+        }
+        __syncthreads();
+    }
+}
+
+uint32_t chunk_of(uint32_t cap) {
+    const uint32_t c = (cap + 4 * kGridMax - 1) / (4 * kGridMax);
+    return c > kChunkMin ? c : kChunkMin;
+}
+
+}  // namespace
+
+void env_scatter_plan(int H, int W, int64_t n_tiles, uint32_t region, EnvScatter& p) {
+    const int n_tex = H * W;
+    p.shift = kShift;
+    p.K = (n_tex + (1 << kShift) - 1) >> kShift;
+    p.n_texels = n_tex;
+    p.n_tiles = n_tiles;
+    p.region = region;
+    p.cap = (uint32_t)(n_tiles * (int64_t)region);
+    p.n_wg = tile_grid(n_tiles);
+}
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t env_scatter_bytes(const EnvScatter& p) {
+    return 2 * al256(sizeof(float4) * (size_t)p.cap) + al256(sizeof(uint32_t) * (size_t)p.n_tiles) +
+           al256(sizeof(uint32_t) * (size_t)p.K) + al256(sizeof(uint32_t) * (size_t)(p.K + 1)) +
+           al256(sizeof(uint32_t) * (size_t)p.K * (size_t)p.n_wg);
+}
+
+void env_scatter_carve(void* base, EnvScatter& p) {
+    char* c = (char*)base;
+    p.rec = (float4*)c;
+    c += al256(sizeof(float4) * (size_t)p.cap);
+    p.sorted = (float4*)c;
+    c += al256(sizeof(float4) * (size_t)p.cap);
+    p.tile_count = (uint32_t*)c;
+    c += al256(sizeof(uint32_t) * (size_t)p.n_tiles);
+    p.cursor = (uint32_t*)c;
+    c += al256(sizeof(uint32_t) * (size_t)p.K);
+    p.start = (uint32_t*)c;
+    c += al256(sizeof(uint32_t) * (size_t)(p.K + 1));
+    p.wg_hist = (uint32_t*)c;
+}
+
+hipError_t launch_env_scatter_init(const EnvScatter& p, hipStream_t s) {
+    hipLaunchKernelGGL(init_kernel, dim3(1), dim3(1024), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_env_scatter(const EnvScatter& p, hipStream_t s) {
+    if (p.cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(hist_kernel, dim3(p.n_wg), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, p);
+    const size_t lds_sc = sizeof(uint32_t) * (size_t)((3 * p.K + 3) & ~3) + sizeof(float4) * kBatch;
+    if (lds_sc > 65536) {   // above the default dynamic LDS limit (large probes only)
+        const hipError_t e = hipFuncSetAttribute((const void*)scatter_kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_sc);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(scatter_kernel, dim3(p.n_wg), dim3(256), lds_sc, s, p);
+    const uint32_t chunk = chunk_of(p.cap);
+    const unsigned grid = (unsigned)((p.cap + chunk - 1) / chunk);
+    hipLaunchKernelGGL(accumulate_kernel, dim3(grid), dim3(256), 0, s, p, chunk);
+    return hipGetLastError();
+}
+
+}  // namespace mcdi

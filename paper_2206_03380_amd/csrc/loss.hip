@@ -2,9 +2,19 @@
 // (paper appendix A: L1 on tonemapped colours, T(x) = sRGB(log(x + 1)), and
 // the light regulariser comparing the luminance of the tonemapped lighting
 // with the HSV value of the tonemapped reference; composition c = kd*c_d + c_s
-// from section 4.2).  HBM-bound: 48 B/px + 1 B mask in, 36 B/px out.
-// Loss partial sums go per workgroup to FP64 scratch and are reduced in a
-// fixed order, so the loss value is deterministic.
+// from section 4.2).  HBM-bound: 48 B/px + 1 B mask in, 36 B/px out, plus a
+// 1 B/px counting pass for the number of valid pixels the means divide by.
+//
+// Two launches.  The counting pass writes per-block integer counts and clears
+// the completion ticket of the loss pass.  The loss pass is a grid-stride
+// stream over pixels; each block first sums the integer counts (exact, so
+// every block gets the same n), writes its FP64 partial loss sums, and the
+// last block to take a ticket reduces all partials in a fixed order -- the
+// loss value does not depend on timing.
+//
+// The transfer curve uses the hardware log2/exp2: log(1+x) with Goldberg's
+// correction x*log(u)/(u-1), u = 1+x (a few ulp), y^(1/2.4) as
+// exp2(log2(y)/2.4), and the derivative reuses that power.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -14,116 +24,183 @@ namespace mcdi {
 namespace {
 
 constexpr float kA = 0.055f, kLin = 0.0031308f;
+constexpr float kLn2 = 0.69314718f;
+constexpr int kCountPx = 4096;  // pixels per block of the counting pass
+constexpr int kLossBlocks = 2048;
 
-__device__ __forceinline__ float srgb(float y) {
-    return y <= kLin ? 12.92f * y : (1.0f + kA) * powf(y, 1.0f / 2.4f) - kA;
+__device__ __forceinline__ float log1p_fast(float x) {
+    const float u = 1.0f + x;
+    const float l = __builtin_amdgcn_logf(u) * kLn2;
+    return (u == 1.0f) ? x : l * (x / (u - 1.0f));
 }
-__device__ __forceinline__ float srgb_d(float y) {
-    return y <= kLin ? 12.92f : ((1.0f + kA) / 2.4f) * powf(y, 1.0f / 2.4f - 1.0f);
+
+// T(x) and T'(x) for x = radiance (clamped at 0; no gradient below 0)
+__device__ __forceinline__ void tonemap(float x, float& t, float& dt) {
+    const float xp = fmaxf(x, 0.0f);
+    const float y = log1p_fast(xp);
+    if (y <= kLin) {
+        t = 12.92f * y;
+        dt = 12.92f;
+    } else {
+        const float p = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(y) * (1.0f / 2.4f));
+        t = (1.0f + kA) * p - kA;
+        dt = ((1.0f + kA) / 2.4f) * p / y;
+    }
+    dt = x > 0.0f ? dt / (1.0f + xp) : 0.0f;
 }
-__device__ __forceinline__ float tm(float x) { return srgb(log1pf(fmaxf(x, 0.0f))); }
-__device__ __forceinline__ float tm_d(float x) { return x > 0.0f ? srgb_d(log1pf(x)) / (1.0f + x) : 0.0f; }
+
+__device__ __forceinline__ float tonemap_value(float x) {
+    float t, dt;
+    tonemap(x, t, dt);
+    return t;
+}
+
 __device__ __forceinline__ float sgn(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
 
-__global__ __launch_bounds__(256) void count_kernel(const uint8_t* mask, int64_t n, double* part) {
-    __shared__ double s[256];
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    s[threadIdx.x] = (k < n && mask[k]) ? 1.0 : 0.0;
+__global__ __launch_bounds__(256) void count_kernel(const uint8_t* __restrict__ mask, int64_t n,
+                                                    long long* __restrict__ part, unsigned* __restrict__ ticket) {
+    __shared__ int s[256];
+    const int64_t base = (int64_t)blockIdx.x * kCountPx;
+    int c = 0;
+    for (int i = threadIdx.x; i < kCountPx; i += 256) {
+        const int64_t k = base + i;
+        c += (k < n && mask[k]) ? 1 : 0;
+    }
+    s[threadIdx.x] = c;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s[0];
+        if (blockIdx.x == 0) *ticket = 0u;
+    }
 }
 
-// sequential sum of partials (fixed order); out[0] = sum
-__global__ void sum_kernel(const double* part, int64_t nb, double* out) {
-    double a = 0.0;
-    for (int64_t i = 0; i < nb; ++i) a += part[i];
-    *out = a;
+// Fixed-order block sum: lane t adds p[t*stride], p[(t+256)*stride], ... in
+// order, then a fixed LDS tree.  Every thread returns the total.
+template <typename T>
+__device__ T fixed_sum(const T* p, int64_t nb, int stride, T* s) {
+    T a = 0;
+    for (int64_t i = threadIdx.x; i < nb; i += 256) a += p[i * stride];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    const T r = s[0];
+    __syncthreads();
+    return r;
 }
 
-__global__ __launch_bounds__(256) void loss_kernel(const float* kd, const float* cd, const float* cs,
-                                                   const float* ref, const uint8_t* mask, int64_t n, float w_light,
-                                                   const double* n_valid, double* part, float* g_kd, float* g_cd,
-                                                   float* g_cs) {
-    __shared__ double s_img[256], s_lit[256];
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double nv = fmax(*n_valid, 1.0);
+__global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ kd, const float* __restrict__ cd,
+                                                   const float* __restrict__ cs, const float* __restrict__ ref,
+                                                   const uint8_t* __restrict__ mask, int64_t n, float w_light,
+                                                   const long long* __restrict__ cnt, int64_t n_cnt,
+                                                   double* __restrict__ part, unsigned* __restrict__ ticket,
+                                                   float* __restrict__ loss, float* __restrict__ g_kd,
+                                                   float* __restrict__ g_cd, float* __restrict__ g_cs) {
+    __shared__ double s_d[256];
+    __shared__ long long s_i[256];
+    __shared__ unsigned s_last;
+    const long long nvi = fixed_sum(cnt, n_cnt, 1, s_i);
+    const double nv = nvi > 0 ? (double)nvi : 1.0;
     const float inv3n = (float)(1.0 / (3.0 * nv)), invn = (float)(1.0 / nv);
     double li = 0.0, ll = 0.0;
-    if (k < n) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += stride) {
         const bool m = mask[k] != 0;
-        float kdc[3], cdc[3], csc[3], gc[3], lsum_d[3];
-        float ysum = 0.0f, vmax = -INFINITY;
+        float kdc[3], cdc[3], gc[3], dls[3];
+        float ysum = 0.0f, vmax = -INFINITY, img = 0.0f;
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
             kdc[c] = kd[c * n + k];
             cdc[c] = cd[c * n + k];
-            csc[c] = cs[c * n + k];
-            const float r = ref[c * n + k];
-            const float col = kdc[c] * cdc[c] + csc[c];
-            const float d = tm(col) - tm(r);
-            li += m ? (double)fabsf(d) : 0.0;
-            gc[c] = m ? sgn(d) * tm_d(col) * inv3n : 0.0f;
-            const float ls = cdc[c] + csc[c];
-            ysum += tm(ls);
-            lsum_d[c] = tm_d(ls);
-            vmax = fmaxf(vmax, tm(r));
+            const float csc = cs[c * n + k];
+            const float tr = tonemap_value(ref[c * n + k]);
+            float tc, dtc;
+            tonemap(kdc[c] * cdc[c] + csc, tc, dtc);
+            const float d = tc - tr;
+            img += fabsf(d);
+            gc[c] = m ? sgn(d) * dtc * inv3n : 0.0f;
+            float tl;
+            tonemap(cdc[c] + csc, tl, dls[c]);
+            ysum += tl;
+            vmax = fmaxf(vmax, tr);
         }
         const float dl = ysum * (1.0f / 3.0f) - vmax;
-        ll = m ? (double)fabsf(dl) : 0.0;
+        if (m) {
+            li += (double)img;
+            ll += (double)fabsf(dl);
+        }
         const float gl = m ? sgn(dl) * invn * w_light * (1.0f / 3.0f) : 0.0f;
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (g_kd) g_kd[c * n + k] = gc[c] * cdc[c];
-            if (g_cd) g_cd[c * n + k] = gc[c] * kdc[c] + gl * lsum_d[c];
-            if (g_cs) g_cs[c * n + k] = gc[c] + gl * lsum_d[c];
+            if (g_cd) g_cd[c * n + k] = gc[c] * kdc[c] + gl * dls[c];
+            if (g_cs) g_cs[c * n + k] = gc[c] + gl * dls[c];
         }
     }
-    s_img[threadIdx.x] = li;
-    s_lit[threadIdx.x] = ll;
+    // block partials (fixed tree), then the last block reduces them all
+    s_d[threadIdx.x] = li;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            s_img[threadIdx.x] += s_img[threadIdx.x + o];
-            s_lit[threadIdx.x] += s_lit[threadIdx.x + o];
-        }
+        if (threadIdx.x < o) s_d[threadIdx.x] += s_d[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double bi = s_d[0];
+    __syncthreads();
+    s_d[threadIdx.x] = ll;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s_d[threadIdx.x] += s_d[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = s_img[0];
-        part[2 * blockIdx.x + 1] = s_lit[0];
+        part[2 * blockIdx.x] = bi;
+        part[2 * blockIdx.x + 1] = s_d[0];
+        __threadfence();
+        s_last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (s_last != gridDim.x - 1) return;
+    __threadfence();
+    const double a = fixed_sum(part, gridDim.x, 2, s_d);
+    const double b = fixed_sum(part + 1, gridDim.x, 2, s_d);
+    if (threadIdx.x == 0) {
+        const double lim = a / (3.0 * nv), llm = b / nv;
+        loss[0] = (float)lim;
+        loss[1] = (float)llm;
+        loss[2] = (float)(lim + (double)w_light * llm);
     }
 }
 
-__global__ void finish_kernel(const double* part, int64_t nb, const double* n_valid, float w_light, float* loss) {
-    double a = 0.0, b = 0.0;
-    for (int64_t i = 0; i < nb; ++i) {
-        a += part[2 * i];
-        b += part[2 * i + 1];
-    }
-    const double nv = fmax(*n_valid, 1.0);
-    const double li = a / (3.0 * nv), ll = b / nv;
-    loss[0] = (float)li;
-    loss[1] = (float)ll;
-    loss[2] = (float)(li + (double)w_light * ll);
+int loss_blocks(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return (int)(b < kLossBlocks ? b : kLossBlocks);
 }
+
+int64_t count_blocks(int64_t n) { return (n + kCountPx - 1) / kCountPx; }
 
 }  // namespace
 
-// scratch: doubles, at least 3 * blocks + 1
+size_t image_loss_scratch_bytes(int64_t n) {
+    return sizeof(long long) * (size_t)count_blocks(n) + sizeof(double) * 2 * (size_t)loss_blocks(n) + 256;
+}
+
 hipError_t launch_image_loss(const float* kd, const float* cd, const float* cs, const float* ref,
                              const uint8_t* mask, int64_t n, float w_light, float* loss, float* g_kd, float* g_cd,
-                             float* g_cs, double* scratch, hipStream_t s) {
-    const int64_t nb = (n + 255) / 256;
-    double* cnt_part = scratch;            // [nb]
-    double* part = scratch + nb;           // [2 nb]
-    double* n_valid = scratch + 3 * nb;    // [1]
-    hipLaunchKernelGGL(count_kernel, dim3((unsigned)nb), dim3(256), 0, s, mask, n, cnt_part);
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1), 0, s, cnt_part, nb, n_valid);
-    hipLaunchKernelGGL(loss_kernel, dim3((unsigned)nb), dim3(256), 0, s, kd, cd, cs, ref, mask, n, w_light, n_valid,
-                       part, g_kd, g_cd, g_cs);
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1), 0, s, part, nb, n_valid, w_light, loss);
+                             float* g_cs, void* scratch, hipStream_t s) {
+    const int64_t nc = count_blocks(n);
+    const int nl = loss_blocks(n);
+    double* part = (double*)scratch;                         // [2 nl]
+    long long* cnt = (long long*)(part + 2 * nl);            // [nc]
+    unsigned* ticket = (unsigned*)(cnt + nc);                // [1]
+    hipLaunchKernelGGL(count_kernel, dim3((unsigned)nc), dim3(256), 0, s, mask, n, cnt, ticket);
+    hipLaunchKernelGGL(loss_kernel, dim3((unsigned)nl), dim3(256), 0, s, kd, cd, cs, ref, mask, n, w_light, cnt, nc,
+                       part, ticket, loss, g_kd, g_cd, g_cs);
     return hipGetLastError();
 }
 

@@ -83,6 +83,12 @@ struct ShadeArgs {
     float4* rays;          // (direction, local pixel | slot << 8)
     int32_t* ray_count;    // [blocks]
     float4* origins;       // [N]
+    // adjoint: probe-gradient records (texel bits, 3 values) of non-hot
+    // texels, one region of rec_region records per tile and a record count
+    // per tile, binned and summed by the env-scatter pass; NULL: direct atomics
+    float4* rec;
+    uint32_t* rec_count;
+    uint32_t rec_region;
 };
 
 // one serving work item: a contiguous range of tiles of one request
@@ -109,9 +115,34 @@ hipError_t launch_shade_bwd(const ShadeArgs& a, hipStream_t s);
 hipError_t launch_trace(const Scene& sc, const float* o, const float* d, int64_t n, uint8_t* hit,
                         int brute, hipStream_t s);
 
+// Probe-gradient scatter of the adjoint over the records the adjoint kernel
+// leaves in per-tile regions: bucket histogram, counting-sort scatter by
+// bucket, and per-bucket LDS accumulation flushed into g_env.
+struct EnvScatter {
+    float4* rec;          // [n_tiles][region] records as appended
+    uint32_t* tile_count; // [n_tiles] records in each region
+    uint32_t region;
+    int64_t n_tiles;
+    float4* sorted;       // [cap] records ordered by bucket
+    uint32_t* cursor;     // [K] bucket sizes, then fill cursors
+    uint32_t* start;      // [K + 1] bucket starts
+    uint32_t* wg_hist;    // [n_wg][K] records per bucket of each histogram workgroup
+    uint32_t cap;         // n_tiles * region
+    int32_t K, shift;     // K buckets of 2^shift texels
+    int32_t n_texels;
+    int32_t n_wg;         // workgroups of the histogram and scatter steps
+    float* g_env;
+};
+void env_scatter_plan(int H, int W, int64_t n_tiles, uint32_t region, EnvScatter& p);
+size_t env_scatter_bytes(const EnvScatter& p);     // after env_scatter_plan
+void env_scatter_carve(void* base, EnvScatter& p); // lay the buffers out in base
+hipError_t launch_env_scatter_init(const EnvScatter& p, hipStream_t s);
+hipError_t launch_env_scatter(const EnvScatter& p, hipStream_t s);
+
+size_t image_loss_scratch_bytes(int64_t n);
 hipError_t launch_image_loss(const float* kd, const float* cd, const float* cs, const float* ref,
                              const uint8_t* mask, int64_t n, float w_light, float* loss, float* g_kd, float* g_cd,
-                             float* g_cs, double* scratch, hipStream_t s);
+                             float* g_cs, void* scratch, hipStream_t s);
 
 // BVH build: temp buffers are obtained through the callbacks
 // Cross-bilateral filter over V views of H x W pixels (N = V*H*W).

@@ -213,10 +213,17 @@ __device__ __forceinline__ void bsdf_texel(const ShadeArgs& A, bool light_on, Sa
     if (light_on && rho > 0.0f) S.pL = A.env.pdf[S.texel] / (2.0f * kPi * kPi * rho);
 }
 
+// where the adjoint puts probe-gradient records of non-hot texels: the tile's
+// record region and its LDS fill counter (base NULL: direct global atomics)
+struct RecSink {
+    float4* base;
+    uint32_t* count;
+};
+
 template <bool BWD>
 __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, const Sample& S, float Hv,
                                             float invspp, FwdAcc& fa, BwdAcc& ba, float3 Ud, float3 Us,
-                                            float* s_hot) {
+                                            float* s_hot, const RecSink& rs) {
     const float NoL = S.wl.z;
     const float3 hl = normalize(P.Vl + S.wl);
     const float NoH = hl.z;
@@ -261,10 +268,25 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
             atomicAdd(s_hot + 3 * slot + 1, v1);
             atomicAdd(s_hot + 3 * slot + 2, v2);
         } else {
-            float* ge = A.g_env + 3 * (size_t)S.texel;
-            atomicAdd(ge + 0, v0);
-            atomicAdd(ge + 1, v1);
-            atomicAdd(ge + 2, v2);
+            if (v0 == 0.0f && v1 == 0.0f && v2 == 0.0f) {
+                // nothing to add (a shadowed sample with tau = 1)
+            } else if (rs.base) {
+                // append to the tile's record region: one LDS counter atomic
+                // per wave; the region holds every sample the tile can make
+                const uint64_t act = __ballot(1);
+                const int lane = (int)__lane_id();
+                const int leader = __ffsll((unsigned long long)act) - 1;
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(rs.count, (uint32_t)__popcll(act));
+                base = (uint32_t)__shfl((int)base, leader);
+                const uint32_t slot = base + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+                rs.base[slot] = make_float4(__uint_as_float((uint32_t)S.texel), v0, v1, v2);
+            } else {
+                float* ge = A.g_env + 3 * (size_t)S.texel;
+                atomicAdd(ge + 0, v0);
+                atomicAdd(ge + 1, v1);
+                atomicAdd(ge + 2, v2);
+            }
         }
     }
     const float udL = Ud.x * L.x + Ud.y * L.y + Ud.z * L.z;
@@ -496,7 +518,8 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
 // 3) evaluation: forward values or the adjoint, from the hit bits.  For the
 //    adjoint, s_hot must be zeroed before and flushed after (hot_flush).
 template <bool BWD, bool DUMP>
-__device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, const float* s_marg, float* s_hot) {
+__device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, const float* s_marg, float* s_hot,
+                                           const RecSink& rs) {
     const int64_t N = A.g.n;
     const int64_t pix = tile * kBlock + threadIdx.x;
     const int spp = A.spp;
@@ -562,7 +585,7 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
                     rec2 |= tech ? kDecBHit : kDecLHit;
                 }
             }
-            eval_sample<BWD>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot);
+            eval_sample<BWD>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
         }
         if (DUMP) {
             uint32_t* d = A.decisions + ((size_t)pix * spp + s) * 3;
@@ -622,17 +645,21 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_
 }
 
 template <bool BWD, bool DUMP>
-__global__ __launch_bounds__(kBlock) void shade_kernel(ShadeArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void shade_kernel(ShadeArgs A) {
     extern __shared__ float smem[];
+    __shared__ uint32_t s_rec;
     float* s_marg = smem;
     float* s_hot = smem + ((A.env.H + 1 + 3) & ~3);
     stage_marg(A, s_marg);
     if (BWD) hot_zero(s_hot);
+    if (threadIdx.x == 0) s_rec = 0u;
     __syncthreads();
-    shade_tile<BWD, DUMP>(A, blockIdx.x, s_marg, s_hot);
+    const RecSink rs{(BWD && A.rec) ? A.rec + (size_t)blockIdx.x * A.rec_region : nullptr, &s_rec};
+    shade_tile<BWD, DUMP>(A, blockIdx.x, s_marg, s_hot, rs);
     if (BWD) {
         __syncthreads();
         hot_flush(A, s_hot);
+        if (A.rec && threadIdx.x == 0) A.rec_count[blockIdx.x] = s_rec;
     }
 }
 
@@ -675,11 +702,11 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(const ServeItem* items, i
         __syncthreads();
         if (reg) trace_tile<false>(A, tile, reg, s_cnt, it.hitbits, &s_next);
         __syncthreads();
-        shade_tile<false, false>(A, tile, s_marg, s_hot);
+        shade_tile<false, false>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
         if (A.g_cd) {
             hot_zero(s_hot);
             __syncthreads();
-            shade_tile<true, false>(A, tile, s_marg, s_hot);
+            shade_tile<true, false>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
             __syncthreads();
             hot_flush(A, s_hot);
         }
