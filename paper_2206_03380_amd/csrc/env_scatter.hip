@@ -8,15 +8,23 @@
 // per-workgroup LDS hot set therefore go through records instead: the adjoint
 // appends one 16-byte record (texel, three values) per sample to its tile's
 // region (LDS fill counter, one atomic per wave), and this pass sums them:
-//   1. histogram: records per bucket of 4096 consecutive texels, per
+//   1. histogram: records per bucket of 1024 (large probes: up to 4096)
+//      consecutive texels, per
 //      workgroup in LDS, kept per workgroup and added to the bucket totals;
 //   2. scan: bucket starts and fill cursors;
 //   3. scatter: counting sort by bucket; each batch of records is sorted in
 //      LDS first so the global writes come out as contiguous runs;
 //   4. accumulate: fixed chunks of the sorted records, each bucket segment
-//      summed in an LDS copy of its texels (LDS float atomics), then one
-//      global add per touched texel channel, consecutive lanes on
-//      consecutive channels (16 per cache line).
+//      summed exactly in 64-bit fixed point in an LDS copy of its texels
+//      (integer LDS atomics run about six times faster than float ones
+//      here), then one float global add per touched texel channel,
+//      consecutive lanes on consecutive channels (16 per cache line).
+// Fixed point: a chunk adds at most 2^c records of magnitude below 2^e (e from
+// the bucket's largest |value|, found by the histogram step), so with scale
+// 2^(62-c-e) the int64 sum cannot overflow, and each record is rounded by at
+// most 2^-(63-c-e), i.e. < 2^-(63-c) of the bucket maximum (c <= 15 here).  A
+// bucket with a non-finite value takes the float-atomic path instead, so NaN
+// and infinity propagate as with direct atomics.
 // Each record crosses HBM five times (written, read by the histogram and the
 // scatter, written sorted, read by the accumulation).
 #include <hip/hip_runtime.h>
@@ -26,43 +34,68 @@
 namespace mcdi {
 namespace {
 
-constexpr int kShift = 12;             // 4096 texels per bucket: 48 KB of LDS
+constexpr int kMinShift = 10;          // at least 1024 texels per bucket
+constexpr int kMaxShift = 12;          // 4096 texels: 96 KB of LDS per fixed-point bucket copy
 constexpr int kMaxBuckets = 4096;      // 4096 x 4096 texels at most
 constexpr int kGridMax = 2048;
 constexpr int kBatch = 1024;           // records per LDS sort batch
-constexpr uint32_t kChunkMin = 4096;   // sorted records per accumulate workgroup
+constexpr uint32_t kChunkMin = 16384;  // sorted records per accumulate workgroup
 
 __device__ __forceinline__ uint32_t rec_texel(const float4& r) { return __float_as_uint(r.x); }
 
 int tile_grid(int64_t n_tiles) { return (int)(n_tiles < kGridMax ? n_tiles : kGridMax); }
 
 __global__ __launch_bounds__(1024) void init_kernel(EnvScatter p) {
-    for (int b = threadIdx.x; b < p.K; b += blockDim.x) p.cursor[b] = 0u;
+    for (int b = threadIdx.x; b < p.K; b += blockDim.x) {
+        p.cursor[b] = 0u;
+        p.bmax[b] = 0u;
+    }
 }
 
-// Records per bucket over the tiles blockIdx.x, + gridDim.x, ...: kept per
-// workgroup (for the scatter) and added to the bucket totals.
+// bits of max(|x|, |y|, |z|): for non-negative floats the bit patterns order
+// like the values, and NaN sorts above infinity
+__device__ __forceinline__ uint32_t abs_max_bits(const float4& r) {
+    const uint32_t a = __float_as_uint(r.y) & 0x7FFFFFFFu, b = __float_as_uint(r.z) & 0x7FFFFFFFu,
+                   c = __float_as_uint(r.w) & 0x7FFFFFFFu;
+    return max(a, max(b, c));
+}
+
+// Records per bucket and the largest |value| per bucket over the tiles
+// blockIdx.x, + gridDim.x, ...: counts kept per workgroup (for the scatter)
+// and added to the bucket totals.
 __global__ __launch_bounds__(256) void hist_kernel(EnvScatter p) {
     __shared__ uint32_t h[kMaxBuckets];
-    for (int b = threadIdx.x; b < p.K; b += 256) h[b] = 0u;
+    __shared__ uint32_t hm[kMaxBuckets];
+    for (int b = threadIdx.x; b < p.K; b += 256) {
+        h[b] = 0u;
+        hm[b] = 0u;
+    }
     __syncthreads();
     for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
         const float4* r = p.rec + (size_t)t * p.region;
         const uint32_t c = p.tile_count[t];
         for (uint32_t i = threadIdx.x; i < c; i += 1024) {
-            uint32_t tx[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) tx[j] = i + 256 * j < c ? rec_texel(r[i + 256 * j]) : 0xFFFFFFFFu;
+            float4 v[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (tx[j] != 0xFFFFFFFFu) atomicAdd(&h[tx[j] >> kShift], 1u);
+                if (i + 256 * j < c) v[j] = r[i + 256 * j];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (i + 256 * j < c) {
+                    const uint32_t b = rec_texel(v[j]) >> p.shift;
+                    atomicAdd(&h[b], 1u);
+                    atomicMax(&hm[b], abs_max_bits(v[j]));
+                }
         }
     }
     __syncthreads();
     uint32_t* mine = p.wg_hist + (size_t)blockIdx.x * p.K;
     for (int b = threadIdx.x; b < p.K; b += 256) {
         mine[b] = h[b];
-        if (h[b]) atomicAdd(&p.cursor[b], h[b]);
+        if (h[b]) {
+            atomicAdd(&p.cursor[b], h[b]);
+            atomicMax(&p.bmax[b], hm[b]);
+        }
     }
 }
 
@@ -154,7 +187,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(EnvScatter p) {
 #pragma unroll
             for (int j = 0; j < kBatch / 256; ++j) {
                 const int i = threadIdx.x + 256 * j;
-                if (i < n) rank[j] = atomicAdd(&lh[rec_texel(r[j]) >> kShift], 1u);
+                if (i < n) rank[j] = atomicAdd(&lh[rec_texel(r[j]) >> p.shift], 1u);
             }
             __syncthreads();
             for (int b = threadIdx.x; b < K; b += 256) lofs[b] = lh[b];
@@ -163,12 +196,12 @@ __global__ __launch_bounds__(256) void scatter_kernel(EnvScatter p) {
 #pragma unroll
             for (int j = 0; j < kBatch / 256; ++j) {
                 const int i = threadIdx.x + 256 * j;
-                if (i < n) srt[lofs[rec_texel(r[j]) >> kShift] + rank[j]] = r[j];
+                if (i < n) srt[lofs[rec_texel(r[j]) >> p.shift] + rank[j]] = r[j];
             }
             __syncthreads();
             for (int i = threadIdx.x; i < n; i += 256) {
                 const float4 v = srt[i];
-                const uint32_t b = rec_texel(v) >> kShift;
+                const uint32_t b = rec_texel(v) >> p.shift;
                 p.sorted[dst[b] + ((uint32_t)i - lofs[b])] = v;
             }
             __syncthreads();
@@ -178,21 +211,31 @@ __global__ __launch_bounds__(256) void scatter_kernel(EnvScatter p) {
     }
 }
 
-__global__ __launch_bounds__(256) void accumulate_kernel(EnvScatter p, uint32_t chunk) {
-    __shared__ float acc[3 << kShift];
+__global__ __launch_bounds__(256) void accumulate_kernel(EnvScatter p, uint32_t chunk, int chunk_log2) {
+    extern __shared__ long long acc[];   // [3 << shift] fixed point (or float in the same space)
     const uint32_t R = p.start[p.K];
     const uint64_t lo64 = (uint64_t)blockIdx.x * chunk;
     if (lo64 >= R) return;
     const uint32_t lo = (uint32_t)lo64;
     const uint32_t hi = (uint32_t)(lo64 + chunk < R ? lo64 + chunk : R);
-    const int b0 = (int)(rec_texel(p.sorted[lo]) >> kShift);
-    const int b1 = (int)(rec_texel(p.sorted[hi - 1]) >> kShift);
+    const int b0 = (int)(rec_texel(p.sorted[lo]) >> p.shift);
+    const int b1 = (int)(rec_texel(p.sorted[hi - 1]) >> p.shift);
+    float* accf = (float*)acc;
     for (int b = b0; b <= b1; ++b) {
         const uint32_t s = max(lo, p.start[b]), e = min(hi, p.start[b + 1]);
         if (s >= e) continue;
-        const int first = b << kShift;
-        const int n_tex = min(1 << kShift, p.n_texels - first);
-        for (int k = threadIdx.x; k < 3 * n_tex; k += 256) acc[k] = 0.0f;
+        const int first = b << p.shift;
+        const int n_tex = min(1 << p.shift, p.n_texels - first);
+        const uint32_t mb = p.bmax[b];
+        const bool fixed = mb < 0x7F800000u;   // finite
+        int ex = 0;
+        frexpf(__uint_as_float(mb), &ex);      // every |value| in the bucket < 2^ex
+        const int S = 62 - chunk_log2 - ex;
+        const double scale = ldexp(1.0, S), unscale = ldexp(1.0, -S);
+        for (int k = threadIdx.x; k < 3 * n_tex; k += 256) {
+            if (fixed) acc[k] = 0;
+            else accf[k] = 0.0f;
+        }
         __syncthreads();
         for (uint32_t i = s + threadIdx.x; i < e; i += 1024) {
             float4 r[4];
@@ -202,24 +245,33 @@ __global__ __launch_bounds__(256) void accumulate_kernel(EnvScatter p, uint32_t 
             for (int j = 0; j < 4; ++j) {
                 if (i + 256 * j < e) {
                     const int k = 3 * (int)(rec_texel(r[j]) - (uint32_t)first);
-                    atomicAdd(&acc[k + 0], r[j].y);
-                    atomicAdd(&acc[k + 1], r[j].z);
-                    atomicAdd(&acc[k + 2], r[j].w);
+                    if (fixed) {
+                        unsigned long long* a = (unsigned long long*)acc;
+                        atomicAdd(&a[k + 0], (unsigned long long)__double2ll_rn((double)r[j].y * scale));
+                        atomicAdd(&a[k + 1], (unsigned long long)__double2ll_rn((double)r[j].z * scale));
+                        atomicAdd(&a[k + 2], (unsigned long long)__double2ll_rn((double)r[j].w * scale));
+                    } else {
+                        atomicAdd(&accf[k + 0], r[j].y);
+                        atomicAdd(&accf[k + 1], r[j].z);
+                        atomicAdd(&accf[k + 2], r[j].w);
+                    }
                 }
             }
         }
         __syncthreads();
         float* g = p.g_env + 3 * (size_t)first;
         for (int k = threadIdx.x; k < 3 * n_tex; k += 256) {
-            const float v = acc[k];
+            const float v = fixed ? (float)((double)acc[k] * unscale) : accf[k];
             if (v != 0.0f) atomicAdd(g + k, v);
         }
         __syncthreads();
     }
 }
 
+// sorted records per accumulate workgroup: large against the bucket's texels,
+// so the per-chunk flush stays a small part of the work
 uint32_t chunk_of(uint32_t cap) {
-    const uint32_t c = (cap + 4 * kGridMax - 1) / (4 * kGridMax);
+    const uint32_t c = (cap + kGridMax - 1) / kGridMax;
     return c > kChunkMin ? c : kChunkMin;
 }
 
@@ -227,8 +279,10 @@ uint32_t chunk_of(uint32_t cap) {
 
 void env_scatter_plan(int H, int W, int64_t n_tiles, uint32_t region, EnvScatter& p) {
     const int n_tex = H * W;
-    p.shift = kShift;
-    p.K = (n_tex + (1 << kShift) - 1) >> kShift;
+    int shift = kMinShift;
+    while (((int64_t)kMaxBuckets << shift) < n_tex) ++shift;   // <= kMaxShift for 4096 x 4096
+    p.shift = shift;
+    p.K = (n_tex + (1 << shift) - 1) >> shift;
     p.n_texels = n_tex;
     p.n_tiles = n_tiles;
     p.region = region;
@@ -240,7 +294,7 @@ static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t env_scatter_bytes(const EnvScatter& p) {
     return 2 * al256(sizeof(float4) * (size_t)p.cap) + al256(sizeof(uint32_t) * (size_t)p.n_tiles) +
-           al256(sizeof(uint32_t) * (size_t)p.K) + al256(sizeof(uint32_t) * (size_t)(p.K + 1)) +
+           2 * al256(sizeof(uint32_t) * (size_t)p.K) + al256(sizeof(uint32_t) * (size_t)(p.K + 1)) +
            al256(sizeof(uint32_t) * (size_t)p.K * (size_t)p.n_wg);
 }
 
@@ -256,6 +310,8 @@ void env_scatter_carve(void* base, EnvScatter& p) {
     c += al256(sizeof(uint32_t) * (size_t)p.K);
     p.start = (uint32_t*)c;
     c += al256(sizeof(uint32_t) * (size_t)(p.K + 1));
+    p.bmax = (uint32_t*)c;
+    c += al256(sizeof(uint32_t) * (size_t)p.K);
     p.wg_hist = (uint32_t*)c;
 }
 
@@ -277,7 +333,15 @@ hipError_t launch_env_scatter(const EnvScatter& p, hipStream_t s) {
     hipLaunchKernelGGL(scatter_kernel, dim3(p.n_wg), dim3(256), lds_sc, s, p);
     const uint32_t chunk = chunk_of(p.cap);
     const unsigned grid = (unsigned)((p.cap + chunk - 1) / chunk);
-    hipLaunchKernelGGL(accumulate_kernel, dim3(grid), dim3(256), 0, s, p, chunk);
+    int clog = 0;
+    while ((1u << clog) < chunk) ++clog;
+    const size_t lds_acc = sizeof(long long) * (3u << p.shift);
+    if (lds_acc > 65536) {   // above the default dynamic LDS limit (large probes only)
+        const hipError_t e = hipFuncSetAttribute((const void*)accumulate_kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_acc);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(accumulate_kernel, dim3(grid), dim3(256), lds_acc, s, p, chunk, clog);
     return hipGetLastError();
 }
 

@@ -126,6 +126,7 @@ struct EnvScatter {
     float4* sorted;       // [cap] records ordered by bucket
     uint32_t* cursor;     // [K] bucket sizes, then fill cursors
     uint32_t* start;      // [K + 1] bucket starts
+    uint32_t* bmax;       // [K] bits of the largest |value| in each bucket
     uint32_t* wg_hist;    // [n_wg][K] records per bucket of each histogram workgroup
     uint32_t cap;         // n_tiles * region
     int32_t K, shift;     // K buckets of 2^shift texels
