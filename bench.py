@@ -181,7 +181,9 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
                 "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
                 "kernel": "trace_rays_kernel", "ops_per_launch": ops, "kernel_ms": trace_ms,
-                "units": {"rays": rays, "box_tests": stats["box_tests"], "tri_tests": stats["tri_tests"]}}
+                "units": {"rays": rays, "box_tests": stats["box_tests"], "tri_tests": stats["tri_tests"]},
+                "lane_utilisation": {"box": stats["box_tests"] / max(stats["box_slots"], 1),
+                                     "tri": stats["tri_tests"] / max(stats["tri_slots"], 1)}}
 
     result = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,

@@ -160,7 +160,8 @@ typedef struct {
     unsigned long long samples_culled;   /* below the horizon */
     unsigned long long box_tests;        /* BVH node boxes tested */
     unsigned long long tri_tests;        /* ray/triangle tests */
-    unsigned long long reserved;
+    unsigned long long box_slots;        /* lane slots of the box phase: 64 per wavefront step */
+    unsigned long long tri_slots;        /* lane slots of the triangle phase */
 } mcdi_stats;
 
 /* Forward pass.

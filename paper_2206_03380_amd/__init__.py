@@ -166,13 +166,13 @@ def hit_words(spp):
 
 
 def new_stats(device="cuda"):
-    return torch.zeros(8, dtype=torch.int64, device=device)
+    return torch.zeros(9, dtype=torch.int64, device=device)
 
 
 def read_stats(t):
     v = t.cpu().tolist()
     return {"valid_pixels": v[0], "invalid_pixels": v[1], "rays_traced": v[2], "rays_hit": v[3],
-            "samples_culled": v[4], "box_tests": v[5], "tri_tests": v[6]}
+            "samples_culled": v[4], "box_tests": v[5], "tri_tests": v[6], "box_slots": v[7], "tri_slots": v[8]}
 
 
 def _params(spp, seed, tau, ray_eps, flags, decisions):

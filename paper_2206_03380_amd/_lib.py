@@ -51,7 +51,7 @@ class ServeItem(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("valid_pixels", C.c_uint64), ("invalid_pixels", C.c_uint64), ("rays_traced", C.c_uint64),
                 ("rays_hit", C.c_uint64), ("samples_culled", C.c_uint64), ("box_tests", C.c_uint64),
-                ("tri_tests", C.c_uint64), ("reserved", C.c_uint64)]
+                ("tri_tests", C.c_uint64), ("box_slots", C.c_uint64), ("tri_slots", C.c_uint64)]
 
 
 class BilateralGuide(C.Structure):

@@ -85,10 +85,24 @@ __device__ __forceinline__ float smith_lambda(float t2, float a2) {
 struct Ray {
     float3 o;
     float3 inv;      // 1/d (zero components replaced, boxes only)
+    float3 clo, chi; // slab offsets for the low and high box corners (box_hit)
     float3 mx, my;   // shear rows
     float sz;        // 1/d[kz]
     int kz;
 };
+
+// Slab offsets: t = corner * inv + c with c = -(o * inv) -/+ e on the near/far
+// side of each axis.  o*inv is rounded once, so e = 2^-21 |o*inv| (eight times
+// that rounding plus the rounding of c itself) keeps every near distance an
+// under- and every far distance an over-estimate before the final rounding of
+// the FMA.
+__device__ __forceinline__ void slab_offsets(float o, float inv, float& clo, float& chi) {
+    const float oi = o * inv;
+    const float e = fabsf(oi) * 0x1p-21f;
+    const float cn = -oi - e, cf = -oi + e;
+    clo = inv >= 0.0f ? cn : cf;
+    chi = inv >= 0.0f ? cf : cn;
+}
 
 __device__ __forceinline__ float comp(float3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
 
@@ -119,6 +133,9 @@ __device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
     const float tiny = 1e-30f;
     r.inv = f3(fast_rcp(d.x != 0.0f ? d.x : tiny), fast_rcp(d.y != 0.0f ? d.y : tiny),
                fast_rcp(d.z != 0.0f ? d.z : tiny));
+    slab_offsets(o.x, r.inv.x, r.clo.x, r.chi.x);
+    slab_offsets(o.y, r.inv.y, r.clo.y, r.chi.y);
+    slab_offsets(o.z, r.inv.z, r.clo.z, r.chi.z);
     return r;
 }
 
@@ -151,9 +168,9 @@ __device__ __forceinline__ bool tri_anyhit(const Ray& r, float4 v0, float4 v1, f
 // n = 4 covers the subtraction, the product and the 1-ulp reciprocal, and the
 // factor is rounded up.
 __device__ __forceinline__ bool box_hit(const Ray& r, float4 a, float4 b) {
-    const float tx0 = (a.x - r.o.x) * r.inv.x, tx1 = (b.x - r.o.x) * r.inv.x;
-    const float ty0 = (a.y - r.o.y) * r.inv.y, ty1 = (b.y - r.o.y) * r.inv.y;
-    const float tz0 = (a.z - r.o.z) * r.inv.z, tz1 = (b.z - r.o.z) * r.inv.z;
+    const float tx0 = fmaf(a.x, r.inv.x, r.clo.x), tx1 = fmaf(b.x, r.inv.x, r.chi.x);
+    const float ty0 = fmaf(a.y, r.inv.y, r.clo.y), ty1 = fmaf(b.y, r.inv.y, r.chi.y);
+    const float tz0 = fmaf(a.z, r.inv.z, r.clo.z), tz1 = fmaf(b.z, r.inv.z, r.chi.z);
     const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
     const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
     return tn <= tf * 1.000001f;

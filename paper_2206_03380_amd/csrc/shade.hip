@@ -424,15 +424,20 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
     bool active = false, exhausted = false;
     Ray ray;
     int node = 0;
-    int tri = 0, tri_end = 0;   // pending leaf: triangles [tri, tri_end)
+    // up to two postponed leaves: triangles [t0, e0), then [t1, e1); the
+    // second slot is only used while the first is pending
+    int t0 = 0, e0 = 0, t1 = 0, e1 = 0;
     int64_t pix = 0;
     int slot = 0;
-    uint32_t c_hits = 0, c_box = 0, c_tri = 0;
+    uint32_t c_hits = 0, c_box = 0, c_tri = 0, c_bstep = 0, c_tstep = 0;   // steps: lane 0 only
+    // scheduling knobs: refill batch, node steps per phase check, and the
+    // phase hand-over ratios (in halves)
+    constexpr int kRefillMin = 32, kBoxSteps = 2, kBoxSwitch2 = 2, kTriSwitch2 = 2;
     while (true) {
-        // refill when a quarter of the wave is idle, or when nobody is busy
+        // refill when half of the wave is idle, or when nobody is busy
         const uint64_t need = __ballot(!active && !exhausted);
         const uint64_t busy = __ballot(active);
-        if (need && (__popcll(need) >= 16 || busy == 0ull)) {
+        if (need && (__popcll(need) >= kRefillMin || busy == 0ull)) {
             const int leader = __ffsll((unsigned long long)need) - 1;
             int b = 0;
             if (lane == leader) b = atomicAdd(s_next, (int)__popcll(need));
@@ -447,7 +452,7 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
                     const float4 o = A.origins[pix];
                     ray = make_ray(f3(o.x, o.y, o.z), f3(rr.x, rr.y, rr.z));
                     node = 0;
-                    tri = tri_end = 0;
+                    t0 = e0 = t1 = e1 = 0;
                     active = n_total > 0;
                 } else {
                     exhausted = true;
@@ -458,52 +463,69 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
             if (!__any(!exhausted)) break;
             continue;
         }
-        // box phase: lanes without a pending leaf walk the tree until they
-        // reach a leaf whose box the ray enters; it ends once as many lanes
-        // wait on a leaf as are still walking
+        // box phase: a lane walks while its second leaf slot is free and the
+        // tree is not finished (a leaf found with the first slot taken goes
+        // to the second); the phase ends once the lanes that hold a leaf and
+        // cannot walk are at least as many as the lanes still walking
         while (true) {
-            const bool walk = active && tri >= tri_end && node < n_total;
-            const uint64_t bw = __ballot(walk);
-            const uint64_t bl = __ballot(active && tri < tri_end);
-            if (bw == 0ull || __popcll(bl) >= __popcll(bw)) break;
-            if (walk) {
-                const float4 a = nodes[2 * node];
-                const float4 b = nodes[2 * node + 1];
-                const int escape = __float_as_int(a.w);
-                const int payload = __float_as_int(b.w);
-                const int next = escape > node ? escape : n_total;
-                if (COUNT) ++c_box;
-                if (!box_hit(ray, a, b)) {
-                    node = next;
-                } else if (payload == 0) {
-                    ++node;
-                } else {
-                    const int first = payload >> 3;
-                    const int cnt = (first + (payload & 7) <= sc.n_tris) ? (payload & 7) : 0;
-                    tri = first;
-                    tri_end = first + cnt;
-                    node = next;
+            if (!__any(active && node < n_total && t1 >= e1)) break;
+#pragma unroll
+            for (int step = 0; step < kBoxSteps; ++step) {
+                const bool walking = active && node < n_total && t1 >= e1;
+                if (COUNT && __any(walking) && lane == 0) ++c_bstep;
+                if (walking) {
+                    const float4 a = nodes[2 * node];
+                    const float4 b = nodes[2 * node + 1];
+                    const int escape = __float_as_int(a.w);
+                    const int payload = __float_as_int(b.w);
+                    const int next = escape > node ? escape : n_total;
+                    if (COUNT) ++c_box;
+                    const bool hit = box_hit(ray, a, b);
+                    const bool leaf = payload != 0;
+                    node = (hit && !leaf) ? node + 1 : next;
+                    if (hit && leaf) {
+                        const int first = payload >> 3;
+                        const int end = first + ((first + (payload & 7) <= sc.n_tris) ? (payload & 7) : 0);
+                        if (t0 < e0) {
+                            t1 = first;
+                            e1 = end;
+                        } else {
+                            t0 = first;
+                            e0 = end;
+                        }
+                    }
                 }
             }
+            const bool walk = active && node < n_total && t1 >= e1;
+            const bool stuck = active && t0 < e0 && !walk;
+            if (2 * __popcll(__ballot(stuck)) >= kBoxSwitch2 * __popcll(__ballot(walk))) break;
         }
-        // triangle phase: every pending leaf, one triangle per iteration
+        // triangle phase: one triangle of the first pending leaf per lane and
+        // step; it ends when no leaf is pending, or when lanes that could walk
+        // but hold no leaf outnumber the lanes testing
         while (true) {
-            const bool test = active && tri < tri_end;
+            const bool test = active && t0 < e0;
             if (!__any(test)) break;
+            if (COUNT && lane == 0) ++c_tstep;
             if (test) {
-                const float4* t = sc.tris + 3 * tri;
+                const float4* t = sc.tris + 3 * t0;
                 if (COUNT) ++c_tri;
                 if (tri_anyhit(ray, t[0], t[1], t[2])) {
                     atomicOr(hitbits + (int64_t)(slot >> 5) * N + pix, 1u << (slot & 31));
                     ++c_hits;
                     active = false;
-                    tri = tri_end = 0;
-                } else {
-                    ++tri;
+                    t0 = e0 = t1 = e1 = 0;
+                } else if (++t0 >= e0) {
+                    t0 = t1;
+                    e0 = e1;
+                    t1 = e1 = 0;
                 }
             }
+            const bool testing = active && t0 < e0;
+            const bool idle = active && !testing && node < n_total;
+            if (2 * __popcll(__ballot(idle)) > kTriSwitch2 * __popcll(__ballot(testing))) break;
         }
-        if (active && tri >= tri_end && node >= n_total) active = false;  // miss
+        if (active && t0 >= e0 && node >= n_total) active = false;  // miss
     }
     if (COUNT) {
         const uint32_t h = wave_sum(c_hits), bx = wave_sum(c_box), tr = wave_sum(c_tri);
@@ -511,6 +533,8 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
             atomicAdd(&A.stats->rays_hit, (unsigned long long)h);
             atomicAdd(&A.stats->box_tests, (unsigned long long)bx);
             atomicAdd(&A.stats->tri_tests, (unsigned long long)tr);
+            atomicAdd(&A.stats->box_slots, 64ull * c_bstep);
+            atomicAdd(&A.stats->tri_slots, 64ull * c_tstep);
         }
     }
 }
