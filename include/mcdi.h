@@ -136,8 +136,17 @@ typedef struct {
 } mcdi_gbuffer;
 
 /* Flags */
+/* Technique subsets (the sampling ablation of appendix D: cosine, BSDF and
+ * light-probe sampling alone against MIS; every subset is unbiased):
+ *   LIGHT_OFF              BSDF sampling only (cosine/GGX mixture)
+ *   BSDF_OFF               light-probe sampling only
+ *   LIGHT_OFF | FORCE_COS  cosine sampling only
+ *   LIGHT_OFF | FORCE_GGX  GGX visible-normal sampling only (cosine where n.v <= 0)
+ * LIGHT_OFF with BSDF_OFF, and FORCE_COS with FORCE_GGX, are rejected. */
 #define MCDI_FLAG_LIGHT_OFF   (1u << 0) /* no light-technique sample; p_light = 0 */
 #define MCDI_FLAG_FORCE_COS   (1u << 1) /* lobe probability q = 1 (cosine only) */
+#define MCDI_FLAG_BSDF_OFF    (1u << 2) /* no BSDF-technique sample; BSDF density not in the MIS sum */
+#define MCDI_FLAG_FORCE_GGX   (1u << 3) /* lobe probability q = 0 where n.v > 0 (GGX only) */
 #define MCDI_FLAG_DUMP        (1u << 8) /* write per-sample decision records */
 #define MCDI_FLAG_TIME_TRACE  (1u << 9) /* bracket the traversal kernel with HIP events */
 
@@ -274,7 +283,7 @@ typedef struct {
     mcdi_scene scene;
     mcdi_env env;
     mcdi_gbuffer gbuf;
-    mcdi_params params;     /* flags: MCDI_FLAG_LIGHT_OFF / FORCE_COS only */
+    mcdi_params params;     /* flags: the technique flags only */
     float* c_d;
     float* c_s;
     uint32_t* hitbits;

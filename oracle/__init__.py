@@ -21,7 +21,7 @@ DEC_LOBE_COS, DEC_L_CULL, DEC_B_CULL = 1 << 0, 1 << 1, 1 << 2
 DEC_L_TRACED, DEC_B_TRACED, DEC_L_HIT, DEC_B_HIT = 1 << 3, 1 << 4, 1 << 5, 1 << 6
 DEC_NOV_POS, DEC_VALID = 1 << 7, 1 << 8
 DEC_NONE = 0xFFFFFFFF
-LIGHT_OFF, FORCE_COS = 1, 2
+LIGHT_OFF, FORCE_COS, BSDF_OFF, FORCE_GGX = 1, 2, 4, 8
 TRI_MISS, TRI_HIT, TRI_NEAR = 0, 1, 2
 
 
@@ -66,7 +66,7 @@ def lib():
         L.orc_env_tables.restype = C.c_int
         L.orc_env_tables.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
         L.orc_shade.restype = C.c_int64
-        L.orc_shade.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, vp, vp, C.c_int, vp, vp, vp, vp,
+        L.orc_shade.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, vp, vp, C.c_int, vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int]
         L.orc_batch_philox.argtypes = [C.c_int64, vp, vp, vp]
         L.orc_batch_uniforms.argtypes = [C.c_int64, C.c_uint64, vp, vp, vp, vp]
@@ -268,15 +268,20 @@ def shade(w, pixels=None, scene=None, tables=None, spp=None, seed=None, tau=None
         out.update(g_kd=np.zeros((3, n)), g_korm=np.zeros((3, n)), g_nrm=np.zeros((3, n)),
                    g_env=np.zeros(tables.env.shape), s_env=np.zeros(tables.env.shape),
                    c_env=np.zeros(tables.env.shape))
+    vcond = np.zeros((15, n))
     r = L.orc_shade(scene.ptr, C.byref(tables.struct), _p(env_ev), C.byref(gs),
                     C.byref(ge) if ge is not None else None, _p(pixels), n, C.byref(prm),
-                    _p(sync_arr), int(grad), _p(ud), _p(us), _p(out["c_d"]), _p(out["c_s"]),
+                    _p(sync_arr), int(grad), _p(ud), _p(us), _p(out["c_d"]), _p(out["c_s"]), _p(vcond),
                     _p(out.get("g_kd")), _p(out.get("g_korm")), _p(out.get("g_nrm")),
                     _p(out.get("g_env")), _p(out.get("s_env")), _p(out.get("c_env")), _p(out["hitbits"]), hw, _p(dec),
                     _p(out["info"]), int(threads))
     if r < 0:
         raise ValueError("oracle rejected the parameters (spp must be in [1, 512])")
     out["nonfinite"] = int(r)
+    # sum over the pixel's samples of |term| * 2^-24 / (n.l), per channel:
+    # the FP32 conditioning of each output in the sampled directions
+    out["c_d_cond"], out["c_s_cond"] = vcond[0:3], vcond[3:6]
+    out["g_kd_cond"], out["g_korm_cond"], out["g_nrm_cond"] = vcond[6:9], vcond[9:12], vcond[12:15]
     if dec is not None:
         out["decisions"] = dec
     return out

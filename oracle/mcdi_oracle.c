@@ -348,6 +348,41 @@ double orc_sample_vndf_local(const double V[3], double alpha, double u1, double 
     return lensq;
 }
 
+/* The same visible-normal sampling steps in FP32 arithmetic.  Not used for
+ * any value: the distance between its direction and the FP64 one measures
+ * how much roundoff the sampling chain lets into the direction for this
+ * sample (the square root near the rim of the stretched hemisphere and the
+ * unstretching amplify it), which sets the sample's tolerance. */
+static void sample_vndf_local_f32(const double V[3], double alpha, double u1, double u2, float L[3])
+{
+    const float a = (float)alpha;
+    float vh[3] = {a * (float)V[0], a * (float)V[1], (float)V[2]};
+    const float l = sqrtf(vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2]);
+    for (int k = 0; k < 3; ++k) vh[k] /= l;
+    const float lensq = vh[0] * vh[0] + vh[1] * vh[1];
+    float T1[3] = {1.0f, 0.0f, 0.0f}, T2[3];
+    if (lensq > 0.0f) {
+        const float il = 1.0f / sqrtf(lensq);
+        T1[0] = -vh[1] * il;
+        T1[1] = vh[0] * il;
+    }
+    T2[0] = vh[1] * T1[2] - vh[2] * T1[1];
+    T2[1] = vh[2] * T1[0] - vh[0] * T1[2];
+    T2[2] = vh[0] * T1[1] - vh[1] * T1[0];
+    const float r = sqrtf((float)u1), ph = 2.0f * (float)ORC_PI * (float)u2;
+    float t1 = r * cosf(ph), t2 = r * sinf(ph);
+    const float s = 0.5f * (1.0f + vh[2]);
+    t2 = (1.0f - s) * sqrtf(fmaxf(0.0f, 1.0f - t1 * t1)) + s * t2;
+    const float tz = sqrtf(fmaxf(0.0f, 1.0f - t1 * t1 - t2 * t2));
+    float nh[3];
+    for (int k = 0; k < 3; ++k) nh[k] = t1 * T1[k] + t2 * T2[k] + tz * vh[k];
+    float ne[3] = {a * nh[0], a * nh[1], fmaxf(0.0f, nh[2])};
+    const float nl = sqrtf(ne[0] * ne[0] + ne[1] * ne[1] + ne[2] * ne[2]);
+    for (int k = 0; k < 3; ++k) ne[k] /= nl;
+    const float vn = (float)V[0] * ne[0] + (float)V[1] * ne[1] + (float)V[2] * ne[2];
+    for (int k = 0; k < 3; ++k) L[k] = 2.0f * vn * ne[k] - (float)V[k];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Shadow-ray visibility (section 3.1): any triangle hit along the ray from  */
 /* o in direction d, t in (0, inf), no back-face culling.  Evaluated in FP64 */
@@ -611,9 +646,12 @@ typedef struct {
     int32_t brute;                       /* all-triangle visibility instead of the BVH */
 } orc_params;
 
-/* flags: debug techniques (white-furnace style checks) */
-#define ORC_LIGHT_OFF 1u  /* no light sample and p_light == 0 */
+/* flags: technique subsets of the estimator (the sampling ablation of
+ * appendix D compares cosine, BSDF and light-probe sampling with MIS) */
+#define ORC_LIGHT_OFF 1u  /* no light sample and p_light == 0: BSDF sampling only */
 #define ORC_FORCE_COS 2u  /* q = 1: the BSDF technique is pure cosine */
+#define ORC_BSDF_OFF 4u   /* no BSDF sample and no BSDF density in P: light sampling only */
+#define ORC_FORCE_GGX 8u  /* q = 0 where n.v > 0: the BSDF technique is pure GGX VNDF */
 
 /* decision record flag bits (shared meaning with the HIP debug dump) */
 #define DEC_LOBE_COS   (1u << 0)
@@ -690,13 +728,17 @@ static float lobe_q(const pix_setup* S, float m_f, uint32_t flags)
     if (q < 0.0f) q = 0.0f;
     if (q > 1.0f) q = 1.0f;
     if (!S->nov_pos || (flags & ORC_FORCE_COS)) q = 1.0f;
+    else if (flags & ORC_FORCE_GGX) q = 0.0f;
     return q;
 }
 
 typedef struct {
     /* outputs of one pixel */
     double cd[3], cs[3];
+    double cd_cond[3], cs_cond[3]; /* sum |term| * u / (n.l): FP32 conditioning of the values */
     double gkd[3], gr, gm, gn[3];
+    double gkd_cond[3], gr_cond, gm_cond, gn_cond; /* the same for the gradient terms */
+    double nlen_cond;                              /* |n_raw|, for the normal's projection */
     uint32_t hitbits[32]; /* 2 bits per sample, spp <= 512 */
     int n_synced, n_flag, n_hard;
 } pix_out;
@@ -713,7 +755,7 @@ typedef struct {
 static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, const double w[3],
                         double pL, const float* Lrad, int spp, double Hv, int grad,
                         const double* Ud, const double* Us, pix_out* out, env_contrib* ec,
-                        int unit_pdf)
+                        double bsdf_w, double e_scale, int unit_pdf)
 {
     double NoL = dot3(Se->n, w);
     double h[3] = {Se->V[0] + w[0], Se->V[1] + w[1], Se->V[2] + w[2]};
@@ -728,13 +770,26 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
     cross3(Ss->n, hs, nxh);
     double q = (double)qf;
     double pcos = NoLs > 0.0 ? NoLs / ORC_PI : 0.0;
-    double pggx = 0.0;
+    double pggx = 0.0, kD = 0.0;
     if (Ss->nov_pos) {
-        double Ds = orc_ggx_D(dot3(Ss->n, hs), dot3(nxh, nxh), Ss->alpha);
-        pggx = Ds / (1.0 + orc_ggx_lambda(Ss->NoV, Ss->alpha)) / (4.0 * Ss->NoV);
+        double s2s = dot3(nxh, nxh), a = Ss->alpha;
+        double Ds = orc_ggx_D(dot3(Ss->n, hs), s2s, a);
+        pggx = Ds / (1.0 + orc_ggx_lambda(Ss->NoV, a)) / (4.0 * Ss->NoV);
+        /* |d ln D / d w| per unit of direction error: D = a^2 / (pi B^2) with
+         * B = a^2 + (1 - a^2)|n x h|^2, and |d|n x h|^2| <= |n x h| |dw| / (v.h) */
+        double B = a * a + (1.0 - a * a) * s2s;
+        double voh = fabs(dot3(Ss->V, hs));
+        kD = 2.0 * (1.0 - a * a) * sqrt(s2s) / (B * fmax(voh, 1e-30));
     }
-    double P = unit_pdf ? 1.0 : pL + q * pcos + (1.0 - q) * pggx;
+    /* balance heuristic over the techniques in use: light (density pL, 0
+     * when off) and the BSDF mixture (weight 0 when off) */
+    double P = unit_pdf ? 1.0 : pL + bsdf_w * (q * pcos + (1.0 - q) * pggx);
     double K = Hv / (P * (double)spp);
+    /* FP32 conditioning of a term in the sampled direction, per unit
+     * roundoff: its log-derivative through n.l (<= 2 / n.l, counted as
+     * 1 / n.l against a factor 2 in the bound) and through the GGX share of P */
+    double cu = 0x1p-24 * e_scale * (1.0 / fmax(fabs(NoL), 1e-30) +
+                                     (unit_pdf ? 0.0 : 0.5 * bsdf_w * (1.0 - q) * pggx * kD / P));
     /* diffuse, demodulated (kd applied outside): (1-m)/pi * NoL * L */
     double kdiff = (1.0 - Se->m) / ORC_PI * NoL * K;
     /* specular: F D G2 / (4 NoV) * L, NoL cancelled */
@@ -770,23 +825,37 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
         double L = (double)Lrad[c];
         out->cd[c] += kdiff * L;
         out->cs[c] += F[c] * S * L * K;
+        /* a sampled direction carries an absolute FP32 error of a few ulp:
+         * relative to n.l it is amplified where the sample grazes */
+        out->cd_cond[c] += fabs(kdiff * L) * cu;
+        out->cs_cond[c] += fabs(F[c] * S * L * K) * cu;
     }
     if (!grad) return;
     double gnd = 0.0, gns = 0.0;
     for (int c = 0; c < 3; ++c) {
         double L = (double)Lrad[c];
         double cdc = kdiff, csc = F[c] * S * K; /* coefficients of L_c */
-        out->gkd[c] += Us[c] * Se->m * (1.0 - Fw) * S * L * K;
-        out->gm += Ud[c] * (-NoL / ORC_PI) * L * K + Us[c] * (Se->kd[c] - 0.04) * (1.0 - Fw) * S * L * K;
-        out->gr += Us[c] * F[c] * L * K * dSdr;
+        const double tkd = Us[c] * Se->m * (1.0 - Fw) * S * L * K;
+        const double tm1 = Ud[c] * (-NoL / ORC_PI) * L * K, tm2 = Us[c] * (Se->kd[c] - 0.04) * (1.0 - Fw) * S * L * K;
+        const double tr = Us[c] * F[c] * L * K * dSdr;
+        out->gkd[c] += tkd;
+        out->gm += tm1 + tm2;
+        out->gr += tr;
+        out->gkd_cond[c] += fabs(tkd) * cu;
+        out->gm_cond += (fabs(tm1) + fabs(tm2)) * cu;
+        out->gr_cond += fabs(tr) * cu;
         gnd += Ud[c] * (1.0 - Se->m) / ORC_PI * L * K;
         gns += Us[c] * F[c] * L * K;
         ec->coef[c] = Ud[c] * cdc + Us[c] * csc;
         ec->absc[c] = fabs(Ud[c] * cdc) + fabs(Us[c] * csc);
-        ec->cond[c] = ec->absc[c] * 0x1p-24 / fmax(fabs(NoL), 1e-30);
+        ec->cond[c] = ec->absc[c] * cu;
     }
-    for (int k = 0; k < 3; ++k)
-        out->gn[k] += gnd * w[k] + gns * (dSdNoV * Se->V[k] + dSdNoL * w[k] + dSdNoH * h[k]);
+    for (int k = 0; k < 3; ++k) {
+        const double t = gnd * w[k] + gns * (dSdNoV * Se->V[k] + dSdNoL * w[k] + dSdNoH * h[k]);
+        out->gn[k] += t;
+        out->gn_cond += (fabs(gnd * w[k]) + fabs(gns) * (fabs(dSdNoV * Se->V[k]) + fabs(dSdNoL * w[k]) +
+                                                         fabs(dSdNoH * h[k]))) * cu;
+    }
 }
 
 typedef struct {
@@ -839,6 +908,7 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
     float m_f = C->gs->korm[2 * ((int64_t)C->gs->n_views * C->gs->height * C->gs->width) + pix];
     float qf = lobe_q(&Ss, m_f, P->flags);
     int light_on = E->light_enabled && !(P->flags & ORC_LIGHT_OFF);
+    int bsdf_on = !(P->flags & ORC_BSDF_OFF);
     int64_t HW = (int64_t)C->gs->height * C->gs->width;
     uint32_t view = (uint32_t)(pix / HW), piv = (uint32_t)(pix % HW);
     double origin[3];
@@ -851,6 +921,7 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
         const uint32_t* gsr = sy ? sy + s * 3 : NULL;
         for (int tech = 0; tech < 2; ++tech) {
             double w[3], pL = 0.0;
+            double e_scale = 1.0;   /* direction-error scale against the 32u bound */
             int ti = -1, tj = -1;
             double tex_margin = INFINITY;
             if (tech == 0) {
@@ -862,6 +933,7 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                 if (gsr && gsr[0] != rec0) out->n_hard++;
                 if (!(pL > 0.0)) { rec2 |= DEC_L_CULL; continue; }
             } else {
+                if (!bsdf_on) continue;
                 double loc[3];
                 int cosl = (float)xi[2] < qf;
                 if (cosl) {
@@ -870,6 +942,11 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                 } else {
                     double lensq = orc_sample_vndf_local(Vl, Ss.alpha, xi[4], xi[5], loc);
                     if (lensq < 1e-14) out->n_flag++;
+                    float l32[3];
+                    sample_vndf_local_f32(Vl, Ss.alpha, xi[4], xi[5], l32);
+                    double ed = 0.0;
+                    for (int k = 0; k < 3; ++k) ed += ((double)l32[k] - loc[k]) * ((double)l32[k] - loc[k]);
+                    e_scale = fmax(1.0, 2.0 * sqrt(ed) / (32.0 * 0x1p-24));
                 }
                 if (gsr && (((gsr[2] & DEC_LOBE_COS) != 0) != cosl)) out->n_hard++;
                 for (int k = 0; k < 3; ++k) w[k] = loc[0] * Ss.t[k] + loc[1] * Ss.b[k] + loc[2] * Ss.n[k];
@@ -925,11 +1002,12 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
             }
             const float* Lrad = envL + ((size_t)ti * E->W + tj) * 3;
             env_contrib* ec = &ecs[2 * s + tech];
-            eval_sample(&Ss, &Se, qf, w, pL, Lrad, spp, Hv, grad, Ud, Us, out, ec, 0);
+            eval_sample(&Ss, &Se, qf, w, pL, Lrad, spp, Hv, grad, Ud, Us, out, ec, bsdf_on ? 1.0 : 0.0, e_scale, 0);
             ec->texel = ti * E->W + tj;
         }
         if (dq) { dq[s * 3] = rec0; dq[s * 3 + 1] = rec1; dq[s * 3 + 2] = rec2; }
     }
+    out->nlen_cond = Se.nlen;
     if (grad) {
         /* d/dn_raw = (I - n n^T) d/dn / |n_raw| */
         double nd = dot3(Se.n, out->gn);
@@ -943,7 +1021,8 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
 int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env_eval,
                   const orc_gbuffer* gs, const orc_gbuffer* ge, const int64_t* pix, int64_t npix,
                   const orc_params* prm, const uint32_t* sync, int grad, const double* Ud,
-                  const double* Us, double* cd, double* cs, double* gkd, double* gkorm, double* gn,
+                  const double* Us, double* cd, double* cs, double* vcond, double* gkd, double* gkorm,
+                  double* gn,
                   double* genv, double* senv, double* cenv, uint32_t* hitbits, int32_t hit_words,
                   uint32_t* dec_out, int32_t* info, int nthreads)
 {
@@ -967,6 +1046,13 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
         for (int c = 0; c < 3; ++c) {
             if (cd) cd[c * npix + q] = o.cd[c];
             if (cs) cs[c * npix + q] = o.cs[c];
+            if (vcond) {
+                vcond[c * npix + q] = o.cd_cond[c];
+                vcond[(3 + c) * npix + q] = o.cs_cond[c];
+                vcond[(6 + c) * npix + q] = o.gkd_cond[c];
+                vcond[(9 + c) * npix + q] = c == 0 ? 0.0 : (c == 1 ? o.gr_cond : o.gm_cond);
+                vcond[(12 + c) * npix + q] = o.gn_cond / (o.nlen_cond > 0.0 ? o.nlen_cond : 1.0);
+            }
             if (grad) {
                 if (gkd) gkd[c * npix + q] = o.gkd[c];
                 if (gn) gn[c * npix + q] = o.gn[c];
@@ -1107,7 +1193,7 @@ void orc_integrand(const orc_scene* scene, const orc_env* E, const orc_gbuffer* 
             double m;
             texel_of_dir(E->H, E->W, wi, &ti, &tj, &m);
             eval_sample(&S, &S, 1.0f, wi, 0.0, E->env + ((size_t)ti * E->W + tj) * 3, 1, Hv, 0, NULL,
-                        NULL, &o, &ec, 1);
+                        NULL, &o, &ec, 1.0, 1.0, 1);
         }
         for (int c = 0; c < 3; ++c) {
             gd[3 * i + c] = o.cd[c];

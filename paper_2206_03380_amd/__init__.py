@@ -11,7 +11,8 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib as L
-from ._lib import MCDIError, FLAG_LIGHT_OFF, FLAG_FORCE_COS, FLAG_DUMP, FLAG_TIME_TRACE  # noqa: F401
+from ._lib import (MCDIError, FLAG_LIGHT_OFF, FLAG_FORCE_COS, FLAG_BSDF_OFF, FLAG_FORCE_GGX,  # noqa: F401
+                   FLAG_DUMP, FLAG_TIME_TRACE)
 
 __all__ = ["Scene", "Env", "GBuffer", "shade_fwd", "shade_bwd", "trace_anyhit", "MCDIShade",
            "MCDIError", "new_stats", "read_stats"]
@@ -256,6 +257,18 @@ def image_loss(kd, c_d, c_s, ref, mask, w_light=0.15, stream=None, out=None):
                                     _ptr(loss), _ptr(g_kd), _ptr(g_cd), _ptr(g_cs), C.byref(_TORCH_ALLOCATOR),
                                     _stream(stream)))
     return loss, g_kd, g_cd, g_cs
+
+
+def shadow_tau(iteration, ramp=1750):
+    """Light-leakage parameter of the shadow ramp: tau rises linearly from 0
+    to 1 over the first `ramp` iterations, so shadowed samples are weighted
+    by H = 1 - tau (appendix A)."""
+    return min(max(iteration / float(ramp), 0.0), 1.0) if ramp > 0 else 1.0
+
+
+def decorrelated_seed(seed):
+    """A backward seed independent of the forward's Philox stream."""
+    return (int(seed) ^ 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
 
 
 def denoise_sigma(iteration, ramp=1750, lo=1e-4, hi=2.0):

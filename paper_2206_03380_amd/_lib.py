@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(_HERE, "libmcdi.so")
 MCDI_OK, MCDI_E_INVALID, MCDI_E_OOM, MCDI_E_DEVICE, MCDI_E_UNSUPPORTED = 0, -1, -2, -3, -4
 FLAG_LIGHT_OFF = 1 << 0
 FLAG_FORCE_COS = 1 << 1
+FLAG_BSDF_OFF = 1 << 2
+FLAG_FORCE_GGX = 1 << 3
 FLAG_DUMP = 1 << 8
 FLAG_TIME_TRACE = 1 << 9
 

@@ -12,15 +12,20 @@ from . import _lib as L
 
 
 class MCDIShade(torch.autograd.Function):
-    """c_d, c_s = MCDIShade.apply(kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed, tau, ray_eps, flags)
+    """c_d, c_s = MCDIShade.apply(kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed, tau, ray_eps, flags,
+                                 bwd_seed)
 
     kd, korm, nrm: [3, N] float32 (differentiable); env: the [H, W, 3] probe
     tensor the tables were built from (differentiable; its gradient is the
     texel scatter).  Positions, mask and eyes come from gbuf (not
-    differentiated: shape gradients come from primary visibility)."""
+    differentiated: shape gradients come from primary visibility).
+    bwd_seed None (default): the backward replays the forward's samples
+    (correlated, section 4.1); otherwise it draws and traces its own samples
+    from bwd_seed (decorrelated, unbiased; see decorrelated_seed)."""
 
     @staticmethod
-    def forward(ctx, kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0):
+    def forward(ctx, kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0,
+                bwd_seed=None):
         from . import _ptr, _stream, hit_words, _params
         import ctypes as C
         n = gbuf.n
@@ -30,14 +35,15 @@ class MCDIShade(torch.autograd.Function):
             raise ValueError("env_tables must be built from the env tensor passed in")
         c_d = torch.empty((3, n), dtype=torch.float32, device=dev)
         c_s = torch.empty((3, n), dtype=torch.float32, device=dev)
-        need_bits = tau != 0.0 and any(ctx.needs_input_grad[:4])
+        need_bits = tau != 0.0 and any(ctx.needs_input_grad[:4]) and bwd_seed is None
         hb = torch.empty((hit_words(spp), n), dtype=torch.int32, device=dev) if need_bits else None
         gs = gbuf.struct(kd=kd, korm=korm, nrm=nrm)
         prm = _params(spp, seed, tau, ray_eps, flags, None)
         L.check(L.lib().mcdi_shade_fwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(c_d),
                                        _ptr(c_s), _ptr(hb), None, _stream()))
         ctx.save_for_backward(kd, korm, nrm, hb if hb is not None else torch.empty(0, device=dev))
-        ctx.meta = (scene, env_tables, gbuf, spp, seed, tau, ray_eps, hb is not None)
+        ctx.meta = (scene, env_tables, gbuf, spp, seed if bwd_seed is None else bwd_seed, tau, ray_eps,
+                    hb is not None, flags & ~(L.FLAG_DUMP | L.FLAG_TIME_TRACE))
         return c_d, c_s
 
     @staticmethod
@@ -45,7 +51,7 @@ class MCDIShade(torch.autograd.Function):
         from . import _ptr, _stream, _params
         import ctypes as C
         kd, korm, nrm, hb = ctx.saved_tensors
-        scene, env_tables, gbuf, spp, seed, tau, ray_eps, has_bits = ctx.meta
+        scene, env_tables, gbuf, spp, seed, tau, ray_eps, has_bits, flags = ctx.meta
         n = gbuf.n
         dev = kd.device
         g_cd = (g_cd if g_cd is not None else torch.zeros((3, n), device=dev)).contiguous().float()
@@ -55,11 +61,11 @@ class MCDIShade(torch.autograd.Function):
         g_nrm = torch.empty((3, n), dtype=torch.float32, device=dev)
         g_env = torch.zeros((env_tables.H, env_tables.W, 3), dtype=torch.float32, device=dev)
         gs = gbuf.struct(kd=kd, korm=korm, nrm=nrm)
-        prm = _params(spp, seed, tau, ray_eps, 0, None)
+        prm = _params(spp, seed, tau, ray_eps, flags, None)
         L.check(L.lib().mcdi_shade_bwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(g_cd),
                                        _ptr(g_cs), _ptr(hb) if has_bits else None, _ptr(g_kd), _ptr(g_korm),
                                        _ptr(g_nrm), _ptr(g_env), None, _stream()))
-        return g_kd, g_korm, g_nrm, g_env, None, None, None, None, None, None, None, None
+        return g_kd, g_korm, g_nrm, g_env, None, None, None, None, None, None, None, None, None
 
 
 class Bilateral(torch.autograd.Function):

@@ -281,6 +281,10 @@ static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, cons
         return fail(MCDI_E_INVALID, "%s: tau must be finite and ray_eps finite and >= 0", who);
     if ((p->flags & MCDI_FLAG_DUMP) && !p->decisions)
         return fail(MCDI_E_INVALID, "%s: MCDI_FLAG_DUMP without a decisions buffer", who);
+    if ((p->flags & MCDI_FLAG_LIGHT_OFF) && (p->flags & MCDI_FLAG_BSDF_OFF))
+        return fail(MCDI_E_INVALID, "%s: LIGHT_OFF and BSDF_OFF leave no sampling technique", who);
+    if ((p->flags & MCDI_FLAG_FORCE_COS) && (p->flags & MCDI_FLAG_FORCE_GGX))
+        return fail(MCDI_E_INVALID, "%s: FORCE_COS and FORCE_GGX together", who);
     std::memset(&a, 0, sizeof(a));
     a.scene = Scene{sc->nodes, sc->tris, sc->n_tris};
     a.env = EnvView{ev->H, ev->W, ev->rgb, ev->cond, ev->marg, ev->pdf, ev->light, ev->hot_slot, ev->hot_texel,

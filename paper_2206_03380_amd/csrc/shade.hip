@@ -28,6 +28,7 @@ struct Pixel {
     float t1x, t1y;        // T1 (z = 0)
     float3 kd, F0;
     float m, r, a2, alpha, q, nov, lamV, G1V, nlen;
+    float bsdf_w;          // 1: the BSDF technique is in use, 0: light sampling only
     bool r_active;
 };
 
@@ -93,7 +94,9 @@ __device__ Pixel setup_pixel(const ShadeArgs& A, int64_t pix, bool& nonfinite) {
     float q = 0.5f * (1.0f - km);
     q = fminf(fmaxf(q, 0.0f), 1.0f);
     if (!P.nov_pos || (A.flags & MCDI_FLAG_FORCE_COS)) q = 1.0f;
+    else if (A.flags & MCDI_FLAG_FORCE_GGX) q = 0.0f;
     P.q = q;
+    P.bsdf_w = (A.flags & MCDI_FLAG_BSDF_OFF) ? 0.0f : 1.0f;
     // Smith Lambda of the view and the visible-normal frame (FP64)
     if (P.nov_pos) {
         const double t2 = (1.0 - nov * nov) / (nov * nov);
@@ -232,7 +235,8 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
     const float D = ggx_D(NoH, s2, P.a2);
     const float pcos = NoL * kInvPi;
     const float pggx = P.nov_pos ? P.G1V * D / (4.0f * P.nov) : 0.0f;
-    const float Pt = S.pL + P.q * pcos + (1.0f - P.q) * pggx;
+    // balance heuristic over the techniques in use
+    const float Pt = S.pL + P.bsdf_w * (P.q * pcos + (1.0f - P.q) * pggx);
     const float w = Hv / Pt;
     const float* Lp = A.env.rgb + 3 * (size_t)S.texel;
     const float3 L = f3(Lp[0], Lp[1], Lp[2]);
@@ -378,7 +382,8 @@ __device__ __forceinline__ void gen_tile(const ShadeArgs& A, int64_t tile, float
             if (go) {
                 bool has = true;
                 if (tech == 0) has = light_on && draw_light(A, P, s_marg, r0, S);
-                else draw_bsdf(P, r0, r1, S);
+                else if (P.bsdf_w != 0.0f) draw_bsdf(P, r0, r1, S);
+                else has = false;
                 want = has && S.wl.z > 0.0f;
                 if (has && !want) ++c_culled;
             }
@@ -593,6 +598,7 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
                 rec0 = (uint32_t)S.texel;
                 if (!has) { rec2 |= kDecLCull; continue; }
             } else {
+                if (P.bsdf_w == 0.0f) continue;
                 if (draw_bsdf(P, r0, r1, S)) rec2 |= kDecLobeCos;
             }
             if (!(S.wl.z > 0.0f)) { rec2 |= tech ? kDecBCull : kDecLCull; continue; }

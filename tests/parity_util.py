@@ -40,12 +40,22 @@ def hitbits_per_pixel(hb_planar):
     return np.ascontiguousarray(hb_planar.T)
 
 
-def compare(gpu, orc, valid, rel=REL_TOL, absf=ABS_TOL, name=""):
-    """Return (ok, worst relative excess, report)."""
+# Grazing samples: an absolute FP32 error of the sampled direction (<= 32u,
+# with a factor 2 margin) changes a term by its log-derivative in n.l (<= 2)
+# times that error over n.l; the oracle sums |term| u / (n.l) per output as
+# `<name>_cond`, and the bound adds COND_K times it.
+COND_K = 64
+
+
+def compare(gpu, orc, valid, rel=REL_TOL, absf=ABS_TOL, name="", cond=None):
+    """Return (ok, worst relative excess, report).  cond: the oracle's
+    per-element conditioning sum (same shape as orc), or None."""
     g = gpu[:, valid].astype(np.float64)
     o = orc[:, valid]
     scale = np.abs(o).mean(axis=1, keepdims=True)
     bound = rel * np.abs(o) + absf * scale
+    if cond is not None:
+        bound = bound + COND_K * cond[:, valid]
     err = np.abs(g - o)
     ok = err <= bound
     worst = float((err / np.maximum(bound, 1e-300)).max()) if err.size else 0.0

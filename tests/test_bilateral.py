@@ -279,6 +279,12 @@ def test_view_depth_is_distance():
     assert np.allclose(z[mask > 0], t[mask > 0], rtol=1e-14) and z[3] == 0
 
 
+def test_shadow_ramp_schedule():
+    import paper_2206_03380_amd as M
+    assert M.shadow_tau(0) == 0.0 and M.shadow_tau(875) == 0.5 and M.shadow_tau(1750) == 1.0
+    assert M.shadow_tau(10 ** 6) == 1.0 and M.decorrelated_seed(5) != 5
+
+
 def test_sigma_schedule():
     import paper_2206_03380_amd as M
     assert M.denoise_sigma(0) == 1e-4 and M.denoise_sigma(1750) == 2.0 and M.denoise_sigma(5000) == 2.0

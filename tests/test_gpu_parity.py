@@ -37,7 +37,7 @@ def _fwd_parity(w, min_valid_frac=0.99, pixels=None, **kw):
     valid = (w.mask[pix] > 0) & ~flagged
     assert valid.sum() >= min_valid_frac * (w.mask[pix] > 0).sum()
     for key in ("c_d", "c_s"):
-        ok, worst, rep = compare(g[key][:, pix], o[key], valid, name=key)
+        ok, worst, rep = compare(g[key][:, pix], o[key], valid, name=key, cond=o[key + "_cond"])
         print(rep)
         assert ok, rep
     # hit masks: equal wherever the oracle did not adopt a kernel decision
@@ -51,11 +51,17 @@ def _fwd_parity(w, min_valid_frac=0.99, pixels=None, **kw):
 def _oracle_flags(f):
     import paper_2206_03380_amd as M
     out = 0
-    if f & M.FLAG_LIGHT_OFF:
-        out |= oracle.LIGHT_OFF
-    if f & M.FLAG_FORCE_COS:
-        out |= oracle.FORCE_COS
+    for mine, theirs in ((M.FLAG_LIGHT_OFF, oracle.LIGHT_OFF), (M.FLAG_FORCE_COS, oracle.FORCE_COS),
+                         (M.FLAG_BSDF_OFF, oracle.BSDF_OFF), (M.FLAG_FORCE_GGX, oracle.FORCE_GGX)):
+        if f & mine:
+            out |= theirs
     return out
+
+
+def _technique(name):
+    import paper_2206_03380_amd as M
+    return {"mis": 0, "bsdf": M.FLAG_LIGHT_OFF, "light": M.FLAG_BSDF_OFF,
+            "cosine": M.FLAG_LIGHT_OFF | M.FLAG_FORCE_COS, "ggx": M.FLAG_LIGHT_OFF | M.FLAG_FORCE_GGX}[name]
 
 
 # ---------------------------------------------------------------------------
@@ -174,6 +180,12 @@ def test_fwd_parity_tiny_cos_only():
     _fwd_parity(w, flags=M.FLAG_LIGHT_OFF | M.FLAG_FORCE_COS)
 
 
+@pytest.mark.parametrize("tech", ["light", "bsdf", "ggx"])
+def test_fwd_parity_tiny_techniques(tech):
+    w = make_workload("tiny")
+    _fwd_parity(w, flags=_technique(tech))
+
+
 def test_fwd_parity_sphere8_ragged():
     # two views, 60x52: several tiles and a ragged last tile
     w = make_workload("sphere8", H=60, W=52, n_views=2)
@@ -227,22 +239,22 @@ def test_fwd_deterministic_and_linear():
 # ---------------------------------------------------------------------------
 # backward parity
 # ---------------------------------------------------------------------------
-def _bwd_parity(w, use_hitbits=True):
+def _bwd_parity(w, use_hitbits=True, flags=0):
     _need_gpu()
     import paper_2206_03380_amd as M
-    g, (scene, env, gb, hb) = gpu_forward(w)
+    g, (scene, env, gb, hb) = gpu_forward(w, flags=flags)
     ud, us = upstream_grads(w)
     tud, tus = torch.from_numpy(ud).cuda(), torch.from_numpy(us).cuda()
     g_kd, g_korm, g_nrm, g_env = M.shade_bwd(scene, env, gb, w.spp, tud, tus, hitbits=hb if use_hitbits else None,
-                                             seed=w.seed, tau=w.tau, ray_eps=w.ray_eps)
+                                             seed=w.seed, tau=w.tau, ray_eps=w.ray_eps, flags=flags)
     torch.cuda.synchronize()
     o = oracle.shade(w, sync=g["decisions"], grad=True, u_d=ud.astype(np.float64), u_s=us.astype(np.float64),
-                     want_decisions=True)
+                     want_decisions=True, flags=_oracle_flags(flags))
     info = o["info"]
     assert info[:, 2].sum() == 0
     valid = (w.mask > 0) & (info[:, 1] == 0)
     for gpu_t, key in ((g_kd, "g_kd"), (g_korm, "g_korm"), (g_nrm, "g_nrm")):
-        ok, worst, rep = compare(to_np(gpu_t), o[key], valid, rel=1e-3, absf=1e-5, name=key)
+        ok, worst, rep = compare(to_np(gpu_t), o[key], valid, rel=1e-3, absf=1e-5, name=key, cond=o[key + "_cond"])
         print(rep)
         assert ok, rep
     # env: an n-term FP32 sum in any order is within gamma_n * sum|terms|
@@ -281,6 +293,21 @@ def test_bwd_parity_tiny():
 
 def test_bwd_parity_tiny_retrace():
     _bwd_parity(make_workload("tiny"), use_hitbits=False)
+
+
+@pytest.mark.parametrize("tech", ["light", "cosine", "ggx"])
+def test_bwd_parity_tiny_techniques(tech):
+    _bwd_parity(make_workload("tiny"), flags=_technique(tech))
+
+
+def test_technique_flag_combinations_rejected():
+    _need_gpu()
+    import paper_2206_03380_amd as M
+    w = make_workload("tiny")
+    _, (scene, env, gb, hb) = gpu_forward(w, dump=False)
+    for bad in (M.FLAG_LIGHT_OFF | M.FLAG_BSDF_OFF, M.FLAG_FORCE_COS | M.FLAG_FORCE_GGX):
+        with pytest.raises(M.MCDIError):
+            M.shade_fwd(scene, env, gb, 2, flags=bad)
 
 
 def test_bwd_parity_sphere8_small():

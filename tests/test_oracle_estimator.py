@@ -153,8 +153,15 @@ def _sphere_dirs(H, W, S):
     return d, wt
 
 
+TECHNIQUES = {"mis": 0, "bsdf": oracle.LIGHT_OFF, "light": oracle.BSDF_OFF,
+              "cosine": oracle.LIGHT_OFF | oracle.FORCE_COS, "ggx": oracle.LIGHT_OFF | oracle.FORCE_GGX}
+
+
+@pytest.mark.parametrize("tech", sorted(TECHNIQUES))
 @pytest.mark.parametrize("pix_sel", [0, 1, 2])
-def test_mc_converges_to_quadrature(pix_sel):
+def test_mc_converges_to_quadrature(pix_sel, tech):
+    """Every technique subset of the sampling ablation (cosine, BSDF, light,
+    GGX alone, and MIS) is an unbiased estimator of the same integral."""
     w = make_workload("tiny")
     valid = np.nonzero((w.mask > 0) & (w.korm[1] > 0.35))[0]
     pix = valid[[len(valid) // 5, len(valid) // 2, (4 * len(valid)) // 5][pix_sel]]
@@ -169,7 +176,7 @@ def test_mc_converges_to_quadrature(pix_sel):
     col = lambda a: np.tile(a[:, pix], (N, 1))  # noqa: E731
     rep = from_arrays("rep", w.verts, w.tris, w.env, col(w.pos), col(w.nrm), col(w.kd), col(w.korm),
                       eye=w.eye[0], spp=spp, ray_eps=w.ray_eps, tau=w.tau)
-    o = oracle.shade(rep, scene=sc, tables=tab)
+    o = oracle.shade(rep, scene=sc, tables=tab, flags=TECHNIQUES[tech])
     for est, quad in ((o["c_d"], quad_d), (o["c_s"], quad_s)):
         mean = est.mean(1)
         se = est.std(1, ddof=1) / np.sqrt(N)
