@@ -201,6 +201,7 @@ def main():
         "roofline": roofline,
     }
 
+    STATE.update(scene=scene, env=envh, w=w)
     result["next_rows"] = next_rows(args, M, gb, out[0], out[1], target, timed)
     if not args.no_serve:
         result["serving"] = serve_quick(args, M, w, gb)
@@ -229,6 +230,37 @@ BILAT_OPS_BWD = 32
 LOSS_BYTES_PER_PX = 86
 
 
+def sampling_study(args, M, gb, timed, seeds=4):
+    """Variance study of the sampling techniques on the step's workload:
+    forward time at the workload's spp, and the mean per-pixel relative
+    variance of the shaded colour over independent seeds; efficiency is
+    1 / (variance x time) relative to MIS."""
+    import torch
+    sc, envh, w = STATE["scene"], STATE["env"], STATE["w"]
+    techs = {"mis": 0, "bsdf": M.FLAG_LIGHT_OFF, "light": M.FLAG_BSDF_OFF,
+             "cosine": M.FLAG_LIGHT_OFF | M.FLAG_FORCE_COS, "ggx": M.FLAG_LIGHT_OFF | M.FLAG_FORCE_GGX}
+    m = gb.mask.bool()
+    res = {}
+    for name, f in techs.items():
+        cols = []
+        for k in range(seeds):
+            cd, cs, _, _ = M.shade_fwd(sc, envh, gb, w.spp, seed=100 + k, tau=w.tau, ray_eps=w.ray_eps, flags=f,
+                                       hitbits=False)
+            cols.append((gb.kd * cd + cs)[:, m].sum(0))
+        c = torch.stack(cols).double()
+        res[name] = {"rel_var": float((c.var(0) / c.mean(0).clamp_min(1e-3) ** 2).mean())}
+        out = M.shade_fwd(sc, envh, gb, w.spp, seed=0, tau=w.tau, ray_eps=w.ray_eps, flags=f)
+        res[name]["fwd_ms"] = timed(lambda: M.shade_fwd(sc, envh, gb, w.spp, seed=0, tau=w.tau, ray_eps=w.ray_eps,
+                                                        flags=f, out=out[:3]), max(3, args.kernel_reps // 2))
+    ref = res["mis"]["rel_var"] * res["mis"]["fwd_ms"]
+    for name in res:
+        res[name]["efficiency_vs_mis"] = ref / (res[name]["rel_var"] * res[name]["fwd_ms"])
+    return {"spp": w.spp, "seeds": seeds, "techniques": res}
+
+
+STATE = {}
+
+
 def next_rows(args, M, gb, c_d, c_s, target, timed):
     """Denoiser and image-loss kernels on the step's own outputs, each timed
     alone with HIP events on the launch stream."""
@@ -254,6 +286,7 @@ def next_rows(args, M, gb, c_d, c_s, target, timed):
         return {"bound": "alu", "achieved": a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
                 "frac": a / VALU_PEAK, "traffic": None}
 
+    sampling = sampling_study(args, M, gb, timed)
     lo = (torch.empty(3, dtype=torch.float32, device=x.device),) + tuple(torch.empty_like(c_d) for _ in range(3))
     l_ms = timed(lambda: M.image_loss(gb.kd, c_d, c_s, target, gb.mask, out=lo), reps)
     lbytes = LOSS_BYTES_PER_PX * n
@@ -262,6 +295,7 @@ def next_rows(args, M, gb, c_d, c_s, target, timed):
                       "fwd_ms": f_ms, "bwd_ms": b_ms, "view_depth_ms": d_ms,
                       "fwd_roofline": alu(taps * BILAT_OPS_FWD, f_ms),
                       "bwd_roofline": alu(taps * BILAT_OPS_BWD, b_ms)},
+        "sampling": sampling,
         "image_loss": {"ms": l_ms, "bytes_per_launch": lbytes,
                        "roofline": {"bound": "hbm", "achieved": lbytes / (l_ms * 1e-3) / 1e9,
                                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
@@ -271,7 +305,7 @@ def next_rows(args, M, gb, c_d, c_s, target, timed):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_rays_sphere8_grad_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_03380_amd", "csrc", f)
-                  for f in ("shade.hip", "device_common.h", "mcdi_internal.h")]
+                  for f in ("shade.hip", "device_common.h", "mcdi_internal.h", "bvh_build.hip")]
 
 
 def kernel_source_hash():
@@ -450,12 +484,15 @@ def cpu_baseline(args, w):
                      u_s=us[:, pix].astype(np.float64))
         return time.time() - t
 
-    n = 512
+    # size the sample from a calibration run large enough that per-call
+    # overheads do not dominate; the whole workload when it fits the budget
+    n = int(min(len(valid), 65536))
     dt = run(n)
     n2 = int(min(len(valid), max(n, n * args.cpu_seconds / max(dt, 1e-3))))
     dt2 = run(n2)
+    what = "all %d valid pixels" % n2 if n2 == len(valid) else "%d random valid pixels" % n2
     return {"value": n2 * w.spp / dt2, "unit": "samples/s", "cores": nthreads, "kind": "oracle",
-            "sample": "%d random valid pixels of the same workload, forward + backward, %.1f s" % (n2, dt2)}
+            "sample": "%s of the same workload, forward + backward, %.1f s" % (what, dt2)}
 
 
 if __name__ == "__main__":

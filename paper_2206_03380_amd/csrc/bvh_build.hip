@@ -161,27 +161,62 @@ __device__ __forceinline__ void tri_box(const float4* t, float4& lo, float4& hi)
                      fmaxf(t[0].z, fmaxf(t[1].z, t[2].z)), 0.0f);
 }
 
-__global__ __launch_bounds__(256) void refit(const float4* tmp, const uint32_t* vals, int nt, Tree T) {
+// fit node p from its two finished children
+__device__ __forceinline__ void fit_node(int p, int nt, const Tree& T) {
+    const int l = T.left[p], r = T.right[p];
+    const float4 al = T.box[2 * l], ah = T.box[2 * l + 1], bl = T.box[2 * r], bh = T.box[2 * r + 1];
+    T.box[2 * p] = make_float4(fminf(al.x, bl.x), fminf(al.y, bl.y), fminf(al.z, bl.z), 0.0f);
+    T.box[2 * p + 1] = make_float4(fmaxf(ah.x, bh.x), fmaxf(ah.y, bh.y), fmaxf(ah.z, bh.z), 0.0f);
+    const int size = T.last[p] - T.first[p] + 1;
+    T.cnt[p] = size <= kLeafMax ? 1 : 1 + T.cnt[l] + T.cnt[r];
+}
+
+// Bottom-up refit, first phase: workgroup b fits the leaves of sorted
+// positions [256 b, 256 b + 256) and every internal node whose range lies
+// inside them, the second of the two children to arrive fitting the parent.
+// All of that happens inside one workgroup, so workgroup-scope atomics order
+// it (an agent-scope release would write the L2 back on every step).  A climb
+// that reaches a node spanning workgroups stops there and records the child
+// it finished.
+__global__ __launch_bounds__(256) void refit_local(const float4* tmp, const uint32_t* vals, int nt, Tree T,
+                                                   int* top_list, int* top_count) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nt) return;
+    const int lo = blockIdx.x * blockDim.x, hi = min(nt, lo + (int)blockDim.x) - 1;
     const int leaf = nt - 1 + k;
-    float4 lo, hi;
-    tri_box(tmp + 3 * (size_t)vals[k], lo, hi);
-    T.box[2 * leaf] = lo;
-    T.box[2 * leaf + 1] = hi;
+    float4 blo, bhi;
+    tri_box(tmp + 3 * (size_t)vals[k], blo, bhi);
+    T.box[2 * leaf] = blo;
+    T.box[2 * leaf + 1] = bhi;
     T.cnt[leaf] = 1;
+    int c = leaf;
     int p = T.parent[leaf];
     for (int guard = 0; p >= 0 && p < nt - 1 && guard < 4096; ++guard) {
-        // the second child to arrive fits the parent
-        const int old = __hip_atomic_fetch_add(&T.flag[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (T.first[p] < lo || T.last[p] > hi) {
+            top_list[atomicAdd(top_count, 1)] = c;
+            return;
+        }
+        const int old = __hip_atomic_fetch_add(&T.flag[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (old == 0) return;
-        const int l = T.left[p], r = T.right[p];
-        const float4 al = T.box[2 * l], ah = T.box[2 * l + 1], bl = T.box[2 * r], bh = T.box[2 * r + 1];
-        T.box[2 * p] = make_float4(fminf(al.x, bl.x), fminf(al.y, bl.y), fminf(al.z, bl.z), 0.0f);
-        T.box[2 * p + 1] = make_float4(fmaxf(ah.x, bh.x), fmaxf(ah.y, bh.y), fmaxf(ah.z, bh.z), 0.0f);
-        const int size = T.last[p] - T.first[p] + 1;
-        T.cnt[p] = size <= kLeafMax ? 1 : 1 + T.cnt[l] + T.cnt[r];
+        fit_node(p, nt, T);
+        c = p;
         p = T.parent[p];
+    }
+}
+
+// Second phase, one workgroup: the nodes spanning workgroups (ancestors of
+// the recorded children), with the first phase's results visible across the
+// launch boundary.
+__global__ __launch_bounds__(1024) void refit_top(const int* top_list, const int* top_count, int nt, Tree T) {
+    const int m = *top_count;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        int p = T.parent[top_list[i]];
+        for (int guard = 0; p >= 0 && p < nt - 1 && guard < 4096; ++guard) {
+            const int old = __hip_atomic_fetch_add(&T.flag[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0) break;
+            fit_node(p, nt, T);
+            p = T.parent[p];
+        }
     }
 }
 
@@ -282,7 +317,7 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     const size_t sz_tmp = al(sizeof(float4) * 3 * ntm), sz_keys = al(sizeof(uint64_t) * ntm),
                  sz_vals = al(sizeof(uint32_t) * ntm), sz_i = al(sizeof(int32_t) * n_nodes),
                  sz_box = al(sizeof(float4) * 2 * n_nodes), sz_cb = al(sizeof(int) * 8), sz_sort = al(sort_bytes);
-    const size_t total = sz_tmp + 2 * sz_keys + 2 * sz_vals + 7 * sz_i + sz_box + sz_cb + sz_sort;
+    const size_t total = sz_tmp + 2 * sz_keys + 2 * sz_vals + 8 * sz_i + sz_box + sz_cb + sz_sort;
     char* base = (char*)ta.alloc(ta.ctx, total, s);
     if (!base) { *oom = 1; return hipErrorOutOfMemory; }
     char* p = base;
@@ -300,6 +335,7 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     T.last = (int32_t*)take(sz_i);
     T.flag = (int32_t*)take(sz_i);
     T.cnt = (int32_t*)take(sz_i);
+    int32_t* top_list = (int32_t*)take(sz_i);
     T.box = (float4*)take(sz_box);
     int* cb = (int*)take(sz_cb);
     void* sort_tmp = take(sz_sort);
@@ -317,7 +353,9 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
             hipLaunchKernelGGL(fill_i32, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, T.parent, (int64_t)(2 * nt - 1), -1);
             hipLaunchKernelGGL(fill_i32, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, T.cnt, (int64_t)(2 * nt - 1), 0);
             hipLaunchKernelGGL(radix_tree, dim3(nblk(nt - 1)), dim3(256), 0, s, keys2, nt, T);
-            hipLaunchKernelGGL(refit, dim3(nblk(nt)), dim3(256), 0, s, tmp, vals2, nt, T);
+            hipLaunchKernelGGL(fill_i32, dim3(1), dim3(256), 0, s, cb + 6, (int64_t)1, 0);   // top-node count
+            hipLaunchKernelGGL(refit_local, dim3(nblk(nt)), dim3(256), 0, s, tmp, vals2, nt, T, top_list, cb + 6);
+            hipLaunchKernelGGL(refit_top, dim3(1), dim3(1024), 0, s, top_list, cb + 6, nt, T);
             hipLaunchKernelGGL(emit, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nt, T, nodes_out, info);
             hipLaunchKernelGGL(reorder, dim3(nblk(nt)), dim3(256), 0, s, tmp, vals2, (int64_t)nt, tris_out);
         }

@@ -5,12 +5,13 @@
 // from section 4.2).  HBM-bound: 48 B/px + 1 B mask in, 36 B/px out, plus a
 // 1 B/px counting pass for the number of valid pixels the means divide by.
 //
-// Two launches.  The counting pass writes per-block integer counts and clears
-// the completion ticket of the loss pass.  The loss pass is a grid-stride
-// stream over pixels; each block first sums the integer counts (exact, so
-// every block gets the same n), writes its FP64 partial loss sums, and the
-// last block to take a ticket reduces all partials in a fixed order -- the
-// loss value does not depend on timing.
+// Three launches.  The counting pass writes per-block integer counts.  The
+// loss pass is a grid-stride stream over pixels; each block first sums the
+// integer counts (exact, so every block gets the same n) and writes its FP64
+// partial loss sums; a one-block pass reduces the partials in a fixed order,
+// so the loss value does not depend on timing.  (A last-block-done ticket
+// would need an agent-scope release per block, which on this chip writes back
+// the L2 and costs more than the extra launch.)
 //
 // The transfer curve uses the hardware log2/exp2: log(1+x) with Goldberg's
 // correction x*log(u)/(u-1), u = 1+x (a few ulp), y^(1/2.4) as
@@ -58,7 +59,7 @@ __device__ __forceinline__ float tonemap_value(float x) {
 __device__ __forceinline__ float sgn(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
 
 __global__ __launch_bounds__(256) void count_kernel(const uint8_t* __restrict__ mask, int64_t n,
-                                                    long long* __restrict__ part, unsigned* __restrict__ ticket) {
+                                                    long long* __restrict__ part) {
     __shared__ int s[256];
     const int64_t base = (int64_t)blockIdx.x * kCountPx;
     int c = 0;
@@ -72,10 +73,7 @@ __global__ __launch_bounds__(256) void count_kernel(const uint8_t* __restrict__ 
         if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = s[0];
-        if (blockIdx.x == 0) *ticket = 0u;
-    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
 // Fixed-order block sum: lane t adds p[t*stride], p[(t+256)*stride], ... in
@@ -99,12 +97,10 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ kd,
                                                    const float* __restrict__ cs, const float* __restrict__ ref,
                                                    const uint8_t* __restrict__ mask, int64_t n, float w_light,
                                                    const long long* __restrict__ cnt, int64_t n_cnt,
-                                                   double* __restrict__ part, unsigned* __restrict__ ticket,
-                                                   float* __restrict__ loss, float* __restrict__ g_kd,
+                                                   double* __restrict__ part, float* __restrict__ g_kd,
                                                    float* __restrict__ g_cd, float* __restrict__ g_cs) {
     __shared__ double s_d[256];
     __shared__ long long s_i[256];
-    __shared__ unsigned s_last;
     const long long nvi = fixed_sum(cnt, n_cnt, 1, s_i);
     const double nv = nvi > 0 ? (double)nvi : 1.0;
     const float inv3n = (float)(1.0 / (3.0 * nv)), invn = (float)(1.0 / nv);
@@ -143,7 +139,7 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ kd,
             if (g_cs) g_cs[c * n + k] = gc[c] + gl * dls[c];
         }
     }
-    // block partials (fixed tree), then the last block reduces them all
+    // block partials (fixed tree)
     s_d[threadIdx.x] = li;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -161,14 +157,18 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ kd,
     if (threadIdx.x == 0) {
         part[2 * blockIdx.x] = bi;
         part[2 * blockIdx.x + 1] = s_d[0];
-        __threadfence();
-        s_last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    if (s_last != gridDim.x - 1) return;
-    __threadfence();
-    const double a = fixed_sum(part, gridDim.x, 2, s_d);
-    const double b = fixed_sum(part + 1, gridDim.x, 2, s_d);
+}
+
+__global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ part, int nb,
+                                                     const long long* __restrict__ cnt, int64_t n_cnt, float w_light,
+                                                     float* __restrict__ loss) {
+    __shared__ double s_d[256];
+    __shared__ long long s_i[256];
+    const long long nvi = fixed_sum(cnt, n_cnt, 1, s_i);
+    const double nv = nvi > 0 ? (double)nvi : 1.0;
+    const double a = fixed_sum(part, nb, 2, s_d);
+    const double b = fixed_sum(part + 1, nb, 2, s_d);
     if (threadIdx.x == 0) {
         const double lim = a / (3.0 * nv), llm = b / nv;
         loss[0] = (float)lim;
@@ -197,10 +197,10 @@ hipError_t launch_image_loss(const float* kd, const float* cd, const float* cs, 
     const int nl = loss_blocks(n);
     double* part = (double*)scratch;                         // [2 nl]
     long long* cnt = (long long*)(part + 2 * nl);            // [nc]
-    unsigned* ticket = (unsigned*)(cnt + nc);                // [1]
-    hipLaunchKernelGGL(count_kernel, dim3((unsigned)nc), dim3(256), 0, s, mask, n, cnt, ticket);
+    hipLaunchKernelGGL(count_kernel, dim3((unsigned)nc), dim3(256), 0, s, mask, n, cnt);
     hipLaunchKernelGGL(loss_kernel, dim3((unsigned)nl), dim3(256), 0, s, kd, cd, cs, ref, mask, n, w_light, cnt, nc,
-                       part, ticket, loss, g_kd, g_cd, g_cs);
+                       part, g_kd, g_cd, g_cs);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, part, nl, cnt, nc, w_light, loss);
     return hipGetLastError();
 }
 
