@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true", help="skip the short serving run of the default line")
     ap.add_argument("--denoise", action="store_true", help="cross-bilateral denoiser (sigma 2) inside the step")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the denoiser, loss and sampling-study measurements (profiling runs of the step's "
+                         "kernels: the study launches the traversal with other technique flags)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 512 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -202,7 +205,8 @@ def main():
     }
 
     STATE.update(scene=scene, env=envh, w=w)
-    result["next_rows"] = next_rows(args, M, gb, out[0], out[1], target, timed)
+    if not args.no_next_rows:
+        result["next_rows"] = next_rows(args, M, gb, out[0], out[1], target, timed)
     if not args.no_serve:
         result["serving"] = serve_quick(args, M, w, gb)
     if args.copy_calibration:
