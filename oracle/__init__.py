@@ -21,7 +21,7 @@ DEC_LOBE_COS, DEC_L_CULL, DEC_B_CULL = 1 << 0, 1 << 1, 1 << 2
 DEC_L_TRACED, DEC_B_TRACED, DEC_L_HIT, DEC_B_HIT = 1 << 3, 1 << 4, 1 << 5, 1 << 6
 DEC_NOV_POS, DEC_VALID = 1 << 7, 1 << 8
 DEC_NONE = 0xFFFFFFFF
-LIGHT_OFF, FORCE_COS, BSDF_OFF, FORCE_GGX = 1, 2, 4, 8
+LIGHT_OFF, FORCE_COS, BSDF_OFF, FORCE_GGX, BILINEAR = 1, 2, 4, 8, 16
 TRI_MISS, TRI_HIT, TRI_NEAR = 0, 1, 2
 
 
@@ -70,9 +70,9 @@ def lib():
                                 vp, vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int]
         L.orc_batch_philox.argtypes = [C.c_int64, vp, vp, vp]
         L.orc_batch_uniforms.argtypes = [C.c_int64, C.c_uint64, vp, vp, vp, vp]
-        L.orc_batch_sample_light.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+        L.orc_batch_sample_light.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_batch_pdf_light.argtypes = [vp, C.c_int64, vp, vp]
-        L.orc_batch_texel_of_dir.argtypes = [C.c_int, C.c_int, C.c_int64, vp, vp, vp, vp]
+        L.orc_batch_texel_of_dir.argtypes = [C.c_int, C.c_int, C.c_int64, vp, vp, vp, vp, vp, vp]
         L.orc_batch_pdf_ggx_local.argtypes = [C.c_int64, vp, C.c_double, vp, vp]
         L.orc_batch_pdf_cos_local.argtypes = [C.c_int64, vp, vp]
         L.orc_batch_sample_vndf_local.argtypes = [C.c_int64, vp, C.c_double, vp, vp, vp]
@@ -80,6 +80,7 @@ def lib():
         L.orc_batch_ggx.argtypes = [C.c_int64, vp, vp, vp, C.c_double, vp, vp]
         L.orc_batch_anyhit.argtypes = [vp, C.c_int64, vp, vp, C.c_double, C.c_double, C.c_int, vp]
         L.orc_integrand.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int64, vp, vp, vp]
+        L.orc_batch_probe_bilinear.argtypes = [vp, C.c_int, C.c_int, C.c_int64, vp, vp, vp]
         L.orc_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -129,13 +130,17 @@ class EnvTables:
         self.struct = Env(H, W, self.env.ctypes.data, self.cond.ctypes.data, self.marg.ctypes.data,
                           self.pdf.ctypes.data, self.light_enabled)
 
-    def sample(self, xi0, xi1):
+    def sample(self, xi0, xi1, coords=False):
+        """Light-technique samples: direction, density, texel (i, j) and,
+        with coords, the continuous texel coordinates (x, y) of the sample."""
         xi0, xi1 = _c(xi0, np.float64), _c(xi1, np.float64)
         n = len(xi0)
         w, p = np.empty((n, 3)), np.empty(n)
         ti, tj = np.empty(n, np.int32), np.empty(n, np.int32)
-        lib().orc_batch_sample_light(C.byref(self.struct), n, _p(xi0), _p(xi1), _p(w), _p(p), _p(ti), _p(tj))
-        return w, p, ti, tj
+        x, y = np.empty(n), np.empty(n)
+        lib().orc_batch_sample_light(C.byref(self.struct), n, _p(xi0), _p(xi1), _p(w), _p(p), _p(ti), _p(tj),
+                                     _p(x), _p(y))
+        return (w, p, ti, tj, x, y) if coords else (w, p, ti, tj)
 
     def pdf_dir(self, w):
         w = _c(w, np.float64).reshape(-1, 3)
@@ -143,12 +148,28 @@ class EnvTables:
         lib().orc_batch_pdf_light(C.byref(self.struct), len(w), _p(w), _p(p))
         return p
 
-    def texel_of_dir(self, w):
+    def texel_of_dir(self, w, coords=False):
+        """Nearest texel (i, j) of unit directions and the angular margin to
+        the closest texel boundary; with coords, also the continuous texel
+        coordinates (x, y) = (phi W / 2 pi, theta H / pi)."""
         w = _c(w, np.float64).reshape(-1, 3)
         n = len(w)
         ti, tj, m = np.empty(n, np.int32), np.empty(n, np.int32), np.empty(n)
-        lib().orc_batch_texel_of_dir(self.H, self.W, n, _p(w), _p(ti), _p(tj), _p(m))
-        return ti, tj, m
+        x, y = np.empty(n), np.empty(n)
+        lib().orc_batch_texel_of_dir(self.H, self.W, n, _p(w), _p(ti), _p(tj), _p(m), _p(x), _p(y))
+        return (ti, tj, m, x, y) if coords else (ti, tj, m)
+
+
+def probe_bilinear(env, x, y):
+    """Bilinear reconstruction of an [H, W, 3] probe at continuous texel
+    coordinates (x, y) = (phi W / 2 pi, theta H / pi); texel centres at
+    (j + 1/2, i + 1/2), columns wrap, rows clamp."""
+    env = _c(env, np.float32)
+    H, W = env.shape[:2]
+    x, y = _c(x, np.float64).reshape(-1), _c(y, np.float64).reshape(-1)
+    L = np.empty((len(x), 3))
+    lib().orc_batch_probe_bilinear(_p(env), H, W, len(x), _p(x), _p(y), _p(L))
+    return L
 
 
 def pdf_ggx_local(V, alpha, L):
@@ -287,15 +308,16 @@ def shade(w, pixels=None, scene=None, tables=None, spp=None, seed=None, tau=None
     return out
 
 
-def integrand(w, pixel, dirs, scene=None, tables=None, tau=None, ray_eps=None, brute=True):
-    """Direct-illumination integrand (g_d, g_s) of one pixel at unit directions."""
+def integrand(w, pixel, dirs, scene=None, tables=None, tau=None, ray_eps=None, brute=True, flags=0):
+    """Direct-illumination integrand (g_d, g_s) of one pixel at unit directions
+    (probe radiance by the nearest texel, or bilinear with BILINEAR in flags)."""
     scene = scene or Scene(w.verts, w.tris)
     tables = tables or EnvTables(w.env)
     arr = _gb_arrays(w)
     gs = _gbuf_struct(w, arr)
     tau = w.tau if tau is None else tau
     ray_eps = w.ray_eps if ray_eps is None else ray_eps
-    prm = Params(1, 0, 0, tau, ray_eps, 0.0, 0.0, 0.0, 0.0, int(brute))
+    prm = Params(1, flags & BILINEAR, 0, tau, ray_eps, 0.0, 0.0, 0.0, 0.0, int(brute))
     dirs = _c(dirs, np.float64).reshape(-1, 3)
     gd, gsp = np.empty((len(dirs), 3)), np.empty((len(dirs), 3))
     lib().orc_integrand(scene.ptr, C.byref(tables.struct), C.byref(gs), int(pixel), C.byref(prm),

@@ -171,10 +171,11 @@ static void dir_of_uv(double u, double v, double w[3])
     w[2] = sin(th) * sin(ph);
 }
 
-/* Sample the probe: returns texel (i, j), the direction and its solid-angle
- * density p = pdf_uv / (2 pi^2 sin theta). */
-void orc_sample_light(const orc_env* e, double xi0, double xi1, double w[3], double* p,
-                      int32_t* ti, int32_t* tj)
+/* Sample the probe: returns texel (i, j), the direction, its solid-angle
+ * density p = pdf_uv / (2 pi^2 sin theta) and the continuous texel
+ * coordinates (x, y) = (u W, v H) of the sample. */
+static void sample_light_xy(const orc_env* e, double xi0, double xi1, double w[3], double* p,
+                            int32_t* ti, int32_t* tj, double* x, double* y)
 {
     int H = e->H, W = e->W;
     int i = cdf_search(e->marg, H, xi0);
@@ -188,11 +189,21 @@ void orc_sample_light(const orc_env* e, double xi0, double xi1, double w[3], dou
     *p = st > 0.0 ? (double)e->pdf[(size_t)i * W + j] / (2.0 * ORC_PI * ORC_PI * st) : 0.0;
     *ti = i;
     *tj = j;
+    *x = (double)j + du;
+    *y = (double)i + dv;
+}
+
+void orc_sample_light(const orc_env* e, double xi0, double xi1, double w[3], double* p,
+                      int32_t* ti, int32_t* tj)
+{
+    double x, y;
+    sample_light_xy(e, xi0, xi1, w, p, ti, tj, &x, &y);
 }
 
 /* Texel of a unit direction (nearest lookup) and the angular distance, in
  * radians of arc, to the closest texel boundary that would change it. */
-static void texel_of_dir(int H, int W, const double w[3], int* ti, int* tj, double* margin)
+static void texel_of_dir_xy(int H, int W, const double w[3], int* ti, int* tj, double* margin,
+                            double* x, double* y)
 {
     double rho = sqrt(w[0] * w[0] + w[2] * w[2]);
     double th = atan2(rho, w[1]);
@@ -214,6 +225,81 @@ static void texel_of_dir(int H, int W, const double w[3], int* ti, int* tj, doub
     *ti = i;
     *tj = j;
     *margin = m;
+    if (x) *x = fj;
+    if (y) *y = fi;
+}
+
+static void texel_of_dir(int H, int W, const double w[3], int* ti, int* tj, double* margin)
+{
+    texel_of_dir_xy(H, W, w, ti, tj, margin, NULL, NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bilinear probe reconstruction.  Section 3.1 stores the probe as a float   */
+/* texture without naming the lookup filter; the default reading is the     */
+/* nearest texel, this is the filtered one.  The light technique keeps the  */
+/* piecewise-constant density of the texels either way (section 4.1).       */
+/* ------------------------------------------------------------------------ */
+
+/* Tent weight of integer tap k at coordinate s (texel centres at integers). */
+static double tent(double s, int k)
+{
+    double d = fabs(s - (double)k);
+    return d < 1.0 ? 1.0 - d : 0.0;
+}
+
+static int wrap_col(int j, int W) { j %= W; return j < 0 ? j + W : j; }
+static int clamp_row(int i, int H) { return i < 0 ? 0 : (i > H - 1 ? H - 1 : i); }
+
+static const float* texel_ptr(const float* env, int H, int W, int i, int j)
+{
+    return env + ((size_t)clamp_row(i, H) * W + wrap_col(j, W)) * 3;
+}
+
+/* Radiance at continuous texel coordinates (x, y) = (phi W / 2 pi, theta H /
+ * pi): texel (i, j) covers [j, j+1) x [i, i+1) and its value sits at the
+ * centre (j + 1/2, i + 1/2).  The reconstruction is the sum over texels of
+ * tent(x - 1/2, j) tent(y - 1/2, i) env[i][j], with columns wrapping across
+ * the phi = 0 seam and rows clamped at the poles; the weights sum to one. */
+void orc_probe_bilinear(const float* env, int H, int W, double x, double y, double L[3])
+{
+    double xs = x - 0.5, ys = y - 0.5;
+    int j0 = (int)floor(xs), i0 = (int)floor(ys);
+    for (int c = 0; c < 3; ++c) L[c] = 0.0;
+    for (int i = i0; i <= i0 + 1; ++i)
+        for (int j = j0; j <= j0 + 1; ++j) {
+            double wt = tent(ys, i) * tent(xs, j);
+            const float* e = texel_ptr(env, H, W, i, j);
+            for (int c = 0; c < 3; ++c) L[c] += wt * (double)e[c];
+        }
+}
+
+/* Bound, per channel, on how far the reconstruction can move when (x, y) move
+ * by at most (dx, dy): the largest neighbouring-texel difference along each
+ * axis in the 4x4 neighbourhood, times the displacement; beyond one texel,
+ * twice the largest magnitude in the rows the displacement can reach. */
+static void bilinear_shift_bound(const float* env, int H, int W, double x, double y, double dx,
+                                 double dy, double dL[3])
+{
+    int j0 = (int)floor(x - 0.5), i0 = (int)floor(y - 0.5);
+    for (int c = 0; c < 3; ++c) {
+        if (dx >= 1.0 || dy >= 1.0) {
+            int r = (int)ceil(dy) + 1;
+            double mx = 0.0;
+            for (int i = i0 - r; i <= i0 + 1 + r; ++i)
+                for (int j = 0; j < W; ++j) mx = fmax(mx, fabs((double)texel_ptr(env, H, W, i, j)[c]));
+            dL[c] = 2.0 * mx;
+            continue;
+        }
+        double sx = 0.0, sy = 0.0;
+        for (int i = i0 - 1; i <= i0 + 2; ++i)
+            for (int j = j0 - 1; j <= j0 + 2; ++j) {
+                double e = texel_ptr(env, H, W, i, j)[c];
+                sx = fmax(sx, fabs(e - (double)texel_ptr(env, H, W, i, j - 1)[c]));
+                sy = fmax(sy, fabs(e - (double)texel_ptr(env, H, W, i - 1, j)[c]));
+            }
+        dL[c] = dx * sx + dy * sy;
+    }
 }
 
 /* Solid-angle density of the light technique at a direction. */
@@ -652,6 +738,7 @@ typedef struct {
 #define ORC_FORCE_COS 2u  /* q = 1: the BSDF technique is pure cosine */
 #define ORC_BSDF_OFF 4u   /* no BSDF sample and no BSDF density in P: light sampling only */
 #define ORC_FORCE_GGX 8u  /* q = 0 where n.v > 0: the BSDF technique is pure GGX VNDF */
+#define ORC_BILINEAR 16u  /* probe radiance by the bilinear reconstruction instead of the nearest texel */
 
 /* decision record flag bits (shared meaning with the HIP debug dump) */
 #define DEC_LOBE_COS   (1u << 0)
@@ -748,12 +835,15 @@ typedef struct {
     double coef[3];
     double absc[3];
     double cond[3]; /* |term| * u / (n.l), u = 2^-24: FP32 conditioning in the cosine */
+    int bil;        /* bilinear: the coefficient spreads over the tent taps around (x, y) */
+    double x, y;    /* continuous texel coordinates of the sample */
+    double dx, dy;  /* bound on the FP32 error of (x, y), in texels */
 } env_contrib;
 
 /* Per-sample evaluation at direction w.  `Ss` drives sampling-side
  * quantities (P, q, ray origin); `Se` the differentiated integrand. */
 static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, const double w[3],
-                        double pL, const float* Lrad, int spp, double Hv, int grad,
+                        double pL, const double* Lv, const double* dLv, int spp, double Hv, int grad,
                         const double* Ud, const double* Us, pix_out* out, env_contrib* ec,
                         double bsdf_w, double e_scale, int unit_pdf)
 {
@@ -821,31 +911,38 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
             dSdNoH = dDdc * G2 / (4.0 * NoV);
         }
     }
+    /* every term is linear in the radiance L_c; its conditioning is the
+     * coefficient times |L_c| cu (direction roundoff through n.l and P) plus
+     * the bound dLv on the radiance's own FP32 error (bilinear coordinates) */
+    double Lc[3];
+    for (int c = 0; c < 3; ++c) Lc[c] = fabs(Lv[c]) * cu + dLv[c];
     for (int c = 0; c < 3; ++c) {
-        double L = (double)Lrad[c];
+        double L = Lv[c];
         out->cd[c] += kdiff * L;
         out->cs[c] += F[c] * S * L * K;
         /* a sampled direction carries an absolute FP32 error of a few ulp:
          * relative to n.l it is amplified where the sample grazes */
-        out->cd_cond[c] += fabs(kdiff * L) * cu;
-        out->cs_cond[c] += fabs(F[c] * S * L * K) * cu;
+        out->cd_cond[c] += fabs(kdiff) * Lc[c];
+        out->cs_cond[c] += fabs(F[c] * S * K) * Lc[c];
     }
     if (!grad) return;
-    double gnd = 0.0, gns = 0.0;
+    double gnd = 0.0, gns = 0.0, gnd_a = 0.0, gns_a = 0.0;
     for (int c = 0; c < 3; ++c) {
-        double L = (double)Lrad[c];
+        double L = Lv[c];
         double cdc = kdiff, csc = F[c] * S * K; /* coefficients of L_c */
-        const double tkd = Us[c] * Se->m * (1.0 - Fw) * S * L * K;
-        const double tm1 = Ud[c] * (-NoL / ORC_PI) * L * K, tm2 = Us[c] * (Se->kd[c] - 0.04) * (1.0 - Fw) * S * L * K;
-        const double tr = Us[c] * F[c] * L * K * dSdr;
-        out->gkd[c] += tkd;
-        out->gm += tm1 + tm2;
-        out->gr += tr;
-        out->gkd_cond[c] += fabs(tkd) * cu;
-        out->gm_cond += (fabs(tm1) + fabs(tm2)) * cu;
-        out->gr_cond += fabs(tr) * cu;
+        const double akd = Us[c] * Se->m * (1.0 - Fw) * S * K;
+        const double am1 = Ud[c] * (-NoL / ORC_PI) * K, am2 = Us[c] * (Se->kd[c] - 0.04) * (1.0 - Fw) * S * K;
+        const double ar = Us[c] * F[c] * K * dSdr;
+        out->gkd[c] += akd * L;
+        out->gm += am1 * L + am2 * L;
+        out->gr += ar * L;
+        out->gkd_cond[c] += fabs(akd) * Lc[c];
+        out->gm_cond += (fabs(am1) + fabs(am2)) * Lc[c];
+        out->gr_cond += fabs(ar) * Lc[c];
         gnd += Ud[c] * (1.0 - Se->m) / ORC_PI * L * K;
         gns += Us[c] * F[c] * L * K;
+        gnd_a += fabs(Ud[c] * (1.0 - Se->m) / ORC_PI * K) * Lc[c];
+        gns_a += fabs(Us[c] * F[c] * K) * Lc[c];
         ec->coef[c] = Ud[c] * cdc + Us[c] * csc;
         ec->absc[c] = fabs(Ud[c] * cdc) + fabs(Us[c] * csc);
         ec->cond[c] = ec->absc[c] * cu;
@@ -853,8 +950,8 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
     for (int k = 0; k < 3; ++k) {
         const double t = gnd * w[k] + gns * (dSdNoV * Se->V[k] + dSdNoL * w[k] + dSdNoH * h[k]);
         out->gn[k] += t;
-        out->gn_cond += (fabs(gnd * w[k]) + fabs(gns) * (fabs(dSdNoV * Se->V[k]) + fabs(dSdNoL * w[k]) +
-                                                         fabs(dSdNoH * h[k]))) * cu;
+        out->gn_cond += gnd_a * fabs(w[k]) +
+                        gns_a * (fabs(dSdNoV * Se->V[k]) + fabs(dSdNoL * w[k]) + fabs(dSdNoH * h[k]));
     }
 }
 
@@ -924,11 +1021,15 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
             double e_scale = 1.0;   /* direction-error scale against the 32u bound */
             int ti = -1, tj = -1;
             double tex_margin = INFINITY;
+            double bx = 0.0, by = 0.0, bdx = 0.0, bdy = 0.0; /* texel coordinates and error bounds */
             if (tech == 0) {
                 if (!light_on) continue;
                 int32_t a, b;
-                orc_sample_light(E, xi[0], xi[1], w, &pL, &a, &b);
+                sample_light_xy(E, xi[0], xi[1], w, &pL, &a, &b, &bx, &by);
                 ti = a; tj = b;
+                /* FP32: one quotient of table differences plus the integer part */
+                bdx = 2.0 * 0x1p-24 * (bx + 8.0);
+                bdy = 2.0 * 0x1p-24 * (by + 8.0);
                 rec0 = (uint32_t)(ti * E->W + tj);
                 if (gsr && gsr[0] != rec0) out->n_hard++;
                 if (!(pL > 0.0)) { rec2 |= DEC_L_CULL; continue; }
@@ -952,7 +1053,20 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                 for (int k = 0; k < 3; ++k) w[k] = loc[0] * Ss.t[k] + loc[1] * Ss.b[k] + loc[2] * Ss.n[k];
                 double wl = norm3(w);
                 for (int k = 0; k < 3; ++k) w[k] /= wl;
-                texel_of_dir(E->H, E->W, w, &ti, &tj, &tex_margin);
+                texel_of_dir_xy(E->H, E->W, w, &ti, &tj, &tex_margin, &bx, &by);
+                {
+                    /* FP32 error of the coordinates: the direction error
+                     * (32 u, scaled as for the visible-normal sample) through
+                     * theta and phi = atan2, plus the roundoff of atan2 and
+                     * of the scaling */
+                    const double u = 0x1p-24, dw = 32.0 * u * e_scale;
+                    const double rho = sqrt(w[0] * w[0] + w[2] * w[2]);
+                    bdy = (dw + 8.0 * u * ORC_PI) * (double)E->H / ORC_PI + 4.0 * u * by;
+                    bdx = (rho > 0.0 ? dw / rho : (double)E->W) * (double)E->W / (2.0 * ORC_PI) +
+                          16.0 * u * ORC_PI * (double)E->W / (2.0 * ORC_PI) + 4.0 * u * bx;
+                    bdx = fmin(bdx, (double)E->W);
+                    bdy = fmin(bdy, (double)E->H);
+                }
                 uint32_t mine = (uint32_t)(ti * E->W + tj);
                 if (gsr && gsr[1] != DEC_NONE && gsr[1] != mine) {
                     if (tex_margin < P->delta_ang) {
@@ -1000,10 +1114,23 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                     Hv = 1.0 - P->tau;
                 }
             }
-            const float* Lrad = envL + ((size_t)ti * E->W + tj) * 3;
+            double Lv[3], dLv[3] = {0.0, 0.0, 0.0};
+            const int bil = (P->flags & ORC_BILINEAR) != 0;
+            if (bil) {
+                orc_probe_bilinear(envL, E->H, E->W, bx, by, Lv);
+                bilinear_shift_bound(envL, E->H, E->W, bx, by, bdx, bdy, dLv);
+            } else {
+                const float* Lrad = envL + ((size_t)ti * E->W + tj) * 3;
+                for (int c = 0; c < 3; ++c) Lv[c] = (double)Lrad[c];
+            }
             env_contrib* ec = &ecs[2 * s + tech];
-            eval_sample(&Ss, &Se, qf, w, pL, Lrad, spp, Hv, grad, Ud, Us, out, ec, bsdf_on ? 1.0 : 0.0, e_scale, 0);
+            eval_sample(&Ss, &Se, qf, w, pL, Lv, dLv, spp, Hv, grad, Ud, Us, out, ec, bsdf_on ? 1.0 : 0.0, e_scale, 0);
             ec->texel = ti * E->W + tj;
+            ec->bil = bil;
+            ec->x = bx;
+            ec->y = by;
+            ec->dx = bdx;
+            ec->dy = bdy;
         }
         if (dq) { dq[s * 3] = rec0; dq[s * 3 + 1] = rec1; dq[s * 3 + 2] = rec2; }
     }
@@ -1013,6 +1140,30 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
         double nd = dot3(Se.n, out->gn);
         for (int k = 0; k < 3; ++k) out->gn[k] = (out->gn[k] - nd * Se.n[k]) / Se.nlen;
     }
+}
+
+/* Probe gradient of one bilinear sample: the coefficient of the radiance
+ * times each tap's tent weight.  The conditioning adds, for every tap an FP32
+ * error of (dx, dy) in the coordinates can reach, the coefficient times the
+ * bound on its weight's change (tent weights are 1-Lipschitz). */
+static void scatter_bilinear(const env_contrib* e, int H, int W, double* genv, double* senv, double* cenv)
+{
+    const double xs = e->x - 0.5, ys = e->y - 0.5;
+    const double ex = fmin(e->dx, 1.0), ey = fmin(e->dy, 1.0);
+    const int ja = (int)floor(xs - e->dx), jb = (int)floor(xs + e->dx) + 1;
+    const int ia = (int)floor(ys - e->dy), ib = (int)floor(ys + e->dy) + 1;
+    for (int i = ia; i <= ib; ++i)
+        for (int j = ja; j <= jb; ++j) {
+            const double tx = tent(xs, j), ty = tent(ys, i);
+            const double wt = tx * ty;
+            const double werr = ex * fmin(ty + ey, 1.0) + tx * ey;
+            const size_t t = (size_t)clamp_row(i, H) * W + wrap_col(j, W);
+            for (int c = 0; c < 3; ++c) {
+                genv[t * 3 + c] += e->coef[c] * wt;
+                if (senv) senv[t * 3 + c] += e->absc[c] * wt;
+                if (cenv) cenv[t * 3 + c] += e->cond[c] * wt + e->absc[c] * werr;
+            }
+        }
 }
 
 /* Forward (grad == 0) or backward (grad == 1) over a list of pixels.
@@ -1070,6 +1221,10 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
         /* fixed order: pixel list order, then sample, then technique */
         for (int64_t k = 0; k < npix * 2 * spp; ++k) {
             if (all[k].texel < 0) continue;
+            if (all[k].bil) {
+                scatter_bilinear(&all[k], env_s->H, env_s->W, genv, senv, cenv);
+                continue;
+            }
             for (int c = 0; c < 3; ++c) {
                 genv[(size_t)all[k].texel * 3 + c] += all[k].coef[c];
                 if (senv) senv[(size_t)all[k].texel * 3 + c] += all[k].absc[c];
@@ -1105,9 +1260,14 @@ void orc_batch_uniforms(int64_t n, uint64_t seed, const uint32_t* pix, const uin
 }
 
 void orc_batch_sample_light(const orc_env* e, int64_t n, const double* xi0, const double* xi1,
-                            double* w, double* p, int32_t* ti, int32_t* tj)
+                            double* w, double* p, int32_t* ti, int32_t* tj, double* x, double* y)
 {
-    for (int64_t i = 0; i < n; ++i) orc_sample_light(e, xi0[i], xi1[i], w + 3 * i, p + i, ti + i, tj + i);
+    for (int64_t i = 0; i < n; ++i) {
+        double a, b;
+        sample_light_xy(e, xi0[i], xi1[i], w + 3 * i, p + i, ti + i, tj + i, &a, &b);
+        if (x) x[i] = a;
+        if (y) y[i] = b;
+    }
 }
 
 void orc_batch_pdf_light(const orc_env* e, int64_t n, const double* w, double* p)
@@ -1116,14 +1276,20 @@ void orc_batch_pdf_light(const orc_env* e, int64_t n, const double* w, double* p
 }
 
 void orc_batch_texel_of_dir(int H, int W, int64_t n, const double* w, int32_t* ti, int32_t* tj,
-                            double* margin)
+                            double* margin, double* x, double* y)
 {
     for (int64_t i = 0; i < n; ++i) {
         int a, b;
-        texel_of_dir(H, W, w + 3 * i, &a, &b, margin + i);
+        texel_of_dir_xy(H, W, w + 3 * i, &a, &b, margin + i, x ? x + i : NULL, y ? y + i : NULL);
         ti[i] = a;
         tj[i] = b;
     }
+}
+
+void orc_batch_probe_bilinear(const float* env, int H, int W, int64_t n, const double* x, const double* y,
+                              double* L)
+{
+    for (int64_t i = 0; i < n; ++i) orc_probe_bilinear(env, H, W, x[i], y[i], L + 3 * i);
 }
 
 void orc_batch_pdf_ggx_local(int64_t n, const double* V, double alpha, const double* L, double* p)
@@ -1165,8 +1331,9 @@ void orc_batch_anyhit(const orc_scene* s, int64_t n, const double* o, const doub
 
 /* The integrand of the direct-illumination integral of one pixel at unit
  * directions w: g_d = (1-m)/pi (n.w) L(w) H(w) and g_s = F D G2/(4 n.v) L(w)
- * H(w), zero below the horizon, nearest-texel radiance, all-triangle
- * visibility (an undecided ray counts as hit).  Used by the quadrature pins. */
+ * H(w), zero below the horizon, nearest-texel radiance (bilinear with
+ * ORC_BILINEAR in the flags), all-triangle visibility (an undecided ray counts
+ * as hit).  Used by the quadrature pins. */
 void orc_integrand(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g, int64_t pix,
                    const orc_params* P, int64_t n, const double* w, double* gd, double* gs)
 {
@@ -1190,10 +1357,15 @@ void orc_integrand(const orc_scene* scene, const orc_env* E, const orc_gbuffer* 
             if (P->tau != 0.0 && orc_anyhit(scene, origin, wi, 0.0, 0.0, P->brute) != TRI_MISS)
                 Hv = 1.0 - P->tau;
             int ti, tj;
-            double m;
-            texel_of_dir(E->H, E->W, wi, &ti, &tj, &m);
-            eval_sample(&S, &S, 1.0f, wi, 0.0, E->env + ((size_t)ti * E->W + tj) * 3, 1, Hv, 0, NULL,
-                        NULL, &o, &ec, 1.0, 1.0, 1);
+            double m, x, y, Lv[3], dLv[3] = {0.0, 0.0, 0.0};
+            texel_of_dir_xy(E->H, E->W, wi, &ti, &tj, &m, &x, &y);
+            if (P->flags & ORC_BILINEAR) {
+                orc_probe_bilinear(E->env, E->H, E->W, x, y, Lv);
+            } else {
+                const float* Lrad = E->env + ((size_t)ti * E->W + tj) * 3;
+                for (int c = 0; c < 3; ++c) Lv[c] = (double)Lrad[c];
+            }
+            eval_sample(&S, &S, 1.0f, wi, 0.0, Lv, dLv, 1, Hv, 0, NULL, NULL, &o, &ec, 1.0, 1.0, 1);
         }
         for (int c = 0; c < 3; ++c) {
             gd[3 * i + c] = o.cd[c];

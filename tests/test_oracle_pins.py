@@ -281,19 +281,22 @@ def test_visibility_bvh_equals_brute_force():
 
 def test_visibility_closed_mesh_geometry():
     """Rays from outside a closed icosphere aimed inside its inscribed ball
-    hit; rays aimed away miss; rays from the centre always hit."""
+    hit; rays aimed away miss; rays from the centre always hit (a centre ray
+    that crosses the mesh within the tolerance of an edge is undecided)."""
+    rng = np.random.Generator(np.random.PCG64(282))
     v, f = meshes.icosphere(3)
     sc = oracle.Scene(v, f)
     n = 5000
-    dirs = RNG.normal(size=(n, 3))
+    dirs = rng.normal(size=(n, 3))
     dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
     o = 3.0 * dirs
-    tgt = RNG.normal(size=(n, 3))
-    tgt = 0.9 * tgt / np.linalg.norm(tgt, axis=1, keepdims=True) * RNG.random((n, 1))
+    tgt = rng.normal(size=(n, 3))
+    tgt = 0.9 * tgt / np.linalg.norm(tgt, axis=1, keepdims=True) * rng.random((n, 1))
     into = tgt - o
     assert np.all(sc.anyhit(o, into, 1e-6, 1e-6) == oracle.TRI_HIT)
     assert np.all(sc.anyhit(o, dirs, 1e-6, 1e-6) == oracle.TRI_MISS)
-    assert np.all(sc.anyhit(np.zeros((n, 3)), dirs, 1e-6, 1e-6) == oracle.TRI_HIT)
+    rc = sc.anyhit(np.zeros((n, 3)), dirs, 1e-6, 1e-6)
+    assert np.all(rc != oracle.TRI_MISS) and np.mean(rc == oracle.TRI_HIT) > 0.99
     # a ray through a shared vertex or edge is undecided, never a robust miss
     r = sc.anyhit(np.array([[0, 0, 0.0]]), v[:1] * 2.0, 1e-6, 1e-6)
     assert r[0] in (oracle.TRI_HIT, oracle.TRI_NEAR)
