@@ -147,6 +147,16 @@ typedef struct {
 #define MCDI_FLAG_FORCE_COS   (1u << 1) /* lobe probability q = 1 (cosine only) */
 #define MCDI_FLAG_BSDF_OFF    (1u << 2) /* no BSDF-technique sample; BSDF density not in the MIS sum */
 #define MCDI_FLAG_FORCE_GGX   (1u << 3) /* lobe probability q = 0 where n.v > 0 (GGX only) */
+/* Probe lookup filter (section 3.1 keeps the probe as a float texture and
+ * names no filter).  Default: the nearest texel.  BILINEAR: tent weights
+ * around texel centres (texel (i, j) centred at (j + 1/2, i + 1/2) in texel
+ * units x = phi W / 2 pi, y = theta H / pi), columns wrapping across phi = 0,
+ * rows clamped at the poles; a light sample is looked up at its own sampled
+ * coordinates.  The light technique keeps the per-texel density, and the
+ * probe gradient of a sample goes to its four taps.  Light-only sampling
+ * (BSDF_OFF) never reaches the radiance that filtering spreads into texels of
+ * zero sampling weight. */
+#define MCDI_FLAG_BILINEAR    (1u << 4)
 #define MCDI_FLAG_DUMP        (1u << 8) /* write per-sample decision records */
 #define MCDI_FLAG_TIME_TRACE  (1u << 9) /* bracket the traversal kernel with HIP events */
 

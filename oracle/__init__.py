@@ -67,7 +67,7 @@ def lib():
         L.orc_env_tables.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
         L.orc_shade.restype = C.c_int64
         L.orc_shade.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, vp, vp, C.c_int, vp, vp, vp, vp, vp,
-                                vp, vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int]
+                                vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int]
         L.orc_batch_philox.argtypes = [C.c_int64, vp, vp, vp]
         L.orc_batch_uniforms.argtypes = [C.c_int64, C.c_uint64, vp, vp, vp, vp]
         L.orc_batch_sample_light.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -288,13 +288,14 @@ def shade(w, pixels=None, scene=None, tables=None, spp=None, seed=None, tau=None
         us = _c(u_s, np.float64).reshape(3, n)
         out.update(g_kd=np.zeros((3, n)), g_korm=np.zeros((3, n)), g_nrm=np.zeros((3, n)),
                    g_env=np.zeros(tables.env.shape), s_env=np.zeros(tables.env.shape),
-                   c_env=np.zeros(tables.env.shape))
-    vcond = np.zeros((15, n))
+                   c_env=np.zeros(tables.env.shape), l_env=np.zeros(tables.env.shape))
+    vcond = np.zeros((30, n))
     r = L.orc_shade(scene.ptr, C.byref(tables.struct), _p(env_ev), C.byref(gs),
                     C.byref(ge) if ge is not None else None, _p(pixels), n, C.byref(prm),
                     _p(sync_arr), int(grad), _p(ud), _p(us), _p(out["c_d"]), _p(out["c_s"]), _p(vcond),
                     _p(out.get("g_kd")), _p(out.get("g_korm")), _p(out.get("g_nrm")),
-                    _p(out.get("g_env")), _p(out.get("s_env")), _p(out.get("c_env")), _p(out["hitbits"]), hw, _p(dec),
+                    _p(out.get("g_env")), _p(out.get("s_env")), _p(out.get("c_env")), _p(out.get("l_env")),
+                    _p(out["hitbits"]), hw, _p(dec),
                     _p(out["info"]), int(threads))
     if r < 0:
         raise ValueError("oracle rejected the parameters (spp must be in [1, 512])")
@@ -303,6 +304,10 @@ def shade(w, pixels=None, scene=None, tables=None, spp=None, seed=None, tau=None
     # the FP32 conditioning of each output in the sampled directions
     out["c_d_cond"], out["c_s_cond"] = vcond[0:3], vcond[3:6]
     out["g_kd_cond"], out["g_korm_cond"], out["g_nrm_cond"] = vcond[6:9], vcond[9:12], vcond[12:15]
+    # absolute bound on the FP32 error entering through the radiance lookup
+    # (bilinear coordinates and tap sums; zero for the nearest texel)
+    out["c_d_lerr"], out["c_s_lerr"] = vcond[15:18], vcond[18:21]
+    out["g_kd_lerr"], out["g_korm_lerr"], out["g_nrm_lerr"] = vcond[21:24], vcond[24:27], vcond[27:30]
     if dec is not None:
         out["decisions"] = dec
     return out

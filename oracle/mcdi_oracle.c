@@ -274,21 +274,39 @@ void orc_probe_bilinear(const float* env, int H, int W, double x, double y, doub
         }
 }
 
-/* Bound, per channel, on how far the reconstruction can move when (x, y) move
- * by at most (dx, dy): the largest neighbouring-texel difference along each
- * axis in the 4x4 neighbourhood, times the displacement; beyond one texel,
- * twice the largest magnitude in the rows the displacement can reach. */
+/* Bound, per channel, on how far an FP32 reconstruction can be from this one
+ * when (x, y) move by at most (dx, dy).  Inside one cell the reconstruction
+ * is bilinear in the offsets, so the change is exactly Lx ex + Ly ey + Lxy ex
+ * ey for offsets (ex, ey): bounded by |Lx| dx + |Ly| dy + |Lxy| dx dy.  Where
+ * the move can leave the cell, the largest neighbouring-texel difference in
+ * the 4x4 neighbourhood bounds the slope (beyond one texel: twice the largest
+ * magnitude in the rows the move can reach).  Plus the FP32 rounding of the
+ * tap weights and of the four-tap sum: a few units in the last place of the
+ * sum of the taps' magnitudes. */
 static void bilinear_shift_bound(const float* env, int H, int W, double x, double y, double dx,
                                  double dy, double dL[3])
 {
-    int j0 = (int)floor(x - 0.5), i0 = (int)floor(y - 0.5);
+    const double xs = x - 0.5, ys = y - 0.5;
+    const int j0 = (int)floor(xs), i0 = (int)floor(ys);
+    const double fx = xs - j0, fy = ys - i0;
+    const int inside = fx >= dx && fx + dx <= 1.0 && fy >= dy && fy + dy <= 1.0;
     for (int c = 0; c < 3; ++c) {
+        const double aa = texel_ptr(env, H, W, i0, j0)[c], ab = texel_ptr(env, H, W, i0, j0 + 1)[c];
+        const double ba = texel_ptr(env, H, W, i0 + 1, j0)[c], bb = texel_ptr(env, H, W, i0 + 1, j0 + 1)[c];
+        const double r = 8.0 * 0x1p-24 * (fabs(aa) + fabs(ab) + fabs(ba) + fabs(bb));
+        if (inside) {
+            const double Lx = (1.0 - fy) * (ab - aa) + fy * (bb - ba);
+            const double Ly = (1.0 - fx) * (ba - aa) + fx * (bb - ab);
+            const double Lxy = bb - ba - ab + aa;
+            dL[c] = fabs(Lx) * dx + fabs(Ly) * dy + fabs(Lxy) * dx * dy + r;
+            continue;
+        }
         if (dx >= 1.0 || dy >= 1.0) {
-            int r = (int)ceil(dy) + 1;
+            int rr = (int)ceil(dy) + 1;
             double mx = 0.0;
-            for (int i = i0 - r; i <= i0 + 1 + r; ++i)
+            for (int i = i0 - rr; i <= i0 + 1 + rr; ++i)
                 for (int j = 0; j < W; ++j) mx = fmax(mx, fabs((double)texel_ptr(env, H, W, i, j)[c]));
-            dL[c] = 2.0 * mx;
+            dL[c] = 2.0 * mx + r;
             continue;
         }
         double sx = 0.0, sy = 0.0;
@@ -298,7 +316,7 @@ static void bilinear_shift_bound(const float* env, int H, int W, double x, doubl
                 sx = fmax(sx, fabs(e - (double)texel_ptr(env, H, W, i, j - 1)[c]));
                 sy = fmax(sy, fabs(e - (double)texel_ptr(env, H, W, i - 1, j)[c]));
             }
-        dL[c] = dx * sx + dy * sy;
+        dL[c] = dx * sx + dy * sy + r;
     }
 }
 
@@ -825,6 +843,10 @@ typedef struct {
     double cd_cond[3], cs_cond[3]; /* sum |term| * u / (n.l): FP32 conditioning of the values */
     double gkd[3], gr, gm, gn[3];
     double gkd_cond[3], gr_cond, gm_cond, gn_cond; /* the same for the gradient terms */
+    /* absolute bound on the FP32 error that enters through the radiance
+     * lookup itself (bilinear coordinates and tap sums; 0 for the nearest
+     * texel), per output */
+    double cd_lerr[3], cs_lerr[3], gkd_lerr[3], gr_lerr, gm_lerr, gn_lerr;
     double nlen_cond;                              /* |n_raw|, for the normal's projection */
     uint32_t hitbits[32]; /* 2 bits per sample, spp <= 512 */
     int n_synced, n_flag, n_hard;
@@ -911,11 +933,12 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
             dSdNoH = dDdc * G2 / (4.0 * NoV);
         }
     }
-    /* every term is linear in the radiance L_c; its conditioning is the
-     * coefficient times |L_c| cu (direction roundoff through n.l and P) plus
-     * the bound dLv on the radiance's own FP32 error (bilinear coordinates) */
+    /* every term is linear in the radiance L_c: its conditioning is the
+     * coefficient times |L_c| cu (direction roundoff through n.l and P), and
+     * its lookup error the coefficient times the bound dLv on the radiance's
+     * own FP32 error */
     double Lc[3];
-    for (int c = 0; c < 3; ++c) Lc[c] = fabs(Lv[c]) * cu + dLv[c];
+    for (int c = 0; c < 3; ++c) Lc[c] = fabs(Lv[c]) * cu;
     for (int c = 0; c < 3; ++c) {
         double L = Lv[c];
         out->cd[c] += kdiff * L;
@@ -924,9 +947,11 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
          * relative to n.l it is amplified where the sample grazes */
         out->cd_cond[c] += fabs(kdiff) * Lc[c];
         out->cs_cond[c] += fabs(F[c] * S * K) * Lc[c];
+        out->cd_lerr[c] += fabs(kdiff) * dLv[c];
+        out->cs_lerr[c] += fabs(F[c] * S * K) * dLv[c];
     }
     if (!grad) return;
-    double gnd = 0.0, gns = 0.0, gnd_a = 0.0, gns_a = 0.0;
+    double gnd = 0.0, gns = 0.0, gnd_a = 0.0, gns_a = 0.0, gnd_e = 0.0, gns_e = 0.0;
     for (int c = 0; c < 3; ++c) {
         double L = Lv[c];
         double cdc = kdiff, csc = F[c] * S * K; /* coefficients of L_c */
@@ -939,10 +964,15 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
         out->gkd_cond[c] += fabs(akd) * Lc[c];
         out->gm_cond += (fabs(am1) + fabs(am2)) * Lc[c];
         out->gr_cond += fabs(ar) * Lc[c];
+        out->gkd_lerr[c] += fabs(akd) * dLv[c];
+        out->gm_lerr += (fabs(am1) + fabs(am2)) * dLv[c];
+        out->gr_lerr += fabs(ar) * dLv[c];
         gnd += Ud[c] * (1.0 - Se->m) / ORC_PI * L * K;
         gns += Us[c] * F[c] * L * K;
         gnd_a += fabs(Ud[c] * (1.0 - Se->m) / ORC_PI * K) * Lc[c];
         gns_a += fabs(Us[c] * F[c] * K) * Lc[c];
+        gnd_e += fabs(Ud[c] * (1.0 - Se->m) / ORC_PI * K) * dLv[c];
+        gns_e += fabs(Us[c] * F[c] * K) * dLv[c];
         ec->coef[c] = Ud[c] * cdc + Us[c] * csc;
         ec->absc[c] = fabs(Ud[c] * cdc) + fabs(Us[c] * csc);
         ec->cond[c] = ec->absc[c] * cu;
@@ -952,6 +982,8 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
         out->gn[k] += t;
         out->gn_cond += gnd_a * fabs(w[k]) +
                         gns_a * (fabs(dSdNoV * Se->V[k]) + fabs(dSdNoL * w[k]) + fabs(dSdNoH * h[k]));
+        out->gn_lerr += gnd_e * fabs(w[k]) +
+                        gns_e * (fabs(dSdNoV * Se->V[k]) + fabs(dSdNoL * w[k]) + fabs(dSdNoH * h[k]));
     }
 }
 
@@ -1056,10 +1088,10 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                 texel_of_dir_xy(E->H, E->W, w, &ti, &tj, &tex_margin, &bx, &by);
                 {
                     /* FP32 error of the coordinates: the direction error
-                     * (32 u, scaled as for the visible-normal sample) through
-                     * theta and phi = atan2, plus the roundoff of atan2 and
-                     * of the scaling */
-                    const double u = 0x1p-24, dw = 32.0 * u * e_scale;
+                     * (32 u, scaled as for the visible-normal sample, with a
+                     * factor 2 margin) through theta and phi = atan2, plus
+                     * the roundoff of atan2 and of the scaling */
+                    const double u = 0x1p-24, dw = 64.0 * u * e_scale;
                     const double rho = sqrt(w[0] * w[0] + w[2] * w[2]);
                     bdy = (dw + 8.0 * u * ORC_PI) * (double)E->H / ORC_PI + 4.0 * u * by;
                     bdx = (rho > 0.0 ? dw / rho : (double)E->W) * (double)E->W / (2.0 * ORC_PI) +
@@ -1143,10 +1175,11 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
 }
 
 /* Probe gradient of one bilinear sample: the coefficient of the radiance
- * times each tap's tent weight.  The conditioning adds, for every tap an FP32
- * error of (dx, dy) in the coordinates can reach, the coefficient times the
- * bound on its weight's change (tent weights are 1-Lipschitz). */
-static void scatter_bilinear(const env_contrib* e, int H, int W, double* genv, double* senv, double* cenv)
+ * times each tap's tent weight.  The lookup error (lenv) adds, for every tap
+ * an FP32 error of (dx, dy) in the coordinates can reach, the coefficient
+ * times the bound on its weight's change (tent weights are 1-Lipschitz). */
+static void scatter_bilinear(const env_contrib* e, int H, int W, double* genv, double* senv, double* cenv,
+                             double* lenv)
 {
     const double xs = e->x - 0.5, ys = e->y - 0.5;
     const double ex = fmin(e->dx, 1.0), ey = fmin(e->dy, 1.0);
@@ -1161,7 +1194,8 @@ static void scatter_bilinear(const env_contrib* e, int H, int W, double* genv, d
             for (int c = 0; c < 3; ++c) {
                 genv[t * 3 + c] += e->coef[c] * wt;
                 if (senv) senv[t * 3 + c] += e->absc[c] * wt;
-                if (cenv) cenv[t * 3 + c] += e->cond[c] * wt + e->absc[c] * werr;
+                if (cenv) cenv[t * 3 + c] += e->cond[c] * wt;
+                if (lenv) lenv[t * 3 + c] += e->absc[c] * werr;
             }
         }
 }
@@ -1174,7 +1208,7 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
                   const orc_params* prm, const uint32_t* sync, int grad, const double* Ud,
                   const double* Us, double* cd, double* cs, double* vcond, double* gkd, double* gkorm,
                   double* gn,
-                  double* genv, double* senv, double* cenv, uint32_t* hitbits, int32_t hit_words,
+                  double* genv, double* senv, double* cenv, double* lenv, uint32_t* hitbits, int32_t hit_words,
                   uint32_t* dec_out, int32_t* info, int nthreads)
 {
     shade_ctx C = {scene, env_s, env_eval, gs, ge, prm, sync, dec_out};
@@ -1203,6 +1237,11 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
                 vcond[(6 + c) * npix + q] = o.gkd_cond[c];
                 vcond[(9 + c) * npix + q] = c == 0 ? 0.0 : (c == 1 ? o.gr_cond : o.gm_cond);
                 vcond[(12 + c) * npix + q] = o.gn_cond / (o.nlen_cond > 0.0 ? o.nlen_cond : 1.0);
+                vcond[(15 + c) * npix + q] = o.cd_lerr[c];
+                vcond[(18 + c) * npix + q] = o.cs_lerr[c];
+                vcond[(21 + c) * npix + q] = o.gkd_lerr[c];
+                vcond[(24 + c) * npix + q] = c == 0 ? 0.0 : (c == 1 ? o.gr_lerr : o.gm_lerr);
+                vcond[(27 + c) * npix + q] = o.gn_lerr / (o.nlen_cond > 0.0 ? o.nlen_cond : 1.0);
             }
             if (grad) {
                 if (gkd) gkd[c * npix + q] = o.gkd[c];
@@ -1222,7 +1261,7 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
         for (int64_t k = 0; k < npix * 2 * spp; ++k) {
             if (all[k].texel < 0) continue;
             if (all[k].bil) {
-                scatter_bilinear(&all[k], env_s->H, env_s->W, genv, senv, cenv);
+                scatter_bilinear(&all[k], env_s->H, env_s->W, genv, senv, cenv, lenv);
                 continue;
             }
             for (int c = 0; c < 3; ++c) {

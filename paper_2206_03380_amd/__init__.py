@@ -11,7 +11,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib as L
-from ._lib import (MCDIError, FLAG_LIGHT_OFF, FLAG_FORCE_COS, FLAG_BSDF_OFF, FLAG_FORCE_GGX,  # noqa: F401
+from ._lib import (MCDIError, FLAG_LIGHT_OFF, FLAG_FORCE_COS, FLAG_BSDF_OFF, FLAG_FORCE_GGX, FLAG_BILINEAR,  # noqa: F401
                    FLAG_DUMP, FLAG_TIME_TRACE)
 
 __all__ = ["Scene", "Env", "GBuffer", "shade_fwd", "shade_bwd", "trace_anyhit", "MCDIShade",

@@ -16,6 +16,7 @@ FLAG_LIGHT_OFF = 1 << 0
 FLAG_FORCE_COS = 1 << 1
 FLAG_BSDF_OFF = 1 << 2
 FLAG_FORCE_GGX = 1 << 3
+FLAG_BILINEAR = 1 << 4
 FLAG_DUMP = 1 << 8
 FLAG_TIME_TRACE = 1 << 9
 

@@ -150,6 +150,7 @@ struct Sample {
     float3 w;      // world direction
     float pL;      // light-technique density
     int texel;     // probe texel index i*W + j
+    float x, y;    // continuous texel coordinates (phi W / 2 pi, theta H / pi)
 };
 
 struct FwdAcc {
@@ -173,8 +174,10 @@ __device__ __forceinline__ bool draw_light(const ShadeArgs& A, const Pixel& P, c
     const int j = cdf_find(crow, W, x1);
     const float m0 = s_marg[i], m1 = s_marg[i + 1];
     const float c0 = crow[j], c1 = crow[j + 1];
-    const float v = ((float)i + (x0 - m0) / (m1 - m0)) / (float)H;
-    const float u = ((float)j + (x1 - c0) / (c1 - c0)) / (float)W;
+    S.y = (float)i + (x0 - m0) / (m1 - m0);
+    S.x = (float)j + (x1 - c0) / (c1 - c0);
+    const float v = S.y / (float)H;
+    const float u = S.x / (float)W;
     float st, ct, sp, cp;
     sincospif(v, &st, &ct);
     sincospif(2.0f * u, &sp, &cp);
@@ -210,8 +213,10 @@ __device__ __forceinline__ void bsdf_texel(const ShadeArgs& A, bool light_on, Sa
     const float th = atan2f(rho, S.w.y);
     float ph = atan2f(S.w.z, S.w.x);
     if (ph < 0.0f) ph += 2.0f * kPi;
-    const int ti = min((int)(th * ((float)H * kInvPi)), H - 1);
-    const int tj = min((int)(ph * ((float)W * (0.5f * kInvPi))), W - 1);
+    S.y = th * ((float)H * kInvPi);
+    S.x = ph * ((float)W * (0.5f * kInvPi));
+    const int ti = min((int)S.y, H - 1);
+    const int tj = min((int)S.x, W - 1);
     S.texel = ti * W + tj;
     if (light_on && rho > 0.0f) S.pL = A.env.pdf[S.texel] / (2.0f * kPi * kPi * rho);
 }
@@ -223,7 +228,73 @@ struct RecSink {
     uint32_t* count;
 };
 
-template <bool BWD>
+// bilinear lookup: the four taps around (x, y) and their tent weights.
+// Texel centres sit at half-integers; columns wrap across phi = 0, rows clamp
+// at the poles.  Indices are clamped before use, so any coordinate (also a
+// non-finite one) stays inside the probe.
+struct Taps {
+    int t[4];
+    float w[4];
+};
+
+__device__ __forceinline__ Taps bilinear_taps(const EnvView& e, float x, float y) {
+    const int H = e.H, W = e.W;
+    const float xs = x - 0.5f, ys = y - 0.5f;
+    const float fj = floorf(xs), fi = floorf(ys);
+    const float fx = xs - fj, fy = ys - fi;
+    const int j0 = min(max((int)fj, -1), W - 1), i0 = min(max((int)fi, -1), H - 1);
+    const int ja = j0 < 0 ? W - 1 : j0;
+    const int jb = j0 + 1 >= W ? 0 : j0 + 1;
+    const int ia = max(i0, 0), ib = min(i0 + 1, H - 1);
+    Taps T;
+    T.t[0] = ia * W + ja;
+    T.t[1] = ia * W + jb;
+    T.t[2] = ib * W + ja;
+    T.t[3] = ib * W + jb;
+    T.w[0] = (1.0f - fx) * (1.0f - fy);
+    T.w[1] = fx * (1.0f - fy);
+    T.w[2] = (1.0f - fx) * fy;
+    T.w[3] = fx * fy;
+    return T;
+}
+
+__device__ __forceinline__ float3 texel_rgb(const EnvView& e, int t) {
+    const float* p = e.rgb + 3 * (size_t)t;
+    return f3(p[0], p[1], p[2]);
+}
+
+// probe-gradient contribution (v0, v1, v2) of one texel: hot texels go to
+// the workgroup's LDS copy, the rest to the tile's records (or straight to
+// global memory when there are none)
+__device__ __forceinline__ void scatter_texel(const ShadeArgs& A, int texel, float v0, float v1, float v2,
+                                              float* s_hot, const RecSink& rs) {
+    const int slot = A.env.hot_slot[texel];
+    if (slot >= 0) {
+        atomicAdd(s_hot + 3 * slot + 0, v0);
+        atomicAdd(s_hot + 3 * slot + 1, v1);
+        atomicAdd(s_hot + 3 * slot + 2, v2);
+    } else if (v0 == 0.0f && v1 == 0.0f && v2 == 0.0f) {
+        // nothing to add (a shadowed sample with tau = 1, a zero tap weight)
+    } else if (rs.base) {
+        // append to the tile's record region: one LDS counter atomic per
+        // wave; the region holds every record the tile can make
+        const uint64_t act = __ballot(1);
+        const int lane = (int)__lane_id();
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(rs.count, (uint32_t)__popcll(act));
+        base = (uint32_t)__shfl((int)base, leader);
+        const uint32_t at = base + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+        rs.base[at] = make_float4(__uint_as_float((uint32_t)texel), v0, v1, v2);
+    } else {
+        float* ge = A.g_env + 3 * (size_t)texel;
+        atomicAdd(ge + 0, v0);
+        atomicAdd(ge + 1, v1);
+        atomicAdd(ge + 2, v2);
+    }
+}
+
+template <bool BWD, bool BIL>
 __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, const Sample& S, float Hv,
                                             float invspp, FwdAcc& fa, BwdAcc& ba, float3 Ud, float3 Us,
                                             float* s_hot, const RecSink& rs) {
@@ -238,8 +309,14 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
     // balance heuristic over the techniques in use
     const float Pt = S.pL + P.bsdf_w * (P.q * pcos + (1.0f - P.q) * pggx);
     const float w = Hv / Pt;
-    const float* Lp = A.env.rgb + 3 * (size_t)S.texel;
-    const float3 L = f3(Lp[0], Lp[1], Lp[2]);
+    float3 L;
+    if (BIL) {
+        const Taps T = bilinear_taps(A.env, S.x, S.y);
+        L = T.w[0] * texel_rgb(A.env, T.t[0]) + T.w[1] * texel_rgb(A.env, T.t[1]) +
+            T.w[2] * texel_rgb(A.env, T.t[2]) + T.w[3] * texel_rgb(A.env, T.t[3]);
+    } else {
+        L = texel_rgb(A.env, S.texel);
+    }
     const float kdiff = (1.0f - P.m) * kInvPi * NoL;
     float S_ = 0.0f, Fw = 0.0f, G2 = 0.0f, lamL = 0.0f, t2L = 0.0f;
     float3 F = f3(0, 0, 0);
@@ -259,38 +336,21 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
         return;
     }
     const float K = w * invspp;
-    // probe texel gradient: coefficient of L_c; hot texels go to the
-    // workgroup's LDS copy, the rest straight to global memory
+    // probe texel gradient: the coefficient of L_c, times the tap weight
     const float cdc = kdiff * K, csc = S_ * K;
     if (A.g_env) {
         const float v0 = Ud.x * cdc + Us.x * F.x * csc;
         const float v1 = Ud.y * cdc + Us.y * F.y * csc;
         const float v2 = Ud.z * cdc + Us.z * F.z * csc;
-        const int slot = A.env.hot_slot[S.texel];
-        if (slot >= 0) {
-            atomicAdd(s_hot + 3 * slot + 0, v0);
-            atomicAdd(s_hot + 3 * slot + 1, v1);
-            atomicAdd(s_hot + 3 * slot + 2, v2);
+        if (BIL) {
+            // taps recomputed from the coordinates: cheaper than keeping
+            // them live across the BSDF terms
+            const Taps T = bilinear_taps(A.env, S.x, S.y);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                scatter_texel(A, T.t[k], T.w[k] * v0, T.w[k] * v1, T.w[k] * v2, s_hot, rs);
         } else {
-            if (v0 == 0.0f && v1 == 0.0f && v2 == 0.0f) {
-                // nothing to add (a shadowed sample with tau = 1)
-            } else if (rs.base) {
-                // append to the tile's record region: one LDS counter atomic
-                // per wave; the region holds every sample the tile can make
-                const uint64_t act = __ballot(1);
-                const int lane = (int)__lane_id();
-                const int leader = __ffsll((unsigned long long)act) - 1;
-                uint32_t base = 0;
-                if (lane == leader) base = atomicAdd(rs.count, (uint32_t)__popcll(act));
-                base = (uint32_t)__shfl((int)base, leader);
-                const uint32_t slot = base + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
-                rs.base[slot] = make_float4(__uint_as_float((uint32_t)S.texel), v0, v1, v2);
-            } else {
-                float* ge = A.g_env + 3 * (size_t)S.texel;
-                atomicAdd(ge + 0, v0);
-                atomicAdd(ge + 1, v1);
-                atomicAdd(ge + 2, v2);
-            }
+            scatter_texel(A, S.texel, v0, v1, v2, s_hot, rs);
         }
     }
     const float udL = Ud.x * L.x + Ud.y * L.y + Ud.z * L.z;
@@ -546,7 +606,9 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
 
 // 3) evaluation: forward values or the adjoint, from the hit bits.  For the
 //    adjoint, s_hot must be zeroed before and flushed after (hot_flush).
-template <bool BWD, bool DUMP>
+//    BIL: bilinear probe lookup (MCDI_FLAG_BILINEAR) instead of the nearest
+//    texel.
+template <bool BWD, bool DUMP, bool BIL>
 __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, const float* s_marg, float* s_hot,
                                            const RecSink& rs) {
     const int64_t N = A.g.n;
@@ -615,7 +677,7 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
                     rec2 |= tech ? kDecBHit : kDecLHit;
                 }
             }
-            eval_sample<BWD>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
+            eval_sample<BWD, BIL>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
         }
         if (DUMP) {
             uint32_t* d = A.decisions + ((size_t)pix * spp + s) * 3;
@@ -674,7 +736,7 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_
     trace_tile<COUNT>(A, blockIdx.x, tile_region(A, blockIdx.x), A.ray_count[blockIdx.x], hitbits, &s_next);
 }
 
-template <bool BWD, bool DUMP>
+template <bool BWD, bool DUMP, bool BIL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void shade_kernel(ShadeArgs A) {
     extern __shared__ float smem[];
     __shared__ uint32_t s_rec;
@@ -685,7 +747,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (threadIdx.x == 0) s_rec = 0u;
     __syncthreads();
     const RecSink rs{(BWD && A.rec) ? A.rec + (size_t)blockIdx.x * A.rec_region : nullptr, &s_rec};
-    shade_tile<BWD, DUMP>(A, blockIdx.x, s_marg, s_hot, rs);
+    shade_tile<BWD, DUMP, BIL>(A, blockIdx.x, s_marg, s_hot, rs);
     if (BWD) {
         __syncthreads();
         hot_flush(A, s_hot);
@@ -732,11 +794,14 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(const ServeItem* items, i
         __syncthreads();
         if (reg) trace_tile<false>(A, tile, reg, s_cnt, it.hitbits, &s_next);
         __syncthreads();
-        shade_tile<false, false>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
+        const bool bil = (A.flags & MCDI_FLAG_BILINEAR) != 0;
+        if (bil) shade_tile<false, false, true>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
+        else shade_tile<false, false, false>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
         if (A.g_cd) {
             hot_zero(s_hot);
             __syncthreads();
-            shade_tile<true, false>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
+            if (bil) shade_tile<true, false, true>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
+            else shade_tile<true, false, false>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
             __syncthreads();
             hot_flush(A, s_hot);
         }
@@ -777,10 +842,12 @@ hipError_t launch_trace_rays(const ShadeArgs& a, uint32_t* hitbits, hipStream_t 
 }
 
 hipError_t launch_shade_fwd(const ShadeArgs& a, hipStream_t s) {
-    if (a.flags & MCDI_FLAG_DUMP)
-        hipLaunchKernelGGL((shade_kernel<false, true>), dim3(n_blocks(a)), dim3(kBlock), marg_lds(a), s, a);
-    else
-        hipLaunchKernelGGL((shade_kernel<false, false>), dim3(n_blocks(a)), dim3(kBlock), marg_lds(a), s, a);
+    const bool dump = (a.flags & MCDI_FLAG_DUMP) != 0, bil = (a.flags & MCDI_FLAG_BILINEAR) != 0;
+    const dim3 g(n_blocks(a)), b(kBlock);
+    if (dump && bil) hipLaunchKernelGGL((shade_kernel<false, true, true>), g, b, marg_lds(a), s, a);
+    else if (dump) hipLaunchKernelGGL((shade_kernel<false, true, false>), g, b, marg_lds(a), s, a);
+    else if (bil) hipLaunchKernelGGL((shade_kernel<false, false, true>), g, b, marg_lds(a), s, a);
+    else hipLaunchKernelGGL((shade_kernel<false, false, false>), g, b, marg_lds(a), s, a);
     return hipGetLastError();
 }
 
@@ -795,7 +862,10 @@ hipError_t launch_serve(const ServeItem* items_dev, int n_items, int64_t total_t
 
 hipError_t launch_shade_bwd(const ShadeArgs& a, hipStream_t s) {
     const size_t lds = marg_lds(a) + sizeof(float) * 3 * kHotMax;
-    hipLaunchKernelGGL((shade_kernel<true, false>), dim3(n_blocks(a)), dim3(kBlock), lds, s, a);
+    if (a.flags & MCDI_FLAG_BILINEAR)
+        hipLaunchKernelGGL((shade_kernel<true, false, true>), dim3(n_blocks(a)), dim3(kBlock), lds, s, a);
+    else
+        hipLaunchKernelGGL((shade_kernel<true, false, false>), dim3(n_blocks(a)), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 

@@ -47,19 +47,34 @@ def hitbits_per_pixel(hb_planar):
 COND_K = 64
 
 
-def compare(gpu, orc, valid, rel=REL_TOL, absf=ABS_TOL, name="", cond=None):
+# The bilinear lookup adds an absolute bound of its own (`<name>_lerr`: the
+# FP32 error of the texel coordinates through the reconstruction's slope, and
+# the rounding of the tap sum), already a bound: the tolerance adds twice it.
+LERR_K = 2
+
+
+def compare(gpu, orc, valid, rel=REL_TOL, absf=ABS_TOL, name="", cond=None, lerr=None, med=None):
     """Return (ok, worst relative excess, report).  cond: the oracle's
-    per-element conditioning sum (same shape as orc), or None."""
+    per-element conditioning sum (same shape as orc), or None; lerr: its
+    absolute lookup-error bound, or None.  med: also require the median
+    relative error (over elements above 1% of the mean magnitude) to stay
+    below med, so that a tolerance widened for ill-conditioned elements
+    cannot hide a systematic error."""
     g = gpu[:, valid].astype(np.float64)
     o = orc[:, valid]
     scale = np.abs(o).mean(axis=1, keepdims=True)
     bound = rel * np.abs(o) + absf * scale
     if cond is not None:
         bound = bound + COND_K * cond[:, valid]
+    if lerr is not None:
+        bound = bound + LERR_K * lerr[:, valid]
     err = np.abs(g - o)
     ok = err <= bound
     worst = float((err / np.maximum(bound, 1e-300)).max()) if err.size else 0.0
-    rep = "%s: max|err|=%.3g, max rel=%.3g, fail=%d/%d, worst/bound=%.3g" % (
+    big = np.abs(o) > 1e-2 * scale
+    med_rel = float(np.median(err[big] / np.abs(o[big]))) if big.any() else 0.0
+    rep = "%s: max|err|=%.3g, max rel=%.3g, median rel=%.3g, fail=%d/%d, worst/bound=%.3g" % (
         name, err.max() if err.size else 0, (err / np.maximum(np.abs(o), 1e-30)).max() if err.size else 0,
-        int((~ok).sum()), ok.size, worst)
-    return bool(ok.all()), worst, rep
+        med_rel, int((~ok).sum()), ok.size, worst)
+    good = bool(ok.all()) and (med is None or med_rel <= med)
+    return good, worst, rep

@@ -24,7 +24,7 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _fwd_parity(w, min_valid_frac=0.99, pixels=None, **kw):
+def _fwd_parity(w, min_valid_frac=0.99, pixels=None, med=None, **kw):
     _need_gpu()
     g, handles = gpu_forward(w, **kw)
     pix = np.arange(w.n_pixels) if pixels is None else np.asarray(pixels)
@@ -37,7 +37,8 @@ def _fwd_parity(w, min_valid_frac=0.99, pixels=None, **kw):
     valid = (w.mask[pix] > 0) & ~flagged
     assert valid.sum() >= min_valid_frac * (w.mask[pix] > 0).sum()
     for key in ("c_d", "c_s"):
-        ok, worst, rep = compare(g[key][:, pix], o[key], valid, name=key, cond=o[key + "_cond"])
+        ok, worst, rep = compare(g[key][:, pix], o[key], valid, name=key, cond=o[key + "_cond"],
+                                 lerr=o[key + "_lerr"], med=med)
         print(rep)
         assert ok, rep
     # hit masks: equal wherever the oracle did not adopt a kernel decision
@@ -52,7 +53,8 @@ def _oracle_flags(f):
     import paper_2206_03380_amd as M
     out = 0
     for mine, theirs in ((M.FLAG_LIGHT_OFF, oracle.LIGHT_OFF), (M.FLAG_FORCE_COS, oracle.FORCE_COS),
-                         (M.FLAG_BSDF_OFF, oracle.BSDF_OFF), (M.FLAG_FORCE_GGX, oracle.FORCE_GGX)):
+                         (M.FLAG_BSDF_OFF, oracle.BSDF_OFF), (M.FLAG_FORCE_GGX, oracle.FORCE_GGX),
+                         (M.FLAG_BILINEAR, oracle.BILINEAR)):
         if f & mine:
             out |= theirs
     return out
@@ -239,7 +241,7 @@ def test_fwd_deterministic_and_linear():
 # ---------------------------------------------------------------------------
 # backward parity
 # ---------------------------------------------------------------------------
-def _bwd_parity(w, use_hitbits=True, flags=0):
+def _bwd_parity(w, use_hitbits=True, flags=0, med=None):
     _need_gpu()
     import paper_2206_03380_amd as M
     g, (scene, env, gb, hb) = gpu_forward(w, flags=flags)
@@ -254,7 +256,8 @@ def _bwd_parity(w, use_hitbits=True, flags=0):
     assert info[:, 2].sum() == 0
     valid = (w.mask > 0) & (info[:, 1] == 0)
     for gpu_t, key in ((g_kd, "g_kd"), (g_korm, "g_korm"), (g_nrm, "g_nrm")):
-        ok, worst, rep = compare(to_np(gpu_t), o[key], valid, rel=1e-3, absf=1e-5, name=key, cond=o[key + "_cond"])
+        ok, worst, rep = compare(to_np(gpu_t), o[key], valid, rel=1e-3, absf=1e-5, name=key, cond=o[key + "_cond"],
+                                 lerr=o[key + "_lerr"], med=med)
         print(rep)
         assert ok, rep
     # env: an n-term FP32 sum in any order is within gamma_n * sum|terms|
@@ -264,18 +267,21 @@ def _bwd_parity(w, use_hitbits=True, flags=0):
     # factor 2 margin), times the term's log-derivative in n.l (<= 2):
     # 64 u |term| / n.l.
     # The oracle accumulates c_env = sum |term| u / n.l per texel.
-    n_t = env_term_counts(o["decisions"], w.mask, w.env.shape[:2])
+    n_t = env_term_counts(o["decisions"], w.mask, w.env.shape[:2], bilinear=bool(flags & M.FLAG_BILINEAR))
     ge = to_np(g_env).astype(np.float64)
     err = np.abs(ge - o["g_env"])
     S = o["s_env"]
-    bound = (2e-5 + n_t[..., None] * 2.0 ** -24) * S + 64 * o["c_env"] + 1e-9 * S.max()
+    bound = (2e-5 + n_t[..., None] * 2.0 ** -24) * S + 64 * o["c_env"] + 2 * o["l_env"] + 1e-9 * S.max()
     print("g_env: max err %.3g, worst/bound %.3g, max terms/texel %d" % (
         err.max(), (err / np.maximum(bound, 1e-300)).max(), n_t.max()))
     assert np.all(err <= bound)
 
 
-def env_term_counts(dec, mask, hw):
-    """Number of probe-gradient terms per texel, from the oracle's own decisions."""
+def env_term_counts(dec, mask, hw, bilinear=False):
+    """Number of probe-gradient terms per texel, from the oracle's own
+    decisions.  With the bilinear lookup a sample's taps lie in the 3x3
+    neighbourhood of its nearest texel (columns wrap, rows clamp): the count
+    of a texel is then bounded by the sum over its neighbourhood."""
     H, W = hw
     cnt = np.zeros(H * W, np.int64)
     d = dec[mask > 0]
@@ -284,7 +290,12 @@ def env_term_counts(dec, mask, hw):
         t = d[..., col]
         ok = (t != oracle.DEC_NONE) & ((fl & cull) == 0)
         cnt += np.bincount(t[ok].astype(np.int64), minlength=H * W)
-    return cnt.reshape(H, W)
+    cnt = cnt.reshape(H, W)
+    if bilinear:
+        p = np.pad(cnt, ((1, 1), (0, 0)), mode="edge")
+        rows = p[:-2] + p[1:-1] + p[2:]
+        cnt = rows + np.roll(rows, 1, axis=1) + np.roll(rows, -1, axis=1)
+    return cnt
 
 
 def test_bwd_parity_tiny():
@@ -298,6 +309,51 @@ def test_bwd_parity_tiny_retrace():
 @pytest.mark.parametrize("tech", ["light", "cosine", "ggx"])
 def test_bwd_parity_tiny_techniques(tech):
     _bwd_parity(make_workload("tiny"), flags=_technique(tech))
+
+
+# The bilinear lookup's tolerance is widened per element by the FP32 error of
+# the texel coordinates through the probe's slope (`_lerr`); the median
+# relative error must still be at the FP32 level of the nearest lookup.
+BIL_MED = 2e-5
+
+
+@pytest.mark.parametrize("tech", ["mis", "light", "bsdf"])
+def test_fwd_parity_tiny_bilinear(tech):
+    import paper_2206_03380_amd as M
+    _fwd_parity(make_workload("tiny"), flags=_technique(tech) | M.FLAG_BILINEAR, med=BIL_MED)
+
+
+def test_fwd_parity_sphere8_bilinear():
+    # 512x256 probe with a sun of 1000x: large differences between taps
+    import paper_2206_03380_amd as M
+    _fwd_parity(make_workload("sphere8", H=60, W=52, n_views=2), flags=M.FLAG_BILINEAR, med=BIL_MED)
+
+
+@pytest.mark.parametrize("tech", ["mis", "ggx"])
+def test_bwd_parity_tiny_bilinear(tech):
+    import paper_2206_03380_amd as M
+    _bwd_parity(make_workload("tiny"), flags=_technique(tech) | M.FLAG_BILINEAR, med=10 * BIL_MED)
+
+
+def test_bwd_parity_sphere8_bilinear():
+    import paper_2206_03380_amd as M
+    _bwd_parity(make_workload("sphere8_grad", H=64, W=64, n_views=1), flags=M.FLAG_BILINEAR, med=10 * BIL_MED)
+
+
+def test_bilinear_differs_and_is_linear():
+    """Same samples and visibility as the nearest lookup, different values;
+    linear in the probe bit for bit."""
+    _need_gpu()
+    import paper_2206_03380_amd as M
+    w = make_workload("tiny")
+    a, _ = gpu_forward(w, dump=False)
+    b, _ = gpu_forward(w, dump=False, flags=M.FLAG_BILINEAR)
+    assert np.array_equal(a["hitbits"], b["hitbits"])
+    assert np.abs(a["c_d"] - b["c_d"]).sum() > 0.05 * np.abs(a["c_d"]).sum()
+    w2 = make_workload("tiny")
+    w2.env = w2.env * np.float32(2)
+    c, _ = gpu_forward(w2, dump=False, flags=M.FLAG_BILINEAR)
+    assert np.array_equal(2 * b["c_d"], c["c_d"]) and np.array_equal(2 * b["c_s"], c["c_s"])
 
 
 def test_technique_flag_combinations_rejected():

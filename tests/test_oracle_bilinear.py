@@ -182,11 +182,12 @@ def test_bilinear_mc_converges_to_quadrature(tech):
 
 
 def _grad_setup():
+    rng = np.random.Generator(np.random.PCG64(2207))
     w = make_workload("tiny")
     valid = np.nonzero((w.mask > 0) & (w.korm[1] > 0.12))[0]
-    pix = RNG.choice(valid, 64, replace=False)
+    pix = rng.choice(valid, 64, replace=False)
     n = len(pix)
-    return w, pix, RNG.normal(size=(3, n)), RNG.normal(size=(3, n))
+    return w, pix, rng.normal(size=(3, n)), rng.normal(size=(3, n))
 
 
 def _loss(o, Ud, Us):
