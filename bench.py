@@ -242,7 +242,8 @@ def sampling_study(args, M, gb, timed, seeds=4):
     import torch
     sc, envh, w = STATE["scene"], STATE["env"], STATE["w"]
     techs = {"mis": 0, "bsdf": M.FLAG_LIGHT_OFF, "light": M.FLAG_BSDF_OFF,
-             "cosine": M.FLAG_LIGHT_OFF | M.FLAG_FORCE_COS, "ggx": M.FLAG_LIGHT_OFF | M.FLAG_FORCE_GGX}
+             "cosine": M.FLAG_LIGHT_OFF | M.FLAG_FORCE_COS, "ggx": M.FLAG_LIGHT_OFF | M.FLAG_FORCE_GGX,
+             "mis_bilinear": M.FLAG_BILINEAR}
     m = gb.mask.bool()
     res = {}
     for name, f in techs.items():
@@ -259,7 +260,20 @@ def sampling_study(args, M, gb, timed, seeds=4):
     ref = res["mis"]["rel_var"] * res["mis"]["fwd_ms"]
     for name in res:
         res[name]["efficiency_vs_mis"] = ref / (res[name]["rel_var"] * res[name]["fwd_ms"])
-    return {"spp": w.spp, "seeds": seeds, "techniques": res}
+    # the backward pass with either lookup (the bilinear one scatters each
+    # sample's probe gradient to four texels)
+    n = gb.n
+    g_cd = torch.randn((3, n), device=gb.kd.device) * m / max(int(m.sum()), 1)
+    g_cs = torch.randn((3, n), device=gb.kd.device) * m / max(int(m.sum()), 1)
+    bwd = {}
+    for name, f in (("nearest", 0), ("bilinear", M.FLAG_BILINEAR)):
+        hb = M.shade_fwd(sc, envh, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps, flags=f)[2]
+        g_env = torch.zeros_like(envh.env)
+        bo = tuple(torch.empty_like(g_cd) for _ in range(3))
+        bwd[name] = timed(lambda: M.shade_bwd(sc, envh, gb, w.spp, g_cd, g_cs, hitbits=hb, seed=w.seed, tau=w.tau,
+                                              ray_eps=w.ray_eps, flags=f, g_env=g_env, out=bo),
+                          max(3, args.kernel_reps // 2))
+    return {"spp": w.spp, "seeds": seeds, "techniques": res, "bwd_ms": bwd}
 
 
 STATE = {}

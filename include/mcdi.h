@@ -76,7 +76,8 @@ typedef struct {
  * replaced by a degenerate triangle that no ray hits (counted in
  * mcdi_scene_info).  n_tris = 0 gives a scene every ray misses.
  * verts/tris are read during the call's stream work only; the handle keeps no
- * reference to them.  Limits: n_verts < 2^31, n_tris < 2^27.
+ * reference to them.  Limits: n_verts < 2^31, n_tris < 2^26 (node and triangle
+ * byte offsets stay 32-bit).
  * ------------------------------------------------------------------------- */
 mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                              const mcdi_allocator* alloc, void* stream, mcdi_scene* out);

@@ -152,7 +152,7 @@ mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t*
     if (!out) return fail(MCDI_E_INVALID, "mcdi_build_scene: out is NULL");
     if (n_verts < 0 || n_tris < 0) return fail(MCDI_E_INVALID, "mcdi_build_scene: negative count");
     if (n_verts >= (int64_t)1 << 31) return fail(MCDI_E_UNSUPPORTED, "mcdi_build_scene: n_verts >= 2^31");
-    if (n_tris >= (int64_t)1 << 27) return fail(MCDI_E_UNSUPPORTED, "mcdi_build_scene: n_tris >= 2^27");
+    if (n_tris >= (int64_t)1 << 26) return fail(MCDI_E_UNSUPPORTED, "mcdi_build_scene: n_tris >= 2^26");
     if (n_tris > 0 && (!verts || !tris)) return fail(MCDI_E_INVALID, "mcdi_build_scene: NULL verts/tris");
     if (n_tris > 0 && n_verts == 0) return fail(MCDI_E_INVALID, "mcdi_build_scene: triangles without vertices");
     if (alloc && (!alloc->alloc || !alloc->free)) return fail(MCDI_E_INVALID, "mcdi_build_scene: allocator incomplete");
@@ -321,12 +321,14 @@ static mcdi_status trace_pipeline(const char* who, mcdi_scene sc, ShadeArgs& a, 
     const size_t sz_bits = hitbits ? 0 : al(sizeof(uint32_t) * words * (size_t)n);
     ws.alloc = &sc->alloc;
     ws.s = s;
-    ws.base = sc->alloc.get(sz_rays + sz_cnt + sz_org + sz_bits, s);
+    ws.base = sc->alloc.get(sz_rays + 2 * sz_cnt + sz_org + sz_bits, s);
     if (!ws.base) return fail(MCDI_E_OOM, "%s: workspace allocation failed", who);
     char* p = (char*)ws.base;
     a.rays = sz_rays ? (float4*)p : nullptr;
     p += sz_rays;
     a.ray_count = (int32_t*)p;
+    p += sz_cnt;
+    a.tile_order = (int32_t*)p;
     p += sz_cnt;
     a.origins = (float4*)p;
     p += sz_org;
@@ -335,6 +337,8 @@ static mcdi_status trace_pipeline(const char* who, mcdi_scene sc, ShadeArgs& a, 
     ShadeArgs g = a;
     if (!g.rays) g.tau = 0.0f;
     hipError_t e = launch_gen_rays(g, bits, s);
+    // tiles with the most rays are traversed first
+    if (e == hipSuccess && a.tau != 0.0f) e = launch_order_tiles(a.ray_count, blocks, a.tile_order, s);
     std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
     if ((a.flags & MCDI_FLAG_TIME_TRACE) && e == hipSuccess && a.tau != 0.0f) {
         ev = g_timer.next();

@@ -82,6 +82,7 @@ struct ShadeArgs {
     // forward ray queue (one region of 2*spp*kBlock rays per workgroup)
     float4* rays;          // (direction, local pixel | slot << 8)
     int32_t* ray_count;    // [blocks]
+    int32_t* tile_order;   // [blocks] traversal order of the tiles (most rays first), or NULL
     float4* origins;       // [N]
     // adjoint: probe-gradient records (texel bits, 3 values) of non-hot
     // texels, one region of rec_region records per tile and a record count
@@ -109,6 +110,7 @@ hipError_t launch_env_hot(const float* pdf, int H, int W, int32_t* hot_slot, int
 // forward = gen_rays -> trace_rays -> shade; hit bits are produced by the
 // first two and read by the third
 hipError_t launch_gen_rays(const ShadeArgs& a, uint32_t* hitbits, hipStream_t s);
+hipError_t launch_order_tiles(const int32_t* ray_count, int64_t n_tiles, int32_t* order, hipStream_t s);
 hipError_t launch_trace_rays(const ShadeArgs& a, uint32_t* hitbits, hipStream_t s);
 hipError_t launch_shade_fwd(const ShadeArgs& a, hipStream_t s);
 hipError_t launch_shade_bwd(const ShadeArgs& a, hipStream_t s);

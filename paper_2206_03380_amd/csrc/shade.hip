@@ -476,6 +476,13 @@ __device__ __forceinline__ void gen_tile(const ShadeArgs& A, int64_t tile, float
 //    take the next one from the region (one LDS atomic per wave per refill);
 //    box steps and triangle steps run in separate phases so a wave keeps its
 //    lanes on the same code (while-while traversal with dynamic fetch).
+//
+//    Per lane: the next node to test (n_total once the walk is over, or when
+//    the lane holds no ray) and up to two postponed leaves, kept as their
+//    packed payload words (first_triangle << 3 | count; 0 = none).  Testing
+//    one triangle of a leaf advances its word by 7: the first index grows by
+//    one and the count drops by one.  The second slot is only used while the
+//    first is pending.
 template <bool COUNT>
 __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, const float4* R, int count,
                                            uint32_t* hitbits, int* s_next) {
@@ -483,15 +490,15 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
     const int64_t N = A.g.n;
     const int64_t base_pix = tile * kBlock;
     const int n_total = sc.nodes[0].escape;
-    const float4* nodes = reinterpret_cast<const float4*>(sc.nodes);
+    const uint32_t n_tris = (uint32_t)sc.n_tris;
+    const char* node_bytes = reinterpret_cast<const char*>(sc.nodes);
+    const char* tri_bytes = reinterpret_cast<const char*>(sc.tris);
     const int lane = __lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool active = false, exhausted = false;
     Ray ray;
-    int node = 0;
-    // up to two postponed leaves: triangles [t0, e0), then [t1, e1); the
-    // second slot is only used while the first is pending
-    int t0 = 0, e0 = 0, t1 = 0, e1 = 0;
+    int node = n_total;
+    uint32_t p0 = 0u, p1 = 0u;
     int64_t pix = 0;
     int slot = 0;
     uint32_t c_hits = 0, c_box = 0, c_tri = 0, c_bstep = 0, c_tstep = 0;   // steps: lane 0 only
@@ -517,7 +524,7 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
                     const float4 o = A.origins[pix];
                     ray = make_ray(f3(o.x, o.y, o.z), f3(rr.x, rr.y, rr.z));
                     node = 0;
-                    t0 = e0 = t1 = e1 = 0;
+                    p0 = p1 = 0u;
                     active = n_total > 0;
                 } else {
                     exhausted = true;
@@ -533,64 +540,65 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
         // to the second); the phase ends once the lanes that hold a leaf and
         // cannot walk are at least as many as the lanes still walking
         while (true) {
-            if (!__any(active && node < n_total && t1 >= e1)) break;
+            if (!__any(node < n_total && p1 == 0u)) break;
 #pragma unroll
             for (int step = 0; step < kBoxSteps; ++step) {
-                const bool walking = active && node < n_total && t1 >= e1;
+                const bool walking = node < n_total && p1 == 0u;
                 if (COUNT && __any(walking) && lane == 0) ++c_bstep;
                 if (walking) {
-                    const float4 a = nodes[2 * node];
-                    const float4 b = nodes[2 * node + 1];
-                    const int escape = __float_as_int(a.w);
-                    const int payload = __float_as_int(b.w);
-                    const int next = escape > node ? escape : n_total;
+                    const uint32_t off = (uint32_t)node * 32u;
+                    const float4 a = *reinterpret_cast<const float4*>(node_bytes + off);
+                    const float4 b = *reinterpret_cast<const float4*>(node_bytes + off + 16u);
+                    const uint32_t payload = __float_as_uint(b.w);
                     if (COUNT) ++c_box;
                     const bool hit = box_hit(ray, a, b);
-                    const bool leaf = payload != 0;
-                    node = (hit && !leaf) ? node + 1 : next;
-                    if (hit && leaf) {
-                        const int first = payload >> 3;
-                        const int end = first + ((first + (payload & 7) <= sc.n_tris) ? (payload & 7) : 0);
-                        if (t0 < e0) {
-                            t1 = first;
-                            e1 = end;
-                        } else {
-                            t0 = first;
-                            e0 = end;
-                        }
-                    }
+                    // skip links point forward; max() keeps every walk finite
+                    const int next = max(__float_as_int(a.w), node + 1);
+                    node = (hit && payload == 0u) ? node + 1 : next;
+                    const bool take = hit && payload != 0u;
+                    const bool first_free = p0 == 0u;
+                    p0 = (take && first_free) ? payload : p0;
+                    p1 = (take && !first_free) ? payload : p1;
                 }
             }
-            const bool walk = active && node < n_total && t1 >= e1;
-            const bool stuck = active && t0 < e0 && !walk;
+            const bool walk = node < n_total && p1 == 0u;
+            const bool stuck = p0 != 0u && !walk;
             if (2 * __popcll(__ballot(stuck)) >= kBoxSwitch2 * __popcll(__ballot(walk))) break;
         }
         // triangle phase: one triangle of the first pending leaf per lane and
         // step; it ends when no leaf is pending, or when lanes that could walk
         // but hold no leaf outnumber the lanes testing
         while (true) {
-            const bool test = active && t0 < e0;
+            const bool test = p0 != 0u;
             if (!__any(test)) break;
             if (COUNT && lane == 0) ++c_tstep;
             if (test) {
-                const float4* t = sc.tris + 3 * t0;
-                if (COUNT) ++c_tri;
-                if (tri_anyhit(ray, t[0], t[1], t[2])) {
+                const uint32_t t = p0 >> 3;
+                bool h = false;
+                if (t < n_tris) {       // a payload past the triangle array tests nothing
+                    const float4* tv = reinterpret_cast<const float4*>(tri_bytes + t * 48u);
+                    if (COUNT) ++c_tri;
+                    h = tri_anyhit(ray, tv[0], tv[1], tv[2]);
+                }
+                if (h) {
                     atomicOr(hitbits + (int64_t)(slot >> 5) * N + pix, 1u << (slot & 31));
                     ++c_hits;
                     active = false;
-                    t0 = e0 = t1 = e1 = 0;
-                } else if (++t0 >= e0) {
-                    t0 = t1;
-                    e0 = e1;
-                    t1 = e1 = 0;
+                    node = n_total;
+                    p0 = p1 = 0u;
+                } else {
+                    p0 += 7u;
+                    if ((p0 & 7u) == 0u) {
+                        p0 = p1;
+                        p1 = 0u;
+                    }
                 }
             }
-            const bool testing = active && t0 < e0;
-            const bool idle = active && !testing && node < n_total;
+            const bool testing = p0 != 0u;
+            const bool idle = !testing && node < n_total;
             if (2 * __popcll(__ballot(idle)) > kTriSwitch2 * __popcll(__ballot(testing))) break;
         }
-        if (active && t0 >= e0 && node >= n_total) active = false;  // miss
+        if (active && p0 == 0u && node >= n_total) active = false;  // miss
     }
     if (COUNT) {
         const uint32_t h = wave_sum(c_hits), bx = wave_sum(c_box), tr = wave_sum(c_tri);
@@ -728,12 +736,47 @@ __global__ __launch_bounds__(kBlock) void gen_rays_kernel(ShadeArgs A, uint32_t*
     if (threadIdx.x == 0) A.ray_count[blockIdx.x] = s_cnt;
 }
 
+// Traversal order of the tiles: a counting sort by ray count, most rays
+// first, so that the longest workgroups start first and the short ones fill
+// the end of the launch (longest-processing-time-first).  One workgroup;
+// counts are bucketed by 8 rays (beyond 8184 rays a tile is just "long").
+// The order of tiles within a bucket is arbitrary: traversal results do not
+// depend on it.
+constexpr int kOrderBuckets = 1024;
+
+__global__ __launch_bounds__(1024) void order_tiles_kernel(const int32_t* __restrict__ cnt, int64_t n,
+                                                           int32_t* __restrict__ order) {
+    __shared__ int h[kOrderBuckets];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    auto bucket = [](int c) { return kOrderBuckets - 1 - min(max(c, 0) >> 3, kOrderBuckets - 1); };
+    for (int64_t t = tid; t < n; t += 1024) atomicAdd(&h[bucket(cnt[t])], 1);
+    __syncthreads();
+    // exclusive scan over the buckets (bucket 0 = the most rays)
+    int v = h[tid];
+    for (int off = 1; off < kOrderBuckets; off <<= 1) {
+        const int a = tid >= off ? h[tid - off] : 0;
+        __syncthreads();
+        h[tid] += a;
+        __syncthreads();
+    }
+    h[tid] -= v;
+    __syncthreads();
+    for (int64_t t = tid; t < n; t += 1024) {
+        const int pos = atomicAdd(&h[bucket(cnt[t])], 1);
+        order[pos] = (int32_t)t;
+    }
+}
+
 template <bool COUNT>
 __global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_t* hitbits) {
     __shared__ int s_next;
+    const int64_t tile = A.tile_order ? A.tile_order[blockIdx.x] : blockIdx.x;
+    if (tile < 0 || tile >= (int64_t)gridDim.x) return;   // uniform: the whole workgroup reads the same entry
     if (threadIdx.x == 0) s_next = 0;
     __syncthreads();
-    trace_tile<COUNT>(A, blockIdx.x, tile_region(A, blockIdx.x), A.ray_count[blockIdx.x], hitbits, &s_next);
+    trace_tile<COUNT>(A, tile, tile_region(A, tile), A.ray_count[tile], hitbits, &s_next);
 }
 
 template <bool BWD, bool DUMP, bool BIL>
@@ -830,6 +873,11 @@ hipError_t launch_gen_rays(const ShadeArgs& a, uint32_t* hitbits, hipStream_t s)
         hipLaunchKernelGGL((gen_rays_kernel<true>), dim3(n_blocks(a)), dim3(kBlock), marg_lds(a), s, a, hitbits);
     else
         hipLaunchKernelGGL((gen_rays_kernel<false>), dim3(n_blocks(a)), dim3(kBlock), marg_lds(a), s, a, hitbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_order_tiles(const int32_t* ray_count, int64_t n_tiles, int32_t* order, hipStream_t s) {
+    hipLaunchKernelGGL(order_tiles_kernel, dim3(1), dim3(1024), 0, s, ray_count, n_tiles, order);
     return hipGetLastError();
 }
 

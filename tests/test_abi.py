@@ -49,6 +49,7 @@ def test_validation_without_device():
     assert b"mcdi_build_scene" in lib.mcdi_last_error()
     assert lib.mcdi_build_scene(None, -1, None, 0, None, None, ctypes.byref(out)) == L.MCDI_E_INVALID
     assert lib.mcdi_build_scene(None, 0, None, 1 << 27, None, None, ctypes.byref(out)) == L.MCDI_E_UNSUPPORTED
+    assert lib.mcdi_build_scene(None, 0, None, 1 << 26, None, None, ctypes.byref(out)) == L.MCDI_E_UNSUPPORTED
     assert lib.mcdi_build_env_cdf(None, 4, 4, None, None, ctypes.byref(out)) == L.MCDI_E_INVALID
     assert lib.mcdi_build_env_cdf(ctypes.c_void_p(16), 5000, 4, None, None, ctypes.byref(out)) == L.MCDI_E_UNSUPPORTED
     assert lib.mcdi_build_env_cdf(ctypes.c_void_p(16), 0, 4, None, None, ctypes.byref(out)) == L.MCDI_E_INVALID
