@@ -97,6 +97,18 @@ typedef struct {
 /* Synchronises the scene's stream and reports build statistics. */
 mcdi_status mcdi_scene_info(mcdi_scene scene, mcdi_scene_info_t* info);
 
+/* Copies the scene's BVH, for inspection and tests, into caller device
+ * buffers (either may be NULL), in stream order:
+ *   nodes  n_nodes x 8 words (mcdi_scene_info), depth-first pre-order:
+ *          float lo[3], int32 escape, float hi[3], int32 payload.  escape is
+ *          the index just past the node's subtree (node 0: the node count);
+ *          payload 0 = internal node (first child at index + 1), else
+ *          (first_triangle << 3) | count (1..4) of a leaf;
+ *   tris   n_tris x 12 floats: the triangles in leaf order, three vertices
+ *          of (x, y, z, 0).
+ * Byte counts: 32 n_nodes and 48 n_tris. */
+mcdi_status mcdi_scene_nodes(mcdi_scene scene, void* nodes, float* tris, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Environment probe sampling tables (section 4.1: light importance sampling
  * with a piecewise-constant 2D distribution; rebuilt every optimisation

@@ -76,6 +76,18 @@ class Scene:
         L.check(L.lib().mcdi_scene_info(self.handle, C.byref(i)))
         return {"n_tris": i.n_tris, "n_nodes": i.n_nodes, "max_depth": i.max_depth, "bad_tris": i.bad_tris}
 
+    def nodes(self, stream=None):
+        """The BVH as device tensors: nodes int32 [n_nodes, 8] (lo xyz and hi
+        xyz as float bits, escape at column 3, payload at column 7) and the
+        triangles in leaf order, float32 [n_tris, 3, 4]."""
+        n = self.info()["n_nodes"]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        nodes = torch.empty((max(n, 0), 8), dtype=torch.int32, device=dev)
+        tris = torch.empty((self.n_tris, 3, 4), dtype=torch.float32, device=dev)
+        L.check(L.lib().mcdi_scene_nodes(self.handle, _ptr(nodes) if n > 0 else None,
+                                         _ptr(tris) if self.n_tris > 0 else None, _stream(stream)))
+        return nodes, tris
+
     def close(self):
         if getattr(self, "handle", None):
             L.lib().mcdi_destroy_scene(self.handle)

@@ -86,6 +86,8 @@ def lib():
     L.mcdi_destroy_scene.restype = None
     L.mcdi_scene_info.argtypes = [vp, C.POINTER(SceneInfo)]
     L.mcdi_scene_info.restype = C.c_int
+    L.mcdi_scene_nodes.argtypes = [vp, vp, vp, vp]
+    L.mcdi_scene_nodes.restype = C.c_int
     L.mcdi_build_env_cdf.restype = C.c_int
     L.mcdi_build_env_cdf.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(vp)]
     L.mcdi_destroy_env.argtypes = [vp]
@@ -128,7 +130,7 @@ def check(status):
         raise MCDIError(status, lib().mcdi_last_error().decode())
 
 
-EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_build_env_cdf",
+EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_scene_nodes", "mcdi_build_env_cdf",
             "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
             "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_server_create", "mcdi_server_launch",
             "mcdi_server_destroy", "mcdi_image_loss", "mcdi_bilateral_radius", "mcdi_bilateral_fwd",

@@ -204,6 +204,20 @@ mcdi_status mcdi_scene_info(mcdi_scene sc, mcdi_scene_info_t* info) {
     return ok();
 }
 
+mcdi_status mcdi_scene_nodes(mcdi_scene sc, void* nodes, float* tris, void* stream) {
+    if (!sc) return fail(MCDI_E_INVALID, "mcdi_scene_nodes: NULL scene");
+    hipStream_t s = (hipStream_t)stream;
+    DeviceSceneInfo h{};
+    hipError_t e = hipStreamSynchronize(sc->stream);
+    if (e == hipSuccess) e = hipMemcpy(&h, sc->info, sizeof(h), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && nodes && h.n_nodes > 0)
+        e = hipMemcpyAsync(nodes, sc->nodes, sizeof(Node) * (size_t)h.n_nodes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && tris && sc->n_tris > 0)
+        e = hipMemcpyAsync(tris, sc->tris, sizeof(float4) * 3 * (size_t)sc->n_tris, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_scene_nodes: %s", hipGetErrorString(e));
+    return ok();
+}
+
 mcdi_status mcdi_build_env_cdf(const float* env_rgb, int32_t H, int32_t W, const mcdi_allocator* alloc,
                                void* stream, mcdi_env* out) {
     if (!out) return fail(MCDI_E_INVALID, "mcdi_build_env_cdf: out is NULL");

@@ -3,10 +3,21 @@
 //
 // Linear BVH: 63-bit Morton codes of triangle centroids, a radix sort, the
 // binary radix tree of the sorted codes built in parallel (one lane per
-// internal node, Karras 2012), a bottom-up pass that fits boxes and counts
-// the nodes that survive collapsing subtrees of <= 4 triangles into leaves,
-// and a final pass that writes every surviving node at its depth-first
-// pre-order index with a skip link, so traversal needs no stack.
+// internal node, Karras 2012), box fitting and the counts of the nodes that
+// survive collapsing subtrees of <= 4 triangles into leaves, and a final pass
+// that writes every surviving node at its depth-first pre-order index with a
+// skip link, so traversal needs no stack.
+//
+// Fitting runs in two parts over blocks of 256 sorted triangles.  Nodes whose
+// triangles lie in one block are fitted bottom-up inside that block's
+// workgroup (workgroup-scope atomics pick the second child to arrive).  A
+// node spanning blocks is fitted directly: its box is the union of a suffix
+// box of its first block, a prefix box of its last block and a sparse-table
+// query over the whole blocks between (min and max are idempotent, so two
+// overlapping power-of-two ranges cover the span), and its surviving-node
+// count is 2 L - 1 for the L leaves in its range, read from a prefix sum of
+// leaf marks (every surviving internal node has two surviving children).  No
+// dependency chain crosses workgroups.
 #include <hip/hip_runtime.h>
 #include <cstring>
 #include <rocprim/device/device_radix_sort.hpp>
@@ -22,11 +33,6 @@ __device__ __forceinline__ int ord_key(float f) {
 }
 __device__ __forceinline__ float ord_val(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7FFFFFFF); }
 
-__global__ void init_bounds(int* b) {
-    if (threadIdx.x < 3) b[threadIdx.x] = 0x7FFFFFFF;        // min keys
-    else if (threadIdx.x < 6) b[threadIdx.x] = (int)0x80000000;  // max keys
-}
-
 __device__ __forceinline__ float wave_min(float v) {
     for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
     return v;
@@ -36,9 +42,13 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-// fetch vertices, replace bad triangles by a degenerate one, centroid bounds
+constexpr int kFitBlock = 256;   // triangles per fitting block (= workgroup size of the block passes)
+
+// fetch vertices, replace bad triangles by a degenerate one; centroid bounds
+// of the workgroup's triangles to part[6 * blockIdx.x] (min xyz, max xyz)
 __global__ __launch_bounds__(256) void tri_prep(const float* verts, int64_t nv, const int32_t* tris, int64_t nt,
-                                                float4* tmp, int* cb, DeviceSceneInfo* info) {
+                                                float4* tmp, float* part, DeviceSceneInfo* info) {
+    __shared__ float sb[4][6];
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float cx = INFINITY, cy = INFINITY, cz = INFINITY, Cx = -INFINITY, Cy = -INFINITY, Cz = -INFINITY;
     if (f < nt) {
@@ -64,9 +74,37 @@ __global__ __launch_bounds__(256) void tri_prep(const float* verts, int64_t nv, 
     }
     cx = wave_min(cx); cy = wave_min(cy); cz = wave_min(cz);
     Cx = wave_max(Cx); Cy = wave_max(Cy); Cz = wave_max(Cz);
-    if ((threadIdx.x & 63) == 0 && cx <= Cx) {
-        atomicMin(cb + 0, ord_key(cx)); atomicMin(cb + 1, ord_key(cy)); atomicMin(cb + 2, ord_key(cz));
-        atomicMax(cb + 3, ord_key(Cx)); atomicMax(cb + 4, ord_key(Cy)); atomicMax(cb + 5, ord_key(Cz));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sb[w][0] = cx; sb[w][1] = cy; sb[w][2] = cz;
+        sb[w][3] = Cx; sb[w][4] = Cy; sb[w][5] = Cz;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        float v = sb[0][k];
+        for (int j = 1; j < 4; ++j) v = k < 3 ? fminf(v, sb[j][k]) : fmaxf(v, sb[j][k]);
+        part[6 * (size_t)blockIdx.x + k] = v;
+    }
+}
+
+// scene centroid bounds from the per-workgroup parts, as order-preserving
+// integer keys (one workgroup)
+__global__ __launch_bounds__(256) void bounds_reduce(const float* part, int nb, int* cb) {
+    __shared__ float sb[4][6];
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nb; b += 256)
+        for (int k = 0; k < 6; ++k) v[k] = k < 3 ? fminf(v[k], part[6 * (size_t)b + k]) : fmaxf(v[k], part[6 * (size_t)b + k]);
+    for (int k = 0; k < 3; ++k) { v[k] = wave_min(v[k]); v[3 + k] = wave_max(v[3 + k]); }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 6; ++k) sb[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        float r = sb[0][k];
+        for (int j = 1; j < 4; ++j) r = k < 3 ? fminf(r, sb[j][k]) : fmaxf(r, sb[j][k]);
+        cb[k] = ord_key(r);
     }
 }
 
@@ -109,6 +147,14 @@ struct Tree {
     int32_t* flag;     // [nt-1]
     int32_t* cnt;      // [2nt-1] surviving nodes in the subtree
     float4* box;       // [2*(2nt-1)]
+    // block fitting (blocks of kFitBlock sorted triangles)
+    int32_t* mark;     // [nt] 1 at the first triangle of every leaf
+    int32_t* mark_pre; // [nt] exclusive prefix of mark within the block
+    int32_t* blk_base; // [nb+1] leaf marks before each block
+    float4* pre;       // [2nt] box of the block's triangles up to k (inclusive)
+    float4* suf;       // [2nt] box of the block's triangles from k to the block end
+    float4* st;        // [levels][nb][2] sparse table of block boxes
+    int nb, levels;
 };
 
 __device__ __forceinline__ int prefix_len(const uint64_t* keys, int nt, int a, int b) {
@@ -171,53 +217,171 @@ __device__ __forceinline__ void fit_node(int p, int nt, const Tree& T) {
     T.cnt[p] = size <= kLeafMax ? 1 : 1 + T.cnt[l] + T.cnt[r];
 }
 
-// Bottom-up refit, first phase: workgroup b fits the leaves of sorted
-// positions [256 b, 256 b + 256) and every internal node whose range lies
-// inside them, the second of the two children to arrive fitting the parent.
-// All of that happens inside one workgroup, so workgroup-scope atomics order
-// it (an agent-scope release would write the L2 back on every step).  A climb
-// that reaches a node spanning workgroups stops there and records the child
-// it finished.
-__global__ __launch_bounds__(256) void refit_local(const float4* tmp, const uint32_t* vals, int nt, Tree T,
-                                                   int* top_list, int* top_count) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nt) return;
-    const int lo = blockIdx.x * blockDim.x, hi = min(nt, lo + (int)blockDim.x) - 1;
-    const int leaf = nt - 1 + k;
-    float4 blo, bhi;
-    tri_box(tmp + 3 * (size_t)vals[k], blo, bhi);
-    T.box[2 * leaf] = blo;
-    T.box[2 * leaf + 1] = bhi;
-    T.cnt[leaf] = 1;
-    int c = leaf;
-    int p = T.parent[leaf];
-    for (int guard = 0; p >= 0 && p < nt - 1 && guard < 4096; ++guard) {
-        if (T.first[p] < lo || T.last[p] > hi) {
-            top_list[atomicAdd(top_count, 1)] = c;
-            return;
+// leaf marks: a node of <= kLeafMax triangles whose parent has more is a
+// leaf of the collapsed tree (the root, when the whole mesh fits in one)
+__global__ __launch_bounds__(256) void mark_leaves(int nt, Tree T) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= 2 * nt - 1) return;
+    const bool prim = x >= nt - 1;
+    const int first = prim ? x - (nt - 1) : T.first[x];
+    const int size = prim ? 1 : T.last[x] - first + 1;
+    if (size > kLeafMax) return;
+    if (x != 0) {
+        const int p = T.parent[x];
+        if (p < 0 || p >= nt - 1 || T.last[p] - T.first[p] + 1 <= kLeafMax) return;
+    }
+    if (first >= 0 && first < nt) T.mark[first] = 1;
+}
+
+// Block pass (workgroup b = sorted triangles [256 b, 256 b + 256)): leaf
+// boxes, the block's prefix and suffix boxes and leaf-mark prefix, its box
+// (sparse-table level 0) and mark count; then the bottom-up fit of every node
+// inside the block, the second of the two children to arrive fitting the
+// parent.  That climb stays inside one workgroup, so workgroup-scope atomics
+// order it (an agent-scope release would write the L2 back on every step); it
+// stops at the first node spanning blocks.
+__global__ __launch_bounds__(kFitBlock) void fit_block(const float4* tmp, const uint32_t* vals, int nt, Tree T) {
+    __shared__ float4 slo[kFitBlock], shi[kFitBlock];
+    __shared__ int sm[kFitBlock];
+    const int t = threadIdx.x;
+    const int lo = blockIdx.x * kFitBlock;
+    const int hi = min(nt, lo + kFitBlock) - 1;
+    const int k = lo + t;
+    const bool valid = k <= hi;
+    float4 blo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f), bhi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    int m = 0;
+    if (valid) {
+        tri_box(tmp + 3 * (size_t)vals[k], blo, bhi);
+        const int leaf = nt - 1 + k;
+        T.box[2 * leaf] = blo;
+        T.box[2 * leaf + 1] = bhi;
+        T.cnt[leaf] = 1;
+        m = T.mark[k];
+    }
+    // inclusive prefix (Hillis-Steele) of boxes and marks
+    slo[t] = blo; shi[t] = bhi; sm[t] = m;
+    __syncthreads();
+    for (int o = 1; o < kFitBlock; o <<= 1) {
+        float4 al = slo[t], ah = shi[t];
+        int am = sm[t];
+        if (t >= o) {
+            const float4 bl = slo[t - o], bh = shi[t - o];
+            al = make_float4(fminf(al.x, bl.x), fminf(al.y, bl.y), fminf(al.z, bl.z), 0.0f);
+            ah = make_float4(fmaxf(ah.x, bh.x), fmaxf(ah.y, bh.y), fmaxf(ah.z, bh.z), 0.0f);
+            am += sm[t - o];
         }
+        __syncthreads();
+        slo[t] = al; shi[t] = ah; sm[t] = am;
+        __syncthreads();
+    }
+    if (valid) {
+        T.pre[2 * k] = slo[t];
+        T.pre[2 * k + 1] = shi[t];
+        T.mark_pre[k] = sm[t] - m;
+    }
+    if (k == hi) {
+        T.st[2 * blockIdx.x] = slo[t];
+        T.st[2 * blockIdx.x + 1] = shi[t];
+        T.blk_base[blockIdx.x] = sm[t];   // the block's mark count (scanned by block_table)
+    }
+    __syncthreads();
+    // suffix: the same scan from the block end
+    slo[t] = blo; shi[t] = bhi;
+    __syncthreads();
+    for (int o = 1; o < kFitBlock; o <<= 1) {
+        float4 al = slo[t], ah = shi[t];
+        if (t + o < kFitBlock) {
+            const float4 bl = slo[t + o], bh = shi[t + o];
+            al = make_float4(fminf(al.x, bl.x), fminf(al.y, bl.y), fminf(al.z, bl.z), 0.0f);
+            ah = make_float4(fmaxf(ah.x, bh.x), fmaxf(ah.y, bh.y), fmaxf(ah.z, bh.z), 0.0f);
+        }
+        __syncthreads();
+        slo[t] = al; shi[t] = ah;
+        __syncthreads();
+    }
+    if (valid) {
+        T.suf[2 * k] = slo[t];
+        T.suf[2 * k + 1] = shi[t];
+    }
+    if (!valid) return;
+    int p = T.parent[nt - 1 + k];
+    for (int guard = 0; p >= 0 && p < nt - 1 && guard < 4096; ++guard) {
+        if (T.first[p] < lo || T.last[p] > hi) return;   // spans blocks: fit_top
         const int old = __hip_atomic_fetch_add(&T.flag[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (old == 0) return;
         fit_node(p, nt, T);
-        c = p;
         p = T.parent[p];
     }
 }
 
-// Second phase, one workgroup: the nodes spanning workgroups (ancestors of
-// the recorded children), with the first phase's results visible across the
-// launch boundary.
-__global__ __launch_bounds__(1024) void refit_top(const int* top_list, const int* top_count, int nt, Tree T) {
-    const int m = *top_count;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        int p = T.parent[top_list[i]];
-        for (int guard = 0; p >= 0 && p < nt - 1 && guard < 4096; ++guard) {
-            const int old = __hip_atomic_fetch_add(&T.flag[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old == 0) break;
-            fit_node(p, nt, T);
-            p = T.parent[p];
+// One workgroup: exclusive scan of the block mark counts (blk_base, with the
+// total at nb) and the sparse table over block boxes, level j holding the box
+// of blocks [b, b + 2^j) (clamped at the last block).
+__global__ __launch_bounds__(1024) void block_table(Tree T) {
+    __shared__ int s[1024];
+    const int t = threadIdx.x, nb = T.nb;
+    int carry = 0;
+    for (int c0 = 0; c0 < nb; c0 += 1024) {
+        const int b = c0 + t;
+        const int v = b < nb ? T.blk_base[b] : 0;
+        s[t] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int a = t >= o ? s[t - o] : 0;
+            __syncthreads();
+            s[t] += a;
+            __syncthreads();
         }
+        if (b < nb) T.blk_base[b] = carry + s[t] - v;
+        const int tot = s[1023];
+        __syncthreads();
+        carry += tot;
     }
+    if (t == 0) T.blk_base[nb] = carry;
+    for (int j = 1; j < T.levels; ++j) {
+        const float4* prev = T.st + 2 * (size_t)(j - 1) * nb;
+        float4* cur = T.st + 2 * (size_t)j * nb;
+        const int h = 1 << (j - 1);
+        for (int b = t; b < nb; b += 1024) {
+            const int b2 = min(b + h, nb - 1);
+            const float4 al = prev[2 * b], ah = prev[2 * b + 1], bl = prev[2 * b2], bh = prev[2 * b2 + 1];
+            cur[2 * b] = make_float4(fminf(al.x, bl.x), fminf(al.y, bl.y), fminf(al.z, bl.z), 0.0f);
+            cur[2 * b + 1] = make_float4(fmaxf(ah.x, bh.x), fmaxf(ah.y, bh.y), fmaxf(ah.z, bh.z), 0.0f);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void grow(float4& lo, float4& hi, const float4* b) {
+    lo = make_float4(fminf(lo.x, b[0].x), fminf(lo.y, b[0].y), fminf(lo.z, b[0].z), 0.0f);
+    hi = make_float4(fmaxf(hi.x, b[1].x), fmaxf(hi.y, b[1].y), fmaxf(hi.z, b[1].z), 0.0f);
+}
+
+// leaves before sorted position i (i in [0, nt])
+__device__ __forceinline__ int leaves_before(const Tree& T, int nt, int i) {
+    return i >= nt ? T.blk_base[T.nb] : T.blk_base[i / kFitBlock] + T.mark_pre[i];
+}
+
+// every internal node spanning blocks: box and surviving-node count directly
+__global__ __launch_bounds__(256) void fit_top(int nt, Tree T) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nt - 1) return;
+    const int f = T.first[p], l = T.last[p];
+    if (f < 0 || l >= nt || f > l) return;
+    const int bf = f / kFitBlock, bl = l / kFitBlock;
+    if (bf == bl) return;   // fitted by its block
+    float4 lo = T.suf[2 * f], hi = T.suf[2 * f + 1];
+    grow(lo, hi, T.pre + 2 * (size_t)l);
+    const int n = bl - bf - 1;   // whole blocks strictly between
+    if (n > 0) {
+        int j = 31 - __clz(n);
+        j = min(j, T.levels - 1);
+        grow(lo, hi, T.st + 2 * ((size_t)j * T.nb + bf + 1));
+        grow(lo, hi, T.st + 2 * ((size_t)j * T.nb + (bl - (1 << j))));
+    }
+    T.box[2 * p] = lo;
+    T.box[2 * p + 1] = hi;
+    T.cnt[p] = 2 * (leaves_before(T, nt, l + 1) - leaves_before(T, nt, f)) - 1;
 }
 
 __global__ __launch_bounds__(256) void emit(int nt, Tree T, Node* out, DeviceSceneInfo* info) {
@@ -314,10 +478,17 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     }
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t ntm = nt > 0 ? (size_t)nt : 1;
+    const int nb = (int)((ntm + kFitBlock - 1) / kFitBlock);
+    int levels = 1;
+    while ((1 << levels) <= nb) ++levels;   // 2^(levels-1) <= nb < 2^levels
     const size_t sz_tmp = al(sizeof(float4) * 3 * ntm), sz_keys = al(sizeof(uint64_t) * ntm),
                  sz_vals = al(sizeof(uint32_t) * ntm), sz_i = al(sizeof(int32_t) * n_nodes),
-                 sz_box = al(sizeof(float4) * 2 * n_nodes), sz_cb = al(sizeof(int) * 8), sz_sort = al(sort_bytes);
-    const size_t total = sz_tmp + 2 * sz_keys + 2 * sz_vals + 8 * sz_i + sz_box + sz_cb + sz_sort;
+                 sz_box = al(sizeof(float4) * 2 * n_nodes), sz_cb = al(sizeof(int) * 8), sz_sort = al(sort_bytes),
+                 sz_part = al(sizeof(float) * 6 * (size_t)nblk(ntm)), sz_nt = al(sizeof(int32_t) * ntm),
+                 sz_base = al(sizeof(int32_t) * (size_t)(nb + 1)), sz_pre = al(sizeof(float4) * 2 * ntm),
+                 sz_st = al(sizeof(float4) * 2 * (size_t)nb * (size_t)levels);
+    const size_t total = sz_tmp + 2 * sz_keys + 2 * sz_vals + 7 * sz_i + sz_box + sz_cb + sz_sort + sz_part +
+                         2 * sz_nt + sz_base + 2 * sz_pre + sz_st;
     char* base = (char*)ta.alloc(ta.ctx, total, s);
     if (!base) { *oom = 1; return hipErrorOutOfMemory; }
     char* p = base;
@@ -335,14 +506,22 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     T.last = (int32_t*)take(sz_i);
     T.flag = (int32_t*)take(sz_i);
     T.cnt = (int32_t*)take(sz_i);
-    int32_t* top_list = (int32_t*)take(sz_i);
     T.box = (float4*)take(sz_box);
     int* cb = (int*)take(sz_cb);
     void* sort_tmp = take(sz_sort);
+    float* part = (float*)take(sz_part);
+    T.mark = (int32_t*)take(sz_nt);
+    T.mark_pre = (int32_t*)take(sz_nt);
+    T.blk_base = (int32_t*)take(sz_base);
+    T.pre = (float4*)take(sz_pre);
+    T.suf = (float4*)take(sz_pre);
+    T.st = (float4*)take(sz_st);
+    T.nb = nb;
+    T.levels = levels;
     hipError_t err = hipSuccess;
     if (nt > 0) {
-        hipLaunchKernelGGL(init_bounds, dim3(1), dim3(64), 0, s, cb);
-        hipLaunchKernelGGL(tri_prep, dim3(nblk(nt)), dim3(256), 0, s, verts, nv, tris, (int64_t)nt, tmp, cb, info);
+        hipLaunchKernelGGL(tri_prep, dim3(nblk(nt)), dim3(256), 0, s, verts, nv, tris, (int64_t)nt, tmp, part, info);
+        hipLaunchKernelGGL(bounds_reduce, dim3(1), dim3(256), 0, s, part, (int)nblk(nt), cb);
     }
     if (nt <= 1) {
         hipLaunchKernelGGL(tiny_scene, dim3(1), dim3(1), 0, s, tmp, nt, nodes_out, tris_out, info);
@@ -352,10 +531,12 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
         if (err == hipSuccess) {
             hipLaunchKernelGGL(fill_i32, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, T.parent, (int64_t)(2 * nt - 1), -1);
             hipLaunchKernelGGL(fill_i32, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, T.cnt, (int64_t)(2 * nt - 1), 0);
+            hipLaunchKernelGGL(fill_i32, dim3(nblk(nt)), dim3(256), 0, s, T.mark, (int64_t)nt, 0);
             hipLaunchKernelGGL(radix_tree, dim3(nblk(nt - 1)), dim3(256), 0, s, keys2, nt, T);
-            hipLaunchKernelGGL(fill_i32, dim3(1), dim3(256), 0, s, cb + 6, (int64_t)1, 0);   // top-node count
-            hipLaunchKernelGGL(refit_local, dim3(nblk(nt)), dim3(256), 0, s, tmp, vals2, nt, T, top_list, cb + 6);
-            hipLaunchKernelGGL(refit_top, dim3(1), dim3(1024), 0, s, top_list, cb + 6, nt, T);
+            hipLaunchKernelGGL(mark_leaves, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nt, T);
+            hipLaunchKernelGGL(fit_block, dim3((unsigned)nb), dim3(kFitBlock), 0, s, tmp, vals2, nt, T);
+            hipLaunchKernelGGL(block_table, dim3(1), dim3(1024), 0, s, T);
+            hipLaunchKernelGGL(fit_top, dim3(nblk(nt - 1)), dim3(256), 0, s, nt, T);
             hipLaunchKernelGGL(emit, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nt, T, nodes_out, info);
             hipLaunchKernelGGL(reorder, dim3(nblk(nt)), dim3(256), 0, s, tmp, vals2, (int64_t)nt, tris_out);
         }

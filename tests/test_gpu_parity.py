@@ -137,6 +137,93 @@ def test_trace_bvh_equals_brute_force(freq):
     assert (~robust).mean() < 1e-3
 
 
+def _check_bvh(nodes, tris_leaf, verts, faces, bad=0):
+    """BVH invariants: depth-first pre-order with skip links, every triangle
+    in exactly one leaf, each internal box exactly the union of its
+    children's, leaf boxes containing their triangles, and the leaf-order
+    triangles a permutation of the input."""
+    n, nt = len(nodes), len(faces)
+    lo = nodes[:, 0:3].copy().view(np.float32)
+    hi = nodes[:, 4:7].copy().view(np.float32)
+    esc, pay = nodes[:, 3], nodes[:, 7]
+    assert esc[0] == n
+    covered = np.zeros(nt, np.int64)
+    for i in range(n):
+        if pay[i] == 0:
+            l = i + 1
+            assert l < n
+            r = esc[l]
+            assert l < r < n and esc[r] == esc[i], (i, l, r)
+            assert np.array_equal(lo[i], np.minimum(lo[l], lo[r])) and np.array_equal(hi[i], np.maximum(hi[l], hi[r]))
+        else:
+            assert esc[i] == i + 1
+            first, cnt = pay[i] >> 3, pay[i] & 7
+            assert 1 <= cnt <= 4 and 0 <= first and first + cnt <= nt
+            covered[first:first + cnt] += 1
+            v = tris_leaf[first:first + cnt, :, :3].reshape(-1, 3)
+            assert np.array_equal(lo[i], v.min(0)) and np.array_equal(hi[i], v.max(0))
+    assert np.all(covered == 1)
+    # permutation of the input triangles (bad ones become a degenerate triangle at the origin)
+    ref = verts[faces].reshape(nt, 9).astype(np.float32)
+    got = tris_leaf[:, :, :3].reshape(nt, 9)
+    key = lambda a: a[np.lexsort(a.T[::-1])]  # noqa: E731
+    if bad == 0:
+        assert np.array_equal(key(ref), key(got))
+
+
+@pytest.mark.parametrize("case", ["soup255", "soup256", "soup257", "soup1000", "dup600", "sphere12", "sphere40",
+                                  "lattice"])
+def test_bvh_structure(case):
+    """Structural invariants of the device BVH on meshes that straddle the
+    256-triangle fitting blocks, with equal Morton codes, and at full size."""
+    _need_gpu()
+    import paper_2206_03380_amd as M
+    r = np.random.Generator(np.random.PCG64(11))
+    if case.startswith("soup"):
+        nt = int(case[4:])
+        v = r.uniform(-1, 1, (3 * nt, 3)).astype(np.float32)
+        v = v + np.repeat(r.uniform(-3, 3, (nt, 3)), 3, axis=0).astype(np.float32)
+        f = np.arange(3 * nt, dtype=np.int32).reshape(nt, 3)
+    elif case == "dup600":
+        # 600 copies of 3 triangles: equal centroids and Morton codes
+        v = r.uniform(-1, 1, (9, 3)).astype(np.float32)
+        f = np.tile(np.arange(9, dtype=np.int32).reshape(3, 3), (200, 1))
+    elif case == "lattice":
+        w = make_workload("lattice", H=8, W=8, n_views=1)
+        v, f = w.verts, w.tris
+    else:
+        w = make_workload("sphere8", H=8, W=8, n_views=1, freq=int(case[6:]))
+        v, f = w.verts, w.tris
+    sc = M.Scene(torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda())
+    info = sc.info()
+    nodes, tris = sc.nodes()
+    torch.cuda.synchronize()
+    nodes, tris = to_np(nodes), to_np(tris)
+    assert info["n_nodes"] == len(nodes) and info["bad_tris"] == 0
+    if case == "lattice":
+        # full structure check on a million triangles is slow in Python: a
+        # random subset of nodes for the local checks, coverage for all
+        n, nt = len(nodes), len(f)
+        esc, pay = nodes[:, 3], nodes[:, 7]
+        assert esc[0] == n
+        leaf = pay != 0
+        first, cnt = pay[leaf] >> 3, pay[leaf] & 7
+        assert np.all(esc[leaf] == np.nonzero(leaf)[0] + 1)
+        cov = np.zeros(nt + 1, np.int64)
+        np.add.at(cov, first, 1)
+        np.add.at(cov, first + cnt, -1)
+        assert np.all(np.cumsum(cov)[:nt] == 1)
+        lo = nodes[:, 0:3].copy().view(np.float32)
+        hi = nodes[:, 4:7].copy().view(np.float32)
+        for i in r.choice(np.nonzero(~leaf)[0], 20000, replace=False):
+            l = i + 1
+            rr = esc[l]
+            assert esc[rr] == esc[i]
+            assert np.array_equal(lo[i], np.minimum(lo[l], lo[rr])) and np.array_equal(hi[i], np.maximum(hi[l], hi[rr]))
+        return
+    _check_bvh(nodes, tris, v, f)
+
+
 def test_trace_edge_scenes():
     _need_gpu()
     import paper_2206_03380_amd as M
