@@ -60,6 +60,21 @@ __device__ __forceinline__ int cdf_find(const float* cdf, int n, float x) {
     return lo;
 }
 
+// The same search with the row's guide (guide[g] = cdf_find(cdf, n, g / G),
+// g = 0..G, G a power of two): for x in [0, 1) with g = floor(x G), the
+// answer lies in [guide[g], guide[g + 1]], since g / G <= x < (g + 1) / G and
+// both bounds are exact in FP32; the binary search over that range returns
+// the same column as cdf_find.
+__device__ __forceinline__ int cdf_find_guided(const float* cdf, const int32_t* guide, int G, float x) {
+    const int g = min(max((int)(x * (float)G), 0), G - 1);
+    int lo = guide[g], hi = guide[g + 1] + 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // GGX with Smith height-correlated masking (alpha = roughness^2)
 // ---------------------------------------------------------------------------

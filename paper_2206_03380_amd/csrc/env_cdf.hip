@@ -9,7 +9,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include "mcdi_internal.h"
+#include "device_common.h"
 
 #pragma clang fp contract(off)
 
@@ -109,7 +109,25 @@ __global__ void hot_kernel(const float* pdf, int H, int W, int32_t* hot_slot, in
     hot_slot[k] = slot;
 }
 
+__global__ __launch_bounds__(256) void guide_kernel(const float* cond, int W, int G, int32_t* guide) {
+    const int i = blockIdx.x;
+    const float* row = cond + (size_t)i * (W + 1);
+    for (int g = threadIdx.x; g <= G; g += 256)
+        guide[(size_t)i * (G + 1) + g] = cdf_find(row, W, (float)g / (float)G);
+}
+
 }  // namespace
+
+int env_guide_cells(int W) {
+    int G = 1;
+    while (4 * 2 * G <= W && G < 1024) G *= 2;   // about four columns per cell
+    return G;
+}
+
+hipError_t launch_env_guide(const float* cond, int H, int W, int G, int32_t* guide, hipStream_t s) {
+    hipLaunchKernelGGL(guide_kernel, dim3((unsigned)H), dim3(256), 0, s, cond, W, G, guide);
+    return hipGetLastError();
+}
 
 hipError_t launch_env_hot(const float* pdf, int H, int W, int32_t* hot_slot, int32_t* hot_texel, int32_t* n_hot,
                           hipStream_t s) {

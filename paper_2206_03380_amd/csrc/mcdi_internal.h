@@ -46,6 +46,8 @@ struct EnvView {
     const int32_t* hot_slot;       // [H*W] LDS slot of a hot texel or -1
     const int32_t* hot_texel;      // [kHotMax] texel of each slot
     const int32_t* n_hot;          // number of hot texels (<= kHotMax)
+    const int32_t* guide;          // [H][G+1] search guide of the conditional rows
+    int32_t G;                     // guide cells per row (power of two)
 };
 
 struct GBufView {
@@ -105,6 +107,10 @@ hipError_t launch_serve(const ServeItem* items_dev, int n_items, int64_t total_t
                         float4* scratch, int spp_max, int n_workgroups, int max_H, hipStream_t s);
 hipError_t launch_env_cdf(const float* env, int H, int W, float* cond, float* marg, float* pdf,
                           double* rowsum, int32_t* light_enabled, hipStream_t s);
+// Search guide of the conditional CDF rows: guide[i][g] = the largest column
+// k <= W-1 with cond[i][k] <= g / G, for g = 0..G.
+int env_guide_cells(int W);
+hipError_t launch_env_guide(const float* cond, int H, int W, int G, int32_t* guide, hipStream_t s);
 hipError_t launch_env_hot(const float* pdf, int H, int W, int32_t* hot_slot, int32_t* hot_texel, int32_t* n_hot,
                           hipStream_t s);
 // forward = gen_rays -> trace_rays -> shade; hit bits are produced by the

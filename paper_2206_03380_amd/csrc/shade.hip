@@ -171,7 +171,7 @@ __device__ __forceinline__ bool draw_light(const ShadeArgs& A, const Pixel& P, c
     const float x0 = u01(r0.x), x1 = u01(r0.y);
     const int i = cdf_find(s_marg, H, x0);
     const float* crow = A.env.cond + (size_t)i * (W + 1);
-    const int j = cdf_find(crow, W, x1);
+    const int j = cdf_find_guided(crow, A.env.guide + (size_t)i * (A.env.G + 1), A.env.G, x1);
     const float m0 = s_marg[i], m1 = s_marg[i + 1];
     const float c0 = crow[j], c1 = crow[j + 1];
     S.y = (float)i + (x0 - m0) / (m1 - m0);

@@ -275,6 +275,26 @@ def test_fwd_parity_tiny_techniques(tech):
     _fwd_parity(w, flags=_technique(tech))
 
 
+@pytest.mark.parametrize("shape", [(32, 64), (7, 13), (1, 1)])
+def test_fwd_parity_sparse_probe(shape):
+    """Light-sample texels on a probe that is mostly zero (long runs of
+    zero-width CDF bins, whole zero rows, isolated bright texels) and on odd
+    and single-texel probes: the row search, guided or not, must pick the
+    oracle's texel every time."""
+    w = make_workload("tiny")
+    r = np.random.Generator(np.random.PCG64(sum(shape)))
+    H, W = shape
+    e = np.zeros((H, W, 3), np.float32)
+    keep = r.random((H, W)) < 0.05
+    keep[r.integers(0, H), r.integers(0, W)] = True
+    e[keep] = r.lognormal(0, 2, (int(keep.sum()), 3)).astype(np.float32)
+    if H > 4:
+        e[H // 3] = 0.0
+        e[H // 2, : W // 2] = 0.0
+    w.env = e
+    _fwd_parity(w)
+
+
 def test_fwd_parity_sphere8_ragged():
     # two views, 60x52: several tiles and a ragged last tile
     w = make_workload("sphere8", H=60, W=52, n_views=2)
