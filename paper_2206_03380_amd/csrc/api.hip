@@ -423,11 +423,10 @@ mcdi_status mcdi_shade_bwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, co
     Workspace wr;
     EnvScatter es{};
     const int64_t tiles = (a.g.n + kBlock - 1) / kBlock;
-    // records per tile: one per probe texel a sample touches (four taps with
-    // the bilinear lookup)
-    const int64_t region = 2 * (int64_t)a.spp * kBlock * ((a.flags & MCDI_FLAG_BILINEAR) ? 4 : 1);
-    if (g_env && tiles * region <= ((int64_t)1 << 30)) {
-        env_scatter_plan(ev->H, ev->W, tiles, (uint32_t)region, es);
+    // records per tile: one per sample (the bilinear record is two float4s)
+    const int64_t region = 2 * (int64_t)a.spp * kBlock;
+    const bool bil = (a.flags & MCDI_FLAG_BILINEAR) != 0;
+    if (g_env && tiles * region <= ((int64_t)1 << 30) && env_scatter_plan(ev->H, ev->W, tiles, (uint32_t)region, bil, es)) {
         wr.alloc = &sc->alloc;
         wr.s = s;
         wr.base = sc->alloc.get(env_scatter_bytes(es), s);

@@ -27,6 +27,15 @@
 // and infinity propagate as with direct atomics.
 // Each record crosses HBM five times (written, read by the histogram and the
 // scatter, written sorted, read by the accumulation).
+//
+// The bilinear lookup spreads a sample's coefficient over four taps.  Its
+// record (32 bytes) carries the upper-left tap as a base index in an extended
+// grid of H + 1 rows (row i0 + 1 for i0 in [-1, H-1], so the row above the
+// first row centre is representable) and the fractions fx, fy.  Buckets and
+// the sort run on the base; the accumulation sums the four tap weights into
+// four accumulators at the base, and a gather adds, for every texel, the
+// accumulators of the bases whose taps land on it (columns wrapping, rows
+// clamped at the poles).  One record per sample instead of four.
 #include <hip/hip_runtime.h>
 
 #include "mcdi_internal.h"
@@ -43,6 +52,29 @@ constexpr uint32_t kChunkMin = 16384;  // sorted records per accumulate workgrou
 
 __device__ __forceinline__ uint32_t rec_texel(const float4& r) { return __float_as_uint(r.x); }
 
+// records: S float4s each (1 nearest, 2 bilinear); the key is the first word,
+// the three values are words 1..3 (nearest) or the second float4's x, y, z
+template <bool BIL> struct RecT;
+template <> struct RecT<false> {
+    float4 a;
+    __device__ __forceinline__ static RecT load(const float4* base, uint32_t i) { return RecT{base[i]}; }
+    __device__ __forceinline__ void store(float4* base, uint32_t i) const { base[i] = a; }
+    __device__ __forceinline__ uint32_t key() const { return rec_texel(a); }
+    __device__ __forceinline__ float v(int c) const { return c == 0 ? a.y : (c == 1 ? a.z : a.w); }
+};
+template <> struct RecT<true> {
+    float4 a, b;
+    __device__ __forceinline__ static RecT load(const float4* base, uint32_t i) {
+        return RecT{base[2 * (size_t)i], base[2 * (size_t)i + 1]};
+    }
+    __device__ __forceinline__ void store(float4* base, uint32_t i) const {
+        base[2 * (size_t)i] = a;
+        base[2 * (size_t)i + 1] = b;
+    }
+    __device__ __forceinline__ uint32_t key() const { return rec_texel(a); }
+    __device__ __forceinline__ float v(int c) const { return c == 0 ? b.x : (c == 1 ? b.y : b.z); }
+};
+
 int tile_grid(int64_t n_tiles) { return (int)(n_tiles < kGridMax ? n_tiles : kGridMax); }
 
 __global__ __launch_bounds__(1024) void init_kernel(EnvScatter p) {
@@ -52,17 +84,25 @@ __global__ __launch_bounds__(1024) void init_kernel(EnvScatter p) {
     }
 }
 
-// bits of max(|x|, |y|, |z|): for non-negative floats the bit patterns order
-// like the values, and NaN sorts above infinity
-__device__ __forceinline__ uint32_t abs_max_bits(const float4& r) {
-    const uint32_t a = __float_as_uint(r.y) & 0x7FFFFFFFu, b = __float_as_uint(r.z) & 0x7FFFFFFFu,
-                   c = __float_as_uint(r.w) & 0x7FFFFFFFu;
+// bilinear accumulators to zero (grid-stride)
+__global__ __launch_bounds__(256) void zero_acc4(float* acc, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) acc[k] = 0.0f;
+}
+
+// bits of the largest |value| of a record: for non-negative floats the bit
+// patterns order like the values, and NaN sorts above infinity (bilinear tap
+// weights are at most 1, so this also bounds every tap's value)
+template <bool BIL>
+__device__ __forceinline__ uint32_t abs_max_bits(const RecT<BIL>& r) {
+    const uint32_t a = __float_as_uint(r.v(0)) & 0x7FFFFFFFu, b = __float_as_uint(r.v(1)) & 0x7FFFFFFFu,
+                   c = __float_as_uint(r.v(2)) & 0x7FFFFFFFu;
     return max(a, max(b, c));
 }
 
 // Records per bucket and the largest |value| per bucket over the tiles
 // blockIdx.x, + gridDim.x, ...: counts kept per workgroup (for the scatter)
 // and added to the bucket totals.
+template <bool BIL>
 __global__ __launch_bounds__(256) void hist_kernel(EnvScatter p) {
     __shared__ uint32_t h[kMaxBuckets];
     __shared__ uint32_t hm[kMaxBuckets];
@@ -71,20 +111,21 @@ __global__ __launch_bounds__(256) void hist_kernel(EnvScatter p) {
         hm[b] = 0u;
     }
     __syncthreads();
+    constexpr int S = BIL ? 2 : 1;
     for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
-        const float4* r = p.rec + (size_t)t * p.region;
+        const float4* r = p.rec + (size_t)t * p.region * S;
         const uint32_t c = p.tile_count[t];
         for (uint32_t i = threadIdx.x; i < c; i += 1024) {
-            float4 v[4];
+            RecT<BIL> v[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (i + 256 * j < c) v[j] = r[i + 256 * j];
+                if (i + 256 * j < c) v[j] = RecT<BIL>::load(r, i + 256 * j);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 if (i + 256 * j < c) {
-                    const uint32_t b = rec_texel(v[j]) >> p.shift;
+                    const uint32_t b = v[j].key() >> p.shift;
                     atomicAdd(&h[b], 1u);
-                    atomicMax(&hm[b], abs_max_bits(v[j]));
+                    atomicMax(&hm[b], abs_max_bits<BIL>(v[j]));
                 }
         }
     }
@@ -159,9 +200,11 @@ __device__ void block_scan_k(uint32_t* a, int K, uint32_t* s256) {
 
 // Counting-sort scatter over the same tiles as the histogram workgroup.
 // LDS: lh, lofs, dst [K] each, then the batch [kBatch] of sorted records.
+template <bool BIL>
 __global__ __launch_bounds__(256) void scatter_kernel(EnvScatter p) {
     extern __shared__ uint32_t sm[];
     __shared__ uint32_t s256[256];
+    constexpr int S = BIL ? 2 : 1;
     const int K = p.K;
     uint32_t* lh = sm;
     uint32_t* lofs = sm + K;
@@ -171,23 +214,23 @@ __global__ __launch_bounds__(256) void scatter_kernel(EnvScatter p) {
     for (int b = threadIdx.x; b < K; b += 256) dst[b] = mine[b] ? atomicAdd(&p.cursor[b], mine[b]) : 0u;
     __syncthreads();
     for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
-        const float4* rr = p.rec + (size_t)t * p.region;
+        const float4* rr = p.rec + (size_t)t * p.region * S;
         const uint32_t c = p.tile_count[t];
         for (uint32_t b0 = 0; b0 < c; b0 += kBatch) {
             const int n = (int)min((uint32_t)kBatch, c - b0);
-            float4 r[kBatch / 256];
+            RecT<BIL> r[kBatch / 256];
             uint32_t rank[kBatch / 256];
             for (int b = threadIdx.x; b < K; b += 256) lh[b] = 0u;
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < kBatch / 256; ++j) {
                 const int i = threadIdx.x + 256 * j;
-                if (i < n) r[j] = rr[b0 + i];
+                if (i < n) r[j] = RecT<BIL>::load(rr, b0 + i);
             }
 #pragma unroll
             for (int j = 0; j < kBatch / 256; ++j) {
                 const int i = threadIdx.x + 256 * j;
-                if (i < n) rank[j] = atomicAdd(&lh[rec_texel(r[j]) >> p.shift], 1u);
+                if (i < n) rank[j] = atomicAdd(&lh[r[j].key() >> p.shift], 1u);
             }
             __syncthreads();
             for (int b = threadIdx.x; b < K; b += 256) lofs[b] = lh[b];
@@ -196,13 +239,13 @@ __global__ __launch_bounds__(256) void scatter_kernel(EnvScatter p) {
 #pragma unroll
             for (int j = 0; j < kBatch / 256; ++j) {
                 const int i = threadIdx.x + 256 * j;
-                if (i < n) srt[lofs[rec_texel(r[j]) >> p.shift] + rank[j]] = r[j];
+                if (i < n) r[j].store(srt, lofs[r[j].key() >> p.shift] + rank[j]);
             }
             __syncthreads();
             for (int i = threadIdx.x; i < n; i += 256) {
-                const float4 v = srt[i];
-                const uint32_t b = rec_texel(v) >> p.shift;
-                p.sorted[dst[b] + ((uint32_t)i - lofs[b])] = v;
+                const RecT<BIL> v = RecT<BIL>::load(srt, (uint32_t)i);
+                const uint32_t b = v.key() >> p.shift;
+                v.store(p.sorted, dst[b] + ((uint32_t)i - lofs[b]));
             }
             __syncthreads();
             for (int b = threadIdx.x; b < K; b += 256) dst[b] += lh[b];
@@ -211,16 +254,21 @@ __global__ __launch_bounds__(256) void scatter_kernel(EnvScatter p) {
     }
 }
 
+// acc holds A accumulators of 3 channels per texel of the bucket, [a][texel][3]:
+// A = 1 (nearest) or the four taps (bilinear), flushed into g_env or acc4
+template <bool BIL>
 __global__ __launch_bounds__(256) void accumulate_kernel(EnvScatter p, uint32_t chunk, int chunk_log2) {
-    extern __shared__ long long acc[];   // [3 << shift] fixed point (or float in the same space)
+    extern __shared__ long long acc[];   // [A][3 << shift] fixed point (or float in the same space)
+    constexpr int A = BIL ? 4 : 1;
     const uint32_t R = p.start[p.K];
     const uint64_t lo64 = (uint64_t)blockIdx.x * chunk;
     if (lo64 >= R) return;
     const uint32_t lo = (uint32_t)lo64;
     const uint32_t hi = (uint32_t)(lo64 + chunk < R ? lo64 + chunk : R);
-    const int b0 = (int)(rec_texel(p.sorted[lo]) >> p.shift);
-    const int b1 = (int)(rec_texel(p.sorted[hi - 1]) >> p.shift);
+    const int b0 = (int)(RecT<BIL>::load(p.sorted, lo).key() >> p.shift);
+    const int b1 = (int)(RecT<BIL>::load(p.sorted, hi - 1).key() >> p.shift);
     float* accf = (float*)acc;
+    const int slab = 3 << p.shift;       // one accumulator's span in acc
     for (int b = b0; b <= b1; ++b) {
         const uint32_t s = max(lo, p.start[b]), e = min(hi, p.start[b + 1]);
         if (s >= e) continue;
@@ -232,40 +280,77 @@ __global__ __launch_bounds__(256) void accumulate_kernel(EnvScatter p, uint32_t 
         frexpf(__uint_as_float(mb), &ex);      // every |value| in the bucket < 2^ex
         const int S = 62 - chunk_log2 - ex;
         const double scale = ldexp(1.0, S), unscale = ldexp(1.0, -S);
-        for (int k = threadIdx.x; k < 3 * n_tex; k += 256) {
-            if (fixed) acc[k] = 0;
-            else accf[k] = 0.0f;
-        }
+        for (int a = 0; a < A; ++a)
+            for (int k = threadIdx.x; k < 3 * n_tex; k += 256) {
+                if (fixed) acc[a * slab + k] = 0;
+                else accf[2 * (a * slab + k)] = 0.0f;
+            }
         __syncthreads();
         for (uint32_t i = s + threadIdx.x; i < e; i += 1024) {
-            float4 r[4];
+            RecT<BIL> r[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) r[j] = i + 256 * j < e ? p.sorted[i + 256 * j] : make_float4(0, 0, 0, 0);
+            for (int j = 0; j < 4; ++j)
+                if (i + 256 * j < e) r[j] = RecT<BIL>::load(p.sorted, i + 256 * j);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (i + 256 * j < e) {
-                    const int k = 3 * (int)(rec_texel(r[j]) - (uint32_t)first);
-                    if (fixed) {
-                        unsigned long long* a = (unsigned long long*)acc;
-                        atomicAdd(&a[k + 0], (unsigned long long)__double2ll_rn((double)r[j].y * scale));
-                        atomicAdd(&a[k + 1], (unsigned long long)__double2ll_rn((double)r[j].z * scale));
-                        atomicAdd(&a[k + 2], (unsigned long long)__double2ll_rn((double)r[j].w * scale));
+                    const int k = 3 * (int)(r[j].key() - (uint32_t)first);
+                    float w[A];
+                    if (BIL) {
+                        const float fx = r[j].a.y, fy = r[j].a.z;
+                        w[0] = (1.0f - fx) * (1.0f - fy);
+                        w[A > 1 ? 1 : 0] = fx * (1.0f - fy);
+                        w[A > 2 ? 2 : 0] = (1.0f - fx) * fy;
+                        w[A > 3 ? 3 : 0] = fx * fy;
                     } else {
-                        atomicAdd(&accf[k + 0], r[j].y);
-                        atomicAdd(&accf[k + 1], r[j].z);
-                        atomicAdd(&accf[k + 2], r[j].w);
+                        w[0] = 1.0f;
+                    }
+#pragma unroll
+                    for (int a = 0; a < A; ++a) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const float v = BIL ? w[a] * r[j].v(c) : r[j].v(c);
+                            if (fixed) {
+                                unsigned long long* ai = (unsigned long long*)acc;
+                                atomicAdd(&ai[a * slab + k + c], (unsigned long long)__double2ll_rn((double)v * scale));
+                            } else {
+                                atomicAdd(&accf[2 * (a * slab + k + c)], v);
+                            }
+                        }
                     }
                 }
             }
         }
         __syncthreads();
-        float* g = p.g_env + 3 * (size_t)first;
-        for (int k = threadIdx.x; k < 3 * n_tex; k += 256) {
-            const float v = fixed ? (float)((double)acc[k] * unscale) : accf[k];
-            if (v != 0.0f) atomicAdd(g + k, v);
+        for (int a = 0; a < A; ++a) {
+            float* g = BIL ? p.acc4 + ((size_t)a * p.n_texels + first) * 3 : p.g_env + 3 * (size_t)first;
+            for (int k = threadIdx.x; k < 3 * n_tex; k += 256) {
+                const float v = fixed ? (float)((double)acc[a * slab + k] * unscale) : accf[2 * (a * slab + k)];
+                if (v != 0.0f) atomicAdd(g + k, v);
+            }
         }
         __syncthreads();
     }
+}
+
+// Bilinear: g_env[i][j] += the four per-tap accumulators of the bases whose
+// taps land on texel (i, j).  A base at extended row r (= i0 + 1) and column
+// c puts tap 00 on (clamp(r - 1), c), tap 01 on (clamp(r - 1), c + 1 mod W),
+// tap 10 on (clamp(r), c) and tap 11 on (clamp(r), c + 1 mod W).
+__global__ __launch_bounds__(256) void gather_kernel(EnvScatter p) {
+    const int64_t n = (int64_t)p.H * p.W;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= 3 * n) return;
+    const int c3 = (int)(k % 3);
+    const int64_t t = k / 3;
+    const int i = (int)(t / p.W), j = (int)(t % p.W);
+    const int jm = j == 0 ? p.W - 1 : j - 1;
+    const int64_t X = (int64_t)(p.H + 1) * p.W;   // extended texels per accumulator
+    auto at = [&](int a, int r, int c) { return p.acc4[((size_t)a * X + (size_t)r * p.W + c) * 3 + c3]; };
+    float v = at(0, i + 1, j) + at(1, i + 1, jm) + at(2, i, j) + at(3, i, jm);
+    if (i == 0) v += at(0, 0, j) + at(1, 0, jm);
+    if (i == p.H - 1) v += at(2, p.H, j) + at(3, p.H, jm);
+    if (v != 0.0f) p.g_env[k] += v;
 }
 
 // sorted records per accumulate workgroup: large against the bucket's texels,
@@ -277,10 +362,16 @@ uint32_t chunk_of(uint32_t cap) {
 
 }  // namespace
 
-void env_scatter_plan(int H, int W, int64_t n_tiles, uint32_t region, EnvScatter& p) {
-    const int n_tex = H * W;
+bool env_scatter_plan(int H, int W, int64_t n_tiles, uint32_t region, bool bil, EnvScatter& p) {
+    // bilinear keys run over the extended grid of H + 1 rows; its four
+    // fixed-point accumulators per texel need buckets of 1024 texels (96 KB)
+    const int n_tex = bil ? (H + 1) * W : H * W;
     int shift = kMinShift;
     while (((int64_t)kMaxBuckets << shift) < n_tex) ++shift;   // <= kMaxShift for 4096 x 4096
+    if (bil && shift > kMinShift) return false;
+    p.bil = bil ? 1 : 0;
+    p.H = H;
+    p.W = W;
     p.shift = shift;
     p.K = (n_tex + (1 << shift) - 1) >> shift;
     p.n_texels = n_tex;
@@ -288,22 +379,32 @@ void env_scatter_plan(int H, int W, int64_t n_tiles, uint32_t region, EnvScatter
     p.region = region;
     p.cap = (uint32_t)(n_tiles * (int64_t)region);
     p.n_wg = tile_grid(n_tiles);
+    return true;
 }
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t env_scatter_bytes(const EnvScatter& p) {
-    return 2 * al256(sizeof(float4) * (size_t)p.cap) + al256(sizeof(uint32_t) * (size_t)p.n_tiles) +
+    const size_t S = p.bil ? 2 : 1;
+    return 2 * al256(sizeof(float4) * S * (size_t)p.cap) + al256(sizeof(uint32_t) * (size_t)p.n_tiles) +
+           (p.bil ? al256(sizeof(float) * 12 * (size_t)p.n_texels) : 0) +
            2 * al256(sizeof(uint32_t) * (size_t)p.K) + al256(sizeof(uint32_t) * (size_t)(p.K + 1)) +
            al256(sizeof(uint32_t) * (size_t)p.K * (size_t)p.n_wg);
 }
 
 void env_scatter_carve(void* base, EnvScatter& p) {
+    const size_t S = p.bil ? 2 : 1;
     char* c = (char*)base;
     p.rec = (float4*)c;
-    c += al256(sizeof(float4) * (size_t)p.cap);
+    c += al256(sizeof(float4) * S * (size_t)p.cap);
     p.sorted = (float4*)c;
-    c += al256(sizeof(float4) * (size_t)p.cap);
+    c += al256(sizeof(float4) * S * (size_t)p.cap);
+    if (p.bil) {
+        p.acc4 = (float*)c;
+        c += al256(sizeof(float) * 12 * (size_t)p.n_texels);
+    } else {
+        p.acc4 = nullptr;
+    }
     p.tile_count = (uint32_t*)c;
     c += al256(sizeof(uint32_t) * (size_t)p.n_tiles);
     p.cursor = (uint32_t*)c;
@@ -317,32 +418,47 @@ void env_scatter_carve(void* base, EnvScatter& p) {
 
 hipError_t launch_env_scatter_init(const EnvScatter& p, hipStream_t s) {
     hipLaunchKernelGGL(init_kernel, dim3(1), dim3(1024), 0, s, p);
+    if (p.bil) {
+        const int64_t n = 12 * (int64_t)p.n_texels;
+        const int64_t g = (n + 255) / 256;
+        hipLaunchKernelGGL(zero_acc4, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, s, p.acc4, n);
+    }
+    return hipGetLastError();
+}
+
+template <bool BIL>
+static hipError_t launch_env_scatter_t(const EnvScatter& p, hipStream_t s) {
+    constexpr int S = BIL ? 2 : 1;
+    hipLaunchKernelGGL(hist_kernel<BIL>, dim3(p.n_wg), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, p);
+    const size_t lds_sc = sizeof(uint32_t) * (size_t)((3 * p.K + 3) & ~3) + sizeof(float4) * S * kBatch;
+    if (lds_sc > 65536) {   // above the default dynamic LDS limit (large probes only)
+        const hipError_t e = hipFuncSetAttribute((const void*)scatter_kernel<BIL>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_sc);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(scatter_kernel<BIL>, dim3(p.n_wg), dim3(256), lds_sc, s, p);
+    const uint32_t chunk = chunk_of(p.cap);
+    const unsigned grid = (unsigned)((p.cap + chunk - 1) / chunk);
+    int clog = 0;
+    while ((1u << clog) < chunk) ++clog;
+    const size_t lds_acc = sizeof(long long) * (3u << p.shift) * (BIL ? 4 : 1);
+    if (lds_acc > 65536) {   // above the default dynamic LDS limit
+        const hipError_t e = hipFuncSetAttribute((const void*)accumulate_kernel<BIL>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_acc);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(accumulate_kernel<BIL>, dim3(grid), dim3(256), lds_acc, s, p, chunk, clog);
+    if (BIL) {
+        const int64_t n = 3 * (int64_t)p.H * p.W;
+        hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_env_scatter(const EnvScatter& p, hipStream_t s) {
     if (p.cap == 0) return hipSuccess;
-    hipLaunchKernelGGL(hist_kernel, dim3(p.n_wg), dim3(256), 0, s, p);
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, p);
-    const size_t lds_sc = sizeof(uint32_t) * (size_t)((3 * p.K + 3) & ~3) + sizeof(float4) * kBatch;
-    if (lds_sc > 65536) {   // above the default dynamic LDS limit (large probes only)
-        const hipError_t e = hipFuncSetAttribute((const void*)scatter_kernel,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_sc);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(scatter_kernel, dim3(p.n_wg), dim3(256), lds_sc, s, p);
-    const uint32_t chunk = chunk_of(p.cap);
-    const unsigned grid = (unsigned)((p.cap + chunk - 1) / chunk);
-    int clog = 0;
-    while ((1u << clog) < chunk) ++clog;
-    const size_t lds_acc = sizeof(long long) * (3u << p.shift);
-    if (lds_acc > 65536) {   // above the default dynamic LDS limit (large probes only)
-        const hipError_t e = hipFuncSetAttribute((const void*)accumulate_kernel,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_acc);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(accumulate_kernel, dim3(grid), dim3(256), lds_acc, s, p, chunk, clog);
-    return hipGetLastError();
+    return p.bil ? launch_env_scatter_t<true>(p, s) : launch_env_scatter_t<false>(p, s);
 }
 
 }  // namespace mcdi

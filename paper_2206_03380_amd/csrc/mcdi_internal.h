@@ -86,9 +86,13 @@ struct ShadeArgs {
     int32_t* ray_count;    // [blocks]
     int32_t* tile_order;   // [blocks] traversal order of the tiles (most rays first), or NULL
     float4* origins;       // [N]
-    // adjoint: probe-gradient records (texel bits, 3 values) of non-hot
-    // texels, one region of rec_region records per tile and a record count
-    // per tile, binned and summed by the env-scatter pass; NULL: direct atomics
+    // adjoint: probe-gradient records of non-hot texels, one region of
+    // rec_region records per tile and a record count per tile, binned and
+    // summed by the env-scatter pass; NULL: direct atomics.  Nearest lookup:
+    // one float4 (texel bits, 3 values).  Bilinear lookup: two float4s
+    // (base bits, fx, fy, 0) (3 values, 0), the base being the sample's
+    // upper-left tap in the extended grid of H + 1 rows (row i0 + 1, i0 in
+    // [-1, H-1]) by W columns.
     float4* rec;
     uint32_t* rec_count;
     uint32_t rec_region;
@@ -127,6 +131,9 @@ hipError_t launch_trace(const Scene& sc, const float* o, const float* d, int64_t
 // leaves in per-tile regions: bucket histogram, counting-sort scatter by
 // bucket, and per-bucket LDS accumulation flushed into g_env.
 struct EnvScatter {
+    int32_t bil;          // records of the bilinear lookup (two float4s, keyed by base)
+    int32_t H, W;         // probe size
+    float* acc4;          // bilinear: [4][(H+1) W][3] per-tap sums at each base, gathered into g_env
     float4* rec;          // [n_tiles][region] records as appended
     uint32_t* tile_count; // [n_tiles] records in each region
     uint32_t region;
@@ -142,7 +149,9 @@ struct EnvScatter {
     int32_t n_wg;         // workgroups of the histogram and scatter steps
     float* g_env;
 };
-void env_scatter_plan(int H, int W, int64_t n_tiles, uint32_t region, EnvScatter& p);
+// bil: records of the bilinear lookup; false when the extended grid is too
+// large for the bucket size the accumulation needs (use direct atomics)
+bool env_scatter_plan(int H, int W, int64_t n_tiles, uint32_t region, bool bil, EnvScatter& p);
 size_t env_scatter_bytes(const EnvScatter& p);     // after env_scatter_plan
 void env_scatter_carve(void* base, EnvScatter& p); // lay the buffers out in base
 hipError_t launch_env_scatter_init(const EnvScatter& p, hipStream_t s);

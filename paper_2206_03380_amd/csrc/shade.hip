@@ -235,6 +235,8 @@ struct RecSink {
 struct Taps {
     int t[4];
     float w[4];
+    int base;      // upper-left tap in the extended grid of H + 1 rows (row i0 + 1)
+    float fx, fy;
 };
 
 __device__ __forceinline__ Taps bilinear_taps(const EnvView& e, float x, float y) {
@@ -255,12 +257,30 @@ __device__ __forceinline__ Taps bilinear_taps(const EnvView& e, float x, float y
     T.w[1] = fx * (1.0f - fy);
     T.w[2] = (1.0f - fx) * fy;
     T.w[3] = fx * fy;
+    T.base = (i0 + 1) * W + ja;
+    T.fx = fx;
+    T.fy = fy;
     return T;
 }
 
 __device__ __forceinline__ float3 texel_rgb(const EnvView& e, int t) {
     const float* p = e.rgb + 3 * (size_t)t;
     return f3(p[0], p[1], p[2]);
+}
+
+// one record (n float4s) appended to the tile's region: one LDS counter
+// atomic per wave; the region holds every record the tile can make
+template <int NQ>
+__device__ __forceinline__ void append_record(const RecSink& rs, const float4 (&q)[NQ]) {
+    const uint64_t act = __ballot(1);
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(rs.count, (uint32_t)__popcll(act));
+    base = (uint32_t)__shfl((int)base, leader);
+    const uint32_t at = base + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) rs.base[(size_t)NQ * at + k] = q[k];
 }
 
 // probe-gradient contribution (v0, v1, v2) of one texel: hot texels go to
@@ -276,16 +296,8 @@ __device__ __forceinline__ void scatter_texel(const ShadeArgs& A, int texel, flo
     } else if (v0 == 0.0f && v1 == 0.0f && v2 == 0.0f) {
         // nothing to add (a shadowed sample with tau = 1, a zero tap weight)
     } else if (rs.base) {
-        // append to the tile's record region: one LDS counter atomic per
-        // wave; the region holds every record the tile can make
-        const uint64_t act = __ballot(1);
-        const int lane = (int)__lane_id();
-        const int leader = __ffsll((unsigned long long)act) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(rs.count, (uint32_t)__popcll(act));
-        base = (uint32_t)__shfl((int)base, leader);
-        const uint32_t at = base + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
-        rs.base[at] = make_float4(__uint_as_float((uint32_t)texel), v0, v1, v2);
+        const float4 q[1] = {make_float4(__uint_as_float((uint32_t)texel), v0, v1, v2)};
+        append_record<1>(rs, q);
     } else {
         float* ge = A.g_env + 3 * (size_t)texel;
         atomicAdd(ge + 0, v0);
@@ -346,9 +358,21 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
             // taps recomputed from the coordinates: cheaper than keeping
             // them live across the BSDF terms
             const Taps T = bilinear_taps(A.env, S.x, S.y);
+            if (rs.base) {
+                // one record per sample (base, fractions, coefficient), split
+                // into the four taps by the env-scatter pass; no LDS hot
+                // sums here: twelve contended LDS float atomics per sample
+                // cost more than the record
+                if (v0 != 0.0f || v1 != 0.0f || v2 != 0.0f) {
+                    const float4 q[2] = {make_float4(__uint_as_float((uint32_t)T.base), T.fx, T.fy, 0.0f),
+                                         make_float4(v0, v1, v2, 0.0f)};
+                    append_record<2>(rs, q);
+                }
+            } else {
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                scatter_texel(A, T.t[k], T.w[k] * v0, T.w[k] * v1, T.w[k] * v2, s_hot, rs);
+                for (int k = 0; k < 4; ++k)
+                    scatter_texel(A, T.t[k], T.w[k] * v0, T.w[k] * v1, T.w[k] * v2, s_hot, rs);
+            }
         } else {
             scatter_texel(A, S.texel, v0, v1, v2, s_hot, rs);
         }
@@ -780,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_
 }
 
 template <bool BWD, bool DUMP, bool BIL>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void shade_kernel(ShadeArgs A) {
+__device__ __forceinline__ void shade_body(const ShadeArgs& A) {
     extern __shared__ float smem[];
     __shared__ uint32_t s_rec;
     float* s_marg = smem;
@@ -789,13 +813,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (BWD) hot_zero(s_hot);
     if (threadIdx.x == 0) s_rec = 0u;
     __syncthreads();
-    const RecSink rs{(BWD && A.rec) ? A.rec + (size_t)blockIdx.x * A.rec_region : nullptr, &s_rec};
+    const RecSink rs{(BWD && A.rec) ? A.rec + (size_t)blockIdx.x * A.rec_region * (BIL ? 2 : 1) : nullptr, &s_rec};
     shade_tile<BWD, DUMP, BIL>(A, blockIdx.x, s_marg, s_hot, rs);
     if (BWD) {
         __syncthreads();
         hot_flush(A, s_hot);
         if (A.rec && threadIdx.x == 0) A.rec_count[blockIdx.x] = s_rec;
     }
+}
+
+// Four waves per SIMD (at most 128 VGPRs) for every variant except the
+// bilinear adjoint, which spills at that bound and runs faster at three.
+template <bool BWD, bool DUMP, bool BIL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void shade_kernel(ShadeArgs A) {
+    shade_body<BWD, DUMP, BIL>(A);
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void shade_bwd_bilinear_kernel(ShadeArgs A) {
+    shade_body<true, false, true>(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -911,7 +946,7 @@ hipError_t launch_serve(const ServeItem* items_dev, int n_items, int64_t total_t
 hipError_t launch_shade_bwd(const ShadeArgs& a, hipStream_t s) {
     const size_t lds = marg_lds(a) + sizeof(float) * 3 * kHotMax;
     if (a.flags & MCDI_FLAG_BILINEAR)
-        hipLaunchKernelGGL((shade_kernel<true, false, true>), dim3(n_blocks(a)), dim3(kBlock), lds, s, a);
+        hipLaunchKernelGGL(shade_bwd_bilinear_kernel, dim3(n_blocks(a)), dim3(kBlock), lds, s, a);
     else
         hipLaunchKernelGGL((shade_kernel<true, false, false>), dim3(n_blocks(a)), dim3(kBlock), lds, s, a);
     return hipGetLastError();
