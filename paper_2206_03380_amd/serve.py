@@ -37,6 +37,7 @@ class Request:
     seed: int = 0
     tau: float = 1.0
     ray_eps: float = 1e-3
+    flags: int = 0                     # technique / probe-lookup flags (FLAG_*; not DUMP or TIME_TRACE)
     g_cd: torch.Tensor = None          # upstream gradients: forward+backward request
     g_cs: torch.Tensor = None
     # filled by the server
@@ -153,7 +154,7 @@ class Server:
         it = L.ServeItem()
         it.scene, it.env = scene.handle, env.handle
         it.gbuf = r.gb.struct()
-        it.params = L.Params(r.spp, 0, r.seed, float(r.tau), float(r.ray_eps), None)
+        it.params = L.Params(r.spp, int(r.flags), r.seed, float(r.tau), float(r.ray_eps), None)
         it.c_d, it.c_s, it.hitbits, it.origins = (r.c_d.data_ptr(), r.c_s.data_ptr(), r._hb.data_ptr(),
                                                   r._org.data_ptr())
         if r.grad:
@@ -236,12 +237,13 @@ class PerRequest:
         scene, env = self.scenes[req.scene]
         with torch.cuda.stream(self.stream):
             req.c_d, req.c_s, hb, _ = shade_fwd(scene, env, req.gb, req.spp, seed=req.seed, tau=req.tau,
-                                                ray_eps=req.ray_eps, hitbits=req.grad, stream=self.stream)
+                                                ray_eps=req.ray_eps, flags=req.flags, hitbits=req.grad,
+                                                stream=self.stream)
             self.n_launches += 1
             if req.grad:
                 req.g_kd, req.g_korm, req.g_nrm, req.g_env = shade_bwd(
                     scene, env, req.gb, req.spp, req.g_cd, req.g_cs, hitbits=hb, seed=req.seed, tau=req.tau,
-                    ray_eps=req.ray_eps, stream=self.stream)
+                    ray_eps=req.ray_eps, flags=req.flags, stream=self.stream)
                 self.n_launches += 1
         ev = torch.cuda.Event()
         ev.record(self.stream)

@@ -35,14 +35,15 @@ def env():
     return M, scenes_np, resident
 
 
-def build_requests(M, scenes_np, draws):
+def build_requests(M, scenes_np, draws, flags=None):
     from paper_2206_03380_amd.serve import Request
     reqs = []
-    for (name, res, spp, grad, vb) in draws:
+    for k, (name, res, spp, grad, vb) in enumerate(draws):
         w = scenes_np[name][res]
         gb = M.GBuffer.from_workload(w, "cuda")
         gb.view_base = vb
-        r = Request(scene=name, gb=gb, spp=spp, seed=3, tau=w.tau, ray_eps=w.ray_eps)
+        r = Request(scene=name, gb=gb, spp=spp, seed=3, tau=w.tau, ray_eps=w.ray_eps,
+                    flags=0 if flags is None else flags[k % len(flags)])
         if grad:
             ud, us = upstream_grads(w, seed=vb)
             r.g_cd, r.g_cs = torch.from_numpy(ud).cuda(), torch.from_numpy(us).cuda()
@@ -96,6 +97,39 @@ def test_served_equals_staged_and_alone(env):
         s1.submit(alone)
         s1.drain()
         check_same(ref_res[i], results(alone))
+
+
+def test_served_technique_flags_equal_staged(env):
+    """Requests with technique subsets and the bilinear lookup, mixed in one
+    launch: each equals its own staged forward/backward (the served adjoint
+    scatters the bilinear taps with atomics, the staged one through records)."""
+    M, scenes_np, resident = env
+    from paper_2206_03380_amd.serve import Server, PerRequest
+    flags = [0, M.FLAG_BILINEAR, M.FLAG_LIGHT_OFF, M.FLAG_BSDF_OFF | M.FLAG_BILINEAR,
+             M.FLAG_LIGHT_OFF | M.FLAG_FORCE_GGX | M.FLAG_BILINEAR]
+    draws = serving.make_requests(scenes_np, 10, seed=21, res=(64, 128), spps=(2, 8))
+    draws = [(n, r, s, True, vb) for (n, r, s, g, vb) in draws]
+    base = PerRequest(resident)
+    ref = build_requests(M, scenes_np, draws, flags)
+    for r in ref:
+        base.submit(r)
+    base.drain()
+    ref_res = [results(r) for r in ref]
+    srv = Server(resident, budget_bytes=1 << 34, max_slots=8, launch_samples=200_000, spp_max=64)
+    mix = build_requests(M, scenes_np, draws, flags)
+    for r in mix:
+        srv.submit(r)
+    srv.drain()
+    torch.cuda.synchronize()
+    assert len(srv.completed) == len(mix)
+    for a, r in zip(ref_res, mix):
+        check_same(a, results(r))
+    # the bilinear requests differ from the same requests with the nearest lookup
+    near = build_requests(M, scenes_np, draws[1:2], [0])[0]
+    b2 = PerRequest(resident)
+    b2.submit(near)
+    b2.drain()
+    assert not np.array_equal(results(near)["c_d"], ref_res[1]["c_d"])
 
 
 def test_admission_respects_budget(env):
