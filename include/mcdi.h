@@ -122,8 +122,10 @@ mcdi_status mcdi_scene_nodes(mcdi_scene scene, void* nodes, float* tris, void* s
  *   cond [H][W+1]  per-row CDF, cond[i][0] = 0, cond[i][W] = 1
  *   marg [H+1]     marginal CDF over rows
  *   pdf  [H][W]    (w_ij / sum w) * W * H, the texel's density in (u, v)
- * The handle BORROWS env_rgb (radiance is read from it while shading): it
- * must stay unchanged until every shade call using the handle has completed.
+ * The handle also keeps a copy of the radiance, packed with the density as
+ * one float4 (r, g, b, pdf) per texel so that a sample reads both from one
+ * cache line.  env_rgb is read only by the build's stream work; shading uses
+ * the copy, so a changed probe needs a new handle.
  * Limits: 1 <= H <= 4096, 1 <= W <= 4096.
  * ------------------------------------------------------------------------- */
 mcdi_status mcdi_build_env_cdf(const float* env_rgb, int32_t H, int32_t W, const mcdi_allocator* alloc,

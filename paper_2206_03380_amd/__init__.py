@@ -101,8 +101,10 @@ class Scene:
 
 
 class Env:
-    """Sampling tables of a lat-long probe (device float32 [H,W,3]); keeps a
-    reference to the probe tensor, which the tables borrow."""
+    """Sampling tables of a lat-long probe (device float32 [H,W,3]) and a
+    packed copy of its radiance made with them; keeps a reference to the probe
+    tensor they were built from (the autograd function sends the probe
+    gradient there).  Build a new Env after changing the probe."""
 
     def __init__(self, env, stream=None, use_torch_allocator=True):
         _need(env, torch.float32, name="env")

@@ -122,6 +122,7 @@ struct mcdi_env_s {
     int32_t* n_hot = nullptr;
     int32_t* guide = nullptr;      // [H][G+1]
     int32_t G = 1;
+    float4* tex = nullptr;         // [H*W] (r, g, b, pdf)
 };
 
 extern "C" {
@@ -245,13 +246,15 @@ mcdi_status mcdi_build_env_cdf(const float* env_rgb, int32_t H, int32_t W, const
     ev->n_hot = (int32_t*)ev->alloc.get(sizeof(int32_t), s);
     ev->G = env_guide_cells(W);
     ev->guide = (int32_t*)ev->alloc.get(sizeof(int32_t) * (size_t)H * (ev->G + 1), s);
+    ev->tex = (float4*)ev->alloc.get(sizeof(float4) * (size_t)H * W, s);
     if (!ev->cond || !ev->marg || !ev->pdf || !ev->rowsum || !ev->light || !ev->hot_slot || !ev->hot_texel ||
-        !ev->n_hot || !ev->guide) {
+        !ev->n_hot || !ev->guide || !ev->tex) {
         mcdi_destroy_env(ev);
         return fail(MCDI_E_OOM, "mcdi_build_env_cdf: device allocation failed");
     }
     hipError_t e = launch_env_cdf(env_rgb, H, W, ev->cond, ev->marg, ev->pdf, ev->rowsum, ev->light, s);
     if (e == hipSuccess) e = launch_env_guide(ev->cond, H, W, ev->G, ev->guide, s);
+    if (e == hipSuccess) e = launch_env_pack(env_rgb, ev->pdf, (int64_t)H * W, ev->tex, s);
     if (e == hipSuccess) e = launch_env_hot(ev->pdf, H, W, ev->hot_slot, ev->hot_texel, ev->n_hot, s);
     if (e != hipSuccess) {
         mcdi_destroy_env(ev);
@@ -272,6 +275,7 @@ void mcdi_destroy_env(mcdi_env ev) {
     ev->alloc.put(ev->hot_texel, ev->stream);
     ev->alloc.put(ev->n_hot, ev->stream);
     ev->alloc.put(ev->guide, ev->stream);
+    ev->alloc.put(ev->tex, ev->stream);
     delete ev;
 }
 
@@ -308,7 +312,7 @@ static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, cons
     std::memset(&a, 0, sizeof(a));
     a.scene = Scene{sc->nodes, sc->tris, sc->n_tris};
     a.env = EnvView{ev->H, ev->W, ev->rgb, ev->cond, ev->marg, ev->pdf, ev->light, ev->hot_slot, ev->hot_texel,
-                    ev->n_hot, ev->guide, ev->G};
+                    ev->n_hot, ev->guide, ev->G, ev->tex};
     a.g = GBufView{g->n_views, g->height, g->width, g->view_base, g->pos, g->nrm, g->kd, g->korm, g->mask, g->eye, n};
     a.spp = p->spp;
     a.flags = p->flags;

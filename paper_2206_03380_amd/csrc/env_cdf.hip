@@ -116,7 +116,17 @@ __global__ __launch_bounds__(256) void guide_kernel(const float* cond, int W, in
         guide[(size_t)i * (G + 1) + g] = cdf_find(row, W, (float)g / (float)G);
 }
 
+__global__ __launch_bounds__(256) void pack_kernel(const float* env, const float* pdf, int64_t n, float4* tex) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) tex[k] = make_float4(env[3 * k], env[3 * k + 1], env[3 * k + 2], pdf[k]);
+}
+
 }  // namespace
+
+hipError_t launch_env_pack(const float* env, const float* pdf, int64_t n, float4* tex, hipStream_t s) {
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, env, pdf, n, tex);
+    return hipGetLastError();
+}
 
 int env_guide_cells(int W) {
     int G = 1;

@@ -48,6 +48,7 @@ struct EnvView {
     const int32_t* n_hot;          // number of hot texels (<= kHotMax)
     const int32_t* guide;          // [H][G+1] search guide of the conditional rows
     int32_t G;                     // guide cells per row (power of two)
+    const float4* tex;             // [H*W] (r, g, b, pdf): radiance and density in one line
 };
 
 struct GBufView {
@@ -114,6 +115,8 @@ hipError_t launch_env_cdf(const float* env, int H, int W, float* cond, float* ma
 // Search guide of the conditional CDF rows: guide[i][g] = the largest column
 // k <= W-1 with cond[i][k] <= g / G, for g = 0..G.
 int env_guide_cells(int W);
+// (r, g, b, pdf) per texel, after the tables
+hipError_t launch_env_pack(const float* env, const float* pdf, int64_t n, float4* tex, hipStream_t s);
 hipError_t launch_env_guide(const float* cond, int H, int W, int G, int32_t* guide, hipStream_t s);
 hipError_t launch_env_hot(const float* pdf, int H, int W, int32_t* hot_slot, int32_t* hot_texel, int32_t* n_hot,
                           hipStream_t s);

@@ -183,7 +183,7 @@ __device__ __forceinline__ bool draw_light(const ShadeArgs& A, const Pixel& P, c
     sincospif(2.0f * u, &sp, &cp);
     S.w = f3(st * cp, ct, st * sp);
     S.texel = i * W + j;
-    S.pL = st > 0.0f ? A.env.pdf[S.texel] / (2.0f * kPi * kPi * st) : 0.0f;
+    S.pL = st > 0.0f ? A.env.tex[S.texel].w / (2.0f * kPi * kPi * st) : 0.0f;
     S.wl = f3(dot(S.w, P.t), dot(S.w, P.b), dot(S.w, P.n));
     return S.pL > 0.0f;
 }
@@ -218,7 +218,7 @@ __device__ __forceinline__ void bsdf_texel(const ShadeArgs& A, bool light_on, Sa
     const int ti = min((int)S.y, H - 1);
     const int tj = min((int)S.x, W - 1);
     S.texel = ti * W + tj;
-    if (light_on && rho > 0.0f) S.pL = A.env.pdf[S.texel] / (2.0f * kPi * kPi * rho);
+    if (light_on && rho > 0.0f) S.pL = A.env.tex[S.texel].w / (2.0f * kPi * kPi * rho);
 }
 
 // where the adjoint puts probe-gradient records of non-hot texels: the tile's
@@ -264,8 +264,8 @@ __device__ __forceinline__ Taps bilinear_taps(const EnvView& e, float x, float y
 }
 
 __device__ __forceinline__ float3 texel_rgb(const EnvView& e, int t) {
-    const float* p = e.rgb + 3 * (size_t)t;
-    return f3(p[0], p[1], p[2]);
+    const float4 p = e.tex[t];
+    return f3(p.x, p.y, p.z);
 }
 
 // one record (n float4s) appended to the tile's region: one LDS counter
