@@ -286,9 +286,11 @@ __device__ __forceinline__ void append_record(const RecSink& rs, const float4 (&
 // probe-gradient contribution (v0, v1, v2) of one texel: hot texels go to
 // the workgroup's LDS copy, the rest to the tile's records (or straight to
 // global memory when there are none)
+// maybe_hot false: the texel's density rules it out of the hot set (its slot
+// is not read)
 __device__ __forceinline__ void scatter_texel(const ShadeArgs& A, int texel, float v0, float v1, float v2,
-                                              float* s_hot, const RecSink& rs) {
-    const int slot = A.env.hot_slot[texel];
+                                              float* s_hot, const RecSink& rs, bool maybe_hot = true) {
+    const int slot = maybe_hot ? A.env.hot_slot[texel] : -1;
     if (slot >= 0) {
         atomicAdd(s_hot + 3 * slot + 0, v0);
         atomicAdd(s_hot + 3 * slot + 1, v1);
@@ -322,12 +324,15 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
     const float Pt = S.pL + P.bsdf_w * (P.q * pcos + (1.0f - P.q) * pggx);
     const float w = Hv / Pt;
     float3 L;
+    float pdf_uv = 0.0f;   // nearest lookup: the texel's density (pdf table)
     if (BIL) {
         const Taps T = bilinear_taps(A.env, S.x, S.y);
         L = T.w[0] * texel_rgb(A.env, T.t[0]) + T.w[1] * texel_rgb(A.env, T.t[1]) +
             T.w[2] * texel_rgb(A.env, T.t[2]) + T.w[3] * texel_rgb(A.env, T.t[3]);
     } else {
-        L = texel_rgb(A.env, S.texel);
+        const float4 tx = A.env.tex[S.texel];
+        L = f3(tx.x, tx.y, tx.z);
+        pdf_uv = tx.w;
     }
     const float kdiff = (1.0f - P.m) * kInvPi * NoL;
     float S_ = 0.0f, Fw = 0.0f, G2 = 0.0f, lamL = 0.0f, t2L = 0.0f;
@@ -374,7 +379,10 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
                     scatter_texel(A, T.t[k], T.w[k] * v0, T.w[k] * v1, T.w[k] * v2, s_hot, rs);
             }
         } else {
-            scatter_texel(A, S.texel, v0, v1, v2, s_hot, rs);
+            // hot texels have pdf > W H / kHotMax (the hot-set rule); half that
+            // bound keeps the test free of rounding questions
+            const bool maybe_hot = pdf_uv > 0.5f * ((float)A.env.W * (float)A.env.H / (float)kHotMax);
+            scatter_texel(A, S.texel, v0, v1, v2, s_hot, rs, maybe_hot);
         }
     }
     const float udL = Ud.x * L.x + Ud.y * L.y + Ud.z * L.z;
