@@ -311,8 +311,8 @@ static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, cons
         return fail(MCDI_E_INVALID, "%s: FORCE_COS and FORCE_GGX together", who);
     std::memset(&a, 0, sizeof(a));
     a.scene = Scene{sc->nodes, sc->tris, sc->n_tris};
-    a.env = EnvView{ev->H, ev->W, ev->rgb, ev->cond, ev->marg, ev->pdf, ev->light, ev->hot_slot, ev->hot_texel,
-                    ev->n_hot, ev->guide, ev->G, ev->tex};
+    a.env = EnvView{ev->H, ev->W, ev->cond, ev->marg, ev->light, ev->hot_slot, ev->hot_texel, ev->n_hot, ev->guide,
+                    ev->G, ev->tex};
     a.g = GBufView{g->n_views, g->height, g->width, g->view_base, g->pos, g->nrm, g->kd, g->korm, g->mask, g->eye, n};
     a.spp = p->spp;
     a.flags = p->flags;

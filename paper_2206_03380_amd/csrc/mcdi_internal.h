@@ -38,10 +38,8 @@ struct Scene {
 
 struct EnvView {
     int32_t H, W;
-    const float* rgb;     // [H][W][3] radiance (borrowed)
     const float* cond;    // [H][W+1]
     const float* marg;    // [H+1]
-    const float* pdf;     // [H][W]
     const int32_t* light_enabled;  // device flag: total weight > 0
     const int32_t* hot_slot;       // [H*W] LDS slot of a hot texel or -1
     const int32_t* hot_texel;      // [kHotMax] texel of each slot
