@@ -82,6 +82,9 @@ def lib():
         L.orc_integrand.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int64, vp, vp, vp]
         L.orc_batch_probe_bilinear.argtypes = [vp, C.c_int, C.c_int, C.c_int64, vp, vp, vp]
         L.orc_max_threads.restype = C.c_int
+        L.orc_edge_grad.restype = C.c_int
+        L.orc_edge_grad.argtypes = [vp, vp, vp, vp, C.c_int64, vp, C.c_int32, vp, C.c_int64, vp, C.c_int64,
+                                    vp, vp, vp, vp, vp, vp, vp, C.c_int]
         _lib = L
     return _lib
 
@@ -332,3 +335,75 @@ def integrand(w, pixel, dirs, scene=None, tables=None, tau=None, ray_eps=None, b
 
 def max_threads():
     return lib().orc_max_threads()
+
+
+# ---------------------------------------------------------------------------
+# visibility gradients of the shadow term by edge sampling
+# ---------------------------------------------------------------------------
+
+def mesh_edges(tris, n_verts):
+    """Unique undirected edges of an indexed triangle mesh, [E, 4] int32 rows
+    (a, b, c, d): the edge a-b as it first appears (triangle f, side k runs
+    from corner k to corner k+1), c the opposite corner of that face, d the
+    opposite corner of the second face that has the edge (-1 if none).
+    Rows are in order of first appearance, f-major then k.  A triangle with
+    a corner outside [0, n_verts) contributes nothing, nor does a side whose
+    two corners are the same vertex; faces after the second are ignored."""
+    tris = np.asarray(tris, np.int64).reshape(-1, 3)
+    first = {}
+    rows = []
+    for f in range(len(tris)):
+        t = tris[f]
+        if (t < 0).any() or (t >= n_verts).any():
+            continue
+        for k in range(3):
+            a, b, c = int(t[k]), int(t[(k + 1) % 3]), int(t[(k + 2) % 3])
+            if a == b:
+                continue
+            key = (a, b) if a < b else (b, a)
+            at = first.get(key)
+            if at is None:
+                first[key] = len(rows)
+                rows.append([a, b, c, -1])
+            elif rows[at][3] == -1:
+                rows[at][3] = c
+    return np.array(rows, np.int32).reshape(-1, 4)
+
+
+def edge_grad(w, edges, n_es, u_d, u_s, pixels=None, scene=None, tables=None, seed=None, tau=None,
+              ray_eps=None, flags=0, tol=None, brute=False, threads=0):
+    """Edge-sampled derivative of sum_pixels (u_d . c_d + u_s . c_s) with
+    respect to the mesh vertices through the shadow-ray visibility, from
+    n_es edge samples per pixel.  Returns a dict: g_verts [Nv, 3] and, per
+    element, abs (sum of |term|), cond (FP32 error bound of the terms),
+    flag (bound on the terms of samples with an undecided step), plus the
+    sample counts."""
+    L = lib()
+    seed = w.seed if seed is None else seed
+    tau = float(np.float32(w.tau if tau is None else tau))
+    ray_eps = float(np.float32(w.ray_eps if ray_eps is None else ray_eps))
+    tol = tol or Tolerances()
+    pixels = np.arange(w.n_pixels, dtype=np.int64) if pixels is None else _c(pixels, np.int64)
+    n = len(pixels)
+    scene = scene or Scene(w.verts, w.tris)
+    tables = tables or EnvTables(w.env)
+    arr = _gb_arrays(w)
+    gs = _gbuf_struct(w, arr)
+    prm = Params(1, flags, seed, tau, ray_eps, tol.vis_abs, tol.vis_rel, tol.ang, tol.cos, int(brute))
+    edges = _c(edges, np.int32).reshape(-1, 4)
+    verts = _c(w.verts, np.float32)
+    nv = len(verts)
+    ud = _c(u_d, np.float64).reshape(3, -1)
+    us = _c(u_s, np.float64).reshape(3, -1)
+    if ud.shape[1] != n:
+        ud, us = np.ascontiguousarray(ud[:, pixels]), np.ascontiguousarray(us[:, pixels])
+    out = {k: np.zeros((nv, 3)) for k in ("g_verts", "abs", "cond", "flag")}
+    counts = np.zeros(5, np.int64)
+    r = L.orc_edge_grad(scene.ptr, C.byref(tables.struct), C.byref(gs), _p(pixels), n, C.byref(prm), int(n_es),
+                        _p(edges), len(edges), _p(verts), nv, _p(ud), _p(us), _p(out["g_verts"]),
+                        _p(out["abs"]), _p(out["cond"]), _p(out["flag"]), _p(counts), int(threads))
+    if r < 0:
+        raise ValueError("oracle rejected the edge-gradient arguments")
+    out.update(samples=int(counts[0]), silhouettes=int(counts[1]), traced=int(counts[2]),
+               blocked=int(counts[3]), flagged=int(counts[4]))
+    return out

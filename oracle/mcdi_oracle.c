@@ -22,7 +22,11 @@
  *   - the same random numbers are replayed in the backward pass (section 4.1,
  *     appendix D);
  *   - diffuse lighting is returned demodulated, specular is not (section 4.2);
- *   - shadowed samples are weighted by H = 1 - tau (appendix A).
+ *   - shadowed samples are weighted by H = 1 - tau (appendix A);
+ *   - separately, the visibility gradient that the estimator detaches: the
+ *     derivative of the shadowed integral with respect to the occluding mesh's
+ *     vertices (section 3.1 "Shadow gradients"; appendix "Visibility
+ *     Gradients from Shadows"), estimated by sampling silhouette edges.
  * Readings of points the paper leaves open (probe parameterisation, lobe
  * selection probability, GGX details, ray offsets, RNG) are listed in the
  * design notes and are identical on both sides.
@@ -1411,4 +1415,274 @@ void orc_integrand(const orc_scene* scene, const orc_env* E, const orc_gbuffer* 
             gs[3 * i + c] = o.cs[c];
         }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Visibility gradients of the shadow term by edge sampling.  The estimator  */
+/* above detaches visibility (section 3.1, "Shadow gradients"); the paper's  */
+/* ablation on shadow gradients (appendix "Visibility Gradients from        */
+/* Shadows") adds the derivative of the shadowed hemisphere integral with   */
+/* respect to the occluding geometry.  Here that derivative is estimated by */
+/* sampling mesh edges (the boundary-integral form of the derivative of an  */
+/* integral over a moving region).                                           */
+/*                                                                           */
+/* Seen from the shadow-ray origin o, the region of directions blocked by a */
+/* triangle is bounded by the great-circle arcs of its edges.  For an edge  */
+/* a-b, a point x(t) = a + t (b - a), t in [0, 1), has direction            */
+/* w = (x - o)/r, r = |x - o|.  The arc lies in the plane through o with    */
+/* normal m = (a - o) x (b - o), and as the vertices move the arc moves     */
+/* along mh = m/|m| at the rate mh . ((1-t) da + t db) / r.  The arc length */
+/* per unit t is |(b - a) x w| / r.  When the integrand jumps across the    */
+/* arc from h_in (the side of the edge's own face) to h_out, the            */
+/* derivative of the integral is the integral along the arc of             */
+/* s (h_out - h_in) (mh . dx/dtheta) / r, with s = +1 when the face lies on */
+/* the +mh side (the arc moving along +mh uncovers directions) and -1      */
+/* otherwise.  With H = 1 - tau on blocked directions, h_in = g (1 - tau)  */
+/* (the face blocks) and h_out = g (1 - tau [the out-side ray is blocked]),*/
+/* so h_out - h_in = tau g when the out-side ray misses and 0 when          */
+/* something else still blocks it.                                           */
+/*                                                                           */
+/* Only unique edges count, and only silhouettes: an edge whose two faces   */
+/* lie on opposite sides of the arc is covered on both sides.  One sample   */
+/* draws an edge uniformly (density 1/E) and t uniformly, so the estimate   */
+/* of d(loss)/d(vertex) adds                                                */
+/*   E s tau g(w) |(b - a) x w| / r^2 / n_es  x  ((1 - t) mh at a, t mh at b)*/
+/* when the out-side ray misses, where g(w) = sum_c Ud_c g_d,c(w) +         */
+/* Us_c g_s,c(w) contracts the integrand of c_d and c_s with the upstream   */
+/* gradients.  The out-side ray leaves o along w turned by ORC_EDGE_DELTA   */
+/* radians away from the face, normalised.                                  */
+/*                                                                           */
+/* Random numbers: Philox block 2 of counter (pixel in view, view id, j),   */
+/* j the edge sample; the edge is (x0 * E) >> 32 (integer, exact), t the    */
+/* 24-bit uniform of x1.                                                    */
+/* ------------------------------------------------------------------------ */
+#define ORC_EDGE_DELTA (1.0 / 8192.0)
+
+/* largest radiance per channel over the 3x3 texels around (i, j): bounds the
+ * lookup when the nearest texel is undecided */
+static void texel_max3(const float* env, int H, int W, int i, int j, double L[3])
+{
+    for (int c = 0; c < 3; ++c) L[c] = 0.0;
+    for (int di = -1; di <= 1; ++di)
+        for (int dj = -1; dj <= 1; ++dj) {
+            const float* e = texel_ptr(env, H, W, i + di, j + dj);
+            for (int c = 0; c < 3; ++c) L[c] = fmax(L[c], fabs((double)e[c]));
+        }
+}
+
+/* Edge-sampled visibility gradient of the listed pixels, accumulated into
+ * gv[n_verts][3].  gv_abs sums |term| per element; gv_cond sums |term|
+ * times the FP32 condition of the term (per unit roundoff); gv_flag sums a
+ * bound on the terms of samples with an undecided discrete step (silhouette
+ * sign, horizon, nearest texel, out-side ray).  counts = {samples, silhouette
+ * samples above the horizon, rays traced, rays blocked, flagged samples}.
+ * Returns 0, or -1 on bad arguments. */
+int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g, const int64_t* pix,
+                  int64_t npix, const orc_params* P, int32_t n_es, const int32_t* edges, int64_t n_edges,
+                  const float* verts, int64_t n_verts, const double* Ud, const double* Us, double* gv,
+                  double* gv_abs, double* gv_cond, double* gv_flag, int64_t* counts, int nthreads)
+{
+    if (n_es < 0 || n_edges < 0 || n_edges > 0xFFFFFFFFll) return -1;
+    for (int k = 0; k < 5; ++k) counts[k] = 0;
+    if (n_es == 0 || n_edges == 0 || P->tau == 0.0) return 0;
+    const double u = 0x1p-24;
+    int nt = 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    nt = omp_get_max_threads();
+#endif
+    const size_t nv3 = (size_t)n_verts * 3;
+    double* acc = (double*)calloc((size_t)nt * 4 * nv3, sizeof(double));
+    int64_t* cnt = (int64_t*)calloc((size_t)nt * 5, sizeof(int64_t));
+    const int64_t HW = (int64_t)g->height * g->width;
+    const uint32_t key[2] = {(uint32_t)P->seed, (uint32_t)(P->seed >> 32)};
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* a_v = acc + (size_t)tid * 4 * nv3;
+        double* a_abs = a_v + nv3;
+        double* a_cond = a_abs + nv3;
+        double* a_flag = a_cond + nv3;
+        int64_t* c5 = cnt + (size_t)tid * 5;
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < npix; ++q) {
+            pix_setup S;
+            int nf = 0;
+            if (!setup_pixel(g, pix[q], &S, &nf)) continue;
+            const double ud[3] = {Ud[q], Ud[npix + q], Ud[2 * npix + q]};
+            const double us[3] = {Us[q], Us[npix + q], Us[2 * npix + q]};
+            const int nov_near = fabs(S.NoV) < 1e-12;
+            double o[3];
+            for (int k = 0; k < 3; ++k) o[k] = S.p[k] + P->ray_eps * S.n[k];
+            const double olen = norm3(o);
+            const uint32_t view = (uint32_t)(pix[q] / HW), piv = (uint32_t)(pix[q] % HW);
+            for (int j = 0; j < n_es; ++j) {
+                uint32_t ctr[4] = {piv, (uint32_t)g->view_base + view, (uint32_t)j, 2u}, r[4];
+                orc_philox4x32_10(ctr, key, r);
+                c5[0]++;
+                const int64_t e = (int64_t)(((uint64_t)r[0] * (uint64_t)n_edges) >> 32);
+                const double t = u01(r[1]);
+                const int32_t* ed = edges + 4 * e;
+                double qa[3], qb[3], qc[3], qd[3] = {0, 0, 0};
+                for (int k = 0; k < 3; ++k) {
+                    qa[k] = (double)verts[3 * (size_t)ed[0] + k] - o[k];
+                    qb[k] = (double)verts[3 * (size_t)ed[1] + k] - o[k];
+                    qc[k] = (double)verts[3 * (size_t)ed[2] + k] - o[k];
+                    if (ed[3] >= 0) qd[k] = (double)verts[3 * (size_t)ed[3] + k] - o[k];
+                }
+                double m[3];
+                cross3(qa, qb, m);
+                const double la = norm3(qa), lb = norm3(qb), lc = norm3(qc), ld = norm3(qd);
+                /* FP32 error bound of a triple product of differences from o
+                 * (o itself rounded to FP32), with a factor 4 margin */
+                const double eo = 32.0 * u * olen;
+                const double tc = 128.0 * u * la * lb * lc + eo * (la * lb + lb * lc + lc * la);
+                const double td = 128.0 * u * la * lb * ld + eo * (la * lb + lb * ld + ld * la);
+                const double sc = dot3(m, qc);
+                const double sd = ed[3] >= 0 ? dot3(m, qd) : 0.0;
+                int flag = nov_near;
+                if (fabs(sc) <= tc) flag = 1;
+                if (ed[3] >= 0 && fabs(sd) <= td) flag = 1;
+                if (sc == 0.0) continue;
+                const int sil = ed[3] < 0 || !((sc > 0.0 && sd < 0.0) || (sc < 0.0 && sd > 0.0));
+                if (!sil && !flag) continue;
+                double w[3], eab[3];
+                for (int k = 0; k < 3; ++k) {
+                    eab[k] = qb[k] - qa[k];
+                    w[k] = qa[k] + t * eab[k];
+                }
+                const double r2 = dot3(w, w), rr = sqrt(r2);
+                for (int k = 0; k < 3; ++k) w[k] /= rr;
+                const double NoL = dot3(S.n, w);
+                if (fabs(NoL) < P->delta_cos) flag = 1;
+                if (NoL <= 0.0 && !flag) continue;
+                const double ml = norm3(m);
+                if (ml == 0.0) continue;
+                double mh[3];
+                for (int k = 0; k < 3; ++k) mh[k] = m[k] / ml;
+                const double s = sc > 0.0 ? 1.0 : -1.0;
+                double ex[3];
+                cross3(eab, w, ex);
+                const double J = norm3(ex) / r2;
+                /* radiance at w */
+                int ti, tj;
+                double margin, x, y, Lv[3], dLv[3] = {0, 0, 0};
+                texel_of_dir_xy(E->H, E->W, w, &ti, &tj, &margin, &x, &y);
+                double Lb[3];
+                if (P->flags & ORC_BILINEAR) {
+                    orc_probe_bilinear(E->env, E->H, E->W, x, y, Lv);
+                    /* coordinates from an FP32 direction: the arc error of w
+                     * (16 u, doubled) through theta and phi, plus atan2 and scaling */
+                    const double dw = 32.0 * u;
+                    const double rho = sqrt(w[0] * w[0] + w[2] * w[2]);
+                    double bdy = (dw + 8.0 * u * ORC_PI) * (double)E->H / ORC_PI + 4.0 * u * y;
+                    double bdx = (rho > 0.0 ? dw / rho : (double)E->W) * (double)E->W / (2.0 * ORC_PI) +
+                                 8.0 * u * (double)E->W + 4.0 * u * x;
+                    bilinear_shift_bound(E->env, E->H, E->W, x, y, fmin(bdx, (double)E->W),
+                                         fmin(bdy, (double)E->H), dLv);
+                    for (int c = 0; c < 3; ++c) Lb[c] = fabs(Lv[c]) + dLv[c];
+                } else {
+                    const float* Lr = E->env + ((size_t)ti * E->W + tj) * 3;
+                    for (int c = 0; c < 3; ++c) Lv[c] = (double)Lr[c];
+                    if (margin < P->delta_ang) {
+                        flag = 1;
+                        texel_max3(E->env, E->H, E->W, ti, tj, Lb);
+                    } else {
+                        for (int c = 0; c < 3; ++c) Lb[c] = fabs(Lv[c]);
+                    }
+                }
+                /* integrand of c_d and c_s at w, unshadowed (unit density, one
+                 * sample), contracted with the upstream gradients */
+                double gsum = 0.0, gabs = 0.0, gcond = 0.0, gbound = 0.0;
+                {
+                    /* below or at the horizon and undecided: bound the terms
+                     * by those of a direction just above it (they vanish
+                     * continuously at the horizon) */
+                    double we[3];
+                    const int above = NoL > 0.0;
+                    for (int k = 0; k < 3; ++k) we[k] = above ? w[k] : w[k] + (2.0 * P->delta_cos - NoL) * S.n[k];
+                    const double wel = norm3(we);
+                    for (int k = 0; k < 3; ++k) we[k] /= wel;
+                    if (above || flag) {
+                        pix_out po;
+                        env_contrib ec;
+                        memset(&po, 0, sizeof(po));
+                        eval_sample(&S, &S, 1.0f, we, 0.0, Lv, dLv, 1, 1.0, 0, NULL, NULL, &po, &ec, 1.0, 1.0, 1);
+                        for (int c = 0; c < 3; ++c) {
+                            const double td = fabs(ud[c] * po.cd[c]) + fabs(us[c] * po.cs[c]);
+                            const double sl = fabs(Lv[c]) > 0.0 ? Lb[c] / fabs(Lv[c]) : 0.0;
+                            gbound += td * sl;
+                            if (!above) continue;
+                            gsum += ud[c] * po.cd[c] + us[c] * po.cs[c];
+                            gabs += td;
+                            gcond += fabs(ud[c]) * (po.cd_cond[c] + po.cd_lerr[c]) +
+                                     fabs(us[c]) * (po.cs_cond[c] + po.cs_lerr[c]);
+                        }
+                        if (!above) gbound *= 2.0;
+                    }
+                }
+                /* a pixel whose n.v sign is undecided may carry a specular
+                 * term or not: twice the bound covers either */
+                if (nov_near) gbound = 2.0 * gbound + gabs;
+                /* FP32 relative error of the geometric factors: mh through |m|
+                 * against |qa||qb|, J through |(b-a) x w| against |b-a|, the
+                 * differences from the rounded o, and a few roundings */
+                const double lex = norm3(ex), leab = norm3(eab);
+                const double rel_geo = u * (16.0 + la * lb / ml + leab / fmax(lex, 1e-300)) +
+                                       eo * ((la + lb) / ml + (4.0 + leab / fmax(lex, 1e-300)) / rr);
+                const double base = (double)n_edges * P->tau * J / (double)n_es;
+                const double wt = s * base * gsum;
+                const double wcond = base * (gcond + gabs * rel_geo);
+                const double wflag = base * fmax(gbound, gabs) * (1.0 + rel_geo);
+                int blocked = 1;
+                if (sil && NoL > 0.0) {
+                    c5[1]++;
+                    if (wt != 0.0 && isfinite(wt)) {
+                        double wo[3];
+                        for (int k = 0; k < 3; ++k) wo[k] = w[k] - s * ORC_EDGE_DELTA * mh[k];
+                        const double wl = norm3(wo);
+                        for (int k = 0; k < 3; ++k) wo[k] /= wl;
+                        const int h = orc_anyhit(scene, o, wo, P->delta_vis_abs, P->delta_vis_rel, P->brute);
+                        c5[2]++;
+                        if (h == TRI_NEAR) flag = 1;
+                        blocked = h != TRI_MISS;
+                        if (blocked) c5[3]++;
+                    }
+                }
+                if (flag) c5[4]++;
+                const double fa = 1.0 - t, fb = t;
+                for (int k = 0; k < 3; ++k) {
+                    const size_t ia = 3 * (size_t)ed[0] + k, ib = 3 * (size_t)ed[1] + k;
+                    if (!blocked) {
+                        a_v[ia] += wt * fa * mh[k];
+                        a_v[ib] += wt * fb * mh[k];
+                        a_abs[ia] += fabs(wt * fa * mh[k]);
+                        a_abs[ib] += fabs(wt * fb * mh[k]);
+                        a_cond[ia] += wcond * fa * fabs(mh[k]);
+                        a_cond[ib] += wcond * fb * fabs(mh[k]);
+                    }
+                    if (flag) {
+                        a_flag[ia] += wflag * fa;
+                        a_flag[ib] += wflag * fb;
+                    }
+                }
+            }
+        }
+    }
+    for (int tid = 0; tid < nt; ++tid) {
+        const double* a = acc + (size_t)tid * 4 * nv3;
+        for (size_t i = 0; i < nv3; ++i) {
+            gv[i] += a[i];
+            gv_abs[i] += a[nv3 + i];
+            gv_cond[i] += a[2 * nv3 + i];
+            gv_flag[i] += a[3 * nv3 + i];
+        }
+        for (int k = 0; k < 5; ++k) counts[k] += cnt[tid * 5 + k];
+    }
+    free(acc);
+    free(cnt);
+    return 0;
 }
