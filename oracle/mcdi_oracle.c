@@ -1526,39 +1526,51 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
                 const int64_t e = (int64_t)(((uint64_t)r[0] * (uint64_t)n_edges) >> 32);
                 const double t = u01(r[1]);
                 const int32_t* ed = edges + 4 * e;
-                double qa[3], qb[3], qc[3], qd[3] = {0, 0, 0};
+                /* the face sides come from the determinant det(a - o, b - o,
+                 * c - o) written with edge vectors, (a - o) . ((b - a) x
+                 * (c - a)): the same number, without the cancellation of
+                 * differences from a distant o */
+                double A[3], qa[3], eab[3], eac[3], ead[3] = {0, 0, 0};
                 for (int k = 0; k < 3; ++k) {
-                    qa[k] = (double)verts[3 * (size_t)ed[0] + k] - o[k];
-                    qb[k] = (double)verts[3 * (size_t)ed[1] + k] - o[k];
-                    qc[k] = (double)verts[3 * (size_t)ed[2] + k] - o[k];
-                    if (ed[3] >= 0) qd[k] = (double)verts[3 * (size_t)ed[3] + k] - o[k];
+                    A[k] = (double)verts[3 * (size_t)ed[0] + k];
+                    qa[k] = A[k] - o[k];
+                    eab[k] = (double)verts[3 * (size_t)ed[1] + k] - A[k];
+                    eac[k] = (double)verts[3 * (size_t)ed[2] + k] - A[k];
+                    if (ed[3] >= 0) ead[k] = (double)verts[3 * (size_t)ed[3] + k] - A[k];
                 }
-                double m[3];
-                cross3(qa, qb, m);
-                const double la = norm3(qa), lb = norm3(qb), lc = norm3(qc), ld = norm3(qd);
-                /* FP32 error bound of a triple product of differences from o
-                 * (o itself rounded to FP32), with a factor 4 margin */
-                const double eo = 32.0 * u * olen;
-                const double tc = 128.0 * u * la * lb * lc + eo * (la * lb + lb * lc + lc * la);
-                const double td = 128.0 * u * la * lb * ld + eo * (la * lb + lb * ld + ld * la);
-                const double sc = dot3(m, qc);
-                const double sd = ed[3] >= 0 ? dot3(m, qd) : 0.0;
+                double m[3], nc[3], nd[3] = {0, 0, 0};
+                cross3(qa, eab, m);                  /* = (a - o) x (b - o) */
+                cross3(eab, eac, nc);
+                if (ed[3] >= 0) cross3(eab, ead, nd);
+                const double la = norm3(qa), leab = norm3(eab);
+                /* FP32 error of (a - o) . (e1 x e2): the cross product of the
+                 * edge vectors is off by at most 4 u |e1||e2| (inputs and
+                 * roundings), a - o by u (|a - o| + |o|), the dot product by
+                 * 3 u |a - o| |e1 x e2|: below (8 u |a - o| + u |o|) |e1||e2|;
+                 * the band takes four times that */
+                const double tc = (32.0 * u * la + 4.0 * u * olen) * leab * norm3(eac);
+                const double td = (32.0 * u * la + 4.0 * u * olen) * leab * norm3(ead);
+                const double eo = 32.0 * u * olen;   /* generous o error for the value bounds below */
+                const double sc = dot3(qa, nc);
+                const double sd = ed[3] >= 0 ? dot3(qa, nd) : 0.0;
                 int flag = nov_near;
                 if (fabs(sc) <= tc) flag = 1;
                 if (ed[3] >= 0 && fabs(sd) <= td) flag = 1;
                 if (sc == 0.0) continue;
                 const int sil = ed[3] < 0 || !((sc > 0.0 && sd < 0.0) || (sc < 0.0 && sd > 0.0));
                 if (!sil && !flag) continue;
-                double w[3], eab[3];
-                for (int k = 0; k < 3; ++k) {
-                    eab[k] = qb[k] - qa[k];
-                    w[k] = qa[k] + t * eab[k];
-                }
+                double w[3];
+                for (int k = 0; k < 3; ++k) w[k] = qa[k] + t * eab[k];
                 const double r2 = dot3(w, w), rr = sqrt(r2);
                 for (int k = 0; k < 3; ++k) w[k] /= rr;
                 const double NoL = dot3(S.n, w);
-                if (fabs(NoL) < P->delta_cos) flag = 1;
-                if (NoL <= 0.0 && !flag) continue;
+                /* bound on the FP32 error of the direction w (radians): a few
+                 * roundings plus o's own rounding seen from distance r */
+                const double wband = 16.0 * u + 4.0 * u * olen / rr;
+                /* robustly below the horizon: no term, whatever else is undecided */
+                const int nol_near = fabs(NoL) < wband;
+                if (NoL <= 0.0 && !nol_near) continue;
+                if (nol_near) flag = 1;
                 const double ml = norm3(m);
                 if (ml == 0.0) continue;
                 double mh[3];
@@ -1587,7 +1599,7 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
                 } else {
                     const float* Lr = E->env + ((size_t)ti * E->W + tj) * 3;
                     for (int c = 0; c < 3; ++c) Lv[c] = (double)Lr[c];
-                    if (margin < P->delta_ang) {
+                    if (margin < 2.0 * wband + 64.0 * u) {
                         flag = 1;
                         texel_max3(E->env, E->H, E->W, ti, tj, Lb);
                     } else {
@@ -1599,11 +1611,11 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
                 double gsum = 0.0, gabs = 0.0, gcond = 0.0, gbound = 0.0;
                 {
                     /* below or at the horizon and undecided: bound the terms
-                     * by those of a direction just above it (they vanish
-                     * continuously at the horizon) */
+                     * by those of the highest direction the FP32 one can be
+                     * (they vanish continuously at the horizon) */
                     double we[3];
                     const int above = NoL > 0.0;
-                    for (int k = 0; k < 3; ++k) we[k] = above ? w[k] : w[k] + (2.0 * P->delta_cos - NoL) * S.n[k];
+                    for (int k = 0; k < 3; ++k) we[k] = above ? w[k] : w[k] + (wband - NoL) * S.n[k];
                     const double wel = norm3(we);
                     for (int k = 0; k < 3; ++k) we[k] /= wel;
                     if (above || flag) {
@@ -1628,11 +1640,15 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
                  * term or not: twice the bound covers either */
                 if (nov_near) gbound = 2.0 * gbound + gabs;
                 /* FP32 relative error of the geometric factors: mh through |m|
-                 * against |qa||qb|, J through |(b-a) x w| against |b-a|, the
+                 * against |a - o||b - a|, J through |(b-a) x w| against |b-a|, the
                  * differences from the rounded o, and a few roundings */
-                const double lex = norm3(ex), leab = norm3(eab);
-                const double rel_geo = u * (16.0 + la * lb / ml + leab / fmax(lex, 1e-300)) +
-                                       eo * ((la + lb) / ml + (4.0 + leab / fmax(lex, 1e-300)) / rr);
+                const double lex = norm3(ex);
+                const double rel_geo = u * (16.0 + la * leab / ml + leab / fmax(lex, 1e-300)) +
+                                       eo * (leab / ml + (4.0 + leab / fmax(lex, 1e-300)) / rr);
+                /* undecided band of the out-side ray: o's FP32 rounding plus
+                 * the direction's error (and the triangle test's rounding)
+                 * times the distance along the ray */
+                const double vis_abs = 8.0 * u * olen, vis_rel = 2.0 * wband + 32.0 * u;
                 const double base = (double)n_edges * P->tau * J / (double)n_es;
                 const double wt = s * base * gsum;
                 const double wcond = base * (gcond + gabs * rel_geo);
@@ -1645,12 +1661,28 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
                         for (int k = 0; k < 3; ++k) wo[k] = w[k] - s * ORC_EDGE_DELTA * mh[k];
                         const double wl = norm3(wo);
                         for (int k = 0; k < 3; ++k) wo[k] /= wl;
-                        const int h = orc_anyhit(scene, o, wo, P->delta_vis_abs, P->delta_vis_rel, P->brute);
+                        const int h = orc_anyhit(scene, o, wo, vis_abs, vis_rel, P->brute);
                         c5[2]++;
                         if (h == TRI_NEAR) flag = 1;
                         blocked = h != TRI_MISS;
                         if (blocked) c5[3]++;
                     }
+                }
+                /* an undecided sample whose out-side rays (either side when
+                 * the face's side itself is undecided) are robustly blocked
+                 * adds nothing on either side of its undecided steps */
+                if (flag) {
+                    const int both = fabs(sc) <= tc;
+                    int all_hit = 1;
+                    for (int side = 0; side < (both ? 2 : 1) && all_hit; ++side) {
+                        const double ss = side == 0 ? s : -s;
+                        double wo[3];
+                        for (int k = 0; k < 3; ++k) wo[k] = w[k] - ss * ORC_EDGE_DELTA * mh[k];
+                        const double wl = norm3(wo);
+                        for (int k = 0; k < 3; ++k) wo[k] /= wl;
+                        all_hit = orc_anyhit(scene, o, wo, vis_abs, vis_rel, P->brute) == TRI_HIT;
+                    }
+                    if (all_hit) flag = 0;
                 }
                 if (flag) c5[4]++;
                 const double fa = 1.0 - t, fb = t;
