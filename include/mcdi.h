@@ -229,6 +229,74 @@ mcdi_status mcdi_trace_anyhit(mcdi_scene scene, const float* orig, const float* 
                               uint8_t* hit, int32_t brute, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Visibility gradients of the shadow term (section 3.1 "Shadow gradients";
+ * the appendix "Visibility Gradients from Shadows"): the derivative of the
+ * shadowed direct-illumination integral with respect to the vertex positions
+ * of the occluding mesh, which mcdi_shade_bwd leaves out (detached
+ * visibility).  Estimated by edge sampling: seen from the shadow-ray origin,
+ * the directions a triangle blocks are bounded by the arcs of its edges, and
+ * the derivative of the integral is an integral along the silhouette arcs of
+ * the jump of the integrand times the arcs' normal velocity.
+ *
+ * mcdi_edges: the mesh's unique edges, built on the device.
+ *   tris     device int32 [n_tris][3], the index buffer of mcdi_build_scene
+ * Rows (a, b, c, d) int32, one per undirected edge, in order of first
+ * appearance: triangle f's side k runs from corner k to corner k+1 (sides
+ * in f-major, k-minor order); a-b is the edge as its first side has it, c
+ * the opposite corner of that face, d the opposite corner of the second face
+ * with the edge, or -1 (boundary edge; faces after the second are ignored).
+ * A triangle with a corner outside [0, n_verts) adds no edge, nor does a side
+ * whose corners coincide.  tris is read only by the build's stream work.
+ * Limits: n_verts < 2^31, n_tris < 2^26.
+ * ------------------------------------------------------------------------- */
+typedef struct mcdi_edges_s* mcdi_edges;
+
+mcdi_status mcdi_build_edges(const int32_t* tris, int64_t n_tris, int64_t n_verts, const mcdi_allocator* alloc,
+                             void* stream, mcdi_edges* out);
+
+/* Frees the handle's memory in stream order on the stream it was built on. */
+void mcdi_destroy_edges(mcdi_edges edges);
+
+/* Synchronises the handle's stream; *n_edges = number of rows E. */
+mcdi_status mcdi_edges_count(mcdi_edges edges, int64_t* n_edges);
+
+/* Synchronises the handle's stream, then copies the E x 4 rows into a caller
+ * device int32 buffer in stream order on `stream`. */
+mcdi_status mcdi_edges_copy(mcdi_edges edges, int32_t* rows, void* stream);
+
+/* Edge-sampled visibility gradient of sum over pixels of g_cd . c_d +
+ * g_cs . c_s with respect to the vertex positions.
+ *   scene, edges  built from the same mesh; verts device float32
+ *                 [n_verts][3] are its vertex positions (n_verts must equal
+ *                 the count the edges were built with)
+ *   params        seed, tau, ray_eps and MCDI_FLAG_BILINEAR as in the forward
+ *                 pass (the other technique flags do not apply; spp is
+ *                 validated but unused)
+ *   edge_spp      edge samples per pixel, 1..1024
+ *   g_cd, g_cs    device [3][N] upstream gradients
+ *   g_verts       device float32 [n_verts][3], ACCUMULATED (+=); the caller
+ *                 zeroes it
+ *   stats         valid_pixels, invalid_pixels, rays_traced (out-side rays)
+ *                 and rays_hit are accumulated, or NULL
+ * Per pixel and edge sample j: Philox4x32-10 with key = seed and counter =
+ * (pixel in view, view_base + view, j, 2) gives x0..x3; the edge is row
+ * (x0 * E) >> 32 and the point on it x(t) = a + t (b - a) with t = the 24-bit
+ * uniform of x1.  From the shadow-ray origin o = p + ray_eps n, with
+ * r = |x - o|, w = (x - o)/r and m = (a - o) x (b - o): a sample counts when
+ * the edge is a silhouette (d = -1, or c and d not strictly on opposite sides
+ * of the plane through o with normal m), n.w > 0, and the out-side ray from
+ * o along w turned by 2^-13 radians away from the face misses the mesh.  It
+ * adds E s tau g(w) |(b - a) x w| / (r^2 edge_spp) times (1 - t) m/|m| to
+ * vertex a and t m/|m| to vertex b, where s = the sign of m . (c - o) and g
+ * is the unshadowed integrand of c_d and c_s at w contracted with g_cd and
+ * g_cs.  G-buffer positions are held fixed (the receivers do not move).
+ * Summation order of g_verts is not deterministic (float atomics). */
+mcdi_status mcdi_shade_bwd_edges(mcdi_scene scene, mcdi_env env, mcdi_edges edges, const float* verts,
+                                 int64_t n_verts, const mcdi_gbuffer* gbuf, const mcdi_params* params,
+                                 int32_t edge_spp, const float* g_cd, const float* g_cs, float* g_verts,
+                                 mcdi_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Image loss on the estimator's outputs (appendix A): composition
  * c = kd*c_d + c_s (section 4.2), L1 on tonemapped colours with
  * T(x) = sRGB(log(max(x,0) + 1)), and the light regulariser

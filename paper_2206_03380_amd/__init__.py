@@ -14,8 +14,8 @@ from . import _lib as L
 from ._lib import (MCDIError, FLAG_LIGHT_OFF, FLAG_FORCE_COS, FLAG_BSDF_OFF, FLAG_FORCE_GGX, FLAG_BILINEAR,  # noqa: F401
                    FLAG_DUMP, FLAG_TIME_TRACE)
 
-__all__ = ["Scene", "Env", "GBuffer", "shade_fwd", "shade_bwd", "trace_anyhit", "MCDIShade",
-           "MCDIError", "new_stats", "read_stats"]
+__all__ = ["Scene", "Env", "GBuffer", "Edges", "shade_fwd", "shade_bwd", "shade_bwd_edges", "trace_anyhit",
+           "MCDIShade", "MCDIError", "new_stats", "read_stats"]
 
 
 def _ptr(t):
@@ -240,6 +240,67 @@ def shade_bwd(scene, env, gb, spp, g_cd, g_cs, hitbits=None, seed=0, tau=1.0, ra
                                    _ptr(hitbits), _ptr(g_kd), _ptr(g_korm), _ptr(g_nrm), _ptr(g_env),
                                    _ptr(stats), _stream(stream)))
     return g_kd, g_korm, g_nrm, g_env
+
+
+class Edges:
+    """Unique edges of a triangle mesh (device int32 [Nt,3] indices over Nv
+    vertices) with the opposite corners of their faces, for the edge-sampled
+    visibility gradient."""
+
+    def __init__(self, tris, n_verts, stream=None, use_torch_allocator=True):
+        _need(tris, torch.int32, name="tris")
+        if tris.dim() != 2 or tris.shape[1] != 3:
+            raise ValueError("tris must be [Nt,3]")
+        h = C.c_void_p()
+        L.check(L.lib().mcdi_build_edges(_ptr(tris), tris.shape[0], int(n_verts),
+                                         C.byref(_TORCH_ALLOCATOR) if use_torch_allocator else None,
+                                         _stream(stream), C.byref(h)))
+        self.handle = h
+        self.n_verts = int(n_verts)
+
+    def count(self):
+        n = C.c_int64()
+        L.check(L.lib().mcdi_edges_count(self.handle, C.byref(n)))
+        return n.value
+
+    def rows(self, stream=None):
+        """The edge rows (a, b, c, d) as a device int32 [E, 4] tensor."""
+        n = self.count()
+        out = torch.empty((n, 4), dtype=torch.int32, device=torch.device("cuda", torch.cuda.current_device()))
+        if n > 0:
+            L.check(L.lib().mcdi_edges_copy(self.handle, _ptr(out), _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib().mcdi_destroy_edges(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def shade_bwd_edges(scene, env, edges, verts, gb, edge_spp, g_cd, g_cs, seed=0, tau=1.0, ray_eps=1e-3, flags=0,
+                    g_verts=None, stats=None, stream=None):
+    """Edge-sampled visibility gradient of the shadow term with respect to the
+    vertex positions verts [Nv,3] (the mesh of scene and edges).  Returns
+    g_verts [Nv,3], accumulated into if given, else a zeroed tensor."""
+    n = gb.n
+    _need(verts, torch.float32, name="verts")
+    _need(g_cd, torch.float32, (3, n), "g_cd")
+    _need(g_cs, torch.float32, (3, n), "g_cs")
+    if g_verts is None:
+        g_verts = torch.zeros(verts.shape, dtype=torch.float32, device=verts.device)
+    _need(g_verts, torch.float32, tuple(verts.shape), "g_verts")
+    gs = gb.struct()
+    prm = _params(1, seed, tau, ray_eps, flags, None)
+    L.check(L.lib().mcdi_shade_bwd_edges(scene.handle, env.handle, edges.handle, _ptr(verts), verts.shape[0],
+                                         C.byref(gs), C.byref(prm), int(edge_spp), _ptr(g_cd), _ptr(g_cs),
+                                         _ptr(g_verts), _ptr(stats), _stream(stream)))
+    return g_verts
 
 
 def trace_times():

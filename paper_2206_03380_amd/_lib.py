@@ -119,6 +119,17 @@ def lib():
     L.mcdi_bilateral_bwd.argtypes = [C.POINTER(BilateralGuide), C.c_int32, vp, vp, vp, vp]
     L.mcdi_view_depth.restype = C.c_int
     L.mcdi_view_depth.argtypes = [C.POINTER(GBuffer), vp, vp]
+    L.mcdi_build_edges.restype = C.c_int
+    L.mcdi_build_edges.argtypes = [vp, C.c_int64, C.c_int64, vp, vp, C.POINTER(vp)]
+    L.mcdi_destroy_edges.restype = None
+    L.mcdi_destroy_edges.argtypes = [vp]
+    L.mcdi_edges_count.restype = C.c_int
+    L.mcdi_edges_count.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.mcdi_edges_copy.restype = C.c_int
+    L.mcdi_edges_copy.argtypes = [vp, vp, vp]
+    L.mcdi_shade_bwd_edges.restype = C.c_int
+    L.mcdi_shade_bwd_edges.argtypes = [vp, vp, vp, vp, C.c_int64, C.POINTER(GBuffer), C.POINTER(Params), C.c_int32,
+                                       vp, vp, vp, vp, vp]
     L.mcdi_last_error.restype = C.c_char_p
     L.mcdi_version.restype = C.c_char_p
     _lib = L
@@ -134,4 +145,5 @@ EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_s
             "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
             "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_server_create", "mcdi_server_launch",
             "mcdi_server_destroy", "mcdi_image_loss", "mcdi_bilateral_radius", "mcdi_bilateral_fwd",
-            "mcdi_bilateral_bwd", "mcdi_view_depth", "mcdi_last_error", "mcdi_version")
+            "mcdi_bilateral_bwd", "mcdi_view_depth", "mcdi_build_edges", "mcdi_destroy_edges", "mcdi_edges_count",
+            "mcdi_edges_copy", "mcdi_shade_bwd_edges", "mcdi_last_error", "mcdi_version")

@@ -682,4 +682,138 @@ mcdi_status mcdi_trace_anyhit(mcdi_scene sc, const float* orig, const float* dir
     return ok();
 }
 
+struct mcdi_edges_s {
+    Alloc alloc;
+    hipStream_t stream = nullptr;
+    int64_t n_verts = 0, n_tris = 0;
+    int4* rows = nullptr;        // [max(3 n_tris, 1)]
+    uint32_t* count = nullptr;   // E
+};
+
+mcdi_status mcdi_build_edges(const int32_t* tris, int64_t n_tris, int64_t n_verts, const mcdi_allocator* alloc,
+                             void* stream, mcdi_edges* out) {
+    if (!out) return fail(MCDI_E_INVALID, "mcdi_build_edges: out is NULL");
+    if (n_verts < 0 || n_tris < 0) return fail(MCDI_E_INVALID, "mcdi_build_edges: negative count");
+    if (n_verts >= (int64_t)1 << 31) return fail(MCDI_E_UNSUPPORTED, "mcdi_build_edges: n_verts >= 2^31");
+    if (n_tris >= (int64_t)1 << 26) return fail(MCDI_E_UNSUPPORTED, "mcdi_build_edges: n_tris >= 2^26");
+    if (n_tris > 0 && !tris) return fail(MCDI_E_INVALID, "mcdi_build_edges: NULL tris");
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(MCDI_E_INVALID, "mcdi_build_edges: allocator incomplete");
+    hipStream_t s = (hipStream_t)stream;
+    mcdi_edges ed = new (std::nothrow) mcdi_edges_s;
+    if (!ed) return fail(MCDI_E_OOM, "mcdi_build_edges: host allocation failed");
+    ed->alloc = make_alloc(alloc);
+    ed->stream = s;
+    ed->n_verts = n_verts;
+    ed->n_tris = n_tris;
+    const int64_t sides = 3 * n_tris;
+    ed->rows = (int4*)ed->alloc.get(sizeof(int4) * (size_t)(sides > 0 ? sides : 1), s);
+    ed->count = (uint32_t*)ed->alloc.get(sizeof(uint32_t), s);
+    const int bits = edge_table_bits(sides);
+    const size_t slots = (size_t)1 << bits;
+    const uint32_t nb = edge_scan_blocks(sides);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t sz_keys = al(sizeof(unsigned long long) * slots), sz_slot = al(sizeof(uint32_t) * slots);
+    const size_t sz_of = al(sizeof(uint32_t) * (size_t)(sides > 0 ? sides : 1));
+    const size_t sz_b = al(sizeof(uint32_t) * ((size_t)nb + 1));
+    void* tmp = ed->rows && ed->count ? ed->alloc.get(sz_keys + 2 * sz_slot + sz_of + sz_b, s) : nullptr;
+    if (!tmp) {
+        mcdi_destroy_edges(ed);
+        return fail(MCDI_E_OOM, "mcdi_build_edges: device allocation failed (%lld triangles)", (long long)n_tris);
+    }
+    char* p = (char*)tmp;
+    unsigned long long* keys = (unsigned long long*)p;
+    uint32_t* first = (uint32_t*)(p + sz_keys);
+    uint32_t* second = (uint32_t*)(p + sz_keys + sz_slot);
+    uint32_t* slot_of = (uint32_t*)(p + sz_keys + 2 * sz_slot);
+    uint32_t* bsum = (uint32_t*)(p + sz_keys + 2 * sz_slot + sz_of);
+    hipError_t e = launch_edges_build(tris, n_tris, n_verts, bits, keys, first, second, slot_of, bsum, ed->rows,
+                                      ed->count, s);
+    ed->alloc.put(tmp, s);
+    if (e != hipSuccess) {
+        mcdi_destroy_edges(ed);
+        return fail(MCDI_E_DEVICE, "mcdi_build_edges: %s", hipGetErrorString(e));
+    }
+    *out = ed;
+    return ok();
+}
+
+void mcdi_destroy_edges(mcdi_edges ed) {
+    if (!ed) return;
+    ed->alloc.put(ed->rows, ed->stream);
+    ed->alloc.put(ed->count, ed->stream);
+    delete ed;
+}
+
+mcdi_status mcdi_edges_count(mcdi_edges ed, int64_t* n_edges) {
+    if (!ed || !n_edges) return fail(MCDI_E_INVALID, "mcdi_edges_count: NULL argument");
+    uint32_t h = 0;
+    hipError_t e = hipStreamSynchronize(ed->stream);
+    if (e == hipSuccess) e = hipMemcpy(&h, ed->count, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_edges_count: %s", hipGetErrorString(e));
+    *n_edges = (int64_t)h;
+    return ok();
+}
+
+mcdi_status mcdi_edges_copy(mcdi_edges ed, int32_t* rows, void* stream) {
+    if (!ed || !rows) return fail(MCDI_E_INVALID, "mcdi_edges_copy: NULL argument");
+    int64_t n = 0;
+    mcdi_status st = mcdi_edges_count(ed, &n);
+    if (st != MCDI_OK) return st;
+    if (n == 0) return ok();
+    hipError_t e = hipMemcpyAsync(rows, ed->rows, sizeof(int4) * (size_t)n, hipMemcpyDeviceToDevice,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_edges_copy: %s", hipGetErrorString(e));
+    return ok();
+}
+
+mcdi_status mcdi_shade_bwd_edges(mcdi_scene sc, mcdi_env ev, mcdi_edges ed, const float* verts, int64_t n_verts,
+                                 const mcdi_gbuffer* g, const mcdi_params* p, int32_t edge_spp, const float* g_cd,
+                                 const float* g_cs, float* g_verts, mcdi_stats* stats, void* stream) {
+    ShadeArgs a;
+    mcdi_status st = fill_common("mcdi_shade_bwd_edges", sc, ev, g, p, a);
+    if (st != MCDI_OK) return st;
+    if (p->flags & MCDI_FLAG_DUMP) return fail(MCDI_E_INVALID, "mcdi_shade_bwd_edges: MCDI_FLAG_DUMP is forward-only");
+    if (!ed) return fail(MCDI_E_INVALID, "mcdi_shade_bwd_edges: NULL edges");
+    if (n_verts != ed->n_verts)
+        return fail(MCDI_E_INVALID, "mcdi_shade_bwd_edges: n_verts %lld differs from the edges' %lld",
+                    (long long)n_verts, (long long)ed->n_verts);
+    if (edge_spp < 1 || edge_spp > 1024)
+        return fail(MCDI_E_INVALID, "mcdi_shade_bwd_edges: edge_spp must be in [1, 1024]");
+    if (!g_cd || !g_cs || (n_verts > 0 && (!verts || !g_verts)))
+        return fail(MCDI_E_INVALID, "mcdi_shade_bwd_edges: NULL buffer");
+    if (a.tau == 0.0f || ed->n_tris == 0) return ok();
+    hipStream_t s = (hipStream_t)stream;
+    a.g_cd = g_cd;
+    a.g_cs = g_cs;
+    a.stats = stats;
+    EdgeArgs E;
+    std::memset(&E, 0, sizeof(E));
+    E.a = a;
+    E.edges = ed->rows;
+    E.n_edges = ed->count;
+    E.verts = verts;
+    E.g_verts = g_verts;
+    E.n_es = edge_spp;
+    // pixels per pass: every sample of a pass fits the queue
+    const int64_t per = ((int64_t)(kEdgeQueueMax / (uint32_t)edge_spp) / kBlock) * kBlock;
+    const int64_t n = a.g.n;
+    const int64_t chunk = per < n ? per : ((n + kBlock - 1) / kBlock) * kBlock;
+    E.q_cap = (uint32_t)(chunk * edge_spp);
+    Workspace ws;
+    ws.alloc = &sc->alloc;
+    ws.s = s;
+    const size_t sz_q = ((sizeof(float4) * 3 * (size_t)E.q_cap) + 255) & ~(size_t)255;
+    ws.base = sc->alloc.get(sz_q + 256, s);
+    if (!ws.base) return fail(MCDI_E_OOM, "mcdi_shade_bwd_edges: workspace allocation failed");
+    E.queue = (float4*)ws.base;
+    E.q_count = (uint32_t*)((char*)ws.base + sz_q);
+    for (int64_t p0 = 0; p0 < n; p0 += chunk) {
+        E.pix0 = p0;
+        E.npix = n - p0 < chunk ? n - p0 : chunk;
+        hipError_t e = launch_edge_grad(E, s);
+        if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd_edges: %s", hipGetErrorString(e));
+    }
+    return ok();
+}
+
 }  // extern "C"

@@ -906,6 +906,199 @@ __global__ void trace_kernel(Scene sc, const float* o, const float* d, int64_t n
     hit[k] = (brute ? brute_anyhit(sc, r) : bvh_anyhit(sc, r, n_total, nb, nt)) ? 1 : 0;
 }
 
+// ---------------------------------------------------------------------------
+// Edge-sampled visibility gradient of the shadow term.  Seen from the ray
+// origin o, a silhouette edge a-b bounds the directions its face blocks; as
+// the vertices move, the arc through x(t) = a + t (b - a) moves along the
+// unit normal mh of the plane (o, a, b) at mh . dx / r, r = |x - o|, and
+// sweeps |(b - a) x w| / r of arc per unit t.  Across the arc the integrand
+// drops from g to g (1 - tau) when nothing else blocks the out side, so a
+// sample (edge e uniform over E, t uniform) adds
+//   E s tau g(w) |(b - a) x w| / r^2 / n_es  x  ((1 - t) mh, t mh)
+// to the gradients of a and b, s = +1 when the face lies on the +mh side.
+// Silhouette: the edge's two faces lie on the same side of the plane (or it
+// has one face).  g contracts the unshadowed integrand of c_d and c_s with
+// the upstream gradients.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float3 load_vert(const float* v, int32_t i) {
+    const float* p = v + 3 * (size_t)i;
+    return f3(p[0], p[1], p[2]);
+}
+
+__device__ __forceinline__ float3 cross(float3 a, float3 b) {
+    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// probe radiance in direction w (nearest texel, or bilinear with BIL)
+__device__ __forceinline__ float3 probe_radiance(const EnvView& e, float3 w, bool bil) {
+    const int H = e.H, W = e.W;
+    const float rho = sqrtf(w.x * w.x + w.z * w.z);
+    const float th = atan2f(rho, w.y);
+    float ph = atan2f(w.z, w.x);
+    if (ph < 0.0f) ph += 2.0f * kPi;
+    const float y = th * ((float)H * kInvPi);
+    const float x = ph * ((float)W * (0.5f * kInvPi));
+    if (bil) {
+        const Taps T = bilinear_taps(e, x, y);
+        return T.w[0] * texel_rgb(e, T.t[0]) + T.w[1] * texel_rgb(e, T.t[1]) + T.w[2] * texel_rgb(e, T.t[2]) +
+               T.w[3] * texel_rgb(e, T.t[3]);
+    }
+    const int ti = min((int)y, H - 1), tj = min((int)x, W - 1);
+    return texel_rgb(e, ti * W + tj);
+}
+
+__global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
+    const ShadeArgs& A = E.a;
+    const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t pix = E.pix0 + local;
+    const bool active = local < E.npix && pix < A.g.n;
+    const uint32_t ne = *E.n_edges;
+    bool nonfinite = false;
+    Pixel P;
+    P.valid = false;
+    if (active) P = setup_pixel(A, pix, nonfinite);
+    const bool go = P.valid && ne > 0u && A.tau != 0.0f;
+    const bool bil = (A.flags & MCDI_FLAG_BILINEAR) != 0;
+    const int64_t N = A.g.n;
+    const int64_t hw = (int64_t)A.g.height * A.g.width;
+    const uint32_t view = active ? (uint32_t)(pix / hw) : 0u;
+    const uint32_t piv = active ? (uint32_t)(pix - (int64_t)view * hw) : 0u;
+    const uint32_t vid = (uint32_t)A.g.view_base + view;
+    const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
+    float3 Ud = f3(0, 0, 0), Us = Ud;
+    if (go) {
+        Ud = f3(A.g_cd[pix], A.g_cd[N + pix], A.g_cd[2 * N + pix]);
+        Us = f3(A.g_cs[pix], A.g_cs[N + pix], A.g_cs[2 * N + pix]);
+    }
+    const int lane = __lane_id();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const float scale = (float)ne * A.tau / (float)E.n_es;
+    for (int j = 0; j < E.n_es; ++j) {
+        bool emit = false;
+        float4 q0, q1, q2;
+        if (go) {
+            const uint4 r = philox10(make_uint4(piv, vid, (uint32_t)j, 2u), k0, k1);
+            const uint32_t e = __umulhi(r.x, ne);
+            const float t = u01(r.y);
+            const int4 ed = E.edges[e];
+            // face sides: det(a - o, b - o, c - o) as (a - o) . ((b - a) x
+            // (c - a)), free of the cancellation of differences from a
+            // distant o
+            const float3 va = load_vert(E.verts, ed.x);
+            const float3 qa = va - P.o, eab = load_vert(E.verts, ed.y) - va;
+            const float3 m = cross(qa, eab);   // = (a - o) x (b - o)
+            const float sc = dot(qa, cross(eab, load_vert(E.verts, ed.z) - va));
+            bool sil = sc != 0.0f;
+            if (sil && ed.w >= 0) {
+                const float sd = dot(qa, cross(eab, load_vert(E.verts, ed.w) - va));
+                sil = !((sc > 0.0f && sd < 0.0f) || (sc < 0.0f && sd > 0.0f));
+            }
+            const float ml2 = dot(m, m);
+            if (sil && ml2 > 0.0f) {
+                float3 w = qa + t * eab;
+                const float r2 = dot(w, w);
+                w = (1.0f / sqrtf(r2)) * w;
+                const float NoL = dot(w, P.n);
+                if (NoL > 0.0f) {
+                    const float3 mh = (1.0f / sqrtf(ml2)) * m;
+                    const float s = sc > 0.0f ? 1.0f : -1.0f;
+                    const float3 ex = cross(eab, w);
+                    const float J = sqrtf(dot(ex, ex)) / r2;
+                    const float3 L = probe_radiance(A.env, w, bil);
+                    // unshadowed integrand at w (unit density), contracted
+                    const float3 wl = f3(dot(w, P.t), dot(w, P.b), NoL);
+                    const float kdiff = (1.0f - P.m) * kInvPi * NoL;
+                    float g = kdiff * (Ud.x * L.x + Ud.y * L.y + Ud.z * L.z);
+                    if (P.nov_pos) {
+                        const float3 hl = normalize(P.Vl + wl);
+                        const float s2 = hl.x * hl.x + hl.y * hl.y;
+                        const float D = ggx_D(hl.z, s2, P.a2);
+                        const float lamL = smith_lambda(smith_t2(NoL), P.a2);
+                        const float Sv = D / (1.0f + P.lamV + lamL) / (4.0f * P.nov);
+                        const float omv = 1.0f - dot(P.Vl, hl);
+                        const float o2 = omv * omv;
+                        const float Fw = o2 * o2 * omv;
+                        const float3 F = f3(P.F0.x + (1.0f - P.F0.x) * Fw, P.F0.y + (1.0f - P.F0.y) * Fw,
+                                            P.F0.z + (1.0f - P.F0.z) * Fw);
+                        g += Sv * (Us.x * F.x * L.x + Us.y * F.y * L.y + Us.z * F.z * L.z);
+                    }
+                    const float wt = s * scale * J * g;
+                    if (wt != 0.0f && isfinite(wt)) {
+                        const float3 wo = normalize(w - (s * kEdgeDelta) * mh);
+                        q0 = make_float4(P.o.x, P.o.y, P.o.z, __uint_as_float(e));
+                        q1 = make_float4(wo.x, wo.y, wo.z, t);
+                        q2 = make_float4(wt * mh.x, wt * mh.y, wt * mh.z, 0.0f);
+                        emit = true;
+                    }
+                }
+            }
+        }
+        const uint64_t bal = __ballot(emit);
+        if (bal == 0ull) continue;
+        const int leader = __ffsll((unsigned long long)bal) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(E.q_count, (uint32_t)__popcll(bal));
+        base = (uint32_t)__shfl((int)base, leader);
+        if (emit) {
+            const uint32_t at = base + (uint32_t)__popcll(bal & lt);
+            // the queue holds every sample of the pass; the check only
+            // guards the bound
+            if (at < E.q_cap) {
+                E.queue[3 * (size_t)at] = q0;
+                E.queue[3 * (size_t)at + 1] = q1;
+                E.queue[3 * (size_t)at + 2] = q2;
+            }
+        }
+    }
+    if (A.stats) {
+        const uint32_t v = wave_sum(P.valid ? 1u : 0u), nf = wave_sum(nonfinite ? 1u : 0u);
+        if (lane == 0) {
+            atomicAdd(&A.stats->valid_pixels, (unsigned long long)v);
+            atomicAdd(&A.stats->invalid_pixels, (unsigned long long)nf);
+        }
+    }
+}
+
+// out-side rays of the queued samples; a ray that reaches the probe adds the
+// sample's term to both vertices of its edge
+__global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
+    const Scene& sc = E.a.scene;
+    const uint32_t n = min(*E.q_count, E.q_cap);
+    const int n_total = sc.nodes[0].escape;
+    uint32_t c_rays = 0, c_hits = 0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float4 q0 = E.queue[3 * (size_t)i], q1 = E.queue[3 * (size_t)i + 1], q2 = E.queue[3 * (size_t)i + 2];
+        const Ray r = make_ray(f3(q0.x, q0.y, q0.z), f3(q1.x, q1.y, q1.z));
+        uint32_t nb = 0, nt = 0;
+        const bool hit = n_total > 0 && bvh_anyhit(sc, r, n_total, nb, nt);
+        ++c_rays;
+        if (hit) {
+            ++c_hits;
+            continue;
+        }
+        const int4 ed = E.edges[__float_as_uint(q0.w)];
+        const float t = q1.w, ta = 1.0f - t;
+        float* ga = E.g_verts + 3 * (size_t)ed.x;
+        float* gb = E.g_verts + 3 * (size_t)ed.y;
+        atomicAdd(ga + 0, ta * q2.x);
+        atomicAdd(ga + 1, ta * q2.y);
+        atomicAdd(ga + 2, ta * q2.z);
+        atomicAdd(gb + 0, t * q2.x);
+        atomicAdd(gb + 1, t * q2.y);
+        atomicAdd(gb + 2, t * q2.z);
+    }
+    if (E.a.stats) {
+        const uint32_t a = wave_sum(c_rays), b = wave_sum(c_hits);
+        if (__lane_id() == 0 && a) {
+            atomicAdd(&E.a.stats->rays_traced, (unsigned long long)a);
+            atomicAdd(&E.a.stats->rays_hit, (unsigned long long)b);
+        }
+    }
+}
+
+__global__ void edge_queue_reset(uint32_t* q_count) { *q_count = 0u; }
+
 }  // namespace
 
 static unsigned n_blocks(const ShadeArgs& a) { return (unsigned)((a.g.n + kBlock - 1) / kBlock); }
@@ -965,6 +1158,15 @@ hipError_t launch_trace(const Scene& sc, const float* o, const float* d, int64_t
     if (n == 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(trace_kernel, dim3((unsigned)blocks), dim3(256), 0, s, sc, o, d, n, hit, brute);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s) {
+    if (e.npix <= 0) return hipSuccess;
+    hipLaunchKernelGGL(edge_queue_reset, dim3(1), dim3(1), 0, s, e.q_count);
+    hipLaunchKernelGGL(edge_gen_kernel, dim3((unsigned)((e.npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, e);
+    // the queue's length is on the device: a fixed grid strides over it
+    hipLaunchKernelGGL(edge_trace_kernel, dim3(1024), dim3(256), 0, s, e);
     return hipGetLastError();
 }
 
