@@ -159,9 +159,12 @@ def _ground_scene(N, seed=5):
 
 def test_edge_grad_ragged_passes():
     """9001 pixels at 512 edge samples: passes of 8192 pixels and a ragged
-    tail of 809; pixels inside the boxes' footprints see no sky at all."""
+    tail of 809; pixels inside the boxes' footprints see no sky at all.  Each
+    of the 60 vertex components sums some 10^4 - 10^5 FP32 terms of both signs
+    (u sqrt(n) ~ 2e-5 of the sum of magnitudes, several times that of the
+    signed sum): the median guard is set from that."""
     _need_gpu()
-    _parity(_ground_scene(9001), 512, med=5e-5)
+    _parity(_ground_scene(9001), 512, med=3e-4)
 
 
 def test_edge_grad_full_size_sampled():
@@ -171,7 +174,7 @@ def test_edge_grad_full_size_sampled():
     w = make_workload("sphere8_grad")
     r = np.random.Generator(np.random.PCG64(9))
     valid_all = np.nonzero(w.mask)[0]
-    keep = np.sort(r.choice(valid_all, 1500, replace=False))
+    keep = np.sort(r.choice(valid_all, 8000, replace=False))
     mask = np.zeros_like(w.mask)
     mask[keep] = 1
     w.mask = mask
