@@ -204,7 +204,7 @@ def main():
         "roofline": roofline,
     }
 
-    STATE.update(scene=scene, env=envh, w=w)
+    STATE.update(scene=scene, env=envh, w=w, verts=verts, tris=tris)
     if not args.no_next_rows:
         result["next_rows"] = next_rows(args, M, gb, out[0], out[1], target, timed)
     if not args.no_serve:
@@ -278,6 +278,52 @@ def sampling_study(args, M, gb, timed, seeds=4):
 
 STATE = {}
 
+# Edge-sampled visibility gradient, VALU lane-operations per edge sample
+# (every sample): Philox4x32-10 (ten rounds of two 32x32->64 products = 4
+# lane ops, and 4 xors: 80), edge choice and t (4), the differences from o
+# and along the edge (6), the arc normal (6), the two face-side determinants
+# (24), sign logic and |m|^2 (7) = 127.  Per sample that reaches the queue
+# (silhouette, above the horizon): direction and distance (14), arc normal and
+# Jacobian (18), probe lookup (two atan2 and the texel, 50), the BSDF terms
+# (50), out-side direction and record (18) = 150.
+EDGE_OPS_PER_SAMPLE = 127
+EDGE_OPS_PER_QUEUED = 150
+EDGE_SPP = 8
+
+
+def visibility_gradient(args, M, gb, timed):
+    """Edge-sampled shadow-visibility gradient on the step's workload: edge
+    list build, and one gradient pass of EDGE_SPP edge samples per pixel."""
+    import torch
+    sc, envh, w = STATE["scene"], STATE["env"], STATE["w"]
+    verts, tris = STATE["verts"], STATE["tris"]
+    nv = verts.shape[0]
+    m = gb.mask.bool()
+    nval = max(int(m.sum()), 1)
+    reps = max(3, args.kernel_reps // 2)
+    ed = M.Edges(tris, nv)
+    n_edges = ed.count()
+    build_ms = timed(lambda: M.Edges(tris, nv), reps)
+    g_cd = torch.randn((3, gb.n), device=gb.kd.device) * m / nval
+    g_cs = torch.randn((3, gb.n), device=gb.kd.device) * m / nval
+    gv = torch.zeros_like(verts)
+    st = M.new_stats(verts.device)
+    M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps,
+                      g_verts=gv, stats=st)
+    stats = M.read_stats(st)
+    ms = timed(lambda: M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=w.seed, tau=w.tau,
+                                         ray_eps=w.ray_eps, g_verts=gv), reps)
+    samples = nval * EDGE_SPP
+    queued = stats["rays_traced"]
+    ops = EDGE_OPS_PER_SAMPLE * samples + EDGE_OPS_PER_QUEUED * queued
+    a = ops / (ms * 1e-3)
+    return {"edge_spp": EDGE_SPP, "edges": n_edges, "edge_build_ms": build_ms, "ms": ms,
+            "edge_samples_per_s": samples / (ms * 1e-3), "samples": samples,
+            "silhouette_rays": queued, "silhouette_rays_blocked": stats["rays_hit"],
+            "roofline": {"bound": "alu", "achieved": a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
+                         "frac": a / VALU_PEAK, "traffic": None, "ops_per_launch": ops,
+                         "note": "whole call: queue reset, sample kernel and out-side-ray kernel per pass"}}
+
 
 def next_rows(args, M, gb, c_d, c_s, target, timed):
     """Denoiser and image-loss kernels on the step's own outputs, each timed
@@ -305,6 +351,7 @@ def next_rows(args, M, gb, c_d, c_s, target, timed):
                 "frac": a / VALU_PEAK, "traffic": None}
 
     sampling = sampling_study(args, M, gb, timed)
+    vis = visibility_gradient(args, M, gb, timed)
     lo = (torch.empty(3, dtype=torch.float32, device=x.device),) + tuple(torch.empty_like(c_d) for _ in range(3))
     l_ms = timed(lambda: M.image_loss(gb.kd, c_d, c_s, target, gb.mask, out=lo), reps)
     lbytes = LOSS_BYTES_PER_PX * n
@@ -314,6 +361,7 @@ def next_rows(args, M, gb, c_d, c_s, target, timed):
                       "fwd_roofline": alu(taps * BILAT_OPS_FWD, f_ms),
                       "bwd_roofline": alu(taps * BILAT_OPS_BWD, b_ms)},
         "sampling": sampling,
+        "visibility_gradient": vis,
         "image_loss": {"ms": l_ms, "bytes_per_launch": lbytes,
                        "roofline": {"bound": "hbm", "achieved": lbytes / (l_ms * 1e-3) / 1e9,
                                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",

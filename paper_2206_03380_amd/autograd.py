@@ -21,11 +21,16 @@ class MCDIShade(torch.autograd.Function):
     differentiated: shape gradients come from primary visibility).
     bwd_seed None (default): the backward replays the forward's samples
     (correlated, section 4.1); otherwise it draws and traces its own samples
-    from bwd_seed (decorrelated, unbiased; see decorrelated_seed)."""
+    from bwd_seed (decorrelated, unbiased; see decorrelated_seed).
+    verts, edges, edge_spp: optionally the mesh's vertex positions [Nv, 3]
+    (the ones scene was built from; differentiable), its Edges and a number
+    of edge samples per pixel: the backward then also returns the
+    edge-sampled visibility gradient of the shadow term for verts (the paper
+    detaches it by default, section 3.1 "Shadow gradients")."""
 
     @staticmethod
     def forward(ctx, kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0,
-                bwd_seed=None):
+                bwd_seed=None, verts=None, edges=None, edge_spp=0):
         from . import _ptr, _stream, hit_words, _params
         import ctypes as C
         n = gbuf.n
@@ -41,16 +46,19 @@ class MCDIShade(torch.autograd.Function):
         prm = _params(spp, seed, tau, ray_eps, flags, None)
         L.check(L.lib().mcdi_shade_fwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(c_d),
                                        _ptr(c_s), _ptr(hb), None, _stream()))
-        ctx.save_for_backward(kd, korm, nrm, hb if hb is not None else torch.empty(0, device=dev))
+        vis = verts is not None and edges is not None and edge_spp > 0
+        ctx.save_for_backward(kd, korm, nrm, hb if hb is not None else torch.empty(0, device=dev),
+                              verts if vis else torch.empty(0, device=dev))
         ctx.meta = (scene, env_tables, gbuf, spp, seed if bwd_seed is None else bwd_seed, tau, ray_eps,
                     hb is not None, flags & ~(L.FLAG_DUMP | L.FLAG_TIME_TRACE))
+        ctx.vis = (edges, edge_spp) if vis else None
         return c_d, c_s
 
     @staticmethod
     def backward(ctx, g_cd, g_cs):
         from . import _ptr, _stream, _params
         import ctypes as C
-        kd, korm, nrm, hb = ctx.saved_tensors
+        kd, korm, nrm, hb, verts = ctx.saved_tensors
         scene, env_tables, gbuf, spp, seed, tau, ray_eps, has_bits, flags = ctx.meta
         n = gbuf.n
         dev = kd.device
@@ -60,12 +68,22 @@ class MCDIShade(torch.autograd.Function):
         g_korm = torch.empty((3, n), dtype=torch.float32, device=dev)
         g_nrm = torch.empty((3, n), dtype=torch.float32, device=dev)
         g_env = torch.zeros((env_tables.H, env_tables.W, 3), dtype=torch.float32, device=dev)
-        gs = gbuf.struct(kd=kd, korm=korm, nrm=nrm)
-        prm = _params(spp, seed, tau, ray_eps, flags, None)
-        L.check(L.lib().mcdi_shade_bwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(g_cd),
-                                       _ptr(g_cs), _ptr(hb) if has_bits else None, _ptr(g_kd), _ptr(g_korm),
-                                       _ptr(g_nrm), _ptr(g_env), None, _stream()))
-        return g_kd, g_korm, g_nrm, g_env, None, None, None, None, None, None, None, None, None
+        if any(ctx.needs_input_grad[:4]):
+            gs = gbuf.struct(kd=kd, korm=korm, nrm=nrm)
+            prm = _params(spp, seed, tau, ray_eps, flags, None)
+            L.check(L.lib().mcdi_shade_bwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(g_cd),
+                                           _ptr(g_cs), _ptr(hb) if has_bits else None, _ptr(g_kd), _ptr(g_korm),
+                                           _ptr(g_nrm), _ptr(g_env), None, _stream()))
+        else:
+            g_kd = g_korm = g_nrm = g_env = None
+        g_verts = None
+        if ctx.vis is not None and ctx.needs_input_grad[13]:
+            from . import shade_bwd_edges
+            edges, edge_spp = ctx.vis
+            g_verts = shade_bwd_edges(scene, env_tables, edges, verts.detach().contiguous(), gbuf, edge_spp, g_cd,
+                                      g_cs, seed=seed, tau=tau, ray_eps=ray_eps, flags=flags & L.FLAG_BILINEAR)
+        return (g_kd, g_korm, g_nrm, g_env, None, None, None, None, None, None, None, None, None, g_verts, None,
+                None)
 
 
 class Bilateral(torch.autograd.Function):

@@ -209,3 +209,29 @@ def test_edge_grad_accumulates_and_degenerate_cases():
     g = M.shade_bwd_edges(M.Scene(verts, no_tris), env, M.Edges(no_tris, len(w.verts)), verts, gb, 4, ud, us)
     torch.cuda.synchronize()
     assert (to_np(g) == 0).all()
+
+
+def test_autograd_returns_visibility_gradient():
+    """MCDIShade with verts/edges: loss.backward() puts the edge-sampled
+    visibility gradient into verts.grad, the same as the direct call."""
+    _need_gpu()
+    import paper_2206_03380_amd as M
+    w = make_workload("tiny")
+    dev = "cuda"
+    verts = torch.from_numpy(w.verts).to(dev).requires_grad_(True)
+    tris = torch.from_numpy(w.tris).to(dev)
+    scene = M.Scene(verts.detach(), tris)
+    env_t = torch.from_numpy(w.env).to(dev)
+    envh = M.Env(env_t)
+    gb = M.GBuffer.from_workload(w, dev)
+    ed = M.Edges(tris, len(w.verts))
+    ud, us = (torch.from_numpy(x).to(dev) for x in upstream_grads(w))
+    c_d, c_s = M.MCDIShade.apply(gb.kd, gb.korm, gb.nrm, env_t, scene, envh, gb, w.spp, w.seed, w.tau, w.ray_eps, 0,
+                                 None, verts, ed, 8)
+    ((c_d * ud).sum() + (c_s * us).sum()).backward()
+    ref = M.shade_bwd_edges(scene, envh, ed, verts.detach(), gb, 8, ud, us, seed=w.seed, tau=w.tau,
+                            ray_eps=w.ray_eps)
+    torch.cuda.synchronize()
+    g, r = to_np(verts.grad), to_np(ref)
+    assert np.abs(r).max() > 0
+    assert np.allclose(g, r, rtol=1e-5, atol=1e-6 * np.abs(r).max())
