@@ -794,18 +794,20 @@ mcdi_status mcdi_shade_bwd_edges(mcdi_scene sc, mcdi_env ev, mcdi_edges ed, cons
     E.verts = verts;
     E.g_verts = g_verts;
     E.n_es = edge_spp;
-    // pixels per pass: every sample of a pass fits the queue
-    const int64_t per = ((int64_t)(kEdgeQueueMax / (uint32_t)edge_spp) / kBlock) * kBlock;
+    // pixels per pass: every sample of a pass fits the queue, and the pixel
+    // in pass fits its 22 bits of the record
+    int64_t per = ((int64_t)(kEdgeQueueMax / (uint32_t)edge_spp) / kBlock) * kBlock;
+    if (per > kEdgePassMax) per = kEdgePassMax;
     const int64_t n = a.g.n;
     const int64_t chunk = per < n ? per : ((n + kBlock - 1) / kBlock) * kBlock;
     E.q_cap = (uint32_t)(chunk * edge_spp);
     Workspace ws;
     ws.alloc = &sc->alloc;
     ws.s = s;
-    const size_t sz_q = ((sizeof(float4) * 3 * (size_t)E.q_cap) + 255) & ~(size_t)255;
+    const size_t sz_q = ((sizeof(uint32_t) * (size_t)E.q_cap) + 255) & ~(size_t)255;
     ws.base = sc->alloc.get(sz_q + 256, s);
     if (!ws.base) return fail(MCDI_E_OOM, "mcdi_shade_bwd_edges: workspace allocation failed");
-    E.queue = (float4*)ws.base;
+    E.queue = (uint32_t*)ws.base;
     E.q_count = (uint32_t*)((char*)ws.base + sz_q);
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {
         E.pix0 = p0;

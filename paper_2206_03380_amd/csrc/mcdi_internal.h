@@ -105,12 +105,13 @@ struct ServeItem {
     int64_t first_global;  // index of that tile in the launch's tile queue
 };
 
-// edge-sampled visibility gradient of the shadow term: one pass over a
-// range of pixels appends the silhouette samples that carry a term to a
-// queue, a second traces their out-side rays and scatters the terms of the
-// rays that miss into g_verts
+// edge-sampled visibility gradient of the shadow term: one kernel over a
+// range of pixels queues the edge samples that are silhouettes above the
+// horizon, a second recomputes them, traces their out-side rays and scatters
+// the terms of the rays that miss into g_verts
 constexpr float kEdgeDelta = 1.0f / 8192.0f;   // angle of the out-side ray off the edge (radians)
-constexpr uint32_t kEdgeQueueMax = 1u << 22;   // queue records per pass (three float4 each)
+constexpr uint32_t kEdgeQueueMax = 1u << 25;   // queue records per pass (4 bytes each)
+constexpr int64_t kEdgePassMax = 1 << 22;      // pixels per pass (22 bits of the record)
 struct EdgeArgs {
     ShadeArgs a;             // scene, env, G-buffer, seed, tau, ray_eps, flags, g_cd, g_cs, stats
     const int4* edges;       // [E] (a, b, c, d) rows
@@ -119,7 +120,7 @@ struct EdgeArgs {
     float* g_verts;          // [Nv][3], accumulated
     int32_t n_es;            // edge samples per pixel
     int64_t pix0, npix;      // pixel range of this pass
-    float4* queue;           // [q_cap][3]: (o, edge bits), (out direction, t), (term * mh, 0)
+    uint32_t* queue;         // [q_cap]: pixel in pass << 10 | edge sample
     uint32_t* q_count;
     uint32_t q_cap;
 };

@@ -947,6 +947,48 @@ __device__ __forceinline__ float3 probe_radiance(const EnvView& e, float3 w, boo
     return texel_rgb(e, ti * W + tj);
 }
 
+// The face sides come from det(a - o, b - o, c - o) written as (a - o) .
+// ((b - a) x (c - a)), free of the cancellation of differences from a
+// distant o.  Returns false when the sample cannot carry a term: no
+// silhouette, a degenerate arc, or the point at or below the horizon.
+struct EdgeGeom {
+    int4 ed;
+    float t, s;          // point on the edge; +1 when the face lies on the +mh side
+    float3 w, mh;        // unit direction to the point; unit arc normal
+    float r2;            // squared distance to the point
+    float3 eab;
+};
+
+__device__ __forceinline__ bool edge_geom(const EdgeArgs& E, const Pixel& P, uint32_t piv, uint32_t vid, int j,
+                                          uint32_t ne, EdgeGeom& G) {
+    const uint32_t k0 = (uint32_t)E.a.seed, k1 = (uint32_t)(E.a.seed >> 32);
+    const uint4 r = philox10(make_uint4(piv, vid, (uint32_t)j, 2u), k0, k1);
+    const uint32_t e = __umulhi(r.x, ne);
+    G.t = u01(r.y);
+    G.ed = E.edges[e];
+    const float3 va = load_vert(E.verts, G.ed.x);
+    const float3 qa = va - P.o;
+    G.eab = load_vert(E.verts, G.ed.y) - va;
+    const float3 m = cross(qa, G.eab);   // = (a - o) x (b - o)
+    const float sc = dot(qa, cross(G.eab, load_vert(E.verts, G.ed.z) - va));
+    if (sc == 0.0f) return false;
+    if (G.ed.w >= 0) {
+        const float sd = dot(qa, cross(G.eab, load_vert(E.verts, G.ed.w) - va));
+        if ((sc > 0.0f && sd < 0.0f) || (sc < 0.0f && sd > 0.0f)) return false;   // both sides covered
+    }
+    const float ml2 = dot(m, m);
+    if (!(ml2 > 0.0f)) return false;
+    const float3 w = qa + G.t * G.eab;
+    G.r2 = dot(w, w);
+    G.w = (1.0f / sqrtf(G.r2)) * w;
+    if (!(dot(G.w, P.n) > 0.0f)) return false;
+    G.mh = (1.0f / sqrtf(ml2)) * m;
+    G.s = sc > 0.0f ? 1.0f : -1.0f;
+    return true;
+}
+
+// 1) every edge sample of a pass of pixels; the candidates (silhouette, above
+//    the horizon) go to the queue as (pixel in pass << 10 | sample)
 __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
     const ShadeArgs& A = E.a;
     const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -958,81 +1000,15 @@ __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
     P.valid = false;
     if (active) P = setup_pixel(A, pix, nonfinite);
     const bool go = P.valid && ne > 0u && A.tau != 0.0f;
-    const bool bil = (A.flags & MCDI_FLAG_BILINEAR) != 0;
-    const int64_t N = A.g.n;
     const int64_t hw = (int64_t)A.g.height * A.g.width;
     const uint32_t view = active ? (uint32_t)(pix / hw) : 0u;
     const uint32_t piv = active ? (uint32_t)(pix - (int64_t)view * hw) : 0u;
     const uint32_t vid = (uint32_t)A.g.view_base + view;
-    const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
-    float3 Ud = f3(0, 0, 0), Us = Ud;
-    if (go) {
-        Ud = f3(A.g_cd[pix], A.g_cd[N + pix], A.g_cd[2 * N + pix]);
-        Us = f3(A.g_cs[pix], A.g_cs[N + pix], A.g_cs[2 * N + pix]);
-    }
     const int lane = __lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const float scale = (float)ne * A.tau / (float)E.n_es;
     for (int j = 0; j < E.n_es; ++j) {
-        bool emit = false;
-        float4 q0, q1, q2;
-        if (go) {
-            const uint4 r = philox10(make_uint4(piv, vid, (uint32_t)j, 2u), k0, k1);
-            const uint32_t e = __umulhi(r.x, ne);
-            const float t = u01(r.y);
-            const int4 ed = E.edges[e];
-            // face sides: det(a - o, b - o, c - o) as (a - o) . ((b - a) x
-            // (c - a)), free of the cancellation of differences from a
-            // distant o
-            const float3 va = load_vert(E.verts, ed.x);
-            const float3 qa = va - P.o, eab = load_vert(E.verts, ed.y) - va;
-            const float3 m = cross(qa, eab);   // = (a - o) x (b - o)
-            const float sc = dot(qa, cross(eab, load_vert(E.verts, ed.z) - va));
-            bool sil = sc != 0.0f;
-            if (sil && ed.w >= 0) {
-                const float sd = dot(qa, cross(eab, load_vert(E.verts, ed.w) - va));
-                sil = !((sc > 0.0f && sd < 0.0f) || (sc < 0.0f && sd > 0.0f));
-            }
-            const float ml2 = dot(m, m);
-            if (sil && ml2 > 0.0f) {
-                float3 w = qa + t * eab;
-                const float r2 = dot(w, w);
-                w = (1.0f / sqrtf(r2)) * w;
-                const float NoL = dot(w, P.n);
-                if (NoL > 0.0f) {
-                    const float3 mh = (1.0f / sqrtf(ml2)) * m;
-                    const float s = sc > 0.0f ? 1.0f : -1.0f;
-                    const float3 ex = cross(eab, w);
-                    const float J = sqrtf(dot(ex, ex)) / r2;
-                    const float3 L = probe_radiance(A.env, w, bil);
-                    // unshadowed integrand at w (unit density), contracted
-                    const float3 wl = f3(dot(w, P.t), dot(w, P.b), NoL);
-                    const float kdiff = (1.0f - P.m) * kInvPi * NoL;
-                    float g = kdiff * (Ud.x * L.x + Ud.y * L.y + Ud.z * L.z);
-                    if (P.nov_pos) {
-                        const float3 hl = normalize(P.Vl + wl);
-                        const float s2 = hl.x * hl.x + hl.y * hl.y;
-                        const float D = ggx_D(hl.z, s2, P.a2);
-                        const float lamL = smith_lambda(smith_t2(NoL), P.a2);
-                        const float Sv = D / (1.0f + P.lamV + lamL) / (4.0f * P.nov);
-                        const float omv = 1.0f - dot(P.Vl, hl);
-                        const float o2 = omv * omv;
-                        const float Fw = o2 * o2 * omv;
-                        const float3 F = f3(P.F0.x + (1.0f - P.F0.x) * Fw, P.F0.y + (1.0f - P.F0.y) * Fw,
-                                            P.F0.z + (1.0f - P.F0.z) * Fw);
-                        g += Sv * (Us.x * F.x * L.x + Us.y * F.y * L.y + Us.z * F.z * L.z);
-                    }
-                    const float wt = s * scale * J * g;
-                    if (wt != 0.0f && isfinite(wt)) {
-                        const float3 wo = normalize(w - (s * kEdgeDelta) * mh);
-                        q0 = make_float4(P.o.x, P.o.y, P.o.z, __uint_as_float(e));
-                        q1 = make_float4(wo.x, wo.y, wo.z, t);
-                        q2 = make_float4(wt * mh.x, wt * mh.y, wt * mh.z, 0.0f);
-                        emit = true;
-                    }
-                }
-            }
-        }
+        EdgeGeom G;
+        const bool emit = go && edge_geom(E, P, piv, vid, j, ne, G);
         const uint64_t bal = __ballot(emit);
         if (bal == 0ull) continue;
         const int leader = __ffsll((unsigned long long)bal) - 1;
@@ -1043,11 +1019,7 @@ __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
             const uint32_t at = base + (uint32_t)__popcll(bal & lt);
             // the queue holds every sample of the pass; the check only
             // guards the bound
-            if (at < E.q_cap) {
-                E.queue[3 * (size_t)at] = q0;
-                E.queue[3 * (size_t)at + 1] = q1;
-                E.queue[3 * (size_t)at + 2] = q2;
-            }
+            if (at < E.q_cap) E.queue[at] = ((uint32_t)local << 10) | (uint32_t)j;
         }
     }
     if (A.stats) {
@@ -1059,40 +1031,83 @@ __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
     }
 }
 
-// out-side rays of the queued samples; a ray that reaches the probe adds the
-// sample's term to both vertices of its edge
+// 2) the queued candidates: the sample is recomputed, its term evaluated and
+//    its out-side ray traced; a ray that reaches the probe adds the term to
+//    both vertices of the edge
 __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
-    const Scene& sc = E.a.scene;
+    const ShadeArgs& A = E.a;
+    const Scene& sc = A.scene;
     const uint32_t n = min(*E.q_count, E.q_cap);
+    const uint32_t ne = *E.n_edges;
     const int n_total = sc.nodes[0].escape;
+    const bool bil = (A.flags & MCDI_FLAG_BILINEAR) != 0;
+    const int64_t N = A.g.n;
+    const int64_t hw = (int64_t)A.g.height * A.g.width;
+    const float scale = (float)ne * A.tau / (float)E.n_es;
     uint32_t c_rays = 0, c_hits = 0;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const float4 q0 = E.queue[3 * (size_t)i], q1 = E.queue[3 * (size_t)i + 1], q2 = E.queue[3 * (size_t)i + 2];
-        const Ray r = make_ray(f3(q0.x, q0.y, q0.z), f3(q1.x, q1.y, q1.z));
+        const uint32_t rec = E.queue[i];
+        const int64_t pix = E.pix0 + (int64_t)(rec >> 10);
+        const int j = (int)(rec & 1023u);
+        if (pix >= N) continue;
+        bool nonfinite;
+        const Pixel P = setup_pixel(A, pix, nonfinite);
+        if (!P.valid) continue;
+        const uint32_t view = (uint32_t)(pix / hw);
+        const uint32_t piv = (uint32_t)(pix - (int64_t)view * hw);
+        EdgeGeom G;
+        if (!edge_geom(E, P, piv, (uint32_t)A.g.view_base + view, j, ne, G)) continue;
+        const float3 Ud = f3(A.g_cd[pix], A.g_cd[N + pix], A.g_cd[2 * N + pix]);
+        const float3 Us = f3(A.g_cs[pix], A.g_cs[N + pix], A.g_cs[2 * N + pix]);
+        const float3 w = G.w;
+        const float NoL = dot(w, P.n);
+        const float3 ex = cross(G.eab, w);
+        const float J = sqrtf(dot(ex, ex)) / G.r2;
+        const float3 L = probe_radiance(A.env, w, bil);
+        // unshadowed integrand at w (unit density), contracted
+        const float3 wl = f3(dot(w, P.t), dot(w, P.b), NoL);
+        const float kdiff = (1.0f - P.m) * kInvPi * NoL;
+        float g = kdiff * (Ud.x * L.x + Ud.y * L.y + Ud.z * L.z);
+        if (P.nov_pos) {
+            const float3 hl = normalize(P.Vl + wl);
+            const float s2 = hl.x * hl.x + hl.y * hl.y;
+            const float D = ggx_D(hl.z, s2, P.a2);
+            const float lamL = smith_lambda(smith_t2(NoL), P.a2);
+            const float Sv = D / (1.0f + P.lamV + lamL) / (4.0f * P.nov);
+            const float omv = 1.0f - dot(P.Vl, hl);
+            const float o2 = omv * omv;
+            const float Fw = o2 * o2 * omv;
+            const float3 F = f3(P.F0.x + (1.0f - P.F0.x) * Fw, P.F0.y + (1.0f - P.F0.y) * Fw,
+                                P.F0.z + (1.0f - P.F0.z) * Fw);
+            g += Sv * (Us.x * F.x * L.x + Us.y * F.y * L.y + Us.z * F.z * L.z);
+        }
+        const float wt = G.s * scale * J * g;
+        if (!(wt != 0.0f && isfinite(wt))) continue;
+        const float3 wo = normalize(w - (G.s * kEdgeDelta) * G.mh);
+        const Ray ray = make_ray(P.o, wo);
         uint32_t nb = 0, nt = 0;
-        const bool hit = n_total > 0 && bvh_anyhit(sc, r, n_total, nb, nt);
+        const bool hit = n_total > 0 && bvh_anyhit(sc, ray, n_total, nb, nt);
         ++c_rays;
         if (hit) {
             ++c_hits;
             continue;
         }
-        const int4 ed = E.edges[__float_as_uint(q0.w)];
-        const float t = q1.w, ta = 1.0f - t;
-        float* ga = E.g_verts + 3 * (size_t)ed.x;
-        float* gb = E.g_verts + 3 * (size_t)ed.y;
-        atomicAdd(ga + 0, ta * q2.x);
-        atomicAdd(ga + 1, ta * q2.y);
-        atomicAdd(ga + 2, ta * q2.z);
-        atomicAdd(gb + 0, t * q2.x);
-        atomicAdd(gb + 1, t * q2.y);
-        atomicAdd(gb + 2, t * q2.z);
+        const float ta = 1.0f - G.t;
+        float* ga = E.g_verts + 3 * (size_t)G.ed.x;
+        float* gb = E.g_verts + 3 * (size_t)G.ed.y;
+        atomicAdd(ga + 0, ta * wt * G.mh.x);
+        atomicAdd(ga + 1, ta * wt * G.mh.y);
+        atomicAdd(ga + 2, ta * wt * G.mh.z);
+        atomicAdd(gb + 0, G.t * wt * G.mh.x);
+        atomicAdd(gb + 1, G.t * wt * G.mh.y);
+        atomicAdd(gb + 2, G.t * wt * G.mh.z);
     }
-    if (E.a.stats) {
+    if (A.stats) {
         const uint32_t a = wave_sum(c_rays), b = wave_sum(c_hits);
         if (__lane_id() == 0 && a) {
-            atomicAdd(&E.a.stats->rays_traced, (unsigned long long)a);
-            atomicAdd(&E.a.stats->rays_hit, (unsigned long long)b);
+            atomicAdd(&A.stats->rays_traced, (unsigned long long)a);
+            atomicAdd(&A.stats->rays_hit, (unsigned long long)b);
         }
     }
 }
