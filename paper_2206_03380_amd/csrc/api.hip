@@ -805,10 +805,15 @@ mcdi_status mcdi_shade_bwd_edges(mcdi_scene sc, mcdi_env ev, mcdi_edges ed, cons
     ws.alloc = &sc->alloc;
     ws.s = s;
     const size_t sz_q = ((sizeof(uint32_t) * (size_t)E.q_cap) + 255) & ~(size_t)255;
-    ws.base = sc->alloc.get(sz_q + 256, s);
+    const uint32_t cap_edges = (uint32_t)(3 * ed->n_tris);   // at most one edge per triangle side
+    const size_t sz_geo = sizeof(float4) * 4 * (size_t)cap_edges;
+    ws.base = sc->alloc.get(sz_q + 256 + sz_geo, s);
     if (!ws.base) return fail(MCDI_E_OOM, "mcdi_shade_bwd_edges: workspace allocation failed");
     E.queue = (uint32_t*)ws.base;
     E.q_count = (uint32_t*)((char*)ws.base + sz_q);
+    E.egeo = (const float4*)((char*)ws.base + sz_q + 256);
+    hipError_t pe = launch_edge_pack(E, cap_edges, s);
+    if (pe != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd_edges: %s", hipGetErrorString(pe));
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {
         E.pix0 = p0;
         E.npix = n - p0 < chunk ? n - p0 : chunk;

@@ -117,6 +117,7 @@ struct EdgeArgs {
     const int4* edges;       // [E] (a, b, c, d) rows
     const uint32_t* n_edges; // E (device)
     const float* verts;      // [Nv][3]
+    const float4* egeo;      // [E][4] corners a, b, c, d of each edge (d.w = 1 when present)
     float* g_verts;          // [Nv][3], accumulated
     int32_t n_es;            // edge samples per pixel
     int64_t pix0, npix;      // pixel range of this pass
@@ -185,6 +186,8 @@ hipError_t launch_image_loss(const float* kd, const float* cd, const float* cs, 
 
 // one pass of the edge-sampled visibility gradient over [pix0, pix0 + npix)
 hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s);
+// packs the corners of the first min(E, cap) edges into e.egeo
+hipError_t launch_edge_pack(const EdgeArgs& e, uint32_t cap, hipStream_t s);
 
 // unique mesh edges: hash table of 2^bits slots (keys, first and second
 // side), side -> slot map [3 n_tris], block sums [edge_scan_blocks]

@@ -952,7 +952,7 @@ __device__ __forceinline__ float3 probe_radiance(const EnvView& e, float3 w, boo
 // distant o.  Returns false when the sample cannot carry a term: no
 // silhouette, a degenerate arc, or the point at or below the horizon.
 struct EdgeGeom {
-    int4 ed;
+    uint32_t e;          // edge row
     float t, s;          // point on the edge; +1 when the face lies on the +mh side
     float3 w, mh;        // unit direction to the point; unit arc normal
     float r2;            // squared distance to the point
@@ -963,17 +963,19 @@ __device__ __forceinline__ bool edge_geom(const EdgeArgs& E, const Pixel& P, uin
                                           uint32_t ne, EdgeGeom& G) {
     const uint32_t k0 = (uint32_t)E.a.seed, k1 = (uint32_t)(E.a.seed >> 32);
     const uint4 r = philox10(make_uint4(piv, vid, (uint32_t)j, 2u), k0, k1);
-    const uint32_t e = __umulhi(r.x, ne);
+    G.e = __umulhi(r.x, ne);
     G.t = u01(r.y);
-    G.ed = E.edges[e];
-    const float3 va = load_vert(E.verts, G.ed.x);
+    // the edge's corners, packed in one 64-byte line for this call
+    const float4* q = E.egeo + 4 * (size_t)G.e;
+    const float4 pa = q[0], pb = q[1], pc = q[2], pd = q[3];
+    const float3 va = f3(pa.x, pa.y, pa.z);
     const float3 qa = va - P.o;
-    G.eab = load_vert(E.verts, G.ed.y) - va;
+    G.eab = f3(pb.x, pb.y, pb.z) - va;
     const float3 m = cross(qa, G.eab);   // = (a - o) x (b - o)
-    const float sc = dot(qa, cross(G.eab, load_vert(E.verts, G.ed.z) - va));
+    const float sc = dot(qa, cross(G.eab, f3(pc.x, pc.y, pc.z) - va));
     if (sc == 0.0f) return false;
-    if (G.ed.w >= 0) {
-        const float sd = dot(qa, cross(G.eab, load_vert(E.verts, G.ed.w) - va));
+    if (pd.w != 0.0f) {
+        const float sd = dot(qa, cross(G.eab, f3(pd.x, pd.y, pd.z) - va));
         if ((sc > 0.0f && sd < 0.0f) || (sc < 0.0f && sd > 0.0f)) return false;   // both sides covered
     }
     const float ml2 = dot(m, m);
@@ -987,43 +989,83 @@ __device__ __forceinline__ bool edge_geom(const EdgeArgs& E, const Pixel& P, uin
     return true;
 }
 
+// The part of setup_pixel the edge filter needs: validity (same rules), the
+// shadow-ray origin and the unit normal, with the same FP64 arithmetic so
+// that both are bit-identical to setup_pixel's.
+__device__ __forceinline__ bool pixel_origin(const ShadeArgs& A, int64_t pix, Pixel& P, bool& nonfinite) {
+    const GBufView& g = A.g;
+    const int64_t N = g.n;
+    nonfinite = false;
+    if (!g.mask[pix]) return false;
+    const int v = (int)(pix / ((int64_t)g.height * g.width));
+    const float px = g.pos[pix], py = g.pos[N + pix], pz = g.pos[2 * N + pix];
+    const float nxf = g.nrm[pix], nyf = g.nrm[N + pix], nzf = g.nrm[2 * N + pix];
+    const float ex = g.eye[3 * v], ey = g.eye[3 * v + 1], ez = g.eye[3 * v + 2];
+    if (!(finite3(px, py, pz) && finite3(nxf, nyf, nzf) &&
+          finite3(g.kd[pix], g.kd[N + pix], g.kd[2 * N + pix]) &&
+          finite3(g.korm[pix], g.korm[N + pix], g.korm[2 * N + pix]) && finite3(ex, ey, ez))) {
+        nonfinite = true;
+        return false;
+    }
+    if (nxf == 0.0f && nyf == 0.0f && nzf == 0.0f) return false;
+    const double wx = (double)ex - px, wy = (double)ey - py, wz = (double)ez - pz;
+    if (wx == 0.0 && wy == 0.0 && wz == 0.0) return false;
+    const double nl = sqrt((double)nxf * nxf + (double)nyf * nyf + (double)nzf * nzf);
+    const double nx = nxf / nl, ny = nyf / nl, nz = nzf / nl;
+    const double eps = (double)A.ray_eps;
+    P.n = f3((float)nx, (float)ny, (float)nz);
+    P.o = f3((float)(px + eps * nx), (float)(py + eps * ny), (float)(pz + eps * nz));
+    return true;
+}
+
 // 1) every edge sample of a pass of pixels; the candidates (silhouette, above
-//    the horizon) go to the queue as (pixel in pass << 10 | sample)
+//    the horizon) go to the queue as (pixel in pass << 10 | sample).  Samples
+//    are filtered 32 at a time into a bit mask before any append, so that
+//    their loads overlap.
 __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
     const ShadeArgs& A = E.a;
     const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t pix = E.pix0 + local;
     const bool active = local < E.npix && pix < A.g.n;
     const uint32_t ne = *E.n_edges;
-    bool nonfinite = false;
+    bool nonfinite = false, valid = false;
     Pixel P;
-    P.valid = false;
-    if (active) P = setup_pixel(A, pix, nonfinite);
-    const bool go = P.valid && ne > 0u && A.tau != 0.0f;
+    if (active) valid = pixel_origin(A, pix, P, nonfinite);
+    const bool go = valid && ne > 0u && A.tau != 0.0f;
     const int64_t hw = (int64_t)A.g.height * A.g.width;
     const uint32_t view = active ? (uint32_t)(pix / hw) : 0u;
     const uint32_t piv = active ? (uint32_t)(pix - (int64_t)view * hw) : 0u;
     const uint32_t vid = (uint32_t)A.g.view_base + view;
     const int lane = __lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int j = 0; j < E.n_es; ++j) {
-        EdgeGeom G;
-        const bool emit = go && edge_geom(E, P, piv, vid, j, ne, G);
-        const uint64_t bal = __ballot(emit);
-        if (bal == 0ull) continue;
-        const int leader = __ffsll((unsigned long long)bal) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(E.q_count, (uint32_t)__popcll(bal));
-        base = (uint32_t)__shfl((int)base, leader);
-        if (emit) {
-            const uint32_t at = base + (uint32_t)__popcll(bal & lt);
-            // the queue holds every sample of the pass; the check only
-            // guards the bound
-            if (at < E.q_cap) E.queue[at] = ((uint32_t)local << 10) | (uint32_t)j;
+    for (int j0 = 0; j0 < E.n_es; j0 += 32) {
+        const int nj = E.n_es - j0 < 32 ? E.n_es - j0 : 32;
+        uint32_t bits = 0u;
+        if (go) {
+            for (int jj = 0; jj < nj; ++jj) {
+                EdgeGeom G;
+                if (edge_geom(E, P, piv, vid, j0 + jj, ne, G)) bits |= 1u << jj;
+            }
+        }
+        if (__ballot(bits != 0u) == 0ull) continue;
+        for (int jj = 0; jj < nj; ++jj) {
+            const bool emit = (bits >> jj) & 1u;
+            const uint64_t bal = __ballot(emit);
+            if (bal == 0ull) continue;
+            const int leader = __ffsll((unsigned long long)bal) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(E.q_count, (uint32_t)__popcll(bal));
+            base = (uint32_t)__shfl((int)base, leader);
+            if (emit) {
+                const uint32_t at = base + (uint32_t)__popcll(bal & lt);
+                // the queue holds every sample of the pass; the check only
+                // guards the bound
+                if (at < E.q_cap) E.queue[at] = ((uint32_t)local << 10) | (uint32_t)(j0 + jj);
+            }
         }
     }
     if (A.stats) {
-        const uint32_t v = wave_sum(P.valid ? 1u : 0u), nf = wave_sum(nonfinite ? 1u : 0u);
+        const uint32_t v = wave_sum(valid ? 1u : 0u), nf = wave_sum(nonfinite ? 1u : 0u);
         if (lane == 0) {
             atomicAdd(&A.stats->valid_pixels, (unsigned long long)v);
             atomicAdd(&A.stats->invalid_pixels, (unsigned long long)nf);
@@ -1031,9 +1073,66 @@ __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
     }
 }
 
-// 2) the queued candidates: the sample is recomputed, its term evaluated and
-//    its out-side ray traced; a ray that reaches the probe adds the term to
-//    both vertices of the edge
+// Any-hit query of one ray by a whole wavefront.  Lane k descends six levels
+// from the root along the bits of k to one of up to 64 disjoint subtrees (the
+// first child of an internal node i is i + 1, the second is the first child's
+// skip link; a leaf reached early belongs to the lane whose remaining bits are
+// zero) and walks its subtree with the skip links, bounded by the subtree's
+// end.  A missed ancestor box implies missed descendants, so testing each
+// subtree root's own box suffices.  The walk stops as soon as any lane finds
+// a hit.  The ray must be the same in every lane; the result is uniform.
+__device__ __forceinline__ bool wave_anyhit(const Scene& sc, const Ray& r, int n_total) {
+    if (n_total <= 0) return false;
+    const float4* nodes = reinterpret_cast<const float4*>(sc.nodes);
+    constexpr int kDepth = 6;
+    const int lane = __lane_id();
+    int node = 0;
+    bool mine = true;
+    for (int lvl = 0; lvl < kDepth; ++lvl) {
+        const int payload = __float_as_int(nodes[2 * node + 1].w);
+        int right = -1;
+        if (payload == 0 && node + 1 < n_total) right = __float_as_int(nodes[2 * (node + 1)].w);
+        // a leaf (or a malformed link) ends the descent here
+        if (payload != 0 || right <= node + 1 || right >= n_total) {
+            mine = (lane >> lvl) == 0;
+            break;
+        }
+        node = ((lane >> lvl) & 1) ? right : node + 1;
+    }
+    const int esc = __float_as_int(nodes[2 * node].w);
+    const int end = (esc > node && esc <= n_total) ? esc : n_total;
+    int i = mine ? node : end;
+    bool hit = false;
+    while (__any(i < end)) {
+        if (i < end) {
+            const float4 a = nodes[2 * i];
+            const float4 b = nodes[2 * i + 1];
+            const int escape = __float_as_int(a.w);
+            const int payload = __float_as_int(b.w);
+            const int next = (escape > i && escape <= end) ? escape : end;
+            if (!box_hit(r, a, b)) {
+                i = next;
+            } else if (payload == 0) {
+                ++i;
+            } else {
+                const int first = payload >> 3;
+                const int cnt = (first + (payload & 7) <= sc.n_tris) ? (payload & 7) : 0;
+                for (int k = 0; k < cnt && !hit; ++k) {
+                    const float4* t = sc.tris + 3 * (first + k);
+                    hit = tri_anyhit(r, t[0], t[1], t[2]);
+                }
+                i = next;
+            }
+        }
+        if (__any(hit)) return true;
+    }
+    return false;
+}
+
+// 2) the queued candidates, one per wavefront: the sample is recomputed (in
+//    every lane alike), its term evaluated and its out-side ray traced by the
+//    whole wavefront; a ray that reaches the probe adds the term to both
+//    vertices of the edge
 __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
     const ShadeArgs& A = E.a;
     const Scene& sc = A.scene;
@@ -1044,9 +1143,11 @@ __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
     const int64_t N = A.g.n;
     const int64_t hw = (int64_t)A.g.height * A.g.width;
     const float scale = (float)ne * A.tau / (float)E.n_es;
+    const bool lead = __lane_id() == 0;
     uint32_t c_rays = 0, c_hits = 0;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t i = wave; i < n; i += n_waves) {
         const uint32_t rec = E.queue[i];
         const int64_t pix = E.pix0 + (int64_t)(rec >> 10);
         const int j = (int)(rec & 1023u);
@@ -1085,34 +1186,52 @@ __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
         const float wt = G.s * scale * J * g;
         if (!(wt != 0.0f && isfinite(wt))) continue;
         const float3 wo = normalize(w - (G.s * kEdgeDelta) * G.mh);
-        const Ray ray = make_ray(P.o, wo);
-        uint32_t nb = 0, nt = 0;
-        const bool hit = n_total > 0 && bvh_anyhit(sc, ray, n_total, nb, nt);
         ++c_rays;
-        if (hit) {
+        if (wave_anyhit(sc, make_ray(P.o, wo), n_total)) {
             ++c_hits;
             continue;
         }
-        const float ta = 1.0f - G.t;
-        float* ga = E.g_verts + 3 * (size_t)G.ed.x;
-        float* gb = E.g_verts + 3 * (size_t)G.ed.y;
-        atomicAdd(ga + 0, ta * wt * G.mh.x);
-        atomicAdd(ga + 1, ta * wt * G.mh.y);
-        atomicAdd(ga + 2, ta * wt * G.mh.z);
-        atomicAdd(gb + 0, G.t * wt * G.mh.x);
-        atomicAdd(gb + 1, G.t * wt * G.mh.y);
-        atomicAdd(gb + 2, G.t * wt * G.mh.z);
-    }
-    if (A.stats) {
-        const uint32_t a = wave_sum(c_rays), b = wave_sum(c_hits);
-        if (__lane_id() == 0 && a) {
-            atomicAdd(&A.stats->rays_traced, (unsigned long long)a);
-            atomicAdd(&A.stats->rays_hit, (unsigned long long)b);
+        if (lead) {
+            const int4 ed = E.edges[G.e];
+            const float ta = 1.0f - G.t;
+            float* ga = E.g_verts + 3 * (size_t)ed.x;
+            float* gb = E.g_verts + 3 * (size_t)ed.y;
+            atomicAdd(ga + 0, ta * wt * G.mh.x);
+            atomicAdd(ga + 1, ta * wt * G.mh.y);
+            atomicAdd(ga + 2, ta * wt * G.mh.z);
+            atomicAdd(gb + 0, G.t * wt * G.mh.x);
+            atomicAdd(gb + 1, G.t * wt * G.mh.y);
+            atomicAdd(gb + 2, G.t * wt * G.mh.z);
         }
+    }
+    if (A.stats && lead && c_rays) {
+        atomicAdd(&A.stats->rays_traced, (unsigned long long)c_rays);
+        atomicAdd(&A.stats->rays_hit, (unsigned long long)c_hits);
     }
 }
 
 __global__ void edge_queue_reset(uint32_t* q_count) { *q_count = 0u; }
+
+// corners of every edge for this call's vertex positions: (a, 0), (b, 0),
+// (c, 0), (d, 1) or (0, 0, 0, 0) without a second face
+__global__ void edge_pack_kernel(const int4* __restrict__ edges, const uint32_t* n_edges, const float* verts,
+                                 float4* egeo, uint32_t cap) {
+    const uint32_t n = min(*n_edges, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int4 ed = edges[i];
+        const float3 a = load_vert(verts, ed.x), b = load_vert(verts, ed.y), c = load_vert(verts, ed.z);
+        float4* q = egeo + 4 * (size_t)i;
+        q[0] = make_float4(a.x, a.y, a.z, 0.0f);
+        q[1] = make_float4(b.x, b.y, b.z, 0.0f);
+        q[2] = make_float4(c.x, c.y, c.z, 0.0f);
+        if (ed.w >= 0) {
+            const float3 d = load_vert(verts, ed.w);
+            q[3] = make_float4(d.x, d.y, d.z, 1.0f);
+        } else {
+            q[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    }
+}
 
 }  // namespace
 
@@ -1176,12 +1295,20 @@ hipError_t launch_trace(const Scene& sc, const float* o, const float* d, int64_t
     return hipGetLastError();
 }
 
+hipError_t launch_edge_pack(const EdgeArgs& e, uint32_t cap, hipStream_t s) {
+    const uint32_t blocks = (cap + 255) / 256 < 4096u ? (cap + 255) / 256 : 4096u;
+    hipLaunchKernelGGL(edge_pack_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, e.edges, e.n_edges, e.verts,
+                       const_cast<float4*>(e.egeo), cap);
+    return hipGetLastError();
+}
+
 hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s) {
     if (e.npix <= 0) return hipSuccess;
     hipLaunchKernelGGL(edge_queue_reset, dim3(1), dim3(1), 0, s, e.q_count);
     hipLaunchKernelGGL(edge_gen_kernel, dim3((unsigned)((e.npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, e);
-    // the queue's length is on the device: a fixed grid strides over it
-    hipLaunchKernelGGL(edge_trace_kernel, dim3(1024), dim3(256), 0, s, e);
+    // the queue's length is on the device: a fixed grid of 8192 wavefronts
+    // strides over it, one record per wavefront
+    hipLaunchKernelGGL(edge_trace_kernel, dim3(2048), dim3(256), 0, s, e);
     return hipGetLastError();
 }
 
