@@ -371,7 +371,7 @@ def next_rows(args, M, gb, c_d, c_s, target, timed):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_rays_sphere8_grad_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_03380_amd", "csrc", f)
-                  for f in ("shade.hip", "device_common.h", "mcdi_internal.h", "bvh_build.hip")]
+                  for f in ("shade.hip", "shade_common.h", "device_common.h", "mcdi_internal.h", "bvh_build.hip")]
 
 
 def kernel_source_hash():

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmcdi.so")
 SOURCES = ["api.hip", "env_cdf.hip", "bvh_build.hip", "shade.hip", "loss.hip", "bilateral.hip", "env_scatter.hip",
-           "edges.hip"]
+           "edges.hip", "edge_grad.hip"]
 ARCH = os.environ.get("MCDI_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-munsafe-fp-atomics",

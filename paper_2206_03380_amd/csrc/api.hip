@@ -12,6 +12,7 @@
 #include <utility>
 #include <vector>
 
+#include "edge_internal.h"
 #include "mcdi_internal.h"
 
 using namespace mcdi;

@@ -1,0 +1,364 @@
+// Edge-sampled visibility gradient of the shadow term on gfx950: a sample
+// kernel that keeps the silhouette samples above the horizon of every pixel
+// as 4-byte records, and a trace kernel that evaluates each kept sample, traces
+// its out-side ray with a whole wavefront and scatters the term into the vertex
+// gradient (paper: section 3.1 "Shadow gradients"; appendix "Visibility
+// Gradients from Shadows").
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "device_common.h"
+#include "edge_internal.h"
+#include "shade_common.h"
+
+namespace mcdi {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Edge-sampled visibility gradient of the shadow term.  Seen from the ray
+// origin o, a silhouette edge a-b bounds the directions its face blocks; as
+// the vertices move, the arc through x(t) = a + t (b - a) moves along the
+// unit normal mh of the plane (o, a, b) at mh . dx / r, r = |x - o|, and
+// sweeps |(b - a) x w| / r of arc per unit t.  Across the arc the integrand
+// drops from g to g (1 - tau) when nothing else blocks the out side, so a
+// sample (edge e uniform over E, t uniform) adds
+//   E s tau g(w) |(b - a) x w| / r^2 / n_es  x  ((1 - t) mh, t mh)
+// to the gradients of a and b, s = +1 when the face lies on the +mh side.
+// Silhouette: the edge's two faces lie on the same side of the plane (or it
+// has one face).  g contracts the unshadowed integrand of c_d and c_s with
+// the upstream gradients.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float3 load_vert(const float* v, int32_t i) {
+    const float* p = v + 3 * (size_t)i;
+    return f3(p[0], p[1], p[2]);
+}
+
+__device__ __forceinline__ float3 cross(float3 a, float3 b) {
+    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// probe radiance in direction w (nearest texel, or bilinear with BIL)
+__device__ __forceinline__ float3 probe_radiance(const EnvView& e, float3 w, bool bil) {
+    const int H = e.H, W = e.W;
+    const float rho = sqrtf(w.x * w.x + w.z * w.z);
+    const float th = atan2f(rho, w.y);
+    float ph = atan2f(w.z, w.x);
+    if (ph < 0.0f) ph += 2.0f * kPi;
+    const float y = th * ((float)H * kInvPi);
+    const float x = ph * ((float)W * (0.5f * kInvPi));
+    if (bil) {
+        const Taps T = bilinear_taps(e, x, y);
+        return T.w[0] * texel_rgb(e, T.t[0]) + T.w[1] * texel_rgb(e, T.t[1]) + T.w[2] * texel_rgb(e, T.t[2]) +
+               T.w[3] * texel_rgb(e, T.t[3]);
+    }
+    const int ti = min((int)y, H - 1), tj = min((int)x, W - 1);
+    return texel_rgb(e, ti * W + tj);
+}
+
+// The face sides come from det(a - o, b - o, c - o) written as (a - o) .
+// ((b - a) x (c - a)), free of the cancellation of differences from a
+// distant o.  Returns false when the sample cannot carry a term: no
+// silhouette, a degenerate arc, or the point at or below the horizon.
+struct EdgeGeom {
+    uint32_t e;          // edge row
+    float t, s;          // point on the edge; +1 when the face lies on the +mh side
+    float3 w, mh;        // unit direction to the point; unit arc normal
+    float r2;            // squared distance to the point
+    float3 eab;
+};
+
+__device__ __forceinline__ bool edge_geom(const EdgeArgs& E, const Pixel& P, uint32_t piv, uint32_t vid, int j,
+                                          uint32_t ne, EdgeGeom& G) {
+    const uint32_t k0 = (uint32_t)E.a.seed, k1 = (uint32_t)(E.a.seed >> 32);
+    const uint4 r = philox10(make_uint4(piv, vid, (uint32_t)j, 2u), k0, k1);
+    G.e = __umulhi(r.x, ne);
+    G.t = u01(r.y);
+    // the edge's corners, packed in one 64-byte line for this call
+    const float4* q = E.egeo + 4 * (size_t)G.e;
+    const float4 pa = q[0], pb = q[1], pc = q[2], pd = q[3];
+    const float3 va = f3(pa.x, pa.y, pa.z);
+    const float3 qa = va - P.o;
+    G.eab = f3(pb.x, pb.y, pb.z) - va;
+    const float3 m = cross(qa, G.eab);   // = (a - o) x (b - o)
+    const float sc = dot(qa, cross(G.eab, f3(pc.x, pc.y, pc.z) - va));
+    if (sc == 0.0f) return false;
+    if (pd.w != 0.0f) {
+        const float sd = dot(qa, cross(G.eab, f3(pd.x, pd.y, pd.z) - va));
+        if ((sc > 0.0f && sd < 0.0f) || (sc < 0.0f && sd > 0.0f)) return false;   // both sides covered
+    }
+    const float ml2 = dot(m, m);
+    if (!(ml2 > 0.0f)) return false;
+    const float3 w = qa + G.t * G.eab;
+    G.r2 = dot(w, w);
+    G.w = (1.0f / sqrtf(G.r2)) * w;
+    if (!(dot(G.w, P.n) > 0.0f)) return false;
+    G.mh = (1.0f / sqrtf(ml2)) * m;
+    G.s = sc > 0.0f ? 1.0f : -1.0f;
+    return true;
+}
+
+// The part of setup_pixel the edge filter needs: validity (same rules), the
+// shadow-ray origin and the unit normal, with the same FP64 arithmetic so
+// that both are bit-identical to setup_pixel's.
+__device__ __forceinline__ bool pixel_origin(const ShadeArgs& A, int64_t pix, Pixel& P, bool& nonfinite) {
+    const GBufView& g = A.g;
+    const int64_t N = g.n;
+    nonfinite = false;
+    if (!g.mask[pix]) return false;
+    const int v = (int)(pix / ((int64_t)g.height * g.width));
+    const float px = g.pos[pix], py = g.pos[N + pix], pz = g.pos[2 * N + pix];
+    const float nxf = g.nrm[pix], nyf = g.nrm[N + pix], nzf = g.nrm[2 * N + pix];
+    const float ex = g.eye[3 * v], ey = g.eye[3 * v + 1], ez = g.eye[3 * v + 2];
+    if (!(finite3(px, py, pz) && finite3(nxf, nyf, nzf) &&
+          finite3(g.kd[pix], g.kd[N + pix], g.kd[2 * N + pix]) &&
+          finite3(g.korm[pix], g.korm[N + pix], g.korm[2 * N + pix]) && finite3(ex, ey, ez))) {
+        nonfinite = true;
+        return false;
+    }
+    if (nxf == 0.0f && nyf == 0.0f && nzf == 0.0f) return false;
+    const double wx = (double)ex - px, wy = (double)ey - py, wz = (double)ez - pz;
+    if (wx == 0.0 && wy == 0.0 && wz == 0.0) return false;
+    const double nl = sqrt((double)nxf * nxf + (double)nyf * nyf + (double)nzf * nzf);
+    const double nx = nxf / nl, ny = nyf / nl, nz = nzf / nl;
+    const double eps = (double)A.ray_eps;
+    P.n = f3((float)nx, (float)ny, (float)nz);
+    P.o = f3((float)(px + eps * nx), (float)(py + eps * ny), (float)(pz + eps * nz));
+    return true;
+}
+
+// 1) every edge sample of a pass of pixels; the candidates (silhouette, above
+//    the horizon) go to the queue as (pixel in pass << 10 | sample).  Samples
+//    are filtered 32 at a time into a bit mask before any append, so that
+//    their loads overlap.
+__global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
+    const ShadeArgs& A = E.a;
+    const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t pix = E.pix0 + local;
+    const bool active = local < E.npix && pix < A.g.n;
+    const uint32_t ne = *E.n_edges;
+    bool nonfinite = false, valid = false;
+    Pixel P;
+    if (active) valid = pixel_origin(A, pix, P, nonfinite);
+    const bool go = valid && ne > 0u && A.tau != 0.0f;
+    const int64_t hw = (int64_t)A.g.height * A.g.width;
+    const uint32_t view = active ? (uint32_t)(pix / hw) : 0u;
+    const uint32_t piv = active ? (uint32_t)(pix - (int64_t)view * hw) : 0u;
+    const uint32_t vid = (uint32_t)A.g.view_base + view;
+    const int lane = __lane_id();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int j0 = 0; j0 < E.n_es; j0 += 32) {
+        const int nj = E.n_es - j0 < 32 ? E.n_es - j0 : 32;
+        uint32_t bits = 0u;
+        if (go) {
+            for (int jj = 0; jj < nj; ++jj) {
+                EdgeGeom G;
+                if (edge_geom(E, P, piv, vid, j0 + jj, ne, G)) bits |= 1u << jj;
+            }
+        }
+        if (__ballot(bits != 0u) == 0ull) continue;
+        for (int jj = 0; jj < nj; ++jj) {
+            const bool emit = (bits >> jj) & 1u;
+            const uint64_t bal = __ballot(emit);
+            if (bal == 0ull) continue;
+            const int leader = __ffsll((unsigned long long)bal) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(E.q_count, (uint32_t)__popcll(bal));
+            base = (uint32_t)__shfl((int)base, leader);
+            if (emit) {
+                const uint32_t at = base + (uint32_t)__popcll(bal & lt);
+                // the queue holds every sample of the pass; the check only
+                // guards the bound
+                if (at < E.q_cap) E.queue[at] = ((uint32_t)local << 10) | (uint32_t)(j0 + jj);
+            }
+        }
+    }
+    if (A.stats) {
+        const uint32_t v = wave_sum(valid ? 1u : 0u), nf = wave_sum(nonfinite ? 1u : 0u);
+        if (lane == 0) {
+            atomicAdd(&A.stats->valid_pixels, (unsigned long long)v);
+            atomicAdd(&A.stats->invalid_pixels, (unsigned long long)nf);
+        }
+    }
+}
+
+// Any-hit query of one ray by a whole wavefront.  Lane k descends six levels
+// from the root along the bits of k to one of up to 64 disjoint subtrees (the
+// first child of an internal node i is i + 1, the second is the first child's
+// skip link; a leaf reached early belongs to the lane whose remaining bits are
+// zero) and walks its subtree with the skip links, bounded by the subtree's
+// end.  A missed ancestor box implies missed descendants, so testing each
+// subtree root's own box suffices.  The walk stops as soon as any lane finds
+// a hit.  The ray must be the same in every lane; the result is uniform.
+__device__ __forceinline__ bool wave_anyhit(const Scene& sc, const Ray& r, int n_total) {
+    if (n_total <= 0) return false;
+    const float4* nodes = reinterpret_cast<const float4*>(sc.nodes);
+    constexpr int kDepth = 6;
+    const int lane = __lane_id();
+    int node = 0;
+    bool mine = true;
+    for (int lvl = 0; lvl < kDepth; ++lvl) {
+        const int payload = __float_as_int(nodes[2 * node + 1].w);
+        int right = -1;
+        if (payload == 0 && node + 1 < n_total) right = __float_as_int(nodes[2 * (node + 1)].w);
+        // a leaf (or a malformed link) ends the descent here
+        if (payload != 0 || right <= node + 1 || right >= n_total) {
+            mine = (lane >> lvl) == 0;
+            break;
+        }
+        node = ((lane >> lvl) & 1) ? right : node + 1;
+    }
+    const int esc = __float_as_int(nodes[2 * node].w);
+    const int end = (esc > node && esc <= n_total) ? esc : n_total;
+    int i = mine ? node : end;
+    bool hit = false;
+    while (__any(i < end)) {
+        if (i < end) {
+            const float4 a = nodes[2 * i];
+            const float4 b = nodes[2 * i + 1];
+            const int escape = __float_as_int(a.w);
+            const int payload = __float_as_int(b.w);
+            const int next = (escape > i && escape <= end) ? escape : end;
+            if (!box_hit(r, a, b)) {
+                i = next;
+            } else if (payload == 0) {
+                ++i;
+            } else {
+                const int first = payload >> 3;
+                const int cnt = (first + (payload & 7) <= sc.n_tris) ? (payload & 7) : 0;
+                for (int k = 0; k < cnt && !hit; ++k) {
+                    const float4* t = sc.tris + 3 * (first + k);
+                    hit = tri_anyhit(r, t[0], t[1], t[2]);
+                }
+                i = next;
+            }
+        }
+        if (__any(hit)) return true;
+    }
+    return false;
+}
+
+// 2) the queued candidates, one per wavefront: the sample is recomputed (in
+//    every lane alike), its term evaluated and its out-side ray traced by the
+//    whole wavefront; a ray that reaches the probe adds the term to both
+//    vertices of the edge
+__global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
+    const ShadeArgs& A = E.a;
+    const Scene& sc = A.scene;
+    const uint32_t n = min(*E.q_count, E.q_cap);
+    const uint32_t ne = *E.n_edges;
+    const int n_total = sc.nodes[0].escape;
+    const bool bil = (A.flags & MCDI_FLAG_BILINEAR) != 0;
+    const int64_t N = A.g.n;
+    const int64_t hw = (int64_t)A.g.height * A.g.width;
+    const float scale = (float)ne * A.tau / (float)E.n_es;
+    const bool lead = __lane_id() == 0;
+    uint32_t c_rays = 0, c_hits = 0;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t i = wave; i < n; i += n_waves) {
+        const uint32_t rec = E.queue[i];
+        const int64_t pix = E.pix0 + (int64_t)(rec >> 10);
+        const int j = (int)(rec & 1023u);
+        if (pix >= N) continue;
+        bool nonfinite;
+        const Pixel P = setup_pixel(A, pix, nonfinite);
+        if (!P.valid) continue;
+        const uint32_t view = (uint32_t)(pix / hw);
+        const uint32_t piv = (uint32_t)(pix - (int64_t)view * hw);
+        EdgeGeom G;
+        if (!edge_geom(E, P, piv, (uint32_t)A.g.view_base + view, j, ne, G)) continue;
+        const float3 Ud = f3(A.g_cd[pix], A.g_cd[N + pix], A.g_cd[2 * N + pix]);
+        const float3 Us = f3(A.g_cs[pix], A.g_cs[N + pix], A.g_cs[2 * N + pix]);
+        const float3 w = G.w;
+        const float NoL = dot(w, P.n);
+        const float3 ex = cross(G.eab, w);
+        const float J = sqrtf(dot(ex, ex)) / G.r2;
+        const float3 L = probe_radiance(A.env, w, bil);
+        // unshadowed integrand at w (unit density), contracted
+        const float3 wl = f3(dot(w, P.t), dot(w, P.b), NoL);
+        const float kdiff = (1.0f - P.m) * kInvPi * NoL;
+        float g = kdiff * (Ud.x * L.x + Ud.y * L.y + Ud.z * L.z);
+        if (P.nov_pos) {
+            const float3 hl = normalize(P.Vl + wl);
+            const float s2 = hl.x * hl.x + hl.y * hl.y;
+            const float D = ggx_D(hl.z, s2, P.a2);
+            const float lamL = smith_lambda(smith_t2(NoL), P.a2);
+            const float Sv = D / (1.0f + P.lamV + lamL) / (4.0f * P.nov);
+            const float omv = 1.0f - dot(P.Vl, hl);
+            const float o2 = omv * omv;
+            const float Fw = o2 * o2 * omv;
+            const float3 F = f3(P.F0.x + (1.0f - P.F0.x) * Fw, P.F0.y + (1.0f - P.F0.y) * Fw,
+                                P.F0.z + (1.0f - P.F0.z) * Fw);
+            g += Sv * (Us.x * F.x * L.x + Us.y * F.y * L.y + Us.z * F.z * L.z);
+        }
+        const float wt = G.s * scale * J * g;
+        if (!(wt != 0.0f && isfinite(wt))) continue;
+        const float3 wo = normalize(w - (G.s * kEdgeDelta) * G.mh);
+        ++c_rays;
+        if (wave_anyhit(sc, make_ray(P.o, wo), n_total)) {
+            ++c_hits;
+            continue;
+        }
+        if (lead) {
+            const int4 ed = E.edges[G.e];
+            const float ta = 1.0f - G.t;
+            float* ga = E.g_verts + 3 * (size_t)ed.x;
+            float* gb = E.g_verts + 3 * (size_t)ed.y;
+            atomicAdd(ga + 0, ta * wt * G.mh.x);
+            atomicAdd(ga + 1, ta * wt * G.mh.y);
+            atomicAdd(ga + 2, ta * wt * G.mh.z);
+            atomicAdd(gb + 0, G.t * wt * G.mh.x);
+            atomicAdd(gb + 1, G.t * wt * G.mh.y);
+            atomicAdd(gb + 2, G.t * wt * G.mh.z);
+        }
+    }
+    if (A.stats && lead && c_rays) {
+        atomicAdd(&A.stats->rays_traced, (unsigned long long)c_rays);
+        atomicAdd(&A.stats->rays_hit, (unsigned long long)c_hits);
+    }
+}
+
+__global__ void edge_queue_reset(uint32_t* q_count) { *q_count = 0u; }
+
+// corners of every edge for this call's vertex positions: (a, 0), (b, 0),
+// (c, 0), (d, 1) or (0, 0, 0, 0) without a second face
+__global__ void edge_pack_kernel(const int4* __restrict__ edges, const uint32_t* n_edges, const float* verts,
+                                 float4* egeo, uint32_t cap) {
+    const uint32_t n = min(*n_edges, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int4 ed = edges[i];
+        const float3 a = load_vert(verts, ed.x), b = load_vert(verts, ed.y), c = load_vert(verts, ed.z);
+        float4* q = egeo + 4 * (size_t)i;
+        q[0] = make_float4(a.x, a.y, a.z, 0.0f);
+        q[1] = make_float4(b.x, b.y, b.z, 0.0f);
+        q[2] = make_float4(c.x, c.y, c.z, 0.0f);
+        if (ed.w >= 0) {
+            const float3 d = load_vert(verts, ed.w);
+            q[3] = make_float4(d.x, d.y, d.z, 1.0f);
+        } else {
+            q[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_edge_pack(const EdgeArgs& e, uint32_t cap, hipStream_t s) {
+    const uint32_t blocks = (cap + 255) / 256 < 4096u ? (cap + 255) / 256 : 4096u;
+    hipLaunchKernelGGL(edge_pack_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, e.edges, e.n_edges, e.verts,
+                       const_cast<float4*>(e.egeo), cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s) {
+    if (e.npix <= 0) return hipSuccess;
+    hipLaunchKernelGGL(edge_queue_reset, dim3(1), dim3(1), 0, s, e.q_count);
+    hipLaunchKernelGGL(edge_gen_kernel, dim3((unsigned)((e.npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, e);
+    // the queue's length is on the device: a fixed grid of 8192 wavefronts
+    // strides over it, one record per wavefront
+    hipLaunchKernelGGL(edge_trace_kernel, dim3(2048), dim3(256), 0, s, e);
+    return hipGetLastError();
+}
+
+}  // namespace mcdi

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "edge_internal.h"
 #include "mcdi_internal.h"
 
 namespace mcdi {

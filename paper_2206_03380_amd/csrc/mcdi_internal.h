@@ -105,27 +105,6 @@ struct ServeItem {
     int64_t first_global;  // index of that tile in the launch's tile queue
 };
 
-// edge-sampled visibility gradient of the shadow term: one kernel over a
-// range of pixels queues the edge samples that are silhouettes above the
-// horizon, a second recomputes them, traces their out-side rays and scatters
-// the terms of the rays that miss into g_verts
-constexpr float kEdgeDelta = 1.0f / 8192.0f;   // angle of the out-side ray off the edge (radians)
-constexpr uint32_t kEdgeQueueMax = 1u << 25;   // queue records per pass (4 bytes each)
-constexpr int64_t kEdgePassMax = 1 << 22;      // pixels per pass (22 bits of the record)
-struct EdgeArgs {
-    ShadeArgs a;             // scene, env, G-buffer, seed, tau, ray_eps, flags, g_cd, g_cs, stats
-    const int4* edges;       // [E] (a, b, c, d) rows
-    const uint32_t* n_edges; // E (device)
-    const float* verts;      // [Nv][3]
-    const float4* egeo;      // [E][4] corners a, b, c, d of each edge (d.w = 1 when present)
-    float* g_verts;          // [Nv][3], accumulated
-    int32_t n_es;            // edge samples per pixel
-    int64_t pix0, npix;      // pixel range of this pass
-    uint32_t* queue;         // [q_cap]: pixel in pass << 10 | edge sample
-    uint32_t* q_count;
-    uint32_t q_cap;
-};
-
 // kernel launchers (return hipError_t of the launch)
 hipError_t launch_serve(const ServeItem* items_dev, int n_items, int64_t total_tiles, int* tile_counter,
                         float4* scratch, int spp_max, int n_workgroups, int max_H, hipStream_t s);
@@ -183,19 +162,6 @@ size_t image_loss_scratch_bytes(int64_t n);
 hipError_t launch_image_loss(const float* kd, const float* cd, const float* cs, const float* ref,
                              const uint8_t* mask, int64_t n, float w_light, float* loss, float* g_kd, float* g_cd,
                              float* g_cs, void* scratch, hipStream_t s);
-
-// one pass of the edge-sampled visibility gradient over [pix0, pix0 + npix)
-hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s);
-// packs the corners of the first min(E, cap) edges into e.egeo
-hipError_t launch_edge_pack(const EdgeArgs& e, uint32_t cap, hipStream_t s);
-
-// unique mesh edges: hash table of 2^bits slots (keys, first and second
-// side), side -> slot map [3 n_tris], block sums [edge_scan_blocks]
-int edge_table_bits(int64_t n_sides);
-uint32_t edge_scan_blocks(int64_t n_sides);
-hipError_t launch_edges_build(const int32_t* tris, int64_t n_tris, int64_t n_verts, int bits,
-                              unsigned long long* keys, uint32_t* first, uint32_t* second, uint32_t* slot_of,
-                              uint32_t* bsum, int4* rows, uint32_t* n_edges, hipStream_t s);
 
 // Cross-bilateral filter over V views of H x W pixels (N = V*H*W).
 constexpr int kBilatMaxR = 8;
