@@ -557,8 +557,21 @@ def cpu_baseline(args, w):
     n2 = int(min(len(valid), max(n, n * args.cpu_seconds / max(dt, 1e-3))))
     dt2 = run(n2)
     what = "all %d valid pixels" % n2 if n2 == len(valid) else "%d random valid pixels" % n2
-    return {"value": n2 * w.spp / dt2, "unit": "samples/s", "cores": nthreads, "kind": "oracle",
-            "sample": "%s of the same workload, forward + backward, %.1f s" % (what, dt2)}
+    res = {"value": n2 * w.spp / dt2, "unit": "samples/s", "cores": nthreads, "kind": "oracle",
+           "sample": "%s of the same workload, forward + backward, %.1f s" % (what, dt2)}
+    if not args.no_next_rows:
+        # the oracle's edge-sampled visibility gradient beside the kernels' (row f4)
+        edges = oracle.mesh_edges(w.tris, len(w.verts))
+        # every valid pixel: the same work as the kernels' measurement
+        t = time.time()
+        oracle.edge_grad(w, edges, EDGE_SPP, ud[:, valid].astype(np.float64), us[:, valid].astype(np.float64),
+                         pixels=valid, scene=scene, tables=tables)
+        dte = time.time() - t
+        res["visibility_gradient"] = {"value": len(valid) * EDGE_SPP / dte, "unit": "edge samples/s",
+                                      "cores": nthreads, "kind": "oracle",
+                                      "sample": "all %d valid pixels x %d edge samples, %.2f s" % (
+                                          len(valid), EDGE_SPP, dte)}
+    return res
 
 
 if __name__ == "__main__":
