@@ -68,34 +68,53 @@ struct EdgeGeom {
     float3 eab;
 };
 
-__device__ __forceinline__ bool edge_geom(const EdgeArgs& E, const Pixel& P, uint32_t piv, uint32_t vid, int j,
-                                          uint32_t ne, EdgeGeom& G) {
+// the sample's random numbers and its edge's corners, fetched in one go
+struct EdgeFetch {
+    uint32_t e;
+    float t;
+    float4 pa, pb, pc, pd;
+};
+
+__device__ __forceinline__ EdgeFetch edge_fetch(const EdgeArgs& E, uint32_t piv, uint32_t vid, int j, uint32_t ne) {
     const uint32_t k0 = (uint32_t)E.a.seed, k1 = (uint32_t)(E.a.seed >> 32);
     const uint4 r = philox10(make_uint4(piv, vid, (uint32_t)j, 2u), k0, k1);
-    G.e = __umulhi(r.x, ne);
-    G.t = u01(r.y);
+    EdgeFetch F;
+    F.e = __umulhi(r.x, ne);
+    F.t = u01(r.y);
     // the edge's corners, packed in one 64-byte line for this call
-    const float4* q = E.egeo + 4 * (size_t)G.e;
-    const float4 pa = q[0], pb = q[1], pc = q[2], pd = q[3];
-    const float3 va = f3(pa.x, pa.y, pa.z);
+    const float4* q = E.egeo + 4 * (size_t)F.e;
+    F.pa = q[0];
+    F.pb = q[1];
+    F.pc = q[2];
+    F.pd = q[3];
+    return F;
+}
+
+__device__ __forceinline__ bool edge_test(const Pixel& P, const EdgeFetch& F, EdgeGeom& G) {
+    G.e = F.e;
+    G.t = F.t;
+    const float3 va = f3(F.pa.x, F.pa.y, F.pa.z);
     const float3 qa = va - P.o;
-    G.eab = f3(pb.x, pb.y, pb.z) - va;
+    G.eab = f3(F.pb.x, F.pb.y, F.pb.z) - va;
     const float3 m = cross(qa, G.eab);   // = (a - o) x (b - o)
-    const float sc = dot(qa, cross(G.eab, f3(pc.x, pc.y, pc.z) - va));
-    if (sc == 0.0f) return false;
-    if (pd.w != 0.0f) {
-        const float sd = dot(qa, cross(G.eab, f3(pd.x, pd.y, pd.z) - va));
-        if ((sc > 0.0f && sd < 0.0f) || (sc < 0.0f && sd > 0.0f)) return false;   // both sides covered
-    }
+    const float sc = dot(qa, cross(G.eab, f3(F.pc.x, F.pc.y, F.pc.z) - va));
+    // the second face's side (its corner is zero without a second face)
+    const float sd = dot(qa, cross(G.eab, f3(F.pd.x, F.pd.y, F.pd.z) - va));
     const float ml2 = dot(m, m);
-    if (!(ml2 > 0.0f)) return false;
     const float3 w = qa + G.t * G.eab;
     G.r2 = dot(w, w);
     G.w = (1.0f / sqrtf(G.r2)) * w;
-    if (!(dot(G.w, P.n) > 0.0f)) return false;
     G.mh = (1.0f / sqrtf(ml2)) * m;
     G.s = sc > 0.0f ? 1.0f : -1.0f;
-    return true;
+    // evaluated without branches, so that every load of the sample is issued
+    // before any of its values is needed
+    const bool covered = (F.pd.w != 0.0f) & (((sc > 0.0f) & (sd < 0.0f)) | ((sc < 0.0f) & (sd > 0.0f)));
+    return (sc != 0.0f) & !covered & (ml2 > 0.0f) & (dot(G.w, P.n) > 0.0f);
+}
+
+__device__ __forceinline__ bool edge_geom(const EdgeArgs& E, const Pixel& P, uint32_t piv, uint32_t vid, int j,
+                                          uint32_t ne, EdgeGeom& G) {
+    return edge_test(P, edge_fetch(E, piv, vid, j, ne), G);
 }
 
 // The part of setup_pixel the edge filter needs: validity (same rules), the
@@ -151,7 +170,16 @@ __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
         const int nj = E.n_es - j0 < 32 ? E.n_es - j0 : 32;
         uint32_t bits = 0u;
         if (go) {
-            for (int jj = 0; jj < nj; ++jj) {
+            // two samples per step: both fetches are in flight before either test
+            int jj = 0;
+            for (; jj + 1 < nj; jj += 2) {
+                const EdgeFetch F0 = edge_fetch(E, piv, vid, j0 + jj, ne);
+                const EdgeFetch F1 = edge_fetch(E, piv, vid, j0 + jj + 1, ne);
+                EdgeGeom G;
+                if (edge_test(P, F0, G)) bits |= 1u << jj;
+                if (edge_test(P, F1, G)) bits |= 2u << jj;
+            }
+            if (jj < nj) {
                 EdgeGeom G;
                 if (edge_geom(E, P, piv, vid, j0 + jj, ne, G)) bits |= 1u << jj;
             }
