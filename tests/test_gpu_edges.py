@@ -131,6 +131,18 @@ def test_edge_grad_parity_tiny():
     assert o["traced"] > 100 and np.abs(o["g_verts"]).max() > 0
 
 
+def test_edge_grad_parity_tau_and_view_base():
+    """tau = 1/2 scales every term; view_base shifts the view id of the random
+    counter; a different seed draws other edges."""
+    _need_gpu()
+    w = make_workload("tiny")
+    w.tau = 0.5
+    w.view_base = 3
+    w.seed = 12345
+    g, o = _parity(w, 16)
+    assert o["traced"] > 100
+
+
 def test_edge_grad_parity_sphere8_small():
     _need_gpu()
     _parity(make_workload("sphere8_grad", H=64, W=64, n_views=1), 8)
