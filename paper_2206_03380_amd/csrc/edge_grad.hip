@@ -266,10 +266,81 @@ __device__ __forceinline__ bool wave_anyhit(const Scene& sc, const Ray& r, int n
     return false;
 }
 
-// 2) the queued candidates, one per wavefront: the sample is recomputed (in
-//    every lane alike), its term evaluated and its out-side ray traced by the
-//    whole wavefront; a ray that reaches the probe adds the term to both
-//    vertices of the edge
+// a queued sample recomputed: ray origin, out-side direction, the term and
+// where it goes (false: the sample carries no term)
+struct EdgeTerm {
+    float3 o, wo, mh;
+    float wt, t;
+    uint32_t e;
+};
+
+__device__ __forceinline__ bool edge_term(const EdgeArgs& E, uint32_t rec, uint32_t ne, float scale, bool bil,
+                                          EdgeTerm& T) {
+    const ShadeArgs& A = E.a;
+    const int64_t N = A.g.n;
+    const int64_t hw = (int64_t)A.g.height * A.g.width;
+    const int64_t pix = E.pix0 + (int64_t)(rec >> 10);
+    const int j = (int)(rec & 1023u);
+    if (pix >= N) return false;
+    bool nonfinite;
+    const Pixel P = setup_pixel(A, pix, nonfinite);
+    if (!P.valid) return false;
+    const uint32_t view = (uint32_t)(pix / hw);
+    const uint32_t piv = (uint32_t)(pix - (int64_t)view * hw);
+    EdgeGeom G;
+    if (!edge_geom(E, P, piv, (uint32_t)A.g.view_base + view, j, ne, G)) return false;
+    const float3 Ud = f3(A.g_cd[pix], A.g_cd[N + pix], A.g_cd[2 * N + pix]);
+    const float3 Us = f3(A.g_cs[pix], A.g_cs[N + pix], A.g_cs[2 * N + pix]);
+    const float3 w = G.w;
+    const float NoL = dot(w, P.n);
+    const float3 ex = cross(G.eab, w);
+    const float J = sqrtf(dot(ex, ex)) / G.r2;
+    const float3 L = probe_radiance(A.env, w, bil);
+    // unshadowed integrand at w (unit density), contracted
+    const float3 wl = f3(dot(w, P.t), dot(w, P.b), NoL);
+    const float kdiff = (1.0f - P.m) * kInvPi * NoL;
+    float g = kdiff * (Ud.x * L.x + Ud.y * L.y + Ud.z * L.z);
+    if (P.nov_pos) {
+        const float3 hl = normalize(P.Vl + wl);
+        const float s2 = hl.x * hl.x + hl.y * hl.y;
+        const float D = ggx_D(hl.z, s2, P.a2);
+        const float lamL = smith_lambda(smith_t2(NoL), P.a2);
+        const float Sv = D / (1.0f + P.lamV + lamL) / (4.0f * P.nov);
+        const float omv = 1.0f - dot(P.Vl, hl);
+        const float o2 = omv * omv;
+        const float Fw = o2 * o2 * omv;
+        const float3 F = f3(P.F0.x + (1.0f - P.F0.x) * Fw, P.F0.y + (1.0f - P.F0.y) * Fw,
+                            P.F0.z + (1.0f - P.F0.z) * Fw);
+        g += Sv * (Us.x * F.x * L.x + Us.y * F.y * L.y + Us.z * F.z * L.z);
+    }
+    T.wt = G.s * scale * J * g;
+    if (!(T.wt != 0.0f && isfinite(T.wt))) return false;
+    T.o = P.o;
+    T.wo = normalize(w - (G.s * kEdgeDelta) * G.mh);
+    T.mh = G.mh;
+    T.t = G.t;
+    T.e = G.e;
+    return true;
+}
+
+__device__ __forceinline__ void edge_scatter(const EdgeArgs& E, const EdgeTerm& T) {
+    const int4 ed = E.edges[T.e];
+    const float ta = 1.0f - T.t;
+    float* ga = E.g_verts + 3 * (size_t)ed.x;
+    float* gb = E.g_verts + 3 * (size_t)ed.y;
+    atomicAdd(ga + 0, ta * T.wt * T.mh.x);
+    atomicAdd(ga + 1, ta * T.wt * T.mh.y);
+    atomicAdd(ga + 2, ta * T.wt * T.mh.z);
+    atomicAdd(gb + 0, T.t * T.wt * T.mh.x);
+    atomicAdd(gb + 1, T.t * T.wt * T.mh.y);
+    atomicAdd(gb + 2, T.t * T.wt * T.mh.z);
+}
+
+// 2) the queued candidates: each is recomputed, its term evaluated and its
+//    out-side ray traced; a ray that reaches the probe adds the term to both
+//    vertices of the edge.  Few candidates (the usual case: silhouettes
+//    above the horizon are rare): one per wavefront, the ray walked by all 64
+//    lanes.  Many (heavy geometry): one per lane, which keeps every lane busy.
 __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
     const ShadeArgs& A = E.a;
     const Scene& sc = A.scene;
@@ -277,69 +348,41 @@ __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
     const uint32_t ne = *E.n_edges;
     const int n_total = sc.nodes[0].escape;
     const bool bil = (A.flags & MCDI_FLAG_BILINEAR) != 0;
-    const int64_t N = A.g.n;
-    const int64_t hw = (int64_t)A.g.height * A.g.width;
     const float scale = (float)ne * A.tau / (float)E.n_es;
     const bool lead = __lane_id() == 0;
     uint32_t c_rays = 0, c_hits = 0;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t i = wave; i < n; i += n_waves) {
-        const uint32_t rec = E.queue[i];
-        const int64_t pix = E.pix0 + (int64_t)(rec >> 10);
-        const int j = (int)(rec & 1023u);
-        if (pix >= N) continue;
-        bool nonfinite;
-        const Pixel P = setup_pixel(A, pix, nonfinite);
-        if (!P.valid) continue;
-        const uint32_t view = (uint32_t)(pix / hw);
-        const uint32_t piv = (uint32_t)(pix - (int64_t)view * hw);
-        EdgeGeom G;
-        if (!edge_geom(E, P, piv, (uint32_t)A.g.view_base + view, j, ne, G)) continue;
-        const float3 Ud = f3(A.g_cd[pix], A.g_cd[N + pix], A.g_cd[2 * N + pix]);
-        const float3 Us = f3(A.g_cs[pix], A.g_cs[N + pix], A.g_cs[2 * N + pix]);
-        const float3 w = G.w;
-        const float NoL = dot(w, P.n);
-        const float3 ex = cross(G.eab, w);
-        const float J = sqrtf(dot(ex, ex)) / G.r2;
-        const float3 L = probe_radiance(A.env, w, bil);
-        // unshadowed integrand at w (unit density), contracted
-        const float3 wl = f3(dot(w, P.t), dot(w, P.b), NoL);
-        const float kdiff = (1.0f - P.m) * kInvPi * NoL;
-        float g = kdiff * (Ud.x * L.x + Ud.y * L.y + Ud.z * L.z);
-        if (P.nov_pos) {
-            const float3 hl = normalize(P.Vl + wl);
-            const float s2 = hl.x * hl.x + hl.y * hl.y;
-            const float D = ggx_D(hl.z, s2, P.a2);
-            const float lamL = smith_lambda(smith_t2(NoL), P.a2);
-            const float Sv = D / (1.0f + P.lamV + lamL) / (4.0f * P.nov);
-            const float omv = 1.0f - dot(P.Vl, hl);
-            const float o2 = omv * omv;
-            const float Fw = o2 * o2 * omv;
-            const float3 F = f3(P.F0.x + (1.0f - P.F0.x) * Fw, P.F0.y + (1.0f - P.F0.y) * Fw,
-                                P.F0.z + (1.0f - P.F0.z) * Fw);
-            g += Sv * (Us.x * F.x * L.x + Us.y * F.y * L.y + Us.z * F.z * L.z);
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n_threads = gridDim.x * blockDim.x;
+    if (n >= kEdgeLaneMode) {
+        for (uint32_t i = tid; i < n; i += n_threads) {
+            EdgeTerm T;
+            if (!edge_term(E, E.queue[i], ne, scale, bil, T)) continue;
+            ++c_rays;
+            uint32_t nb = 0, nt = 0;
+            if (n_total > 0 && bvh_anyhit(sc, make_ray(T.o, T.wo), n_total, nb, nt)) {
+                ++c_hits;
+                continue;
+            }
+            edge_scatter(E, T);
         }
-        const float wt = G.s * scale * J * g;
-        if (!(wt != 0.0f && isfinite(wt))) continue;
-        const float3 wo = normalize(w - (G.s * kEdgeDelta) * G.mh);
+        if (A.stats) {
+            const uint32_t a = wave_sum(c_rays), b = wave_sum(c_hits);
+            if (lead && a) {
+                atomicAdd(&A.stats->rays_traced, (unsigned long long)a);
+                atomicAdd(&A.stats->rays_hit, (unsigned long long)b);
+            }
+        }
+        return;
+    }
+    for (uint32_t i = tid >> 6; i < n; i += n_threads >> 6) {
+        EdgeTerm T;
+        if (!edge_term(E, E.queue[i], ne, scale, bil, T)) continue;
         ++c_rays;
-        if (wave_anyhit(sc, make_ray(P.o, wo), n_total)) {
+        if (wave_anyhit(sc, make_ray(T.o, T.wo), n_total)) {
             ++c_hits;
             continue;
         }
-        if (lead) {
-            const int4 ed = E.edges[G.e];
-            const float ta = 1.0f - G.t;
-            float* ga = E.g_verts + 3 * (size_t)ed.x;
-            float* gb = E.g_verts + 3 * (size_t)ed.y;
-            atomicAdd(ga + 0, ta * wt * G.mh.x);
-            atomicAdd(ga + 1, ta * wt * G.mh.y);
-            atomicAdd(ga + 2, ta * wt * G.mh.z);
-            atomicAdd(gb + 0, G.t * wt * G.mh.x);
-            atomicAdd(gb + 1, G.t * wt * G.mh.y);
-            atomicAdd(gb + 2, G.t * wt * G.mh.z);
-        }
+        if (lead) edge_scatter(E, T);
     }
     if (A.stats && lead && c_rays) {
         atomicAdd(&A.stats->rays_traced, (unsigned long long)c_rays);
@@ -384,7 +427,7 @@ hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s) {
     hipLaunchKernelGGL(edge_queue_reset, dim3(1), dim3(1), 0, s, e.q_count);
     hipLaunchKernelGGL(edge_gen_kernel, dim3((unsigned)((e.npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, e);
     // the queue's length is on the device: a fixed grid of 8192 wavefronts
-    // strides over it, one record per wavefront
+    // strides over it (one record per wavefront or per lane)
     hipLaunchKernelGGL(edge_trace_kernel, dim3(2048), dim3(256), 0, s, e);
     return hipGetLastError();
 }

@@ -13,6 +13,8 @@ namespace mcdi {
 constexpr float kEdgeDelta = 1.0f / 8192.0f;   // angle of the out-side ray off the edge (radians)
 constexpr uint32_t kEdgeQueueMax = 1u << 25;   // queue records per pass (4 bytes each)
 constexpr int64_t kEdgePassMax = 1 << 22;      // pixels per pass (22 bits of the record)
+// from this many queued rays on, one lane traces each ray instead of one wavefront
+constexpr uint32_t kEdgeLaneMode = 1u << 16;
 struct EdgeArgs {
     ShadeArgs a;             // scene, env, G-buffer, seed, tau, ray_eps, flags, g_cd, g_cs, stats
     const int4* edges;       // [E] (a, b, c, d) rows

@@ -247,3 +247,26 @@ def test_autograd_returns_visibility_gradient():
     g, r = to_np(verts.grad), to_np(ref)
     assert np.abs(r).max() > 0
     assert np.allclose(g, r, rtol=1e-5, atol=1e-6 * np.abs(r).max())
+
+
+def test_edge_list_and_grad_lattice_sampled():
+    """Maximum size: the 1.0M-triangle lattice room (thin beams, heavy
+    occlusion, many silhouettes); its edge list bit for bit, and the gradient
+    with the upstream gradient nonzero on sampled pixels."""
+    _need_gpu()
+    import paper_2206_03380_amd as M
+    w = make_workload("lattice", H=256, W=256, n_views=2)
+    print("lattice", len(w.verts), "verts", len(w.tris), "tris", flush=True)
+    ed = M.Edges(torch.from_numpy(w.tris).cuda(), len(w.verts))
+    rows = to_np(ed.rows())
+    ref = oracle.mesh_edges(w.tris, len(w.verts))
+    assert rows.shape == ref.shape and (rows == ref).all()
+    r = np.random.Generator(np.random.PCG64(5))
+    keep = np.sort(r.choice(np.nonzero(w.mask)[0], 2500, replace=False))
+    mask = np.zeros_like(w.mask)
+    mask[keep] = 1
+    w.mask = mask
+    # inside the closed room almost every out-side ray is blocked; 256 edge
+    # samples per pixel give a few that leave through the windows
+    g, o = _parity(w, 256, pixels=keep)
+    assert o["traced"] > 10000 and (o["g_verts"] != 0).sum() > 0
