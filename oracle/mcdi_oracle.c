@@ -1538,6 +1538,12 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
                     eac[k] = (double)verts[3 * (size_t)ed[2] + k] - A[k];
                     if (ed[3] >= 0) ead[k] = (double)verts[3 * (size_t)ed[3] + k] - A[k];
                 }
+                /* a non-finite corner: the sample adds nothing (no decision
+                 * the FP32 path takes on it can pass) */
+                int finite = 1;
+                for (int k = 0; k < 3; ++k)
+                    finite &= isfinite(qa[k]) && isfinite(eab[k]) && isfinite(eac[k]) && isfinite(ead[k]);
+                if (!finite) continue;
                 double m[3], nc[3], nd[3] = {0, 0, 0};
                 cross3(qa, eab, m);                  /* = (a - o) x (b - o) */
                 cross3(eab, eac, nc);

@@ -109,7 +109,8 @@ __device__ __forceinline__ bool edge_test(const Pixel& P, const EdgeFetch& F, Ed
     // evaluated without branches, so that every load of the sample is issued
     // before any of its values is needed
     const bool covered = (F.pd.w != 0.0f) & (((sc > 0.0f) & (sd < 0.0f)) | ((sc < 0.0f) & (sd > 0.0f)));
-    return (sc != 0.0f) & !covered & (ml2 > 0.0f) & (dot(G.w, P.n) > 0.0f);
+    // a non-finite corner makes a side non-finite: no term
+    return (sc != 0.0f) & isfinite(sc) & isfinite(sd) & !covered & (ml2 > 0.0f) & (dot(G.w, P.n) > 0.0f);
 }
 
 __device__ __forceinline__ bool edge_geom(const EdgeArgs& E, const Pixel& P, uint32_t piv, uint32_t vid, int j,

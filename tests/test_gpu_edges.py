@@ -193,6 +193,17 @@ def test_edge_grad_full_size_sampled():
     _parity(w, 8, pixels=keep)
 
 
+def test_edge_grad_parity_non_finite_vertex():
+    """A vertex at NaN: the scene drops its triangles, and no edge sample that
+    touches it adds a term (on either side)."""
+    _need_gpu()
+    w = make_workload("tiny")
+    w.verts = w.verts.copy()
+    w.verts[7] = np.nan
+    g, o = _parity(w, 16)
+    assert np.isfinite(g).all() and (g[7] == 0).all()
+
+
 def test_edge_grad_accumulates_and_degenerate_cases():
     _need_gpu()
     import paper_2206_03380_amd as M

@@ -272,3 +272,14 @@ def test_shared_silhouette_edge_counts_once():
     # out-side offset of the shared corners: a vanishing remainder
     assert np.abs(mean[3]).max() <= 1e-5 * np.abs(expect).max()
     _check_stat(mean[:3], se[:3], expect)
+
+
+def test_non_finite_vertex_adds_nothing():
+    """A triangle with a non-finite corner contributes nothing; the others
+    keep their closed form."""
+    V = np.vstack([TRI, [[np.nan, 1.0, 0.0], [0.5, 1.5, 0.5], [0.6, 1.4, 0.4]]])
+    w = _receiver(V, [[0, 1, 2], [3, 4, 5]])
+    ud, us = _ud_us(w)
+    mean, se = _mean_grad(w, ud, us, seeds=4)
+    assert np.isfinite(mean).all()
+    assert (mean[3:] == 0.0).all() or np.abs(mean[3:]).max() < 1e-12
