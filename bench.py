@@ -110,8 +110,14 @@ def main():
         target = (gbt.kd * cd_t + cs_t).detach()
         del sc0, ev0
 
+    side = torch.cuda.Stream()
+
     def step():
-        scene = M.Scene(verts, tris)                      # BVH rebuild (mesh changes every iteration)
+        # BVH rebuild (the mesh changes every iteration) on a side stream: the
+        # traversal waits for it, the ray generation before it does not
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            scene = M.Scene(verts, tris)
         envh = M.Env(env_t.detach())                      # probe tables rebuild
         c_d, c_s = M.MCDIShade.apply(kd, korm, nrm, env_t, scene, envh, gb, w.spp, w.seed, w.tau, w.ray_eps,
                                      M.FLAG_TIME_TRACE)

@@ -78,12 +78,18 @@ typedef struct {
  * verts/tris are read during the call's stream work only; the handle keeps no
  * reference to them.  Limits: n_verts < 2^31, n_tris < 2^26 (node and triangle
  * byte offsets stay 32-bit).
+ * Streams: every call that reads the scene makes its stream wait for the build
+ * (an event), right before its first kernel that reads the BVH, so a scene may
+ * be built on one stream and used on others, and the work of such a call that
+ * does not need the BVH (ray generation) overlaps the build.
  * ------------------------------------------------------------------------- */
 mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                              const mcdi_allocator* alloc, void* stream, mcdi_scene* out);
 
-/* Frees the scene's memory in stream order on the stream it was built on.
- * Work on other streams that uses the scene must have completed. */
+/* Frees the scene's memory in stream order on the stream it was built on,
+ * after the work of the last call that read the scene (also on another
+ * stream).  With calls enqueued on several streams at once, only the last one
+ * enqueued is waited for: the caller orders the others. */
 void mcdi_destroy_scene(mcdi_scene scene);
 
 typedef struct {

@@ -106,7 +106,25 @@ struct mcdi_scene_s {
     Node* nodes = nullptr;
     float4* tris = nullptr;
     DeviceSceneInfo* info = nullptr;
+    hipEvent_t built = nullptr;     // recorded on the build stream after the build
+    hipEvent_t last_use = nullptr;  // recorded after the last enqueued work that reads the scene
+    bool used = false;
 };
+
+namespace {
+
+// work that reads the scene on stream u waits for the build (a no-op order
+// on the build stream itself)
+hipError_t scene_acquire(mcdi_scene sc, hipStream_t u) { return hipStreamWaitEvent(u, sc->built, 0); }
+
+// marks the end of work that reads the scene on stream u; the scene's memory
+// is released only after it
+hipError_t scene_release(mcdi_scene sc, hipStream_t u) {
+    sc->used = true;
+    return hipEventRecord(sc->last_use, u);
+}
+
+}  // namespace
 
 struct mcdi_env_s {
     Alloc alloc;
@@ -174,9 +192,16 @@ mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t*
         mcdi_destroy_scene(sc);
         return fail(MCDI_E_OOM, "mcdi_build_scene: device allocation failed (%lld triangles)", (long long)n_tris);
     }
+    if (hipEventCreateWithFlags(&sc->built, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sc->last_use, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        mcdi_destroy_scene(sc);
+        return fail(MCDI_E_DEVICE, "mcdi_build_scene: event creation failed");
+    }
     TempAlloc ta{temp_alloc, temp_free, &sc->alloc};
     int oom = 0;
     hipError_t e = build_bvh(verts, n_verts, tris, n_tris, sc->nodes, sc->tris, sc->info, ta, s, &oom);
+    if (e == hipSuccess) e = hipEventRecord(sc->built, s);
     if (e != hipSuccess) {
         mcdi_destroy_scene(sc);
         if (oom) return fail(MCDI_E_OOM, "mcdi_build_scene: temporary allocation failed");
@@ -188,9 +213,14 @@ mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t*
 
 void mcdi_destroy_scene(mcdi_scene sc) {
     if (!sc) return;
+    // the memory goes back in the build stream's order, after the last
+    // enqueued work that reads it
+    if (sc->used) (void)hipStreamWaitEvent(sc->stream, sc->last_use, 0);
     sc->alloc.put(sc->nodes, sc->stream);
     sc->alloc.put(sc->tris, sc->stream);
     sc->alloc.put(sc->info, sc->stream);
+    if (sc->built) (void)hipEventDestroy(sc->built);
+    if (sc->last_use) (void)hipEventDestroy(sc->last_use);
     delete sc;
 }
 
@@ -218,6 +248,7 @@ mcdi_status mcdi_scene_nodes(mcdi_scene sc, void* nodes, float* tris, void* stre
         e = hipMemcpyAsync(nodes, sc->nodes, sizeof(Node) * (size_t)h.n_nodes, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess && tris && sc->n_tris > 0)
         e = hipMemcpyAsync(tris, sc->tris, sizeof(float4) * 3 * (size_t)sc->n_tris, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = scene_release(sc, s);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_scene_nodes: %s", hipGetErrorString(e));
     return ok();
 }
@@ -364,6 +395,9 @@ static mcdi_status trace_pipeline(const char* who, mcdi_scene sc, ShadeArgs& a, 
     hipError_t e = launch_gen_rays(g, bits, s);
     // tiles with the most rays are traversed first
     if (e == hipSuccess && a.tau != 0.0f) e = launch_order_tiles(a.ray_count, blocks, a.tile_order, s);
+    // the BVH may still be building on another stream: wait for it before
+    // the traversal (and before its timing starts)
+    if (e == hipSuccess && a.tau != 0.0f) e = scene_acquire(sc, s);
     std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
     if ((a.flags & MCDI_FLAG_TIME_TRACE) && e == hipSuccess && a.tau != 0.0f) {
         ev = g_timer.next();
@@ -371,6 +405,7 @@ static mcdi_status trace_pipeline(const char* who, mcdi_scene sc, ShadeArgs& a, 
     }
     if (e == hipSuccess && a.tau != 0.0f) e = launch_trace_rays(a, bits, s);
     if (ev && e == hipSuccess) e = hipEventRecord(ev->second, s);
+    if (e == hipSuccess && a.tau != 0.0f) e = scene_release(sc, s);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "%s: %s", who, hipGetErrorString(e));
     *bits_out = bits;
     return MCDI_OK;
@@ -587,9 +622,17 @@ mcdi_status mcdi_server_launch(mcdi_server sv, const mcdi_serve_item* items, int
     hipError_t e = hipMemcpyAsync(sv->items_dev, h, sizeof(ServeItem) * (size_t)n_items, hipMemcpyHostToDevice,
                                   sv->stream);
     if (e == hipSuccess) e = hipEventRecord(sv->copied[b], sv->stream);
+    // every distinct scene of the launch: its build before, its release after
+    std::vector<mcdi_scene> scenes;
+    for (int i = 0; i < n_items; ++i)
+        if (std::find(scenes.begin(), scenes.end(), items[i].scene) == scenes.end()) scenes.push_back(items[i].scene);
+    for (mcdi_scene scn : scenes)
+        if (e == hipSuccess) e = scene_acquire(scn, sv->stream);
     if (e == hipSuccess)
         e = launch_serve(sv->items_dev, n_items, total, sv->counter, sv->scratch, sv->spp_max, sv->n_wg, max_H,
                          sv->stream);
+    for (mcdi_scene scn : scenes)
+        if (e == hipSuccess) e = scene_release(scn, sv->stream);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_server_launch: %s", hipGetErrorString(e));
     return ok();
 }
@@ -677,8 +720,10 @@ mcdi_status mcdi_trace_anyhit(mcdi_scene sc, const float* orig, const float* dir
     if (n < 0) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: negative n");
     if (n >= (int64_t)1 << 31) return fail(MCDI_E_UNSUPPORTED, "mcdi_trace_anyhit: n >= 2^31");
     if (n > 0 && (!orig || !dir || !hit)) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: NULL buffer");
-    hipError_t e = launch_trace(Scene{sc->nodes, sc->tris, sc->n_tris}, orig, dir, n, hit, brute,
-                                (hipStream_t)stream);
+    hipError_t e = scene_acquire(sc, (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = launch_trace(Scene{sc->nodes, sc->tris, sc->n_tris}, orig, dir, n, hit, brute, (hipStream_t)stream);
+    if (e == hipSuccess) e = scene_release(sc, (hipStream_t)stream);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_trace_anyhit: %s", hipGetErrorString(e));
     return ok();
 }
@@ -814,6 +859,7 @@ mcdi_status mcdi_shade_bwd_edges(mcdi_scene sc, mcdi_env ev, mcdi_edges ed, cons
     E.q_count = (uint32_t*)((char*)ws.base + sz_q);
     E.egeo = (const float4*)((char*)ws.base + sz_q + 256);
     hipError_t pe = launch_edge_pack(E, cap_edges, s);
+    if (pe == hipSuccess) pe = scene_acquire(sc, s);
     if (pe != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd_edges: %s", hipGetErrorString(pe));
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {
         E.pix0 = p0;
@@ -821,6 +867,8 @@ mcdi_status mcdi_shade_bwd_edges(mcdi_scene sc, mcdi_env ev, mcdi_edges ed, cons
         hipError_t e = launch_edge_grad(E, s);
         if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd_edges: %s", hipGetErrorString(e));
     }
+    hipError_t re = scene_release(sc, s);
+    if (re != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd_edges: %s", hipGetErrorString(re));
     return ok();
 }
 
