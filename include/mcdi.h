@@ -136,6 +136,9 @@ mcdi_status mcdi_scene_nodes(mcdi_scene scene, void* nodes, float* tris, void* s
  * ------------------------------------------------------------------------- */
 mcdi_status mcdi_build_env_cdf(const float* env_rgb, int32_t H, int32_t W, const mcdi_allocator* alloc,
                                void* stream, mcdi_env* out);
+/* Frees the tables in stream order on the stream they were built on.  Unlike
+ * a scene, the tables carry no events: work on other streams that uses them
+ * must be ordered after the build and before the destroy by the caller. */
 void mcdi_destroy_env(mcdi_env env);
 
 /* Copies the tables into caller device buffers (any may be NULL), in stream
