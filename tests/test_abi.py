@@ -59,3 +59,16 @@ def test_validation_without_device():
     n = ctypes.c_int32()
     assert lib.mcdi_trace_times(None, 4, ctypes.byref(n)) == L.MCDI_E_INVALID
     assert lib.mcdi_trace_anyhit(None, None, None, 0, None, 0, None) == L.MCDI_E_INVALID
+    # edge list and edge-sampled visibility gradient
+    assert lib.mcdi_build_edges(None, 3, 10, None, None, None) == L.MCDI_E_INVALID
+    assert lib.mcdi_build_edges(None, 3, 10, None, None, ctypes.byref(out)) == L.MCDI_E_INVALID
+    assert b"mcdi_build_edges" in lib.mcdi_last_error()
+    assert lib.mcdi_build_edges(None, -1, 10, None, None, ctypes.byref(out)) == L.MCDI_E_INVALID
+    assert lib.mcdi_build_edges(None, 1 << 26, 10, None, None, ctypes.byref(out)) == L.MCDI_E_UNSUPPORTED
+    assert lib.mcdi_build_edges(None, 0, 1 << 31, None, None, ctypes.byref(out)) == L.MCDI_E_UNSUPPORTED
+    cnt = ctypes.c_int64()
+    assert lib.mcdi_edges_count(None, ctypes.byref(cnt)) == L.MCDI_E_INVALID
+    assert lib.mcdi_edges_copy(None, None, None) == L.MCDI_E_INVALID
+    assert lib.mcdi_shade_bwd_edges(None, None, None, None, 0, ctypes.byref(g), ctypes.byref(p), 4, None, None,
+                                    None, None, None) == L.MCDI_E_INVALID
+    assert b"mcdi_shade_bwd_edges" in lib.mcdi_last_error()
