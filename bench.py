@@ -319,6 +319,18 @@ def visibility_gradient(args, M, gb, timed):
     stats = M.read_stats(st)
     ms = timed(lambda: M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=w.seed, tau=w.tau,
                                          ray_eps=w.ray_eps, g_verts=gv), reps)
+    # spread of the estimate over independent seeds: per vertex component
+    # with a clear mean, the standard deviation of one call over |mean|
+    runs = []
+    for k in range(4):
+        gk = torch.zeros_like(verts)
+        M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=1000 + k, tau=w.tau,
+                          ray_eps=w.ray_eps, g_verts=gk)
+        runs.append(gk.double())
+    r = torch.stack(runs)
+    mean, std = r.mean(0), r.std(0)
+    clear = mean.abs() > std                  # two standard errors of the 4-call mean (std / 2) from 0
+    rel_std = float((std[clear] / mean[clear].abs()).median()) if bool(clear.any()) else None
     samples = nval * EDGE_SPP
     queued = stats["rays_traced"]
     ops = EDGE_OPS_PER_SAMPLE * samples + EDGE_OPS_PER_QUEUED * queued
@@ -326,6 +338,7 @@ def visibility_gradient(args, M, gb, timed):
     return {"edge_spp": EDGE_SPP, "edges": n_edges, "edge_build_ms": build_ms, "ms": ms,
             "edge_samples_per_s": samples / (ms * 1e-3), "samples": samples,
             "silhouette_rays": queued, "silhouette_rays_blocked": stats["rays_hit"],
+            "rel_std_per_call": rel_std, "components_with_clear_mean": int(clear.sum()),
             "roofline": {"bound": "alu", "achieved": a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
                          "frac": a / VALU_PEAK, "traffic": None, "ops_per_launch": ops,
                          "note": "whole call: queue reset, sample kernel and out-side-ray kernel per pass"}}
