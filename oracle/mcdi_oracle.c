@@ -1444,19 +1444,62 @@ void orc_integrand(const orc_scene* scene, const orc_env* E, const orc_gbuffer* 
 /*                                                                           */
 /* Only unique edges count, and only silhouettes: an edge whose two faces   */
 /* lie on opposite sides of the arc is covered on both sides.  One sample   */
-/* draws an edge uniformly (density 1/E) and t uniformly, so the estimate   */
-/* of d(loss)/d(vertex) adds                                                */
-/*   E s tau g(w) |(b - a) x w| / r^2 / n_es  x  ((1 - t) mh at a, t mh at b)*/
+/* draws an edge e with probability p_e (the two-class distribution below) */
+/* and t uniformly, so the estimate of d(loss)/d(vertex) adds              */
+/*   s tau g(w) |(b - a) x w| / (r^2 p_e n_es) x ((1-t) mh at a, t mh at b) */
 /* when the out-side ray misses, where g(w) = sum_c Ud_c g_d,c(w) +         */
 /* Us_c g_s,c(w) contracts the integrand of c_d and c_s with the upstream   */
 /* gradients.  The out-side ray leaves o along w turned by ORC_EDGE_DELTA   */
 /* radians away from the face, normalised.                                  */
 /*                                                                           */
 /* Random numbers: Philox block 2 of counter (pixel in view, view id, j),   */
-/* j the edge sample; the edge is (x0 * E) >> 32 (integer, exact), t the    */
-/* 24-bit uniform of x1.                                                    */
+/* j the edge sample, gives x0..x3: x2 picks the class, (x0 * n_class) >>   */
+/* 32 the edge within it (integers, exact), the 24-bit uniform of x1 is t.  */
 /* ------------------------------------------------------------------------ */
 #define ORC_EDGE_DELTA (1.0 / 8192.0)
+
+/* Edge classes of the sampling distribution.  An edge is sharp when it has
+ * one face, or when the normals of its faces, (b-a)x(c-a) and (a-b)x(d-b),
+ * are more than 20 degrees apart: dot < 0, or dot^2 < cos^2(20 deg) |n1|^2
+ * |n2|^2.  The test is evaluated in FP32, operation by operation in this
+ * order, so that the kernel takes the same decision (it is an integer the
+ * sampling depends on).  Sharp edges are 64 times as likely per edge as the
+ * others: a sample picks the sharp class when (x2 >> 8) (64 nS + nR) <
+ * 64 nS 2^24 (exact integers), then an edge uniformly in its class, and
+ * weighs it by the class size over the class probability.  The expectation is
+ * unchanged; silhouettes of coarse objects are drawn far more often than
+ * under a uniform choice. */
+#define ORC_SHARP_COS2 0.883022221559489f /* cos^2(20 degrees) */
+#define ORC_SHARP_GAIN 64u
+
+static int edge_is_sharp(const float* verts, const int32_t* ed)
+{
+    if (ed[3] < 0) return 1;
+    const float* A = verts + 3 * (size_t)ed[0];
+    const float* B = verts + 3 * (size_t)ed[1];
+    const float* Cc = verts + 3 * (size_t)ed[2];
+    const float* D = verts + 3 * (size_t)ed[3];
+    float e1[3], e2[3], f1[3], f2[3];
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = B[k] - A[k];
+        e2[k] = Cc[k] - A[k];
+        f1[k] = A[k] - B[k];
+        f2[k] = D[k] - B[k];
+    }
+    float n1[3], n2[3];
+    n1[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    n1[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    n1[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    n2[0] = f1[1] * f2[2] - f1[2] * f2[1];
+    n2[1] = f1[2] * f2[0] - f1[0] * f2[2];
+    n2[2] = f1[0] * f2[1] - f1[1] * f2[0];
+    float dt = n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2];
+    float q1 = n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2];
+    float q2 = n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2];
+    float lhs = dt * dt;
+    float rhs = ORC_SHARP_COS2 * (q1 * q2);
+    return dt < 0.0f || lhs < rhs;
+}
 
 /* largest radiance per channel over the 3x3 texels around (i, j): bounds the
  * lookup when the nearest texel is undecided */
@@ -1480,12 +1523,28 @@ static void texel_max3(const float* env, int H, int W, int i, int j, double L[3]
 int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g, const int64_t* pix,
                   int64_t npix, const orc_params* P, int32_t n_es, const int32_t* edges, int64_t n_edges,
                   const float* verts, int64_t n_verts, const double* Ud, const double* Us, double* gv,
-                  double* gv_abs, double* gv_cond, double* gv_flag, int64_t* counts, int nthreads)
+                  double* gv_abs, double* gv_cond, double* gv_flag, int64_t* counts, int nthreads,
+                  uint32_t sharp_gain)
 {
     if (n_es < 0 || n_edges < 0 || n_edges > 0xFFFFFFFFll) return -1;
     for (int k = 0; k < 5; ++k) counts[k] = 0;
     if (n_es == 0 || n_edges == 0 || P->tau == 0.0) return 0;
     const double u = 0x1p-24;
+    /* the two classes, each in edge order */
+    int64_t* cls = (int64_t*)malloc(sizeof(int64_t) * (size_t)n_edges);
+    int64_t nS = 0;
+    for (int64_t e = 0; e < n_edges; ++e)
+        if (edge_is_sharp(verts, edges + 4 * e)) cls[nS++] = e;
+    const int64_t nR = n_edges - nS;
+    for (int64_t e = 0, k = nS; e < n_edges; ++e)
+        if (!edge_is_sharp(verts, edges + 4 * e)) cls[k++] = e;
+    /* sharp_gain: the per-edge weight of the sharp class (the estimator's is
+     * ORC_SHARP_GAIN; 1 gives a uniform choice, for the tests) */
+    const uint64_t gain = sharp_gain ? sharp_gain : ORC_SHARP_GAIN;
+    const uint64_t Nn = gain * (uint64_t)nS, Dd = Nn + (uint64_t)nR;
+    const uint64_t cS = (Nn << 24) / Dd + (((Nn << 24) % Dd) != 0); /* u24 values that pick the sharp class */
+    const double wS = cS > 0 ? (double)nS * 16777216.0 / (double)cS : 0.0;
+    const double wR = cS < 16777216u ? (double)nR * 16777216.0 / (double)(16777216u - cS) : 0.0;
     int nt = 1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -1523,7 +1582,10 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
                 uint32_t ctr[4] = {piv, (uint32_t)g->view_base + view, (uint32_t)j, 2u}, r[4];
                 orc_philox4x32_10(ctr, key, r);
                 c5[0]++;
-                const int64_t e = (int64_t)(((uint64_t)r[0] * (uint64_t)n_edges) >> 32);
+                const int sharp = (uint64_t)(r[2] >> 8) * Dd < (Nn << 24);
+                const int64_t ncls = sharp ? nS : nR;
+                const int64_t e = cls[(sharp ? 0 : nS) + (int64_t)(((uint64_t)r[0] * (uint64_t)ncls) >> 32)];
+                const double wcls = sharp ? wS : wR;
                 const double t = u01(r[1]);
                 const int32_t* ed = edges + 4 * e;
                 /* the face sides come from the determinant det(a - o, b - o,
@@ -1655,7 +1717,7 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
                  * the direction's error (and the triangle test's rounding)
                  * times the distance along the ray */
                 const double vis_abs = 8.0 * u * olen, vis_rel = 2.0 * wband + 32.0 * u;
-                const double base = (double)n_edges * P->tau * J / (double)n_es;
+                const double base = wcls * P->tau * J / (double)n_es;
                 const double wt = s * base * gsum;
                 const double wcond = base * (gcond + gabs * rel_geo);
                 const double wflag = base * fmax(gbound, gabs) * (1.0 + rel_geo);
@@ -1722,5 +1784,12 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
     }
     free(acc);
     free(cnt);
+    free(cls);
     return 0;
+}
+
+/* class of each edge (1 = sharp), for the pin tests */
+void orc_edge_sharp(const float* verts, const int32_t* edges, int64_t n_edges, int32_t* out)
+{
+    for (int64_t e = 0; e < n_edges; ++e) out[e] = edge_is_sharp(verts, edges + 4 * e);
 }

@@ -283,3 +283,53 @@ def test_non_finite_vertex_adds_nothing():
     mean, se = _mean_grad(w, ud, us, seeds=4)
     assert np.isfinite(mean).all()
     assert (mean[3:] == 0.0).all() or np.abs(mean[3:]).max() < 1e-12
+
+
+def test_edge_classes():
+    """Sharp: a box's edges (not its face diagonals), an icosahedron's
+    (normals 41.8 degrees apart), the boundary of a flat grid.  Not sharp: a
+    fine icosphere's, the inside of a flat grid."""
+    v, f = meshes.box([0.0, 0.0, 0.0], [0.3, 0.2, 0.1], 0.4)
+    E = oracle.mesh_edges(f, len(v))
+    sharp = oracle.edge_sharp(v, E)
+    assert sharp.sum() == 12 and len(E) == 18
+    # corner index = 4 ix + 2 iy + iz: a box edge flips one bit, a face
+    # diagonal two
+    flips = np.array([bin(int(a) ^ int(b)).count("1") for a, b in E[:, :2]])
+    assert ((flips == 1) == sharp).all()
+    v, f = meshes.icosphere(0)
+    assert oracle.edge_sharp(v, oracle.mesh_edges(f, len(v))).all()
+    v, f = meshes.icosphere(3)
+    assert not oracle.edge_sharp(v, oracle.mesh_edges(f, len(v))).any()
+    n = 4
+    idx = np.arange(n * n).reshape(n, n)
+    g = np.stack(np.meshgrid(np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 2)
+    v = np.stack([g[:, 0], np.zeros(n * n), g[:, 1]], 1).astype(np.float32)
+    f = np.array([[idx[i, j], idx[i + 1, j], idx[i + 1, j + 1]] for i in range(n - 1) for j in range(n - 1)] +
+                 [[idx[i, j], idx[i + 1, j + 1], idx[i, j + 1]] for i in range(n - 1) for j in range(n - 1)])
+    E = oracle.mesh_edges(f, n * n)
+    assert (oracle.edge_sharp(v, E) == (E[:, 3] < 0)).all()
+
+
+def test_class_weights_keep_the_expectation():
+    """A box (sharp and smooth edges) and a smooth icosphere shell above the
+    receiver: the two-class choice (gain 64) and a uniform choice (gain 1)
+    have the same expectation, and the two-class one draws the box's
+    silhouettes far more often."""
+    bv, bf = meshes.box([0.0, 1.0, 0.0], [0.2, 0.05, 0.2], 0.3)
+    sv, sf = meshes.icosphere(3)
+    sv = sv * 0.25 + np.array([0.35, 1.6, 0.2])
+    V, F = meshes.merge([(bv, bf), (sv, sf)])
+    w = _receiver(V, F)
+    ud, us = _ud_us(w)
+    E = oracle.mesh_edges(w.tris, len(w.verts))
+    sharp = oracle.edge_sharp(w.verts, E)
+    assert 0 < sharp.sum() < len(E)
+    m64, s64 = _mean_grad(w, ud, us, n_es=64, seeds=8)
+    m1, s1 = _mean_grad(w, ud, us, n_es=64, seeds=8, sharp_gain=1)
+    scale = np.abs(m64).max()
+    assert scale > 0
+    assert (np.abs(m64 - m1) <= 5 * np.sqrt(s64 ** 2 + s1 ** 2) + 2e-3 * scale).all()
+    # the box's vertices: the two-class estimate is much less noisy
+    nb = len(bv)
+    assert np.median(s64[:nb][np.abs(m64[:nb]) > 0]) < 0.5 * np.median(s1[:nb][np.abs(m64[:nb]) > 0])
