@@ -286,20 +286,22 @@ STATE = {}
 
 # Edge-sampled visibility gradient, VALU lane-operations per edge sample
 # (every sample): Philox4x32-10 (ten rounds of two 32x32->64 products = 4
-# lane ops, and 4 xors: 80), edge choice and t (4), the differences from o
-# and along the edge (6), the arc normal (6), the two face-side determinants
-# (24), sign logic and |m|^2 (7) = 127.  Per sample that reaches the queue
+# lane ops, and 4 xors: 80), class choice (a 64-bit product and a compare: 4),
+# edge choice and t (4), the differences from o and along the edge (6), the
+# arc normal (6), the two face-side determinants (24), sign logic and |m|^2
+# (7) = 131.  Per sample that reaches the queue
 # (silhouette, above the horizon): direction and distance (14), arc normal and
 # Jacobian (18), probe lookup (two atan2 and the texel, 50), the BSDF terms
 # (50), out-side direction and record (18) = 150.
-EDGE_OPS_PER_SAMPLE = 127
+EDGE_OPS_PER_SAMPLE = 131
 EDGE_OPS_PER_QUEUED = 150
 EDGE_SPP = 8
 
 
 def visibility_gradient(args, M, gb, timed):
     """Edge-sampled shadow-visibility gradient on the step's workload: edge
-    list build, and one gradient pass of EDGE_SPP edge samples per pixel."""
+    list build, and one gradient pass of EDGE_SPP edge samples per pixel, with
+    a uniform edge choice and with sharp edges 64 times as likely."""
     import torch
     sc, envh, w = STATE["scene"], STATE["env"], STATE["w"]
     verts, tris = STATE["verts"], STATE["tris"]
@@ -312,36 +314,50 @@ def visibility_gradient(args, M, gb, timed):
     build_ms = timed(lambda: M.Edges(tris, nv), reps)
     g_cd = torch.randn((3, gb.n), device=gb.kd.device) * m / nval
     g_cs = torch.randn((3, gb.n), device=gb.kd.device) * m / nval
-    gv = torch.zeros_like(verts)
-    st = M.new_stats(verts.device)
-    M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps,
-                      g_verts=gv, stats=st)
-    stats = M.read_stats(st)
-    ms = timed(lambda: M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=w.seed, tau=w.tau,
-                                         ray_eps=w.ray_eps, g_verts=gv), reps)
-    # spread of the estimate over independent seeds: per vertex component
-    # with a clear mean, the standard deviation of one call over |mean|
-    runs = []
-    for k in range(4):
-        gk = torch.zeros_like(verts)
-        M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=1000 + k, tau=w.tau,
-                          ray_eps=w.ray_eps, g_verts=gk)
-        runs.append(gk.double())
-    r = torch.stack(runs)
-    mean, std = r.mean(0), r.std(0)
-    clear = mean.abs() > std                  # two standard errors of the 4-call mean (std / 2) from 0
-    rel_std = float((std[clear] / mean[clear].abs()).median()) if bool(clear.any()) else None
     samples = nval * EDGE_SPP
+
+    def measure(gain):
+        gv = torch.zeros_like(verts)
+        st = M.new_stats(verts.device)
+        M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=w.seed, tau=w.tau,
+                          ray_eps=w.ray_eps, g_verts=gv, stats=st, sharp_gain=gain)
+        stats = M.read_stats(st)
+        ms = timed(lambda: M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=w.seed,
+                                             tau=w.tau, ray_eps=w.ray_eps, g_verts=gv, sharp_gain=gain), reps)
+        # spread of the estimate over independent seeds: per vertex component
+        # with a clear mean, the standard deviation of one call over |mean|
+        runs = []
+        for k in range(4):
+            gk = torch.zeros_like(verts)
+            M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=1000 + k, tau=w.tau,
+                              ray_eps=w.ray_eps, g_verts=gk, sharp_gain=gain)
+            runs.append(gk.double())
+        r = torch.stack(runs)
+        return ms, stats, r
+
+    ms, stats, r1 = measure(1)
+    ms64, stats64, r64 = measure(64)
+    # noise of one call against the signal, over the whole vertex gradient:
+    # the spread of the calls about the mean of all 8 (both choices have the
+    # same expectation) over the norm of that mean
+    mean = torch.cat([r1, r64]).mean(0)
+
+    def noise(r):
+        return float(((r - mean) ** 2).sum(dim=(1, 2)).mean().sqrt() / mean.norm())
+
     queued = stats["rays_traced"]
     ops = EDGE_OPS_PER_SAMPLE * samples + EDGE_OPS_PER_QUEUED * queued
     a = ops / (ms * 1e-3)
     return {"edge_spp": EDGE_SPP, "edges": n_edges, "edge_build_ms": build_ms, "ms": ms,
             "edge_samples_per_s": samples / (ms * 1e-3), "samples": samples,
             "silhouette_rays": queued, "silhouette_rays_blocked": stats["rays_hit"],
-            "rel_std_per_call": rel_std, "components_with_clear_mean": int(clear.sum()),
+            "noise_per_call": noise(r1),
+            "sharp_gain_64": {"ms": ms64, "silhouette_rays": stats64["rays_traced"],
+                              "silhouette_rays_blocked": stats64["rays_hit"], "noise_per_call": noise(r64)},
             "roofline": {"bound": "alu", "achieved": a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
                          "frac": a / VALU_PEAK, "traffic": None, "ops_per_launch": ops,
-                         "note": "whole call: queue reset, sample kernel and out-side-ray kernel per pass"}}
+                         "note": "whole call, uniform edge choice: classes and corners packed, sample kernel, "
+                                 "out-side-ray kernel"}}
 
 
 def next_rows(args, M, gb, c_d, c_s, target, timed):

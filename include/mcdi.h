@@ -282,28 +282,39 @@ mcdi_status mcdi_edges_copy(mcdi_edges edges, int32_t* rows, void* stream);
  *                 pass (the other technique flags do not apply; spp is
  *                 validated but unused)
  *   edge_spp      edge samples per pixel, 1..1024
+ *   sharp_gain    1..1024: sharp edges are this many times as likely per edge
+ *                 as the others (1: a uniform choice over the edges).  The
+ *                 expectation does not depend on it; the variance and the
+ *                 number of traced rays do
  *   g_cd, g_cs    device [3][N] upstream gradients
  *   g_verts       device float32 [n_verts][3], ACCUMULATED (+=); the caller
  *                 zeroes it
  *   stats         valid_pixels, invalid_pixels, rays_traced (out-side rays)
  *                 and rays_hit are accumulated, or NULL
+ * Edge classes: an edge is sharp when it has one face (d = -1) or when its
+ * face normals (b-a)x(c-a) and (a-b)x(d-b) are more than 20 degrees apart
+ * (dot < 0 or dot^2 < cos^2(20 deg) |n1|^2 |n2|^2, evaluated in FP32 in this
+ * order without contraction); nS sharp edges, nR = E - nS others.
  * Per pixel and edge sample j: Philox4x32-10 with key = seed and counter =
- * (pixel in view, view_base + view, j, 2) gives x0..x3; the edge is row
- * (x0 * E) >> 32 and the point on it x(t) = a + t (b - a) with t = the 24-bit
- * uniform of x1.  From the shadow-ray origin o = p + ray_eps n, with
- * r = |x - o|, w = (x - o)/r and m = (a - o) x (b - o): a sample counts when
- * the edge is a silhouette (d = -1, or c and d not strictly on opposite sides
- * of the plane through o with normal m), n.w > 0, and the out-side ray from
- * o along w turned by 2^-13 radians away from the face misses the mesh.  It
- * adds E s tau g(w) |(b - a) x w| / (r^2 edge_spp) times (1 - t) m/|m| to
- * vertex a and t m/|m| to vertex b, where s = the sign of m . (c - o) and g
- * is the unshadowed integrand of c_d and c_s at w contracted with g_cd and
- * g_cs.  G-buffer positions are held fixed (the receivers do not move).
+ * (pixel in view, view_base + view, j, 2) gives x0..x3.  With K = sharp_gain,
+ * the sample is in the sharp class when (x2 >> 8) (K nS + nR) < K nS 2^24
+ * (probability P_S = ceil(2^24 K nS / (K nS + nR)) / 2^24), and its edge is the
+ * ((x0 n_class) >> 32)-th of the class, in row order; the point on it is
+ * x(t) = a + t (b - a) with t = the 24-bit uniform of x1.  From the
+ * shadow-ray origin o = p + ray_eps n, with r = |x - o|, w = (x - o)/r and
+ * m = (a - o) x (b - o): a sample counts when the edge is a silhouette (d =
+ * -1, or c and d not strictly on opposite sides of the plane through o with
+ * normal m), n.w > 0, and the out-side ray from o along w turned by 2^-13
+ * radians away from the face misses the mesh.  It adds (n_class / P_class) s
+ * tau g(w) |(b - a) x w| / (r^2 edge_spp) times (1 - t) m/|m| to vertex a and
+ * t m/|m| to vertex b, where s = the sign of m . (c - o) and g is the
+ * unshadowed integrand of c_d and c_s at w contracted with g_cd and g_cs.
+ * G-buffer positions are held fixed (the receivers do not move).
  * Summation order of g_verts is not deterministic (float atomics). */
 mcdi_status mcdi_shade_bwd_edges(mcdi_scene scene, mcdi_env env, mcdi_edges edges, const float* verts,
                                  int64_t n_verts, const mcdi_gbuffer* gbuf, const mcdi_params* params,
-                                 int32_t edge_spp, const float* g_cd, const float* g_cs, float* g_verts,
-                                 mcdi_stats* stats, void* stream);
+                                 int32_t edge_spp, uint32_t sharp_gain, const float* g_cd, const float* g_cs,
+                                 float* g_verts, mcdi_stats* stats, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Image loss on the estimator's outputs (appendix A): composition

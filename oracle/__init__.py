@@ -382,12 +382,12 @@ def edge_sharp(verts, edges):
 
 
 def edge_grad(w, edges, n_es, u_d, u_s, pixels=None, scene=None, tables=None, seed=None, tau=None,
-              ray_eps=None, flags=0, tol=None, brute=False, threads=0, sharp_gain=64):
+              ray_eps=None, flags=0, tol=None, brute=False, threads=0, sharp_gain=1):
     """Edge-sampled derivative of sum_pixels (u_d . c_d + u_s . c_s) with
     respect to the mesh vertices through the shadow-ray visibility, from
     n_es edge samples per pixel (sharp edges sharp_gain times as likely per
-    edge as the others; the estimator's gain is 64, 1 is a uniform choice,
-    the same expectation).  Returns a dict: g_verts [Nv, 3] and, per
+    edge as the others; 1 is a uniform choice; every gain has the same
+    expectation).  Returns a dict: g_verts [Nv, 3] and, per
     element, abs (sum of |term|), cond (FP32 error bound of the terms),
     flag (bound on the terms of samples with an undecided step), plus the
     sample counts."""

@@ -1463,14 +1463,13 @@ void orc_integrand(const orc_scene* scene, const orc_env* E, const orc_gbuffer* 
  * are more than 20 degrees apart: dot < 0, or dot^2 < cos^2(20 deg) |n1|^2
  * |n2|^2.  The test is evaluated in FP32, operation by operation in this
  * order, so that the kernel takes the same decision (it is an integer the
- * sampling depends on).  Sharp edges are 64 times as likely per edge as the
- * others: a sample picks the sharp class when (x2 >> 8) (64 nS + nR) <
- * 64 nS 2^24 (exact integers), then an edge uniformly in its class, and
- * weighs it by the class size over the class probability.  The expectation is
- * unchanged; silhouettes of coarse objects are drawn far more often than
- * under a uniform choice. */
+ * sampling depends on).  Sharp edges are K = sharp_gain times as likely per
+ * edge as the others: a sample picks the sharp class when (x2 >> 8) (K nS +
+ * nR) < K nS 2^24 (exact integers), then an edge uniformly in its class, and
+ * weighs it by the class size over the class probability.  The expectation
+ * does not depend on K; with K > 1 silhouettes of coarse objects are drawn
+ * far more often than under the uniform choice (K = 1). */
 #define ORC_SHARP_COS2 0.883022221559489f /* cos^2(20 degrees) */
-#define ORC_SHARP_GAIN 64u
 
 static int edge_is_sharp(const float* verts, const int32_t* ed)
 {
@@ -1538,9 +1537,8 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
     const int64_t nR = n_edges - nS;
     for (int64_t e = 0, k = nS; e < n_edges; ++e)
         if (!edge_is_sharp(verts, edges + 4 * e)) cls[k++] = e;
-    /* sharp_gain: the per-edge weight of the sharp class (the estimator's is
-     * ORC_SHARP_GAIN; 1 gives a uniform choice, for the tests) */
-    const uint64_t gain = sharp_gain ? sharp_gain : ORC_SHARP_GAIN;
+    /* sharp_gain: the per-edge weight of the sharp class (1: a uniform choice) */
+    const uint64_t gain = sharp_gain ? sharp_gain : 1u;
     const uint64_t Nn = gain * (uint64_t)nS, Dd = Nn + (uint64_t)nR;
     const uint64_t cS = (Nn << 24) / Dd + (((Nn << 24) % Dd) != 0); /* u24 values that pick the sharp class */
     const double wS = cS > 0 ? (double)nS * 16777216.0 / (double)cS : 0.0;

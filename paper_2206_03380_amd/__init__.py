@@ -284,10 +284,11 @@ class Edges:
 
 
 def shade_bwd_edges(scene, env, edges, verts, gb, edge_spp, g_cd, g_cs, seed=0, tau=1.0, ray_eps=1e-3, flags=0,
-                    g_verts=None, stats=None, stream=None):
+                    g_verts=None, stats=None, stream=None, sharp_gain=1):
     """Edge-sampled visibility gradient of the shadow term with respect to the
-    vertex positions verts [Nv,3] (the mesh of scene and edges).  Returns
-    g_verts [Nv,3], accumulated into if given, else a zeroed tensor."""
+    vertex positions verts [Nv,3] (the mesh of scene and edges); sharp edges
+    are sharp_gain times as likely per edge as the others (1: uniform).
+    Returns g_verts [Nv,3], accumulated into if given, else a zeroed tensor."""
     n = gb.n
     _need(verts, torch.float32, name="verts")
     _need(g_cd, torch.float32, (3, n), "g_cd")
@@ -298,7 +299,8 @@ def shade_bwd_edges(scene, env, edges, verts, gb, edge_spp, g_cd, g_cs, seed=0, 
     gs = gb.struct()
     prm = _params(1, seed, tau, ray_eps, flags, None)
     L.check(L.lib().mcdi_shade_bwd_edges(scene.handle, env.handle, edges.handle, _ptr(verts), verts.shape[0],
-                                         C.byref(gs), C.byref(prm), int(edge_spp), _ptr(g_cd), _ptr(g_cs),
+                                         C.byref(gs), C.byref(prm), int(edge_spp), int(sharp_gain), _ptr(g_cd),
+                                         _ptr(g_cs),
                                          _ptr(g_verts), _ptr(stats), _stream(stream)))
     return g_verts
 

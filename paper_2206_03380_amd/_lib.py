@@ -129,7 +129,7 @@ def lib():
     L.mcdi_edges_copy.argtypes = [vp, vp, vp]
     L.mcdi_shade_bwd_edges.restype = C.c_int
     L.mcdi_shade_bwd_edges.argtypes = [vp, vp, vp, vp, C.c_int64, C.POINTER(GBuffer), C.POINTER(Params), C.c_int32,
-                                       vp, vp, vp, vp, vp]
+                                       C.c_uint32, vp, vp, vp, vp, vp]
     L.mcdi_last_error.restype = C.c_char_p
     L.mcdi_version.restype = C.c_char_p
     _lib = L

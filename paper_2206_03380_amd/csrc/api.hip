@@ -813,8 +813,9 @@ mcdi_status mcdi_edges_copy(mcdi_edges ed, int32_t* rows, void* stream) {
 }
 
 mcdi_status mcdi_shade_bwd_edges(mcdi_scene sc, mcdi_env ev, mcdi_edges ed, const float* verts, int64_t n_verts,
-                                 const mcdi_gbuffer* g, const mcdi_params* p, int32_t edge_spp, const float* g_cd,
-                                 const float* g_cs, float* g_verts, mcdi_stats* stats, void* stream) {
+                                 const mcdi_gbuffer* g, const mcdi_params* p, int32_t edge_spp, uint32_t sharp_gain,
+                                 const float* g_cd, const float* g_cs, float* g_verts, mcdi_stats* stats,
+                                 void* stream) {
     ShadeArgs a;
     mcdi_status st = fill_common("mcdi_shade_bwd_edges", sc, ev, g, p, a);
     if (st != MCDI_OK) return st;
@@ -825,6 +826,8 @@ mcdi_status mcdi_shade_bwd_edges(mcdi_scene sc, mcdi_env ev, mcdi_edges ed, cons
                     (long long)n_verts, (long long)ed->n_verts);
     if (edge_spp < 1 || edge_spp > 1024)
         return fail(MCDI_E_INVALID, "mcdi_shade_bwd_edges: edge_spp must be in [1, 1024]");
+    if (sharp_gain < 1 || sharp_gain > kSharpGainMax)
+        return fail(MCDI_E_INVALID, "mcdi_shade_bwd_edges: sharp_gain must be in [1, %u]", kSharpGainMax);
     if (!g_cd || !g_cs || (n_verts > 0 && (!verts || !g_verts)))
         return fail(MCDI_E_INVALID, "mcdi_shade_bwd_edges: NULL buffer");
     if (a.tau == 0.0f || ed->n_tris == 0) return ok();
@@ -840,6 +843,7 @@ mcdi_status mcdi_shade_bwd_edges(mcdi_scene sc, mcdi_env ev, mcdi_edges ed, cons
     E.verts = verts;
     E.g_verts = g_verts;
     E.n_es = edge_spp;
+    E.gain = sharp_gain;
     // pixels per pass: every sample of a pass fits the queue, and the pixel
     // in pass fits its 22 bits of the record
     int64_t per = ((int64_t)(kEdgeQueueMax / (uint32_t)edge_spp) / kBlock) * kBlock;
@@ -853,12 +857,16 @@ mcdi_status mcdi_shade_bwd_edges(mcdi_scene sc, mcdi_env ev, mcdi_edges ed, cons
     const size_t sz_q = ((sizeof(uint32_t) * (size_t)E.q_cap) + 255) & ~(size_t)255;
     const uint32_t cap_edges = (uint32_t)(3 * ed->n_tris);   // at most one edge per triangle side
     const size_t sz_geo = sizeof(float4) * 4 * (size_t)cap_edges;
-    ws.base = sc->alloc.get(sz_q + 256 + sz_geo, s);
+    const size_t sz_bsum = ((sizeof(uint32_t) * ((size_t)edge_pack_blocks(cap_edges) + 1)) + 255) & ~(size_t)255;
+    ws.base = sc->alloc.get(sz_q + 256 + sz_geo + sz_bsum, s);
     if (!ws.base) return fail(MCDI_E_OOM, "mcdi_shade_bwd_edges: workspace allocation failed");
     E.queue = (uint32_t*)ws.base;
     E.q_count = (uint32_t*)((char*)ws.base + sz_q);
+    uint32_t* n_sharp = E.q_count + 1;
+    E.n_sharp = n_sharp;
     E.egeo = (const float4*)((char*)ws.base + sz_q + 256);
-    hipError_t pe = launch_edge_pack(E, cap_edges, s);
+    uint32_t* bsum = (uint32_t*)((char*)ws.base + sz_q + 256 + sz_geo);
+    hipError_t pe = launch_edge_pack(E, cap_edges, bsum, n_sharp, s);
     if (pe == hipSuccess) pe = scene_acquire(sc, s);
     if (pe != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd_edges: %s", hipGetErrorString(pe));
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {

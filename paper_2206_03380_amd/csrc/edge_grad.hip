@@ -62,6 +62,7 @@ __device__ __forceinline__ float3 probe_radiance(const EnvView& e, float3 w, boo
 // silhouette, a degenerate arc, or the point at or below the horizon.
 struct EdgeGeom {
     uint32_t e;          // edge row
+    bool sharp;          // its sampling class
     float t, s;          // point on the edge; +1 when the face lies on the +mh side
     float3 w, mh;        // unit direction to the point; unit arc normal
     float r2;            // squared distance to the point
@@ -71,27 +72,36 @@ struct EdgeGeom {
 // the sample's random numbers and its edge's corners, fetched in one go
 struct EdgeFetch {
     uint32_t e;
+    bool sharp;
     float t;
     float4 pa, pb, pc, pd;
 };
 
-__device__ __forceinline__ EdgeFetch edge_fetch(const EdgeArgs& E, uint32_t piv, uint32_t vid, int j, uint32_t ne) {
+// the sample's class (sharp edges are E.gain times as likely per edge: an
+// exact integer test on the 24-bit uniform of x2), its edge (uniform in
+// the class) and that edge's corners, packed in one 64-byte line (sharp
+// edges first) for this call
+__device__ __forceinline__ EdgeFetch edge_fetch(const EdgeArgs& E, uint32_t piv, uint32_t vid, int j, uint32_t ne,
+                                                uint32_t ns) {
     const uint32_t k0 = (uint32_t)E.a.seed, k1 = (uint32_t)(E.a.seed >> 32);
     const uint4 r = philox10(make_uint4(piv, vid, (uint32_t)j, 2u), k0, k1);
+    const uint64_t num = (uint64_t)E.gain * ns, den = num + (uint64_t)(ne - ns);
     EdgeFetch F;
-    F.e = __umulhi(r.x, ne);
+    F.sharp = (uint64_t)(r.z >> 8) * den < (num << 24);
+    const uint32_t line = (F.sharp ? 0u : ns) + __umulhi(r.x, F.sharp ? ns : ne - ns);
     F.t = u01(r.y);
-    // the edge's corners, packed in one 64-byte line for this call
-    const float4* q = E.egeo + 4 * (size_t)F.e;
+    const float4* q = E.egeo + 4 * (size_t)line;
     F.pa = q[0];
     F.pb = q[1];
     F.pc = q[2];
     F.pd = q[3];
+    F.e = __float_as_uint(F.pa.w);
     return F;
 }
 
 __device__ __forceinline__ bool edge_test(const Pixel& P, const EdgeFetch& F, EdgeGeom& G) {
     G.e = F.e;
+    G.sharp = F.sharp;
     G.t = F.t;
     const float3 va = f3(F.pa.x, F.pa.y, F.pa.z);
     const float3 qa = va - P.o;
@@ -114,8 +124,8 @@ __device__ __forceinline__ bool edge_test(const Pixel& P, const EdgeFetch& F, Ed
 }
 
 __device__ __forceinline__ bool edge_geom(const EdgeArgs& E, const Pixel& P, uint32_t piv, uint32_t vid, int j,
-                                          uint32_t ne, EdgeGeom& G) {
-    return edge_test(P, edge_fetch(E, piv, vid, j, ne), G);
+                                          uint32_t ne, uint32_t ns, EdgeGeom& G) {
+    return edge_test(P, edge_fetch(E, piv, vid, j, ne, ns), G);
 }
 
 // The part of setup_pixel the edge filter needs: validity (same rules), the
@@ -156,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
     const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t pix = E.pix0 + local;
     const bool active = local < E.npix && pix < A.g.n;
-    const uint32_t ne = *E.n_edges;
+    const uint32_t ne = *E.n_edges, ns = *E.n_sharp;
     bool nonfinite = false, valid = false;
     Pixel P;
     if (active) valid = pixel_origin(A, pix, P, nonfinite);
@@ -174,15 +184,15 @@ __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
             // two samples per step: both fetches are in flight before either test
             int jj = 0;
             for (; jj + 1 < nj; jj += 2) {
-                const EdgeFetch F0 = edge_fetch(E, piv, vid, j0 + jj, ne);
-                const EdgeFetch F1 = edge_fetch(E, piv, vid, j0 + jj + 1, ne);
+                const EdgeFetch F0 = edge_fetch(E, piv, vid, j0 + jj, ne, ns);
+                const EdgeFetch F1 = edge_fetch(E, piv, vid, j0 + jj + 1, ne, ns);
                 EdgeGeom G;
                 if (edge_test(P, F0, G)) bits |= 1u << jj;
                 if (edge_test(P, F1, G)) bits |= 2u << jj;
             }
             if (jj < nj) {
                 EdgeGeom G;
-                if (edge_geom(E, P, piv, vid, j0 + jj, ne, G)) bits |= 1u << jj;
+                if (edge_geom(E, P, piv, vid, j0 + jj, ne, ns, G)) bits |= 1u << jj;
             }
         }
         if (__ballot(bits != 0u) == 0ull) continue;
@@ -275,8 +285,8 @@ struct EdgeTerm {
     uint32_t e;
 };
 
-__device__ __forceinline__ bool edge_term(const EdgeArgs& E, uint32_t rec, uint32_t ne, float scale, bool bil,
-                                          EdgeTerm& T) {
+__device__ __forceinline__ bool edge_term(const EdgeArgs& E, uint32_t rec, uint32_t ne, uint32_t ns, float2 scale,
+                                          bool bil, EdgeTerm& T) {
     const ShadeArgs& A = E.a;
     const int64_t N = A.g.n;
     const int64_t hw = (int64_t)A.g.height * A.g.width;
@@ -289,7 +299,7 @@ __device__ __forceinline__ bool edge_term(const EdgeArgs& E, uint32_t rec, uint3
     const uint32_t view = (uint32_t)(pix / hw);
     const uint32_t piv = (uint32_t)(pix - (int64_t)view * hw);
     EdgeGeom G;
-    if (!edge_geom(E, P, piv, (uint32_t)A.g.view_base + view, j, ne, G)) return false;
+    if (!edge_geom(E, P, piv, (uint32_t)A.g.view_base + view, j, ne, ns, G)) return false;
     const float3 Ud = f3(A.g_cd[pix], A.g_cd[N + pix], A.g_cd[2 * N + pix]);
     const float3 Us = f3(A.g_cs[pix], A.g_cs[N + pix], A.g_cs[2 * N + pix]);
     const float3 w = G.w;
@@ -314,7 +324,7 @@ __device__ __forceinline__ bool edge_term(const EdgeArgs& E, uint32_t rec, uint3
                             P.F0.z + (1.0f - P.F0.z) * Fw);
         g += Sv * (Us.x * F.x * L.x + Us.y * F.y * L.y + Us.z * F.z * L.z);
     }
-    T.wt = G.s * scale * J * g;
+    T.wt = G.s * (G.sharp ? scale.x : scale.y) * J * g;
     if (!(T.wt != 0.0f && isfinite(T.wt))) return false;
     T.o = P.o;
     T.wo = normalize(w - (G.s * kEdgeDelta) * G.mh);
@@ -346,10 +356,17 @@ __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
     const ShadeArgs& A = E.a;
     const Scene& sc = A.scene;
     const uint32_t n = min(*E.q_count, E.q_cap);
-    const uint32_t ne = *E.n_edges;
+    const uint32_t ne = *E.n_edges, ns = *E.n_sharp;
     const int n_total = sc.nodes[0].escape;
     const bool bil = (A.flags & MCDI_FLAG_BILINEAR) != 0;
-    const float scale = (float)ne * A.tau / (float)E.n_es;
+    // per class: class size over class probability, times tau / n_es; the
+    // sharp class takes ceil(2^24 num / den) of the 2^24 values of the test
+    const uint64_t num = (uint64_t)E.gain * ns, den = num + (uint64_t)(ne - ns);
+    const uint64_t cs = den ? ((num << 24) + den - 1) / den : 0;
+    const float k = A.tau / (float)E.n_es;
+    const float2 scale = make_float2(cs ? (float)ns * 16777216.0f / (float)cs * k : 0.0f,
+                                     cs < 16777216u ? (float)(ne - ns) * 16777216.0f / (float)(16777216u - cs) * k
+                                                    : 0.0f);
     const bool lead = __lane_id() == 0;
     uint32_t c_rays = 0, c_hits = 0;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -357,7 +374,7 @@ __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
     if (n >= kEdgeLaneMode) {
         for (uint32_t i = tid; i < n; i += n_threads) {
             EdgeTerm T;
-            if (!edge_term(E, E.queue[i], ne, scale, bil, T)) continue;
+            if (!edge_term(E, E.queue[i], ne, ns, scale, bil, T)) continue;
             ++c_rays;
             uint32_t nb = 0, nt = 0;
             if (n_total > 0 && bvh_anyhit(sc, make_ray(T.o, T.wo), n_total, nb, nt)) {
@@ -377,7 +394,7 @@ __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
     }
     for (uint32_t i = tid >> 6; i < n; i += n_threads >> 6) {
         EdgeTerm T;
-        if (!edge_term(E, E.queue[i], ne, scale, bil, T)) continue;
+        if (!edge_term(E, E.queue[i], ne, ns, scale, bil, T)) continue;
         ++c_rays;
         if (wave_anyhit(sc, make_ray(T.o, T.wo), n_total)) {
             ++c_hits;
@@ -393,16 +410,107 @@ __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
 
 __global__ void edge_queue_reset(uint32_t* q_count) { *q_count = 0u; }
 
-// corners of every edge for this call's vertex positions: (a, 0), (b, 0),
-// (c, 0), (d, 1) or (0, 0, 0, 0) without a second face
-__global__ void edge_pack_kernel(const int4* __restrict__ edges, const uint32_t* n_edges, const float* verts,
-                                 float4* egeo, uint32_t cap) {
-    const uint32_t n = min(*n_edges, cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+// Sampling class of an edge: sharp when it has one face, or when the normals
+// of its faces, (b-a)x(c-a) and (a-b)x(d-b), are more than 20 degrees apart
+// (dot < 0, or dot^2 < cos^2(20 deg) |n1|^2 |n2|^2).  FP32, no contraction,
+// in this order: the CPU check takes the same decision bit for bit.
+__device__ bool edge_is_sharp(const int4& ed, const float* __restrict__ verts) {
+#pragma clang fp contract(off)
+    if (ed.w < 0) return true;
+    const float3 A = load_vert(verts, ed.x), B = load_vert(verts, ed.y);
+    const float3 Cc = load_vert(verts, ed.z), D = load_vert(verts, ed.w);
+    const float e1x = B.x - A.x, e1y = B.y - A.y, e1z = B.z - A.z;
+    const float e2x = Cc.x - A.x, e2y = Cc.y - A.y, e2z = Cc.z - A.z;
+    const float f1x = A.x - B.x, f1y = A.y - B.y, f1z = A.z - B.z;
+    const float f2x = D.x - B.x, f2y = D.y - B.y, f2z = D.z - B.z;
+    const float n1x = e1y * e2z - e1z * e2y, n1y = e1z * e2x - e1x * e2z, n1z = e1x * e2y - e1y * e2x;
+    const float n2x = f1y * f2z - f1z * f2y, n2y = f1z * f2x - f1x * f2z, n2z = f1x * f2y - f1y * f2x;
+    const float dt = n1x * n2x + n1y * n2y + n1z * n2z;
+    const float q1 = n1x * n1x + n1y * n1y + n1z * n1z;
+    const float q2 = n2x * n2x + n2y * n2y + n2z * n2z;
+    const float lhs = dt * dt;
+    const float rhs = kSharpCos2 * (q1 * q2);
+    return dt < 0.0f || lhs < rhs;
+}
+
+constexpr int kPackItems = 4;
+constexpr int kPackThreads = 256;
+constexpr int kPackBlock = kPackItems * kPackThreads;
+
+// exclusive scan over the workgroup; *total the sum
+__device__ __forceinline__ uint32_t pack_scan(uint32_t v, uint32_t* s_buf, uint32_t* total) {
+    const int t = threadIdx.x;
+    s_buf[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kPackThreads; off <<= 1) {
+        const uint32_t add = t >= off ? s_buf[t - off] : 0u;
+        __syncthreads();
+        s_buf[t] += add;
+        __syncthreads();
+    }
+    const uint32_t incl = s_buf[t];
+    *total = s_buf[kPackThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// sharp edges per block of kPackBlock edges
+__global__ __launch_bounds__(kPackThreads) void edge_class_count(const int4* __restrict__ edges,
+                                                                 const uint32_t* n_edges, const float* verts,
+                                                                 uint32_t* bsum) {
+    __shared__ uint32_t s_buf[kPackThreads];
+    const uint32_t n = *n_edges;
+    const uint32_t i0 = blockIdx.x * (uint32_t)kPackBlock + threadIdx.x * (uint32_t)kPackItems;
+    uint32_t v = 0;
+    for (int k = 0; k < kPackItems; ++k)
+        if (i0 + k < n && edge_is_sharp(edges[i0 + k], verts)) ++v;
+    uint32_t total;
+    pack_scan(v, s_buf, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// exclusive scan of the block counts in place (one workgroup); the sharp count
+__global__ __launch_bounds__(kPackThreads) void edge_class_scan(uint32_t nb, uint32_t* bsum, uint32_t* n_sharp) {
+    __shared__ uint32_t s_buf[kPackThreads];
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kPackThreads) {
+        const uint32_t i = b0 + threadIdx.x;
+        const uint32_t v = i < nb ? bsum[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = pack_scan(v, s_buf, &total);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *n_sharp = carry;
+}
+
+// corners of every edge for this call's vertex positions, sharp edges first
+// and each class in edge order: (a, edge id bits), (b, 0), (c, 0), (d, 1) or
+// (0, 0, 0, 0) without a second face
+__global__ __launch_bounds__(kPackThreads) void edge_pack_kernel(const int4* __restrict__ edges,
+                                                                 const uint32_t* n_edges, const float* verts,
+                                                                 const uint32_t* __restrict__ bsum,
+                                                                 const uint32_t* n_sharp, float4* egeo) {
+    __shared__ uint32_t s_buf[kPackThreads];
+    const uint32_t n = *n_edges, ns = *n_sharp;
+    const uint32_t i0 = blockIdx.x * (uint32_t)kPackBlock + threadIdx.x * (uint32_t)kPackItems;
+    bool sharp[kPackItems];
+    uint32_t v = 0;
+    for (int k = 0; k < kPackItems; ++k) {
+        sharp[k] = i0 + k < n && edge_is_sharp(edges[i0 + k], verts);
+        v += sharp[k] ? 1u : 0u;
+    }
+    uint32_t total;
+    uint32_t before = bsum[blockIdx.x] + pack_scan(v, s_buf, &total);   // sharp edges before i0
+    for (int k = 0; k < kPackItems; ++k) {
+        const uint32_t i = i0 + k;
+        if (i >= n) break;
+        const uint32_t at = sharp[k] ? before : ns + (i - before);
+        if (sharp[k]) ++before;
         const int4 ed = edges[i];
         const float3 a = load_vert(verts, ed.x), b = load_vert(verts, ed.y), c = load_vert(verts, ed.z);
-        float4* q = egeo + 4 * (size_t)i;
-        q[0] = make_float4(a.x, a.y, a.z, 0.0f);
+        float4* q = egeo + 4 * (size_t)at;
+        q[0] = make_float4(a.x, a.y, a.z, __uint_as_float(i));
         q[1] = make_float4(b.x, b.y, b.z, 0.0f);
         q[2] = make_float4(c.x, c.y, c.z, 0.0f);
         if (ed.w >= 0) {
@@ -416,10 +524,16 @@ __global__ void edge_pack_kernel(const int4* __restrict__ edges, const uint32_t*
 
 }  // namespace
 
-hipError_t launch_edge_pack(const EdgeArgs& e, uint32_t cap, hipStream_t s) {
-    const uint32_t blocks = (cap + 255) / 256 < 4096u ? (cap + 255) / 256 : 4096u;
-    hipLaunchKernelGGL(edge_pack_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, e.edges, e.n_edges, e.verts,
-                       const_cast<float4*>(e.egeo), cap);
+uint32_t edge_pack_blocks(uint32_t cap) { return (cap + kPackBlock - 1) / kPackBlock; }
+
+hipError_t launch_edge_pack(const EdgeArgs& e, uint32_t cap, uint32_t* bsum, uint32_t* n_sharp, hipStream_t s) {
+    const uint32_t nb = edge_pack_blocks(cap);
+    float4* egeo = const_cast<float4*>(e.egeo);
+    hipLaunchKernelGGL(edge_class_count, dim3(nb > 0 ? nb : 1), dim3(kPackThreads), 0, s, e.edges, e.n_edges, e.verts,
+                       bsum);
+    hipLaunchKernelGGL(edge_class_scan, dim3(1), dim3(kPackThreads), 0, s, nb > 0 ? nb : 1u, bsum, n_sharp);
+    hipLaunchKernelGGL(edge_pack_kernel, dim3(nb > 0 ? nb : 1), dim3(kPackThreads), 0, s, e.edges, e.n_edges, e.verts,
+                       bsum, n_sharp, egeo);
     return hipGetLastError();
 }
 

@@ -15,14 +15,20 @@ constexpr uint32_t kEdgeQueueMax = 1u << 25;   // queue records per pass (4 byte
 constexpr int64_t kEdgePassMax = 1 << 22;      // pixels per pass (22 bits of the record)
 // from this many queued rays on, one lane traces each ray instead of one wavefront
 constexpr uint32_t kEdgeLaneMode = 1u << 16;
+// edge classes of the sampling distribution: sharp edges have one face, or
+// face normals more than 20 degrees apart; the call's gain weights them
+constexpr float kSharpCos2 = 0.883022221559489f;   // cos^2(20 degrees)
+constexpr uint32_t kSharpGainMax = 1024;
 struct EdgeArgs {
     ShadeArgs a;             // scene, env, G-buffer, seed, tau, ray_eps, flags, g_cd, g_cs, stats
     const int4* edges;       // [E] (a, b, c, d) rows
     const uint32_t* n_edges; // E (device)
     const float* verts;      // [Nv][3]
-    const float4* egeo;      // [E][4] corners a, b, c, d of each edge (d.w = 1 when present)
+    const float4* egeo;      // [E][4] corners (a, edge id), b, c, (d, 1 when present); sharp edges first
+    const uint32_t* n_sharp; // edges of the sharp class (device)
     float* g_verts;          // [Nv][3], accumulated
     int32_t n_es;            // edge samples per pixel
+    uint32_t gain;           // per-edge weight of the sharp class (1: uniform over edges)
     int64_t pix0, npix;      // pixel range of this pass
     uint32_t* queue;         // [q_cap]: pixel in pass << 10 | edge sample
     uint32_t* q_count;
@@ -31,8 +37,10 @@ struct EdgeArgs {
 
 // one pass of the edge-sampled visibility gradient over [pix0, pix0 + npix)
 hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s);
-// packs the corners of the first min(E, cap) edges into e.egeo
-hipError_t launch_edge_pack(const EdgeArgs& e, uint32_t cap, hipStream_t s);
+// classifies the edges and packs their corners into e.egeo, sharp edges
+// first (cap >= E); bsum: [edge_pack_blocks(cap)] block sums
+uint32_t edge_pack_blocks(uint32_t cap);
+hipError_t launch_edge_pack(const EdgeArgs& e, uint32_t cap, uint32_t* bsum, uint32_t* n_sharp, hipStream_t s);
 
 // unique mesh edges: hash table of 2^bits slots (keys, first and second
 // side), side -> slot map [3 n_tris], block sums [edge_scan_blocks]

@@ -69,6 +69,6 @@ def test_validation_without_device():
     cnt = ctypes.c_int64()
     assert lib.mcdi_edges_count(None, ctypes.byref(cnt)) == L.MCDI_E_INVALID
     assert lib.mcdi_edges_copy(None, None, None) == L.MCDI_E_INVALID
-    assert lib.mcdi_shade_bwd_edges(None, None, None, None, 0, ctypes.byref(g), ctypes.byref(p), 4, None, None,
+    assert lib.mcdi_shade_bwd_edges(None, None, None, None, 0, ctypes.byref(g), ctypes.byref(p), 4, 1, None, None,
                                     None, None, None) == L.MCDI_E_INVALID
     assert b"mcdi_shade_bwd_edges" in lib.mcdi_last_error()

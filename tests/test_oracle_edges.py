@@ -325,7 +325,7 @@ def test_class_weights_keep_the_expectation():
     E = oracle.mesh_edges(w.tris, len(w.verts))
     sharp = oracle.edge_sharp(w.verts, E)
     assert 0 < sharp.sum() < len(E)
-    m64, s64 = _mean_grad(w, ud, us, n_es=64, seeds=8)
+    m64, s64 = _mean_grad(w, ud, us, n_es=64, seeds=8, sharp_gain=64)
     m1, s1 = _mean_grad(w, ud, us, n_es=64, seeds=8, sharp_gain=1)
     scale = np.abs(m64).max()
     assert scale > 0
