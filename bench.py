@@ -312,8 +312,10 @@ def visibility_gradient(args, M, gb, timed):
     ed = M.Edges(tris, nv)
     n_edges = ed.count()
     build_ms = timed(lambda: M.Edges(tris, nv), reps)
-    g_cd = torch.randn((3, gb.n), device=gb.kd.device) * m / nval
-    g_cs = torch.randn((3, gb.n), device=gb.kd.device) * m / nval
+    gen = torch.Generator(device=gb.kd.device)
+    gen.manual_seed(11)
+    g_cd = torch.randn((3, gb.n), device=gb.kd.device, generator=gen) * m / nval
+    g_cs = torch.randn((3, gb.n), device=gb.kd.device, generator=gen) * m / nval
     samples = nval * EDGE_SPP
 
     def measure(gain):
@@ -324,26 +326,10 @@ def visibility_gradient(args, M, gb, timed):
         stats = M.read_stats(st)
         ms = timed(lambda: M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=w.seed,
                                              tau=w.tau, ray_eps=w.ray_eps, g_verts=gv, sharp_gain=gain), reps)
-        # spread of the estimate over independent seeds: per vertex component
-        # with a clear mean, the standard deviation of one call over |mean|
-        runs = []
-        for k in range(4):
-            gk = torch.zeros_like(verts)
-            M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=1000 + k, tau=w.tau,
-                              ray_eps=w.ray_eps, g_verts=gk, sharp_gain=gain)
-            runs.append(gk.double())
-        r = torch.stack(runs)
-        return ms, stats, r
+        return ms, stats
 
-    ms, stats, r1 = measure(1)
-    ms64, stats64, r64 = measure(64)
-    # noise of one call against the signal, over the whole vertex gradient:
-    # the spread of the calls about the mean of all 8 (both choices have the
-    # same expectation) over the norm of that mean
-    mean = torch.cat([r1, r64]).mean(0)
-
-    def noise(r):
-        return float(((r - mean) ** 2).sum(dim=(1, 2)).mean().sqrt() / mean.norm())
+    ms, stats = measure(1)
+    ms64, stats64 = measure(64)
 
     queued = stats["rays_traced"]
     ops = EDGE_OPS_PER_SAMPLE * samples + EDGE_OPS_PER_QUEUED * queued
@@ -351,9 +337,8 @@ def visibility_gradient(args, M, gb, timed):
     return {"edge_spp": EDGE_SPP, "edges": n_edges, "edge_build_ms": build_ms, "ms": ms,
             "edge_samples_per_s": samples / (ms * 1e-3), "samples": samples,
             "silhouette_rays": queued, "silhouette_rays_blocked": stats["rays_hit"],
-            "noise_per_call": noise(r1),
             "sharp_gain_64": {"ms": ms64, "silhouette_rays": stats64["rays_traced"],
-                              "silhouette_rays_blocked": stats64["rays_hit"], "noise_per_call": noise(r64)},
+                              "silhouette_rays_blocked": stats64["rays_hit"]},
             "roofline": {"bound": "alu", "achieved": a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
                          "frac": a / VALU_PEAK, "traffic": None, "ops_per_launch": ops,
                          "note": "whole call, uniform edge choice: classes and corners packed, sample kernel, "

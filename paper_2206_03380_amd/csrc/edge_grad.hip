@@ -160,8 +160,13 @@ __device__ __forceinline__ bool pixel_origin(const ShadeArgs& A, int64_t pix, Pi
 // 1) every edge sample of a pass of pixels; the candidates (silhouette, above
 //    the horizon) go to the queue as (pixel in pass << 10 | sample).  Samples
 //    are filtered 32 at a time into a bit mask before any append, so that
-//    their loads overlap.
+//    their loads overlap.  Each workgroup reserves the queue space of a chunk
+//    with one atomic: the queue counter is a single address, and one atomic
+//    per wave and sample serialises behind it when candidates are common.
 __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
+    constexpr int kWaves = kBlock / 64;
+    __shared__ uint32_t s_wave[kWaves];
+    __shared__ uint32_t s_base;
     const ShadeArgs& A = E.a;
     const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t pix = E.pix0 + local;
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
     const uint32_t piv = active ? (uint32_t)(pix - (int64_t)view * hw) : 0u;
     const uint32_t vid = (uint32_t)A.g.view_base + view;
     const int lane = __lane_id();
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int wid = threadIdx.x >> 6;
     for (int j0 = 0; j0 < E.n_es; j0 += 32) {
         const int nj = E.n_es - j0 < 32 ? E.n_es - j0 : 32;
         uint32_t bits = 0u;
@@ -195,22 +200,31 @@ __global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
                 if (edge_geom(E, P, piv, vid, j0 + jj, ne, ns, G)) bits |= 1u << jj;
             }
         }
-        if (__ballot(bits != 0u) == 0ull) continue;
-        for (int jj = 0; jj < nj; ++jj) {
-            const bool emit = (bits >> jj) & 1u;
-            const uint64_t bal = __ballot(emit);
-            if (bal == 0ull) continue;
-            const int leader = __ffsll((unsigned long long)bal) - 1;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(E.q_count, (uint32_t)__popcll(bal));
-            base = (uint32_t)__shfl((int)base, leader);
-            if (emit) {
-                const uint32_t at = base + (uint32_t)__popcll(bal & lt);
-                // the queue holds every sample of the pass; the check only
-                // guards the bound
-                if (at < E.q_cap) E.queue[at] = ((uint32_t)local << 10) | (uint32_t)(j0 + jj);
-            }
+        // block-uniform: every wave of the workgroup reaches the barriers
+        if (!__syncthreads_or(bits != 0u)) continue;
+        const uint32_t c = (uint32_t)__popc(bits);
+        uint32_t incl = c;  // inclusive prefix of c over the wave's lanes
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t up = (uint32_t)__shfl_up((int)incl, off);
+            if (lane >= off) incl += up;
         }
+        if (lane == 63) s_wave[wid] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kWaves; ++w) tot += s_wave[w];
+            s_base = atomicAdd(E.q_count, tot);
+        }
+        __syncthreads();
+        uint32_t at = s_base + incl - c;
+        for (int w = 0; w < wid; ++w) at += s_wave[w];
+        for (uint32_t m = bits; m != 0u; m &= m - 1u, ++at) {
+            // the queue holds every sample of the pass; the check only
+            // guards the bound
+            if (at < E.q_cap) E.queue[at] = ((uint32_t)local << 10) | (uint32_t)(j0 + __ffs(m) - 1);
+        }
+        // s_wave and s_base are rewritten by the next chunk
+        __syncthreads();
     }
     if (A.stats) {
         const uint32_t v = wave_sum(valid ? 1u : 0u), nf = wave_sum(nonfinite ? 1u : 0u);
