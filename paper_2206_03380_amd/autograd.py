@@ -13,7 +13,7 @@ from . import _lib as L
 
 class MCDIShade(torch.autograd.Function):
     """c_d, c_s = MCDIShade.apply(kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed, tau, ray_eps, flags,
-                                 bwd_seed)
+                                 bwd_seed, verts, edges, edge_spp, sharp_gain)
 
     kd, korm, nrm: [3, N] float32 (differentiable); env: the [H, W, 3] probe
     tensor the tables were built from (differentiable; its gradient is the
@@ -26,11 +26,13 @@ class MCDIShade(torch.autograd.Function):
     (the ones scene was built from; differentiable), its Edges and a number
     of edge samples per pixel: the backward then also returns the
     edge-sampled visibility gradient of the shadow term for verts (the paper
-    detaches it by default, section 3.1 "Shadow gradients")."""
+    detaches it by default, section 3.1 "Shadow gradients").  sharp_gain: how
+    many times as likely a sharp edge is drawn as a smooth one (1 = uniform
+    over the edges; see shade_bwd_edges)."""
 
     @staticmethod
     def forward(ctx, kd, korm, nrm, env, scene, env_tables, gbuf, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0,
-                bwd_seed=None, verts=None, edges=None, edge_spp=0):
+                bwd_seed=None, verts=None, edges=None, edge_spp=0, sharp_gain=1):
         from . import _ptr, _stream, hit_words, _params
         import ctypes as C
         n = gbuf.n
@@ -51,7 +53,7 @@ class MCDIShade(torch.autograd.Function):
                               verts if vis else torch.empty(0, device=dev))
         ctx.meta = (scene, env_tables, gbuf, spp, seed if bwd_seed is None else bwd_seed, tau, ray_eps,
                     hb is not None, flags & ~(L.FLAG_DUMP | L.FLAG_TIME_TRACE))
-        ctx.vis = (edges, edge_spp) if vis else None
+        ctx.vis = (edges, edge_spp, sharp_gain) if vis else None
         return c_d, c_s
 
     @staticmethod
@@ -79,11 +81,12 @@ class MCDIShade(torch.autograd.Function):
         g_verts = None
         if ctx.vis is not None and ctx.needs_input_grad[13]:
             from . import shade_bwd_edges
-            edges, edge_spp = ctx.vis
+            edges, edge_spp, sharp_gain = ctx.vis
             g_verts = shade_bwd_edges(scene, env_tables, edges, verts.detach().contiguous(), gbuf, edge_spp, g_cd,
-                                      g_cs, seed=seed, tau=tau, ray_eps=ray_eps, flags=flags & L.FLAG_BILINEAR)
+                                      g_cs, seed=seed, tau=tau, ray_eps=ray_eps, flags=flags & L.FLAG_BILINEAR,
+                                      sharp_gain=sharp_gain)
         return (g_kd, g_korm, g_nrm, g_env, None, None, None, None, None, None, None, None, None, g_verts, None,
-                None)
+                None, None)
 
 
 class Bilateral(torch.autograd.Function):

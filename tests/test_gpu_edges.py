@@ -182,14 +182,17 @@ def _ground_scene(N, seed=5):
                        eye=[[0.5, 3.0, 4.0]], height=1, width=N, ray_eps=1e-4, tau=1.0, seed=3)
 
 
-def test_edge_grad_ragged_passes():
+@pytest.mark.parametrize("gain", [1, 64])
+def test_edge_grad_ragged_passes(gain):
     """9001 pixels at 512 edge samples: passes of 8192 pixels and a ragged
     tail of 809; pixels inside the boxes' footprints see no sky at all.  Each
     of the 60 vertex components sums some 10^4 - 10^5 FP32 terms of both signs
     (u sqrt(n) ~ 2e-5 of the sum of magnitudes, several times that of the
-    signed sum): the median guard is set from that."""
+    signed sum): the median guard is set from that.  At gain 64 the box edges
+    and the ground's border (sharp) take nearly every sample and the face
+    diagonals (smooth) the rest, in every pass."""
     _need_gpu()
-    _parity(_ground_scene(9001), 512, med=3e-4)
+    _parity(_ground_scene(9001), 512, med=3e-4, gain=gain)
 
 
 def test_edge_grad_full_size_sampled():
@@ -252,9 +255,11 @@ def test_edge_grad_accumulates_and_degenerate_cases():
     assert (to_np(g) == 0).all()
 
 
-def test_autograd_returns_visibility_gradient():
+@pytest.mark.parametrize("gain", [1, 64])
+def test_autograd_returns_visibility_gradient(gain):
     """MCDIShade with verts/edges: loss.backward() puts the edge-sampled
-    visibility gradient into verts.grad, the same as the direct call."""
+    visibility gradient into verts.grad, the same as the direct call with the
+    same sharp-class gain."""
     _need_gpu()
     import paper_2206_03380_amd as M
     w = make_workload("tiny")
@@ -268,10 +273,10 @@ def test_autograd_returns_visibility_gradient():
     ed = M.Edges(tris, len(w.verts))
     ud, us = (torch.from_numpy(x).to(dev) for x in upstream_grads(w))
     c_d, c_s = M.MCDIShade.apply(gb.kd, gb.korm, gb.nrm, env_t, scene, envh, gb, w.spp, w.seed, w.tau, w.ray_eps, 0,
-                                 None, verts, ed, 8)
+                                 None, verts, ed, 8, gain)
     ((c_d * ud).sum() + (c_s * us).sum()).backward()
     ref = M.shade_bwd_edges(scene, envh, ed, verts.detach(), gb, 8, ud, us, seed=w.seed, tau=w.tau,
-                            ray_eps=w.ray_eps)
+                            ray_eps=w.ray_eps, sharp_gain=gain)
     torch.cuda.synchronize()
     g, r = to_np(verts.grad), to_np(ref)
     assert np.abs(r).max() > 0
