@@ -562,12 +562,12 @@ def cpu_baseline(args, w):
     tables = oracle.EnvTables(w.env)
     ud, us = upstream_grads(w)
 
-    def run(n):
+    def run(n, threads=0):
         pix = np.sort(rng.choice(valid, n, replace=False))
         t = time.time()
-        oracle.shade(w, pixels=pix, scene=scene, tables=tables)
+        oracle.shade(w, pixels=pix, scene=scene, tables=tables, threads=threads)
         oracle.shade(w, pixels=pix, scene=scene, tables=tables, grad=True, u_d=ud[:, pix].astype(np.float64),
-                     u_s=us[:, pix].astype(np.float64))
+                     u_s=us[:, pix].astype(np.float64), threads=threads)
         return time.time() - t
 
     # size the sample from a calibration run large enough that per-call
@@ -579,6 +579,10 @@ def cpu_baseline(args, w):
     what = "all %d valid pixels" % n2 if n2 == len(valid) else "%d random valid pixels" % n2
     res = {"value": n2 * w.spp / dt2, "unit": "samples/s", "cores": nthreads, "kind": "oracle",
            "sample": "%s of the same workload, forward + backward, %.1f s" % (what, dt2)}
+    n1 = int(min(len(valid), 8192))
+    dt1 = run(n1, threads=1)
+    res["single_thread"] = {"value": n1 * w.spp / dt1, "unit": "samples/s", "cores": 1,
+                            "sample": "%d random valid pixels, forward + backward, %.1f s" % (n1, dt1)}
     if not args.no_next_rows:
         # the oracle's edge-sampled visibility gradient beside the kernels' (row f4)
         edges = oracle.mesh_edges(w.tris, len(w.verts))

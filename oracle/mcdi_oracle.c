@@ -1221,10 +1221,12 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
     env_contrib* all = NULL;
     if (grad && genv) all = (env_contrib*)malloc(sizeof(env_contrib) * (size_t)npix * 2 * spp);
     int64_t nonfinite = 0;
+    int nt = 1;  // a thread count for this call only (num_threads clause)
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #endif
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : nonfinite)
+    (void)nt;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : nonfinite) num_threads(nt)
     for (int64_t q = 0; q < npix; ++q) {
         pix_out o;
         env_contrib local[2 * 512];
@@ -1543,17 +1545,16 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
     const uint64_t cS = (Nn << 24) / Dd + (((Nn << 24) % Dd) != 0); /* u24 values that pick the sharp class */
     const double wS = cS > 0 ? (double)nS * 16777216.0 / (double)cS : 0.0;
     const double wR = cS < 16777216u ? (double)nR * 16777216.0 / (double)(16777216u - cS) : 0.0;
-    int nt = 1;
+    int nt = 1;  // a thread count for this call only (num_threads clause)
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-    nt = omp_get_max_threads();
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #endif
     const size_t nv3 = (size_t)n_verts * 3;
     double* acc = (double*)calloc((size_t)nt * 4 * nv3, sizeof(double));
     int64_t* cnt = (int64_t*)calloc((size_t)nt * 5, sizeof(int64_t));
     const int64_t HW = (int64_t)g->height * g->width;
     const uint32_t key[2] = {(uint32_t)P->seed, (uint32_t)(P->seed >> 32)};
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
     {
         int tid = 0;
 #ifdef _OPENMP
