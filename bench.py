@@ -66,8 +66,9 @@ def log(args, *a):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path (the env-gradient all-reduce "
-              "that sharding would need is described in the design notes); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path (pixels are independent, so "
+              "sharding by views would only add an all-reduce of the probe gradient); use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -222,8 +223,11 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-# per-unit VALU lane-operation counts of the traversal (see the design notes):
-# slab test of one node box, watertight test of one triangle, ray setup
+# per-unit VALU lane-operation counts of the traversal: slab test of one node
+# box (6 sub, 6 mul, 6 min/max per axis, 5 min/max for the interval, 1 mul for
+# the slack, 1 compare), watertight test of one triangle (9 sub, 6 shear FMA,
+# 6 mul + 3 sub for the edge functions, 6 sign compares, 2 add, 6 for the hit
+# distance, 1 compare), ray setup
 OPS_PER_BOX = 25
 OPS_PER_TRI = 39
 OPS_PER_RAY = 25

@@ -234,7 +234,11 @@ class Scene:
 # ---------------------------------------------------------------------------
 
 class Tolerances:
-    """Decision tolerances of the parity protocol (see the design notes)."""
+    """Decision tolerances of the parity protocol: a discrete decision whose
+    margin is below these (visibility: absolute and relative edge distance;
+    texel boundaries: radians of arc; signs of n.v and n.l: cosine) is
+    undecided in FP32, so the oracle adopts the kernel's dumped decision
+    there or flags it."""
 
     def __init__(self, vis_abs=1e-5, vis_rel=1e-5, ang=2e-5, cos=1e-5):
         self.vis_abs, self.vis_rel, self.ang, self.cos = vis_abs, vis_rel, ang, cos

@@ -27,9 +27,9 @@
  *     derivative of the shadowed integral with respect to the occluding mesh's
  *     vertices (section 3.1 "Shadow gradients"; appendix "Visibility
  *     Gradients from Shadows"), estimated by sampling silhouette edges.
- * Readings of points the paper leaves open (probe parameterisation, lobe
- * selection probability, GGX details, ray offsets, RNG) are listed in the
- * design notes and are identical on both sides.
+ * Points the paper leaves open (probe parameterisation, lobe selection
+ * probability, GGX details, ray offsets, RNG) take one reading each, stated
+ * where the code implements it, and the kernels take the same.
  *
  * Everything here is FP64 except two discrete decisions that the HIP kernel
  * takes in FP32 and that the oracle therefore also takes in FP32: the

@@ -4,8 +4,8 @@ and the oracle on the same seeded inputs, compare at the stated tolerance."""
 import numpy as np
 
 # c_d, c_s and per-pixel gradients: |gpu - oracle| <= REL * |oracle| + ABS * mean|oracle|
-# (per channel, valid pixels).  Derivation in the design notes: FP32 per-sample
-# terms carry ~1e-6 relative error, sums over 2*spp terms of like sign.
+# (per channel, valid pixels).  FP32 per-sample terms carry ~1e-6 relative
+# error, and the sums run over 2*spp terms of like sign.
 REL_TOL = 1e-4
 ABS_TOL = 1e-6
 
