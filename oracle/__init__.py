@@ -306,7 +306,7 @@ def shade(w, pixels=None, scene=None, tables=None, spp=None, seed=None, tau=None
                     _p(out["hitbits"]), hw, _p(dec),
                     _p(out["info"]), int(threads))
     if r < 0:
-        raise ValueError("oracle rejected the parameters (spp must be in [1, 512])")
+        raise ValueError("oracle rejected the parameters (spp must be in [1, 1024])")
     out["nonfinite"] = int(r)
     # sum over the pixel's samples of |term| * 2^-24 / (n.l), per channel:
     # the FP32 conditioning of each output in the sampled directions

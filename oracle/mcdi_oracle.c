@@ -852,7 +852,7 @@ typedef struct {
      * texel), per output */
     double cd_lerr[3], cs_lerr[3], gkd_lerr[3], gr_lerr, gm_lerr, gn_lerr;
     double nlen_cond;                              /* |n_raw|, for the normal's projection */
-    uint32_t hitbits[32]; /* 2 bits per sample, spp <= 512 */
+    uint32_t hitbits[64]; /* 2 bits per sample, spp <= 1024 */
     int n_synced, n_flag, n_hard;
 } pix_out;
 
@@ -1217,7 +1217,7 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
 {
     shade_ctx C = {scene, env_s, env_eval, gs, ge, prm, sync, dec_out};
     int spp = prm->spp;
-    if (spp < 1 || spp > 512 || hit_words > 32) return -1;
+    if (spp < 1 || spp > 1024 || hit_words > 64) return -1;
     env_contrib* all = NULL;
     if (grad && genv) all = (env_contrib*)malloc(sizeof(env_contrib) * (size_t)npix * 2 * spp);
     int64_t nonfinite = 0;
@@ -1229,8 +1229,11 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : nonfinite) num_threads(nt)
     for (int64_t q = 0; q < npix; ++q) {
         pix_out o;
-        env_contrib local[2 * 512];
-        env_contrib* ec = all ? all + (size_t)q * 2 * spp : local;
+        env_contrib local[2 * 256];
+        // above 256 samples the pixel's records go to the heap (worker
+        // threads may have small stacks)
+        env_contrib* big = (!all && spp > 256) ? (env_contrib*)malloc(sizeof(env_contrib) * 2 * (size_t)spp) : NULL;
+        env_contrib* ec = all ? all + (size_t)q * 2 * spp : (big ? big : local);
         double ud[3] = {0, 0, 0}, us[3] = {0, 0, 0};
         if (grad) for (int c = 0; c < 3; ++c) { ud[c] = Ud[c * npix + q]; us[c] = Us[c * npix + q]; }
         shade_pixel(&C, q, pix[q], grad, ud, us, &o, ec, &nonfinite);
@@ -1261,6 +1264,7 @@ int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env
         }
         if (hitbits) for (int k = 0; k < hit_words; ++k) hitbits[(size_t)q * hit_words + k] = o.hitbits[k];
         if (info) { info[q * 3] = o.n_synced; info[q * 3 + 1] = o.n_flag; info[q * 3 + 2] = o.n_hard; }
+        free(big);
     }
     if (all) {
         /* fixed order: pixel list order, then sample, then technique */

@@ -413,6 +413,17 @@ def test_bwd_parity_tiny_retrace():
     _bwd_parity(make_workload("tiny"), use_hitbits=False)
 
 
+def test_fwd_bwd_parity_largest_spp():
+    """spp = 1024, the largest the library takes: 64 hit words per pixel and
+    tile ray regions of 2 x 1024 x 256 rays; the backward replays from the
+    stored bits and by re-tracing."""
+    w = make_workload("tiny", H=24, W=24, spp=1024)
+    print("largest spp", w.n_pixels, "px", w.spp, "spp", flush=True)
+    _fwd_parity(w)
+    _bwd_parity(w)
+    _bwd_parity(w, use_hitbits=False)
+
+
 @pytest.mark.parametrize("tech", ["light", "cosine", "ggx"])
 def test_bwd_parity_tiny_techniques(tech):
     _bwd_parity(make_workload("tiny"), flags=_technique(tech))

@@ -337,6 +337,28 @@ def test_decisions_and_hitbits_consistent():
     assert np.all(dec[~valid, :, 0] == oracle.DEC_NONE)
 
 
+def test_largest_spp_keeps_the_sample_sequence():
+    """spp = 1024 (the library's largest): sample s draws from counter s
+    whatever spp is, so the first 512 samples' decisions and hit words equal
+    those of spp = 512; every hit bit, up to word 63, agrees with its sample's
+    decision; spp = 1025 is rejected."""
+    w = make_workload("tiny", H=12, W=12)
+    a = oracle.shade(w, spp=1024, want_decisions=True)
+    b = oracle.shade(w, spp=512, want_decisions=True)
+    assert a["hitbits"].shape[1] == 64
+    assert np.array_equal(a["decisions"][:, :512], b["decisions"])
+    assert np.array_equal(a["hitbits"][:, :32], b["hitbits"])
+    dec, hb = a["decisions"], a["hitbits"]
+    for s in range(1024):
+        fl = dec[:, s, 2]
+        word = hb[:, s // 16]
+        for tech, bit in ((0, oracle.DEC_L_HIT), (1, oracle.DEC_B_HIT)):
+            assert np.array_equal(((word >> (2 * s % 32 + tech)) & 1) != 0, (fl & bit) != 0)
+    assert (hb[:, 32:] != 0).any()
+    with pytest.raises(ValueError):
+        oracle.shade(w, spp=1025)
+
+
 def test_brute_force_equals_bvh_render():
     w = make_workload("tiny")
     a = oracle.shade(w)
