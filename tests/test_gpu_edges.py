@@ -161,6 +161,15 @@ def test_edge_grad_parity_sharp_gain(gain):
     _parity(make_workload("tiny"), 16, gain=gain)
 
 
+def test_edge_grad_parity_largest_edge_spp():
+    """1024 edge samples per pixel, the most the library takes: 32 filter
+    chunks of 32 samples per pixel and all 10 bits of the sample index in the
+    queue records.  Each vertex component sums ~10^3 terms (u sqrt(n) ~ 2e-6
+    of their magnitudes), well inside the default median guard."""
+    _need_gpu()
+    _parity(make_workload("tiny", H=16, W=16), 1024)
+
+
 def test_edge_grad_parity_bilinear():
     _need_gpu()
     import paper_2206_03380_amd as M
