@@ -72,3 +72,19 @@ def test_validation_without_device():
     assert lib.mcdi_shade_bwd_edges(None, None, None, None, 0, ctypes.byref(g), ctypes.byref(p), 4, 1, None, None,
                                     None, None, None) == L.MCDI_E_INVALID
     assert b"mcdi_shade_bwd_edges" in lib.mcdi_last_error()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library the loader raises, and host tensors are
+    refused before any call: there is no fallback path."""
+    import torch
+    import paper_2206_03380_amd as M
+    from paper_2206_03380_amd import _lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libmcdi.so"))
+    with pytest.raises(ImportError, match="no fallback"):
+        L.lib()
+    verts = torch.zeros((3, 3))
+    tris = torch.zeros((1, 3), dtype=torch.int32)
+    with pytest.raises(TypeError, match="CUDA"):
+        M.Scene(verts, tris)
