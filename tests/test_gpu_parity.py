@@ -413,6 +413,26 @@ def test_bwd_parity_tiny_retrace():
     _bwd_parity(make_workload("tiny"), use_hitbits=False)
 
 
+def test_fwd_bwd_parity_view_base():
+    """Views numbered from view_base = 6 (the counter's view word): forward
+    and backward parity, and views 6 and 7 of an 8-view render rendered on
+    their own give the same values and hit bits bit for bit."""
+    import dataclasses
+    w = make_workload("sphere8", H=32, W=32, n_views=8, spp=4)
+    hw = 32 * 32
+    sl = slice(6 * hw, 8 * hw)
+    part = dataclasses.replace(w, n_views=2, pos=w.pos[:, sl].copy(), nrm=w.nrm[:, sl].copy(),
+                               kd=w.kd[:, sl].copy(), korm=w.korm[:, sl].copy(), mask=w.mask[sl].copy(),
+                               eye=w.eye[6:8].copy(), view_base=6, depth=None)
+    _fwd_parity(part)
+    _bwd_parity(part)
+    full, _ = gpu_forward(w, dump=False)
+    alone, _ = gpu_forward(part, dump=False)
+    for key in ("c_d", "c_s"):
+        assert np.array_equal(full[key][:, sl], alone[key])
+    assert np.array_equal(hitbits_per_pixel(full["hitbits"])[sl], hitbits_per_pixel(alone["hitbits"]))
+
+
 def test_fwd_bwd_parity_largest_spp():
     """spp = 1024, the largest the library takes: 64 hit words per pixel and
     tile ray regions of 2 x 1024 x 256 rays; the backward replays from the

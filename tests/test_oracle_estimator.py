@@ -337,6 +337,32 @@ def test_decisions_and_hitbits_consistent():
     assert np.all(dec[~valid, :, 0] == oracle.DEC_NONE)
 
 
+def _views(w, v0, v1, view_base):
+    """The workload's views v0..v1-1 on their own, numbered from view_base."""
+    import dataclasses
+    hw = w.height * w.width
+    sl = slice(v0 * hw, v1 * hw)
+    return dataclasses.replace(w, n_views=v1 - v0, pos=w.pos[:, sl].copy(), nrm=w.nrm[:, sl].copy(),
+                               kd=w.kd[:, sl].copy(), korm=w.korm[:, sl].copy(), mask=w.mask[sl].copy(),
+                               eye=w.eye[v0:v1].copy(), view_base=view_base, depth=None)
+
+
+def test_view_base_is_the_global_view_id():
+    """Views 6 and 7 of an 8-view render, rendered on their own with
+    view_base = 6, give the same values bit for bit: the counter's second
+    word is the global view id.  With view_base = 0 instead they draw other
+    samples."""
+    w = make_workload("sphere8", H=16, W=16, n_views=8, spp=4)
+    hw = 16 * 16
+    full = oracle.shade(w)
+    part = oracle.shade(_views(w, 6, 8, 6))
+    other = oracle.shade(_views(w, 6, 8, 0))
+    for key in ("c_d", "c_s"):
+        assert np.array_equal(full[key][:, 6 * hw:], part[key])
+        assert not np.array_equal(part[key], other[key])
+    assert np.array_equal(full["hitbits"][6 * hw:], part["hitbits"])
+
+
 def test_largest_spp_keeps_the_sample_sequence():
     """spp = 1024 (the library's largest): sample s draws from counter s
     whatever spp is, so the first 512 samples' decisions and hit words equal
