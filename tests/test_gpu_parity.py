@@ -413,6 +413,20 @@ def test_bwd_parity_tiny_retrace():
     _bwd_parity(make_workload("tiny"), use_hitbits=False)
 
 
+def test_fwd_bwd_parity_negative_texels():
+    """A tenth of the probe's texels negative: they weigh 0 in the light
+    technique's distribution, but BSDF samples still read them, so some
+    contributions and probe-gradient terms change sign."""
+    w = make_workload("tiny")
+    r = np.random.Generator(np.random.PCG64(21))
+    env = w.env.copy()
+    neg = r.random(env.shape[:2]) < 0.1
+    env[neg] = -env[neg]
+    w.env = env
+    _fwd_parity(w)
+    _bwd_parity(w)
+
+
 def test_fwd_bwd_parity_view_base():
     """Views numbered from view_base = 6 (the counter's view word): forward
     and backward parity, and views 6 and 7 of an 8-view render rendered on
