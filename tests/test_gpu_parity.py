@@ -413,6 +413,18 @@ def test_bwd_parity_tiny_retrace():
     _bwd_parity(make_workload("tiny"), use_hitbits=False)
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (1, 8), (7, 13)])
+def test_fwd_bwd_parity_small_probes(shape):
+    """Probes of one texel, one row and odd sizes: the row and column searches
+    run over one or a few bins, and BSDF directions fall on few texel
+    boundaries."""
+    w = make_workload("tiny")
+    r = np.random.Generator(np.random.PCG64(31))
+    w.env = r.lognormal(0.0, 1.0, size=shape + (3,)).astype(np.float32)
+    _fwd_parity(w)
+    _bwd_parity(w)
+
+
 def test_fwd_bwd_parity_negative_texels():
     """A tenth of the probe's texels negative: they weigh 0 in the light
     technique's distribution, but BSDF samples still read them, so some
