@@ -413,6 +413,22 @@ def test_bwd_parity_tiny_retrace():
     _bwd_parity(make_workload("tiny"), use_hitbits=False)
 
 
+def test_fwd_bwd_parity_material_extremes():
+    """Roughness at, just above and below the 0.08 clamp (the clamp is an FP32
+    decision on both sides; below it the roughness gradient is 0), and
+    metallic and albedo at 0 and 1."""
+    w = make_workload("tiny")
+    r = np.random.Generator(np.random.PCG64(41))
+    n = w.n_pixels
+    rough = np.array([0.0, 0.05, 0.08, np.nextafter(np.float32(0.08), np.float32(1)), 0.5, 1.0], np.float32)
+    w.korm = w.korm.copy()
+    w.korm[1] = rough[r.integers(0, len(rough), n)]
+    w.korm[2] = np.array([0.0, 1.0, 0.5], np.float32)[r.integers(0, 3, n)]
+    w.kd = np.where(r.random((3, n)) < 0.5, 0.0, 1.0).astype(np.float32)
+    _fwd_parity(w)
+    _bwd_parity(w)
+
+
 @pytest.mark.parametrize("shape", [(1, 1), (1, 8), (7, 13)])
 def test_fwd_bwd_parity_small_probes(shape):
     """Probes of one texel, one row and odd sizes: the row and column searches
