@@ -45,6 +45,23 @@ def test_loss_hand_case():
     assert np.allclose(gcs[:, 0], 0.15 / 3 * OL.tonemap_d(1.0))
 
 
+def test_loss_hand_case_coloured_reference():
+    """A reference whose channels differ: the image term is the mean over the
+    three channels of |T(c) - T(ref)|, and the light term compares the mean
+    of T(c_d + c_s) with the largest channel of T(ref), which is T(1) here,
+    so it vanishes.  A second, masked pixel changes nothing and gets no
+    gradient."""
+    kd = np.array([[1.0, 0.3], [1.0, 0.3], [1.0, 0.3]])
+    cd = np.ones((3, 2))
+    cs = np.zeros((3, 2))
+    ref = np.array([[0.2, 5.0], [0.5, 5.0], [1.0, 5.0]])
+    li, ll, gkd, gcd, gcs = OL.image_loss(kd, cd, cs, ref, np.array([1, 0]), w_light=0.15)
+    T = lambda x: OL.srgb(np.log(x + 1.0))  # noqa: E731
+    assert abs(li - (abs(T(1.0) - T(0.2)) + abs(T(1.0) - T(0.5))) / 3) < 1e-15
+    assert abs(ll) < 1e-15
+    assert np.all(gkd[:, 1] == 0) and np.all(gcd[:, 1] == 0) and np.all(gcs[:, 1] == 0)
+
+
 def test_loss_gradients_match_finite_differences():
     n = 40
     kd, cd, cs, ref = (RNG.uniform(0.05, 2.0, (3, n)) for _ in range(4))
