@@ -111,6 +111,32 @@ def test_env_tables_invariants():
     assert abs(t.pdf.astype(np.float64).sum() / (H * W) - 1.0) < 1e-6
 
 
+def test_env_tables_negative_texels_and_edge_ties():
+    """Negative texels weigh 0 (zero density, flat CDF steps).  With the
+    first row and the first column black, the first bins have zero width:
+    xi = 0 and xi equal to any table entry must still select a texel of
+    positive density (the search takes the largest k with cdf[k] <= xi)."""
+    e = _env()
+    e[0] = 0.0
+    e[:, 0] = 0.0
+    e[7, 5] = -2.0
+    e[8, 9] = np.float32(-1e-3)
+    t = oracle.EnvTables(e)
+    H, W = t.H, t.W
+    assert t.pdf[7, 5] == 0 and t.pdf[8, 9] == 0
+    assert np.all(t.pdf[0] == 0) and np.all(t.pdf[:, 0] == 0)
+    assert np.all(np.diff(t.cond, axis=1) >= 0) and np.all(np.diff(t.marg) >= 0)
+    xi0 = np.unique(np.concatenate([[0.0], t.marg[:-1].astype(np.float64)]))
+    xi1 = np.unique(np.concatenate([[0.0], t.cond[:, :-1].astype(np.float64).ravel()]))
+    a, b = np.meshgrid(xi0, xi1, indexing="ij")
+    w, p, ti, tj = t.sample(a.ravel(), b.ravel())
+    assert np.all(t.pdf[ti, tj] > 0) and np.all(p > 0)
+    # and the same on random uniforms of the 24-bit grid
+    u = np.floor(RNG.random((2, 100_000)) * 2 ** 24) / 2 ** 24
+    w, p, ti, tj = t.sample(u[0], u[1])
+    assert np.all(t.pdf[ti, tj] > 0)
+
+
 def test_env_tables_zero_env_disables_light():
     t = oracle.EnvTables(np.zeros((8, 16, 3), np.float32))
     assert not t.light_enabled and t.total == 0.0
