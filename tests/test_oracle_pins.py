@@ -305,6 +305,24 @@ def test_visibility_bvh_equals_brute_force():
     assert 0.05 < (a == oracle.TRI_HIT).mean() < 0.95
 
 
+def test_visibility_triangle_straddling_the_origin_plane():
+    """A triangle with vertices on both sides of the plane through the ray
+    origin: (-1,-1,-10), (1,-1,2), (0,1,5).  The line x = y = 0 meets it at
+    barycentric weights (1/4, 1/4, 1/2), so at z = 0.5 (plane geometry).
+    Rays along +z hit it from below z = 0.5 and miss from above; rays along
+    -z do the opposite."""
+    V = np.array([[-1.0, -1.0, -10.0], [1.0, -1.0, 2.0], [0.0, 1.0, 5.0]])
+    sc = oracle.Scene(V.astype(np.float32), np.array([[0, 1, 2]], np.int32))
+    zs = np.array([-3.0, 0.0, 0.4, 0.6, 1.0, 4.0])
+    o = np.stack([np.zeros_like(zs), np.zeros_like(zs), zs], 1)
+    up = np.tile([0.0, 0.0, 1.0], (len(zs), 1))
+    hit_up = sc.anyhit(o, up, 1e-9, 1e-9)
+    hit_down = sc.anyhit(o, -up, 1e-9, 1e-9)
+    below = zs < 0.5
+    assert np.all((hit_up == oracle.TRI_HIT) == below) and np.all((hit_up == oracle.TRI_MISS) == ~below)
+    assert np.all((hit_down == oracle.TRI_HIT) == ~below) and np.all((hit_down == oracle.TRI_MISS) == below)
+
+
 def test_visibility_closed_mesh_geometry():
     """Rays from outside a closed icosphere aimed inside its inscribed ball
     hit; rays aimed away miss; rays from the centre always hit (a centre ray
