@@ -344,7 +344,9 @@ def visibility_gradient(args, M, gb, timed):
             "sharp_gain_64": {"ms": ms64, "silhouette_rays": stats64["rays_traced"],
                               "silhouette_rays_blocked": stats64["rays_hit"]},
             "roofline": {"bound": "alu", "achieved": a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
-                         "frac": a / VALU_PEAK, "traffic": None, "ops_per_launch": ops,
+                         "frac": a / VALU_PEAK, "traffic": measured_traffic(EDGE_TRAFFIC_FILE, EDGE_SOURCES,
+                                                                            "traffic-bytes-per-call"),
+                         "ops_per_launch": ops,
                          "note": "whole call, uniform edge choice: classes and corners packed, sample kernel, "
                                  "out-side-ray kernel"}}
 
@@ -396,31 +398,35 @@ def next_rows(args, M, gb, c_d, c_s, target, timed):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_rays_sphere8_grad_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_03380_amd", "csrc", f)
                   for f in ("shade.hip", "shade_common.h", "device_common.h", "mcdi_internal.h", "bvh_build.hip")]
+# the edge-gradient call's kernels (classes, packing, samples, out-side rays)
+EDGE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "edge_grad_sphere8_grad_pmc.md")
+EDGE_SOURCES = [os.path.join(ROOT, "paper_2206_03380_amd", "csrc", f)
+                for f in ("edge_grad.hip", "edge_internal.h", "shade_common.h", "device_common.h", "mcdi_internal.h")]
 
 
-def kernel_source_hash():
+def kernel_source_hash(files=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (KERNEL_SOURCES if files is None else files):
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the traversal kernel from the committed
-    FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel calibration;
-    None when the kernel sources changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(path=TRAFFIC_FILE, files=None, key="traffic-bytes-per-launch"):
+    """HBM bytes per launch (or per call) from a committed FETCH_SIZE /
+    WRITE_SIZE summary, scaled by the copy-kernel calibration; None when the
+    kernel sources changed since the counters were taken."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source-sha256") != kernel_source_hash():
+    if vals.get("source-sha256") != kernel_source_hash(files):
         return None
     try:
-        return float(vals["traffic-bytes-per-launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
