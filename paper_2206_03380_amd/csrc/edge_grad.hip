@@ -160,10 +160,11 @@ __device__ __forceinline__ bool pixel_origin(const ShadeArgs& A, int64_t pix, Pi
 // 1) every edge sample of a pass of pixels; the candidates (silhouette, above
 //    the horizon) go to the queue as (pixel in pass << 10 | sample).  Samples
 //    are filtered 32 at a time into a bit mask before any append, so that
-//    their loads overlap.  Each workgroup reserves the queue space of a chunk
+//    their loads overlap (eight waves per SIMD: the corner-line reads miss
+//    L2 and need the waves in flight).  Each workgroup reserves the queue space of a chunk
 //    with one atomic: the queue counter is a single address, and one atomic
 //    per wave and sample serialises behind it when candidates are common.
-__global__ __launch_bounds__(kBlock) void edge_gen_kernel(EdgeArgs E) {
+__global__ __launch_bounds__(kBlock, 8) void edge_gen_kernel(EdgeArgs E) {
     constexpr int kWaves = kBlock / 64;
     __shared__ uint32_t s_wave[kWaves];
     __shared__ uint32_t s_base;
