@@ -22,9 +22,13 @@
 // Fixed point: a chunk adds at most 2^c records of magnitude below 2^e (e from
 // the bucket's largest |value|, found by the histogram step), so with scale
 // 2^(62-c-e) the int64 sum cannot overflow, and each record is rounded by at
-// most 2^-(63-c-e), i.e. < 2^-(63-c) of the bucket maximum (c <= 15 here).  A
-// bucket with a non-finite value takes the float-atomic path instead, so NaN
-// and infinity propagate as with direct atomics.
+// most 2^-(63-c-e), i.e. < 2^-(63-c) of the bucket maximum.  A chunk holds
+// max(2^14, ceil(record capacity / 2048)) records and c is the ceiling of its
+// log2; the capacity is at most 2^30, so 14 <= c <= 19 (15 for 8 views of 512^2 at
+// 12 spp, 17 for 4 views of 1024^2 at 32 spp): the rounding of one record is
+// below 2^-44 of the bucket maximum.  A bucket with a non-finite value takes
+// the float-atomic path instead, so NaN and infinity propagate as with direct
+// atomics.
 // Each record crosses HBM five times (written, read by the histogram and the
 // scatter, written sorted, read by the accumulation).
 //
@@ -350,7 +354,9 @@ __global__ __launch_bounds__(256) void gather_kernel(EnvScatter p) {
     float v = at(0, i + 1, j) + at(1, i + 1, jm) + at(2, i, j) + at(3, i, jm);
     if (i == 0) v += at(0, 0, j) + at(1, 0, jm);
     if (i == p.H - 1) v += at(2, p.H, j) + at(3, p.H, jm);
-    if (v != 0.0f) p.g_env[k] += v;
+    // an atomic add: g_env is accumulated, and another call may add into it
+    // concurrently (several views' backward passes on several streams)
+    if (v != 0.0f) atomicAdd(p.g_env + k, v);
 }
 
 // sorted records per accumulate workgroup: large against the bucket's texels,

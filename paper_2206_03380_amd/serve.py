@@ -56,6 +56,7 @@ class Request:
     _tiles: int = 0
     _bytes: int = 0
     _last_launch: int = -1
+    _ready: object = None              # event on the submitting stream: inputs written
 
     @property
     def grad(self):
@@ -69,6 +70,30 @@ class Request:
     def latency(self):
         return None if self.t_done is None else self.t_done - self.t_submit
 
+
+
+def _inputs(req):
+    """Device tensors a request reads: its G-buffer planes and upstream
+    gradients."""
+    gb = req.gb
+    ts = [gb.pos, gb.nrm, gb.kd, gb.korm, gb.mask, gb.eye]
+    if req.grad:
+        ts += [req.g_cd, req.g_cs]
+    return ts
+
+
+def _order_after_caller(req, stream):
+    """The server's stream must not read a request's inputs (or the probe
+    tables built before it) before the caller's stream has written them: an
+    event recorded on the submitting stream, waited for by `stream` before
+    the first launch that reads the request.  The inputs are also marked as
+    used on `stream`, so the caching allocator does not hand their memory out
+    again while that stream may still read it."""
+    ev = torch.cuda.Event()
+    ev.record(torch.cuda.current_stream())
+    req._ready = ev
+    for t in _inputs(req):
+        t.record_stream(stream)
 
 
 def request_bytes(n_pixels, spp, grad, env_hw):
@@ -126,6 +151,7 @@ class Server:
         req._bytes = request_bytes(req.gb.n, req.spp, req.grad, (env.H, env.W))
         if req._bytes > self.budget:
             raise ValueError("request larger than the memory budget")
+        _order_after_caller(req, self.stream)
         self.queue.append(req)
         return req
 
@@ -180,6 +206,11 @@ class Server:
                 finishing.append(r)
         if not items:
             return False
+        # first launch of a request: after the caller's writes of its inputs
+        for r in self.admitted:
+            if r._ready is not None and r._next_tile > 0:
+                self.stream.wait_event(r._ready)
+                r._ready = None
         arr = (L.ServeItem * len(items))(*items)
         L.check(L.lib().mcdi_server_launch(self.handle, arr, len(items)))
         ev = torch.cuda.Event()
@@ -235,6 +266,8 @@ class PerRequest:
         self._rid += 1
         req.t_submit = time.perf_counter()
         scene, env = self.scenes[req.scene]
+        _order_after_caller(req, self.stream)
+        self.stream.wait_event(req._ready)
         with torch.cuda.stream(self.stream):
             req.c_d, req.c_s, hb, _ = shade_fwd(scene, env, req.gb, req.spp, seed=req.seed, tau=req.tau,
                                                 ray_eps=req.ray_eps, flags=req.flags, hitbits=req.grad,

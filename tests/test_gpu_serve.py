@@ -162,3 +162,41 @@ def test_server_rejects_bad_requests(env):
     r2 = build_requests(M, scenes_np, [("A", 64, 4, False, 2)])[0]
     with pytest.raises(ValueError):
         small.submit(r2)
+
+
+def test_submit_orders_after_the_callers_stream(env):
+    """Inputs written on the caller's stream right before submit() (no
+    synchronisation in between, the stream still busy): the serving stream
+    waits for them, so the results equal the staged path's, for the batched
+    server and for per-request launches."""
+    M, scenes_np, resident = env
+    from paper_2206_03380_amd.serve import Server, PerRequest, Request
+    draws = serving.make_requests(scenes_np, 6, seed=33, res=(64, 128), spps=(4, 8))
+    draws = [(n, r, s, True, vb) for (n, r, s, g, vb) in draws]
+    base = PerRequest(resident)
+    ref = build_requests(M, scenes_np, draws)
+    for r in ref:
+        base.submit(r)
+    base.drain()
+    torch.cuda.synchronize()
+    ref_res = [results(r) for r in ref]
+    makers = (lambda: Server(resident, budget_bytes=1 << 34, max_slots=8, launch_samples=200_000, spp_max=64),
+              lambda: PerRequest(resident))
+    for make in makers:
+        sysm = make()
+        src = build_requests(M, scenes_np, draws)      # synchronised copies
+        torch.cuda._sleep(50_000_000)                  # keep the caller's stream busy
+        reqs = []
+        for r in src:
+            gb = r.gb
+            g2 = M.GBuffer(gb.pos.clone(), gb.nrm.clone(), gb.kd.clone(), gb.korm.clone(), gb.mask.clone(),
+                           gb.eye.clone(), gb.n_views, gb.height, gb.width, gb.view_base)
+            r2 = Request(scene=r.scene, gb=g2, spp=r.spp, seed=r.seed, tau=r.tau, ray_eps=r.ray_eps,
+                         g_cd=r.g_cd * 1.0, g_cs=r.g_cs * 1.0)
+            reqs.append(sysm.submit(r2))
+        del src
+        sysm.drain()
+        torch.cuda.synchronize()
+        assert len(sysm.completed) == len(reqs)
+        for a, r in zip(ref_res, reqs):
+            check_same(a, results(r))

@@ -8,6 +8,10 @@ intersects the beams of each cell's 12 edges; the room walls are planes with
 rectangular holes.  Closest hit only (primary visibility).
 """
 
+import multiprocessing
+import os
+from concurrent.futures import ProcessPoolExecutor
+
 import numpy as np
 
 from . import meshes
@@ -162,6 +166,28 @@ def cast_room(o, d):
     return t_best, nrm
 
 
+def _cast_chunk(args):
+    o, d, kx, ky, kz, cells, half = args
+    t1, n1 = cast_lattice(o, d, kx, ky, kz, cells, half)
+    t2, n2 = cast_room(o, d)
+    return t1, n1, t2, n2
+
+
+def cast_scene(o, d, kx, ky, kz, cells, half, workers=None):
+    """Closest hits against the beams and the room of every ray, in parallel
+    chunks of rays (every ray's result depends only on that ray, so the
+    chunking does not change it): (t_beams, n_beams, t_room, n_room)."""
+    n = len(d)
+    workers = workers or min(16, os.cpu_count() or 1)
+    if workers <= 1 or n < 65536:
+        return _cast_chunk((o, d, kx, ky, kz, cells, half))
+    parts = np.array_split(np.arange(n), 2 * workers)
+    ctx = multiprocessing.get_context("spawn")
+    with ProcessPoolExecutor(workers, mp_context=ctx) as ex:
+        res = list(ex.map(_cast_chunk, [(o[p], d[p], kx, ky, kz, cells, half) for p in parts]))
+    return tuple(np.concatenate([r[k] for r in res]) for k in range(4))
+
+
 def make_lattice(k=3, H=1024, W=1024, spp=32, n_views=4, cells=32, env_hw=(1024, 2048), views=None):
     rng = np.random.Generator(np.random.PCG64(1000 + k))
     half = 0.004
@@ -187,11 +213,13 @@ def make_lattice(k=3, H=1024, W=1024, spp=32, n_views=4, cells=32, env_hw=(1024,
     nrm = np.zeros((N, 3))
     mask = np.zeros(N, np.uint8)
     depth = np.zeros(N)
+    d_all = np.concatenate([look_at_rays(eye, [0, 0, 0], 60.0, H, W) for eye in eyes])
+    o_all = np.concatenate([np.broadcast_to(eye, (H * W, 3)) for eye in eyes]).astype(np.float64)
+    hits = cast_scene(o_all, d_all, kx, ky, kz, cells, half)
     for vi, eye in enumerate(eyes):
-        d = look_at_rays(eye, [0, 0, 0], 60.0, H, W)
-        o = np.broadcast_to(eye, d.shape).copy()
-        t1, n1 = cast_lattice(o, d, kx, ky, kz, cells, half)
-        t2, n2 = cast_room(o, d)
+        sl = slice(vi * H * W, (vi + 1) * H * W)
+        d, o = d_all[sl], o_all[sl]
+        t1, n1, t2, n2 = (h[sl] for h in hits)
         use1 = t1 <= t2
         t = np.where(use1, t1, t2)
         n_ = np.where(use1[:, None], n1, n2)
