@@ -332,6 +332,21 @@ mcdi_status mcdi_image_loss(const float* kd, const float* c_d, const float* c_s,
                             const uint8_t* mask, int64_t n, float w_light, float* loss, float* g_kd, float* g_cd,
                             float* g_cs, const mcdi_allocator* alloc, void* stream);
 
+/* The same image loss without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc.  Arguments, outputs and
+ * results are those of mcdi_image_loss (bit for bit: the same kernels).  The
+ * per-block partial sums live in a static device array of 1 MiB per device
+ * instead of allocated scratch, so n is limited to what it holds (about
+ * 5.2e8 pixels); a larger n returns MCDI_E_UNSUPPORTED before anything is
+ * enqueued.  Every call on one device shares that device's array: calls that
+ * overlap in time on one device (different streams or threads) race and give
+ * wrong results; calls ordered on one stream do not.  The first call on a
+ * device looks up the array's address (no allocation). */
+mcdi_status mcdi_image_loss_noalloc(const float* kd, const float* c_d, const float* c_s, const float* ref,
+                                    const uint8_t* mask, int64_t n, float w_light, float* loss, float* g_kd,
+                                    float* g_cd, float* g_cs, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Differentiable cross-bilateral denoiser (appendix B "Bilateral Denoiser"):
  * the spatial filter of SVGF evaluated densely, applied to the demodulated

@@ -314,11 +314,12 @@ def trace_times():
     return [buf[i] for i in range(n.value)]
 
 
-def image_loss(kd, c_d, c_s, ref, mask, w_light=0.15, stream=None, out=None):
+def image_loss(kd, c_d, c_s, ref, mask, w_light=0.15, stream=None, out=None, noalloc=False):
     """Loss of the composed image (kd*c_d + c_s) against ref: L1 on tonemapped
     colours + w_light * light regulariser.  Returns (loss [3] = (L_image,
     L_light, L), g_kd, g_cd, g_cs), all on the device; `out` may pass the
-    four buffers in."""
+    four buffers in.  noalloc: the library's allocation-free entry point
+    (static scratch; calls overlapping on one device race)."""
     n = mask.shape[0]
     for name, t in (("kd", kd), ("c_d", c_d), ("c_s", c_s), ("ref", ref)):
         _need(t, torch.float32, (3, n), name)
@@ -330,9 +331,14 @@ def image_loss(kd, c_d, c_s, ref, mask, w_light=0.15, stream=None, out=None):
     _need(loss, torch.float32, (3,), "loss")
     for name, t in (("g_kd", g_kd), ("g_cd", g_cd), ("g_cs", g_cs)):
         _need(t, torch.float32, (3, n), name)
-    L.check(L.lib().mcdi_image_loss(_ptr(kd), _ptr(c_d), _ptr(c_s), _ptr(ref), _ptr(mask), n, float(w_light),
-                                    _ptr(loss), _ptr(g_kd), _ptr(g_cd), _ptr(g_cs), C.byref(_TORCH_ALLOCATOR),
-                                    _stream(stream)))
+    if noalloc:
+        L.check(L.lib().mcdi_image_loss_noalloc(_ptr(kd), _ptr(c_d), _ptr(c_s), _ptr(ref), _ptr(mask), n,
+                                                float(w_light), _ptr(loss), _ptr(g_kd), _ptr(g_cd), _ptr(g_cs),
+                                                _stream(stream)))
+    else:
+        L.check(L.lib().mcdi_image_loss(_ptr(kd), _ptr(c_d), _ptr(c_s), _ptr(ref), _ptr(mask), n, float(w_light),
+                                        _ptr(loss), _ptr(g_kd), _ptr(g_cd), _ptr(g_cs), C.byref(_TORCH_ALLOCATOR),
+                                        _stream(stream)))
     return loss, g_kd, g_cd, g_cs
 
 

@@ -111,6 +111,8 @@ def lib():
     L.mcdi_server_destroy.argtypes = [vp]
     L.mcdi_image_loss.restype = C.c_int
     L.mcdi_image_loss.argtypes = [vp, vp, vp, vp, vp, C.c_int64, C.c_float, vp, vp, vp, vp, vp, vp]
+    L.mcdi_image_loss_noalloc.restype = C.c_int
+    L.mcdi_image_loss_noalloc.argtypes = [vp, vp, vp, vp, vp, C.c_int64, C.c_float, vp, vp, vp, vp, vp]
     L.mcdi_bilateral_radius.restype = C.c_int32
     L.mcdi_bilateral_radius.argtypes = [C.c_float]
     L.mcdi_bilateral_fwd.restype = C.c_int
@@ -144,6 +146,6 @@ def check(status):
 EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_scene_nodes", "mcdi_build_env_cdf",
             "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
             "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_server_create", "mcdi_server_launch",
-            "mcdi_server_destroy", "mcdi_image_loss", "mcdi_bilateral_radius", "mcdi_bilateral_fwd",
+            "mcdi_server_destroy", "mcdi_image_loss", "mcdi_image_loss_noalloc", "mcdi_bilateral_radius", "mcdi_bilateral_fwd",
             "mcdi_bilateral_bwd", "mcdi_view_depth", "mcdi_build_edges", "mcdi_destroy_edges", "mcdi_edges_count",
             "mcdi_edges_copy", "mcdi_shade_bwd_edges", "mcdi_last_error", "mcdi_version")

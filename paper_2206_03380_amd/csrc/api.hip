@@ -655,6 +655,27 @@ mcdi_status mcdi_image_loss(const float* kd, const float* c_d, const float* c_s,
     return ok();
 }
 
+mcdi_status mcdi_image_loss_noalloc(const float* kd, const float* c_d, const float* c_s, const float* ref,
+                                    const uint8_t* mask, int64_t n, float w_light, float* loss, float* g_kd,
+                                    float* g_cd, float* g_cs, void* stream) {
+    if (!kd || !c_d || !c_s || !ref || !mask || !loss)
+        return fail(MCDI_E_INVALID, "mcdi_image_loss_noalloc: NULL input");
+    if (n < 1) return fail(MCDI_E_INVALID, "mcdi_image_loss_noalloc: n must be >= 1");
+    if (n >= ((int64_t)1 << 31)) return fail(MCDI_E_UNSUPPORTED, "mcdi_image_loss_noalloc: n >= 2^31");
+    if (!std::isfinite(w_light)) return fail(MCDI_E_INVALID, "mcdi_image_loss_noalloc: w_light must be finite");
+    if (image_loss_scratch_bytes(n) > kLossStaticScratch)
+        return fail(MCDI_E_UNSUPPORTED, "mcdi_image_loss_noalloc: n = %lld needs %zu bytes of scratch, above the "
+                    "static %zu", (long long)n, image_loss_scratch_bytes(n), kLossStaticScratch);
+    // the current device's static scratch: no allocation; every entry the
+    // kernels read is written earlier in the same call, so nothing is cleared
+    void* scratch = nullptr;
+    hipError_t e = image_loss_static_scratch(&scratch);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_image_loss_noalloc: %s", hipGetErrorString(e));
+    e = launch_image_loss(kd, c_d, c_s, ref, mask, n, w_light, loss, g_kd, g_cd, g_cs, scratch, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_image_loss_noalloc: %s", hipGetErrorString(e));
+    return ok();
+}
+
 static mcdi_status bilat_args(const char* who, const mcdi_bilateral_guide* g, int32_t nc, BilatArgs& a) {
     if (!g) return fail(MCDI_E_INVALID, "%s: NULL guide", who);
     if (g->n_views < 0 || g->height < 0 || g->width < 0)

@@ -19,7 +19,16 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "mcdi_internal.h"
+
+// Scratch of the allocation-free entry point (mcdi_image_loss_noalloc): the
+// per-block FP64 partial sums and the per-block mask counts of one call.
+// Each device that loads the library holds its own copy until the process
+// ends.  Host code never passes this name to a kernel: in host code it is a
+// stand-in, and the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[mcdi::kLossStaticScratch];
 
 namespace mcdi {
 namespace {
@@ -185,6 +194,28 @@ int loss_blocks(int64_t n) {
 int64_t count_blocks(int64_t n) { return (n + kCountPx - 1) / kCountPx; }
 
 }  // namespace
+
+namespace {
+std::mutex g_static_mu;
+void* g_static_ptr[kLossStaticDevices] = {};
+}  // namespace
+
+hipError_t image_loss_static_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kLossStaticDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        // the current device's copy of the array (once per device)
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return hipSuccess;
+}
 
 size_t image_loss_scratch_bytes(int64_t n) {
     return sizeof(long long) * (size_t)count_blocks(n) + sizeof(double) * 2 * (size_t)loss_blocks(n) + 256;

@@ -159,6 +159,13 @@ hipError_t launch_env_scatter_init(const EnvScatter& p, hipStream_t s);
 hipError_t launch_env_scatter(const EnvScatter& p, hipStream_t s);
 
 size_t image_loss_scratch_bytes(int64_t n);
+// Static scratch of the allocation-free image loss: 1 MiB per device, enough
+// for image_loss_scratch_bytes(n) up to n of about 5.2e8 pixels.
+constexpr size_t kLossStaticScratch = (size_t)1 << 20;
+constexpr int kLossStaticDevices = 64;
+// Device address of the current device's static scratch (looked up once per
+// device, kept for the process).
+hipError_t image_loss_static_scratch(void** out);
 hipError_t launch_image_loss(const float* kd, const float* cd, const float* cs, const float* ref,
                              const uint8_t* mask, int64_t n, float w_light, float* loss, float* g_kd, float* g_cd,
                              float* g_cs, void* scratch, hipStream_t s);
