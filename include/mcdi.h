@@ -182,6 +182,10 @@ typedef struct {
  * zero sampling weight. */
 #define MCDI_FLAG_BILINEAR    (1u << 4)
 #define MCDI_FLAG_DUMP        (1u << 8) /* write per-sample decision records */
+/* With MCDI_FLAG_DUMP: each record also holds the two sampled world
+ * directions (FP32 bits; NaN where the technique drew none), 9 words instead
+ * of 3 -- the parity protocol compares them with the oracle's. */
+#define MCDI_FLAG_DUMP_DIRS   (1u << 10)
 #define MCDI_FLAG_TIME_TRACE  (1u << 9) /* bracket the traversal kernel with HIP events */
 
 typedef struct {
@@ -190,7 +194,9 @@ typedef struct {
     uint64_t seed;          /* Philox4x32-10 key */
     float tau;              /* shadow weight: H = 1 - tau on hit (appendix A) */
     float ray_eps;          /* shadow-ray origin offset along the normal (world units) */
-    uint32_t* decisions;    /* device [N][spp][3] when MCDI_FLAG_DUMP, else NULL */
+    uint32_t* decisions;    /* device [N][spp][3] when MCDI_FLAG_DUMP ([N][spp][9] with
+                               MCDI_FLAG_DUMP_DIRS: words 3-5 and 6-8 the light and BSDF
+                               samples' world directions), else NULL */
 } mcdi_params;
 
 /* Device-side counters, accumulated (+=) by every call that receives them.

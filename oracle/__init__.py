@@ -50,7 +50,9 @@ class GBuf(C.Structure):
 class Params(C.Structure):
     _fields_ = [("spp", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64), ("tau", C.c_double),
                 ("ray_eps", C.c_double), ("delta_vis_abs", C.c_double), ("delta_vis_rel", C.c_double),
-                ("delta_ang", C.c_double), ("delta_cos", C.c_double), ("brute", C.c_int32)]
+                ("delta_ang", C.c_double), ("delta_cos", C.c_double), ("brute", C.c_int32),
+                ("dir_light", C.c_double), ("dir_cos", C.c_double), ("dir_ggx0", C.c_double),
+                ("dir_ggx1", C.c_double), ("dir_arg", C.c_double)]
 
 
 def lib():
@@ -67,7 +69,7 @@ def lib():
         L.orc_env_tables.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
         L.orc_shade.restype = C.c_int64
         L.orc_shade.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, vp, vp, C.c_int, vp, vp, vp, vp, vp,
-                                vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int]
+                                vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp, vp, C.c_int]
         L.orc_batch_philox.argtypes = [C.c_int64, vp, vp, vp]
         L.orc_batch_uniforms.argtypes = [C.c_int64, C.c_uint64, vp, vp, vp, vp]
         L.orc_batch_sample_light.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -238,10 +240,25 @@ class Tolerances:
     margin is below these (visibility: absolute and relative edge distance;
     texel boundaries: radians of arc; signs of n.v and n.l: cosine) is
     undecided in FP32, so the oracle adopts the kernel's dumped decision
-    there or flags it."""
+    there or flags it.
 
-    def __init__(self, vis_abs=1e-5, vis_rel=1e-5, ang=2e-5, cos=1e-5):
+    dir: the direction-error model of an FP32 evaluation of the sampling
+    chains, a dict of counts in units of u = 2^-24 (keys light, cos, ggx0,
+    ggx1, arg; see orc_params in mcdi_oracle.c), or None.  With it the oracle
+    reports, per output, the conditioning of its terms in their sampled
+    directions (`<name>_cond`), widens the texel and horizon decisions by twice
+    each sample's bound, and bounds the bilinear lookup's coordinate error by
+    it.  Without it no conditioning is computed."""
+
+    def __init__(self, vis_abs=1e-5, vis_rel=1e-5, ang=2e-5, cos=1e-5, dir=None):
         self.vis_abs, self.vis_rel, self.ang, self.cos = vis_abs, vis_rel, ang, cos
+        self.dir = dict(dir) if dir else None
+
+    def params(self, spp, flags, seed, tau, ray_eps, brute):
+        d = self.dir or {}
+        return Params(spp, flags, seed, tau, ray_eps, self.vis_abs, self.vis_rel, self.ang, self.cos, int(brute),
+                      float(d.get("light", 0.0)), float(d.get("cos", 0.0)), float(d.get("ggx0", 0.0)),
+                      float(d.get("ggx1", 0.0)), float(d.get("arg", 0.0)))
 
 
 def _gbuf_struct(w, arrays):
@@ -259,13 +276,19 @@ def _gb_arrays(w, override=None):
 
 def shade(w, pixels=None, scene=None, tables=None, spp=None, seed=None, tau=None, ray_eps=None,
           flags=0, grad=False, u_d=None, u_s=None, sync=None, eval_override=None, env_eval=None,
-          tol=None, brute=False, threads=0, want_decisions=False):
+          tol=None, brute=False, threads=0, want_decisions=False, want_dirs=False):
     """Run the oracle forward (grad=False) or backward (grad=True) on the
     listed pixels of workload `w` (all pixels if None).
 
     eval_override: dict of G-buffer arrays replacing the evaluation-side
     inputs (the frozen-sample finite-difference hook); env_eval likewise for
-    the probe radiance.  Returns a dict of FP64 arrays in pixel-list order."""
+    the probe radiance.  Returns a dict of FP64 arrays in pixel-list order:
+    the outputs, and per output `<name>_abs` (sum of the absolute values of
+    the summands of its terms), `<name>_cond` (conditioning of its terms in
+    their sampled directions; 0 without a direction model in `tol`) and
+    `<name>_lerr` (bound on the radiance lookup's own FP32 error); with
+    want_dirs, `dirs` [n, spp, 2, 4]: each sample's direction (light, then
+    BSDF technique) and its direction-error bound, NaN where none was drawn."""
     L = lib()
     spp = w.spp if spp is None else spp
     seed = w.seed if seed is None else seed
@@ -284,7 +307,7 @@ def shade(w, pixels=None, scene=None, tables=None, spp=None, seed=None, tau=None
         ge_arr = _gb_arrays(w, eval_override)
         ge = _gbuf_struct(w, ge_arr)
     env_ev = _c(env_eval, np.float32) if env_eval is not None else None
-    prm = Params(spp, flags, seed, tau, ray_eps, tol.vis_abs, tol.vis_rel, tol.ang, tol.cos, int(brute))
+    prm = tol.params(spp, flags, seed, tau, ray_eps, brute)
     hw = (2 * spp + 31) // 32
     out = {"c_d": np.zeros((3, n)), "c_s": np.zeros((3, n)), "hitbits": np.zeros((n, hw), np.uint32),
            "info": np.zeros((n, 3), np.int32)}
@@ -297,27 +320,25 @@ def shade(w, pixels=None, scene=None, tables=None, spp=None, seed=None, tau=None
         out.update(g_kd=np.zeros((3, n)), g_korm=np.zeros((3, n)), g_nrm=np.zeros((3, n)),
                    g_env=np.zeros(tables.env.shape), s_env=np.zeros(tables.env.shape),
                    c_env=np.zeros(tables.env.shape), l_env=np.zeros(tables.env.shape))
-    vcond = np.zeros((30, n))
+    vaux = np.zeros((3, 15, n))
+    dirs = np.zeros((n, spp, 2, 4)) if want_dirs else None
     r = L.orc_shade(scene.ptr, C.byref(tables.struct), _p(env_ev), C.byref(gs),
                     C.byref(ge) if ge is not None else None, _p(pixels), n, C.byref(prm),
-                    _p(sync_arr), int(grad), _p(ud), _p(us), _p(out["c_d"]), _p(out["c_s"]), _p(vcond),
+                    _p(sync_arr), int(grad), _p(ud), _p(us), _p(out["c_d"]), _p(out["c_s"]), _p(vaux),
                     _p(out.get("g_kd")), _p(out.get("g_korm")), _p(out.get("g_nrm")),
                     _p(out.get("g_env")), _p(out.get("s_env")), _p(out.get("c_env")), _p(out.get("l_env")),
-                    _p(out["hitbits"]), hw, _p(dec),
+                    _p(out["hitbits"]), hw, _p(dec), _p(dirs),
                     _p(out["info"]), int(threads))
     if r < 0:
         raise ValueError("oracle rejected the parameters (spp must be in [1, 1024])")
     out["nonfinite"] = int(r)
-    # sum over the pixel's samples of |term| * 2^-24 / (n.l), per channel:
-    # the FP32 conditioning of each output in the sampled directions
-    out["c_d_cond"], out["c_s_cond"] = vcond[0:3], vcond[3:6]
-    out["g_kd_cond"], out["g_korm_cond"], out["g_nrm_cond"] = vcond[6:9], vcond[9:12], vcond[12:15]
-    # absolute bound on the FP32 error entering through the radiance lookup
-    # (bilinear coordinates and tap sums; zero for the nearest texel)
-    out["c_d_lerr"], out["c_s_lerr"] = vcond[15:18], vcond[18:21]
-    out["g_kd_lerr"], out["g_korm_lerr"], out["g_nrm_lerr"] = vcond[21:24], vcond[24:27], vcond[27:30]
+    for kind, suffix in enumerate(("_abs", "_cond", "_lerr")):
+        for k, name in enumerate(("c_d", "c_s", "g_kd", "g_korm", "g_nrm")):
+            out[name + suffix] = vaux[kind, 3 * k:3 * k + 3]
     if dec is not None:
         out["decisions"] = dec
+    if dirs is not None:
+        out["dirs"] = dirs
     return out
 
 
@@ -330,7 +351,7 @@ def integrand(w, pixel, dirs, scene=None, tables=None, tau=None, ray_eps=None, b
     gs = _gbuf_struct(w, arr)
     tau = w.tau if tau is None else tau
     ray_eps = w.ray_eps if ray_eps is None else ray_eps
-    prm = Params(1, flags & BILINEAR, 0, tau, ray_eps, 0.0, 0.0, 0.0, 0.0, int(brute))
+    prm = Tolerances(0.0, 0.0, 0.0, 0.0).params(1, flags & BILINEAR, 0, tau, ray_eps, brute)
     dirs = _c(dirs, np.float64).reshape(-1, 3)
     gd, gsp = np.empty((len(dirs), 3)), np.empty((len(dirs), 3))
     lib().orc_integrand(scene.ptr, C.byref(tables.struct), C.byref(gs), int(pixel), C.byref(prm),
@@ -406,7 +427,7 @@ def edge_grad(w, edges, n_es, u_d, u_s, pixels=None, scene=None, tables=None, se
     tables = tables or EnvTables(w.env)
     arr = _gb_arrays(w)
     gs = _gbuf_struct(w, arr)
-    prm = Params(1, flags, seed, tau, ray_eps, tol.vis_abs, tol.vis_rel, tol.ang, tol.cos, int(brute))
+    prm = tol.params(1, flags, seed, tau, ray_eps, brute)
     edges = _c(edges, np.int32).reshape(-1, 4)
     verts = _c(w.verts, np.float32)
     nv = len(verts)

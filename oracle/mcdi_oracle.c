@@ -421,11 +421,19 @@ void orc_sample_cos_local(double u1, double u2, double L[3])
     L[2] = sqrt(fmax(0.0, 1.0 - u1));
 }
 
+/* Intermediates of one visible-normal sample that decide how much FP32
+ * roundoff its direction can carry: g = 1 - t1^2 and h = 1 - t1^2 - t2^2 (the
+ * arguments of the two square roots), the blend weight s and the length of
+ * the un-stretched normal before normalisation. */
+typedef struct {
+    double g, h, s, mlen;
+} vndf_aux;
+
 /* Visible-normal sampling of GGX (Heitz, JCGT 2018): stretch the view vector,
  * sample the projected visible hemisphere, un-stretch the normal, reflect.
  * Returns lensq of the stretched view's tangential part (the degenerate-frame
- * decision). */
-double orc_sample_vndf_local(const double V[3], double alpha, double u1, double u2, double L[3])
+ * decision); aux (may be NULL) receives the intermediates above. */
+static double sample_vndf_aux(const double V[3], double alpha, double u1, double u2, double L[3], vndf_aux* aux)
 {
     double vh[3] = {alpha * V[0], alpha * V[1], V[2]};
     double l = norm3(vh);
@@ -444,8 +452,10 @@ double orc_sample_vndf_local(const double V[3], double alpha, double u1, double 
     double r = sqrt(u1), ph = 2.0 * ORC_PI * u2;
     double t1 = r * cos(ph), t2 = r * sin(ph);
     double s = 0.5 * (1.0 + vh[2]);
-    t2 = (1.0 - s) * sqrt(fmax(0.0, 1.0 - t1 * t1)) + s * t2;
-    double tz = sqrt(fmax(0.0, 1.0 - t1 * t1 - t2 * t2));
+    const double g = 1.0 - t1 * t1;
+    t2 = (1.0 - s) * sqrt(fmax(0.0, g)) + s * t2;
+    const double h = 1.0 - t1 * t1 - t2 * t2;
+    double tz = sqrt(fmax(0.0, h));
     double nh[3];
     for (int k = 0; k < 3; ++k) nh[k] = t1 * T1[k] + t2 * T2[k] + tz * vh[k];
     double ne[3] = {alpha * nh[0], alpha * nh[1], fmax(0.0, nh[2])};
@@ -453,42 +463,18 @@ double orc_sample_vndf_local(const double V[3], double alpha, double u1, double 
     for (int k = 0; k < 3; ++k) ne[k] /= nl;
     double vn = dot3(V, ne);
     for (int k = 0; k < 3; ++k) L[k] = 2.0 * vn * ne[k] - V[k];
+    if (aux) {
+        aux->g = g;
+        aux->h = h;
+        aux->s = s;
+        aux->mlen = nl;
+    }
     return lensq;
 }
 
-/* The same visible-normal sampling steps in FP32 arithmetic.  Not used for
- * any value: the distance between its direction and the FP64 one measures
- * how much roundoff the sampling chain lets into the direction for this
- * sample (the square root near the rim of the stretched hemisphere and the
- * unstretching amplify it), which sets the sample's tolerance. */
-static void sample_vndf_local_f32(const double V[3], double alpha, double u1, double u2, float L[3])
+double orc_sample_vndf_local(const double V[3], double alpha, double u1, double u2, double L[3])
 {
-    const float a = (float)alpha;
-    float vh[3] = {a * (float)V[0], a * (float)V[1], (float)V[2]};
-    const float l = sqrtf(vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2]);
-    for (int k = 0; k < 3; ++k) vh[k] /= l;
-    const float lensq = vh[0] * vh[0] + vh[1] * vh[1];
-    float T1[3] = {1.0f, 0.0f, 0.0f}, T2[3];
-    if (lensq > 0.0f) {
-        const float il = 1.0f / sqrtf(lensq);
-        T1[0] = -vh[1] * il;
-        T1[1] = vh[0] * il;
-    }
-    T2[0] = vh[1] * T1[2] - vh[2] * T1[1];
-    T2[1] = vh[2] * T1[0] - vh[0] * T1[2];
-    T2[2] = vh[0] * T1[1] - vh[1] * T1[0];
-    const float r = sqrtf((float)u1), ph = 2.0f * (float)ORC_PI * (float)u2;
-    float t1 = r * cosf(ph), t2 = r * sinf(ph);
-    const float s = 0.5f * (1.0f + vh[2]);
-    t2 = (1.0f - s) * sqrtf(fmaxf(0.0f, 1.0f - t1 * t1)) + s * t2;
-    const float tz = sqrtf(fmaxf(0.0f, 1.0f - t1 * t1 - t2 * t2));
-    float nh[3];
-    for (int k = 0; k < 3; ++k) nh[k] = t1 * T1[k] + t2 * T2[k] + tz * vh[k];
-    float ne[3] = {a * nh[0], a * nh[1], fmaxf(0.0f, nh[2])};
-    const float nl = sqrtf(ne[0] * ne[0] + ne[1] * ne[1] + ne[2] * ne[2]);
-    for (int k = 0; k < 3; ++k) ne[k] /= nl;
-    const float vn = (float)V[0] * ne[0] + (float)V[1] * ne[1] + (float)V[2] * ne[2];
-    for (int k = 0; k < 3; ++k) L[k] = 2.0f * vn * ne[k] - (float)V[k];
+    return sample_vndf_aux(V, alpha, u1, u2, L, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -752,6 +738,18 @@ typedef struct {
     double delta_ang;                    /* texel-boundary tolerance, radians of arc */
     double delta_cos;                    /* tolerance on n.v / n.l sign decisions */
     int32_t brute;                       /* all-triangle visibility instead of the BVH */
+    /* Direction-error model of the parity protocol, in units of u = 2^-24
+     * (all 0: no conditioning is computed).  An FP32 evaluation of a
+     * sampling chain moves the sampled direction by at most
+     *   light    dir_light u
+     *   cosine   dir_cos u
+     *   GGX      (dir_ggx0 + dir_ggx1 (1 + (1 - s) A(g)) (1 + A(h)) / |m|) u
+     * where A(x) = 1 / (sqrt(x + dir_arg u) + sqrt(x)) is how much the square
+     * root amplifies an absolute error of its argument x, g and h are the
+     * arguments of the two square roots of the visible-normal warp, s its
+     * blend weight and |m| the length of the un-stretched normal (the
+     * normalisation divides the error by it). */
+    double dir_light, dir_cos, dir_ggx0, dir_ggx1, dir_arg;
 } orc_params;
 
 /* flags: technique subsets of the estimator (the sampling ablation of
@@ -841,17 +839,28 @@ static float lobe_q(const pix_setup* S, float m_f, uint32_t flags)
     return q;
 }
 
+/* Per-sample terms and per-pixel accumulators.  The outputs of a pixel are
+ * sums over its samples of terms; each term is itself a sum of products, and
+ * the FP32 error of evaluating it is bounded by a small multiple of u times
+ * the sum of the absolute values of those summands (`abs`).  The normal
+ * gradient is kept in the pixel's tangent frame (t, b): the gradient with
+ * respect to the unnormalised normal lies in the tangent plane. */
+enum { T_CD = 0, T_CS = 3, T_GKD = 6, T_GR = 9, T_GM = 10, T_GNT = 11, T_GNB = 12, T_COEF = 13, T_N = 16 };
+#define O_N T_COEF /* per-pixel accumulated terms: all but the probe coefficients */
+
 typedef struct {
-    /* outputs of one pixel */
-    double cd[3], cs[3];
-    double cd_cond[3], cs_cond[3]; /* sum |term| * u / (n.l): FP32 conditioning of the values */
-    double gkd[3], gr, gm, gn[3];
-    double gkd_cond[3], gr_cond, gm_cond, gn_cond; /* the same for the gradient terms */
-    /* absolute bound on the FP32 error that enters through the radiance
-     * lookup itself (bilinear coordinates and tap sums; 0 for the nearest
-     * texel), per output */
-    double cd_lerr[3], cs_lerr[3], gkd_lerr[3], gr_lerr, gm_lerr, gn_lerr;
-    double nlen_cond;                              /* |n_raw|, for the normal's projection */
+    double v[T_N]; /* the terms */
+    double a[T_N]; /* sums of the absolute values of their summands */
+} sample_terms;
+
+typedef struct {
+    /* outputs of one pixel, in the term layout above */
+    double val[O_N];
+    double abs[O_N];  /* sum over samples of the summands' absolute values */
+    double cond[O_N]; /* sum over samples of |d term / d direction| times the sample's direction-error bound */
+    double lerr[O_N]; /* absolute bound on the FP32 error entering through the radiance lookup itself
+                         (bilinear coordinates and tap sums; 0 for the nearest texel) */
+    double t[3], b[3], nlen; /* tangent frame and |n_raw| of the evaluation side */
     uint32_t hitbits[64]; /* 2 bits per sample, spp <= 1024 */
     int n_synced, n_flag, n_hard;
 } pix_out;
@@ -860,19 +869,21 @@ typedef struct {
     int32_t texel;
     double coef[3];
     double absc[3];
-    double cond[3]; /* |term| * u / (n.l), u = 2^-24: FP32 conditioning in the cosine */
+    double cond[3]; /* |d coef / d direction| times the direction-error bound */
     int bil;        /* bilinear: the coefficient spreads over the tent taps around (x, y) */
     double x, y;    /* continuous texel coordinates of the sample */
     double dx, dy;  /* bound on the FP32 error of (x, y), in texels */
 } env_contrib;
 
-/* Per-sample evaluation at direction w.  `Ss` drives sampling-side
- * quantities (P, q, ray origin); `Se` the differentiated integrand. */
-static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, const double w[3],
-                        double pL, const double* Lv, const double* dLv, int spp, double Hv, int grad,
-                        const double* Ud, const double* Us, pix_out* out, env_contrib* ec,
-                        double bsdf_w, double e_scale, int unit_pdf)
+/* The terms of one sample at direction w.  `Ss` drives sampling-side
+ * quantities (P, q), `Se` the differentiated integrand (they differ only in
+ * the frozen-sample finite-difference hook).  pL is the light technique's
+ * density at w, L the radiance.  unit_pdf: P = 1 (the bare integrand). */
+static void terms_at(const pix_setup* Ss, const pix_setup* Se, double q, const double w[3], double pL,
+                     const double* Lv, int spp, double Hv, int grad, const double* Ud, const double* Us,
+                     double bsdf_w, int unit_pdf, sample_terms* T)
 {
+    memset(T, 0, sizeof(*T));
     double NoL = dot3(Se->n, w);
     double h[3] = {Se->V[0] + w[0], Se->V[1] + w[1], Se->V[2] + w[2]};
     double hl = norm3(h);
@@ -884,35 +895,25 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
     for (int k = 0; k < 3; ++k) hs[k] /= hsl;
     double nxh[3];
     cross3(Ss->n, hs, nxh);
-    double q = (double)qf;
     double pcos = NoLs > 0.0 ? NoLs / ORC_PI : 0.0;
-    double pggx = 0.0, kD = 0.0;
+    double pggx = 0.0;
     if (Ss->nov_pos) {
-        double s2s = dot3(nxh, nxh), a = Ss->alpha;
-        double Ds = orc_ggx_D(dot3(Ss->n, hs), s2s, a);
+        double a = Ss->alpha;
+        double Ds = orc_ggx_D(dot3(Ss->n, hs), dot3(nxh, nxh), a);
         pggx = Ds / (1.0 + orc_ggx_lambda(Ss->NoV, a)) / (4.0 * Ss->NoV);
-        /* |d ln D / d w| per unit of direction error: D = a^2 / (pi B^2) with
-         * B = a^2 + (1 - a^2)|n x h|^2, and |d|n x h|^2| <= |n x h| |dw| / (v.h) */
-        double B = a * a + (1.0 - a * a) * s2s;
-        double voh = fabs(dot3(Ss->V, hs));
-        kD = 2.0 * (1.0 - a * a) * sqrt(s2s) / (B * fmax(voh, 1e-30));
     }
     /* balance heuristic over the techniques in use: light (density pL, 0
      * when off) and the BSDF mixture (weight 0 when off) */
     double P = unit_pdf ? 1.0 : pL + bsdf_w * (q * pcos + (1.0 - q) * pggx);
     double K = Hv / (P * (double)spp);
-    /* FP32 conditioning of a term in the sampled direction, per unit
-     * roundoff: its log-derivative through n.l (<= 2 / n.l, counted as
-     * 1 / n.l against a factor 2 in the bound) and through the GGX share of P */
-    double cu = 0x1p-24 * e_scale * (1.0 / fmax(fabs(NoL), 1e-30) +
-                                     (unit_pdf ? 0.0 : 0.5 * bsdf_w * (1.0 - q) * pggx * kD / P));
     /* diffuse, demodulated (kd applied outside): (1-m)/pi * NoL * L */
     double kdiff = (1.0 - Se->m) / ORC_PI * NoL * K;
-    /* specular: F D G2 / (4 NoV) * L, NoL cancelled */
-    double S = 0.0, Fw = 0.0, dSdr = 0.0, dSdNoV = 0.0, dSdNoL = 0.0, dSdNoH = 0.0;
+    /* specular: F D G2 / (4 NoV) * L, NoL cancelled; the _a values are the
+     * sums of the absolute values of the summands of each difference */
+    double S = 0.0, Fw = 0.0, dSdr = 0.0, dSdr_a = 0.0, dSdNoV = 0.0, dSdNoV_a = 0.0, dSdNoL = 0.0,
+           dSdNoH = 0.0;
     double F[3] = {0, 0, 0};
-    int spec = Ss->nov_pos;
-    if (spec) {
+    if (Ss->nov_pos) {
         double a = Se->alpha, NoV = Se->NoV, NoH = dot3(Se->n, h), VoH = dot3(Se->V, h);
         cross3(Se->n, h, nxh);
         double s2 = dot3(nxh, nxh);
@@ -926,68 +927,139 @@ static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, cons
         if (grad) {
             double B = a * a * NoH * NoH + s2;
             double dDda = D * (2.0 / a - 4.0 * a * NoH * NoH / B);
-            double dG2da = -G2 * G2 * (lambda_dalpha(NoV, a) + lambda_dalpha(NoL, a));
-            double dSda = (dDda * G2 + D * dG2da) / (4.0 * NoV);
+            double dDda_a = D * (2.0 / a + 4.0 * a * NoH * NoH / B);
+            double dlv = lambda_dalpha(NoV, a), dll = lambda_dalpha(NoL, a);
+            double dSda = (dDda * G2 - D * G2 * G2 * (dlv + dll)) / (4.0 * NoV);
+            double dSda_a = (dDda_a * G2 + D * G2 * G2 * (fabs(dlv) + fabs(dll))) / (4.0 * NoV);
             dSdr = Se->r_active ? dSda * 2.0 * Se->r : 0.0;
+            dSdr_a = Se->r_active ? dSda_a * 2.0 * fabs(Se->r) : 0.0;
             double dDdc = D * 4.0 * (1.0 - a * a) * NoH / B;
             double dG2dV = -G2 * G2 * lambda_dx(NoV, a);
             double dG2dL = -G2 * G2 * lambda_dx(NoL, a);
             dSdNoV = D * dG2dV / (4.0 * NoV) - S / NoV;
+            dSdNoV_a = fabs(D * dG2dV / (4.0 * NoV)) + fabs(S / NoV);
             dSdNoL = D * dG2dL / (4.0 * NoV);
             dSdNoH = dDdc * G2 / (4.0 * NoV);
         }
     }
-    /* every term is linear in the radiance L_c: its conditioning is the
-     * coefficient times |L_c| cu (direction roundoff through n.l and P), and
-     * its lookup error the coefficient times the bound dLv on the radiance's
-     * own FP32 error */
-    double Lc[3];
-    for (int c = 0; c < 3; ++c) Lc[c] = fabs(Lv[c]) * cu;
     for (int c = 0; c < 3; ++c) {
-        double L = Lv[c];
-        out->cd[c] += kdiff * L;
-        out->cs[c] += F[c] * S * L * K;
-        /* a sampled direction carries an absolute FP32 error of a few ulp:
-         * relative to n.l it is amplified where the sample grazes */
-        out->cd_cond[c] += fabs(kdiff) * Lc[c];
-        out->cs_cond[c] += fabs(F[c] * S * K) * Lc[c];
-        out->cd_lerr[c] += fabs(kdiff) * dLv[c];
-        out->cs_lerr[c] += fabs(F[c] * S * K) * dLv[c];
+        const double L = Lv[c];
+        T->v[T_CD + c] = kdiff * L;
+        T->a[T_CD + c] = fabs(kdiff * L);
+        T->v[T_CS + c] = F[c] * S * K * L;
+        T->a[T_CS + c] = fabs(F[c] * S * K * L);
     }
     if (!grad) return;
-    double gnd = 0.0, gns = 0.0, gnd_a = 0.0, gns_a = 0.0, gnd_e = 0.0, gns_e = 0.0;
+    double gnd = 0.0, gns = 0.0, gnd_a = 0.0, gns_a = 0.0;
     for (int c = 0; c < 3; ++c) {
-        double L = Lv[c];
-        double cdc = kdiff, csc = F[c] * S * K; /* coefficients of L_c */
+        const double L = Lv[c];
         const double akd = Us[c] * Se->m * (1.0 - Fw) * S * K;
-        const double am1 = Ud[c] * (-NoL / ORC_PI) * K, am2 = Us[c] * (Se->kd[c] - 0.04) * (1.0 - Fw) * S * K;
-        const double ar = Us[c] * F[c] * K * dSdr;
-        out->gkd[c] += akd * L;
-        out->gm += am1 * L + am2 * L;
-        out->gr += ar * L;
-        out->gkd_cond[c] += fabs(akd) * Lc[c];
-        out->gm_cond += (fabs(am1) + fabs(am2)) * Lc[c];
-        out->gr_cond += fabs(ar) * Lc[c];
-        out->gkd_lerr[c] += fabs(akd) * dLv[c];
-        out->gm_lerr += (fabs(am1) + fabs(am2)) * dLv[c];
-        out->gr_lerr += fabs(ar) * dLv[c];
+        const double am1 = Ud[c] * (-NoL / ORC_PI) * K;
+        const double am2 = Us[c] * (Se->kd[c] - 0.04) * (1.0 - Fw) * S * K;
+        const double am2_a = fabs(Us[c]) * (fabs(Se->kd[c]) + 0.04) * (1.0 - Fw) * S * fabs(K);
+        T->v[T_GKD + c] = akd * L;
+        T->a[T_GKD + c] = fabs(akd * L);
+        T->v[T_GM] += am1 * L + am2 * L;
+        T->a[T_GM] += fabs(am1 * L) + am2_a * fabs(L);
+        T->v[T_GR] += Us[c] * F[c] * K * dSdr * L;
+        T->a[T_GR] += fabs(Us[c] * F[c] * K * L) * dSdr_a;
         gnd += Ud[c] * (1.0 - Se->m) / ORC_PI * L * K;
         gns += Us[c] * F[c] * L * K;
-        gnd_a += fabs(Ud[c] * (1.0 - Se->m) / ORC_PI * K) * Lc[c];
-        gns_a += fabs(Us[c] * F[c] * K) * Lc[c];
-        gnd_e += fabs(Ud[c] * (1.0 - Se->m) / ORC_PI * K) * dLv[c];
-        gns_e += fabs(Us[c] * F[c] * K) * dLv[c];
-        ec->coef[c] = Ud[c] * cdc + Us[c] * csc;
-        ec->absc[c] = fabs(Ud[c] * cdc) + fabs(Us[c] * csc);
-        ec->cond[c] = ec->absc[c] * cu;
+        gnd_a += fabs(Ud[c] * (1.0 - Se->m) / ORC_PI * L * K);
+        gns_a += fabs(Us[c] * F[c] * L * K);
+        T->v[T_COEF + c] = Ud[c] * kdiff + Us[c] * F[c] * S * K;
+        T->a[T_COEF + c] = fabs(Ud[c] * kdiff) + fabs(Us[c] * F[c] * S * K);
     }
-    for (int k = 0; k < 3; ++k) {
-        const double t = gnd * w[k] + gns * (dSdNoV * Se->V[k] + dSdNoL * w[k] + dSdNoH * h[k]);
-        out->gn[k] += t;
-        out->gn_cond += gnd_a * fabs(w[k]) +
-                        gns_a * (fabs(dSdNoV * Se->V[k]) + fabs(dSdNoL * w[k]) + fabs(dSdNoH * h[k]));
-        out->gn_lerr += gnd_e * fabs(w[k]) +
-                        gns_e * (fabs(dSdNoV * Se->V[k]) + fabs(dSdNoL * w[k]) + fabs(dSdNoH * h[k]));
+    /* d/dn of the sample (the view and half vectors held fixed), in the
+     * tangent frame: gnd w + gns (dS/dNoV V + dS/dNoL w + dS/dNoH h) */
+    const double* fr[2] = {Se->t, Se->b};
+    for (int d = 0; d < 2; ++d) {
+        const double wt = dot3(w, fr[d]), vt = dot3(Se->V, fr[d]), ht = dot3(h, fr[d]);
+        T->v[T_GNT + d] = gnd * wt + gns * (dSdNoV * vt + dSdNoL * wt + dSdNoH * ht);
+        T->a[T_GNT + d] = gnd_a * fabs(wt) +
+                          gns_a * (dSdNoV_a * fabs(vt) + fabs(dSdNoL * wt) + fabs(dSdNoH * ht));
+    }
+}
+
+/* unit vectors e1, e2 orthogonal to the unit vector w and to each other */
+static void tangent_pair(const double w[3], double e1[3], double e2[3])
+{
+    const double a[3] = {1.0, 0.0, 0.0}, b[3] = {0.0, 1.0, 0.0};
+    cross3(w, fabs(w[0]) < 0.9 ? a : b, e1);
+    const double l = norm3(e1);
+    for (int k = 0; k < 3; ++k) e1[k] /= l;
+    cross3(w, e1, e2);
+}
+
+/* Per-sample evaluation at direction w: accumulates the terms, the sums of
+ * their summands' magnitudes, their conditioning in the direction and their
+ * lookup error into `out`, and fills the probe-gradient contribution.
+ *   pL      the light technique's density at w (0 when off or none)
+ *   pl_num  its numerator pdf_uv / (2 pi^2): the density at a nearby direction
+ *           w' of the same texel is pl_num / sin(theta(w'))
+ *   e_dir   the sample's direction-error bound (radians; 0: no conditioning).
+ *           The conditioning of each term is |grad_w term| e_dir, with the
+ *           gradient over the directions orthogonal to w taken by central
+ *           differences (texel, radiance and visibility held fixed).
+ * unit_pdf (the bare integrand): P = 1 and the conditioning is the old
+ * one-ulp measure |term| u / |n.l|. */
+static void eval_sample(const pix_setup* Ss, const pix_setup* Se, float qf, const double w[3], double pL,
+                        double pl_num, const double* Lv, const double* dLv, int spp, double Hv, int grad,
+                        const double* Ud, const double* Us, pix_out* out, env_contrib* ec, double bsdf_w,
+                        double e_dir, int unit_pdf)
+{
+    const double q = (double)qf;
+    sample_terms T;
+    terms_at(Ss, Se, q, w, pL, Lv, spp, Hv, grad, Ud, Us, bsdf_w, unit_pdf, &T);
+    double cond[T_N] = {0};
+    if (unit_pdf) {
+        const double cu = 0x1p-24 / fmax(fabs(dot3(Se->n, w)), 1e-30);
+        for (int i = 0; i < T_N; ++i) cond[i] = T.a[i] * cu;
+    } else if (e_dir > 0.0) {
+        const double eps = 1e-6;
+        double e[2][3], g2[T_N] = {0};
+        tangent_pair(w, e[0], e[1]);
+        for (int d = 0; d < 2; ++d) {
+            sample_terms Tp[2];
+            for (int sg = 0; sg < 2; ++sg) {
+                double wp[3];
+                for (int k = 0; k < 3; ++k) wp[k] = w[k] + (sg ? -eps : eps) * e[d][k];
+                const double l = norm3(wp);
+                for (int k = 0; k < 3; ++k) wp[k] /= l;
+                const double rho = sqrt(wp[0] * wp[0] + wp[2] * wp[2]);
+                const double pLp = (pl_num > 0.0 && rho > 0.0) ? pl_num / rho : 0.0;
+                terms_at(Ss, Se, q, wp, pLp, Lv, spp, Hv, grad, Ud, Us, bsdf_w, unit_pdf, &Tp[sg]);
+            }
+            for (int i = 0; i < T_N; ++i) {
+                const double dd = (Tp[0].v[i] - Tp[1].v[i]) / (2.0 * eps);
+                g2[i] += dd * dd;
+            }
+        }
+        for (int i = 0; i < T_N; ++i) cond[i] = sqrt(g2[i]) * e_dir;
+    }
+    /* the lookup error: every term is linear in the radiance, so its change
+     * is bounded by the coefficient of each channel times that channel's
+     * radiance bound */
+    double lerr[T_N] = {0};
+    if (dLv[0] > 0.0 || dLv[1] > 0.0 || dLv[2] > 0.0) {
+        for (int c = 0; c < 3; ++c) {
+            double unit[3] = {0.0, 0.0, 0.0};
+            unit[c] = 1.0;
+            sample_terms Tc;
+            terms_at(Ss, Se, q, w, pL, unit, spp, Hv, grad, Ud, Us, bsdf_w, unit_pdf, &Tc);
+            for (int i = 0; i < T_N; ++i) lerr[i] += fabs(Tc.v[i]) * dLv[c];
+        }
+    }
+    for (int i = 0; i < O_N; ++i) {
+        out->val[i] += T.v[i];
+        out->abs[i] += T.a[i];
+        out->cond[i] += cond[i];
+        out->lerr[i] += lerr[i];
+    }
+    for (int c = 0; c < 3; ++c) {
+        ec->coef[c] = T.v[T_COEF + c];
+        ec->absc[c] = T.a[T_COEF + c];
+        ec->cond[c] = cond[T_COEF + c];
     }
 }
 
@@ -1000,7 +1072,19 @@ typedef struct {
     const orc_params* prm;
     const uint32_t* sync;     /* [npix][spp][3] decisions of the HIP path or NULL */
     uint32_t* dec_out;        /* [npix][spp][3] or NULL */
+    double* dir_out;          /* [npix][spp][2][4] sampled direction and its error bound, or NULL */
 } shade_ctx;
+
+/* Direction-error bound (radians) of a sample drawn by an FP32 evaluation of
+ * its sampling chain; the constants are the parity protocol's (orc_params). */
+static double dir_err_ggx(const orc_params* P, const vndf_aux* a)
+{
+    const double u = 0x1p-24, d = P->dir_arg * u;
+    const double g = fmax(a->g, 0.0), h = fmax(a->h, 0.0);
+    const double Ag = 1.0 / (sqrt(g + d) + sqrt(g));
+    const double Ah = 1.0 / (sqrt(h + d) + sqrt(h));
+    return u * (P->dir_ggx0 + P->dir_ggx1 * (1.0 + (1.0 - a->s) * Ag) * (1.0 + Ah) / fmax(a->mlen, 1e-300));
+}
 
 static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, const double* Ud,
                         const double* Us, pix_out* out, env_contrib* ecs, int64_t* nonfinite)
@@ -1009,6 +1093,8 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
     const orc_env* E = C->env_s;
     const float* envL = C->env_eval ? C->env_eval : E->env;
     int spp = P->spp;
+    const double u = 0x1p-24;
+    const int want_cond = P->dir_light > 0.0 || P->dir_cos > 0.0 || P->dir_ggx0 > 0.0 || P->dir_ggx1 > 0.0;
     memset(out, 0, sizeof(*out));
     for (int s = 0; s < 2 * spp; ++s) ecs[s].texel = -1;
     pix_setup Ss, Se;
@@ -1017,6 +1103,8 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
     if (nf) (*nonfinite)++;
     const uint32_t* sy = C->sync ? C->sync + (size_t)q * spp * 3 : NULL;
     uint32_t* dq = C->dec_out ? C->dec_out + (size_t)q * spp * 3 : NULL;
+    double* dirq = C->dir_out ? C->dir_out + (size_t)q * spp * 8 : NULL;
+    if (dirq) for (int k = 0; k < 8 * spp; ++k) dirq[k] = NAN;
     if (!ok) {
         if (dq) for (int s = 0; s < spp; ++s) { dq[s * 3] = DEC_NONE; dq[s * 3 + 1] = DEC_NONE; dq[s * 3 + 2] = 0; }
         if (sy && (sy[2] & DEC_VALID)) out->n_hard++;
@@ -1047,14 +1135,15 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
     double origin[3];
     for (int k = 0; k < 3; ++k) origin[k] = Ss.p[k] + P->ray_eps * Ss.n[k];
     double Vl[3] = {dot3(Ss.V, Ss.t), dot3(Ss.V, Ss.b), Ss.NoV};
+    const double two_pi2 = 2.0 * ORC_PI * ORC_PI;
     for (int s = 0; s < spp; ++s) {
         double xi[8];
         sample_uniforms(P->seed, piv, (uint32_t)C->gs->view_base + view, (uint32_t)s, xi);
         uint32_t rec0 = DEC_NONE, rec1 = DEC_NONE, rec2 = DEC_VALID | (Ss.nov_pos ? DEC_NOV_POS : 0u);
         const uint32_t* gsr = sy ? sy + s * 3 : NULL;
         for (int tech = 0; tech < 2; ++tech) {
-            double w[3], pL = 0.0;
-            double e_scale = 1.0;   /* direction-error scale against the 32u bound */
+            double w[3], pL = 0.0, pl_num = 0.0;
+            double e_dir = 0.0;   /* bound on the FP32 direction's distance from w (radians) */
             int ti = -1, tj = -1;
             double tex_margin = INFINITY;
             double bx = 0.0, by = 0.0, bdx = 0.0, bdy = 0.0; /* texel coordinates and error bounds */
@@ -1063,9 +1152,11 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                 int32_t a, b;
                 sample_light_xy(E, xi[0], xi[1], w, &pL, &a, &b, &bx, &by);
                 ti = a; tj = b;
+                pl_num = (double)E->pdf[(size_t)ti * E->W + tj] / two_pi2;
+                e_dir = P->dir_light * u;
                 /* FP32: one quotient of table differences plus the integer part */
-                bdx = 2.0 * 0x1p-24 * (bx + 8.0);
-                bdy = 2.0 * 0x1p-24 * (by + 8.0);
+                bdx = 2.0 * u * (bx + 8.0);
+                bdy = 2.0 * u * (by + 8.0);
                 rec0 = (uint32_t)(ti * E->W + tj);
                 if (gsr && gsr[0] != rec0) out->n_hard++;
                 if (!(pL > 0.0)) { rec2 |= DEC_L_CULL; continue; }
@@ -1076,14 +1167,12 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                 if (cosl) {
                     rec2 |= DEC_LOBE_COS;
                     orc_sample_cos_local(xi[4], xi[5], loc);
+                    e_dir = P->dir_cos * u;
                 } else {
-                    double lensq = orc_sample_vndf_local(Vl, Ss.alpha, xi[4], xi[5], loc);
+                    vndf_aux aux;
+                    double lensq = sample_vndf_aux(Vl, Ss.alpha, xi[4], xi[5], loc, &aux);
                     if (lensq < 1e-14) out->n_flag++;
-                    float l32[3];
-                    sample_vndf_local_f32(Vl, Ss.alpha, xi[4], xi[5], l32);
-                    double ed = 0.0;
-                    for (int k = 0; k < 3; ++k) ed += ((double)l32[k] - loc[k]) * ((double)l32[k] - loc[k]);
-                    e_scale = fmax(1.0, 2.0 * sqrt(ed) / (32.0 * 0x1p-24));
+                    e_dir = want_cond ? dir_err_ggx(P, &aux) : 0.0;
                 }
                 if (gsr && (((gsr[2] & DEC_LOBE_COS) != 0) != cosl)) out->n_hard++;
                 for (int k = 0; k < 3; ++k) w[k] = loc[0] * Ss.t[k] + loc[1] * Ss.b[k] + loc[2] * Ss.n[k];
@@ -1092,10 +1181,10 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                 texel_of_dir_xy(E->H, E->W, w, &ti, &tj, &tex_margin, &bx, &by);
                 {
                     /* FP32 error of the coordinates: the direction error
-                     * (32 u, scaled as for the visible-normal sample, with a
-                     * factor 2 margin) through theta and phi = atan2, plus
-                     * the roundoff of atan2 and of the scaling */
-                    const double u = 0x1p-24, dw = 64.0 * u * e_scale;
+                     * (twice its bound; 64 u without a direction model)
+                     * through theta and phi = atan2, plus the roundoff of
+                     * atan2 and of the scaling */
+                    const double dw = e_dir > 0.0 ? 2.0 * e_dir : 64.0 * u;
                     const double rho = sqrt(w[0] * w[0] + w[2] * w[2]);
                     bdy = (dw + 8.0 * u * ORC_PI) * (double)E->H / ORC_PI + 4.0 * u * by;
                     bdx = (rho > 0.0 ? dw / rho : (double)E->W) * (double)E->W / (2.0 * ORC_PI) +
@@ -1105,7 +1194,9 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                 }
                 uint32_t mine = (uint32_t)(ti * E->W + tj);
                 if (gsr && gsr[1] != DEC_NONE && gsr[1] != mine) {
-                    if (tex_margin < P->delta_ang) {
+                    /* undecided in FP32 within the tolerance or within twice
+                     * the sample's own direction-error bound */
+                    if (tex_margin < fmax(P->delta_ang, 2.0 * e_dir)) {
                         ti = (int)(gsr[1] / (uint32_t)E->W);
                         tj = (int)(gsr[1] % (uint32_t)E->W);
                         out->n_synced++;
@@ -1116,15 +1207,20 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                 rec1 = (uint32_t)(ti * E->W + tj);
                 if (light_on) {
                     double rho = sqrt(w[0] * w[0] + w[2] * w[2]);
-                    pL = rho > 0.0 ? (double)E->pdf[(size_t)ti * E->W + tj] / (2.0 * ORC_PI * ORC_PI * rho) : 0.0;
+                    pl_num = (double)E->pdf[(size_t)ti * E->W + tj] / two_pi2;
+                    pL = rho > 0.0 ? pl_num / rho : 0.0;
                 }
+            }
+            if (dirq) {
+                for (int k = 0; k < 3; ++k) dirq[(s * 2 + tech) * 4 + k] = w[k];
+                dirq[(s * 2 + tech) * 4 + 3] = e_dir;
             }
             uint32_t bit_cull = tech ? DEC_B_CULL : DEC_L_CULL;
             uint32_t bit_tr = tech ? DEC_B_TRACED : DEC_L_TRACED;
             uint32_t bit_hit = tech ? DEC_B_HIT : DEC_L_HIT;
             double NoL = dot3(Ss.n, w);
             int cull = !(NoL > 0.0);
-            if (gsr && fabs(NoL) < P->delta_cos) {
+            if (gsr && fabs(NoL) < fmax(P->delta_cos, 2.0 * e_dir)) {
                 int gc = (gsr[2] & bit_cull) != 0;
                 if (gc != cull) { cull = gc; out->n_synced++; }
             } else if (gsr && (((gsr[2] & bit_cull) != 0) != cull)) {
@@ -1160,7 +1256,8 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                 for (int c = 0; c < 3; ++c) Lv[c] = (double)Lrad[c];
             }
             env_contrib* ec = &ecs[2 * s + tech];
-            eval_sample(&Ss, &Se, qf, w, pL, Lv, dLv, spp, Hv, grad, Ud, Us, out, ec, bsdf_on ? 1.0 : 0.0, e_scale, 0);
+            eval_sample(&Ss, &Se, qf, w, pL, light_on ? pl_num : 0.0, Lv, dLv, spp, Hv, grad, Ud, Us, out, ec,
+                        bsdf_on ? 1.0 : 0.0, e_dir, 0);
             ec->texel = ti * E->W + tj;
             ec->bil = bil;
             ec->x = bx;
@@ -1170,12 +1267,11 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
         }
         if (dq) { dq[s * 3] = rec0; dq[s * 3 + 1] = rec1; dq[s * 3 + 2] = rec2; }
     }
-    out->nlen_cond = Se.nlen;
-    if (grad) {
-        /* d/dn_raw = (I - n n^T) d/dn / |n_raw| */
-        double nd = dot3(Se.n, out->gn);
-        for (int k = 0; k < 3; ++k) out->gn[k] = (out->gn[k] - nd * Se.n[k]) / Se.nlen;
+    for (int k = 0; k < 3; ++k) {
+        out->t[k] = Se.t[k];
+        out->b[k] = Se.b[k];
     }
+    out->nlen = Se.nlen;
 }
 
 /* Probe gradient of one bilinear sample: the coefficient of the radiance
@@ -1206,82 +1302,100 @@ static void scatter_bilinear(const env_contrib* e, int H, int W, double* genv, d
 
 /* Forward (grad == 0) or backward (grad == 1) over a list of pixels.
  * Outputs are [3][npix] in list order.  info = [npix][3]: synced decisions,
- * unsyncable (flagged) decisions, hard mismatches against `sync`. */
+ * unsyncable (flagged) decisions, hard mismatches against `sync`.
+ * vaux (or NULL) = [3][15][npix]: for each of the 15 per-pixel outputs (c_d,
+ * c_s, g_kd, g_korm, g_nrm; 3 channels each) the sum of the absolute values
+ * of the summands of its terms, the conditioning of its terms in their
+ * sampled directions, and the bound on the error that enters through the
+ * radiance lookup.  dir_out (or NULL) = [npix][spp][2][4]: each sample's
+ * direction (light, then BSDF technique) and its direction-error bound; NaN
+ * where no direction was drawn. */
 int64_t orc_shade(const orc_scene* scene, const orc_env* env_s, const float* env_eval,
                   const orc_gbuffer* gs, const orc_gbuffer* ge, const int64_t* pix, int64_t npix,
                   const orc_params* prm, const uint32_t* sync, int grad, const double* Ud,
-                  const double* Us, double* cd, double* cs, double* vcond, double* gkd, double* gkorm,
+                  const double* Us, double* cd, double* cs, double* vaux, double* gkd, double* gkorm,
                   double* gn,
                   double* genv, double* senv, double* cenv, double* lenv, uint32_t* hitbits, int32_t hit_words,
-                  uint32_t* dec_out, int32_t* info, int nthreads)
+                  uint32_t* dec_out, double* dir_out, int32_t* info, int nthreads)
 {
-    shade_ctx C = {scene, env_s, env_eval, gs, ge, prm, sync, dec_out};
+    shade_ctx C = {scene, env_s, env_eval, gs, ge, prm, sync, dec_out, dir_out};
     int spp = prm->spp;
     if (spp < 1 || spp > 1024 || hit_words > 64) return -1;
+    /* pixels are taken in chunks, and the probe-gradient contributions of a
+     * chunk are added in list order after it: the same fixed order as one
+     * pass, with bounded memory */
+    const int64_t chunk = 65536;
     env_contrib* all = NULL;
-    if (grad && genv) all = (env_contrib*)malloc(sizeof(env_contrib) * (size_t)npix * 2 * spp);
+    if (grad && genv) all = (env_contrib*)malloc(sizeof(env_contrib) * (size_t)(npix < chunk ? npix : chunk) * 2 * spp);
     int64_t nonfinite = 0;
     int nt = 1;  // a thread count for this call only (num_threads clause)
 #ifdef _OPENMP
     nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #endif
     (void)nt;
+    for (int64_t q0 = 0; q0 < npix; q0 += chunk) {
+        const int64_t q1 = npix - q0 < chunk ? npix : q0 + chunk;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : nonfinite) num_threads(nt)
-    for (int64_t q = 0; q < npix; ++q) {
-        pix_out o;
-        env_contrib local[2 * 256];
-        // above 256 samples the pixel's records go to the heap (worker
-        // threads may have small stacks)
-        env_contrib* big = (!all && spp > 256) ? (env_contrib*)malloc(sizeof(env_contrib) * 2 * (size_t)spp) : NULL;
-        env_contrib* ec = all ? all + (size_t)q * 2 * spp : (big ? big : local);
-        double ud[3] = {0, 0, 0}, us[3] = {0, 0, 0};
-        if (grad) for (int c = 0; c < 3; ++c) { ud[c] = Ud[c * npix + q]; us[c] = Us[c * npix + q]; }
-        shade_pixel(&C, q, pix[q], grad, ud, us, &o, ec, &nonfinite);
-        for (int c = 0; c < 3; ++c) {
-            if (cd) cd[c * npix + q] = o.cd[c];
-            if (cs) cs[c * npix + q] = o.cs[c];
-            if (vcond) {
-                vcond[c * npix + q] = o.cd_cond[c];
-                vcond[(3 + c) * npix + q] = o.cs_cond[c];
-                vcond[(6 + c) * npix + q] = o.gkd_cond[c];
-                vcond[(9 + c) * npix + q] = c == 0 ? 0.0 : (c == 1 ? o.gr_cond : o.gm_cond);
-                vcond[(12 + c) * npix + q] = o.gn_cond / (o.nlen_cond > 0.0 ? o.nlen_cond : 1.0);
-                vcond[(15 + c) * npix + q] = o.cd_lerr[c];
-                vcond[(18 + c) * npix + q] = o.cs_lerr[c];
-                vcond[(21 + c) * npix + q] = o.gkd_lerr[c];
-                vcond[(24 + c) * npix + q] = c == 0 ? 0.0 : (c == 1 ? o.gr_lerr : o.gm_lerr);
-                vcond[(27 + c) * npix + q] = o.gn_lerr / (o.nlen_cond > 0.0 ? o.nlen_cond : 1.0);
-            }
-            if (grad) {
-                if (gkd) gkd[c * npix + q] = o.gkd[c];
-                if (gn) gn[c * npix + q] = o.gn[c];
-            }
-        }
-        if (grad && gkorm) {
-            gkorm[0 * npix + q] = 0.0;
-            gkorm[1 * npix + q] = o.gr;
-            gkorm[2 * npix + q] = o.gm;
-        }
-        if (hitbits) for (int k = 0; k < hit_words; ++k) hitbits[(size_t)q * hit_words + k] = o.hitbits[k];
-        if (info) { info[q * 3] = o.n_synced; info[q * 3 + 1] = o.n_flag; info[q * 3 + 2] = o.n_hard; }
-        free(big);
-    }
-    if (all) {
-        /* fixed order: pixel list order, then sample, then technique */
-        for (int64_t k = 0; k < npix * 2 * spp; ++k) {
-            if (all[k].texel < 0) continue;
-            if (all[k].bil) {
-                scatter_bilinear(&all[k], env_s->H, env_s->W, genv, senv, cenv, lenv);
-                continue;
-            }
+        for (int64_t q = q0; q < q1; ++q) {
+            pix_out o;
+            env_contrib local[2 * 256];
+            // above 256 samples the pixel's records go to the heap (worker
+            // threads may have small stacks)
+            env_contrib* big = (!all && spp > 256) ? (env_contrib*)malloc(sizeof(env_contrib) * 2 * (size_t)spp) : NULL;
+            env_contrib* ec = all ? all + (size_t)(q - q0) * 2 * spp : (big ? big : local);
+            double ud[3] = {0, 0, 0}, us[3] = {0, 0, 0};
+            if (grad) for (int c = 0; c < 3; ++c) { ud[c] = Ud[c * npix + q]; us[c] = Us[c * npix + q]; }
+            shade_pixel(&C, q, pix[q], grad, ud, us, &o, ec, &nonfinite);
+            const double il = o.nlen > 0.0 ? 1.0 / o.nlen : 0.0;
             for (int c = 0; c < 3; ++c) {
-                genv[(size_t)all[k].texel * 3 + c] += all[k].coef[c];
-                if (senv) senv[(size_t)all[k].texel * 3 + c] += all[k].absc[c];
-                if (cenv) cenv[(size_t)all[k].texel * 3 + c] += all[k].cond[c];
+                if (cd) cd[c * npix + q] = o.val[T_CD + c];
+                if (cs) cs[c * npix + q] = o.val[T_CS + c];
+                if (grad) {
+                    if (gkd) gkd[c * npix + q] = o.val[T_GKD + c];
+                    /* d/dn_raw = (I - n n^T) d/dn / |n_raw| = (t (t.g) + b (b.g)) / |n_raw| */
+                    if (gn) gn[c * npix + q] = (o.val[T_GNT] * o.t[c] + o.val[T_GNB] * o.b[c]) * il;
+                }
+            }
+            if (grad && gkorm) {
+                gkorm[0 * npix + q] = 0.0;
+                gkorm[1 * npix + q] = o.val[T_GR];
+                gkorm[2 * npix + q] = o.val[T_GM];
+            }
+            if (vaux) {
+                const double* src[3] = {o.abs, o.cond, o.lerr};
+                for (int kind = 0; kind < 3; ++kind) {
+                    const double* x = src[kind];
+                    double* dst = vaux + (size_t)kind * 15 * npix;
+                    for (int c = 0; c < 3; ++c) {
+                        dst[(0 + c) * npix + q] = x[T_CD + c];
+                        dst[(3 + c) * npix + q] = x[T_CS + c];
+                        dst[(6 + c) * npix + q] = x[T_GKD + c];
+                        dst[(9 + c) * npix + q] = c == 0 ? 0.0 : (c == 1 ? x[T_GR] : x[T_GM]);
+                        dst[(12 + c) * npix + q] = (x[T_GNT] * fabs(o.t[c]) + x[T_GNB] * fabs(o.b[c])) * il;
+                    }
+                }
+            }
+            if (hitbits) for (int k = 0; k < hit_words; ++k) hitbits[(size_t)q * hit_words + k] = o.hitbits[k];
+            if (info) { info[q * 3] = o.n_synced; info[q * 3 + 1] = o.n_flag; info[q * 3 + 2] = o.n_hard; }
+            free(big);
+        }
+        if (all) {
+            /* fixed order: pixel list order, then sample, then technique */
+            for (int64_t k = 0; k < (q1 - q0) * 2 * spp; ++k) {
+                if (all[k].texel < 0) continue;
+                if (all[k].bil) {
+                    scatter_bilinear(&all[k], env_s->H, env_s->W, genv, senv, cenv, lenv);
+                    continue;
+                }
+                for (int c = 0; c < 3; ++c) {
+                    genv[(size_t)all[k].texel * 3 + c] += all[k].coef[c];
+                    if (senv) senv[(size_t)all[k].texel * 3 + c] += all[k].absc[c];
+                    if (cenv) cenv[(size_t)all[k].texel * 3 + c] += all[k].cond[c];
+                }
             }
         }
-        free(all);
     }
+    free(all);
     return nonfinite;
 }
 
@@ -1414,11 +1528,11 @@ void orc_integrand(const orc_scene* scene, const orc_env* E, const orc_gbuffer* 
                 const float* Lrad = E->env + ((size_t)ti * E->W + tj) * 3;
                 for (int c = 0; c < 3; ++c) Lv[c] = (double)Lrad[c];
             }
-            eval_sample(&S, &S, 1.0f, wi, 0.0, Lv, dLv, 1, Hv, 0, NULL, NULL, &o, &ec, 1.0, 1.0, 1);
+            eval_sample(&S, &S, 1.0f, wi, 0.0, 0.0, Lv, dLv, 1, Hv, 0, NULL, NULL, &o, &ec, 1.0, 0.0, 1);
         }
         for (int c = 0; c < 3; ++c) {
-            gd[3 * i + c] = o.cd[c];
-            gs[3 * i + c] = o.cs[c];
+            gd[3 * i + c] = o.val[T_CD + c];
+            gs[3 * i + c] = o.val[T_CS + c];
         }
     }
 }
@@ -1693,16 +1807,16 @@ int orc_edge_grad(const orc_scene* scene, const orc_env* E, const orc_gbuffer* g
                         pix_out po;
                         env_contrib ec;
                         memset(&po, 0, sizeof(po));
-                        eval_sample(&S, &S, 1.0f, we, 0.0, Lv, dLv, 1, 1.0, 0, NULL, NULL, &po, &ec, 1.0, 1.0, 1);
+                        eval_sample(&S, &S, 1.0f, we, 0.0, 0.0, Lv, dLv, 1, 1.0, 0, NULL, NULL, &po, &ec, 1.0, 0.0, 1);
                         for (int c = 0; c < 3; ++c) {
-                            const double td = fabs(ud[c] * po.cd[c]) + fabs(us[c] * po.cs[c]);
+                            const double td = fabs(ud[c] * po.val[T_CD + c]) + fabs(us[c] * po.val[T_CS + c]);
                             const double sl = fabs(Lv[c]) > 0.0 ? Lb[c] / fabs(Lv[c]) : 0.0;
                             gbound += td * sl;
                             if (!above) continue;
-                            gsum += ud[c] * po.cd[c] + us[c] * po.cs[c];
+                            gsum += ud[c] * po.val[T_CD + c] + us[c] * po.val[T_CS + c];
                             gabs += td;
-                            gcond += fabs(ud[c]) * (po.cd_cond[c] + po.cd_lerr[c]) +
-                                     fabs(us[c]) * (po.cs_cond[c] + po.cs_lerr[c]);
+                            gcond += fabs(ud[c]) * (po.cond[T_CD + c] + po.lerr[T_CD + c]) +
+                                     fabs(us[c]) * (po.cond[T_CS + c] + po.lerr[T_CS + c]);
                         }
                         if (!above) gbound *= 2.0;
                     }

@@ -12,7 +12,7 @@ import torch
 
 from . import _lib as L
 from ._lib import (MCDIError, FLAG_LIGHT_OFF, FLAG_FORCE_COS, FLAG_BSDF_OFF, FLAG_FORCE_GGX, FLAG_BILINEAR,  # noqa: F401
-                   FLAG_DUMP, FLAG_TIME_TRACE)
+                   FLAG_DUMP, FLAG_DUMP_DIRS, FLAG_TIME_TRACE)
 
 __all__ = ["Scene", "Env", "GBuffer", "Edges", "shade_fwd", "shade_bwd", "shade_bwd_edges", "trace_anyhit",
            "MCDIShade", "MCDIError", "new_stats", "read_stats"]
@@ -198,7 +198,9 @@ def _params(spp, seed, tau, ray_eps, flags, decisions):
 def shade_fwd(scene, env, gb, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0, hitbits=True, decisions=False,
               stats=None, out=None, stream=None):
     """Forward pass.  Returns (c_d [3,N], c_s [3,N], hitbits [words,N] or None,
-    decisions [N,spp,3] or None)."""
+    decisions [N,spp,3] or None).  decisions="dirs": records of 9 words
+    [N,spp,9], the last six the light and BSDF samples' world directions
+    (float32 bits)."""
     n = gb.n
     dev = gb.pos.device
     if out is None:
@@ -209,8 +211,9 @@ def shade_fwd(scene, env, gb, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0, hitbi
         c_d, c_s, hb = out
     dec = None
     if decisions:
-        dec = torch.empty((n, spp, 3), dtype=torch.int32, device=dev)
-        flags |= FLAG_DUMP
+        dirs = decisions == "dirs"
+        dec = torch.empty((n, spp, 9 if dirs else 3), dtype=torch.int32, device=dev)
+        flags |= FLAG_DUMP | (FLAG_DUMP_DIRS if dirs else 0)
     gs = gb.struct()
     prm = _params(spp, seed, tau, ray_eps, flags, dec)
     L.check(L.lib().mcdi_shade_fwd(scene.handle, env.handle, C.byref(gs), C.byref(prm), _ptr(c_d), _ptr(c_s),

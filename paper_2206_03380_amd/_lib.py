@@ -18,6 +18,7 @@ FLAG_BSDF_OFF = 1 << 2
 FLAG_FORCE_GGX = 1 << 3
 FLAG_BILINEAR = 1 << 4
 FLAG_DUMP = 1 << 8
+FLAG_DUMP_DIRS = 1 << 10
 FLAG_TIME_TRACE = 1 << 9
 
 vp = C.c_void_p

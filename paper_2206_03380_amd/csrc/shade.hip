@@ -495,6 +495,11 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
 //    adjoint, s_hot must be zeroed before and flushed after (hot_flush).
 //    BIL: bilinear probe lookup (MCDI_FLAG_BILINEAR) instead of the nearest
 //    texel.
+// words per sample of the decision dump: 3, or 9 with the sampled world
+// directions (MCDI_FLAG_DUMP_DIRS)
+constexpr uint32_t kNanBits = 0x7FC00000u;
+__device__ __forceinline__ int dump_stride(const ShadeArgs& A) { return (A.flags & MCDI_FLAG_DUMP_DIRS) ? 9 : 3; }
+
 template <bool BWD, bool DUMP, bool BIL>
 __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, const float* s_marg, float* s_hot,
                                            const RecSink& rs) {
@@ -515,8 +520,12 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
             }
         }
         if (DUMP) {
-            uint32_t* d = A.decisions + (size_t)pix * spp * 3;
-            for (int s = 0; s < spp; ++s) { d[3 * s] = kNone; d[3 * s + 1] = kNone; d[3 * s + 2] = 0u; }
+            const int st = dump_stride(A);
+            uint32_t* d = A.decisions + (size_t)pix * spp * st;
+            for (int s = 0; s < spp; ++s) {
+                d[st * s] = kNone; d[st * s + 1] = kNone; d[st * s + 2] = 0u;
+                for (int k = 3; k < st; ++k) d[st * s + k] = kNanBits;
+            }
         }
         return;
     }
@@ -539,16 +548,19 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
         const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
         uint32_t rec0 = kNone, rec1 = kNone;
         uint32_t rec2 = kDecValid | (P.nov_pos ? kDecNovPos : 0u);
+        float3 dir[2] = {f3(__uint_as_float(kNanBits), 0.0f, 0.0f), f3(__uint_as_float(kNanBits), 0.0f, 0.0f)};
         for (int tech = 0; tech < 2; ++tech) {
             Sample S;
             if (tech == 0) {
                 if (!light_on) continue;
                 const bool has = draw_light(A, P, s_marg, r0, S);
                 rec0 = (uint32_t)S.texel;
+                if (DUMP) dir[0] = S.w;
                 if (!has) { rec2 |= kDecLCull; continue; }
             } else {
                 if (P.bsdf_w == 0.0f) continue;
                 if (draw_bsdf(P, r0, r1, S)) rec2 |= kDecLobeCos;
+                if (DUMP) dir[1] = S.w;
             }
             if (!(S.wl.z > 0.0f)) { rec2 |= tech ? kDecBCull : kDecLCull; continue; }
             if (tech == 1) {
@@ -567,8 +579,16 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
             eval_sample<BWD, BIL>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
         }
         if (DUMP) {
-            uint32_t* d = A.decisions + ((size_t)pix * spp + s) * 3;
+            const int st = dump_stride(A);
+            uint32_t* d = A.decisions + ((size_t)pix * spp + s) * st;
             d[0] = rec0; d[1] = rec1; d[2] = rec2;
+            if (st == 9) {
+                for (int t = 0; t < 2; ++t) {
+                    d[3 + 3 * t] = __float_as_uint(dir[t].x);
+                    d[4 + 3 * t] = __float_as_uint(dir[t].y);
+                    d[5 + 3 * t] = __float_as_uint(dir[t].z);
+                }
+            }
         }
     }
     if (!BWD) {

@@ -1,5 +1,9 @@
 """Estimator-level pins of the FP64 oracle.
 
+  lobe choice        the BSDF technique picks the cosine lobe with frequency
+                     q = (1 - m)/2 where n.v > 0 and always where n.v <= 0
+                     (every q in (0, 1) is unbiased, so the expectation pins
+                     below cannot see it);
   white furnace      uniform probe, no occluder: E[c_d] = (1 - m) L0, and with
                      the light technique off and q = 1 every sample equals it;
   Lambert occluder   uniform probe, a convex polyhedron above a receiver:
@@ -68,6 +72,67 @@ def test_white_furnace_cosine_only_is_exact():
     o = oracle.shade(w, flags=oracle.LIGHT_OFF | oracle.FORCE_COS)
     m = w.korm[2].astype(np.float64)
     assert np.allclose(o["c_d"], (1 - m)[None, :] * L0[:, None], rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# lobe-selection probability (the paper leaves the mixture weight open; the
+# reading is q = (1 - m)/2 where the view is above the surface, else 1)
+# ---------------------------------------------------------------------------
+def _lobe_workload(m, n=1024, spp=64):
+    """Half the pixels face the eye (n.v > 0), half face away (n.v < 0);
+    metallic m everywhere, albedo and roughness random (q must not depend on
+    them)."""
+    eye = np.array([0.0, 0.0, 5.0])
+    pos = RNG.uniform(-0.5, 0.5, (n, 3)) * np.array([1.0, 1.0, 0.0])
+    tilt = _unit(np.concatenate([RNG.normal(size=(n, 2)) * 0.4, np.ones((n, 1))], 1))
+    nrm = tilt.copy()
+    nrm[n // 2:] *= -1.0
+    kd = RNG.random((n, 3))
+    korm = np.stack([np.ones(n), RNG.uniform(0.08, 1, n), np.full(n, m)], 1)
+    env = np.ones((8, 16, 3), np.float32)
+    v, f = _empty_mesh()
+    return from_arrays("lobes", v, f, env, pos, nrm, kd, korm, eye=eye, spp=spp)
+
+
+@pytest.mark.parametrize("m", [0.0, 0.3, 1.0])
+def test_lobe_choice_frequency(m):
+    """The BSDF sample takes the cosine lobe with frequency q = (1 - m)/2
+    where n.v > 0 (binomial, within 4 standard deviations; exactly never at
+    m = 1), and always where n.v <= 0.  A q that depended on kd or on the
+    roughness, or a weight like m/2 or 1 - m, fails."""
+    w = _lobe_workload(m)
+    o = oracle.shade(w, want_decisions=True)
+    cos = (o["decisions"][..., 2] & oracle.DEC_LOBE_COS) != 0
+    nov_pos = (o["decisions"][..., 2] & oracle.DEC_NOV_POS) != 0
+    front = nov_pos.all(axis=1)
+    assert front.sum() == w.n_pixels // 2 and (~nov_pos[~front]).all()
+    q = float(np.float32(0.5) * (np.float32(1.0) - np.float32(m)))
+    k = cos[front]
+    freq = k.mean()
+    if q == 0.0:
+        assert not k.any()
+    else:
+        sd = np.sqrt(q * (1 - q) / k.size)
+        assert abs(freq - q) < 4 * sd, (freq, q, sd)
+    # q does not depend on albedo or roughness: the frequency is the same in
+    # the two halves of the pixels sorted by roughness
+    order = np.argsort(w.korm[1][: w.n_pixels // 2])
+    lo, hi = k[order[: len(order) // 2]].mean(), k[order[len(order) // 2:]].mean()
+    if q > 0:
+        assert abs(lo - hi) < 6 * np.sqrt(q * (1 - q) / (k.size / 2))
+    assert cos[~front].all()
+
+
+def test_lobe_choice_forced():
+    """FORCE_COS: q = 1 everywhere; FORCE_GGX: q = 0 where n.v > 0 (cosine
+    where the view is below the surface, where GGX visible-normal sampling
+    has no density)."""
+    w = _lobe_workload(0.3, n=256, spp=16)
+    for flag, want_front in ((oracle.FORCE_COS, True), (oracle.FORCE_GGX, False)):
+        o = oracle.shade(w, want_decisions=True, flags=oracle.LIGHT_OFF | flag)
+        cos = (o["decisions"][..., 2] & oracle.DEC_LOBE_COS) != 0
+        front = ((o["decisions"][..., 2] & oracle.DEC_NOV_POS) != 0).all(axis=1)
+        assert (cos[front] == want_front).all() and cos[~front].all()
 
 
 # ---------------------------------------------------------------------------
@@ -427,3 +492,33 @@ def test_brute_force_equals_bvh_render():
     a = oracle.shade(w)
     b = oracle.shade(w, brute=True)
     assert np.array_equal(a["c_d"], b["c_d"]) and np.array_equal(a["hitbits"], b["hitbits"])
+
+
+# ---------------------------------------------------------------------------
+# tolerance quantities the oracle reports beside its outputs
+# ---------------------------------------------------------------------------
+def test_abs_sums_and_direction_conditioning():
+    """Per output, the sum of the summands' magnitudes bounds the value (and
+    equals it where every summand is positive: the values under a positive
+    probe); without a direction model no conditioning is reported, with one
+    it scales linearly with the model's counts."""
+    from workloads import upstream_grads
+    w = make_workload("tiny", H=32, W=32)
+    ud, us = upstream_grads(w)
+    base = dict(grad=True, u_d=ud.astype(np.float64), u_s=us.astype(np.float64))
+    o0 = oracle.shade(w, **base)
+    for k in ("c_d", "c_s", "g_kd", "g_korm", "g_nrm"):
+        assert np.all(o0[k + "_abs"] >= np.abs(o0[k]) * (1 - 1e-12))
+        assert np.all(o0[k + "_cond"] == 0.0)
+    for k in ("c_d", "c_s"):
+        assert np.allclose(o0[k + "_abs"], np.abs(o0[k]), rtol=1e-12, atol=0)
+    counts = {"light": 32, "cos": 16, "ggx0": 16, "ggx1": 16, "arg": 16}
+    o1 = oracle.shade(w, tol=oracle.Tolerances(dir=counts), **base)
+    o2 = oracle.shade(w, tol=oracle.Tolerances(dir={k: 2 * v for k, v in counts.items() if k != "arg"} |
+                                               {"arg": 16}), **base)
+    for k in ("c_d", "c_s", "g_kd", "g_nrm"):
+        assert np.array_equal(o1[k], o0[k])
+        c1, c2 = o1[k + "_cond"], o2[k + "_cond"]
+        assert (c1 > 0).mean() > 0.5
+        assert np.allclose(c2, 2 * c1, rtol=1e-9, atol=1e-300)
+    assert np.all(o1["c_env"] >= 0) and o1["c_env"].max() > 0
