@@ -7,13 +7,17 @@ shading (samples, MIS, shadow rays), the fused image loss (tonemapped L1 +
 light regulariser, value and gradients in one kernel pass) and the backward
 pass through the autograd Function (adjoint kernel with the probe-texel
 scatter); with --denoise the cross-bilateral denoiser (sigma 2) sits between
-shading and loss.  Inputs are resident in HBM before timing starts.  The
-denoiser and the loss kernels are also timed on their own, each with its
-roofline, under "next_rows".
+shading and loss.  Inputs are resident in HBM before timing starts.
 
-Default workload: 8 views at 512x512 of a 101,060-triangle displaced sphere
-with 20 box occluders, a 512x256 probe, 12 samples per pixel, forward +
-backward (synthetic data shaped like the paper's multi-view batches).
+Default workload (the headline): the heavy-occlusion lattice room, 4 views
+at 1024x1024 of a 1.0M-triangle lattice, a 2048x1024 probe, 32 samples per
+pixel, forward + backward -- the largest single-GPU configuration, shaped
+like the paper's multi-view batches and mesh sizes (synthetic data).  The
+line also carries, as secondary keys, the 8 x 512^2 displaced-sphere
+workload at 12 spp, the three-scene serving mix (batched persistent
+launches against per-request launches at 0.5/0.7/0.9 of the saturated
+rate), the next rows' kernels (denoiser, loss, sampling study, visibility
+gradient) and the FP64 oracle's rate on the host cores.
 
 Prints ONE JSON line.
 """
@@ -40,15 +44,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sphere8_grad")
+    ap.add_argument("--workload", default="lattice")
+    ap.add_argument("--secondary", default="sphere8_grad",
+                    help="workload measured as a secondary key with fewer steps ('' to skip)")
+    ap.add_argument("--secondary-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark on the three-scene mix (50k/300k/1M triangles)")
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--no-serve", action="store_true", help="skip the short serving run of the default line")
+    ap.add_argument("--serve-requests", type=int, default=None,
+                    help="measured requests per load of the serving mix (default 400 in the line, 2000 with --serve)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving mix of the default line")
     ap.add_argument("--denoise", action="store_true", help="cross-bilateral denoiser (sigma 2) inside the step")
     ap.add_argument("--no-next-rows", action="store_true",
                     help="skip the denoiser, loss and sampling-study measurements (profiling runs of the step's "
@@ -70,21 +78,62 @@ def main():
               "sharding by views would only add an all-reduce of the probe gradient); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import paper_2206_03380_amd as M
     from workloads import make_workload
 
-    dev = "cuda:0"
     torch.cuda.set_device(0)
     if args.serve:
-        print(json.dumps(serve_full(args, M)), flush=True)
+        print(json.dumps(serve_mix(args, M, args.serve_requests or 2000)), flush=True)
         return
     t0 = time.time()
     w = make_workload(args.workload)
     log(args, "workload %s generated in %.1fs: %d px (%d valid), %d tris, env %s, spp %d" % (
         w.name, time.time() - t0, w.n_pixels, w.n_valid, len(w.tris), w.env.shape[:2], w.spp))
+    m = measure(args, M, w, args.steps, args.warmup)
+    result = {
+        "metric": METRIC, "value": m["value"], "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": m["config"],
+    }
+    for k in ("shadow_rays_per_s", "fwd_ms", "bwd_ms", "trace_ms", "adjoint_ms", "bvh_build_ms", "env_cdf_ms",
+              "shade_only_samples_per_s", "work", "roofline", "adjoint_roofline"):
+        result[k] = m[k]
+    gb = m["gb"]
+    if not args.no_next_rows:
+        result["next_rows"] = next_rows(args, M, gb, m["c_d"], m["c_s"], m["target"], m["timed"])
+    del m
+    torch.cuda.empty_cache()
+    if args.secondary and args.secondary != args.workload:
+        t0 = time.time()
+        w2 = make_workload(args.secondary)
+        log(args, "secondary workload %s generated in %.1fs" % (w2.name, time.time() - t0))
+        m2 = measure(args, M, w2, args.secondary_steps, 2)
+        result["secondary"] = {w2.name: {k: m2[k] for k in (
+            "config", "value", "ms_per_step", "shadow_rays_per_s", "fwd_ms", "bwd_ms", "trace_ms", "adjoint_ms",
+            "roofline", "adjoint_roofline")}}
+        result["secondary"][w2.name]["steps"] = args.secondary_steps
+        del m2, w2
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        result["serving"] = serve_mix(args, M, args.serve_requests or 400)
+    if args.copy_calibration:
+        result["copy_calibration_bytes"] = copy_calibration("cuda:0")
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args, w)
+    print(json.dumps(result), flush=True)
 
+
+def measure(args, M, w, steps, warmup):
+    """Time `steps` optimisation steps of workload w (after `warmup`), then
+    the forward and backward calls, the BVH and table builds on their own,
+    the work counts of the statistics instantiation, and the rooflines of the
+    traversal and adjoint kernels (their HIP-event durations over the timed
+    steps)."""
+    import numpy as np
+    import torch
+    dev = "cuda:0"
     verts = torch.from_numpy(w.verts).to(dev)
     tris = torch.from_numpy(w.tris).to(dev)
     env_p = torch.from_numpy(w.env).to(dev)
@@ -109,9 +158,10 @@ def main():
                         gb.eye, gb.n_views, gb.height, gb.width)
         cd_t, cs_t, _, _ = M.shade_fwd(sc0, ev0, gbt, w.spp, seed=0, tau=w.tau, ray_eps=w.ray_eps, hitbits=False)
         target = (gbt.kd * cd_t + cs_t).detach()
-        del sc0, ev0
+        del sc0, ev0, cd_t, cs_t
 
     side = torch.cuda.Stream()
+    timing = M.FLAG_TIME_TRACE | M.FLAG_TIME_ADJOINT
 
     def step():
         # BVH rebuild (the mesh changes every iteration) on a side stream: the
@@ -121,35 +171,38 @@ def main():
             scene = M.Scene(verts, tris)
         envh = M.Env(env_t.detach())                      # probe tables rebuild
         c_d, c_s = M.MCDIShade.apply(kd, korm, nrm, env_t, scene, envh, gb, w.spp, w.seed, w.tau, w.ray_eps,
-                                     M.FLAG_TIME_TRACE)
+                                     timing)
         if args.denoise:
             guide = M.BilateralGuide.from_gbuffer(gb, sigma=2.0)
             y = M.Bilateral.apply(torch.cat([c_d, c_s]), guide)
             c_d, c_s = y[:3], y[3:]
         loss = M.ImageLoss.apply(kd, c_d, c_s, target, gb.mask, 0.15)
         loss.backward()
-        return scene, envh
+        for t in (kd, korm, nrm, env_t):
+            t.grad = None
 
-    # warmup
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     M.trace_times()                                       # forget warm-up timings
+    M.adjoint_times()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     end.record()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / args.steps
-    trace_ms_list = M.trace_times()                       # traversal kernel, HIP events on its stream
+    ms = start.elapsed_time(end) / steps
+    # traversal and adjoint kernels: HIP events on the stream they run on
+    trace_ms_list, adj_ms_list = M.trace_times(), M.adjoint_times()
     trace_ms = sum(trace_ms_list) / max(len(trace_ms_list), 1)
+    adj_ms = sum(adj_ms_list) / max(len(adj_ms_list), 1)
     samples = n_valid * w.spp
     value = samples / (ms * 1e-3)
-    log(args, "step %.3f ms -> %.3g samples/s; trace kernel %.3f ms (%d launches)" % (
-        ms, value, trace_ms, len(trace_ms_list)))
+    log(args, "%s: step %.3f ms -> %.3g samples/s; trace kernel %.3f ms (%d launches), adjoint kernel %.3f ms" % (
+        w.name, ms, value, trace_ms, len(trace_ms_list), adj_ms))
 
-    # ---- per-kernel timing on the launch stream (HIP events) ----
+    # ---- per-call timing on the launch stream (HIP events) ----
     scene = M.Scene(verts, tris)
     envh = M.Env(env_p)
     stream = torch.cuda.current_stream()
@@ -171,12 +224,13 @@ def main():
     g_cs = torch.randn((3, gb.n), device=dev) * mask / n_valid
     g_env = torch.zeros_like(env_p)
     bwd_out = (torch.empty_like(g_cd), torch.empty_like(g_cd), torch.empty_like(g_cd))
+    reps = max(3, min(args.kernel_reps, int(2000 / max(ms, 1.0))))
     fwd_ms = timed(lambda: M.shade_fwd(scene, envh, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps,
-                                       out=out[:3]), args.kernel_reps)
+                                       out=out[:3]), reps)
     bwd_ms = timed(lambda: M.shade_bwd(scene, envh, gb, w.spp, g_cd, g_cs, hitbits=hb, seed=w.seed, tau=w.tau,
-                                       ray_eps=w.ray_eps, g_env=g_env, out=bwd_out), args.kernel_reps)
-    bvh_ms = timed(lambda: M.Scene(verts, tris), max(3, args.kernel_reps // 2))
-    cdf_ms = timed(lambda: M.Env(env_p), max(3, args.kernel_reps // 2))
+                                       ray_eps=w.ray_eps, g_env=g_env, out=bwd_out), reps)
+    bvh_ms = timed(lambda: M.Scene(verts, tris), max(3, reps // 2))
+    cdf_ms = timed(lambda: M.Env(env_p), max(3, reps // 2))
 
     # ---- statistics instantiation (same rays): work counts ----
     st = M.new_stats(dev)
@@ -188,39 +242,50 @@ def main():
     # VALU lane-operations the method performs per launch, from the work counts
     ops = OPS_PER_RAY * rays + OPS_PER_BOX * stats["box_tests"] + OPS_PER_TRI * stats["tri_tests"]
     achieved = ops / (trace_ms * 1e-3)
+    tfile = os.path.join(ROOT, "profiles", "trace_rays_%s_pmc.md" % w.name)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
+                "frac": achieved / VALU_PEAK, "traffic": measured_traffic(tfile),
                 "kernel": "trace_rays_kernel", "ops_per_launch": ops, "kernel_ms": trace_ms,
                 "units": {"rays": rays, "box_tests": stats["box_tests"], "tri_tests": stats["tri_tests"]},
                 "lane_utilisation": {"box": stats["box_tests"] / max(stats["box_slots"], 1),
                                      "tri": stats["tri_tests"] / max(stats["tri_slots"], 1)}}
-
-    result = {
-        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+    # ---- roofline of the adjoint kernel (shade_kernel<true>) ----
+    adj_ops = ADJ_OPS_PER_SAMPLE * stats["valid_pixels"] * w.spp + ADJ_OPS_PER_EVAL * rays
+    adj_a = adj_ops / (adj_ms * 1e-3) if adj_ms > 0 else 0.0
+    adjoint_roofline = {"bound": "alu", "achieved": adj_a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
+                        "frac": adj_a / VALU_PEAK, "traffic": None, "kernel": "shade_kernel<true>",
+                        "ops_per_launch": adj_ops, "kernel_ms": adj_ms,
+                        "units": {"samples": stats["valid_pixels"] * w.spp, "evaluated_directions": rays}}
+    STATE.update(scene=scene, env=envh, w=w, verts=verts, tris=tris)
+    return {
         "config": {"workload": "%s: %d views %dx%d, %d tris, env %dx%d, %d spp, fwd+bwd" % (
             w.name, w.n_views, w.width, w.height, len(w.tris), w.env.shape[1], w.env.shape[0], w.spp),
             "views": w.n_views, "height": w.height, "width": w.width, "spp": w.spp, "tris": int(len(w.tris)),
             "env": [int(w.env.shape[0]), int(w.env.shape[1])], "valid_px": n_valid,
             "parallelism": "single-gpu"},
+        "value": value, "ms_per_step": ms,
         "shadow_rays_per_s": rays / (fwd_ms * 1e-3),
-        "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "trace_ms": trace_ms, "bvh_build_ms": bvh_ms, "env_cdf_ms": cdf_ms,
-        "shade_only_samples_per_s": samples / ((fwd_ms + bwd_ms) * 1e-3),
-        "work": stats,
-        "roofline": roofline,
+        "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "trace_ms": trace_ms, "adjoint_ms": adj_ms, "bvh_build_ms": bvh_ms,
+        "env_cdf_ms": cdf_ms, "shade_only_samples_per_s": samples / ((fwd_ms + bwd_ms) * 1e-3),
+        "work": stats, "roofline": roofline, "adjoint_roofline": adjoint_roofline,
+        "gb": gb, "c_d": out[0], "c_s": out[1], "target": target, "timed": timed,
     }
 
-    STATE.update(scene=scene, env=envh, w=w, verts=verts, tris=tris)
-    if not args.no_next_rows:
-        result["next_rows"] = next_rows(args, M, gb, out[0], out[1], target, timed)
-    if not args.no_serve:
-        result["serving"] = serve_quick(args, M, w, gb)
-    if args.copy_calibration:
-        result["copy_calibration_bytes"] = copy_calibration(dev)
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(args, w)
-    print(json.dumps(result), flush=True)
+
+# Adjoint kernel (shade_kernel<true>), VALU lane operations of the method.
+# Per drawn sample of a valid pixel: two Philox4x32-10 blocks (ten rounds of
+# two 32x32->64 products, two xors and the key schedule: 160), the light
+# technique's draw (marginal and guided conditional searches, in-texel
+# offsets, two sincospi, the direction and its density: 50) and the BSDF
+# technique's (lobe choice, cosine or visible-normal warp, world frame,
+# normalisation, two atan2 for the texel and its density: 100) = 310.  Per
+# evaluated direction: the balance heuristic and the BSDF (half vector, D,
+# both Smith Lambdas, G2, Schlick F, three densities: 60) and the
+# derivatives (D and Lambda in alpha, S in alpha, n.v, n.l and n.h, the
+# normal gradient in the tangent frame, kd/m/r terms, the probe coefficient
+# and its scatter: 85) = 145.
+ADJ_OPS_PER_SAMPLE = 310
+ADJ_OPS_PER_EVAL = 145
 
 
 # per-unit VALU lane-operation counts of the traversal: slab test of one node
@@ -328,25 +393,42 @@ def visibility_gradient(args, M, gb, timed):
         M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=w.seed, tau=w.tau,
                           ray_eps=w.ray_eps, g_verts=gv, stats=st, sharp_gain=gain)
         stats = M.read_stats(st)
+        M.adjoint_times()
         ms = timed(lambda: M.shade_bwd_edges(sc, envh, ed, verts, gb, EDGE_SPP, g_cd, g_cs, seed=w.seed,
-                                             tau=w.tau, ray_eps=w.ray_eps, g_verts=gv, sharp_gain=gain), reps)
-        return ms, stats
+                                             tau=w.tau, ray_eps=w.ray_eps, g_verts=gv, sharp_gain=gain,
+                                             flags=M.FLAG_TIME_ADJOINT), reps)
+        # the edge-sample kernel of every pass of the timed calls (HIP events)
+        gen = M.adjoint_times()
+        calls = reps + 1
+        return ms, stats, sum(gen) / calls, len(gen) // calls
 
-    ms, stats = measure(1)
-    ms64, stats64 = measure(64)
+    ms, stats, gen_ms, passes = measure(1)
+    ms64, stats64, _, _ = measure(64)
 
     queued = stats["rays_traced"]
     ops = EDGE_OPS_PER_SAMPLE * samples + EDGE_OPS_PER_QUEUED * queued
     a = ops / (ms * 1e-3)
+    # the edge-sample kernel streams one random 64-byte line (the drawn edge's
+    # packed corners) per sample past the L2, plus the G-buffer position and
+    # normal of each valid pixel, the mask of every pixel and a 4-byte record
+    # per queued candidate: bound by memory bandwidth
+    gen_bytes = 64 * samples + 24 * nval + gb.n + 4 * queued
+    gen_a = gen_bytes / (gen_ms * 1e-3) if gen_ms > 0 else 0.0
+    efile = os.path.join(ROOT, "profiles", "edge_grad_%s_pmc.md" % w.name)
     return {"edge_spp": EDGE_SPP, "edges": n_edges, "edge_build_ms": build_ms, "ms": ms,
             "edge_samples_per_s": samples / (ms * 1e-3), "samples": samples,
             "silhouette_rays": queued, "silhouette_rays_blocked": stats["rays_hit"],
             "sharp_gain_64": {"ms": ms64, "silhouette_rays": stats64["rays_traced"],
                               "silhouette_rays_blocked": stats64["rays_hit"]},
-            "roofline": {"bound": "alu", "achieved": a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
-                         "frac": a / VALU_PEAK, "traffic": measured_traffic(EDGE_TRAFFIC_FILE, EDGE_SOURCES,
-                                                                            "traffic-bytes-per-call"),
-                         "ops_per_launch": ops,
+            "roofline": {"bound": "hbm", "achieved": gen_a / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                         "frac": gen_a / HBM_PEAK,
+                         "traffic": measured_traffic(efile, EDGE_SOURCES, "sample-kernel-bytes-per-call"),
+                         "kernel": "edge_gen_kernel", "kernel_ms": gen_ms, "passes": passes,
+                         "bytes_per_call": gen_bytes},
+            "call_alu": {"bound": "alu", "achieved": a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
+                         "frac": a / VALU_PEAK,
+                         "traffic": measured_traffic(efile, EDGE_SOURCES, "traffic-bytes-per-call"),
+                         "ops_per_call": ops,
                          "note": "whole call, uniform edge choice: classes and corners packed, sample kernel, "
                                  "out-side-ray kernel"}}
 
@@ -395,11 +477,9 @@ def next_rows(args, M, gb, c_d, c_s, target, timed):
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_rays_sphere8_grad_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_03380_amd", "csrc", f)
                   for f in ("shade.hip", "shade_common.h", "device_common.h", "mcdi_internal.h", "bvh_build.hip")]
 # the edge-gradient call's kernels (classes, packing, samples, out-side rays)
-EDGE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "edge_grad_sphere8_grad_pmc.md")
 EDGE_SOURCES = [os.path.join(ROOT, "paper_2206_03380_amd", "csrc", f)
                 for f in ("edge_grad.hip", "edge_internal.h", "shade_common.h", "device_common.h", "mcdi_internal.h")]
 
@@ -412,7 +492,7 @@ def kernel_source_hash(files=None):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path=TRAFFIC_FILE, files=None, key="traffic-bytes-per-launch"):
+def measured_traffic(path, files=None, key="traffic-bytes-per-launch"):
     """HBM bytes per launch (or per call) from a committed FETCH_SIZE /
     WRITE_SIZE summary, scaled by the copy-kernel calibration; None when the
     kernel sources changed since the counters were taken."""
@@ -462,18 +542,22 @@ def _serve_run(M, make_system, requests, arrivals):
             "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99), "launches": sysm.n_launches}
 
 
-def _serving_compare(args, M, resident, requests, label, fracs=(0.7,), warm=10):
+def _serving_compare(args, M, resident, requests, label, fracs=(0.5, 0.7, 0.9), warm=10):
     import numpy as np
     from paper_2206_03380_amd.serve import Server, PerRequest
     from workloads.serving import poisson_arrivals
     mk_srv = lambda: Server(resident, budget_bytes=64 << 30, max_slots=64, spp_max=32)  # noqa: E731
     mk_base = lambda: PerRequest(resident)  # noqa: E731
-    # warm-up, then the saturated rate: everything arrives at once
+    # warm-up, then the saturated rates: everything arrives at once
     _serve_run(M, mk_srv, requests[:warm], np.zeros(warm))
     _serve_run(M, mk_base, requests[:warm], np.zeros(warm))
     sat = _serve_run(M, mk_srv, requests, np.zeros(len(requests)))
+    sat_base = _serve_run(M, mk_base, requests, np.zeros(len(requests)))
     rate = sat["requests"] / sat["wall_s"]
-    out = {"workload": label, "saturated_requests_per_s": rate, "saturated_samples_per_s": sat["samples_per_s"],
+    out = {"workload": label, "requests_per_load": len(requests), "budget_bytes": 64 << 30, "slots": 64,
+           "saturated": {"batched": {"requests_per_s": rate, "samples_per_s": sat["samples_per_s"]},
+                         "per_request_launches": {"requests_per_s": sat_base["requests"] / sat_base["wall_s"],
+                                                  "samples_per_s": sat_base["samples_per_s"]}},
            "loads": []}
     for f in fracs:
         arr = poisson_arrivals(len(requests), f * rate)
@@ -483,48 +567,13 @@ def _serving_compare(args, M, resident, requests, label, fracs=(0.7,), warm=10):
     return out
 
 
-def serve_quick(args, M, w, gb):
-    """Short serving run on the main scene: each request is one 512x512 view
-    with spp in {4, 8, 16, 32}, forward or forward+backward (50/50), Poisson
-    arrivals at 0.7x the batched saturated rate; same requests through plain
-    per-request launches."""
-    import numpy as np
-    import torch
-    from paper_2206_03380_amd.serve import Request
-    from workloads import upstream_grads
-    dev = "cuda:0"
-    resident = {"main": (M.Scene(torch.from_numpy(w.verts).to(dev), torch.from_numpy(w.tris).to(dev)),
-                         M.Env(torch.from_numpy(w.env).to(dev)))}
-    hw = w.height * w.width
-    ud, us = upstream_grads(w)
-    rng = np.random.Generator(np.random.PCG64(5))
-    views = []
-    for v in range(w.n_views):
-        sl = slice(v * hw, (v + 1) * hw)
-        g1 = M.GBuffer(gb.pos[:, sl].contiguous(), gb.nrm[:, sl].contiguous(), gb.kd[:, sl].contiguous(),
-                       gb.korm[:, sl].contiguous(), gb.mask[sl].contiguous(), gb.eye[v:v + 1].contiguous(), 1,
-                       w.height, w.width, v)
-        views.append((g1, torch.from_numpy(np.ascontiguousarray(ud[:, sl])).to(dev),
-                      torch.from_numpy(np.ascontiguousarray(us[:, sl])).to(dev), int(w.mask[sl].sum())))
-    reqs = []
-    for i in range(120):
-        v = int(rng.integers(w.n_views))
-        g1, gd, gs, nv = views[v]
-        r = Request(scene="main", gb=g1, spp=int(rng.choice([4, 8, 16, 32])), seed=i, tau=w.tau,
-                    ray_eps=w.ray_eps)
-        if rng.random() < 0.5:
-            r.g_cd, r.g_cs = gd, gs
-        r._valid = nv
-        reqs.append(r)
-    torch.cuda.synchronize()
-    return _serving_compare(args, M, resident, reqs, "one 512x512 view of the main scene per request")
-
-
-def serve_full(args, M):
+def serve_mix(args, M, n_requests):
     """Serving mix: resident scenes of ~50k, ~298k and ~1.0M triangles (probes
     512x256 to 2048x1024); requests draw scene, resolution in {128..1024}^2,
-    spp in {4, 8, 16, 32}, forward or forward+backward; Poisson arrivals at
-    0.5/0.7/0.9 of the saturated request rate."""
+    spp in {4, 8, 16, 32}, forward or forward+backward; the saturated request
+    rate of batched persistent launches and of one launch per request, then
+    Poisson arrivals at 0.5/0.7/0.9 of the batched saturated rate through
+    both (the same requests and seeds, hence identical results)."""
     import torch
     from paper_2206_03380_amd.serve import Request
     from workloads import serving, upstream_grads
@@ -542,7 +591,8 @@ def serve_full(args, M):
             ud, us = upstream_grads(w)
             gbs[(name, res)] = (M.GBuffer.from_workload(w, dev), torch.from_numpy(ud).to(dev),
                                 torch.from_numpy(us).to(dev), w.n_valid, w.tau, w.ray_eps)
-    draws = serving.make_requests(scenes_np, args.serve_requests + 50)
+    warm = 50
+    draws = serving.make_requests(scenes_np, n_requests + warm)
     reqs = []
     for (name, res, spp, grad, vb) in draws:
         gb, gd, gs, nv, tau, eps = gbs[(name, res)]
@@ -553,8 +603,8 @@ def serve_full(args, M):
         r._valid = nv
         reqs.append(r)
     torch.cuda.synchronize()
-    out = _serving_compare(args, M, resident, reqs[50:], "three-scene serving mix (50k/298k/1.0M triangles)",
-                           fracs=(0.5, 0.7, 0.9), warm=50)
+    out = _serving_compare(args, M, resident, reqs[warm:], "three-scene serving mix (50k/298k/1.0M triangles)",
+                           warm=warm)
     out["metric"] = METRIC
     out["tris"] = {n: int(len(next(iter(v.values())).tris)) for n, v in scenes_np.items()}
     return out
@@ -586,7 +636,8 @@ def cpu_baseline(args, w):
     dt = run(n)
     n2 = int(min(len(valid), max(n, n * args.cpu_seconds / max(dt, 1e-3))))
     dt2 = run(n2)
-    what = "all %d valid pixels" % n2 if n2 == len(valid) else "%d random valid pixels" % n2
+    what = ("all %d valid pixels" % n2 if n2 == len(valid) else
+            "%d random valid pixels of the %d (rate extrapolated to the whole workload)" % (n2, len(valid)))
     res = {"value": n2 * w.spp / dt2, "unit": "samples/s", "cores": nthreads, "kind": "oracle",
            "sample": "%s of the same workload, forward + backward, %.1f s" % (what, dt2)}
     n1 = int(min(len(valid), 8192))
@@ -596,15 +647,16 @@ def cpu_baseline(args, w):
     if not args.no_next_rows:
         # the oracle's edge-sampled visibility gradient beside the kernels' (row f4)
         edges = oracle.mesh_edges(w.tris, len(w.verts))
-        # every valid pixel: the same work as the kernels' measurement
+        # up to 2^18 random valid pixels (all of them on smaller workloads)
+        pe = valid if len(valid) <= (1 << 18) else np.sort(rng.choice(valid, 1 << 18, replace=False))
         t = time.time()
-        oracle.edge_grad(w, edges, EDGE_SPP, ud[:, valid].astype(np.float64), us[:, valid].astype(np.float64),
-                         pixels=valid, scene=scene, tables=tables)
+        oracle.edge_grad(w, edges, EDGE_SPP, ud[:, pe].astype(np.float64), us[:, pe].astype(np.float64),
+                         pixels=pe, scene=scene, tables=tables)
         dte = time.time() - t
-        res["visibility_gradient"] = {"value": len(valid) * EDGE_SPP / dte, "unit": "edge samples/s",
+        res["visibility_gradient"] = {"value": len(pe) * EDGE_SPP / dte, "unit": "edge samples/s",
                                       "cores": nthreads, "kind": "oracle",
-                                      "sample": "all %d valid pixels x %d edge samples, %.2f s" % (
-                                          len(valid), EDGE_SPP, dte)}
+                                      "sample": "%d of the %d valid pixels x %d edge samples, %.2f s" % (
+                                          len(pe), len(valid), EDGE_SPP, dte)}
     return res
 
 

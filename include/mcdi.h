@@ -187,6 +187,9 @@ typedef struct {
  * of 3 -- the parity protocol compares them with the oracle's. */
 #define MCDI_FLAG_DUMP_DIRS   (1u << 10)
 #define MCDI_FLAG_TIME_TRACE  (1u << 9) /* bracket the traversal kernel with HIP events */
+#define MCDI_FLAG_TIME_ADJOINT (1u << 11) /* bracket the adjoint kernel of mcdi_shade_bwd, and the
+                                             edge-sample kernel of each pass of mcdi_shade_bwd_edges,
+                                             with HIP events */
 
 typedef struct {
     int32_t spp;            /* samples per pixel, 1..1024; each = 1 light + 1 BSDF sample */
@@ -443,11 +446,17 @@ mcdi_status mcdi_server_launch(mcdi_server server, const mcdi_serve_item* items,
 void mcdi_server_destroy(mcdi_server server);
 
 /* Durations (ms) of the traversal kernels of the calls made with
- * MCDI_FLAG_TIME_TRACE on this thread since the previous mcdi_trace_times
- * call, oldest first (at most 1024 are kept).  Synchronises on their end
+ * MCDI_FLAG_TIME_TRACE in this process (from any thread) since the previous
+ * mcdi_trace_times call, oldest first (at most 1024 are kept).  Synchronises on their end
  * events, copies at most cap values to out, stores the count in *n and
  * forgets them. */
 mcdi_status mcdi_trace_times(float* out, int32_t cap, int32_t* n);
+
+/* The same for the kernels bracketed by MCDI_FLAG_TIME_ADJOINT: the adjoint
+ * kernel of mcdi_shade_bwd (the evaluation kernel only, not the
+ * probe-gradient scatter that follows it) and the edge-sample kernel of each
+ * pass of mcdi_shade_bwd_edges, in call order. */
+mcdi_status mcdi_adjoint_times(float* out, int32_t cap, int32_t* n);
 
 /* Thread-local text of the last non-OK status ("" if none). */
 const char* mcdi_last_error(void);

@@ -12,7 +12,7 @@ import torch
 
 from . import _lib as L
 from ._lib import (MCDIError, FLAG_LIGHT_OFF, FLAG_FORCE_COS, FLAG_BSDF_OFF, FLAG_FORCE_GGX, FLAG_BILINEAR,  # noqa: F401
-                   FLAG_DUMP, FLAG_DUMP_DIRS, FLAG_TIME_TRACE)
+                   FLAG_DUMP, FLAG_DUMP_DIRS, FLAG_TIME_TRACE, FLAG_TIME_ADJOINT)
 
 __all__ = ["Scene", "Env", "GBuffer", "Edges", "shade_fwd", "shade_bwd", "shade_bwd_edges", "trace_anyhit",
            "MCDIShade", "MCDIError", "new_stats", "read_stats"]
@@ -314,6 +314,16 @@ def trace_times():
     buf = (C.c_float * 1024)()
     n = C.c_int32()
     L.check(L.lib().mcdi_trace_times(buf, 1024, C.byref(n)))
+    return [buf[i] for i in range(n.value)]
+
+
+def adjoint_times():
+    """Adjoint-kernel durations (ms) of the backward calls made with
+    FLAG_TIME_ADJOINT since the previous call (HIP events on the launch
+    stream)."""
+    buf = (C.c_float * 1024)()
+    n = C.c_int32()
+    L.check(L.lib().mcdi_adjoint_times(buf, 1024, C.byref(n)))
     return [buf[i] for i in range(n.value)]
 
 

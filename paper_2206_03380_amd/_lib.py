@@ -20,6 +20,7 @@ FLAG_BILINEAR = 1 << 4
 FLAG_DUMP = 1 << 8
 FLAG_DUMP_DIRS = 1 << 10
 FLAG_TIME_TRACE = 1 << 9
+FLAG_TIME_ADJOINT = 1 << 11
 
 vp = C.c_void_p
 
@@ -104,6 +105,8 @@ def lib():
     L.mcdi_trace_anyhit.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int32, vp]
     L.mcdi_trace_times.restype = C.c_int
     L.mcdi_trace_times.argtypes = [C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
+    L.mcdi_adjoint_times.restype = C.c_int
+    L.mcdi_adjoint_times.argtypes = [C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
     L.mcdi_server_create.restype = C.c_int
     L.mcdi_server_create.argtypes = [C.c_int32, C.c_int32, vp, vp, C.POINTER(vp)]
     L.mcdi_server_launch.restype = C.c_int
@@ -146,7 +149,7 @@ def check(status):
 
 EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_scene_nodes", "mcdi_build_env_cdf",
             "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
-            "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_server_create", "mcdi_server_launch",
+            "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_adjoint_times", "mcdi_server_create", "mcdi_server_launch",
             "mcdi_server_destroy", "mcdi_image_loss", "mcdi_image_loss_noalloc", "mcdi_bilateral_radius", "mcdi_bilateral_fwd",
             "mcdi_bilateral_bwd", "mcdi_view_depth", "mcdi_build_edges", "mcdi_destroy_edges", "mcdi_edges_count",
             "mcdi_edges_copy", "mcdi_shade_bwd_edges", "mcdi_last_error", "mcdi_version")

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -48,7 +49,37 @@ struct TraceTimer {
         return &pool[used++];
     }
 };
-thread_local TraceTimer g_timer;
+// Process-wide (a framework may run the backward pass on a thread of its
+// own), guarded by g_timer_mu.
+TraceTimer g_timer;       // traversal kernels (MCDI_FLAG_TIME_TRACE)
+TraceTimer g_timer_adj;   // adjoint and edge-sample kernels (MCDI_FLAG_TIME_ADJOINT)
+std::mutex g_timer_mu;
+
+std::pair<hipEvent_t, hipEvent_t>* timer_next(TraceTimer& t) {
+    std::lock_guard<std::mutex> lock(g_timer_mu);
+    return t.next();
+}
+
+mcdi_status fail(mcdi_status st, const char* fmt, ...);
+
+mcdi_status drain_times(TraceTimer& t, float* out, int32_t cap, int32_t* n, const char* who) {
+    std::lock_guard<std::mutex> lock(g_timer_mu);
+    int32_t k = 0;
+    for (int i = 0; i < t.used; ++i) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(t.pool[i].second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.pool[i].first, t.pool[i].second);
+        if (e != hipSuccess) {
+            t.used = 0;
+            return fail(MCDI_E_DEVICE, "%s: %s", who, hipGetErrorString(e));
+        }
+        if (k < cap) out[k] = ms;
+        ++k;
+    }
+    t.used = 0;
+    *n = k < cap ? k : cap;
+    return MCDI_OK;
+}
 
 mcdi_status fail(mcdi_status st, const char* fmt, ...) {
     char buf[512];
@@ -150,21 +181,14 @@ const char* mcdi_last_error(void) { return g_err.c_str(); }
 
 mcdi_status mcdi_trace_times(float* out, int32_t cap, int32_t* n) {
     if (!n || (cap > 0 && !out)) return fail(MCDI_E_INVALID, "mcdi_trace_times: NULL argument");
-    int32_t k = 0;
-    for (int i = 0; i < g_timer.used; ++i) {
-        float ms = 0.0f;
-        hipError_t e = hipEventSynchronize(g_timer.pool[i].second);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_timer.pool[i].first, g_timer.pool[i].second);
-        if (e != hipSuccess) {
-            g_timer.used = 0;
-            return fail(MCDI_E_DEVICE, "mcdi_trace_times: %s", hipGetErrorString(e));
-        }
-        if (k < cap) out[k] = ms;
-        ++k;
-    }
-    g_timer.used = 0;
-    *n = k < cap ? k : cap;
-    return ok();
+    mcdi_status st = drain_times(g_timer, out, cap, n, "mcdi_trace_times");
+    return st == MCDI_OK ? ok() : st;
+}
+
+mcdi_status mcdi_adjoint_times(float* out, int32_t cap, int32_t* n) {
+    if (!n || (cap > 0 && !out)) return fail(MCDI_E_INVALID, "mcdi_adjoint_times: NULL argument");
+    mcdi_status st = drain_times(g_timer_adj, out, cap, n, "mcdi_adjoint_times");
+    return st == MCDI_OK ? ok() : st;
 }
 
 const char* mcdi_version(void) { return "mcdi 0.1 gfx950"; }
@@ -400,7 +424,7 @@ static mcdi_status trace_pipeline(const char* who, mcdi_scene sc, ShadeArgs& a, 
     if (e == hipSuccess && a.tau != 0.0f) e = scene_acquire(sc, s);
     std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
     if ((a.flags & MCDI_FLAG_TIME_TRACE) && e == hipSuccess && a.tau != 0.0f) {
-        ev = g_timer.next();
+        ev = timer_next(g_timer);
         if (ev) e = hipEventRecord(ev->first, s);
     }
     if (e == hipSuccess && a.tau != 0.0f) e = launch_trace_rays(a, bits, s);
@@ -479,7 +503,13 @@ mcdi_status mcdi_shade_bwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, co
         }
     }
     hipError_t e = a.rec ? launch_env_scatter_init(es, s) : hipSuccess;
+    std::pair<hipEvent_t, hipEvent_t>* tev = nullptr;
+    if ((a.flags & MCDI_FLAG_TIME_ADJOINT) && e == hipSuccess) {
+        tev = timer_next(g_timer_adj);
+        if (tev) e = hipEventRecord(tev->first, s);
+    }
     if (e == hipSuccess) e = launch_shade_bwd(a, s);
+    if (tev && e == hipSuccess) e = hipEventRecord(tev->second, s);
     if (e == hipSuccess && a.rec) e = launch_env_scatter(es, s);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd: %s", hipGetErrorString(e));
     return ok();
@@ -591,7 +621,7 @@ mcdi_status mcdi_server_launch(mcdi_server sv, const mcdi_serve_item* items, int
         st = fill_common("mcdi_server_launch", it.scene, it.env, &it.gbuf, &it.params, a);
         if (st != MCDI_OK) return st;
         if (it.params.spp > sv->spp_max) return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d spp > spp_max", i);
-        if (it.params.flags & (MCDI_FLAG_DUMP | MCDI_FLAG_TIME_TRACE))
+        if (it.params.flags & (MCDI_FLAG_DUMP | MCDI_FLAG_TIME_TRACE | MCDI_FLAG_TIME_ADJOINT))
             return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d: dump/timing flags are not served", i);
         if (!it.c_d || !it.c_s || !it.hitbits || !it.origins)
             return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d: NULL output or scratch", i);
@@ -893,7 +923,8 @@ mcdi_status mcdi_shade_bwd_edges(mcdi_scene sc, mcdi_env ev, mcdi_edges ed, cons
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {
         E.pix0 = p0;
         E.npix = n - p0 < chunk ? n - p0 : chunk;
-        hipError_t e = launch_edge_grad(E, s);
+        std::pair<hipEvent_t, hipEvent_t>* tev = (a.flags & MCDI_FLAG_TIME_ADJOINT) ? timer_next(g_timer_adj) : nullptr;
+        hipError_t e = tev ? launch_edge_grad(E, s, tev->first, tev->second) : launch_edge_grad(E, s);
         if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_bwd_edges: %s", hipGetErrorString(e));
     }
     hipError_t re = scene_release(sc, s);

@@ -552,10 +552,18 @@ hipError_t launch_edge_pack(const EdgeArgs& e, uint32_t cap, uint32_t* bsum, uin
     return hipGetLastError();
 }
 
-hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s) {
+hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s, hipEvent_t gen_begin, hipEvent_t gen_end) {
     if (e.npix <= 0) return hipSuccess;
     hipLaunchKernelGGL(edge_queue_reset, dim3(1), dim3(1), 0, s, e.q_count);
+    if (gen_begin) {
+        const hipError_t r = hipEventRecord(gen_begin, s);
+        if (r != hipSuccess) return r;
+    }
     hipLaunchKernelGGL(edge_gen_kernel, dim3((unsigned)((e.npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, e);
+    if (gen_end) {
+        const hipError_t r = hipEventRecord(gen_end, s);
+        if (r != hipSuccess) return r;
+    }
     // the queue's length is on the device: a fixed grid of 8192 wavefronts
     // strides over it (one record per wavefront or per lane)
     hipLaunchKernelGGL(edge_trace_kernel, dim3(2048), dim3(256), 0, s, e);

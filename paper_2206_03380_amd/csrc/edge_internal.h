@@ -36,7 +36,10 @@ struct EdgeArgs {
 };
 
 // one pass of the edge-sampled visibility gradient over [pix0, pix0 + npix)
-hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s);
+// gen_begin / gen_end (or null): events recorded right before and after the
+// edge-sample kernel
+hipError_t launch_edge_grad(const EdgeArgs& e, hipStream_t s, hipEvent_t gen_begin = nullptr,
+                            hipEvent_t gen_end = nullptr);
 // classifies the edges and packs their corners into e.egeo, sharp edges
 // first (cap >= E); bsum: [edge_pack_blocks(cap)] block sums
 uint32_t edge_pack_blocks(uint32_t cap);

@@ -16,7 +16,10 @@ Per-pixel arrays are planar [C][N] float32 with N = views*H*W and pixel id
 Random streams are numpy PCG64(1000 + k) for workload k.
 """
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
+
 import numpy as np
 
 from . import meshes
@@ -211,14 +214,15 @@ def make_sphere8(k=1, H=512, W=512, spp=8, n_views=8, freq=71, views=None, env_h
     rng, ds, boxes, verts, tris, env, tex_kd, tex_orm = scene
     surfaces = [ds.intersect] + [
         (lambda c, h, y: (lambda o, d: hit_box(o, d, c, h, y)))(c, h, y) for (c, h, y) in boxes]
-    eyes, hv = [], []
+    eyes = []
     view_ids = range(n_views) if views is None else views
     for v in view_ids:
         az = np.radians(45.0 * v)
         el = np.radians(15.0 if v % 2 == 0 else 35.0)
-        eye = 4.0 * np.array([np.cos(el) * np.cos(az), np.sin(el), np.cos(el) * np.sin(az)])
-        eyes.append(eye)
-        hv.append(_cast(eye, [0, 0, 0], 40.0, H, W, surfaces))
+        eyes.append(4.0 * np.array([np.cos(el) * np.cos(az), np.sin(el), np.cos(el) * np.sin(az)]))
+    # views are independent: cast them on threads (numpy releases the GIL)
+    with ThreadPoolExecutor(max(1, min(len(eyes), os.cpu_count() or 1))) as ex:
+        hv = list(ex.map(lambda e: _cast(e, [0, 0, 0], 40.0, H, W, surfaces), eyes))
 
     def materials(pos, mask):
         a = spherical_lookup(tex_kd, pos)
