@@ -8,9 +8,7 @@ intersects the beams of each cell's 12 edges; the room walls are planes with
 rectangular holes.  Closest hit only (primary visibility).
 """
 
-import multiprocessing
 import os
-from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
@@ -173,18 +171,48 @@ def _cast_chunk(args):
     return t1, n1, t2, n2
 
 
+def _worker_main():
+    """Worker process: read one chunk's arguments (pickled by the parent, this
+    package's own arrays) from stdin, write its hits to stdout."""
+    import pickle
+    import sys
+    args = pickle.load(sys.stdin.buffer)
+    pickle.dump(_cast_chunk(args), sys.stdout.buffer, protocol=pickle.HIGHEST_PROTOCOL)
+    sys.stdout.buffer.flush()
+
+
 def cast_scene(o, d, kx, ky, kz, cells, half, workers=None):
     """Closest hits against the beams and the room of every ray, in parallel
     chunks of rays (every ray's result depends only on that ray, so the
-    chunking does not change it): (t_beams, n_beams, t_room, n_room)."""
+    chunking does not change it): (t_beams, n_beams, t_room, n_room).  The
+    chunks run in fresh worker processes that import only this package (the
+    calling program is not re-imported, and no process is forked from one that
+    may hold a GPU context)."""
+    import pickle
+    import subprocess
+    import sys
     n = len(d)
     workers = workers or min(16, os.cpu_count() or 1)
     if workers <= 1 or n < 65536:
         return _cast_chunk((o, d, kx, ky, kz, cells, half))
-    parts = np.array_split(np.arange(n), 2 * workers)
-    ctx = multiprocessing.get_context("spawn")
-    with ProcessPoolExecutor(workers, mp_context=ctx) as ex:
-        res = list(ex.map(_cast_chunk, [(o[p], d[p], kx, ky, kz, cells, half) for p in parts]))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    env["PYTHONPATH"] = root + (os.pathsep + env["PYTHONPATH"] if env.get("PYTHONPATH") else "")
+    parts = np.array_split(np.arange(n), workers)
+    procs = []
+    for p in parts:
+        pr = subprocess.Popen([sys.executable, "-c", "from workloads.lattice import _worker_main; _worker_main()"],
+                              stdin=subprocess.PIPE, stdout=subprocess.PIPE, env=env, cwd=root)
+        pickle.dump((o[p], d[p], kx, ky, kz, cells, half), pr.stdin, protocol=pickle.HIGHEST_PROTOCOL)
+        pr.stdin.close()
+        procs.append(pr)
+    res = []
+    for pr in procs:
+        out = pickle.load(pr.stdout)
+        pr.stdout.close()
+        if pr.wait() != 0:
+            raise RuntimeError("lattice casting worker failed")
+        res.append(out)
     return tuple(np.concatenate([r[k] for r in res]) for k in range(4))
 
 

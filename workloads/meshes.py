@@ -90,7 +90,7 @@ def box(center, half, yaw=0.0):
                         for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], dtype=np.float64)
     cy, sy = np.cos(yaw), np.sin(yaw)
     rot = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
-    v = corners @ rot.T + c
+    v = corners[:, 0, None] * rot.T[0] + corners[:, 1, None] * rot.T[1] + corners[:, 2, None] * rot.T[2] + c
     # corner index = 4*ix + 2*iy + iz
     f = np.array([
         [0, 1, 3], [0, 3, 2],   # -x

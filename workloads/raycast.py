@@ -8,6 +8,13 @@ tessellate.  Closest hit only; this is not the estimator's shadow-ray test.
 import numpy as np
 
 
+def mat3(a, m):
+    """a [N, 3] times m [3, K] as an explicit sum over the three terms, in a
+    fixed order: the result does not depend on how many threads a BLAS
+    library happens to use (the generated inputs are bit-reproducible)."""
+    return a[:, 0, None] * m[0] + a[:, 1, None] * m[1] + a[:, 2, None] * m[2]
+
+
 def look_at_rays(eye, target, fov_deg, height, width, up=(0.0, 1.0, 0.0)):
     """Unit ray directions through pixel centres, row-major (y down)."""
     eye = np.asarray(eye, np.float64)
@@ -74,8 +81,8 @@ def hit_box(o, d, center, half, yaw=0.0):
     c = np.asarray(center, np.float64)
     cy, sy = np.cos(yaw), np.sin(yaw)
     rot = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])  # local -> world
-    ol = (o - c) @ rot
-    dl = d @ rot
+    ol = mat3(o - c, rot)
+    dl = mat3(d, rot)
     half = np.asarray(half, np.float64)
     with np.errstate(divide="ignore", invalid="ignore"):
         inv = 1.0 / dl
@@ -97,7 +104,7 @@ def hit_box(o, d, center, half, yaw=0.0):
     rows = np.arange(len(d))
     sgn = np.where(tn > 1e-9, -np.sign(dl[rows, ax]), np.sign(dl[rows, ax]))
     nl[rows, ax] = sgn
-    return t, nl @ rot.T
+    return t, mat3(nl, rot.T)
 
 
 class DisplacedSphere:
@@ -113,7 +120,7 @@ class DisplacedSphere:
         self.n_waves = n_waves
 
     def noise(self, dirs):
-        arg = (dirs @ self.u.T) * self.freq + self.phase
+        arg = mat3(dirs, self.u.T) * self.freq + self.phase
         return np.sin(arg).sum(-1) / self.n_waves
 
     def radius(self, dirs):
@@ -126,9 +133,9 @@ class DisplacedSphere:
     def grad(self, x):
         r = np.linalg.norm(x, axis=-1, keepdims=True)
         xh = x / r
-        arg = (xh @ self.u.T) * self.freq + self.phase
+        arg = mat3(xh, self.u.T) * self.freq + self.phase
         c = np.cos(arg) * self.freq / self.n_waves  # d noise / d(xh.u_k)
-        proj = self.u[None, :, :] - (xh @ self.u.T)[:, :, None] * xh[:, None, :]
+        proj = self.u[None, :, :] - mat3(xh, self.u.T)[:, :, None] * xh[:, None, :]
         dn = (c[:, :, None] * proj).sum(1) / r
         return xh - self.amp * dn
 
