@@ -71,7 +71,11 @@ typedef struct {
  * verts   device float32 [n_verts][3]
  * tris    device int32   [n_tris][3], vertex indices
  * Builds a bounding-volume hierarchy on the device (Morton-ordered linear BVH,
- * leaves of <= 4 triangles, depth-first node order with skip links).
+ * leaves of <= 4 triangles, depth-first node order with skip links), and a
+ * copy of its nodes for the shadow-ray traversal whose boxes are quantised
+ * outward to 16 bits per coordinate against the scene's bounding box (16
+ * bytes per node, one load per box test; a box grows by at most 1/65535 of
+ * the scene's extent per side, which costs box tests, never a wrong answer).
  * A triangle with an index outside [0, n_verts) or a non-finite vertex is
  * replaced by a degenerate triangle that no ray hits (counted in
  * mcdi_scene_info).  n_tris = 0 gives a scene every ray misses.

@@ -136,6 +136,8 @@ struct mcdi_scene_s {
     int64_t n_tris = 0;
     Node* nodes = nullptr;
     float4* tris = nullptr;
+    QNode* qnodes = nullptr;
+    QFrame* frame = nullptr;
     DeviceSceneInfo* info = nullptr;
     hipEvent_t built = nullptr;     // recorded on the build stream after the build
     hipEvent_t last_use = nullptr;  // recorded after the last enqueued work that reads the scene
@@ -211,8 +213,10 @@ mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t*
     const size_t n_nodes = n_tris > 0 ? (size_t)(2 * n_tris - 1) : 1;
     sc->nodes = (Node*)sc->alloc.get(sizeof(Node) * n_nodes, s);
     sc->tris = (float4*)sc->alloc.get(sizeof(float4) * 3 * (size_t)(n_tris > 0 ? n_tris : 1), s);
+    sc->qnodes = (QNode*)sc->alloc.get(sizeof(QNode) * n_nodes, s);
+    sc->frame = (QFrame*)sc->alloc.get(sizeof(QFrame), s);
     sc->info = (DeviceSceneInfo*)sc->alloc.get(sizeof(DeviceSceneInfo), s);
-    if (!sc->nodes || !sc->tris || !sc->info) {
+    if (!sc->nodes || !sc->tris || !sc->qnodes || !sc->frame || !sc->info) {
         mcdi_destroy_scene(sc);
         return fail(MCDI_E_OOM, "mcdi_build_scene: device allocation failed (%lld triangles)", (long long)n_tris);
     }
@@ -224,7 +228,8 @@ mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t*
     }
     TempAlloc ta{temp_alloc, temp_free, &sc->alloc};
     int oom = 0;
-    hipError_t e = build_bvh(verts, n_verts, tris, n_tris, sc->nodes, sc->tris, sc->info, ta, s, &oom);
+    hipError_t e = build_bvh(verts, n_verts, tris, n_tris, sc->nodes, sc->tris, sc->qnodes, sc->frame, sc->info, ta,
+                             s, &oom);
     if (e == hipSuccess) e = hipEventRecord(sc->built, s);
     if (e != hipSuccess) {
         mcdi_destroy_scene(sc);
@@ -242,6 +247,8 @@ void mcdi_destroy_scene(mcdi_scene sc) {
     if (sc->used) (void)hipStreamWaitEvent(sc->stream, sc->last_use, 0);
     sc->alloc.put(sc->nodes, sc->stream);
     sc->alloc.put(sc->tris, sc->stream);
+    sc->alloc.put(sc->qnodes, sc->stream);
+    sc->alloc.put(sc->frame, sc->stream);
     sc->alloc.put(sc->info, sc->stream);
     if (sc->built) (void)hipEventDestroy(sc->built);
     if (sc->last_use) (void)hipEventDestroy(sc->last_use);
@@ -366,7 +373,7 @@ static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, cons
     if ((p->flags & MCDI_FLAG_FORCE_COS) && (p->flags & MCDI_FLAG_FORCE_GGX))
         return fail(MCDI_E_INVALID, "%s: FORCE_COS and FORCE_GGX together", who);
     std::memset(&a, 0, sizeof(a));
-    a.scene = Scene{sc->nodes, sc->tris, sc->n_tris};
+    a.scene = Scene{sc->nodes, sc->tris, sc->n_tris, sc->qnodes, sc->frame};
     a.env = EnvView{ev->H, ev->W, ev->cond, ev->marg, ev->light, ev->hot_slot, ev->hot_texel, ev->n_hot, ev->guide,
                     ev->G, ev->tex};
     a.g = GBufView{g->n_views, g->height, g->width, g->view_base, g->pos, g->nrm, g->kd, g->korm, g->mask, g->eye, n};
@@ -773,7 +780,7 @@ mcdi_status mcdi_trace_anyhit(mcdi_scene sc, const float* orig, const float* dir
     if (n > 0 && (!orig || !dir || !hit)) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: NULL buffer");
     hipError_t e = scene_acquire(sc, (hipStream_t)stream);
     if (e == hipSuccess)
-        e = launch_trace(Scene{sc->nodes, sc->tris, sc->n_tris}, orig, dir, n, hit, brute, (hipStream_t)stream);
+        e = launch_trace(Scene{sc->nodes, sc->tris, sc->n_tris, sc->qnodes, sc->frame}, orig, dir, n, hit, brute, (hipStream_t)stream);
     if (e == hipSuccess) e = scene_release(sc, (hipStream_t)stream);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_trace_anyhit: %s", hipGetErrorString(e));
     return ok();

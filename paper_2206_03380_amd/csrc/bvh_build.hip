@@ -384,7 +384,53 @@ __global__ __launch_bounds__(256) void fit_top(int nt, Tree T) {
     T.cnt[p] = 2 * (leaves_before(T, nt, l + 1) - leaves_before(T, nt, f)) - 1;
 }
 
-__global__ __launch_bounds__(256) void emit(int nt, Tree T, Node* out, DeviceSceneInfo* info) {
+// Quantisation frame of the scene from its root box: base below the box and
+// a step such that base + 65535 step lies above it, both with a pad of
+// 2^-20 of the largest extent, base rounded down and step up to FP32.
+__device__ void qframe_of(float4 rlo, float4 rhi, QFrame& F) {
+    const double ext = fmax(fmax((double)rhi.x - rlo.x, (double)rhi.y - rlo.y), (double)rhi.z - rlo.z);
+    const double pad = fmax(ext * 0x1p-20, 1e-30);
+    const double lo[3] = {rlo.x, rlo.y, rlo.z}, hi[3] = {rhi.x, rhi.y, rhi.z};
+    for (int a = 0; a < 3; ++a) {
+        F.base[a] = __double2float_rd(lo[a] - pad);
+        F.step[a] = __double2float_ru((hi[a] + pad - (double)F.base[a]) / 65535.0);
+    }
+}
+
+// Outward 16-bit quantisation: the plane of q_lo is at or below lo, that of
+// q_hi at or above hi (exact in FP64: q * step needs at most 41 bits).  A
+// non-finite coordinate gives the whole range.
+__device__ uint32_t quant_lo(float v, float base, float step) {
+    if (!isfinite(v)) return 0u;
+    double q = floor(((double)v - base) / step);
+    q = fmin(fmax(q, 0.0), 65535.0);
+    while (q > 0.0 && (double)base + q * (double)step > (double)v) q -= 1.0;
+    return (uint32_t)q;
+}
+__device__ uint32_t quant_hi(float v, float base, float step) {
+    if (!isfinite(v)) return 65535u;
+    double q = ceil(((double)v - base) / step);
+    q = fmin(fmax(q, 0.0), 65535.0);
+    while (q < 65535.0 && (double)base + q * (double)step < (double)v) q += 1.0;
+    return (uint32_t)q;
+}
+
+__device__ QNode quantise(const QFrame& F, const Node& nd) {
+    uint32_t l[3], h[3];
+    for (int a = 0; a < 3; ++a) {
+        l[a] = quant_lo(nd.lo[a], F.base[a], F.step[a]);
+        h[a] = quant_hi(nd.hi[a], F.base[a], F.step[a]);
+    }
+    QNode q;
+    q.x = l[0] | (l[1] << 16);
+    q.y = l[2] | (h[0] << 16);
+    q.z = h[1] | (h[2] << 16);
+    q.w = nd.payload != 0 ? (kQLeaf | (uint32_t)nd.payload) : (uint32_t)nd.escape;
+    return q;
+}
+
+__global__ __launch_bounds__(256) void emit(int nt, Tree T, Node* out, QNode* qout, QFrame* frame,
+                                            DeviceSceneInfo* info) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= 2 * nt - 1) return;
     const bool is_prim = x >= nt - 1;
@@ -417,6 +463,11 @@ __global__ __launch_bounds__(256) void emit(int nt, Tree T, Node* out, DeviceSce
     nd.escape = idx + T.cnt[x];
     nd.payload = payload;
     out[idx] = nd;
+    // the root's box (internal node 0) sets the frame, the same for every thread
+    QFrame F;
+    qframe_of(T.box[0], T.box[1], F);
+    qout[idx] = quantise(F, nd);
+    if (idx == 0) *frame = F;
     atomicMax(&info->max_depth, depth);
     if (x == 0) info->n_nodes = T.cnt[0];
 }
@@ -431,7 +482,8 @@ __global__ void reorder(const float4* tmp, const uint32_t* vals, int64_t nt, flo
 }
 
 // scene of 0 or 1 triangles
-__global__ void tiny_scene(const float4* tmp, int nt, Node* out, float4* tris_out, DeviceSceneInfo* info) {
+__global__ void tiny_scene(const float4* tmp, int nt, Node* out, float4* tris_out, QNode* qout, QFrame* frame,
+                           DeviceSceneInfo* info) {
     Node nd;
     if (nt == 0) {
         for (int k = 0; k < 3; ++k) { nd.lo[k] = 0.0f; nd.hi[k] = 0.0f; }
@@ -449,6 +501,10 @@ __global__ void tiny_scene(const float4* tmp, int nt, Node* out, float4* tris_ou
         info->n_nodes = 1;
     }
     out[0] = nd;
+    QFrame F;
+    qframe_of(make_float4(nd.lo[0], nd.lo[1], nd.lo[2], 0.0f), make_float4(nd.hi[0], nd.hi[1], nd.hi[2], 0.0f), F);
+    qout[0] = quantise(F, nd);
+    *frame = F;
     info->max_depth = 0;
 }
 
@@ -464,7 +520,8 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_t nt64, Node* nodes_out,
-                     float4* tris_out, DeviceSceneInfo* info, const TempAlloc& ta, hipStream_t s, int* oom) {
+                     float4* tris_out, QNode* qnodes_out, QFrame* frame_out, DeviceSceneInfo* info,
+                     const TempAlloc& ta, hipStream_t s, int* oom) {
     *oom = 0;
     const int nt = (int)nt64;
     hipLaunchKernelGGL(init_info, dim3(1), dim3(1), 0, s, info);
@@ -524,7 +581,8 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
         hipLaunchKernelGGL(bounds_reduce, dim3(1), dim3(256), 0, s, part, (int)nblk(nt), cb);
     }
     if (nt <= 1) {
-        hipLaunchKernelGGL(tiny_scene, dim3(1), dim3(1), 0, s, tmp, nt, nodes_out, tris_out, info);
+        hipLaunchKernelGGL(tiny_scene, dim3(1), dim3(1), 0, s, tmp, nt, nodes_out, tris_out, qnodes_out, frame_out,
+                           info);
     } else {
         hipLaunchKernelGGL(morton, dim3(nblk(nt)), dim3(256), 0, s, tmp, (int64_t)nt, cb, keys, vals);
         err = rocprim::radix_sort_pairs(sort_tmp, sort_bytes, keys, keys2, vals, vals2, (size_t)nt, 0, 63, s);
@@ -537,7 +595,8 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
             hipLaunchKernelGGL(fit_block, dim3((unsigned)nb), dim3(kFitBlock), 0, s, tmp, vals2, nt, T);
             hipLaunchKernelGGL(block_table, dim3(1), dim3(1024), 0, s, T);
             hipLaunchKernelGGL(fit_top, dim3(nblk(nt - 1)), dim3(256), 0, s, nt, T);
-            hipLaunchKernelGGL(emit, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nt, T, nodes_out, info);
+            hipLaunchKernelGGL(emit, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nt, T, nodes_out, qnodes_out,
+                               frame_out, info);
             hipLaunchKernelGGL(reorder, dim3(nblk(nt)), dim3(256), 0, s, tmp, vals2, (int64_t)nt, tris_out);
         }
     }

@@ -191,6 +191,75 @@ __device__ __forceinline__ bool box_hit(const Ray& r, float4 a, float4 b) {
     return tn <= tf * 1.000001f;
 }
 
+// Slab constants of a ray against the scene's quantisation frame: the plane q
+// of axis a lies at base + q step, so t = q (step inv) + (base - o) inv, one
+// FMA per plane.  The offsets carry a margin of 2^-20 (65535 |step inv| +
+// |(base - o) inv|) -- sixteen times the roundings of the two products, the
+// difference and the FMA against the magnitudes involved -- on the side that
+// keeps near distances under- and far distances over-estimated.
+struct QRay {
+    float3 s, clo, chi;
+};
+
+__device__ __forceinline__ void qslab(float o, float inv, float base, float step, float& s, float& clo,
+                                      float& chi) {
+    s = step * inv;
+    const float c = (base - o) * inv;
+    const float e = 0x1p-20f * (fabsf(s) * 65535.0f + fabsf(c));
+    clo = inv >= 0.0f ? c - e : c + e;
+    chi = inv >= 0.0f ? c + e : c - e;
+}
+
+__device__ __forceinline__ QRay make_qray(const Ray& r, const QFrame& F) {
+    QRay q;
+    qslab(r.o.x, r.inv.x, F.base[0], F.step[0], q.s.x, q.clo.x, q.chi.x);
+    qslab(r.o.y, r.inv.y, F.base[1], F.step[1], q.s.y, q.clo.y, q.chi.y);
+    qslab(r.o.z, r.inv.z, F.base[2], F.step[2], q.s.z, q.clo.z, q.chi.z);
+    return q;
+}
+
+// The slab test of box_hit on a quantised node (the 16-bit coordinates
+// convert to FP32 exactly).
+__device__ __forceinline__ bool qbox_hit(const QRay& q, uint4 n) {
+    const float lx = (float)(n.x & 0xFFFFu), ly = (float)(n.x >> 16), lz = (float)(n.y & 0xFFFFu);
+    const float hx = (float)(n.y >> 16), hy = (float)(n.z & 0xFFFFu), hz = (float)(n.z >> 16);
+    const float tx0 = fmaf(lx, q.s.x, q.clo.x), tx1 = fmaf(hx, q.s.x, q.chi.x);
+    const float ty0 = fmaf(ly, q.s.y, q.clo.y), ty1 = fmaf(hy, q.s.y, q.chi.y);
+    const float tz0 = fmaf(lz, q.s.z, q.clo.z), tz1 = fmaf(hz, q.s.z, q.chi.z);
+    const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+    const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+    return tn <= tf * 1.000001f;
+}
+
+// Stackless any-hit traversal over the quantised nodes (the order and the
+// skip links of the pre-order BVH; a leaf's escape is the next node).
+template <bool COUNT = false>
+__device__ __forceinline__ bool qbvh_anyhit(const Scene& sc, const Ray& r, int n_total, uint32_t& n_box,
+                                            uint32_t& n_tri) {
+    const uint4* nodes = reinterpret_cast<const uint4*>(sc.qnodes);
+    const QRay q = make_qray(r, *sc.frame);
+    int i = 0;
+    while (i < n_total) {
+        const uint4 n = nodes[i];
+        const bool leaf = (n.w & kQLeaf) != 0u;
+        // skip links always point forward; anything else ends the walk
+        const int next = leaf ? i + 1 : ((int)n.w > i ? (int)n.w : n_total);
+        if (COUNT) ++n_box;
+        if (!qbox_hit(q, n)) { i = next; continue; }
+        if (!leaf) { ++i; continue; }
+        const uint32_t payload = n.w & ~kQLeaf;
+        const int first = (int)(payload >> 3);
+        const int cnt = (first + (int)(payload & 7u) <= sc.n_tris) ? (int)(payload & 7u) : 0;
+        for (int k = 0; k < cnt; ++k) {
+            const float4* t = sc.tris + 3 * (first + k);
+            if (COUNT) ++n_tri;
+            if (tri_anyhit(r, t[0], t[1], t[2])) return true;
+        }
+        i = next;
+    }
+    return false;
+}
+
 // Stackless any-hit traversal over the pre-order BVH with skip links.
 // COUNT: tally box tests and triangle tests (statistics instantiation only).
 template <bool COUNT = false>

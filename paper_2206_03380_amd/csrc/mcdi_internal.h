@@ -30,10 +30,30 @@ struct DeviceSceneInfo {
     int32_t pad;
 };
 
+// The scene's quantisation frame: node box coordinates as 16-bit integers q,
+// the plane q standing for base + q * step (per axis).
+struct QFrame {
+    float base[3];
+    float step[3];
+};
+
+// Compact node of the shadow-ray traversal (16 bytes, one load): the box of
+// the Node with the same index quantised against the frame outward (lo
+// rounded down, hi rounded up: it contains the exact box) and one link word.
+//   x = qlo.x | qlo.y << 16, y = qlo.z | qhi.x << 16, z = qhi.y | qhi.z << 16
+//   w = leaf: 0x80000000 | payload (first_triangle << 3 | count), its
+//       escape being the next index; internal: the escape index
+struct QNode {
+    uint32_t x, y, z, w;
+};
+constexpr uint32_t kQLeaf = 0x80000000u;
+
 struct Scene {
-    const Node* nodes;   // [>= 1]
-    const float4* tris;  // [3 * n_tris] vertex positions, w unused
+    const Node* nodes;    // [>= 1]
+    const float4* tris;   // [3 * n_tris] vertex positions, w unused
     int64_t n_tris;
+    const QNode* qnodes;  // [>= 1] the same nodes, quantised
+    const QFrame* frame;
 };
 
 struct EnvView {
@@ -196,7 +216,7 @@ struct TempAlloc {
     void* ctx;
 };
 hipError_t build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
-                     Node* nodes_out, float4* tris_out, DeviceSceneInfo* info, const TempAlloc& ta,
-                     hipStream_t s, int* oom);
+                     Node* nodes_out, float4* tris_out, QNode* qnodes_out, QFrame* frame_out,
+                     DeviceSceneInfo* info, const TempAlloc& ta, hipStream_t s, int* oom);
 
 }  // namespace mcdi

@@ -370,12 +370,14 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
     const int64_t base_pix = tile * kBlock;
     const int n_total = sc.nodes[0].escape;
     const uint32_t n_tris = (uint32_t)sc.n_tris;
-    const char* node_bytes = reinterpret_cast<const char*>(sc.nodes);
+    const uint4* qnodes = reinterpret_cast<const uint4*>(sc.qnodes);
+    const QFrame F = *sc.frame;
     const char* tri_bytes = reinterpret_cast<const char*>(sc.tris);
     const int lane = __lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool active = false, exhausted = false;
     Ray ray;
+    QRay qray;
     int node = n_total;
     uint32_t p0 = 0u, p1 = 0u;
     int64_t pix = 0;
@@ -402,6 +404,7 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
                     slot = (int)(tag >> 8);
                     const float4 o = A.origins[pix];
                     ray = make_ray(f3(o.x, o.y, o.z), f3(rr.x, rr.y, rr.z));
+                    qray = make_qray(ray, F);
                     node = 0;
                     p0 = p1 = 0u;
                     active = n_total > 0;
@@ -425,16 +428,16 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
                 const bool walking = node < n_total && p1 == 0u;
                 if (COUNT && __any(walking) && lane == 0) ++c_bstep;
                 if (walking) {
-                    const uint32_t off = (uint32_t)node * 32u;
-                    const float4 a = *reinterpret_cast<const float4*>(node_bytes + off);
-                    const float4 b = *reinterpret_cast<const float4*>(node_bytes + off + 16u);
-                    const uint32_t payload = __float_as_uint(b.w);
+                    // one 16-byte load per node: the quantised box and the link
+                    const uint4 n = qnodes[node];
+                    const bool leaf = (n.w & kQLeaf) != 0u;
                     if (COUNT) ++c_box;
-                    const bool hit = box_hit(ray, a, b);
+                    const bool hit = qbox_hit(qray, n);
                     // skip links point forward; max() keeps every walk finite
-                    const int next = max(__float_as_int(a.w), node + 1);
-                    node = (hit && payload == 0u) ? node + 1 : next;
-                    const bool take = hit && payload != 0u;
+                    const int next = leaf ? node + 1 : max((int)n.w, node + 1);
+                    node = (hit && !leaf) ? node + 1 : next;
+                    const uint32_t payload = n.w & ~kQLeaf;
+                    const bool take = hit && leaf;
                     const bool first_free = p0 == 0u;
                     p0 = (take && first_free) ? payload : p0;
                     p1 = (take && !first_free) ? payload : p1;
@@ -770,7 +773,7 @@ __global__ void trace_kernel(Scene sc, const float* o, const float* d, int64_t n
     const Ray r = make_ray(f3(o[k], o[n + k], o[2 * n + k]), f3(d[k], d[n + k], d[2 * n + k]));
     const int n_total = sc.nodes[0].escape;
     uint32_t nb = 0, nt = 0;
-    hit[k] = (brute ? brute_anyhit(sc, r) : bvh_anyhit(sc, r, n_total, nb, nt)) ? 1 : 0;
+    hit[k] = (brute ? brute_anyhit(sc, r) : qbvh_anyhit(sc, r, n_total, nb, nt)) ? 1 : 0;
 }
 
 }  // namespace
