@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=None,
                     help="measured requests per load of the serving mix (default 400 in the line, 2000 with --serve)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving mix of the default line")
+    ap.add_argument("--serve-launch-samples", type=int, default=40_000_000,
+                    help="work of one batched serving launch, in samples")
     ap.add_argument("--denoise", action="store_true", help="cross-bilateral denoiser (sigma 2) inside the step")
     ap.add_argument("--no-next-rows", action="store_true",
                     help="skip the denoiser, loss and sampling-study measurements (profiling runs of the step's "
@@ -546,7 +548,8 @@ def _serving_compare(args, M, resident, requests, label, fracs=(0.5, 0.7, 0.9), 
     import numpy as np
     from paper_2206_03380_amd.serve import Server, PerRequest
     from workloads.serving import poisson_arrivals
-    mk_srv = lambda: Server(resident, budget_bytes=64 << 30, max_slots=64, spp_max=32)  # noqa: E731
+    mk_srv = lambda: Server(resident, budget_bytes=64 << 30, max_slots=64, spp_max=32,  # noqa: E731
+                            launch_samples=args.serve_launch_samples)
     mk_base = lambda: PerRequest(resident)  # noqa: E731
     # warm-up, then the saturated rates: everything arrives at once
     _serve_run(M, mk_srv, requests[:warm], np.zeros(warm))
@@ -555,6 +558,7 @@ def _serving_compare(args, M, resident, requests, label, fracs=(0.5, 0.7, 0.9), 
     sat_base = _serve_run(M, mk_base, requests, np.zeros(len(requests)))
     rate = sat["requests"] / sat["wall_s"]
     out = {"workload": label, "requests_per_load": len(requests), "budget_bytes": 64 << 30, "slots": 64,
+           "launch_samples": args.serve_launch_samples,
            "saturated": {"batched": {"requests_per_s": rate, "samples_per_s": sat["samples_per_s"]},
                          "per_request_launches": {"requests_per_s": sat_base["requests"] / sat_base["wall_s"],
                                                   "samples_per_s": sat_base["samples_per_s"]}},

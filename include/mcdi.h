@@ -401,52 +401,112 @@ mcdi_status mcdi_bilateral_bwd(const mcdi_bilateral_guide* guide, int32_t n_chan
 mcdi_status mcdi_view_depth(const mcdi_gbuffer* gbuf, float* depth, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Serving: one persistent launch over the tiles of many requests.
+ * Serving: continuous batching of shading requests over resident scenes and
+ * probe tables (the per-iteration shading of section 3 issued by many
+ * independent callers).
  *
- * A tile is 256 consecutive pixels of a request's G-buffer.  Each item gives
- * one request (scene, probe tables, G-buffer, parameters, outputs) and a
- * contiguous range of its tiles; a launch may carry several ranges of
- * different requests, and a request may be spread over several launches.
+ * A request is one G-buffer (scene, probe tables, parameters) with its output
+ * buffers; with g_cd non-NULL the adjoint runs too.  Requests are admitted in
+ * submission order while the server's memory budget and slot count allow: an
+ * admitted request holds device scratch of
+ *     mcdi_server_request_bytes(N, spp) = align256(4 * ceil(2 spp / 32) * N)
+ *                                       + align256(16 * N)
+ * (its hit bits and ray origins) from the server's allocator until it
+ * completes.  Their tiles (256 consecutive pixels) are packed, oldest admitted
+ * request first, into persistent launches of at most launch_samples samples
+ * (a forward+backward sample counts twice; a launch takes at least one tile
+ * of each request it serves).  Launches run on two streams the server
+ * creates (lanes), one launch in flight per lane, so that the tail of one
+ * launch overlaps the next; requests submitted meanwhile join the next
+ * launch.  A request completes when every launch holding its tiles has
+ * finished.  `stream` (home) carries the server's allocations and frees
+ * only; a lane waits for home before it first uses memory allocated there.
  * Every pixel is computed exactly as by mcdi_shade_fwd / mcdi_shade_bwd (the
  * random numbers depend on the pixel and view_base only), so a request's
- * per-pixel results do not depend on what else shares its launches.
- *   hitbits  device uint32 [ceil(2*spp/32)][N] scratch of the request
- *   origins  device float32 [N][4] scratch of the request
- *   g_cd     NULL for a forward-only request; otherwise the adjoint also runs
- *            and g_kd, g_korm, g_nrm (overwritten) and g_env (accumulated)
- *            must be given.
- * The server owns the ray queues of its workgroups (n_workgroups regions of
- * 2*spp_max*256 rays) and a double-buffered item staging area; items of a
- * launch are copied to the device in stream order.  Calls on one server must
- * come from one thread and use one stream.
+ * per-pixel results do not depend on what it was served with (the probe
+ * gradient up to FP32 summation order).
+ *
+ * Ownership: inputs and outputs are caller device buffers that must stay
+ * valid, and unread and unwritten by the caller, until the request's ticket
+ * is reported by mcdi_server_poll or mcdi_server_wait; the same holds for
+ * its scene and probe handles (a scene destroyed earlier would only wait for
+ * the last lane that read it).  The server owns its
+ * ray queues (n_workgroups regions of 2 * spp_max * 256 rays of 16 bytes),
+ * two item buffers and two pinned host staging areas of `slots` items each
+ * (allocated at create), and the requests' scratch; destroy frees them.
+ * Threads: calls on one server come from one thread.
  * ------------------------------------------------------------------------- */
+typedef struct mcdi_server_s* mcdi_server;
+
+typedef struct {
+    int64_t budget_bytes;   /* device scratch the admitted requests may hold, >= 1 */
+    int64_t launch_samples; /* work of one launch, in samples, >= 1 */
+    int32_t slots;          /* most requests admitted at once, 1..65536 */
+    int32_t spp_max;        /* largest spp of a request, 1..1024 */
+    int32_t n_workgroups;   /* persistent grid size, 0..65536 (0: 4 per compute unit) */
+    int32_t reserved;
+} mcdi_server_config;
+
 typedef struct {
     mcdi_scene scene;
     mcdi_env env;
     mcdi_gbuffer gbuf;
-    mcdi_params params;     /* flags: the technique flags only */
-    float* c_d;
-    float* c_s;
-    uint32_t* hitbits;
-    float* origins;
-    const float* g_cd;
+    mcdi_params params;     /* flags: the technique and lookup flags only (no DUMP, no TIME_*) */
+    float* c_d;             /* device [3][N], written */
+    float* c_s;             /* device [3][N], written */
+    const float* g_cd;      /* device [3][N] upstream gradients, or NULL: forward only */
     const float* g_cs;
-    float* g_kd;
+    float* g_kd;            /* device [3][N], written (with g_cd) */
     float* g_korm;
     float* g_nrm;
-    float* g_env;
-    int64_t first_tile;     /* tile range [first_tile, first_tile + n_tiles) */
-    int64_t n_tiles;
-} mcdi_serve_item;
+    float* g_env;           /* device [H][W][3], accumulated (with g_cd; may be NULL) */
+} mcdi_request;
 
-typedef struct mcdi_server_s* mcdi_server;
+typedef struct {
+    int64_t used_bytes;     /* scratch held by admitted requests */
+    int64_t launches;       /* launches enqueued since create */
+    int32_t queued;         /* submitted, not admitted */
+    int32_t admitted;       /* admitted, not completed */
+    int32_t in_flight;      /* launches not known to have finished */
+    int32_t reserved;
+} mcdi_server_info_t;
 
-/* spp_max: largest spp any item may use (1..1024); n_workgroups: persistent
- * grid size (0: 4 per compute unit). */
-mcdi_status mcdi_server_create(int32_t spp_max, int32_t n_workgroups, const mcdi_allocator* alloc, void* stream,
+/* Errors: MCDI_E_INVALID for a bad config; MCDI_E_OOM if the ray queues or
+ * item buffers cannot be allocated (*out untouched, nothing leaked). */
+mcdi_status mcdi_server_create(const mcdi_server_config* config, const mcdi_allocator* alloc, void* stream,
                                mcdi_server* out);
-mcdi_status mcdi_server_launch(mcdi_server server, const mcdi_serve_item* items, int32_t n_items);
-/* Synchronises the server's stream, then frees its memory. */
+
+/* Scratch bytes a request of n pixels at spp holds while admitted. */
+int64_t mcdi_server_request_bytes(int64_t n_pixels, int32_t spp);
+
+/* Queues a request and stores its ticket (> 0, increasing) in *ticket.  The
+ * server's first read of the request's inputs waits for the work enqueued on
+ * input_stream so far (an event; pass the server's own stream when no wait is
+ * needed -- NULL is the null stream).  Then admits and launches what it can
+ * without blocking.  Errors (nothing queued, *ticket untouched):
+ * MCDI_E_INVALID for a bad request (as mcdi_shade_fwd, plus spp > spp_max,
+ * DUMP/TIME flags, incomplete gradient buffers); MCDI_E_UNSUPPORTED if the
+ * request's scratch alone exceeds budget_bytes.  A device error while
+ * launching earlier requests is returned too (this request is queued). */
+mcdi_status mcdi_server_submit(mcdi_server server, const mcdi_request* req, void* input_stream, int64_t* ticket);
+
+/* Retires finished launches, admits and launches without blocking, and
+ * copies at most cap tickets of completed requests (oldest first; each is
+ * reported once) to done, their count to *n_done.  If the allocator returns
+ * NULL at admission, the request stays queued and admission is retried at
+ * the next call. */
+mcdi_status mcdi_server_poll(mcdi_server server, int64_t* done, int32_t cap, int32_t* n_done);
+
+/* As poll, but blocks on the oldest launch in flight until at least one
+ * request has completed (returns at once with *n_done = 0 when nothing is
+ * pending).  MCDI_E_OOM when queued requests cannot be admitted because the
+ * allocator fails with nothing in flight. */
+mcdi_status mcdi_server_wait(mcdi_server server, int64_t* done, int32_t cap, int32_t* n_done);
+
+mcdi_status mcdi_server_info(mcdi_server server, mcdi_server_info_t* info);
+
+/* Synchronises the server's stream, then frees its memory; requests not yet
+ * completed are abandoned (their outputs undefined). */
 void mcdi_server_destroy(mcdi_server server);
 
 /* Durations (ms) of the traversal kernels of the calls made with

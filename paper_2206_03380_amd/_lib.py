@@ -47,10 +47,19 @@ class Params(C.Structure):
                 ("ray_eps", C.c_float), ("decisions", vp)]
 
 
-class ServeItem(C.Structure):
+class ServerConfig(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("launch_samples", C.c_int64), ("slots", C.c_int32),
+                ("spp_max", C.c_int32), ("n_workgroups", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Request(C.Structure):
     _fields_ = [("scene", vp), ("env", vp), ("gbuf", GBuffer), ("params", Params), ("c_d", vp), ("c_s", vp),
-                ("hitbits", vp), ("origins", vp), ("g_cd", vp), ("g_cs", vp), ("g_kd", vp), ("g_korm", vp),
-                ("g_nrm", vp), ("g_env", vp), ("first_tile", C.c_int64), ("n_tiles", C.c_int64)]
+                ("g_cd", vp), ("g_cs", vp), ("g_kd", vp), ("g_korm", vp), ("g_nrm", vp), ("g_env", vp)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("used_bytes", C.c_int64), ("launches", C.c_int64), ("queued", C.c_int32),
+                ("admitted", C.c_int32), ("in_flight", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -108,9 +117,17 @@ def lib():
     L.mcdi_adjoint_times.restype = C.c_int
     L.mcdi_adjoint_times.argtypes = [C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
     L.mcdi_server_create.restype = C.c_int
-    L.mcdi_server_create.argtypes = [C.c_int32, C.c_int32, vp, vp, C.POINTER(vp)]
-    L.mcdi_server_launch.restype = C.c_int
-    L.mcdi_server_launch.argtypes = [vp, vp, C.c_int32]
+    L.mcdi_server_create.argtypes = [C.POINTER(ServerConfig), vp, vp, C.POINTER(vp)]
+    L.mcdi_server_request_bytes.restype = C.c_int64
+    L.mcdi_server_request_bytes.argtypes = [C.c_int64, C.c_int32]
+    L.mcdi_server_submit.restype = C.c_int
+    L.mcdi_server_submit.argtypes = [vp, C.POINTER(Request), vp, C.POINTER(C.c_int64)]
+    L.mcdi_server_poll.restype = C.c_int
+    L.mcdi_server_poll.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)]
+    L.mcdi_server_wait.restype = C.c_int
+    L.mcdi_server_wait.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)]
+    L.mcdi_server_info.restype = C.c_int
+    L.mcdi_server_info.argtypes = [vp, C.POINTER(ServerInfo)]
     L.mcdi_server_destroy.restype = None
     L.mcdi_server_destroy.argtypes = [vp]
     L.mcdi_image_loss.restype = C.c_int
@@ -149,7 +166,8 @@ def check(status):
 
 EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_scene_nodes", "mcdi_build_env_cdf",
             "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
-            "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_adjoint_times", "mcdi_server_create", "mcdi_server_launch",
-            "mcdi_server_destroy", "mcdi_image_loss", "mcdi_image_loss_noalloc", "mcdi_bilateral_radius", "mcdi_bilateral_fwd",
+            "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_adjoint_times", "mcdi_server_create",
+            "mcdi_server_request_bytes", "mcdi_server_submit", "mcdi_server_poll", "mcdi_server_wait",
+            "mcdi_server_info", "mcdi_server_destroy", "mcdi_image_loss", "mcdi_image_loss_noalloc", "mcdi_bilateral_radius", "mcdi_bilateral_fwd",
             "mcdi_bilateral_bwd", "mcdi_view_depth", "mcdi_build_edges", "mcdi_destroy_edges", "mcdi_edges_count",
             "mcdi_edges_copy", "mcdi_shade_bwd_edges", "mcdi_last_error", "mcdi_version")

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <string>
@@ -524,73 +525,313 @@ mcdi_status mcdi_shade_bwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, co
 
 }  // extern "C"
 
-struct mcdi_server_s {
-    Alloc alloc;
-    hipStream_t stream = nullptr;
-    int spp_max = 0;
-    int n_wg = 0;
-    float4* scratch = nullptr;
-    int* counter = nullptr;
-    ServeItem* items_dev = nullptr;
-    int cap = 0;
-    ServeItem* staging[2] = {nullptr, nullptr};  // pinned host
-    hipEvent_t copied[2] = {nullptr, nullptr};
-    int flip = 0;
+// ---------------------------------------------------------------------------
+// Serving: requests are admitted while the server's memory budget and slot
+// count allow, and their tiles packed, oldest request first, into persistent
+// launches of bounded work.  A launch ends in a tail of a few long tiles, so
+// launches alternate between two lanes (streams of the server's own): the
+// next launch fills the compute units while the previous one drains.  The
+// caller's stream (home) carries only the server's allocations and frees;
+// a lane waits for home before its first use of memory allocated there.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kLanes = 2;
+
+struct SrvReq {
+    int64_t ticket = 0;
+    ShadeArgs args{};
+    int64_t tiles = 0, next_tile = 0;
+    int outstanding = 0;       // launches in flight holding tiles of the request
+    size_t bytes = 0;          // scratch the request holds while admitted
+    hipEvent_t ready = nullptr;  // recorded on the caller's input stream, or null
+    unsigned ready_seen = 0;   // lanes already made to wait for `ready`
+    void* scratch = nullptr;
+    uint32_t* hitbits = nullptr;
+    float4* origins = nullptr;
+    bool grad = false;
+    mcdi_scene scene_handle = nullptr;
 };
 
-static void server_free_items(mcdi_server sv) {
-    sv->alloc.put(sv->items_dev, sv->stream);
-    for (int i = 0; i < 2; ++i) {
-        if (sv->copied[i]) (void)hipEventSynchronize(sv->copied[i]);
-        if (sv->staging[i]) (void)hipHostFree(sv->staging[i]);
-        sv->staging[i] = nullptr;
-    }
-    sv->items_dev = nullptr;
-    sv->cap = 0;
+struct SrvLane {
+    hipStream_t stream = nullptr;
+    float4* rays = nullptr;        // per-workgroup ray regions of the persistent grid
+    int* counter = nullptr;
+    ServeItem* items_dev = nullptr;
+    ServeItem* staging = nullptr;  // pinned host
+    bool busy = false;             // a launch in flight
+    int64_t home_seen = 0;         // home epoch this lane has waited for
+};
+
+struct SrvLaunch {
+    int lane = 0;
+    hipEvent_t done = nullptr;
+    std::vector<SrvReq*> reqs;
+};
+
+}  // namespace
+
+struct mcdi_server_s {
+    Alloc alloc;
+    hipStream_t home = nullptr;
+    mcdi_server_config cfg{};
+    SrvLane lane[kLanes];
+    hipEvent_t home_ev = nullptr;  // recorded on home after allocations
+    int64_t home_epoch = 0;        // allocations made on home so far (a counter)
+    int64_t home_recorded = 0;     // epoch home_ev was last recorded at
+    std::deque<SrvReq*> queue;     // submitted, not admitted
+    std::vector<SrvReq*> admitted;
+    std::vector<SrvLaunch> in_flight;
+    std::vector<hipEvent_t> spare_events;
+    std::deque<int64_t> completed; // tickets done, not yet reported
+    size_t used = 0;
+    int64_t next_ticket = 1, launches = 0;
+};
+
+namespace {
+
+size_t srv_align(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t srv_hitbit_bytes(int64_t n, int32_t spp) {
+    return srv_align(sizeof(uint32_t) * (size_t)((2 * spp + 31) / 32) * (size_t)n);
 }
 
-static mcdi_status server_reserve(mcdi_server sv, int n) {
-    if (n <= sv->cap) return MCDI_OK;
-    int cap = sv->cap ? sv->cap : 64;
-    while (cap < n) cap *= 2;
-    server_free_items(sv);
-    sv->items_dev = (ServeItem*)sv->alloc.get(sizeof(ServeItem) * (size_t)cap, sv->stream);
-    if (!sv->items_dev) return fail(MCDI_E_OOM, "mcdi_server_launch: item buffer allocation failed");
-    for (int i = 0; i < 2; ++i) {
-        if (hipHostMalloc((void**)&sv->staging[i], sizeof(ServeItem) * (size_t)cap, hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(MCDI_E_OOM, "mcdi_server_launch: pinned staging allocation failed");
-        }
+size_t srv_request_bytes(int64_t n, int32_t spp) {
+    return srv_hitbit_bytes(n, spp) + srv_align(sizeof(float4) * (size_t)n);
+}
+
+hipEvent_t srv_event(mcdi_server sv) {
+    if (!sv->spare_events.empty()) {
+        hipEvent_t e = sv->spare_events.back();
+        sv->spare_events.pop_back();
+        return e;
     }
-    sv->cap = cap;
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+void* srv_get(mcdi_server sv, size_t bytes) {
+    void* p = sv->alloc.get(bytes, sv->home);
+    if (p) ++sv->home_epoch;
+    return p;
+}
+
+void srv_release(mcdi_server sv, SrvReq* r) {
+    // only after every launch that used it has been seen to finish
+    if (r->scratch) sv->alloc.put(r->scratch, sv->home);
+    r->scratch = nullptr;
+    if (r->ready) sv->spare_events.push_back(r->ready);
+    r->ready = nullptr;
+}
+
+void srv_finish(mcdi_server sv, SrvLaunch& L) {
+    for (SrvReq* r : L.reqs) {
+        if (--r->outstanding > 0 || r->next_tile < r->tiles) continue;
+        sv->used -= r->bytes;
+        sv->admitted.erase(std::find(sv->admitted.begin(), sv->admitted.end(), r));
+        sv->completed.push_back(r->ticket);
+        srv_release(sv, r);
+        delete r;
+    }
+    sv->lane[L.lane].busy = false;
+    sv->spare_events.push_back(L.done);
+}
+
+// finished launches (block: wait for the oldest first)
+mcdi_status srv_retire(mcdi_server sv, bool block) {
+    for (size_t i = 0; i < sv->in_flight.size();) {
+        SrvLaunch& L = sv->in_flight[i];
+        const hipError_t q = (block && i == 0) ? hipEventSynchronize(L.done) : hipEventQuery(L.done);
+        if (q == hipErrorNotReady) {
+            (void)hipGetLastError();
+            ++i;
+            continue;
+        }
+        if (q != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_server_poll: %s", hipGetErrorString(q));
+        srv_finish(sv, L);
+        sv->in_flight.erase(sv->in_flight.begin() + (ptrdiff_t)i);
+    }
     return MCDI_OK;
 }
 
+void srv_admit(mcdi_server sv) {
+    while (!sv->queue.empty() && (int)sv->admitted.size() < sv->cfg.slots &&
+           sv->used + sv->queue.front()->bytes <= (size_t)sv->cfg.budget_bytes) {
+        SrvReq* r = sv->queue.front();
+        r->scratch = srv_get(sv, r->bytes);
+        if (!r->scratch) return;   // the device is short of memory: retry after completions
+        r->hitbits = (uint32_t*)r->scratch;
+        r->origins = (float4*)((char*)r->scratch + srv_hitbit_bytes(r->args.g.n, r->args.spp));
+        sv->queue.pop_front();
+        sv->used += r->bytes;
+        sv->admitted.push_back(r);
+    }
+}
+
+// order a lane after home's allocations so far
+hipError_t srv_sync_home(mcdi_server sv, SrvLane& ln) {
+    if (ln.home_seen == sv->home_epoch) return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (sv->home_recorded != sv->home_epoch) {
+        e = hipEventRecord(sv->home_ev, sv->home);
+        if (e != hipSuccess) return e;
+        sv->home_recorded = sv->home_epoch;
+    }
+    e = hipStreamWaitEvent(ln.stream, sv->home_ev, 0);
+    if (e == hipSuccess) ln.home_seen = sv->home_epoch;
+    return e;
+}
+
+// one launch of pending tiles on an idle lane, oldest admitted request first,
+// up to the launch's work
+mcdi_status srv_launch(mcdi_server sv, bool* launched) {
+    *launched = false;
+    int li = -1;
+    for (int i = 0; i < kLanes && li < 0; ++i)
+        if (!sv->lane[i].busy) li = i;
+    if (li < 0) return MCDI_OK;
+    SrvLane& ln = sv->lane[li];
+    struct Pick { SrvReq* r; int64_t first, count; };
+    std::vector<Pick> picks;
+    int64_t budget = sv->cfg.launch_samples;
+    for (SrvReq* r : sv->admitted) {
+        if (r->next_tile >= r->tiles || budget <= 0) continue;
+        const int64_t per_tile = (int64_t)kBlock * r->args.spp * (r->grad ? 2 : 1);
+        int64_t take = budget / per_tile;
+        take = take < 1 ? 1 : take;
+        take = take < r->tiles - r->next_tile ? take : r->tiles - r->next_tile;
+        picks.push_back({r, r->next_tile, take});
+        budget -= take * per_tile;
+    }
+    if (picks.empty()) return MCDI_OK;
+    if ((int)picks.size() > sv->cfg.slots) return fail(MCDI_E_DEVICE, "mcdi_server_poll: item buffer too small");
+    ServeItem* h = ln.staging;   // the lane's previous copy has completed (its launch finished)
+    int64_t total = 0;
+    int max_H = 1;
+    for (size_t i = 0; i < picks.size(); ++i) {
+        SrvReq* r = picks[i].r;
+        ShadeArgs a = r->args;
+        a.hitbits_in = r->hitbits;
+        a.origins = r->origins;
+        a.rays = ln.rays;   // marks tracing available; regions are per workgroup
+        h[i].args = a;
+        h[i].hitbits = r->hitbits;
+        h[i].first_tile = picks[i].first;
+        h[i].first_global = total;
+        total += picks[i].count;
+        if (a.env.H > max_H) max_H = a.env.H;
+    }
+    if (total >= ((int64_t)1 << 31)) return fail(MCDI_E_UNSUPPORTED, "mcdi_server_poll: too many tiles");
+    SrvLaunch L;
+    L.lane = li;
+    L.done = srv_event(sv);
+    if (!L.done) return fail(MCDI_E_DEVICE, "mcdi_server_poll: event creation failed");
+    hipError_t e = srv_sync_home(sv, ln);
+    // inputs: after the caller's writes on its stream
+    for (const Pick& p : picks)
+        if (e == hipSuccess && p.r->ready && !(p.r->ready_seen & (1u << li))) {
+            e = hipStreamWaitEvent(ln.stream, p.r->ready, 0);
+            p.r->ready_seen |= 1u << li;
+        }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ln.items_dev, h, sizeof(ServeItem) * picks.size(), hipMemcpyHostToDevice, ln.stream);
+    std::vector<mcdi_scene> scenes;
+    for (const Pick& p : picks)
+        if (std::find(scenes.begin(), scenes.end(), p.r->scene_handle) == scenes.end())
+            scenes.push_back(p.r->scene_handle);
+    for (mcdi_scene sc : scenes)
+        if (e == hipSuccess) e = scene_acquire(sc, ln.stream);
+    if (e == hipSuccess)
+        e = launch_serve(ln.items_dev, (int)picks.size(), total, ln.counter, ln.rays, sv->cfg.spp_max,
+                         sv->cfg.n_workgroups, max_H, ln.stream);
+    for (mcdi_scene sc : scenes)
+        if (e == hipSuccess) e = scene_release(sc, ln.stream);
+    if (e == hipSuccess) e = hipEventRecord(L.done, ln.stream);
+    if (e != hipSuccess) {
+        sv->spare_events.push_back(L.done);
+        return fail(MCDI_E_DEVICE, "mcdi_server_poll: %s", hipGetErrorString(e));
+    }
+    for (const Pick& p : picks) {
+        p.r->next_tile += p.count;
+        ++p.r->outstanding;
+        L.reqs.push_back(p.r);
+    }
+    ln.busy = true;
+    sv->in_flight.push_back(L);
+    ++sv->launches;
+    *launched = true;
+    return MCDI_OK;
+}
+
+// retire, admit, and keep both lanes busy
+mcdi_status srv_pump(mcdi_server sv, bool block) {
+    mcdi_status st = srv_retire(sv, block);
+    if (st != MCDI_OK) return st;
+    srv_admit(sv);
+    for (;;) {
+        bool launched = false;
+        st = srv_launch(sv, &launched);
+        if (st != MCDI_OK || !launched) return st;
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
-mcdi_status mcdi_server_create(int32_t spp_max, int32_t n_workgroups, const mcdi_allocator* alloc, void* stream,
+int64_t mcdi_server_request_bytes(int64_t n_pixels, int32_t spp) {
+    if (n_pixels < 0 || spp < 1) return 0;
+    return (int64_t)srv_request_bytes(n_pixels, spp);
+}
+
+mcdi_status mcdi_server_create(const mcdi_server_config* cfg, const mcdi_allocator* alloc, void* stream,
                                mcdi_server* out) {
-    if (!out) return fail(MCDI_E_INVALID, "mcdi_server_create: out is NULL");
-    if (spp_max < 1 || spp_max > 1024) return fail(MCDI_E_INVALID, "mcdi_server_create: spp_max must be in [1, 1024]");
-    if (n_workgroups < 0 || n_workgroups > 65536) return fail(MCDI_E_INVALID, "mcdi_server_create: bad n_workgroups");
+    if (!out || !cfg) return fail(MCDI_E_INVALID, "mcdi_server_create: NULL argument");
+    if (cfg->spp_max < 1 || cfg->spp_max > 1024)
+        return fail(MCDI_E_INVALID, "mcdi_server_create: spp_max must be in [1, 1024]");
+    if (cfg->n_workgroups < 0 || cfg->n_workgroups > 65536)
+        return fail(MCDI_E_INVALID, "mcdi_server_create: bad n_workgroups");
+    if (cfg->slots < 1 || cfg->slots > 65536 || cfg->budget_bytes < 1 || cfg->launch_samples < 1)
+        return fail(MCDI_E_INVALID,
+                    "mcdi_server_create: slots must be in [1, 65536], budget_bytes and launch_samples >= 1");
     if (alloc && (!alloc->alloc || !alloc->free)) return fail(MCDI_E_INVALID, "mcdi_server_create: allocator incomplete");
-    int n_wg = n_workgroups;
-    if (n_wg == 0) {
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        n_wg = 4 * cus;
-    }
     mcdi_server sv = new (std::nothrow) mcdi_server_s;
     if (!sv) return fail(MCDI_E_OOM, "mcdi_server_create: host allocation failed");
     sv->alloc = make_alloc(alloc);
-    sv->stream = (hipStream_t)stream;
-    sv->spp_max = spp_max;
-    sv->n_wg = n_wg;
-    sv->scratch = (float4*)sv->alloc.get(sizeof(float4) * (size_t)n_wg * 2 * spp_max * kBlock, sv->stream);
-    sv->counter = (int*)sv->alloc.get(sizeof(int), sv->stream);
-    bool ok_ev = hipEventCreateWithFlags(&sv->copied[0], hipEventDisableTiming) == hipSuccess &&
-                 hipEventCreateWithFlags(&sv->copied[1], hipEventDisableTiming) == hipSuccess;
-    if (!sv->scratch || !sv->counter || !ok_ev) {
+    sv->home = (hipStream_t)stream;
+    sv->cfg = *cfg;
+    if (sv->cfg.n_workgroups == 0) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        sv->cfg.n_workgroups = 4 * cus;
+    }
+    bool dev_ok = hipEventCreateWithFlags(&sv->home_ev, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < kLanes && dev_ok; ++i)
+        dev_ok = hipStreamCreateWithFlags(&sv->lane[i].stream, hipStreamNonBlocking) == hipSuccess;
+    if (!dev_ok) {
+        (void)hipGetLastError();
+        mcdi_server_destroy(sv);
+        return fail(MCDI_E_DEVICE, "mcdi_server_create: stream or event creation failed");
+    }
+    bool mem_ok = true;
+    for (int i = 0; i < kLanes && mem_ok; ++i) {
+        SrvLane& ln = sv->lane[i];
+        ln.rays = (float4*)srv_get(sv, sizeof(float4) * (size_t)sv->cfg.n_workgroups * 2 * sv->cfg.spp_max * kBlock);
+        ln.counter = (int*)srv_get(sv, sizeof(int));
+        // one item per admitted request at most: the item buffers never grow
+        ln.items_dev = (ServeItem*)srv_get(sv, sizeof(ServeItem) * (size_t)sv->cfg.slots);
+        if (hipHostMalloc((void**)&ln.staging, sizeof(ServeItem) * (size_t)sv->cfg.slots, hipHostMallocDefault) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            ln.staging = nullptr;
+        }
+        mem_ok = ln.rays && ln.counter && ln.items_dev && ln.staging;
+    }
+    if (!mem_ok) {
         mcdi_server_destroy(sv);
         return fail(MCDI_E_OOM, "mcdi_server_create: allocation failed");
     }
@@ -598,80 +839,117 @@ mcdi_status mcdi_server_create(int32_t spp_max, int32_t n_workgroups, const mcdi
     return ok();
 }
 
-void mcdi_server_destroy(mcdi_server sv) {
-    if (!sv) return;
-    (void)hipStreamSynchronize(sv->stream);
-    server_free_items(sv);
-    sv->alloc.put(sv->scratch, sv->stream);
-    sv->alloc.put(sv->counter, sv->stream);
-    for (int i = 0; i < 2; ++i)
-        if (sv->copied[i]) (void)hipEventDestroy(sv->copied[i]);
-    delete sv;
+mcdi_status mcdi_server_submit(mcdi_server sv, const mcdi_request* req, void* input_stream, int64_t* ticket) {
+    if (!sv || !req || !ticket) return fail(MCDI_E_INVALID, "mcdi_server_submit: NULL argument");
+    ShadeArgs a;
+    mcdi_status st = fill_common("mcdi_server_submit", req->scene, req->env, &req->gbuf, &req->params, a);
+    if (st != MCDI_OK) return st;
+    if (req->params.spp > sv->cfg.spp_max) return fail(MCDI_E_INVALID, "mcdi_server_submit: spp > spp_max");
+    if (req->params.flags & (MCDI_FLAG_DUMP | MCDI_FLAG_DUMP_DIRS | MCDI_FLAG_TIME_TRACE | MCDI_FLAG_TIME_ADJOINT))
+        return fail(MCDI_E_INVALID, "mcdi_server_submit: dump and timing flags are not served");
+    if (!req->c_d || !req->c_s) return fail(MCDI_E_INVALID, "mcdi_server_submit: NULL c_d/c_s");
+    if (req->g_cd && (!req->g_cs || !req->g_kd || !req->g_korm || !req->g_nrm))
+        return fail(MCDI_E_INVALID, "mcdi_server_submit: incomplete gradient buffers");
+    const size_t bytes = srv_request_bytes(a.g.n, a.spp);
+    if (bytes > (size_t)sv->cfg.budget_bytes)
+        return fail(MCDI_E_UNSUPPORTED, "mcdi_server_submit: request needs %zu bytes, above the budget %lld", bytes,
+                    (long long)sv->cfg.budget_bytes);
+    SrvReq* r = new (std::nothrow) SrvReq;
+    if (!r) return fail(MCDI_E_OOM, "mcdi_server_submit: host allocation failed");
+    a.c_d = req->c_d;
+    a.c_s = req->c_s;
+    a.g_cd = req->g_cd;
+    a.g_cs = req->g_cs;
+    a.g_kd = req->g_kd;
+    a.g_korm = req->g_korm;
+    a.g_nrm = req->g_nrm;
+    a.g_env = req->g_cd ? req->g_env : nullptr;
+    r->args = a;
+    r->scene_handle = req->scene;
+    r->grad = req->g_cd != nullptr;
+    r->tiles = (a.g.n + kBlock - 1) / kBlock;
+    r->bytes = bytes;
+    r->ready = srv_event(sv);
+    if (!r->ready || hipEventRecord(r->ready, (hipStream_t)input_stream) != hipSuccess) {
+        (void)hipGetLastError();
+        if (r->ready) sv->spare_events.push_back(r->ready);
+        delete r;
+        return fail(MCDI_E_DEVICE, "mcdi_server_submit: event record on the input stream failed");
+    }
+    r->ticket = sv->next_ticket++;
+    sv->queue.push_back(r);
+    *ticket = r->ticket;
+    st = srv_pump(sv, false);
+    return st == MCDI_OK ? ok() : st;
 }
 
-mcdi_status mcdi_server_launch(mcdi_server sv, const mcdi_serve_item* items, int32_t n_items) {
-    if (!sv) return fail(MCDI_E_INVALID, "mcdi_server_launch: NULL server");
-    if (n_items < 0 || (n_items > 0 && !items)) return fail(MCDI_E_INVALID, "mcdi_server_launch: bad items");
-    if (n_items == 0) return ok();
-    mcdi_status st = server_reserve(sv, n_items);
-    if (st != MCDI_OK) return st;
-    // staging buffer of this launch: wait until its previous copy completed
-    const int b = sv->flip;
-    sv->flip ^= 1;
-    if (hipEventSynchronize(sv->copied[b]) != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_server_launch: event");
-    ServeItem* h = sv->staging[b];
-    int64_t total = 0;
-    int max_H = 1;
-    for (int i = 0; i < n_items; ++i) {
-        const mcdi_serve_item& it = items[i];
-        ShadeArgs a;
-        st = fill_common("mcdi_server_launch", it.scene, it.env, &it.gbuf, &it.params, a);
-        if (st != MCDI_OK) return st;
-        if (it.params.spp > sv->spp_max) return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d spp > spp_max", i);
-        if (it.params.flags & (MCDI_FLAG_DUMP | MCDI_FLAG_TIME_TRACE | MCDI_FLAG_TIME_ADJOINT))
-            return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d: dump/timing flags are not served", i);
-        if (!it.c_d || !it.c_s || !it.hitbits || !it.origins)
-            return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d: NULL output or scratch", i);
-        if (it.g_cd && (!it.g_cs || !it.g_kd || !it.g_korm || !it.g_nrm))
-            return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d: incomplete gradient buffers", i);
-        const int64_t tiles = (a.g.n + kBlock - 1) / kBlock;
-        if (it.first_tile < 0 || it.n_tiles < 1 || it.first_tile + it.n_tiles > tiles)
-            return fail(MCDI_E_INVALID, "mcdi_server_launch: item %d: tile range outside the request", i);
-        a.c_d = it.c_d;
-        a.c_s = it.c_s;
-        a.hitbits_in = it.hitbits;
-        a.origins = (float4*)it.origins;
-        a.g_cd = it.g_cd;
-        a.g_cs = it.g_cs;
-        a.g_kd = it.g_kd;
-        a.g_korm = it.g_korm;
-        a.g_nrm = it.g_nrm;
-        a.g_env = it.g_env;
-        a.rays = sv->scratch;  // marks tracing available; regions are per workgroup
-        h[i].args = a;
-        h[i].hitbits = it.hitbits;
-        h[i].first_tile = it.first_tile;
-        h[i].first_global = total;
-        total += it.n_tiles;
-        if (a.env.H > max_H) max_H = a.env.H;
+static int32_t srv_report(mcdi_server sv, int64_t* done, int32_t cap) {
+    int32_t k = 0;
+    while (k < cap && !sv->completed.empty()) {
+        done[k++] = sv->completed.front();
+        sv->completed.pop_front();
     }
-    if (total >= ((int64_t)1 << 31)) return fail(MCDI_E_UNSUPPORTED, "mcdi_server_launch: too many tiles");
-    hipError_t e = hipMemcpyAsync(sv->items_dev, h, sizeof(ServeItem) * (size_t)n_items, hipMemcpyHostToDevice,
-                                  sv->stream);
-    if (e == hipSuccess) e = hipEventRecord(sv->copied[b], sv->stream);
-    // every distinct scene of the launch: its build before, its release after
-    std::vector<mcdi_scene> scenes;
-    for (int i = 0; i < n_items; ++i)
-        if (std::find(scenes.begin(), scenes.end(), items[i].scene) == scenes.end()) scenes.push_back(items[i].scene);
-    for (mcdi_scene scn : scenes)
-        if (e == hipSuccess) e = scene_acquire(scn, sv->stream);
-    if (e == hipSuccess)
-        e = launch_serve(sv->items_dev, n_items, total, sv->counter, sv->scratch, sv->spp_max, sv->n_wg, max_H,
-                         sv->stream);
-    for (mcdi_scene scn : scenes)
-        if (e == hipSuccess) e = scene_release(scn, sv->stream);
-    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_server_launch: %s", hipGetErrorString(e));
+    return k;
+}
+
+mcdi_status mcdi_server_poll(mcdi_server sv, int64_t* done, int32_t cap, int32_t* n_done) {
+    if (!sv || !n_done || (cap > 0 && !done)) return fail(MCDI_E_INVALID, "mcdi_server_poll: NULL argument");
+    const mcdi_status st = srv_pump(sv, false);
+    *n_done = srv_report(sv, done, cap);
+    return st == MCDI_OK ? ok() : st;
+}
+
+mcdi_status mcdi_server_wait(mcdi_server sv, int64_t* done, int32_t cap, int32_t* n_done) {
+    if (!sv || !n_done || (cap > 0 && !done)) return fail(MCDI_E_INVALID, "mcdi_server_wait: NULL argument");
+    mcdi_status st = MCDI_OK;
+    while (sv->completed.empty() && (!sv->in_flight.empty() || !sv->queue.empty() || !sv->admitted.empty())) {
+        st = srv_pump(sv, true);
+        if (st != MCDI_OK) break;
+        if (sv->in_flight.empty() && sv->completed.empty()) {
+            // nothing could be launched: the allocator refused the admission
+            st = fail(MCDI_E_OOM, "mcdi_server_wait: requests cannot be admitted (device allocation failed)");
+            break;
+        }
+    }
+    *n_done = srv_report(sv, done, cap);
+    return st == MCDI_OK ? ok() : st;
+}
+
+mcdi_status mcdi_server_info(mcdi_server sv, mcdi_server_info_t* info) {
+    if (!sv || !info) return fail(MCDI_E_INVALID, "mcdi_server_info: NULL argument");
+    info->used_bytes = (int64_t)sv->used;
+    info->launches = sv->launches;
+    info->queued = (int32_t)sv->queue.size();
+    info->admitted = (int32_t)sv->admitted.size();
+    info->in_flight = (int32_t)sv->in_flight.size();
+    info->reserved = 0;
     return ok();
+}
+
+void mcdi_server_destroy(mcdi_server sv) {
+    if (!sv) return;
+    for (int i = 0; i < kLanes; ++i)
+        if (sv->lane[i].stream) (void)hipStreamSynchronize(sv->lane[i].stream);
+    for (SrvLaunch& L : sv->in_flight) sv->spare_events.push_back(L.done);
+    for (SrvReq* r : sv->admitted) {
+        srv_release(sv, r);
+        delete r;
+    }
+    for (SrvReq* r : sv->queue) {
+        srv_release(sv, r);
+        delete r;
+    }
+    for (int i = 0; i < kLanes; ++i) {
+        SrvLane& ln = sv->lane[i];
+        sv->alloc.put(ln.rays, sv->home);
+        sv->alloc.put(ln.counter, sv->home);
+        sv->alloc.put(ln.items_dev, sv->home);
+        if (ln.staging) (void)hipHostFree(ln.staging);
+        if (ln.stream) (void)hipStreamDestroy(ln.stream);
+    }
+    for (hipEvent_t e : sv->spare_events) (void)hipEventDestroy(e);
+    if (sv->home_ev) (void)hipEventDestroy(sv->home_ev);
+    delete sv;
 }
 
 mcdi_status mcdi_image_loss(const float* kd, const float* c_d, const float* c_s, const float* ref,

@@ -2,13 +2,13 @@
 
 Scenes (BVH) and probe tables stay resident on the device.  Requests (a
 G-buffer already on the device, spp, seed, forward-only or forward+backward
-with upstream gradients) are admitted while a device-memory budget and a slot
-count allow, and their tiles (256 pixels) are packed, oldest request first,
-into persistent launches of bounded work; requests that arrive while earlier
-ones are on the GPU join the next launch.  Two launches are kept in flight on
-one stream so the device never waits for the host.  A request completes when
-the launch holding its last tile has finished (HIP event); latency is
-measured from submit() to that moment on the host clock.
+with upstream gradients) go to the library's server (mcdi_server_*), which
+admits them while its scratch budget and slot count allow, packs their tiles
+(256 pixels), oldest request first, into persistent launches of bounded work
+on two alternating streams (one launch's tail overlaps the next launch), and
+reports completed requests by ticket.  This module only allocates each request's outputs and marshals the
+calls; latency is measured from submit() to the poll that reports the
+request's ticket, on the host clock.
 
 Every pixel is computed by the same code as the staged forward/backward with
 random numbers keyed by (pixel, view_base, sample), so a request's results do
@@ -19,12 +19,12 @@ summation order).
 import ctypes as C
 import time
 from collections import deque
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import torch
 
 from . import _lib as L
-from . import _ptr, _stream, hit_words, GBuffer, _TORCH_ALLOCATOR
+from . import _ptr, GBuffer, _TORCH_ALLOCATOR
 
 TILE = 256
 
@@ -37,7 +37,7 @@ class Request:
     seed: int = 0
     tau: float = 1.0
     ray_eps: float = 1e-3
-    flags: int = 0                     # technique / probe-lookup flags (FLAG_*; not DUMP or TIME_TRACE)
+    flags: int = 0                     # technique / probe-lookup flags (FLAG_*; not DUMP or TIME_*)
     g_cd: torch.Tensor = None          # upstream gradients: forward+backward request
     g_cs: torch.Tensor = None
     # filled by the server
@@ -50,13 +50,6 @@ class Request:
     g_korm: torch.Tensor = None
     g_nrm: torch.Tensor = None
     g_env: torch.Tensor = None
-    _hb: torch.Tensor = None
-    _org: torch.Tensor = None
-    _next_tile: int = 0
-    _tiles: int = 0
-    _bytes: int = 0
-    _last_launch: int = -1
-    _ready: object = None              # event on the submitting stream: inputs written
 
     @property
     def grad(self):
@@ -71,61 +64,42 @@ class Request:
         return None if self.t_done is None else self.t_done - self.t_submit
 
 
-
-def _inputs(req):
-    """Device tensors a request reads: its G-buffer planes and upstream
-    gradients."""
-    gb = req.gb
-    ts = [gb.pos, gb.nrm, gb.kd, gb.korm, gb.mask, gb.eye]
+def _alloc_outputs(req, env):
+    """Outputs on the caller's stream (the server's first read of the request
+    waits for that stream's work so far, the zero fill of g_env included)."""
+    n, dev = req.gb.n, req.gb.pos.device
+    req.c_d = torch.empty((3, n), dtype=torch.float32, device=dev)
+    req.c_s = torch.empty((3, n), dtype=torch.float32, device=dev)
     if req.grad:
-        ts += [req.g_cd, req.g_cs]
-    return ts
+        req.g_kd = torch.empty((3, n), dtype=torch.float32, device=dev)
+        req.g_korm = torch.empty((3, n), dtype=torch.float32, device=dev)
+        req.g_nrm = torch.empty((3, n), dtype=torch.float32, device=dev)
+        req.g_env = torch.zeros((env.H, env.W, 3), dtype=torch.float32, device=dev)
 
 
-def _order_after_caller(req, stream):
-    """The server's stream must not read a request's inputs (or the probe
-    tables built before it) before the caller's stream has written them: an
-    event recorded on the submitting stream, waited for by `stream` before
-    the first launch that reads the request.  The inputs are also marked as
-    used on `stream`, so the caching allocator does not hand their memory out
-    again while that stream may still read it."""
-    ev = torch.cuda.Event()
-    ev.record(torch.cuda.current_stream())
-    req._ready = ev
-    for t in _inputs(req):
-        t.record_stream(stream)
-
-
-def request_bytes(n_pixels, spp, grad, env_hw):
-    """Device memory a request holds while admitted."""
-    b = n_pixels * (24 + 4 * hit_words(spp) + 16)
-    if grad:
-        b += n_pixels * 36 + env_hw[0] * env_hw[1] * 12
-    return b
+def request_bytes(n_pixels, spp):
+    """Server scratch a request holds while admitted (hit bits and ray
+    origins)."""
+    return int(L.lib().mcdi_server_request_bytes(int(n_pixels), int(spp)))
 
 
 class Server:
     def __init__(self, scenes, budget_bytes=64 << 30, max_slots=64, launch_samples=40_000_000, spp_max=64,
                  n_workgroups=0, stream=None):
-        """scenes: {name: (Scene, Env)} resident on the device."""
+        """scenes: {name: (Scene, Env)} resident on the device.  stream: the
+        server's allocation stream (its launches run on two streams of the
+        library's own)."""
         self.scenes = scenes
-        self.budget = budget_bytes
-        self.max_slots = max_slots
-        self.launch_samples = launch_samples
-        self.spp_max = spp_max
         self.stream = stream or torch.cuda.Stream()
+        cfg = L.ServerConfig(int(budget_bytes), int(launch_samples), int(max_slots), int(spp_max), int(n_workgroups), 0)
         h = C.c_void_p()
-        L.check(L.lib().mcdi_server_create(spp_max, n_workgroups, C.byref(_TORCH_ALLOCATOR),
+        L.check(L.lib().mcdi_server_create(C.byref(cfg), C.byref(_TORCH_ALLOCATOR),
                                            C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.handle = h
-        self.queue = deque()          # submitted, not admitted
-        self.admitted = []            # admitted, tiles pending or in flight
-        self.in_flight = deque()      # (launch id, event, [requests completing in it])
-        self.used = 0
-        self.launch_id = 0
-        self.n_launches = 0
-        self._rid = 0
+        self.pending = {}             # ticket -> request
         self.completed = []
+        self._rid = 0
+        self._buf = (C.c_int64 * 256)()
 
     def close(self):
         if getattr(self, "handle", None):
@@ -138,112 +112,60 @@ class Server:
         except Exception:
             pass
 
+    def info(self):
+        i = L.ServerInfo()
+        L.check(L.lib().mcdi_server_info(self.handle, C.byref(i)))
+        return {"used_bytes": i.used_bytes, "launches": i.launches, "queued": i.queued, "admitted": i.admitted,
+                "in_flight": i.in_flight}
+
+    @property
+    def n_launches(self):
+        return self.info()["launches"]
+
     # ------------------------------------------------------------------
     def submit(self, req):
-        if req.spp > self.spp_max:
-            raise ValueError("spp above the server's spp_max")
-        if req.scene not in self.scenes:
-            raise KeyError(req.scene)
+        scene, env = self.scenes[req.scene]
+        req.t_submit = time.perf_counter()
+        _alloc_outputs(req, env)
+        q = L.Request()
+        q.scene, q.env = scene.handle, env.handle
+        q.gbuf = req.gb.struct()
+        q.params = L.Params(req.spp, int(req.flags), req.seed, float(req.tau), float(req.ray_eps), None)
+        q.c_d, q.c_s = _ptr(req.c_d), _ptr(req.c_s)
+        if req.grad:
+            q.g_cd, q.g_cs = _ptr(req.g_cd), _ptr(req.g_cs)
+            q.g_kd, q.g_korm, q.g_nrm, q.g_env = _ptr(req.g_kd), _ptr(req.g_korm), _ptr(req.g_nrm), _ptr(req.g_env)
+        ticket = C.c_int64()
+        caller = torch.cuda.current_stream()
+        L.check(L.lib().mcdi_server_submit(self.handle, C.byref(q), C.c_void_p(caller.cuda_stream),
+                                           C.byref(ticket)))
+        # the request (and through it every buffer the server reads or
+        # writes) stays referenced until its ticket is reported
         req.rid = self._rid
         self._rid += 1
-        req.t_submit = time.perf_counter()
-        env = self.scenes[req.scene][1]
-        req._bytes = request_bytes(req.gb.n, req.spp, req.grad, (env.H, env.W))
-        if req._bytes > self.budget:
-            raise ValueError("request larger than the memory budget")
-        _order_after_caller(req, self.stream)
-        self.queue.append(req)
+        self.pending[ticket.value] = req
         return req
 
-    def _admit(self):
-        while self.queue and len(self.admitted) < self.max_slots and self.used + self.queue[0]._bytes <= self.budget:
-            r = self.queue.popleft()
-            env = self.scenes[r.scene][1]
-            n, dev = r.gb.n, r.gb.pos.device
-            with torch.cuda.stream(self.stream):
-                r.c_d = torch.empty((3, n), dtype=torch.float32, device=dev)
-                r.c_s = torch.empty((3, n), dtype=torch.float32, device=dev)
-                r._hb = torch.empty((hit_words(r.spp), n), dtype=torch.int32, device=dev)
-                r._org = torch.empty((n, 4), dtype=torch.float32, device=dev)
-                if r.grad:
-                    r.g_kd = torch.empty((3, n), dtype=torch.float32, device=dev)
-                    r.g_korm = torch.empty((3, n), dtype=torch.float32, device=dev)
-                    r.g_nrm = torch.empty((3, n), dtype=torch.float32, device=dev)
-                    r.g_env = torch.zeros((env.H, env.W, 3), dtype=torch.float32, device=dev)
-            r._tiles = (n + TILE - 1) // TILE
-            r._next_tile = 0
-            self.used += r._bytes
-            self.admitted.append(r)
-
-    def _item(self, r, first, count):
-        scene, env = self.scenes[r.scene]
-        it = L.ServeItem()
-        it.scene, it.env = scene.handle, env.handle
-        it.gbuf = r.gb.struct()
-        it.params = L.Params(r.spp, int(r.flags), r.seed, float(r.tau), float(r.ray_eps), None)
-        it.c_d, it.c_s, it.hitbits, it.origins = (r.c_d.data_ptr(), r.c_s.data_ptr(), r._hb.data_ptr(),
-                                                  r._org.data_ptr())
-        if r.grad:
-            it.g_cd, it.g_cs = r.g_cd.data_ptr(), r.g_cs.data_ptr()
-            it.g_kd, it.g_korm, it.g_nrm, it.g_env = (r.g_kd.data_ptr(), r.g_korm.data_ptr(), r.g_nrm.data_ptr(),
-                                                      r.g_env.data_ptr())
-        it.first_tile, it.n_tiles = first, count
-        return it
-
-    def _launch(self):
-        """Pack pending tiles, oldest request first, up to the launch's work budget."""
-        items, finishing = [], []
-        budget = self.launch_samples
-        for r in self.admitted:
-            if r._next_tile >= r._tiles or budget <= 0:
-                continue
-            per_tile = TILE * r.spp * (2 if r.grad else 1)
-            take = min(r._tiles - r._next_tile, max(1, budget // per_tile))
-            items.append(self._item(r, r._next_tile, take))
-            r._next_tile += take
-            budget -= take * per_tile
-            if r._next_tile >= r._tiles:
-                finishing.append(r)
-        if not items:
-            return False
-        # first launch of a request: after the caller's writes of its inputs
-        for r in self.admitted:
-            if r._ready is not None and r._next_tile > 0:
-                self.stream.wait_event(r._ready)
-                r._ready = None
-        arr = (L.ServeItem * len(items))(*items)
-        L.check(L.lib().mcdi_server_launch(self.handle, arr, len(items)))
-        ev = torch.cuda.Event()
-        ev.record(self.stream)
-        self.in_flight.append((self.launch_id, ev, finishing))
-        self.launch_id += 1
-        self.n_launches += 1
-        return True
-
-    def _poll(self):
-        while self.in_flight and self.in_flight[0][1].query():
-            _, _, finishing = self.in_flight.popleft()
-            now = time.perf_counter()
-            for r in finishing:
-                r.t_done = now
-                self.used -= r._bytes
-                self.admitted.remove(r)
-                r._hb = None
-                r._org = None
-                self.completed.append(r)
+    def _collect(self, fn):
+        n = C.c_int32()
+        L.check(fn(self.handle, self._buf, len(self._buf), C.byref(n)))
+        now = time.perf_counter()
+        for k in range(n.value):
+            r = self.pending.pop(self._buf[k])
+            r.t_done = now
+            self.completed.append(r)
+        return n.value
 
     def pump(self):
-        """One scheduling step: completions, admission, and a launch if fewer
-        than two are in flight.  Returns True if work remains."""
-        self._poll()
-        self._admit()
-        while len(self.in_flight) < 2 and self._launch():
+        """Completions, admission and launches, without blocking.  Returns
+        True while requests are outstanding."""
+        while self._collect(L.lib().mcdi_server_poll) == len(self._buf):
             pass
-        return bool(self.queue or self.admitted or self.in_flight)
+        return bool(self.pending)
 
     def drain(self):
-        while self.pump():
-            time.sleep(0)
+        while self.pending:
+            self._collect(L.lib().mcdi_server_wait)
         return self.completed
 
 
@@ -266,8 +188,14 @@ class PerRequest:
         self._rid += 1
         req.t_submit = time.perf_counter()
         scene, env = self.scenes[req.scene]
-        _order_after_caller(req, self.stream)
-        self.stream.wait_event(req._ready)
+        # the inputs were written on the caller's stream: order after it, and
+        # keep their memory from being reused while this stream reads them
+        ready = torch.cuda.Event()
+        ready.record(torch.cuda.current_stream())
+        self.stream.wait_event(ready)
+        gb = req.gb
+        for t in [gb.pos, gb.nrm, gb.kd, gb.korm, gb.mask, gb.eye] + ([req.g_cd, req.g_cs] if req.grad else []):
+            t.record_stream(self.stream)
         with torch.cuda.stream(self.stream):
             req.c_d, req.c_s, hb, _ = shade_fwd(scene, env, req.gb, req.spp, seed=req.seed, tau=req.tau,
                                                 ray_eps=req.ray_eps, flags=req.flags, hitbits=req.grad,

@@ -133,35 +133,54 @@ def test_served_technique_flags_equal_staged(env):
 
 
 def test_admission_respects_budget(env):
+    """The server's scratch stays under the budget and the admitted requests
+    under the slot count at every poll; every request completes once."""
     M, scenes_np, resident = env
     from paper_2206_03380_amd.serve import Server, request_bytes
     draws = serving.make_requests(scenes_np, 20, seed=9, res=(64, 128))
     reqs = build_requests(M, scenes_np, draws)
-    sizes = [request_bytes(r.gb.n, r.spp, r.grad, (resident[r.scene][1].H, resident[r.scene][1].W)) for r in reqs]
+    sizes = [request_bytes(r.gb.n, r.spp) for r in reqs]
     budget = 3 * max(sizes)
     srv = Server(resident, budget_bytes=budget, max_slots=3, launch_samples=100_000, spp_max=64)
-    peak, peak_slots = 0, 0
+    peak, peak_slots, peak_queue = 0, 0, 0
     for r in reqs:
         srv.submit(r)
+        i = srv.info()
+        peak_queue = max(peak_queue, i["queued"])
     while srv.pump():
-        peak = max(peak, srv.used)
-        peak_slots = max(peak_slots, len(srv.admitted))
-    assert peak <= budget and peak_slots <= 3
-    assert len(srv.completed) == len(reqs)
+        i = srv.info()
+        peak = max(peak, i["used_bytes"])
+        peak_slots = max(peak_slots, i["admitted"])
+    assert 0 < peak <= budget and 0 < peak_slots <= 3 and peak_queue > 0
+    i = srv.info()
+    assert i["used_bytes"] == 0 and i["admitted"] == 0 and i["queued"] == 0
+    assert len(srv.completed) == len(reqs) and len({id(r) for r in srv.completed}) == len(reqs)
     assert all(r.done and r.latency > 0 for r in reqs)
 
 
 def test_server_rejects_bad_requests(env):
     M, scenes_np, resident = env
-    from paper_2206_03380_amd.serve import Server
+    from paper_2206_03380_amd.serve import Server, request_bytes
+    from paper_2206_03380_amd._lib import MCDIError, MCDI_E_INVALID, MCDI_E_UNSUPPORTED
     srv = Server(resident, spp_max=8)
     r = build_requests(M, scenes_np, [("A", 64, 16, False, 1)])[0]
-    with pytest.raises(ValueError):
+    with pytest.raises(MCDIError) as ei:
         srv.submit(r)
+    assert ei.value.status == MCDI_E_INVALID
+    r3 = build_requests(M, scenes_np, [("A", 64, 4, False, 3)])[0]
+    r3.flags = M.FLAG_DUMP
+    with pytest.raises(MCDIError) as ei:
+        srv.submit(r3)
+    assert ei.value.status == MCDI_E_INVALID
     small = Server(resident, budget_bytes=1024, spp_max=8)
     r2 = build_requests(M, scenes_np, [("A", 64, 4, False, 2)])[0]
-    with pytest.raises(ValueError):
+    assert request_bytes(r2.gb.n, r2.spp) > 1024
+    with pytest.raises(MCDIError) as ei:
         small.submit(r2)
+    assert ei.value.status == MCDI_E_UNSUPPORTED
+    assert small.info()["queued"] == 0 and not small.pending
+    # nothing was queued: both servers drain at once
+    assert srv.drain() == [] and small.drain() == []
 
 
 def test_submit_orders_after_the_callers_stream(env):
