@@ -232,6 +232,24 @@ mcdi_status mcdi_shade_fwd(mcdi_scene scene, mcdi_env env, const mcdi_gbuffer* g
                            const mcdi_params* params, float* c_d, float* c_s, uint32_t* hitbits,
                            mcdi_stats* stats, void* stream);
 
+/* Test hook: the forward pass with frozen sampling.  The sampling G-buffer
+ * g_s and probe env_s draw every sample, its technique densities (the
+ * balance-heuristic denominator), the lobe choice q and the shadow ray; the
+ * evaluation G-buffer g_e (its nrm, kd and korm planes) and probe env_e (its
+ * radiance) evaluate the BSDF, the cosine and the incident radiance of each
+ * sample (the sample's world direction re-expressed in g_e's shading frame).
+ * With g_e = g_s and env_e = env_s it equals mcdi_shade_fwd.  Central
+ * differences of it in the evaluation inputs are the derivatives that
+ * mcdi_shade_bwd computes, since the backward pass detaches sampling
+ * (section 4.1; section 3.1 "Shadow gradients").
+ * g_e must share size, view_base, pos, mask and eye with g_s; the probes
+ * must have the same size.  A pixel invalid in either G-buffer shades to 0.
+ * Allocates the ray workspace and a copy of the probe texels from the
+ * scene's allocator.  DUMP and TIME flags are rejected. */
+mcdi_status mcdi_shade_fwd_frozen(mcdi_scene scene, mcdi_env env_s, const mcdi_gbuffer* g_s, mcdi_env env_e,
+                                  const mcdi_gbuffer* g_e, const mcdi_params* params, float* c_d, float* c_s,
+                                  void* stream);
+
 /* Backward pass of the detached estimator, same samples as the forward.
  *   g_cd, g_cs   device [3][N] upstream gradients dL/dc_d, dL/dc_s
  *   hitbits      the forward pass's hit bits, or NULL to re-trace the rays

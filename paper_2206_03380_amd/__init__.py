@@ -221,6 +221,22 @@ def shade_fwd(scene, env, gb, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0, hitbi
     return c_d, c_s, hb, dec
 
 
+def shade_fwd_frozen(scene, env_s, gb_s, env_e, gb_e, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0,
+                     stream=None):
+    """Forward pass with frozen sampling (test hook): gb_s / env_s draw the
+    samples, gb_e (nrm, kd, korm) / env_e (radiance) evaluate them.
+    Returns (c_d, c_s)."""
+    n = gb_s.n
+    dev = gb_s.pos.device
+    c_d = torch.empty((3, n), dtype=torch.float32, device=dev)
+    c_s = torch.empty((3, n), dtype=torch.float32, device=dev)
+    g1, g2 = gb_s.struct(), gb_e.struct()
+    prm = _params(spp, seed, tau, ray_eps, flags, None)
+    L.check(L.lib().mcdi_shade_fwd_frozen(scene.handle, env_s.handle, C.byref(g1), env_e.handle, C.byref(g2),
+                                          C.byref(prm), _ptr(c_d), _ptr(c_s), _stream(stream)))
+    return c_d, c_s
+
+
 def shade_bwd(scene, env, gb, spp, g_cd, g_cs, hitbits=None, seed=0, tau=1.0, ray_eps=1e-3, flags=0,
               g_env=None, stats=None, out=None, stream=None):
     """Backward pass.  Returns (g_kd, g_korm, g_nrm, g_env); g_env is

@@ -107,6 +107,9 @@ def lib():
     L.mcdi_env_tables.restype = C.c_int
     L.mcdi_shade_fwd.restype = C.c_int
     L.mcdi_shade_fwd.argtypes = [vp, vp, C.POINTER(GBuffer), C.POINTER(Params), vp, vp, vp, vp, vp]
+    L.mcdi_shade_fwd_frozen.restype = C.c_int
+    L.mcdi_shade_fwd_frozen.argtypes = [vp, vp, C.POINTER(GBuffer), vp, C.POINTER(GBuffer), C.POINTER(Params), vp,
+                                        vp, vp]
     L.mcdi_shade_bwd.restype = C.c_int
     L.mcdi_shade_bwd.argtypes = [vp, vp, C.POINTER(GBuffer), C.POINTER(Params), vp, vp, vp, vp, vp, vp,
                                  vp, vp, vp]
@@ -165,7 +168,7 @@ def check(status):
 
 
 EXPORTED = ("mcdi_build_scene", "mcdi_destroy_scene", "mcdi_scene_info", "mcdi_scene_nodes", "mcdi_build_env_cdf",
-            "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_bwd",
+            "mcdi_destroy_env", "mcdi_env_tables", "mcdi_shade_fwd", "mcdi_shade_fwd_frozen", "mcdi_shade_bwd",
             "mcdi_trace_anyhit", "mcdi_trace_times", "mcdi_adjoint_times", "mcdi_server_create",
             "mcdi_server_request_bytes", "mcdi_server_submit", "mcdi_server_poll", "mcdi_server_wait",
             "mcdi_server_info", "mcdi_server_destroy", "mcdi_image_loss", "mcdi_image_loss_noalloc", "mcdi_bilateral_radius", "mcdi_bilateral_fwd",

@@ -463,6 +463,47 @@ mcdi_status mcdi_shade_fwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, co
     return ok();
 }
 
+mcdi_status mcdi_shade_fwd_frozen(mcdi_scene sc, mcdi_env ev_s, const mcdi_gbuffer* g_s, mcdi_env ev_e,
+                                  const mcdi_gbuffer* g_e, const mcdi_params* p, float* c_d, float* c_s,
+                                  void* stream) {
+    ShadeArgs a;
+    mcdi_status st = fill_common("mcdi_shade_fwd_frozen", sc, ev_s, g_s, p, a);
+    if (st != MCDI_OK) return st;
+    if (!ev_e || !g_e || !c_d || !c_s) return fail(MCDI_E_INVALID, "mcdi_shade_fwd_frozen: NULL argument");
+    if (p->flags & (MCDI_FLAG_DUMP | MCDI_FLAG_DUMP_DIRS | MCDI_FLAG_TIME_TRACE | MCDI_FLAG_TIME_ADJOINT))
+        return fail(MCDI_E_INVALID, "mcdi_shade_fwd_frozen: dump and timing flags are not supported");
+    if (ev_e->H != ev_s->H || ev_e->W != ev_s->W)
+        return fail(MCDI_E_INVALID, "mcdi_shade_fwd_frozen: the probes differ in size");
+    if (g_e->n_views != g_s->n_views || g_e->height != g_s->height || g_e->width != g_s->width ||
+        g_e->view_base != g_s->view_base || g_e->pos != g_s->pos || g_e->mask != g_s->mask || g_e->eye != g_s->eye)
+        return fail(MCDI_E_INVALID,
+                    "mcdi_shade_fwd_frozen: the G-buffers must share size, view_base, pos, mask and eye");
+    if (!g_e->nrm || !g_e->kd || !g_e->korm) return fail(MCDI_E_INVALID, "mcdi_shade_fwd_frozen: NULL G-buffer plane");
+    hipStream_t s = (hipStream_t)stream;
+    a.c_d = c_d;
+    a.c_s = c_s;
+    a.e_nrm = g_e->nrm;
+    a.e_kd = g_e->kd;
+    a.e_korm = g_e->korm;
+    // probe texels: the evaluation probe's radiance with the sampling probe's density
+    const int64_t n_tex = (int64_t)ev_s->H * ev_s->W;
+    Workspace wt;
+    wt.alloc = &sc->alloc;
+    wt.s = s;
+    wt.base = sc->alloc.get(sizeof(float4) * (size_t)n_tex, s);
+    if (!wt.base) return fail(MCDI_E_OOM, "mcdi_shade_fwd_frozen: workspace allocation failed");
+    Workspace ws;
+    uint32_t* bits = nullptr;
+    st = trace_pipeline("mcdi_shade_fwd_frozen", sc, a, nullptr, s, ws, &bits);
+    if (st != MCDI_OK) return st;
+    a.hitbits_in = bits;
+    a.env.tex = (float4*)wt.base;
+    hipError_t e = launch_env_mix(ev_e->tex, ev_s->tex, n_tex, (float4*)wt.base, s);
+    if (e == hipSuccess) e = launch_shade_fwd_frozen(a, s);
+    if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_shade_fwd_frozen: %s", hipGetErrorString(e));
+    return ok();
+}
+
 mcdi_status mcdi_shade_bwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, const mcdi_params* p,
                            const float* g_cd, const float* g_cs, const uint32_t* hitbits, float* g_kd,
                            float* g_korm, float* g_nrm, float* g_env, mcdi_stats* stats, void* stream) {

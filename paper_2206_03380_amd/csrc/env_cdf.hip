@@ -121,7 +121,19 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* env, const float
     if (k < n) tex[k] = make_float4(env[3 * k], env[3 * k + 1], env[3 * k + 2], pdf[k]);
 }
 
+__global__ __launch_bounds__(256) void mix_kernel(const float4* rgb, const float4* dens, int64_t n, float4* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float4 a = rgb[k];
+    out[k] = make_float4(a.x, a.y, a.z, dens[k].w);
+}
+
 }  // namespace
+
+hipError_t launch_env_mix(const float4* rgb, const float4* dens, int64_t n, float4* out, hipStream_t s) {
+    hipLaunchKernelGGL(mix_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rgb, dens, n, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_env_pack(const float* env, const float* pdf, int64_t n, float4* tex, hipStream_t s) {
     hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, env, pdf, n, tex);

@@ -115,6 +115,12 @@ struct ShadeArgs {
     float4* rec;
     uint32_t* rec_count;
     uint32_t rec_region;
+    // frozen sampling (forward only): the planes that evaluate the samples
+    // drawn from g (normal, albedo, occlusion/roughness/metallic); NULL
+    // otherwise
+    const float* e_nrm;
+    const float* e_kd;
+    const float* e_korm;
 };
 
 // one serving work item: a contiguous range of tiles of one request
@@ -135,6 +141,8 @@ hipError_t launch_env_cdf(const float* env, int H, int W, float* cond, float* ma
 int env_guide_cells(int W);
 // (r, g, b, pdf) per texel, after the tables
 hipError_t launch_env_pack(const float* env, const float* pdf, int64_t n, float4* tex, hipStream_t s);
+// out[k] = (rgb[k].xyz, dens[k].w)
+hipError_t launch_env_mix(const float4* rgb, const float4* dens, int64_t n, float4* out, hipStream_t s);
 hipError_t launch_env_guide(const float* cond, int H, int W, int G, int32_t* guide, hipStream_t s);
 hipError_t launch_env_hot(const float* pdf, int H, int W, int32_t* hot_slot, int32_t* hot_texel, int32_t* n_hot,
                           hipStream_t s);
@@ -145,6 +153,10 @@ hipError_t launch_order_tiles(const int32_t* ray_count, int64_t n_tiles, int32_t
 hipError_t launch_trace_rays(const ShadeArgs& a, uint32_t* hitbits, hipStream_t s);
 hipError_t launch_shade_fwd(const ShadeArgs& a, hipStream_t s);
 hipError_t launch_shade_bwd(const ShadeArgs& a, hipStream_t s);
+// forward with frozen sampling: samples, densities, lobe choice and
+// visibility from a.g, the material and the probe radiance evaluated from
+// a.e_* and a.env.tex (whose w, the density, is the sampling probe's)
+hipError_t launch_shade_fwd_frozen(const ShadeArgs& a, hipStream_t s);
 hipError_t launch_trace(const Scene& sc, const float* o, const float* d, int64_t n, uint8_t* hit,
                         int brute, hipStream_t s);
 

@@ -160,10 +160,22 @@ __device__ __forceinline__ void scatter_texel(const ShadeArgs& A, int texel, flo
     }
 }
 
-template <bool BWD, bool BIL>
+// balance-heuristic denominator of a sample: the densities of the techniques
+// in use at its direction
+__device__ __forceinline__ float mis_density(const Pixel& P, const Sample& S) {
+    const float3 hl = normalize(P.Vl + S.wl);
+    const float D = ggx_D(hl.z, hl.x * hl.x + hl.y * hl.y, P.a2);
+    const float pcos = S.wl.z * kInvPi;
+    const float pggx = P.nov_pos ? P.G1V * D / (4.0f * P.nov) : 0.0f;
+    return S.pL + P.bsdf_w * (P.q * pcos + (1.0f - P.q) * pggx);
+}
+
+// FROZEN: the sample was drawn from another pixel state, whose density
+// (Pt_frozen) weighs it; P and S.wl evaluate it
+template <bool BWD, bool BIL, bool FROZEN = false>
 __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, const Sample& S, float Hv,
                                             float invspp, FwdAcc& fa, BwdAcc& ba, float3 Ud, float3 Us,
-                                            float* s_hot, const RecSink& rs) {
+                                            float* s_hot, const RecSink& rs, float Pt_frozen = 0.0f) {
     const float NoL = S.wl.z;
     const float3 hl = normalize(P.Vl + S.wl);
     const float NoH = hl.z;
@@ -173,7 +185,7 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
     const float pcos = NoL * kInvPi;
     const float pggx = P.nov_pos ? P.G1V * D / (4.0f * P.nov) : 0.0f;
     // balance heuristic over the techniques in use
-    const float Pt = S.pL + P.bsdf_w * (P.q * pcos + (1.0f - P.q) * pggx);
+    const float Pt = FROZEN ? Pt_frozen : S.pL + P.bsdf_w * (P.q * pcos + (1.0f - P.q) * pggx);
     const float w = Hv / Pt;
     float3 L;
     float pdf_uv = 0.0f;   // nearest lookup: the texel's density (pdf table)
@@ -503,7 +515,9 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
 constexpr uint32_t kNanBits = 0x7FC00000u;
 __device__ __forceinline__ int dump_stride(const ShadeArgs& A) { return (A.flags & MCDI_FLAG_DUMP_DIRS) ? 9 : 3; }
 
-template <bool BWD, bool DUMP, bool BIL>
+// FROZEN (forward only): samples, densities, lobe choice and visibility from
+// the G-buffer A.g, the samples evaluated with the planes A.e_*
+template <bool BWD, bool DUMP, bool BIL, bool FROZEN = false>
 __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, const float* s_marg, float* s_hot,
                                            const RecSink& rs) {
     const int64_t N = A.g.n;
@@ -514,7 +528,16 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
     if (pix >= N) return;
     bool nonfinite;
     const Pixel P = setup_pixel(A, pix, nonfinite);
-    if (!P.valid) {
+    Pixel Pe;
+    if (FROZEN) {
+        ShadeArgs Ae = A;
+        Ae.g.nrm = A.e_nrm;
+        Ae.g.kd = A.e_kd;
+        Ae.g.korm = A.e_korm;
+        bool nf;
+        Pe = setup_pixel(Ae, pix, nf);
+    }
+    if (!P.valid || (FROZEN && !Pe.valid)) {
         if (!BWD) {
             for (int c = 0; c < 3; ++c) { A.c_d[c * N + pix] = 0.0f; A.c_s[c * N + pix] = 0.0f; }
         } else {
@@ -579,7 +602,16 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
                     rec2 |= tech ? kDecBHit : kDecLHit;
                 }
             }
-            eval_sample<BWD, BIL>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
+            if (FROZEN) {
+                // the sample's direction in the evaluation frame (the
+                // sampled local direction itself where the frame is the same)
+                Sample Se = S;
+                if (!(Pe.n.x == P.n.x && Pe.n.y == P.n.y && Pe.n.z == P.n.z))
+                    Se.wl = f3(dot(S.w, Pe.t), dot(S.w, Pe.b), dot(S.w, Pe.n));
+                eval_sample<BWD, BIL, true>(A, Pe, Se, Hv, invspp, fa, ba, Ud, Us, s_hot, rs, mis_density(P, S));
+            } else {
+                eval_sample<BWD, BIL>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
+            }
         }
         if (DUMP) {
             const int st = dump_stride(A);
@@ -707,6 +739,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     shade_body<BWD, DUMP, BIL>(A);
 }
 
+// forward with frozen sampling (a test instantiation: finite differences of
+// the estimator with its samples held fixed)
+template <bool BIL>
+__global__ __launch_bounds__(kBlock) void shade_frozen_kernel(ShadeArgs A) {
+    extern __shared__ float smem[];
+    stage_marg(A, smem);
+    __syncthreads();
+    shade_tile<false, false, BIL, true>(A, blockIdx.x, smem, nullptr, RecSink{nullptr, nullptr});
+}
+
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void shade_bwd_bilinear_kernel(ShadeArgs A) {
     shade_body<true, false, true>(A);
 }
@@ -818,6 +860,13 @@ hipError_t launch_serve(const ServeItem* items_dev, int n_items, int64_t total_t
     const size_t lds = sizeof(float) * (3 * kHotMax + (size_t)max_H + 1);
     hipLaunchKernelGGL(serve_kernel, dim3(n_workgroups), dim3(kBlock), lds, s, items_dev, n_items, total_tiles,
                        tile_counter, scratch, spp_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade_fwd_frozen(const ShadeArgs& a, hipStream_t s) {
+    const dim3 g(n_blocks(a)), b(kBlock);
+    if (a.flags & MCDI_FLAG_BILINEAR) hipLaunchKernelGGL(shade_frozen_kernel<true>, g, b, marg_lds(a), s, a);
+    else hipLaunchKernelGGL(shade_frozen_kernel<false>, g, b, marg_lds(a), s, a);
     return hipGetLastError();
 }
 
