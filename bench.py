@@ -249,8 +249,9 @@ def measure(args, M, w, steps, warmup):
                 "frac": achieved / VALU_PEAK, "traffic": measured_traffic(tfile),
                 "kernel": "trace_rays_kernel", "ops_per_launch": ops, "kernel_ms": trace_ms,
                 "units": {"rays": rays, "box_tests": stats["box_tests"], "tri_tests": stats["tri_tests"]},
-                "lane_utilisation": {"box": stats["box_tests"] / max(stats["box_slots"], 1),
-                                     "tri": stats["tri_tests"] / max(stats["tri_slots"], 1)}}
+                "lane_utilisation": {"box": stats["box_lanes"] / max(stats["box_slots"], 1),
+                                     "tri": stats["tri_tests"] / max(stats["tri_slots"], 1)},
+                "box_tests_per_lane_step": stats["box_tests"] / max(stats["box_lanes"], 1)}
     # ---- roofline of the adjoint kernel (shade_kernel<true>) ----
     adj_ops = ADJ_OPS_PER_SAMPLE * stats["valid_pixels"] * w.spp + ADJ_OPS_PER_EVAL * rays
     adj_a = adj_ops / (adj_ms * 1e-3) if adj_ms > 0 else 0.0
@@ -290,12 +291,12 @@ ADJ_OPS_PER_SAMPLE = 310
 ADJ_OPS_PER_EVAL = 145
 
 
-# per-unit VALU lane-operation counts of the traversal: slab test of one node
-# box (6 sub, 6 mul, 6 min/max per axis, 5 min/max for the interval, 1 mul for
-# the slack, 1 compare), watertight test of one triangle (9 sub, 6 shear FMA,
-# 6 mul + 3 sub for the edge functions, 6 sign compares, 2 add, 6 for the hit
-# distance, 1 compare), ray setup
-OPS_PER_BOX = 25
+# per-unit VALU lane-operation counts of the traversal: slab test of one
+# child box (6 sub, 6 mul, 6 min/max per axis, 5 min/max for the interval, 1
+# compare), watertight test of one triangle (9 sub, 6 shear FMA, 6 mul + 3 sub
+# for the edge functions, 6 sign compares, 2 add, 6 for the hit distance, 1
+# compare), ray setup
+OPS_PER_BOX = 24
 OPS_PER_TRI = 39
 OPS_PER_RAY = 25
 

@@ -72,10 +72,18 @@ typedef struct {
  * tris    device int32   [n_tris][3], vertex indices
  * Builds a bounding-volume hierarchy on the device (Morton-ordered linear BVH,
  * leaves of <= 4 triangles, depth-first node order with skip links), and a
- * copy of its nodes for the shadow-ray traversal whose boxes are quantised
- * outward to 16 bits per coordinate against the scene's bounding box (16
- * bytes per node, one load per box test; a box grows by at most 1/65535 of
- * the scene's extent per side, which costs box tests, never a wrong answer).
+ * copy of its nodes whose boxes are quantised outward to 16 bits per
+ * coordinate against the scene's bounding box (16 bytes per node; a box grows
+ * by at most 1/65535 of the scene's extent per side, which costs box tests,
+ * never a wrong answer), and a 4-wide hierarchy: the binary tree collapsed
+ * every other level, each wide node holding the quantised boxes and
+ * references of up to four children in one 64-byte segment (one memory round
+ * trip tests four boxes).  The build also measures the scene's depth
+ * complexity (the leaf boxes' surface areas summed, over the root box's):
+ * shadow rays walk the 4-wide hierarchy when it is at least 4 (volume-
+ * filling geometry: long walks bound by memory latency), else the binary
+ * one (surfaces: short cache-resident walks bound by instruction issue).
+ * Either walk gives the same answers.
  * A triangle with an index outside [0, n_verts) or a non-finite vertex is
  * replaced by a degenerate triangle that no ray hits (counted in
  * mcdi_scene_info).  n_tris = 0 gives a scene every ray misses.
@@ -101,7 +109,9 @@ typedef struct {
     int32_t n_nodes;      /* BVH nodes after leaf collapsing */
     int32_t max_depth;    /* longest root-to-leaf path */
     int32_t bad_tris;     /* triangles replaced by degenerate ones */
-    int32_t reserved;
+    int32_t n_groups;     /* 4-wide nodes */
+    int32_t wide;         /* 1: shadow rays walk the 4-wide hierarchy, 0: the binary one */
+    float depth_complexity; /* sum of the leaf boxes' surface areas over the root box's */
 } mcdi_scene_info_t;
 
 /* Synchronises the scene's stream and reports build statistics. */
@@ -214,10 +224,11 @@ typedef struct {
     unsigned long long rays_traced;
     unsigned long long rays_hit;
     unsigned long long samples_culled;   /* below the horizon */
-    unsigned long long box_tests;        /* BVH node boxes tested */
+    unsigned long long box_tests;        /* child boxes tested (empty slots of wide nodes not counted) */
     unsigned long long tri_tests;        /* ray/triangle tests */
     unsigned long long box_slots;        /* lane slots of the box phase: 64 per wavefront step */
     unsigned long long tri_slots;        /* lane slots of the triangle phase */
+    unsigned long long box_lanes;        /* lanes that stepped in the box phase, summed over its steps */
 } mcdi_stats;
 
 /* Forward pass.
@@ -263,8 +274,9 @@ mcdi_status mcdi_shade_bwd(mcdi_scene scene, mcdi_env env, const mcdi_gbuffer* g
 
 /* Any-hit queries for explicit rays (tests and tools).
  *   orig, dir  device float32 [3][n]; hit device uint8 [n] (1 = occluded),
- *   t in (0, inf), no culling.  brute != 0 tests every triangle instead of
- *   traversing the BVH. */
+ *   t in (0, inf), no culling.  mode (the `brute` argument): 0 traverses the
+ *   binary hierarchy, 1 tests every triangle, 2 traverses the 4-wide
+ *   hierarchy (the one the shading calls use). */
 mcdi_status mcdi_trace_anyhit(mcdi_scene scene, const float* orig, const float* dir, int64_t n,
                               uint8_t* hit, int32_t brute, void* stream);
 

@@ -74,7 +74,8 @@ class Scene:
     def info(self):
         i = L.SceneInfo()
         L.check(L.lib().mcdi_scene_info(self.handle, C.byref(i)))
-        return {"n_tris": i.n_tris, "n_nodes": i.n_nodes, "max_depth": i.max_depth, "bad_tris": i.bad_tris}
+        return {"n_tris": i.n_tris, "n_nodes": i.n_nodes, "max_depth": i.max_depth, "bad_tris": i.bad_tris,
+                "n_groups": i.n_groups, "wide": i.wide, "depth_complexity": i.depth_complexity}
 
     def nodes(self, stream=None):
         """The BVH as device tensors: nodes int32 [n_nodes, 8] (lo xyz and hi
@@ -181,13 +182,14 @@ def hit_words(spp):
 
 
 def new_stats(device="cuda"):
-    return torch.zeros(9, dtype=torch.int64, device=device)
+    return torch.zeros(10, dtype=torch.int64, device=device)
 
 
 def read_stats(t):
     v = t.cpu().tolist()
     return {"valid_pixels": v[0], "invalid_pixels": v[1], "rays_traced": v[2], "rays_hit": v[3],
-            "samples_culled": v[4], "box_tests": v[5], "tri_tests": v[6], "box_slots": v[7], "tri_slots": v[8]}
+            "samples_culled": v[4], "box_tests": v[5], "tri_tests": v[6], "box_slots": v[7], "tri_slots": v[8],
+            "box_lanes": v[9]}
 
 
 def _params(spp, seed, tau, ray_eps, flags, decisions):
@@ -460,14 +462,16 @@ def bilateral_bwd(guide, g_out, wsum, stream=None, out=None):
     return g_in
 
 
-def trace_anyhit(scene, orig, dirs, brute=False, stream=None):
-    """orig, dirs: device f32 [3, n].  Returns uint8 [n] (1 = occluded)."""
+def trace_anyhit(scene, orig, dirs, brute=False, stream=None, mode=None):
+    """orig, dirs: device f32 [3, n].  Returns uint8 [n] (1 = occluded).
+    mode: "binary", "brute" or "wide" (default: "brute" if brute else
+    "binary")."""
     n = orig.shape[1]
     _need(orig, torch.float32, (3, n), "orig")
     _need(dirs, torch.float32, (3, n), "dirs")
     hit = torch.empty(n, dtype=torch.uint8, device=orig.device)
-    L.check(L.lib().mcdi_trace_anyhit(scene.handle, _ptr(orig), _ptr(dirs), n, _ptr(hit), int(brute),
-                                      _stream(stream)))
+    m = {"binary": 0, "brute": 1, "wide": 2}[mode or ("brute" if brute else "binary")]
+    L.check(L.lib().mcdi_trace_anyhit(scene.handle, _ptr(orig), _ptr(dirs), n, _ptr(hit), m, _stream(stream)))
     return hit
 
 

@@ -65,7 +65,8 @@ class ServerInfo(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("valid_pixels", C.c_uint64), ("invalid_pixels", C.c_uint64), ("rays_traced", C.c_uint64),
                 ("rays_hit", C.c_uint64), ("samples_culled", C.c_uint64), ("box_tests", C.c_uint64),
-                ("tri_tests", C.c_uint64), ("box_slots", C.c_uint64), ("tri_slots", C.c_uint64)]
+                ("tri_tests", C.c_uint64), ("box_slots", C.c_uint64), ("tri_slots", C.c_uint64),
+                ("box_lanes", C.c_uint64)]
 
 
 class BilateralGuide(C.Structure):
@@ -76,7 +77,8 @@ class BilateralGuide(C.Structure):
 
 class SceneInfo(C.Structure):
     _fields_ = [("n_tris", C.c_int64), ("n_nodes", C.c_int32), ("max_depth", C.c_int32),
-                ("bad_tris", C.c_int32), ("reserved", C.c_int32)]
+                ("bad_tris", C.c_int32), ("n_groups", C.c_int32), ("wide", C.c_int32),
+                ("depth_complexity", C.c_float)]
 
 
 _lib = None

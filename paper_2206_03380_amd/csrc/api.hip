@@ -138,6 +138,8 @@ struct mcdi_scene_s {
     Node* nodes = nullptr;
     float4* tris = nullptr;
     QNode* qnodes = nullptr;
+    QNode* groups = nullptr;       // 4 * group_cap records
+    size_t group_cap = 0;
     QFrame* frame = nullptr;
     DeviceSceneInfo* info = nullptr;
     hipEvent_t built = nullptr;     // recorded on the build stream after the build
@@ -146,6 +148,11 @@ struct mcdi_scene_s {
 };
 
 namespace {
+
+Scene scene_view(mcdi_scene sc) {
+    return Scene{sc->nodes, sc->tris, sc->n_tris, sc->qnodes, sc->frame, sc->groups,
+                 (uint32_t)(sizeof(QNode) * 4 * sc->group_cap), sc->info};
+}
 
 // work that reads the scene on stream u waits for the build (a no-op order
 // on the build stream itself)
@@ -216,8 +223,10 @@ mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t*
     sc->tris = (float4*)sc->alloc.get(sizeof(float4) * 3 * (size_t)(n_tris > 0 ? n_tris : 1), s);
     sc->qnodes = (QNode*)sc->alloc.get(sizeof(QNode) * n_nodes, s);
     sc->frame = (QFrame*)sc->alloc.get(sizeof(QFrame), s);
+    sc->group_cap = n_tris > 1 ? (size_t)n_tris : 1;
+    sc->groups = (QNode*)sc->alloc.get(sizeof(QNode) * 4 * sc->group_cap, s);
     sc->info = (DeviceSceneInfo*)sc->alloc.get(sizeof(DeviceSceneInfo), s);
-    if (!sc->nodes || !sc->tris || !sc->qnodes || !sc->frame || !sc->info) {
+    if (!sc->nodes || !sc->tris || !sc->qnodes || !sc->frame || !sc->groups || !sc->info) {
         mcdi_destroy_scene(sc);
         return fail(MCDI_E_OOM, "mcdi_build_scene: device allocation failed (%lld triangles)", (long long)n_tris);
     }
@@ -229,7 +238,7 @@ mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t*
     }
     TempAlloc ta{temp_alloc, temp_free, &sc->alloc};
     int oom = 0;
-    hipError_t e = build_bvh(verts, n_verts, tris, n_tris, sc->nodes, sc->tris, sc->qnodes, sc->frame, sc->info, ta,
+    hipError_t e = build_bvh(verts, n_verts, tris, n_tris, sc->nodes, sc->tris, sc->qnodes, sc->frame, sc->groups, sc->info, ta,
                              s, &oom);
     if (e == hipSuccess) e = hipEventRecord(sc->built, s);
     if (e != hipSuccess) {
@@ -250,6 +259,7 @@ void mcdi_destroy_scene(mcdi_scene sc) {
     sc->alloc.put(sc->tris, sc->stream);
     sc->alloc.put(sc->qnodes, sc->stream);
     sc->alloc.put(sc->frame, sc->stream);
+    sc->alloc.put(sc->groups, sc->stream);
     sc->alloc.put(sc->info, sc->stream);
     if (sc->built) (void)hipEventDestroy(sc->built);
     if (sc->last_use) (void)hipEventDestroy(sc->last_use);
@@ -266,7 +276,9 @@ mcdi_status mcdi_scene_info(mcdi_scene sc, mcdi_scene_info_t* info) {
     info->n_nodes = h.n_nodes;
     info->max_depth = h.max_depth;
     info->bad_tris = h.bad_tris;
-    info->reserved = 0;
+    info->n_groups = h.n_groups;
+    info->wide = h.wide;
+    info->depth_complexity = h.depth_complexity;
     return ok();
 }
 
@@ -374,7 +386,7 @@ static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, cons
     if ((p->flags & MCDI_FLAG_FORCE_COS) && (p->flags & MCDI_FLAG_FORCE_GGX))
         return fail(MCDI_E_INVALID, "%s: FORCE_COS and FORCE_GGX together", who);
     std::memset(&a, 0, sizeof(a));
-    a.scene = Scene{sc->nodes, sc->tris, sc->n_tris, sc->qnodes, sc->frame};
+    a.scene = scene_view(sc);
     a.env = EnvView{ev->H, ev->W, ev->cond, ev->marg, ev->light, ev->hot_slot, ev->hot_texel, ev->n_hot, ev->guide,
                     ev->G, ev->tex};
     a.g = GBufView{g->n_views, g->height, g->width, g->view_base, g->pos, g->nrm, g->kd, g->korm, g->mask, g->eye, n};
@@ -1097,9 +1109,10 @@ mcdi_status mcdi_trace_anyhit(mcdi_scene sc, const float* orig, const float* dir
     if (n < 0) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: negative n");
     if (n >= (int64_t)1 << 31) return fail(MCDI_E_UNSUPPORTED, "mcdi_trace_anyhit: n >= 2^31");
     if (n > 0 && (!orig || !dir || !hit)) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: NULL buffer");
+    if (brute < 0 || brute > 2) return fail(MCDI_E_INVALID, "mcdi_trace_anyhit: mode must be 0, 1 or 2");
     hipError_t e = scene_acquire(sc, (hipStream_t)stream);
     if (e == hipSuccess)
-        e = launch_trace(Scene{sc->nodes, sc->tris, sc->n_tris, sc->qnodes, sc->frame}, orig, dir, n, hit, brute, (hipStream_t)stream);
+        e = launch_trace(scene_view(sc), orig, dir, n, hit, brute, (hipStream_t)stream);
     if (e == hipSuccess) e = scene_release(sc, (hipStream_t)stream);
     if (e != hipSuccess) return fail(MCDI_E_DEVICE, "mcdi_trace_anyhit: %s", hipGetErrorString(e));
     return ok();

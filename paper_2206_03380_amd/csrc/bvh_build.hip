@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 #include <cstring>
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "mcdi_internal.h"
 
@@ -430,7 +431,7 @@ __device__ QNode quantise(const QFrame& F, const Node& nd) {
 }
 
 __global__ __launch_bounds__(256) void emit(int nt, Tree T, Node* out, QNode* qout, QFrame* frame,
-                                            DeviceSceneInfo* info) {
+                                            DeviceSceneInfo* info, int32_t* gflag) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= 2 * nt - 1) return;
     const bool is_prim = x >= nt - 1;
@@ -468,6 +469,8 @@ __global__ __launch_bounds__(256) void emit(int nt, Tree T, Node* out, QNode* qo
     qframe_of(T.box[0], T.box[1], F);
     qout[idx] = quantise(F, nd);
     if (idx == 0) *frame = F;
+    // a wide node for the root and for every internal node at even depth
+    gflag[idx] = (idx == 0 || (payload == 0 && (depth & 1) == 0)) ? 1 : 0;
     atomicMax(&info->max_depth, depth);
     if (x == 0) info->n_nodes = T.cnt[0];
 }
@@ -482,8 +485,58 @@ __global__ void reorder(const float4* tmp, const uint32_t* vals, int64_t nt, flo
 }
 
 // scene of 0 or 1 triangles
+// The 4-wide hierarchy of the shadow-ray traversal, collapsed from the binary
+// one: a wide node for the root and for every internal node N at even depth,
+// whose up to four children are N's children, a child that is internal being
+// replaced by its own two children.  A child record is the quantised box of
+// that binary node with w = its wide node's index (internal) or kQLeaf |
+// payload (leaf); unused slots hold an empty record (lo > hi: no ray hits it).
+// Wide nodes are numbered in the binary pre-order of their nodes (an
+// exclusive scan of the flags), so the wide hierarchy is in pre-order too.
+__device__ __forceinline__ QNode empty_record() {
+    QNode q;
+    q.x = 0xFFFFFFFFu;   // lo.x = lo.y = 65535
+    q.y = 0x0000FFFFu;   // lo.z = 65535, hi.x = 0
+    q.z = 0u;            // hi.y = hi.z = 0
+    q.w = kQLeaf;        // an empty leaf, should it ever be taken
+    return q;
+}
+
+__device__ __forceinline__ QNode child_record(const Node* out, const QNode* qout, const int32_t* gidx, int x) {
+    QNode q = qout[x];
+    if (out[x].payload == 0) q.w = (uint32_t)gidx[x];
+    return q;
+}
+
+__global__ __launch_bounds__(256) void wide_groups(const Node* out, const QNode* qout, const int32_t* gflag,
+                                                   const int32_t* gidx, int n_max, QNode* groups) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n_max) return;
+    const int n_nodes = out[0].escape;            // surviving binary nodes
+    if (x >= n_nodes || !gflag[x]) return;
+    QNode* g = groups + 4 * (size_t)gidx[x];
+    int k = 0;
+    if (out[x].payload != 0) {                    // a root that is a leaf
+        g[k++] = child_record(out, qout, gidx, x);
+    } else {
+        const int c[2] = {x + 1, out[x + 1].escape};
+        for (int i = 0; i < 2; ++i) {
+            const int y = c[i];
+            if (y <= x || y >= n_nodes) continue;    // never for a valid tree
+            if (out[y].payload != 0) {
+                g[k++] = child_record(out, qout, gidx, y);
+            } else {
+                const int d[2] = {y + 1, out[y + 1].escape};
+                for (int j = 0; j < 2; ++j)
+                    if (d[j] > y && d[j] < n_nodes) g[k++] = child_record(out, qout, gidx, d[j]);
+            }
+        }
+    }
+    for (; k < 4; ++k) g[k] = empty_record();
+}
+
 __global__ void tiny_scene(const float4* tmp, int nt, Node* out, float4* tris_out, QNode* qout, QFrame* frame,
-                           DeviceSceneInfo* info) {
+                           DeviceSceneInfo* info, QNode* groups) {
     Node nd;
     if (nt == 0) {
         for (int k = 0; k < 3; ++k) { nd.lo[k] = 0.0f; nd.hi[k] = 0.0f; }
@@ -506,13 +559,49 @@ __global__ void tiny_scene(const float4* tmp, int nt, Node* out, float4* tris_ou
     qout[0] = quantise(F, nd);
     *frame = F;
     info->max_depth = 0;
+    groups[0] = nt == 0 ? empty_record() : qout[0];
+    for (int k = 1; k < 4; ++k) groups[k] = empty_record();
+    info->n_groups = 1;
+}
+
+__global__ void count_groups(const int32_t* gflag, const int32_t* gidx, int n, DeviceSceneInfo* info) {
+    info->n_groups = gidx[n - 1] + gflag[n - 1];
 }
 
 __global__ void init_info(DeviceSceneInfo* info) {
     info->n_nodes = 0;
     info->max_depth = 0;
     info->bad_tris = 0;
-    info->pad = 0;
+    info->n_groups = 0;
+    info->wide = 0;
+    info->depth_complexity = 0.0f;
+    info->leaf_area = 0.0;
+}
+
+__device__ __forceinline__ double box_area(const Node& nd) {
+    const double dx = fmax((double)nd.hi[0] - nd.lo[0], 0.0), dy = fmax((double)nd.hi[1] - nd.lo[1], 0.0),
+                 dz = fmax((double)nd.hi[2] - nd.lo[2], 0.0);
+    return 2.0 * (dx * dy + dy * dz + dz * dx);
+}
+
+// the leaf boxes' surface areas, summed into info->leaf_area
+__global__ __launch_bounds__(256) void leaf_area_sum(const Node* out, int n_max, DeviceSceneInfo* info) {
+    __shared__ double part[4];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0;
+    if (x < n_max && x < out[0].escape && out[x].payload != 0) a = box_area(out[x]);
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&info->leaf_area, part[0] + part[1] + part[2] + part[3]);
+}
+
+// depth complexity and the traversal it selects
+__global__ void choose_walk(const Node* out, DeviceSceneInfo* info) {
+    const double root = box_area(out[0]);
+    const double d = root > 0.0 ? info->leaf_area / root : 0.0;
+    info->depth_complexity = (float)d;
+    info->wide = d >= (double)kWideDepthComplexity ? 1 : 0;
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -520,8 +609,8 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_t nt64, Node* nodes_out,
-                     float4* tris_out, QNode* qnodes_out, QFrame* frame_out, DeviceSceneInfo* info,
-                     const TempAlloc& ta, hipStream_t s, int* oom) {
+                     float4* tris_out, QNode* qnodes_out, QFrame* frame_out, QNode* groups_out,
+                     DeviceSceneInfo* info, const TempAlloc& ta, hipStream_t s, int* oom) {
     *oom = 0;
     const int nt = (int)nt64;
     hipLaunchKernelGGL(init_info, dim3(1), dim3(1), 0, s, info);
@@ -531,6 +620,12 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     if (nt > 1) {
         hipError_t e = rocprim::radix_sort_pairs(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
                                                  (uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)nt, 0, 63, s);
+        if (e != hipSuccess) return e;
+    }
+    size_t scan_bytes = 0;
+    if (nt > 1) {
+        hipError_t e = rocprim::exclusive_scan(nullptr, scan_bytes, (const int32_t*)nullptr, (int32_t*)nullptr, 0,
+                                               n_nodes, rocprim::plus<int32_t>(), s);
         if (e != hipSuccess) return e;
     }
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -544,8 +639,9 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
                  sz_part = al(sizeof(float) * 6 * (size_t)nblk(ntm)), sz_nt = al(sizeof(int32_t) * ntm),
                  sz_base = al(sizeof(int32_t) * (size_t)(nb + 1)), sz_pre = al(sizeof(float4) * 2 * ntm),
                  sz_st = al(sizeof(float4) * 2 * (size_t)nb * (size_t)levels);
-    const size_t total = sz_tmp + 2 * sz_keys + 2 * sz_vals + 7 * sz_i + sz_box + sz_cb + sz_sort + sz_part +
-                         2 * sz_nt + sz_base + 2 * sz_pre + sz_st;
+    const size_t sz_scan = al(scan_bytes);
+    const size_t total = sz_tmp + 2 * sz_keys + 2 * sz_vals + 9 * sz_i + sz_box + sz_cb + sz_sort + sz_part +
+                         2 * sz_nt + sz_base + 2 * sz_pre + sz_st + sz_scan;
     char* base = (char*)ta.alloc(ta.ctx, total, s);
     if (!base) { *oom = 1; return hipErrorOutOfMemory; }
     char* p = base;
@@ -573,6 +669,9 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     T.pre = (float4*)take(sz_pre);
     T.suf = (float4*)take(sz_pre);
     T.st = (float4*)take(sz_st);
+    int32_t* gflag = (int32_t*)take(sz_i);
+    int32_t* gidx = (int32_t*)take(sz_i);
+    void* scan_tmp = take(sz_scan);
     T.nb = nb;
     T.levels = levels;
     hipError_t err = hipSuccess;
@@ -582,7 +681,7 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     }
     if (nt <= 1) {
         hipLaunchKernelGGL(tiny_scene, dim3(1), dim3(1), 0, s, tmp, nt, nodes_out, tris_out, qnodes_out, frame_out,
-                           info);
+                           info, groups_out);
     } else {
         hipLaunchKernelGGL(morton, dim3(nblk(nt)), dim3(256), 0, s, tmp, (int64_t)nt, cb, keys, vals);
         err = rocprim::radix_sort_pairs(sort_tmp, sort_bytes, keys, keys2, vals, vals2, (size_t)nt, 0, 63, s);
@@ -595,9 +694,19 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
             hipLaunchKernelGGL(fit_block, dim3((unsigned)nb), dim3(kFitBlock), 0, s, tmp, vals2, nt, T);
             hipLaunchKernelGGL(block_table, dim3(1), dim3(1024), 0, s, T);
             hipLaunchKernelGGL(fit_top, dim3(nblk(nt - 1)), dim3(256), 0, s, nt, T);
+            hipLaunchKernelGGL(fill_i32, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, gflag, (int64_t)(2 * nt - 1), 0);
             hipLaunchKernelGGL(emit, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nt, T, nodes_out, qnodes_out,
-                               frame_out, info);
+                               frame_out, info, gflag);
             hipLaunchKernelGGL(reorder, dim3(nblk(nt)), dim3(256), 0, s, tmp, vals2, (int64_t)nt, tris_out);
+            err = rocprim::exclusive_scan(scan_tmp, scan_bytes, gflag, gidx, 0, (size_t)(2 * nt - 1),
+                                          rocprim::plus<int32_t>(), s);
+        }
+        if (err == hipSuccess) {
+            hipLaunchKernelGGL(wide_groups, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nodes_out, qnodes_out, gflag,
+                               gidx, 2 * nt - 1, groups_out);
+            hipLaunchKernelGGL(count_groups, dim3(1), dim3(1), 0, s, gflag, gidx, 2 * nt - 1, info);
+            hipLaunchKernelGGL(leaf_area_sum, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nodes_out, 2 * nt - 1, info);
+            hipLaunchKernelGGL(choose_walk, dim3(1), dim3(1), 0, s, nodes_out, info);
         }
     }
     if (err == hipSuccess) err = hipGetLastError();

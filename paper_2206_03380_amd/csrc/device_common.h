@@ -12,6 +12,9 @@ namespace mcdi {
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kInvPi = 0.318309886183790671538f;
 constexpr float kRMin = 0.08f;  // roughness clamp (alpha >= 0.0064)
+// Word 3 of a raw buffer resource on gfx9 (data format 32, no swizzle): the
+// descriptor of __builtin_amdgcn_make_buffer_rsrc for plain byte-offset loads.
+constexpr int kBufferWord3 = 0x00020000;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // decision-record bits (debug dump)
@@ -196,39 +199,50 @@ __device__ __forceinline__ bool box_hit(const Ray& r, float4 a, float4 b) {
 // FMA per plane.  The offsets carry a margin of 2^-20 (65535 |step inv| +
 // |(base - o) inv|) -- sixteen times the roundings of the two products, the
 // difference and the FMA against the magnitudes involved -- on the side that
-// keeps near distances under- and far distances over-estimated.
+// keeps near distances under- and far distances over-estimated; they also
+// cover the reciprocal's 1-ulp error, so the final comparison needs no slack.
+// Which plane of an axis is near follows from the sign of the direction: per
+// axis a byte selector gathers the near plane's 16-bit coordinate (low half)
+// and the far plane's (high half) from the two words holding them, so that
+// the test needs no min/max pairs.
 struct QRay {
-    float3 s, clo, chi;
+    float3 s, cn, cf;
+    uint32_t sx, sy, sz;
 };
 
-__device__ __forceinline__ void qslab(float o, float inv, float base, float step, float& s, float& clo,
-                                      float& chi) {
+__device__ __forceinline__ void qslab(float o, float inv, float base, float step, float& s, float& cn,
+                                      float& cf) {
     s = step * inv;
     const float c = (base - o) * inv;
     const float e = 0x1p-20f * (fabsf(s) * 65535.0f + fabsf(c));
-    clo = inv >= 0.0f ? c - e : c + e;
-    chi = inv >= 0.0f ? c + e : c - e;
+    cn = c - e;
+    cf = c + e;
 }
 
 __device__ __forceinline__ QRay make_qray(const Ray& r, const QFrame& F) {
     QRay q;
-    qslab(r.o.x, r.inv.x, F.base[0], F.step[0], q.s.x, q.clo.x, q.chi.x);
-    qslab(r.o.y, r.inv.y, F.base[1], F.step[1], q.s.y, q.clo.y, q.chi.y);
-    qslab(r.o.z, r.inv.z, F.base[2], F.step[2], q.s.z, q.clo.z, q.chi.z);
+    qslab(r.o.x, r.inv.x, F.base[0], F.step[0], q.s.x, q.cn.x, q.cf.x);
+    qslab(r.o.y, r.inv.y, F.base[1], F.step[1], q.s.y, q.cn.y, q.cf.y);
+    qslab(r.o.z, r.inv.z, F.base[2], F.step[2], q.s.z, q.cn.z, q.cf.z);
+    // x: lo in word 0 of n.x, hi in word 1 of n.y; y: lo in word 1 of n.x,
+    // hi in word 0 of n.z; z: lo in word 0 of n.y, hi in word 1 of n.z
+    // (selector bytes 0-3 take the second operand, 4-7 the first)
+    q.sx = r.inv.x >= 0.0f ? 0x07060100u : 0x01000706u;
+    q.sy = r.inv.y >= 0.0f ? 0x05040302u : 0x03020504u;
+    q.sz = r.inv.z >= 0.0f ? 0x07060100u : 0x01000706u;
     return q;
 }
 
-// The slab test of box_hit on a quantised node (the 16-bit coordinates
-// convert to FP32 exactly).
 __device__ __forceinline__ bool qbox_hit(const QRay& q, uint4 n) {
-    const float lx = (float)(n.x & 0xFFFFu), ly = (float)(n.x >> 16), lz = (float)(n.y & 0xFFFFu);
-    const float hx = (float)(n.y >> 16), hy = (float)(n.z & 0xFFFFu), hz = (float)(n.z >> 16);
-    const float tx0 = fmaf(lx, q.s.x, q.clo.x), tx1 = fmaf(hx, q.s.x, q.chi.x);
-    const float ty0 = fmaf(ly, q.s.y, q.clo.y), ty1 = fmaf(hy, q.s.y, q.chi.y);
-    const float tz0 = fmaf(lz, q.s.z, q.clo.z), tz1 = fmaf(hz, q.s.z, q.chi.z);
-    const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
-    const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
-    return tn <= tf * 1.000001f;
+    const uint32_t ax = __builtin_amdgcn_perm(n.y, n.x, q.sx);
+    const uint32_t ay = __builtin_amdgcn_perm(n.z, n.x, q.sy);
+    const uint32_t az = __builtin_amdgcn_perm(n.z, n.y, q.sz);
+    const float tnx = fmaf((float)(ax & 0xFFFFu), q.s.x, q.cn.x), tfx = fmaf((float)(ax >> 16), q.s.x, q.cf.x);
+    const float tny = fmaf((float)(ay & 0xFFFFu), q.s.y, q.cn.y), tfy = fmaf((float)(ay >> 16), q.s.y, q.cf.y);
+    const float tnz = fmaf((float)(az & 0xFFFFu), q.s.z, q.cn.z), tfz = fmaf((float)(az >> 16), q.s.z, q.cf.z);
+    const float tn = fmaxf(fmaxf(fmaxf(tnx, tny), tnz), 0.0f);
+    const float tf = fminf(fminf(tfx, tfy), tfz);
+    return tn <= tf;
 }
 
 // Stackless any-hit traversal over the quantised nodes (the order and the
@@ -258,6 +272,51 @@ __device__ __forceinline__ bool qbvh_anyhit(const Scene& sc, const Ray& r, int n
         i = next;
     }
     return false;
+}
+
+// Any-hit traversal of the 4-wide hierarchy with a stack of pending
+// references (a one-ray form; the shading kernels keep their stacks in LDS).
+// A stack that would overflow sends the ray to the binary traversal from the
+// root, which gives the same answer.
+template <bool COUNT = false>
+__device__ __forceinline__ bool wbvh_anyhit(const Scene& sc, const Ray& r, int n_total, uint32_t& n_box,
+                                            uint32_t& n_tri) {
+    constexpr int kDepth = 64;
+    const uint4* g = reinterpret_cast<const uint4*>(sc.groups);
+    const uint32_t n_groups = sc.group_bytes / 64u;
+    const QRay q = make_qray(r, *sc.frame);
+    uint32_t stack[kDepth];
+    int sp = 0;
+    uint32_t node = n_total > 0 ? 0u : kWideNone;
+    while (true) {
+        if (node == kWideNone) {
+            if (sp == 0) return false;
+            node = stack[--sp];
+        }
+        if (node & kQLeaf) {
+            const uint32_t payload = node & ~kQLeaf;
+            const int first = (int)(payload >> 3);
+            const int cnt = (first + (int)(payload & 7u) <= sc.n_tris) ? (int)(payload & 7u) : 0;
+            for (int k = 0; k < cnt; ++k) {
+                const float4* t = sc.tris + 3 * (first + k);
+                if (COUNT) ++n_tri;
+                if (tri_anyhit(r, t[0], t[1], t[2])) return true;
+            }
+            node = kWideNone;
+            continue;
+        }
+        if (node >= n_groups) { node = kWideNone; continue; }   // never for a valid hierarchy
+        uint32_t next = kWideNone;
+        for (int k = 0; k < 4; ++k) {
+            const uint4 c = g[4 * (size_t)node + k];
+            if (COUNT && c.w != kQLeaf) ++n_box;
+            if (!qbox_hit(q, c)) continue;
+            if (next == kWideNone) next = c.w;
+            else if (sp < kDepth) stack[sp++] = c.w;
+            else return qbvh_anyhit<COUNT>(sc, r, n_total, n_box, n_tri);
+        }
+        node = next;
+    }
 }
 
 // Stackless any-hit traversal over the pre-order BVH with skip links.

@@ -27,7 +27,10 @@ struct DeviceSceneInfo {
     int32_t n_nodes;
     int32_t max_depth;
     int32_t bad_tris;
-    int32_t pad;
+    int32_t n_groups;          // wide nodes
+    int32_t wide;              // 1: shadow rays walk the wide hierarchy
+    float depth_complexity;    // sum of leaf box areas / root box area
+    double leaf_area;          // the sum (accumulated by the builder)
 };
 
 // The scene's quantisation frame: node box coordinates as 16-bit integers q,
@@ -48,13 +51,32 @@ struct QNode {
 };
 constexpr uint32_t kQLeaf = 0x80000000u;
 
+// Wide node of the shadow-ray traversal: four child records in QNode form
+// (64 bytes, one aligned segment), w = the child's wide-node index (internal)
+// or kQLeaf | payload (leaf); unused slots have an empty box.  Node 0 is the
+// root.
+constexpr uint32_t kWideNone = 0xFFFFFFFFu;   // no node (a traversal state)
+
 struct Scene {
     const Node* nodes;    // [>= 1]
     const float4* tris;   // [3 * n_tris] vertex positions, w unused
     int64_t n_tris;
     const QNode* qnodes;  // [>= 1] the same nodes, quantised
     const QFrame* frame;
+    const QNode* groups;  // [4 * capacity] wide nodes
+    uint32_t group_bytes; // 64 * capacity (the bound of a buffer resource)
+    const DeviceSceneInfo* info;   // info->wide selects the traversal (read by the kernels)
 };
+
+// Traversal choice, made by the builder on the device.  The depth
+// complexity -- the surface areas of the leaf boxes summed, over the root
+// box's -- estimates how many leaves a ray through the scene crosses.  Surface
+// scenes (about 1.5 for the displaced spheres) are walked on the binary
+// hierarchy, whose cache-resident walk is bound by instruction issue;
+// volume-filling ones (16 for the beam lattice in its room, 95 for the beams
+// alone), whose rays cross many boxes and whose walk is bound by memory round
+// trips, on the 4-wide hierarchy (about a quarter of the round trips).
+constexpr float kWideDepthComplexity = 4.0f;
 
 struct EnvView {
     int32_t H, W;
@@ -227,8 +249,9 @@ struct TempAlloc {
     void (*free)(void* ctx, void* p, hipStream_t s);
     void* ctx;
 };
+// groups_out: capacity for max(1, n_tris) wide nodes (>= internal nodes + 1)
 hipError_t build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
-                     Node* nodes_out, float4* tris_out, QNode* qnodes_out, QFrame* frame_out,
+                     Node* nodes_out, float4* tris_out, QNode* qnodes_out, QFrame* frame_out, QNode* groups_out,
                      DeviceSceneInfo* info, const TempAlloc& ta, hipStream_t s, int* oom);
 
 }  // namespace mcdi

@@ -374,17 +374,19 @@ __device__ __forceinline__ void gen_tile(const ShadeArgs& A, int64_t tile, float
 //    one triangle of a leaf advances its word by 7: the first index grows by
 //    one and the count drops by one.  The second slot is only used while the
 //    first is pending.
+// Binary walk: pre-order with skip links, one 16-byte node per step, no stack.
 template <bool COUNT>
-__device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, const float4* R, int count,
-                                           uint32_t* hitbits, int* s_next) {
+__device__ __forceinline__ void trace_tile_binary(const ShadeArgs& A, int64_t tile, const float4* R, int count,
+                                                  uint32_t* hitbits, int* s_next) {
     const Scene& sc = A.scene;
     const int64_t N = A.g.n;
     const int64_t base_pix = tile * kBlock;
     const int n_total = sc.nodes[0].escape;
     const uint32_t n_tris = (uint32_t)sc.n_tris;
-    const uint4* qnodes = reinterpret_cast<const uint4*>(sc.qnodes);
     const QFrame F = *sc.frame;
     const char* tri_bytes = reinterpret_cast<const char*>(sc.tris);
+    const __amdgpu_buffer_rsrc_t qrs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)sc.qnodes, (short)0, (int)((uint32_t)n_total * 16u), kBufferWord3);
     const int lane = __lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool active = false, exhausted = false;
@@ -392,9 +394,9 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
     QRay qray;
     int node = n_total;
     uint32_t p0 = 0u, p1 = 0u;
-    int64_t pix = 0;
-    int slot = 0;
+    uint32_t tag = 0u;     // the ray's pixel within the tile | sample slot << 8
     uint32_t c_hits = 0, c_box = 0, c_tri = 0, c_bstep = 0, c_tstep = 0;   // steps: lane 0 only
+    uint32_t c_blane = 0;
     // scheduling knobs: refill batch, node steps per phase check, and the
     // phase hand-over ratios (in halves)
     constexpr int kRefillMin = 32, kBoxSteps = 2, kBoxSwitch2 = 2, kTriSwitch2 = 2;
@@ -411,10 +413,8 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
                 const int idx = b + (int)__popcll(need & lt);
                 if (idx < count) {
                     const float4 rr = R[idx];
-                    const uint32_t tag = __float_as_uint(rr.w);
-                    pix = base_pix + (tag & 255u);
-                    slot = (int)(tag >> 8);
-                    const float4 o = A.origins[pix];
+                    tag = __float_as_uint(rr.w);
+                    const float4 o = A.origins[base_pix + (tag & 255u)];
                     ray = make_ray(f3(o.x, o.y, o.z), f3(rr.x, rr.y, rr.z));
                     qray = make_qray(ray, F);
                     node = 0;
@@ -439,9 +439,11 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
             for (int step = 0; step < kBoxSteps; ++step) {
                 const bool walking = node < n_total && p1 == 0u;
                 if (COUNT && __any(walking) && lane == 0) ++c_bstep;
+                if (COUNT && walking) ++c_blane;
                 if (walking) {
                     // one 16-byte load per node: the quantised box and the link
-                    const uint4 n = qnodes[node];
+                    const uint4 n = __builtin_bit_cast(
+                        uint4, __builtin_amdgcn_raw_buffer_load_b128(qrs, (uint32_t)node * 16u, 0, 0));
                     const bool leaf = (n.w & kQLeaf) != 0u;
                     if (COUNT) ++c_box;
                     const bool hit = qbox_hit(qray, n);
@@ -475,7 +477,8 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
                     h = tri_anyhit(ray, tv[0], tv[1], tv[2]);
                 }
                 if (h) {
-                    atomicOr(hitbits + (int64_t)(slot >> 5) * N + pix, 1u << (slot & 31));
+                    const uint32_t slot = tag >> 8;
+                    atomicOr(hitbits + (int64_t)(slot >> 5) * N + base_pix + (tag & 255u), 1u << (slot & 31));
                     ++c_hits;
                     active = false;
                     node = n_total;
@@ -495,8 +498,9 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
         if (active && p0 == 0u && node >= n_total) active = false;  // miss
     }
     if (COUNT) {
-        const uint32_t h = wave_sum(c_hits), bx = wave_sum(c_box), tr = wave_sum(c_tri);
+        const uint32_t h = wave_sum(c_hits), bx = wave_sum(c_box), tr = wave_sum(c_tri), bl = wave_sum(c_blane);
         if (lane == 0) {
+            atomicAdd(&A.stats->box_lanes, (unsigned long long)bl);
             atomicAdd(&A.stats->rays_hit, (unsigned long long)h);
             atomicAdd(&A.stats->box_tests, (unsigned long long)bx);
             atomicAdd(&A.stats->tri_tests, (unsigned long long)tr);
@@ -504,6 +508,222 @@ __device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, con
             atomicAdd(&A.stats->tri_slots, 64ull * c_tstep);
         }
     }
+}
+
+// Pending references of the wide traversal, per lane, in LDS: entry k of
+// the workgroup's lane t at [k * kBlock + t] (lanes of a wave hit distinct
+// banks whatever their stack depths); row kStack is a spare row.
+constexpr int kStack = 16;
+
+template <bool COUNT>
+__device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile, const float4* R, int count,
+                                                uint32_t* hitbits, int* s_next, uint32_t* s_stack) {
+    const Scene& sc = A.scene;
+    const int64_t N = A.g.n;
+    const int64_t base_pix = tile * kBlock;
+    const int n_total = sc.nodes[0].escape;
+    const uint32_t n_tris = (uint32_t)sc.n_tris;
+    const QFrame F = *sc.frame;
+    const char* tri_bytes = reinterpret_cast<const char*>(sc.tris);
+    // nodes as buffer resources: 32-bit offsets, and a load past the end
+    // returns zeros instead of reading out of bounds
+    const __amdgpu_buffer_rsrc_t qrs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)sc.qnodes, (short)0, (int)((uint32_t)n_total * 16u), kBufferWord3);
+    const __amdgpu_buffer_rsrc_t grs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)sc.groups, (short)0, (int)sc.group_bytes, kBufferWord3);
+    uint32_t* stk = s_stack + threadIdx.x;
+    const int lane = __lane_id();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool active = false, exhausted = false;
+    Ray ray;
+    QRay qray;
+    // wide: node = a wide node, a leaf reference waiting for a pending slot,
+    // or kWideNone (done); binary (after a stack overflow): a node index, done
+    // at n_total
+    bool wide = false;
+    uint32_t node = (uint32_t)n_total;
+    int sp = 0;
+    // visits of one ray's wide walk are bounded by the hierarchy's size (every
+    // wide node is entered at most once); past that bound the walk would be
+    // cycling through corrupt references, and the lane takes the binary walk
+    uint32_t visits = 0u;
+    const uint32_t visit_cap = sc.group_bytes / 64u + 64u;
+    uint32_t p0 = 0u, p1 = 0u;
+    uint32_t tag = 0u;     // the ray's pixel within the tile | sample slot << 8
+    uint32_t c_hits = 0, c_box = 0, c_tri = 0, c_bstep = 0, c_tstep = 0;   // steps: lane 0 only
+    uint32_t c_blane = 0;
+    // scheduling knobs: refill batch, node steps per phase check, and the
+    // phase hand-over ratios (in halves)
+    constexpr int kRefillMin = 32, kBoxSteps = 2, kBoxSwitch2 = 2, kTriSwitch2 = 2;
+    auto walkable = [&]() { return (wide ? node != kWideNone : node < (uint32_t)n_total) && p1 == 0u; };
+    while (true) {
+        // refill when half of the wave is idle, or when nobody is busy
+        const uint64_t need = __ballot(!active && !exhausted);
+        const uint64_t busy = __ballot(active);
+        if (need && (__popcll(need) >= kRefillMin || busy == 0ull)) {
+            const int leader = __ffsll((unsigned long long)need) - 1;
+            int b = 0;
+            if (lane == leader) b = atomicAdd(s_next, (int)__popcll(need));
+            b = __shfl(b, leader);
+            if (!active && !exhausted) {
+                const int idx = b + (int)__popcll(need & lt);
+                if (idx < count) {
+                    const float4 rr = R[idx];
+                    tag = __float_as_uint(rr.w);
+                    const float4 o = A.origins[base_pix + (tag & 255u)];
+                    ray = make_ray(f3(o.x, o.y, o.z), f3(rr.x, rr.y, rr.z));
+                    qray = make_qray(ray, F);
+                    wide = true;
+                    node = 0u;
+                    sp = 0;
+                    visits = 0u;
+                    p0 = p1 = 0u;
+                    active = n_total > 0;
+                } else {
+                    exhausted = true;
+                }
+            }
+        }
+        if (!__any(active)) {
+            if (!__any(!exhausted)) break;
+            continue;
+        }
+        // box phase: a lane walks while its second leaf slot is free and the
+        // walk is not finished (a leaf found with the first slot taken goes
+        // to the second); the phase ends once the lanes that hold a leaf and
+        // cannot walk are at least as many as the lanes still walking
+        while (true) {
+            if (!__any(active && walkable())) break;
+#pragma unroll
+            for (int step = 0; step < kBoxSteps; ++step) {
+                const bool walking = active && walkable();
+                if (COUNT && __any(walking) && lane == 0) ++c_bstep;
+                if (COUNT && walking) ++c_blane;
+                if (walking && wide) {
+                    if (node & kQLeaf) {
+                        // a leaf reference: to the free pending slot
+                        const uint32_t payload = node & ~kQLeaf;
+                        if (p0 == 0u) p0 = payload;
+                        else p1 = payload;
+                        node = sp > 0 ? stk[--sp * kBlock] : kWideNone;
+                    } else {
+                        // one wide node: four child records from one 64-byte segment
+                        const uint32_t off = node * 64u;
+                        uint4 c[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            c[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(grs, off + 16u * k, 0, 0));
+                        // branch-free: a hit leaf goes to a free pending slot,
+                        // every other hit is pushed (the store goes to the
+                        // spare row kStack when there is nothing to push or no
+                        // room), then the top is popped as the next node
+                        bool over = false;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (COUNT && c[k].w != kQLeaf) ++c_box;
+                            const bool h = qbox_hit(qray, c[k]);
+                            const uint32_t w = c[k].w;
+                            const bool leaf = (w & kQLeaf) != 0u;
+                            const bool a0 = h && leaf && p0 == 0u;
+                            const bool a1 = h && leaf && !a0 && p1 == 0u;
+                            p0 = a0 ? (w & ~kQLeaf) : p0;
+                            p1 = a1 ? (w & ~kQLeaf) : p1;
+                            const bool psh = h && !a0 && !a1;
+                            const bool room = sp < kStack;
+                            stk[((psh && room) ? sp : kStack) * kBlock] = w;
+                            over = over || (psh && !room);
+                            sp += (psh && room) ? 1 : 0;
+                        }
+                        const uint32_t top = stk[(sp > 0 ? sp - 1 : 0) * kBlock];
+                        const uint32_t next = sp > 0 ? top : kWideNone;
+                        sp = sp > 0 ? sp - 1 : 0;
+                        node = next;
+                        if (over || ++visits > visit_cap) {
+                            // the stack is full (or the walk is too long): walk
+                            // the binary tree from the root instead (the same
+                            // answer, more steps)
+                            wide = false;
+                            node = 0u;
+                            sp = 0;
+                        }
+                    }
+                } else if (walking) {
+                    // binary pre-order walk with skip links: one 16-byte node
+                    const uint4 n = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(qrs, node * 16u, 0, 0));
+                    const bool leaf = (n.w & kQLeaf) != 0u;
+                    if (COUNT) ++c_box;
+                    const bool hit = qbox_hit(qray, n);
+                    // skip links point forward; max() keeps every walk finite
+                    const uint32_t next = leaf ? node + 1u : max(n.w, node + 1u);
+                    node = (hit && !leaf) ? node + 1u : next;
+                    const uint32_t payload = n.w & ~kQLeaf;
+                    const bool take = hit && leaf;
+                    const bool first_free = p0 == 0u;
+                    p0 = (take && first_free) ? payload : p0;
+                    p1 = (take && !first_free) ? payload : p1;
+                }
+            }
+            const bool walk = active && walkable();
+            const bool stuck = p0 != 0u && !walk;
+            if (2 * __popcll(__ballot(stuck)) >= kBoxSwitch2 * __popcll(__ballot(walk))) break;
+        }
+        // triangle phase: one triangle of the first pending leaf per lane and
+        // step; it ends when no leaf is pending, or when lanes that could walk
+        // but hold no leaf outnumber the lanes testing
+        while (true) {
+            const bool test = p0 != 0u;
+            if (!__any(test)) break;
+            if (COUNT && lane == 0) ++c_tstep;
+            if (test) {
+                const uint32_t t = p0 >> 3;
+                bool h = false;
+                if (t < n_tris) {       // a payload past the triangle array tests nothing
+                    const float4* tv = reinterpret_cast<const float4*>(tri_bytes + t * 48u);
+                    if (COUNT) ++c_tri;
+                    h = tri_anyhit(ray, tv[0], tv[1], tv[2]);
+                }
+                if (h) {
+                    const uint32_t slot = tag >> 8;
+                    atomicOr(hitbits + (int64_t)(slot >> 5) * N + base_pix + (tag & 255u), 1u << (slot & 31));
+                    ++c_hits;
+                    active = false;
+                    wide = false;
+                    node = (uint32_t)n_total;
+                    sp = 0;
+                    p0 = p1 = 0u;
+                } else {
+                    p0 += 7u;
+                    if ((p0 & 7u) == 0u) {
+                        p0 = p1;
+                        p1 = 0u;
+                    }
+                }
+            }
+            const bool testing = p0 != 0u;
+            const bool idle = !testing && active && walkable();
+            if (2 * __popcll(__ballot(idle)) > kTriSwitch2 * __popcll(__ballot(testing))) break;
+        }
+        if (active && p0 == 0u && !(wide ? node != kWideNone : node < (uint32_t)n_total)) active = false;  // miss
+    }
+    if (COUNT) {
+        const uint32_t h = wave_sum(c_hits), bx = wave_sum(c_box), tr = wave_sum(c_tri), bl = wave_sum(c_blane);
+        if (lane == 0) {
+            atomicAdd(&A.stats->box_lanes, (unsigned long long)bl);
+            atomicAdd(&A.stats->rays_hit, (unsigned long long)h);
+            atomicAdd(&A.stats->box_tests, (unsigned long long)bx);
+            atomicAdd(&A.stats->tri_tests, (unsigned long long)tr);
+            atomicAdd(&A.stats->box_slots, 64ull * c_bstep);
+            atomicAdd(&A.stats->tri_slots, 64ull * c_tstep);
+        }
+    }
+}
+
+// The walk the scene's builder chose (a uniform branch: one scalar load).
+template <bool COUNT>
+__device__ __forceinline__ void trace_tile(const ShadeArgs& A, int64_t tile, const float4* R, int count,
+                                           uint32_t* hitbits, int* s_next, uint32_t* s_stack) {
+    if (A.scene.info->wide) trace_tile_wide<COUNT>(A, tile, R, count, hitbits, s_next, s_stack);
+    else trace_tile_binary<COUNT>(A, tile, R, count, hitbits, s_next);
 }
 
 // 3) evaluation: forward values or the adjoint, from the hit bits.  For the
@@ -703,14 +923,17 @@ __global__ __launch_bounds__(1024) void order_tiles_kernel(const int32_t* __rest
     }
 }
 
+// eight waves per SIMD (the hardware's limit): 64 registers per lane
 template <bool COUNT>
-__global__ __launch_bounds__(kBlock) void trace_rays_kernel(ShadeArgs A, uint32_t* hitbits) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void trace_rays_kernel(ShadeArgs A,
+                                                                                                   uint32_t* hitbits) {
     __shared__ int s_next;
+    __shared__ uint32_t s_stack[(kStack + 1) * kBlock];
     const int64_t tile = A.tile_order ? A.tile_order[blockIdx.x] : blockIdx.x;
     if (tile < 0 || tile >= (int64_t)gridDim.x) return;   // uniform: the whole workgroup reads the same entry
     if (threadIdx.x == 0) s_next = 0;
     __syncthreads();
-    trace_tile<COUNT>(A, tile, tile_region(A, tile), A.ray_count[tile], hitbits, &s_next);
+    trace_tile<COUNT>(A, tile, tile_region(A, tile), A.ray_count[tile], hitbits, &s_next, s_stack);
 }
 
 template <bool BWD, bool DUMP, bool BIL>
@@ -763,6 +986,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(const ServeItem* items, i
                                                        int* tile_counter, float4* scratch, int spp_max) {
     extern __shared__ float smem[];
     __shared__ int s_tile, s_item, s_cnt, s_next;
+    __shared__ uint32_t s_stack[(kStack + 1) * kBlock];
     float* s_hot = smem;                     // 3 * kHotMax
     float* s_marg = smem + 3 * kHotMax;      // H + 1 of the current item
     float4* region = scratch + (size_t)blockIdx.x * (size_t)(2 * spp_max * kBlock);
@@ -790,7 +1014,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(const ServeItem* items, i
         float4* reg = A.tau != 0.0f ? region : nullptr;
         gen_tile<false>(A, tile, reg, it.hitbits, s_marg, &s_cnt);
         __syncthreads();
-        if (reg) trace_tile<false>(A, tile, reg, s_cnt, it.hitbits, &s_next);
+        if (reg) trace_tile<false>(A, tile, reg, s_cnt, it.hitbits, &s_next, s_stack);
         __syncthreads();
         const bool bil = (A.flags & MCDI_FLAG_BILINEAR) != 0;
         if (bil) shade_tile<false, false, true>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
@@ -815,7 +1039,11 @@ __global__ void trace_kernel(Scene sc, const float* o, const float* d, int64_t n
     const Ray r = make_ray(f3(o[k], o[n + k], o[2 * n + k]), f3(d[k], d[n + k], d[2 * n + k]));
     const int n_total = sc.nodes[0].escape;
     uint32_t nb = 0, nt = 0;
-    hit[k] = (brute ? brute_anyhit(sc, r) : qbvh_anyhit(sc, r, n_total, nb, nt)) ? 1 : 0;
+    bool h;
+    if (brute == 1) h = brute_anyhit(sc, r);
+    else if (brute == 2) h = wbvh_anyhit(sc, r, n_total, nb, nt);
+    else h = qbvh_anyhit(sc, r, n_total, nb, nt);
+    hit[k] = h ? 1 : 0;
 }
 
 }  // namespace

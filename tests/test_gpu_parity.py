@@ -130,8 +130,10 @@ def test_trace_bvh_equals_brute_force(freq):
     dt = torch.from_numpy(np.ascontiguousarray(d.T)).cuda()
     a = to_np(M.trace_anyhit(sc, ot, dt, brute=False))
     b = to_np(M.trace_anyhit(sc, ot, dt, brute=True))
-    assert np.array_equal(a, b)
+    c = to_np(M.trace_anyhit(sc, ot, dt, mode="wide"))
+    assert np.array_equal(a, b) and np.array_equal(c, b)
     assert 0.05 < a.mean() < 0.95
+    assert 1 <= info["n_groups"] < info["n_nodes"]
     # against the FP64 oracle on the same FP32 rays: equal unless undecided
     osc = oracle.Scene(w.verts, w.tris)
     ref = osc.anyhit(o.astype(np.float64), d.astype(np.float64), 1e-5, 1e-5)
@@ -235,12 +237,19 @@ def test_trace_edge_scenes():
     dt = torch.from_numpy(np.ascontiguousarray(d.T)).cuda()
     empty = M.Scene(torch.zeros((3, 3), device="cuda"), torch.zeros((0, 3), dtype=torch.int32, device="cuda"))
     assert to_np(M.trace_anyhit(empty, ot, dt)).sum() == 0
+    assert to_np(M.trace_anyhit(empty, ot, dt, mode="wide")).sum() == 0
     assert empty.info()["n_nodes"] == 0
     tri_v = np.array([[-10, -10, 0], [10, -10, 0], [0, 10, 0]], np.float32)
     one = M.Scene(torch.from_numpy(tri_v).cuda(), torch.tensor([[0, 1, 2]], dtype=torch.int32, device="cuda"))
     a = to_np(M.trace_anyhit(one, ot, dt))
     b = to_np(M.trace_anyhit(one, ot, dt, brute=True))
-    assert np.array_equal(a, b) and a.sum() > 0
+    c = to_np(M.trace_anyhit(one, ot, dt, mode="wide"))
+    assert np.array_equal(a, b) and np.array_equal(c, b) and a.sum() > 0
+    # a root that is a leaf (2..4 triangles)
+    few = M.Scene(torch.from_numpy(np.concatenate([tri_v, tri_v + 3])).cuda(),
+                  torch.tensor([[0, 1, 2], [3, 4, 5]], dtype=torch.int32, device="cuda"))
+    assert np.array_equal(to_np(M.trace_anyhit(few, ot, dt, mode="wide")),
+                          to_np(M.trace_anyhit(few, ot, dt, brute=True)))
     # bad indices and non-finite vertices become degenerate triangles
     v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [np.nan, 0, 0]], np.float32)
     f = np.array([[0, 1, 2], [0, 1, 7], [0, 3, 2], [-1, 0, 1]], np.int32)
