@@ -512,8 +512,10 @@ __device__ __forceinline__ void trace_tile_binary(const ShadeArgs& A, int64_t ti
 
 // Pending references of the wide traversal, per lane, in LDS: entry k of
 // the workgroup's lane t at [k * kBlock + t] (lanes of a wave hit distinct
-// banks whatever their stack depths); row kStack is a spare row.
-constexpr int kStack = 16;
+// banks whatever their stack depths).  kStack entries, and four spare rows
+// for the stores of a visit that begins with a full stack (18 KB per
+// workgroup: eight workgroups per CU still fit).
+constexpr int kStack = 14, kStackRows = kStack + 4;
 
 template <bool COUNT>
 __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile, const float4* R, int count,
@@ -613,27 +615,23 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
 #pragma unroll
                         for (int k = 0; k < 4; ++k)
                             c[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(grs, off + 16u * k, 0, 0));
-                        // branch-free: a hit leaf goes to a free pending slot,
-                        // every other hit is pushed (the store goes to the
-                        // spare row kStack when there is nothing to push or no
-                        // room), then the top is popped as the next node
-                        bool over = false;
+                        // every hit child is pushed: each record is stored at
+                        // the first free row and the row is kept if the child
+                        // was hit (rows up to kStack + 3 exist, so a visit
+                        // starting with a full stack stays in bounds; the
+                        // overflow is checked once per visit); then the top is
+                        // popped as the next node (a leaf reference moves to a
+                        // pending slot at the next step)
+                        uint32_t* at = stk + sp * kBlock;
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             if (COUNT && c[k].w != kQLeaf) ++c_box;
                             const bool h = qbox_hit(qray, c[k]);
-                            const uint32_t w = c[k].w;
-                            const bool leaf = (w & kQLeaf) != 0u;
-                            const bool a0 = h && leaf && p0 == 0u;
-                            const bool a1 = h && leaf && !a0 && p1 == 0u;
-                            p0 = a0 ? (w & ~kQLeaf) : p0;
-                            p1 = a1 ? (w & ~kQLeaf) : p1;
-                            const bool psh = h && !a0 && !a1;
-                            const bool room = sp < kStack;
-                            stk[((psh && room) ? sp : kStack) * kBlock] = w;
-                            over = over || (psh && !room);
-                            sp += (psh && room) ? 1 : 0;
+                            *at = c[k].w;
+                            at += h ? kBlock : 0;
                         }
+                        sp = (int)((at - stk) / kBlock);
+                        const bool over = sp > kStack;
                         const uint32_t top = stk[(sp > 0 ? sp - 1 : 0) * kBlock];
                         const uint32_t next = sp > 0 ? top : kWideNone;
                         sp = sp > 0 ? sp - 1 : 0;
@@ -928,7 +926,7 @@ template <bool COUNT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void trace_rays_kernel(ShadeArgs A,
                                                                                                    uint32_t* hitbits) {
     __shared__ int s_next;
-    __shared__ uint32_t s_stack[(kStack + 1) * kBlock];
+    __shared__ uint32_t s_stack[kStackRows * kBlock];
     const int64_t tile = A.tile_order ? A.tile_order[blockIdx.x] : blockIdx.x;
     if (tile < 0 || tile >= (int64_t)gridDim.x) return;   // uniform: the whole workgroup reads the same entry
     if (threadIdx.x == 0) s_next = 0;
@@ -986,7 +984,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(const ServeItem* items, i
                                                        int* tile_counter, float4* scratch, int spp_max) {
     extern __shared__ float smem[];
     __shared__ int s_tile, s_item, s_cnt, s_next;
-    __shared__ uint32_t s_stack[(kStack + 1) * kBlock];
+    __shared__ uint32_t s_stack[kStackRows * kBlock];
     float* s_hot = smem;                     // 3 * kHotMax
     float* s_marg = smem + 3 * kHotMax;      // H + 1 of the current item
     float4* region = scratch + (size_t)blockIdx.x * (size_t)(2 * spp_max * kBlock);
