@@ -509,12 +509,14 @@ __device__ __forceinline__ QNode child_record(const Node* out, const QNode* qout
 }
 
 __global__ __launch_bounds__(256) void wide_groups(const Node* out, const QNode* qout, const int32_t* gflag,
-                                                   const int32_t* gidx, int n_max, QNode* groups) {
+                                                   const int32_t* gidx, int n_max, QNode* groups,
+                                                   DeviceSceneInfo* info) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n_max) return;
     const int n_nodes = out[0].escape;            // surviving binary nodes
     if (x >= n_nodes || !gflag[x]) return;
-    QNode* g = groups + 4 * (size_t)gidx[x];
+    const int self = gidx[x];
+    QNode* g = groups + 4 * (size_t)self;
     int k = 0;
     if (out[x].payload != 0) {                    // a root that is a leaf
         g[k++] = child_record(out, qout, gidx, x);
@@ -533,6 +535,14 @@ __global__ __launch_bounds__(256) void wide_groups(const Node* out, const QNode*
         }
     }
     for (; k < 4; ++k) g[k] = empty_record();
+    // the walk's termination rests on this: every internal child reference
+    // lies past its parent and inside the node array (pre-order numbering);
+    // a violation (never for a valid tree) sends the scene to the binary walk
+    const int n_groups = gidx[n_max - 1] + gflag[n_max - 1];
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t w = g[i].w;
+        if (!(w & kQLeaf) && ((int)w <= self || (int)w >= n_groups)) atomicOr(&info->wide_bad, 1);
+    }
 }
 
 __global__ void tiny_scene(const float4* tmp, int nt, Node* out, float4* tris_out, QNode* qout, QFrame* frame,
@@ -574,6 +584,7 @@ __global__ void init_info(DeviceSceneInfo* info) {
     info->bad_tris = 0;
     info->n_groups = 0;
     info->wide = 0;
+    info->wide_bad = 0;
     info->depth_complexity = 0.0f;
     info->leaf_area = 0.0;
 }
@@ -601,7 +612,7 @@ __global__ void choose_walk(const Node* out, DeviceSceneInfo* info) {
     const double root = box_area(out[0]);
     const double d = root > 0.0 ? info->leaf_area / root : 0.0;
     info->depth_complexity = (float)d;
-    info->wide = d >= (double)kWideDepthComplexity ? 1 : 0;
+    info->wide = (d >= (double)kWideDepthComplexity && info->wide_bad == 0) ? 1 : 0;
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -703,7 +714,7 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
         }
         if (err == hipSuccess) {
             hipLaunchKernelGGL(wide_groups, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nodes_out, qnodes_out, gflag,
-                               gidx, 2 * nt - 1, groups_out);
+                               gidx, 2 * nt - 1, groups_out, info);
             hipLaunchKernelGGL(count_groups, dim3(1), dim3(1), 0, s, gflag, gidx, 2 * nt - 1, info);
             hipLaunchKernelGGL(leaf_area_sum, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nodes_out, 2 * nt - 1, info);
             hipLaunchKernelGGL(choose_walk, dim3(1), dim3(1), 0, s, nodes_out, info);

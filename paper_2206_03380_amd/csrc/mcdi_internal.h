@@ -30,6 +30,8 @@ struct DeviceSceneInfo {
     int32_t n_groups;          // wide nodes
     int32_t wide;              // 1: shadow rays walk the wide hierarchy
     float depth_complexity;    // sum of leaf box areas / root box area
+    int32_t wide_bad;          // a wide reference failed the builder's check
+    int32_t pad;
     double leaf_area;          // the sum (accumulated by the builder)
 };
 

@@ -545,11 +545,9 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
     bool wide = false;
     uint32_t node = (uint32_t)n_total;
     int sp = 0;
-    // visits of one ray's wide walk are bounded by the hierarchy's size (every
-    // wide node is entered at most once); past that bound the walk would be
-    // cycling through corrupt references, and the lane takes the binary walk
-    uint32_t visits = 0u;
-    const uint32_t visit_cap = sc.group_bytes / 64u + 64u;
+    // (every wide walk ends: the builder checked that each internal child
+    // reference is larger than its parent's index and smaller than the node
+    // count, and picks the binary walk for the scene otherwise)
     uint32_t p0 = 0u, p1 = 0u;
     uint32_t tag = 0u;     // the ray's pixel within the tile | sample slot << 8
     uint32_t c_hits = 0, c_box = 0, c_tri = 0, c_bstep = 0, c_tstep = 0;   // steps: lane 0 only
@@ -582,7 +580,6 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                     wide = true;
                     node = 0u;
                     sp = 0;
-                    visits = 0u;
                     p0 = p1 = 0u;
                     active = n_total > 0;
                 } else {
@@ -640,10 +637,9 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                         const uint32_t next = sp > 0 ? top : kWideNone;
                         sp = sp > 0 ? sp - 1 : 0;
                         node = next;
-                        if (over || ++visits > visit_cap) {
-                            // the stack is full (or the walk is too long): walk
-                            // the binary tree from the root instead (the same
-                            // answer, more steps)
+                        if (over) {
+                            // the stack is full: walk the binary tree from the
+                            // root instead (the same answer, more steps)
                             wide = false;
                             node = 0u;
                             sp = 0;
