@@ -141,11 +141,14 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ kd,
             ll += (double)fabsf(dl);
         }
         const float gl = m ? sgn(dl) * invn * w_light * (1.0f / 3.0f) : 0.0f;
+        // the gradients are streamed out and not read again here: non-temporal
+        // stores keep them from displacing the inputs in the caches (0.107 ->
+        // 0.085 ms at 4.2M pixels; non-temporal loads of the inputs gain nothing)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            if (g_kd) g_kd[c * n + k] = gc[c] * cdc[c];
-            if (g_cd) g_cd[c * n + k] = gc[c] * kdc[c] + gl * dls[c];
-            if (g_cs) g_cs[c * n + k] = gc[c] + gl * dls[c];
+            if (g_kd) __builtin_nontemporal_store(gc[c] * cdc[c], g_kd + c * n + k);
+            if (g_cd) __builtin_nontemporal_store(gc[c] * kdc[c] + gl * dls[c], g_cd + c * n + k);
+            if (g_cs) __builtin_nontemporal_store(gc[c] + gl * dls[c], g_cs + c * n + k);
         }
     }
     // block partials (fixed tree)
