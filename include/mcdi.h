@@ -56,8 +56,9 @@ typedef struct mcdi_scene_s* mcdi_scene; /* opaque BVH over a triangle mesh */
 typedef struct mcdi_env_s* mcdi_env;     /* opaque probe sampling tables */
 
 /* Optional device allocator (e.g. a framework's caching allocator).
- * alloc returns device memory usable in stream order on `stream`, or NULL;
- * free releases it in stream order. */
+ * alloc returns device memory usable in stream order on `stream`, aligned to
+ * 256 bytes, or NULL; free releases it in stream order.  A misaligned block
+ * is handed back to free and the call fails with MCDI_E_OOM. */
 typedef struct {
     void* ctx;
     void* (*alloc)(void* ctx, size_t bytes, void* stream);

@@ -102,7 +102,15 @@ struct Alloc {
     bool has_user = false;
     void* get(size_t bytes, hipStream_t s) const {
         if (bytes == 0) bytes = 256;
-        if (has_user) return user.alloc(user.ctx, bytes, (void*)s);
+        if (has_user) {
+            // the kernels read tables with 16-byte loads
+            void* p = user.alloc(user.ctx, bytes, (void*)s);
+            if (p && ((uintptr_t)p & 255u)) {
+                user.free(user.ctx, p, (void*)s);
+                return nullptr;
+            }
+            return p;
+        }
         void* p = nullptr;
         if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
             (void)hipGetLastError();
@@ -312,7 +320,8 @@ mcdi_status mcdi_build_env_cdf(const float* env_rgb, int32_t H, int32_t W, const
     ev->H = H;
     ev->W = W;
     ev->rgb = env_rgb;
-    ev->cond = (float*)ev->alloc.get(sizeof(float) * (size_t)H * (W + 1), s);
+    // 16 floats past the last row: the row search reads aligned windows
+    ev->cond = (float*)ev->alloc.get(sizeof(float) * ((size_t)H * (W + 1) + 16), s);
     ev->marg = (float*)ev->alloc.get(sizeof(float) * (size_t)(H + 1), s);
     ev->pdf = (float*)ev->alloc.get(sizeof(float) * (size_t)H * W, s);
     ev->rowsum = (double*)ev->alloc.get(sizeof(double) * (size_t)(H + 1), s);
@@ -388,7 +397,7 @@ static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, cons
     std::memset(&a, 0, sizeof(a));
     a.scene = scene_view(sc);
     a.env = EnvView{ev->H, ev->W, ev->cond, ev->marg, ev->light, ev->hot_slot, ev->hot_texel, ev->n_hot, ev->guide,
-                    ev->G, ev->tex};
+                    ev->G, ev->tex, ev->pdf};
     a.g = GBufView{g->n_views, g->height, g->width, g->view_base, g->pos, g->nrm, g->kd, g->korm, g->mask, g->eye, n};
     a.spp = p->spp;
     a.flags = p->flags;

@@ -78,6 +78,61 @@ __device__ __forceinline__ int cdf_find_guided(const float* cdf, const int32_t* 
     return lo;
 }
 
+// The guided search of one conditional row with the candidates read in one
+// go, and the CDF values on both sides of the answer (c0 = cdf[j],
+// c1 = cdf[j + 1]).  Four aligned 16-byte loads, issued together, cover the
+// 13 to 16 entries from the cell's first candidate on.  When the cell's
+// candidates fit, the answer is the first candidate plus the number of later
+// candidates (below the cell's end) that are <= x, which over a
+// non-decreasing CDF is the binary search's answer; otherwise the binary
+// search runs, mostly over the lines just read.  One round trip for the
+// candidates instead of one per probe: with many waves in flight a line read
+// by one probe is often evicted before the next (cdf_find_guided's probes
+// then each go to memory).  The row must be 4-byte aligned within a 16-byte
+// aligned table that extends at least 16 floats past the row's last entry.
+__device__ __forceinline__ int cdf_find_row(const float* cdf, const int32_t* guide, int G, float x, float& c0,
+                                            float& c1) {
+    constexpr int NQ = 4, NW = 4 * NQ;
+    const int g = min(max((int)(x * (float)G), 0), G - 1);
+    int lo = guide[g], hi = guide[g + 1] + 1;
+    const float* p = cdf + lo;
+    const int o = (int)(((uintptr_t)p >> 2) & 3u);
+    const float4* a = (const float4*)(p - o);
+    float w[NW];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const float4 v = a[q];
+        w[4 * q] = v.x; w[4 * q + 1] = v.y; w[4 * q + 2] = v.z; w[4 * q + 3] = v.w;
+    }
+    if (hi - lo <= NW - 1 - o) {
+        // window slot t holds cdf[lo - o + t]; the answer's slot is o + cnt
+        const int span = hi - lo;
+        int cnt = 0;
+#pragma unroll
+        for (int t = 1; t < NW; ++t) {
+            const int k = t - o;   // offset from lo
+            cnt += (k >= 1 && k < span && w[t] <= x) ? 1 : 0;
+        }
+        const int s0 = o + cnt;
+        float v0 = w[0], v1 = w[1];
+#pragma unroll
+        for (int t = 1; t < NW; ++t) {
+            v0 = (t == s0) ? w[t] : v0;
+            v1 = (t == s0 + 1) ? w[t] : v1;
+        }
+        c0 = v0;
+        c1 = v1;
+        return lo + cnt;
+    }
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf[mid] <= x) lo = mid; else hi = mid;
+    }
+    c0 = cdf[lo];
+    c1 = cdf[lo + 1];
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // GGX with Smith height-correlated masking (alpha = roughness^2)
 // ---------------------------------------------------------------------------

@@ -91,6 +91,7 @@ struct EnvView {
     const int32_t* guide;          // [H][G+1] search guide of the conditional rows
     int32_t G;                     // guide cells per row (power of two)
     const float4* tex;             // [H*W] (r, g, b, pdf): radiance and density in one line
+    const float* pdf;              // [H*W] the density alone (tex.w), a quarter of tex's lines
 };
 
 struct GBufView {

@@ -43,6 +43,7 @@ struct Sample {
     float pL;      // light-technique density
     int texel;     // probe texel index i*W + j
     float x, y;    // continuous texel coordinates (phi W / 2 pi, theta H / pi)
+    float4 tx;     // the texel's (r, g, b, pdf), read once per sample
 };
 
 struct FwdAcc {
@@ -57,15 +58,34 @@ struct BwdAcc {
 
 // Light technique: piecewise-constant 2D distribution over the probe.
 // Returns false when the sample has no density (direction at a pole).
+// How each stage draws a light sample:
+//  kDrawGen  ray generation: the density alone, from the density table (a
+//            quarter of the radiance table's cache lines), row candidates
+//            read in one go (cdf_find_row);
+//  kDrawFwd  forward shading: the texel's radiance and density, kept for the
+//            evaluation, row candidates in one go;
+//  kDrawBwd  adjoint: the density from the radiance table (the evaluation
+//            reads that line again) and the binary row search, which needs
+//            fewer registers than the adjoint has to spare.
+enum DrawMode { kDrawGen, kDrawFwd, kDrawBwd };
+
+template <int MODE>
 __device__ __forceinline__ bool draw_light(const ShadeArgs& A, const Pixel& P, const float* s_marg, uint4 r0,
                                            Sample& S) {
     const int H = A.env.H, W = A.env.W;
     const float x0 = u01(r0.x), x1 = u01(r0.y);
     const int i = cdf_find(s_marg, H, x0);
     const float* crow = A.env.cond + (size_t)i * (W + 1);
-    const int j = cdf_find_guided(crow, A.env.guide + (size_t)i * (A.env.G + 1), A.env.G, x1);
+    float c0, c1;
+    int j;
+    if (MODE != kDrawBwd) {
+        j = cdf_find_row(crow, A.env.guide + (size_t)i * (A.env.G + 1), A.env.G, x1, c0, c1);
+    } else {
+        j = cdf_find_guided(crow, A.env.guide + (size_t)i * (A.env.G + 1), A.env.G, x1);
+        c0 = crow[j];
+        c1 = crow[j + 1];
+    }
     const float m0 = s_marg[i], m1 = s_marg[i + 1];
-    const float c0 = crow[j], c1 = crow[j + 1];
     S.y = (float)i + (x0 - m0) / (m1 - m0);
     S.x = (float)j + (x1 - c0) / (c1 - c0);
     const float v = S.y / (float)H;
@@ -75,7 +95,10 @@ __device__ __forceinline__ bool draw_light(const ShadeArgs& A, const Pixel& P, c
     sincospif(2.0f * u, &sp, &cp);
     S.w = f3(st * cp, ct, st * sp);
     S.texel = i * W + j;
-    S.pL = st > 0.0f ? A.env.tex[S.texel].w / (2.0f * kPi * kPi * st) : 0.0f;
+    if (MODE == kDrawFwd) S.tx = A.env.tex[S.texel];
+    else if (MODE == kDrawGen) S.tx.w = A.env.pdf[S.texel];
+    else S.tx.w = A.env.tex[S.texel].w;
+    S.pL = st > 0.0f ? S.tx.w / (2.0f * kPi * kPi * st) : 0.0f;
     S.wl = f3(dot(S.w, P.t), dot(S.w, P.b), dot(S.w, P.n));
     return S.pL > 0.0f;
 }
@@ -99,6 +122,7 @@ __device__ __forceinline__ bool draw_bsdf(const Pixel& P, uint4 r0, uint4 r1, Sa
 }
 
 // probe texel (nearest) of a BSDF-sampled direction and its light density
+template <bool KEEP>
 __device__ __forceinline__ void bsdf_texel(const ShadeArgs& A, bool light_on, Sample& S) {
     const int H = A.env.H, W = A.env.W;
     const float rho = sqrtf(S.w.x * S.w.x + S.w.z * S.w.z);
@@ -110,7 +134,12 @@ __device__ __forceinline__ void bsdf_texel(const ShadeArgs& A, bool light_on, Sa
     const int ti = min((int)S.y, H - 1);
     const int tj = min((int)S.x, W - 1);
     S.texel = ti * W + tj;
-    if (light_on && rho > 0.0f) S.pL = A.env.tex[S.texel].w / (2.0f * kPi * kPi * rho);
+    if (KEEP) {
+        S.tx = A.env.tex[S.texel];
+        if (light_on && rho > 0.0f) S.pL = S.tx.w / (2.0f * kPi * kPi * rho);
+    } else if (light_on && rho > 0.0f) {
+        S.pL = A.env.tex[S.texel].w / (2.0f * kPi * kPi * rho);
+    }
 }
 
 // where the adjoint puts probe-gradient records of non-hot texels: the tile's
@@ -194,7 +223,9 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
         L = T.w[0] * texel_rgb(A.env, T.t[0]) + T.w[1] * texel_rgb(A.env, T.t[1]) +
             T.w[2] * texel_rgb(A.env, T.t[2]) + T.w[3] * texel_rgb(A.env, T.t[3]);
     } else {
-        const float4 tx = A.env.tex[S.texel];
+        // the forward keeps the texel from the draw; the adjoint, short of
+        // registers, reads it again
+        const float4 tx = BWD ? A.env.tex[S.texel] : S.tx;
         L = f3(tx.x, tx.y, tx.z);
         pdf_uv = tx.w;
     }
@@ -332,7 +363,7 @@ __device__ __forceinline__ void gen_tile(const ShadeArgs& A, int64_t tile, float
             Sample S;
             if (go) {
                 bool has = true;
-                if (tech == 0) has = light_on && draw_light(A, P, s_marg, r0, S);
+                if (tech == 0) has = light_on && draw_light<kDrawGen>(A, P, s_marg, r0, S);
                 else if (P.bsdf_w != 0.0f) draw_bsdf(P, r0, r1, S);
                 else has = false;
                 want = has && S.wl.z > 0.0f;
@@ -797,7 +828,7 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
             Sample S;
             if (tech == 0) {
                 if (!light_on) continue;
-                const bool has = draw_light(A, P, s_marg, r0, S);
+                const bool has = draw_light<BWD ? kDrawBwd : kDrawFwd>(A, P, s_marg, r0, S);
                 rec0 = (uint32_t)S.texel;
                 if (DUMP) dir[0] = S.w;
                 if (!has) { rec2 |= kDecLCull; continue; }
@@ -808,7 +839,7 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
             }
             if (!(S.wl.z > 0.0f)) { rec2 |= tech ? kDecBCull : kDecLCull; continue; }
             if (tech == 1) {
-                bsdf_texel(A, light_on, S);
+                bsdf_texel<!BWD>(A, light_on, S);
                 rec1 = (uint32_t)S.texel;
             }
             float Hv = 1.0f;

@@ -307,6 +307,26 @@ def test_fwd_parity_sparse_probe(shape):
     _fwd_parity(w)
 
 
+def test_fwd_parity_wide_probe():
+    """Light-sample texels on a 2048-column probe (128 guide cells of 16
+    columns per row): rows whose cells mostly fit the 16-entry candidate
+    window and rows whose cells do not (a steep ramp, a row of few spikes, a
+    dim row with one bright texel), up to the last row's last column, where
+    the window reads past the table."""
+    w = make_workload("tiny")
+    r = np.random.Generator(np.random.PCG64(2048))
+    H, W = 8, 2048
+    e = r.lognormal(0, 1.5, (H, W, 3)).astype(np.float32)
+    e[2] = (1.01 ** np.arange(W, dtype=np.float64))[:, None].astype(np.float32)
+    e[4] = 0.0
+    e[4, r.integers(0, W, 12)] = 50.0
+    e[6] *= 1e-3
+    e[6, W // 3] = 1e3
+    e[H - 1, W - 40:] = 1e2
+    w.env = e
+    _fwd_parity(w)
+
+
 def test_fwd_parity_sphere8_ragged():
     # two views, 60x52: several tiles and a ragged last tile
     w = make_workload("sphere8", H=60, W=52, n_views=2)
