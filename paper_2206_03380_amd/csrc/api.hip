@@ -190,6 +190,7 @@ struct mcdi_env_s {
     int32_t* n_hot = nullptr;
     int32_t* guide = nullptr;      // [H][G+1]
     int32_t G = 1;
+    int32_t win = 0;
     float4* tex = nullptr;         // [H*W] (r, g, b, pdf)
 };
 
@@ -329,7 +330,8 @@ mcdi_status mcdi_build_env_cdf(const float* env_rgb, int32_t H, int32_t W, const
     ev->hot_slot = (int32_t*)ev->alloc.get(sizeof(int32_t) * (size_t)H * W, s);
     ev->hot_texel = (int32_t*)ev->alloc.get(sizeof(int32_t) * kHotMax, s);
     ev->n_hot = (int32_t*)ev->alloc.get(sizeof(int32_t), s);
-    ev->G = env_guide_cells(W);
+    ev->win = env_row_window(H, W);
+    ev->G = env_guide_cells(W, ev->win);
     ev->guide = (int32_t*)ev->alloc.get(sizeof(int32_t) * (size_t)H * (ev->G + 1), s);
     ev->tex = (float4*)ev->alloc.get(sizeof(float4) * (size_t)H * W, s);
     if (!ev->cond || !ev->marg || !ev->pdf || !ev->rowsum || !ev->light || !ev->hot_slot || !ev->hot_texel ||
@@ -397,7 +399,7 @@ static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, cons
     std::memset(&a, 0, sizeof(a));
     a.scene = scene_view(sc);
     a.env = EnvView{ev->H, ev->W, ev->cond, ev->marg, ev->light, ev->hot_slot, ev->hot_texel, ev->n_hot, ev->guide,
-                    ev->G, ev->tex, ev->pdf};
+                    ev->G, ev->tex, ev->pdf, ev->win};
     a.g = GBufView{g->n_views, g->height, g->width, g->view_base, g->pos, g->nrm, g->kd, g->korm, g->mask, g->eye, n};
     a.spp = p->spp;
     a.flags = p->flags;

@@ -140,13 +140,25 @@ hipError_t launch_env_pack(const float* env, const float* pdf, int64_t n, float4
     return hipGetLastError();
 }
 
-// About sixteen columns per cell, at most 1024 cells.  A draw reads the guide,
-// then the cell's candidates (cdf_find_row); the guide, a sixteenth of the
-// rows' size, then stays in the L2 cache, and on a 2048-column probe finer
-// guides (8, 4 or 2 columns per cell) measured slower for it.
-int env_guide_cells(int W) {
+#ifndef MCDI_WIN_BYTES
+#define MCDI_WIN_BYTES (4 << 20)
+#endif
+// Whether light draws read a cell's candidates in one go (cdf_find_row): for
+// conditional tables larger than one XCD's L2 (4 MB), where a line read by
+// one binary-search probe is often gone by the next.  A table that stays in
+// the cache is searched faster by the binary search.
+int env_row_window(int H, int W) {
+    return (double)H * (W + 1) * sizeof(float) > (double)MCDI_WIN_BYTES ? 1 : 0;
+}
+
+// Guide cells per row, at most 1024: about eight columns per cell for the
+// binary search; sixteen with the candidate window, whose guide (a sixteenth
+// of the rows' size) then stays in the L2 cache (on a 2048-column probe finer
+// guides measured slower).
+int env_guide_cells(int W, int win) {
+    const int cols = win ? 16 : 8;
     int G = 1;
-    while (16 * G <= W && G < 1024) G *= 2;
+    while (cols * G <= W && G < 1024) G *= 2;
     return G;
 }
 

@@ -92,6 +92,7 @@ struct EnvView {
     int32_t G;                     // guide cells per row (power of two)
     const float4* tex;             // [H*W] (r, g, b, pdf): radiance and density in one line
     const float* pdf;              // [H*W] the density alone (tex.w), a quarter of tex's lines
+    int32_t win;                   // 1: row searches read the cell's candidates in one go
 };
 
 struct GBufView {
@@ -163,7 +164,8 @@ hipError_t launch_env_cdf(const float* env, int H, int W, float* cond, float* ma
                           double* rowsum, int32_t* light_enabled, hipStream_t s);
 // Search guide of the conditional CDF rows: guide[i][g] = the largest column
 // k <= W-1 with cond[i][k] <= g / G, for g = 0..G.
-int env_guide_cells(int W);
+int env_row_window(int H, int W);
+int env_guide_cells(int W, int win);
 // (r, g, b, pdf) per texel, after the tables
 hipError_t launch_env_pack(const float* env, const float* pdf, int64_t n, float4* tex, hipStream_t s);
 // out[k] = (rgb[k].xyz, dens[k].w)

@@ -60,13 +60,14 @@ struct BwdAcc {
 // Returns false when the sample has no density (direction at a pole).
 // How each stage draws a light sample:
 //  kDrawGen  ray generation: the density alone, from the density table (a
-//            quarter of the radiance table's cache lines), row candidates
-//            read in one go (cdf_find_row);
+//            quarter of the radiance table's cache lines);
 //  kDrawFwd  forward shading: the texel's radiance and density, kept for the
-//            evaluation, row candidates in one go;
+//            evaluation;
 //  kDrawBwd  adjoint: the density from the radiance table (the evaluation
-//            reads that line again) and the binary row search, which needs
-//            fewer registers than the adjoint has to spare.
+//            reads that line again) and always the binary row search, which
+//            needs fewer registers than the adjoint has to spare.
+// The other two read the row's candidates in one go (cdf_find_row) where the
+// tables ask for it (env.win).
 enum DrawMode { kDrawGen, kDrawFwd, kDrawBwd };
 
 template <int MODE>
@@ -78,7 +79,7 @@ __device__ __forceinline__ bool draw_light(const ShadeArgs& A, const Pixel& P, c
     const float* crow = A.env.cond + (size_t)i * (W + 1);
     float c0, c1;
     int j;
-    if (MODE != kDrawBwd) {
+    if (MODE != kDrawBwd && A.env.win) {
         j = cdf_find_row(crow, A.env.guide + (size_t)i * (A.env.G + 1), A.env.G, x1, c0, c1);
     } else {
         j = cdf_find_guided(crow, A.env.guide + (size_t)i * (A.env.G + 1), A.env.G, x1);

@@ -308,21 +308,22 @@ def test_fwd_parity_sparse_probe(shape):
 
 
 def test_fwd_parity_wide_probe():
-    """Light-sample texels on a 2048-column probe (128 guide cells of 16
-    columns per row): rows whose cells mostly fit the 16-entry candidate
-    window and rows whose cells do not (a steep ramp, a row of few spikes, a
-    dim row with one bright texel), up to the last row's last column, where
-    the window reads past the table."""
+    """Light-sample texels on a 512 x 2048 probe, whose conditional table
+    (4.2 MB) is past the size where draws read a guide cell's candidates in
+    one window (128 cells of 16 columns per row): rows whose cells mostly fit
+    the 16-entry window and rows whose cells do not (a steep ramp, a row of
+    few spikes, a dim row with one bright texel), up to the last row's last
+    columns, where the window reads past the table."""
     w = make_workload("tiny")
     r = np.random.Generator(np.random.PCG64(2048))
-    H, W = 8, 2048
+    H, W = 512, 2048
     e = r.lognormal(0, 1.5, (H, W, 3)).astype(np.float32)
-    e[2] = (1.01 ** np.arange(W, dtype=np.float64))[:, None].astype(np.float32)
-    e[4] = 0.0
-    e[4, r.integers(0, W, 12)] = 50.0
-    e[6] *= 1e-3
-    e[6, W // 3] = 1e3
-    e[H - 1, W - 40:] = 1e2
+    e[100] = (1.01 ** np.arange(W, dtype=np.float64))[:, None].astype(np.float32) * 1e-3
+    e[200] = 0.0
+    e[200, r.integers(0, W, 12)] = 5e3
+    e[300] *= 1e-3
+    e[300, W // 3] = 1e5
+    e[H - 1, W - 40:] = 1e4
     w.env = e
     _fwd_parity(w)
 
