@@ -22,7 +22,10 @@
  *   - the same random numbers are replayed in the backward pass (section 4.1,
  *     appendix D);
  *   - diffuse lighting is returned demodulated, specular is not (section 4.2);
- *   - shadowed samples are weighted by H = 1 - tau (appendix A);
+ *   - shadowed samples are weighted by H = 1 - tau (appendix A); the
+ *     incident radiance is the probe's times H, so with H = 0 a blocked
+ *     direction carries none, whatever the probe holds there (also where it
+ *     is not finite, where an IEEE product would give NaN);
  *   - separately, the visibility gradient that the estimator detaches: the
  *     derivative of the shadowed integral with respect to the occluding mesh's
  *     vertices (section 3.1 "Shadow gradients"; appendix "Visibility
@@ -1246,6 +1249,7 @@ static void shade_pixel(const shade_ctx* C, int64_t q, int64_t pix, int grad, co
                     Hv = 1.0 - P->tau;
                 }
             }
+            if (Hv == 0.0) continue;   /* no incident radiance (appendix A) */
             double Lv[3], dLv[3] = {0.0, 0.0, 0.0};
             const int bil = (P->flags & ORC_BILINEAR) != 0;
             if (bil) {
@@ -1528,7 +1532,8 @@ void orc_integrand(const orc_scene* scene, const orc_env* E, const orc_gbuffer* 
                 const float* Lrad = E->env + ((size_t)ti * E->W + tj) * 3;
                 for (int c = 0; c < 3; ++c) Lv[c] = (double)Lrad[c];
             }
-            eval_sample(&S, &S, 1.0f, wi, 0.0, 0.0, Lv, dLv, 1, Hv, 0, NULL, NULL, &o, &ec, 1.0, 0.0, 1);
+            if (Hv != 0.0)   /* a blocked direction carries no radiance with H = 0 */
+                eval_sample(&S, &S, 1.0f, wi, 0.0, 0.0, Lv, dLv, 1, Hv, 0, NULL, NULL, &o, &ec, 1.0, 0.0, 1);
         }
         for (int c = 0; c < 3; ++c) {
             gd[3 * i + c] = o.val[T_CD + c];

@@ -818,14 +818,22 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
     FwdAcc fa{f3(0, 0, 0), f3(0, 0, 0)};
     BwdAcc ba{f3(0, 0, 0), 0.0f, 0.0f, f3(0, 0, 0)};
     uint32_t bits = 0;
+    // With tau = 1 a blocked sample is weighted by H = 0 and adds nothing
+    // (the incident radiance is the probe's times H, appendix A): its hit
+    // bit (set only for a traced, blocked ray) skips it before it is drawn,
+    // and a sample pair with both rays blocked skips its Philox blocks.  The
+    // decision dump draws every sample and skips only the evaluation.
+    const bool skip_blocked = !DUMP && A.tau == 1.0f;
     for (int s = 0; s < spp; ++s) {
         if (((2 * s) & 31) == 0) bits = A.hitbits_in[((2 * s) >> 5) * N + pix];
+        if (skip_blocked && ((bits >> ((2 * s) & 31)) & 3u) == 3u) continue;
         const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
         const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
         uint32_t rec0 = kNone, rec1 = kNone;
         uint32_t rec2 = kDecValid | (P.nov_pos ? kDecNovPos : 0u);
         float3 dir[2] = {f3(__uint_as_float(kNanBits), 0.0f, 0.0f), f3(__uint_as_float(kNanBits), 0.0f, 0.0f)};
         for (int tech = 0; tech < 2; ++tech) {
+            if (skip_blocked && ((bits >> ((2 * s + tech) & 31)) & 1u)) continue;
             Sample S;
             if (tech == 0) {
                 if (!light_on) continue;
@@ -852,6 +860,8 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
                     rec2 |= tech ? kDecBHit : kDecLHit;
                 }
             }
+            // H = 0: no incident radiance, whatever the probe holds there
+            if (Hv == 0.0f) continue;
             if (FROZEN) {
                 // the sample's direction in the evaluation frame (the
                 // sampled local direction itself where the frame is the same)

@@ -141,3 +141,32 @@ def check_dirs(g_dirs, o_dirs, name=""):
     print("%s directions: %d samples, largest distance %.1f u, worst distance/bound %.3f, median bound %.1f u" % (
         name, d.size, d.max() / U, ratio, float(np.median(e)) / U))
     return ratio, float(d.max() / U), int(d.size)
+
+
+def occluder_with_hidden_infinity(level=3, H=16, W=32, seed=31):
+    """A unit icosphere at (0, 0.2, 0) over a receiver point at (0.5, -1, 0)
+    (normal +y), a lognormal probe, and a copy of the probe with +inf in every
+    texel whose corners all lie within 35 degrees of the direction to the
+    sphere's centre (the sphere's angular radius there is 50 degrees), so that
+    the receiver sees those texels only through the sphere.
+    Returns (verts, tris, p, n, env, env_inf)."""
+    from workloads import meshes
+    v, f = meshes.icosphere(level)
+    v = v + np.array([0.0, 0.2, 0.0])
+    p = np.array([0.5, -1.0, 0.0])
+    n = np.array([0.0, 1.0, 0.0])
+    rng = np.random.Generator(np.random.PCG64(seed))
+    env = rng.lognormal(0, 1, (H, W, 3)).astype(np.float32)
+    c = np.array([0.0, 0.2, 0.0]) - p
+    c /= np.linalg.norm(c)
+    inside = np.zeros((H, W), bool)
+    for i in range(H):
+        for j in range(W):
+            th = np.pi * np.array([i, i, i + 1, i + 1]) / H
+            ph = 2 * np.pi * np.array([j, j + 1, j, j + 1]) / W
+            d = np.stack([np.sin(th) * np.cos(ph), np.cos(th), np.sin(th) * np.sin(ph)], -1)
+            inside[i, j] = np.all(d @ c > np.cos(np.radians(35.0)))
+    assert inside.sum() >= 4
+    env_inf = env.copy()
+    env_inf[inside] = np.inf
+    return v, f, p, n, env, env_inf

@@ -328,6 +328,53 @@ def test_fwd_parity_wide_probe():
     _fwd_parity(w)
 
 
+@pytest.mark.parametrize("tau", [1.0, 0.5])
+def test_fwd_skip_blocked_equals_dump(tau):
+    """With tau = 1 the forward skips samples whose ray was blocked (weight
+    H = 0) before drawing them; the decision dump draws and evaluates every
+    sample.  The two agree bit for bit, on a scene with blocked rays (the
+    ground under the sphere), as they do for tau = 0.5, where nothing is
+    skipped."""
+    w = make_workload("tiny")
+    w.tau = tau
+    a, _ = gpu_forward(w, dump=False)
+    b, _ = gpu_forward(w, dump=True)
+    bits = hitbits_per_pixel(a["hitbits"])
+    assert bits.any()
+    assert np.array_equal(a["hitbits"], b["hitbits"])
+    for key in ("c_d", "c_s"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_blocked_directions_carry_no_radiance():
+    """With tau = 1 the receiver under the sphere sees probe texels that hold
+    +inf only through the sphere: forward (with and without the decision
+    dump) and adjoint equal those of the finite probe bit for bit, as the
+    oracle's do (the incident radiance is the probe's times H = 0)."""
+    import torch
+    import paper_2206_03380_amd as M
+    from tests.parity_util import occluder_with_hidden_infinity
+    v, f, p, n, env, env_inf = occluder_with_hidden_infinity()
+    N = 256
+    korm = np.tile([1.0, 0.5, 0.3], (N, 1))
+    res = []
+    for e, dump in ((env, False), (env_inf, False), (env_inf, True)):
+        w = from_arrays("occluder", v, f, e, np.tile(p, (N, 1)), np.tile(n, (N, 1)), np.full((N, 3), 0.5), korm,
+                        eye=np.array([3.0, 2.0, 1.0]), spp=16, ray_eps=1e-4, tau=1.0)
+        g, (scene, envh, gb, hb) = gpu_forward(w, dump=dump, flags=M.FLAG_LIGHT_OFF)
+        ud = torch.full((3, N), 0.25, device="cuda")
+        grads = M.shade_bwd(scene, envh, gb, w.spp, ud, ud, hitbits=hb, seed=w.seed, tau=w.tau,
+                            ray_eps=w.ray_eps, flags=M.FLAG_LIGHT_OFF)
+        res.append((g, [to_np(t) for t in grads[:3]]))
+    (a, ga), (b, gb_), (c, _) = res
+    assert hitbits_per_pixel(a["hitbits"]).any()
+    for key in ("c_d", "c_s"):
+        assert np.all(np.isfinite(b[key])), key
+        assert np.array_equal(a[key], b[key]) and np.array_equal(a[key], c[key]), key
+    for x, y in zip(ga, gb_):
+        assert np.all(np.isfinite(y)) and np.array_equal(x, y)
+
+
 def test_fwd_parity_sphere8_ragged():
     # two views, 60x52: several tiles and a ragged last tile
     w = make_workload("sphere8", H=60, W=52, n_views=2)

@@ -25,6 +25,7 @@ import pytest
 import oracle
 from workloads import make_workload, from_arrays
 from workloads import meshes
+from tests.parity_util import occluder_with_hidden_infinity
 
 RNG = np.random.Generator(np.random.PCG64(1185))
 
@@ -239,6 +240,29 @@ def test_lambert_occluder_expectation(tau):
     assert np.all(np.abs(est - expect) < 4 * se), (est, expect, se)
     # rays passing within the tolerance of an edge are undecided: rare
     assert o["info"][:, 1].sum() < 1e-3 * N * spp
+
+
+def test_blocked_directions_carry_no_radiance():
+    """With tau = 1 a direction the occluder blocks carries no radiance
+    (appendix A: the incident radiance is the probe's times H, H = 0 on
+    blocked directions), whatever the probe holds there: BSDF-only estimates
+    with infinite radiance in probe texels that the occluder covers entirely
+    equal those with finite radiance, bit for bit.  With tau = 0.5 the
+    infinity shows."""
+    v, f, p, n, env, env_inf = occluder_with_hidden_infinity()
+    N, spp = 256, 16
+    korm = np.tile([1.0, 0.5, 0.3], (N, 1))
+
+    def run(e, tau):
+        w = from_arrays("occluder", v, f, e, np.tile(p, (N, 1)), np.tile(n, (N, 1)), np.full((N, 3), 0.5), korm,
+                        eye=np.array([3.0, 2.0, 1.0]), spp=spp, ray_eps=1e-4, tau=tau)
+        return oracle.shade(w, flags=oracle.LIGHT_OFF)
+
+    a, b = run(env, 1.0), run(env_inf, 1.0)
+    for k in ("c_d", "c_s"):
+        assert np.all(np.isfinite(b[k]))
+        assert np.array_equal(a[k], b[k]), k
+    assert not np.all(np.isfinite(run(env_inf, 0.5)["c_d"]))
 
 
 # ---------------------------------------------------------------------------
