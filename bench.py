@@ -253,12 +253,13 @@ def measure(args, M, w, steps, warmup):
                                      "tri": stats["tri_tests"] / max(stats["tri_slots"], 1)},
                 "box_tests_per_lane_step": stats["box_tests"] / max(stats["box_lanes"], 1)}
     # ---- roofline of the adjoint kernel (shade_kernel<true>) ----
-    adj_ops = ADJ_OPS_PER_SAMPLE * stats["valid_pixels"] * w.spp + ADJ_OPS_PER_EVAL * rays
+    adj_units = adjoint_units(hb, stats, w)
+    adj_ops = (ADJ_OPS_PHILOX * adj_units["pairs_drawn"] + ADJ_OPS_LIGHT * adj_units["light_draws"] +
+               ADJ_OPS_BSDF * adj_units["bsdf_draws"] + ADJ_OPS_PER_EVAL * adj_units["evaluated_directions"])
     adj_a = adj_ops / (adj_ms * 1e-3) if adj_ms > 0 else 0.0
     adjoint_roofline = {"bound": "alu", "achieved": adj_a / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
                         "frac": adj_a / VALU_PEAK, "traffic": None, "kernel": "shade_kernel<true>",
-                        "ops_per_launch": adj_ops, "kernel_ms": adj_ms,
-                        "units": {"samples": stats["valid_pixels"] * w.spp, "evaluated_directions": rays}}
+                        "ops_per_launch": adj_ops, "kernel_ms": adj_ms, "units": adj_units}
     STATE.update(scene=scene, env=envh, w=w, verts=verts, tris=tris)
     return {
         "config": {"workload": "%s: %d views %dx%d, %d tris, env %dx%d, %d spp, fwd+bwd" % (
@@ -276,19 +277,43 @@ def measure(args, M, w, steps, warmup):
 
 
 # Adjoint kernel (shade_kernel<true>), VALU lane operations of the method.
-# Per drawn sample of a valid pixel: two Philox4x32-10 blocks (ten rounds of
-# two 32x32->64 products, two xors and the key schedule: 160), the light
-# technique's draw (marginal and guided conditional searches, in-texel
-# offsets, two sincospi, the direction and its density: 50) and the BSDF
-# technique's (lobe choice, cosine or visible-normal warp, world frame,
-# normalisation, two atan2 for the texel and its density: 100) = 310.  Per
-# evaluated direction: the balance heuristic and the BSDF (half vector, D,
+# Per drawn sample pair of a valid pixel: two Philox4x32-10 blocks (ten
+# rounds of two 32x32->64 products, two xors and the key schedule: 160); per
+# light draw (marginal and guided conditional searches, in-texel offsets, two
+# sincospi, the direction and its density: 50); per BSDF draw (lobe choice,
+# cosine or visible-normal warp, world frame, normalisation, two atan2 for
+# the texel and its density: 100).  Per evaluated direction: the balance heuristic and the BSDF (half vector, D,
 # both Smith Lambdas, G2, Schlick F, three densities: 60) and the
 # derivatives (D and Lambda in alpha, S in alpha, n.v, n.l and n.h, the
 # normal gradient in the tangent frame, kd/m/r terms, the probe coefficient
 # and its scatter: 85) = 145.
-ADJ_OPS_PER_SAMPLE = 310
+ADJ_OPS_PHILOX = 160
+ADJ_OPS_LIGHT = 50
+ADJ_OPS_BSDF = 100
 ADJ_OPS_PER_EVAL = 145
+
+
+def adjoint_units(hb, stats, w):
+    """The adjoint's units of work.  With tau = 1 a sample whose ray was
+    blocked adds nothing, and the kernel skips it before drawing it (its hit
+    bit is set); a sample pair with both rays blocked skips its Philox
+    blocks.  Counted from the step's hit bits ([words][N] u32, bit 2s the
+    light sample of sample s, bit 2s + 1 its BSDF sample).  Otherwise every
+    sample of a valid pixel is drawn and every traced direction evaluated."""
+    import numpy as np
+    pairs = stats["valid_pixels"] * w.spp
+    if w.tau != 1.0:
+        return {"pairs_drawn": pairs, "light_draws": pairs, "bsdf_draws": pairs,
+                "evaluated_directions": stats["rays_traced"]}
+    bits = hb.cpu().numpy().view(np.uint32)
+    even = np.uint32(0x55555555)
+    light, bsdf = bits & even, (bits >> np.uint32(1)) & even
+    both = int(np.bitwise_count(light & bsdf).sum())
+    light_only = int(np.bitwise_count(light & ~bsdf).sum())
+    bsdf_only = int(np.bitwise_count(bsdf & ~light).sum())
+    drawn = pairs - both
+    return {"pairs_drawn": drawn, "light_draws": drawn - light_only, "bsdf_draws": drawn - bsdf_only,
+            "evaluated_directions": stats["rays_traced"] - stats["rays_hit"]}
 
 
 # per-unit VALU lane-operation counts of the traversal: slab test of one
