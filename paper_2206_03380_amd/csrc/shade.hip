@@ -312,6 +312,16 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& A, const Pixel& P, 
     ba.gnl = ba.gnl + gn;
 }
 
+// bit k of the result = bit 2k of x (k < 16)
+__device__ __forceinline__ uint32_t even_bits(uint32_t x) {
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    x = (x | (x >> 8)) & 0x0000FFFFu;
+    return x;
+}
+
 __device__ __forceinline__ void stage_marg(const ShadeArgs& A, float* s_marg) {
     for (int k = threadIdx.x; k <= A.env.H; k += blockDim.x) s_marg[k] = A.env.marg[k];
 }
@@ -817,71 +827,78 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
     }
     FwdAcc fa{f3(0, 0, 0), f3(0, 0, 0)};
     BwdAcc ba{f3(0, 0, 0), 0.0f, 0.0f, f3(0, 0, 0)};
-    uint32_t bits = 0;
     // With tau = 1 a blocked sample is weighted by H = 0 and adds nothing
     // (the incident radiance is the probe's times H, appendix A): its hit
-    // bit (set only for a traced, blocked ray) skips it before it is drawn,
-    // and a sample pair with both rays blocked skips its Philox blocks.  The
-    // decision dump draws every sample and skips only the evaluation.
+    // bit (set only for a traced, blocked ray) skips it before it is drawn.
+    // A lane walks only its pixel's sample pairs that are not blocked twice
+    // over (in increasing order, so the sums are those of the full loop), so
+    // a wavefront runs as many pair steps as its busiest lane rather than
+    // spp.  The decision dump draws every sample and skips only the
+    // evaluation.
     const bool skip_blocked = !DUMP && A.tau == 1.0f;
-    for (int s = 0; s < spp; ++s) {
-        if (((2 * s) & 31) == 0) bits = A.hitbits_in[((2 * s) >> 5) * N + pix];
-        if (skip_blocked && ((bits >> ((2 * s) & 31)) & 3u) == 3u) continue;
-        const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
-        const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
-        uint32_t rec0 = kNone, rec1 = kNone;
-        uint32_t rec2 = kDecValid | (P.nov_pos ? kDecNovPos : 0u);
-        float3 dir[2] = {f3(__uint_as_float(kNanBits), 0.0f, 0.0f), f3(__uint_as_float(kNanBits), 0.0f, 0.0f)};
-        for (int tech = 0; tech < 2; ++tech) {
-            if (skip_blocked && ((bits >> ((2 * s + tech) & 31)) & 1u)) continue;
-            Sample S;
-            if (tech == 0) {
-                if (!light_on) continue;
-                const bool has = draw_light<BWD ? kDrawBwd : kDrawFwd>(A, P, s_marg, r0, S);
-                rec0 = (uint32_t)S.texel;
-                if (DUMP) dir[0] = S.w;
-                if (!has) { rec2 |= kDecLCull; continue; }
-            } else {
-                if (P.bsdf_w == 0.0f) continue;
-                if (draw_bsdf(P, r0, r1, S)) rec2 |= kDecLobeCos;
-                if (DUMP) dir[1] = S.w;
-            }
-            if (!(S.wl.z > 0.0f)) { rec2 |= tech ? kDecBCull : kDecLCull; continue; }
-            if (tech == 1) {
-                bsdf_texel<!BWD>(A, light_on, S);
-                rec1 = (uint32_t)S.texel;
-            }
-            float Hv = 1.0f;
-            if (trace) {
-                const int bitpos = 2 * s + tech;
-                rec2 |= tech ? kDecBTraced : kDecLTraced;
-                if ((bits >> (bitpos & 31)) & 1u) {
-                    Hv = 1.0f - A.tau;
-                    rec2 |= tech ? kDecBHit : kDecLHit;
+    for (int s0 = 0; s0 < spp; s0 += 16) {
+        const uint32_t bits = A.hitbits_in[(s0 >> 4) * N + pix];   // pairs s0 .. s0 + 15
+        uint32_t todo = (spp - s0 >= 16) ? 0xFFFFu : (1u << (spp - s0)) - 1u;
+        if (skip_blocked) todo &= ~even_bits(bits & (bits >> 1));
+        while (todo) {
+            const int s = s0 + __ffs(todo) - 1;
+            todo &= todo - 1u;
+            const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
+            const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
+            uint32_t rec0 = kNone, rec1 = kNone;
+            uint32_t rec2 = kDecValid | (P.nov_pos ? kDecNovPos : 0u);
+            float3 dir[2] = {f3(__uint_as_float(kNanBits), 0.0f, 0.0f), f3(__uint_as_float(kNanBits), 0.0f, 0.0f)};
+            for (int tech = 0; tech < 2; ++tech) {
+                if (skip_blocked && ((bits >> ((2 * s + tech) & 31)) & 1u)) continue;
+                Sample S;
+                if (tech == 0) {
+                    if (!light_on) continue;
+                    const bool has = draw_light<BWD ? kDrawBwd : kDrawFwd>(A, P, s_marg, r0, S);
+                    rec0 = (uint32_t)S.texel;
+                    if (DUMP) dir[0] = S.w;
+                    if (!has) { rec2 |= kDecLCull; continue; }
+                } else {
+                    if (P.bsdf_w == 0.0f) continue;
+                    if (draw_bsdf(P, r0, r1, S)) rec2 |= kDecLobeCos;
+                    if (DUMP) dir[1] = S.w;
+                }
+                if (!(S.wl.z > 0.0f)) { rec2 |= tech ? kDecBCull : kDecLCull; continue; }
+                if (tech == 1) {
+                    bsdf_texel<!BWD>(A, light_on, S);
+                    rec1 = (uint32_t)S.texel;
+                }
+                float Hv = 1.0f;
+                if (trace) {
+                    const int bitpos = 2 * s + tech;
+                    rec2 |= tech ? kDecBTraced : kDecLTraced;
+                    if ((bits >> (bitpos & 31)) & 1u) {
+                        Hv = 1.0f - A.tau;
+                        rec2 |= tech ? kDecBHit : kDecLHit;
+                    }
+                }
+                // H = 0: no incident radiance, whatever the probe holds there
+                if (Hv == 0.0f) continue;
+                if (FROZEN) {
+                    // the sample's direction in the evaluation frame (the
+                    // sampled local direction itself where the frame is the same)
+                    Sample Se = S;
+                    if (!(Pe.n.x == P.n.x && Pe.n.y == P.n.y && Pe.n.z == P.n.z))
+                        Se.wl = f3(dot(S.w, Pe.t), dot(S.w, Pe.b), dot(S.w, Pe.n));
+                    eval_sample<BWD, BIL, true>(A, Pe, Se, Hv, invspp, fa, ba, Ud, Us, s_hot, rs, mis_density(P, S));
+                } else {
+                    eval_sample<BWD, BIL>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
                 }
             }
-            // H = 0: no incident radiance, whatever the probe holds there
-            if (Hv == 0.0f) continue;
-            if (FROZEN) {
-                // the sample's direction in the evaluation frame (the
-                // sampled local direction itself where the frame is the same)
-                Sample Se = S;
-                if (!(Pe.n.x == P.n.x && Pe.n.y == P.n.y && Pe.n.z == P.n.z))
-                    Se.wl = f3(dot(S.w, Pe.t), dot(S.w, Pe.b), dot(S.w, Pe.n));
-                eval_sample<BWD, BIL, true>(A, Pe, Se, Hv, invspp, fa, ba, Ud, Us, s_hot, rs, mis_density(P, S));
-            } else {
-                eval_sample<BWD, BIL>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
-            }
-        }
-        if (DUMP) {
-            const int st = dump_stride(A);
-            uint32_t* d = A.decisions + ((size_t)pix * spp + s) * st;
-            d[0] = rec0; d[1] = rec1; d[2] = rec2;
-            if (st == 9) {
-                for (int t = 0; t < 2; ++t) {
-                    d[3 + 3 * t] = __float_as_uint(dir[t].x);
-                    d[4 + 3 * t] = __float_as_uint(dir[t].y);
-                    d[5 + 3 * t] = __float_as_uint(dir[t].z);
+            if (DUMP) {
+                const int st = dump_stride(A);
+                uint32_t* d = A.decisions + ((size_t)pix * spp + s) * st;
+                d[0] = rec0; d[1] = rec1; d[2] = rec2;
+                if (st == 9) {
+                    for (int t = 0; t < 2; ++t) {
+                        d[3 + 3 * t] = __float_as_uint(dir[t].x);
+                        d[4 + 3 * t] = __float_as_uint(dir[t].y);
+                        d[5 + 3 * t] = __float_as_uint(dir[t].z);
+                    }
                 }
             }
         }
