@@ -776,8 +776,11 @@ constexpr uint32_t kNanBits = 0x7FC00000u;
 __device__ __forceinline__ int dump_stride(const ShadeArgs& A) { return (A.flags & MCDI_FLAG_DUMP_DIRS) ? 9 : 3; }
 
 // FROZEN (forward only): samples, densities, lobe choice and visibility from
-// the G-buffer A.g, the samples evaluated with the planes A.e_*
-template <bool BWD, bool DUMP, bool BIL, bool FROZEN = false>
+// the G-buffer A.g, the samples evaluated with the planes A.e_*.
+// LOCKSTEP: the lanes step through every sample pair together, skipping a pair
+// blocked twice over in place (the persistent serving kernel, whose launches
+// ran a quarter slower with the per-lane walk below).
+template <bool BWD, bool DUMP, bool BIL, bool FROZEN = false, bool LOCKSTEP = false>
 __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, const float* s_marg, float* s_hot,
                                            const RecSink& rs) {
     const int64_t N = A.g.n;
@@ -839,10 +842,11 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
     for (int s0 = 0; s0 < spp; s0 += 16) {
         const uint32_t bits = A.hitbits_in[(s0 >> 4) * N + pix];   // pairs s0 .. s0 + 15
         uint32_t todo = (spp - s0 >= 16) ? 0xFFFFu : (1u << (spp - s0)) - 1u;
-        if (skip_blocked) todo &= ~even_bits(bits & (bits >> 1));
+        if (skip_blocked && !LOCKSTEP) todo &= ~even_bits(bits & (bits >> 1));
         while (todo) {
             const int s = s0 + __ffs(todo) - 1;
             todo &= todo - 1u;
+            if (LOCKSTEP && skip_blocked && ((bits >> ((2 * s) & 31)) & 3u) == 3u) continue;
             const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
             const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
             uint32_t rec0 = kNone, rec1 = kNone;
@@ -1074,13 +1078,13 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(const ServeItem* items, i
         if (reg) trace_tile<false>(A, tile, reg, s_cnt, it.hitbits, &s_next, s_stack);
         __syncthreads();
         const bool bil = (A.flags & MCDI_FLAG_BILINEAR) != 0;
-        if (bil) shade_tile<false, false, true>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
-        else shade_tile<false, false, false>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
+        if (bil) shade_tile<false, false, true, false, true>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
+        else shade_tile<false, false, false, false, true>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
         if (A.g_cd) {
             hot_zero(s_hot);
             __syncthreads();
-            if (bil) shade_tile<true, false, true>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
-            else shade_tile<true, false, false>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
+            if (bil) shade_tile<true, false, true, false, true>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
+            else shade_tile<true, false, false, false, true>(A, tile, s_marg, s_hot, RecSink{nullptr, nullptr});
             __syncthreads();
             hot_flush(A, s_hot);
         }
