@@ -146,7 +146,7 @@ struct mcdi_scene_s {
     Node* nodes = nullptr;
     float4* tris = nullptr;
     QNode* qnodes = nullptr;
-    QNode* groups = nullptr;       // 4 * group_cap records
+    QNode* groups = nullptr;       // 4 * group_cap records, then group_cap visit orders
     size_t group_cap = 0;
     QFrame* frame = nullptr;
     DeviceSceneInfo* info = nullptr;
@@ -159,7 +159,8 @@ namespace {
 
 Scene scene_view(mcdi_scene sc) {
     return Scene{sc->nodes, sc->tris, sc->n_tris, sc->qnodes, sc->frame, sc->groups,
-                 (uint32_t)(sizeof(QNode) * 4 * sc->group_cap), sc->info};
+                 (uint32_t)(sizeof(QNode) * 4 * sc->group_cap),
+                 reinterpret_cast<const uint32_t*>(sc->groups + 4 * sc->group_cap), sc->info};
 }
 
 // work that reads the scene on stream u waits for the build (a no-op order
@@ -233,7 +234,7 @@ mcdi_status mcdi_build_scene(const float* verts, int64_t n_verts, const int32_t*
     sc->qnodes = (QNode*)sc->alloc.get(sizeof(QNode) * n_nodes, s);
     sc->frame = (QFrame*)sc->alloc.get(sizeof(QFrame), s);
     sc->group_cap = n_tris > 1 ? (size_t)n_tris : 1;
-    sc->groups = (QNode*)sc->alloc.get(sizeof(QNode) * 4 * sc->group_cap, s);
+    sc->groups = (QNode*)sc->alloc.get((sizeof(QNode) * 4 + sizeof(uint32_t)) * sc->group_cap, s);
     sc->info = (DeviceSceneInfo*)sc->alloc.get(sizeof(DeviceSceneInfo), s);
     if (!sc->nodes || !sc->tris || !sc->qnodes || !sc->frame || !sc->groups || !sc->info) {
         mcdi_destroy_scene(sc);

@@ -146,6 +146,7 @@ struct Tree {
     int32_t* first;    // [nt-1] sorted-primitive range
     int32_t* last;
     int32_t* flag;     // [nt-1]
+    int32_t* axis;     // [nt-1] the axis the node's Morton split separates its children on
     int32_t* cnt;      // [2nt-1] surviving nodes in the subtree
     float4* box;       // [2*(2nt-1)]
     // block fitting (blocks of kFitBlock sorted triangles)
@@ -195,6 +196,11 @@ __global__ __launch_bounds__(256) void radix_tree(const uint64_t* keys, int nt, 
     T.right[i] = R;
     T.first[i] = lo;
     T.last[i] = hi;
+    // the split is at the first bit the range's codes differ in, bit 63 - dnode
+    // (x, y, z interleaved from bit 62 down: bit b is x, y or z as b % 3 is 2,
+    // 1 or 0); the left child holds the codes with a 0 there, the lower side;
+    // equal codes (split by index) take x
+    T.axis[i] = dnode < 64 ? 2 - (63 - dnode) % 3 : 0;
     T.parent[L] = i;
     T.parent[R] = i;
     T.flag[i] = 0;
@@ -431,7 +437,7 @@ __device__ QNode quantise(const QFrame& F, const Node& nd) {
 }
 
 __global__ __launch_bounds__(256) void emit(int nt, Tree T, Node* out, QNode* qout, QFrame* frame,
-                                            DeviceSceneInfo* info, int32_t* gflag) {
+                                            DeviceSceneInfo* info, int32_t* gflag, int32_t* naxis) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= 2 * nt - 1) return;
     const bool is_prim = x >= nt - 1;
@@ -464,6 +470,7 @@ __global__ __launch_bounds__(256) void emit(int nt, Tree T, Node* out, QNode* qo
     nd.escape = idx + T.cnt[x];
     nd.payload = payload;
     out[idx] = nd;
+    naxis[idx] = is_prim ? 0 : T.axis[x];
     // the root's box (internal node 0) sets the frame, the same for every thread
     QFrame F;
     qframe_of(T.box[0], T.box[1], F);
@@ -484,15 +491,23 @@ __global__ void reorder(const float4* tmp, const uint32_t* vals, int64_t nt, flo
     out[3 * k + 2] = t[2];
 }
 
-// scene of 0 or 1 triangles
 // The 4-wide hierarchy of the shadow-ray traversal, collapsed from the binary
 // one: a wide node for the root and for every internal node N at even depth,
 // whose up to four children are N's children, a child that is internal being
-// replaced by its own two children.  A child record is the quantised box of
-// that binary node with w = its wide node's index (internal) or kQLeaf |
-// payload (leaf); unused slots hold an empty record (lo > hi: no ray hits it).
+// replaced by its own two children.  Slots 0-1 hold what N's first child
+// contributes (itself when it is a leaf, else its two children), slots 2-3
+// what the second contributes; a child record is the quantised box of that
+// binary node with w = its wide node's index (internal) or kQLeaf | payload
+// (leaf), and an unused slot holds an empty record (lo > hi: no ray hits it).
 // Wide nodes are numbered in the binary pre-order of their nodes (an
 // exclusive scan of the flags), so the wide hierarchy is in pre-order too.
+//
+// Beside each wide node, its visit order: for each of the eight octants of a
+// ray direction (bit a set where the component on axis a is negative), three
+// bits -- swap slots 0 and 1, swap slots 2 and 3, swap the two pairs -- that
+// put each binary split's child farther along the ray after the nearer one in
+// slot order.  The walk pushes hit children in slot order and pops the last
+// pushed, so it descends into the farther child first.
 __device__ __forceinline__ QNode empty_record() {
     QNode q;
     q.x = 0xFFFFFFFFu;   // lo.x = lo.y = 65535
@@ -509,32 +524,42 @@ __device__ __forceinline__ QNode child_record(const Node* out, const QNode* qout
 }
 
 __global__ __launch_bounds__(256) void wide_groups(const Node* out, const QNode* qout, const int32_t* gflag,
-                                                   const int32_t* gidx, int n_max, QNode* groups,
-                                                   DeviceSceneInfo* info) {
+                                                   const int32_t* gidx, const int32_t* naxis, int n_max,
+                                                   QNode* groups, uint32_t* gorder, DeviceSceneInfo* info) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n_max) return;
     const int n_nodes = out[0].escape;            // surviving binary nodes
     if (x >= n_nodes || !gflag[x]) return;
     const int self = gidx[x];
     QNode* g = groups + 4 * (size_t)self;
-    int k = 0;
+    for (int k = 0; k < 4; ++k) g[k] = empty_record();
+    uint32_t order = 0u;
     if (out[x].payload != 0) {                    // a root that is a leaf
-        g[k++] = child_record(out, qout, gidx, x);
+        g[0] = child_record(out, qout, gidx, x);
     } else {
         const int c[2] = {x + 1, out[x + 1].escape};
+        int sub_axis[2] = {-1, -1};
         for (int i = 0; i < 2; ++i) {
             const int y = c[i];
             if (y <= x || y >= n_nodes) continue;    // never for a valid tree
             if (out[y].payload != 0) {
-                g[k++] = child_record(out, qout, gidx, y);
+                g[2 * i] = child_record(out, qout, gidx, y);
             } else {
+                sub_axis[i] = naxis[y];
                 const int d[2] = {y + 1, out[y + 1].escape};
                 for (int j = 0; j < 2; ++j)
-                    if (d[j] > y && d[j] < n_nodes) g[k++] = child_record(out, qout, gidx, d[j]);
+                    if (d[j] > y && d[j] < n_nodes) g[2 * i + j] = child_record(out, qout, gidx, d[j]);
             }
         }
+        const int top = naxis[x];
+        for (int o = 0; o < 8; ++o) {
+            uint32_t f = ((o >> top) & 1) ? 4u : 0u;
+            if (sub_axis[0] >= 0 && ((o >> sub_axis[0]) & 1)) f |= 1u;
+            if (sub_axis[1] >= 0 && ((o >> sub_axis[1]) & 1)) f |= 2u;
+            order |= f << (3 * o);
+        }
     }
-    for (; k < 4; ++k) g[k] = empty_record();
+    gorder[self] = order;
     // the walk's termination rests on this: every internal child reference
     // lies past its parent and inside the node array (pre-order numbering);
     // a violation (never for a valid tree) sends the scene to the binary walk
@@ -546,7 +571,7 @@ __global__ __launch_bounds__(256) void wide_groups(const Node* out, const QNode*
 }
 
 __global__ void tiny_scene(const float4* tmp, int nt, Node* out, float4* tris_out, QNode* qout, QFrame* frame,
-                           DeviceSceneInfo* info, QNode* groups) {
+                           DeviceSceneInfo* info, QNode* groups, uint32_t* gorder) {
     Node nd;
     if (nt == 0) {
         for (int k = 0; k < 3; ++k) { nd.lo[k] = 0.0f; nd.hi[k] = 0.0f; }
@@ -571,6 +596,7 @@ __global__ void tiny_scene(const float4* tmp, int nt, Node* out, float4* tris_ou
     info->max_depth = 0;
     groups[0] = nt == 0 ? empty_record() : qout[0];
     for (int k = 1; k < 4; ++k) groups[k] = empty_record();
+    gorder[0] = 0u;
     info->n_groups = 1;
 }
 
@@ -651,7 +677,7 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
                  sz_base = al(sizeof(int32_t) * (size_t)(nb + 1)), sz_pre = al(sizeof(float4) * 2 * ntm),
                  sz_st = al(sizeof(float4) * 2 * (size_t)nb * (size_t)levels);
     const size_t sz_scan = al(scan_bytes);
-    const size_t total = sz_tmp + 2 * sz_keys + 2 * sz_vals + 9 * sz_i + sz_box + sz_cb + sz_sort + sz_part +
+    const size_t total = sz_tmp + 2 * sz_keys + 2 * sz_vals + 11 * sz_i + sz_box + sz_cb + sz_sort + sz_part +
                          2 * sz_nt + sz_base + 2 * sz_pre + sz_st + sz_scan;
     char* base = (char*)ta.alloc(ta.ctx, total, s);
     if (!base) { *oom = 1; return hipErrorOutOfMemory; }
@@ -669,6 +695,7 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     T.first = (int32_t*)take(sz_i);
     T.last = (int32_t*)take(sz_i);
     T.flag = (int32_t*)take(sz_i);
+    T.axis = (int32_t*)take(sz_i);
     T.cnt = (int32_t*)take(sz_i);
     T.box = (float4*)take(sz_box);
     int* cb = (int*)take(sz_cb);
@@ -682,7 +709,10 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     T.st = (float4*)take(sz_st);
     int32_t* gflag = (int32_t*)take(sz_i);
     int32_t* gidx = (int32_t*)take(sz_i);
+    int32_t* naxis = (int32_t*)take(sz_i);
     void* scan_tmp = take(sz_scan);
+    // the visit orders follow the wide nodes in the same allocation
+    uint32_t* gorder = reinterpret_cast<uint32_t*>(groups_out + 4 * ntm);
     T.nb = nb;
     T.levels = levels;
     hipError_t err = hipSuccess;
@@ -692,7 +722,7 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     }
     if (nt <= 1) {
         hipLaunchKernelGGL(tiny_scene, dim3(1), dim3(1), 0, s, tmp, nt, nodes_out, tris_out, qnodes_out, frame_out,
-                           info, groups_out);
+                           info, groups_out, gorder);
     } else {
         hipLaunchKernelGGL(morton, dim3(nblk(nt)), dim3(256), 0, s, tmp, (int64_t)nt, cb, keys, vals);
         err = rocprim::radix_sort_pairs(sort_tmp, sort_bytes, keys, keys2, vals, vals2, (size_t)nt, 0, 63, s);
@@ -707,14 +737,14 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
             hipLaunchKernelGGL(fit_top, dim3(nblk(nt - 1)), dim3(256), 0, s, nt, T);
             hipLaunchKernelGGL(fill_i32, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, gflag, (int64_t)(2 * nt - 1), 0);
             hipLaunchKernelGGL(emit, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nt, T, nodes_out, qnodes_out,
-                               frame_out, info, gflag);
+                               frame_out, info, gflag, naxis);
             hipLaunchKernelGGL(reorder, dim3(nblk(nt)), dim3(256), 0, s, tmp, vals2, (int64_t)nt, tris_out);
             err = rocprim::exclusive_scan(scan_tmp, scan_bytes, gflag, gidx, 0, (size_t)(2 * nt - 1),
                                           rocprim::plus<int32_t>(), s);
         }
         if (err == hipSuccess) {
             hipLaunchKernelGGL(wide_groups, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nodes_out, qnodes_out, gflag,
-                               gidx, 2 * nt - 1, groups_out, info);
+                               gidx, naxis, 2 * nt - 1, groups_out, gorder, info);
             hipLaunchKernelGGL(count_groups, dim3(1), dim3(1), 0, s, gflag, gidx, 2 * nt - 1, info);
             hipLaunchKernelGGL(leaf_area_sum, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, nodes_out, 2 * nt - 1, info);
             hipLaunchKernelGGL(choose_walk, dim3(1), dim3(1), 0, s, nodes_out, info);

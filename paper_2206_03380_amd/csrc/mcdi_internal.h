@@ -67,6 +67,7 @@ struct Scene {
     const QFrame* frame;
     const QNode* groups;  // [4 * capacity] wide nodes
     uint32_t group_bytes; // 64 * capacity (the bound of a buffer resource)
+    const uint32_t* gorder;   // [capacity] each wide node's visit orders (per ray octant)
     const DeviceSceneInfo* info;   // info->wide selects the traversal (read by the kernels)
 };
 
@@ -254,7 +255,8 @@ struct TempAlloc {
     void (*free)(void* ctx, void* p, hipStream_t s);
     void* ctx;
 };
-// groups_out: capacity for max(1, n_tris) wide nodes (>= internal nodes + 1)
+// groups_out: capacity for max(1, n_tris) wide nodes (>= internal nodes + 1),
+// followed by as many 32-bit visit orders
 hipError_t build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                      Node* nodes_out, float4* tris_out, QNode* qnodes_out, QFrame* frame_out, QNode* groups_out,
                      DeviceSceneInfo* info, const TempAlloc& ta, hipStream_t s, int* oom);

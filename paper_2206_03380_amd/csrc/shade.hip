@@ -575,12 +575,15 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
         (void*)sc.qnodes, (short)0, (int)((uint32_t)n_total * 16u), kBufferWord3);
     const __amdgpu_buffer_rsrc_t grs = __builtin_amdgcn_make_buffer_rsrc(
         (void*)sc.groups, (short)0, (int)sc.group_bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t ors = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)sc.gorder, (short)0, (int)(sc.group_bytes / 16u), kBufferWord3);
     uint32_t* stk = s_stack + threadIdx.x;
     const int lane = __lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool active = false, exhausted = false;
     Ray ray;
     QRay qray;
+    uint32_t oct3 = 0u;    // 3 x the ray's octant (bit a: negative on axis a)
     // wide: node = a wide node, a leaf reference waiting for a pending slot,
     // or kWideNone (done); binary (after a stack overflow): a node index, done
     // at n_total
@@ -619,6 +622,7 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                     const float4 o = A.origins[base_pix + (tag & 255u)];
                     ray = make_ray(f3(o.x, o.y, o.z), f3(rr.x, rr.y, rr.z));
                     qray = make_qray(ray, F);
+                    oct3 = 3u * ((rr.x < 0.0f ? 1u : 0u) | (rr.y < 0.0f ? 2u : 0u) | (rr.z < 0.0f ? 4u : 0u));
                     wide = true;
                     node = 0u;
                     sp = 0;
@@ -652,12 +656,32 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                         else p1 = payload;
                         node = sp > 0 ? stk[--sp * kBlock] : kWideNone;
                     } else {
-                        // one wide node: four child records from one 64-byte segment
+                        // one wide node: four child records from one 64-byte
+                        // segment, and its visit order for the ray's octant
                         const uint32_t off = node * 64u;
                         uint4 c[4];
 #pragma unroll
                         for (int k = 0; k < 4; ++k)
                             c[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(grs, off + 16u * k, 0, 0));
+                        const uint32_t f = (__builtin_amdgcn_raw_buffer_load_b32(ors, node * 4u, 0, 0) >> oct3) & 7u;
+                        uint32_t w[4];
+                        bool h[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (COUNT && c[k].w != kQLeaf) ++c_box;
+                            h[k] = qbox_hit(qray, c[k]);
+                            w[k] = c[k].w;
+                        }
+                        // farther child of each split after the nearer one
+                        // (the pushed-last is popped first): within each pair,
+                        // then the pairs
+                        const bool s0 = (f & 1u) != 0u, s1 = (f & 2u) != 0u, sT = (f & 4u) != 0u;
+                        const uint32_t a0 = s0 ? w[1] : w[0], a1 = s0 ? w[0] : w[1];
+                        const uint32_t a2 = s1 ? w[3] : w[2], a3 = s1 ? w[2] : w[3];
+                        const bool g0 = s0 ? h[1] : h[0], g1 = s0 ? h[0] : h[1];
+                        const bool g2 = s1 ? h[3] : h[2], g3 = s1 ? h[2] : h[3];
+                        const uint32_t ws[4] = {sT ? a2 : a0, sT ? a3 : a1, sT ? a0 : a2, sT ? a1 : a3};
+                        const bool hs[4] = {sT ? g2 : g0, sT ? g3 : g1, sT ? g0 : g2, sT ? g1 : g3};
                         // every hit child is pushed: each record is stored at
                         // the first free row and the row is kept if the child
                         // was hit (rows up to kStack + 3 exist, so a visit
@@ -668,10 +692,8 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                         uint32_t* at = stk + sp * kBlock;
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            if (COUNT && c[k].w != kQLeaf) ++c_box;
-                            const bool h = qbox_hit(qray, c[k]);
-                            *at = c[k].w;
-                            at += h ? kBlock : 0;
+                            *at = ws[k];
+                            at += hs[k] ? kBlock : 0;
                         }
                         sp = (int)((at - stk) / kBlock);
                         const bool over = sp > kStack;
