@@ -220,7 +220,8 @@ def measure(args, M, w, steps, warmup):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    out = M.shade_fwd(scene, envh, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps)
+    live = torch.empty((M.hit_words(w.spp), gb.n), dtype=torch.int32, device=dev)
+    out = M.shade_fwd(scene, envh, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps, live=live)
     hb = out[2]
     g_cd = torch.randn((3, gb.n), device=dev) * mask / n_valid
     g_cs = torch.randn((3, gb.n), device=dev) * mask / n_valid
@@ -228,9 +229,9 @@ def measure(args, M, w, steps, warmup):
     bwd_out = (torch.empty_like(g_cd), torch.empty_like(g_cd), torch.empty_like(g_cd))
     reps = max(3, min(args.kernel_reps, int(2000 / max(ms, 1.0))))
     fwd_ms = timed(lambda: M.shade_fwd(scene, envh, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps,
-                                       out=out[:3]), reps)
+                                       out=out[:3], live=live), reps)
     bwd_ms = timed(lambda: M.shade_bwd(scene, envh, gb, w.spp, g_cd, g_cs, hitbits=hb, seed=w.seed, tau=w.tau,
-                                       ray_eps=w.ray_eps, g_env=g_env, out=bwd_out), reps)
+                                       ray_eps=w.ray_eps, g_env=g_env, out=bwd_out, live=live), reps)
     bvh_ms = timed(lambda: M.Scene(verts, tris), max(3, reps // 2))
     cdf_ms = timed(lambda: M.Env(env_p), max(3, reps // 2))
 
@@ -253,7 +254,7 @@ def measure(args, M, w, steps, warmup):
                                      "tri": stats["tri_tests"] / max(stats["tri_slots"], 1)},
                 "box_tests_per_lane_step": stats["box_tests"] / max(stats["box_lanes"], 1)}
     # ---- roofline of the adjoint kernel (shade_kernel<true>) ----
-    adj_units = adjoint_units(hb, stats, w)
+    adj_units = adjoint_units(hb, live, stats, w)
     adj_ops = (ADJ_OPS_PHILOX * adj_units["pairs_drawn"] + ADJ_OPS_LIGHT * adj_units["light_draws"] +
                ADJ_OPS_BSDF * adj_units["bsdf_draws"] + ADJ_OPS_PER_EVAL * adj_units["evaluated_directions"])
     adj_a = adj_ops / (adj_ms * 1e-3) if adj_ms > 0 else 0.0
@@ -277,43 +278,42 @@ def measure(args, M, w, steps, warmup):
 
 
 # Adjoint kernel (shade_kernel<true>), VALU lane operations of the method.
-# Per drawn sample pair of a valid pixel: two Philox4x32-10 blocks (ten
-# rounds of two 32x32->64 products, two xors and the key schedule: 160); per
+# Per drawn sample pair of a valid pixel: the first Philox4x32-10 block (ten
+# rounds of two 32x32->64 products, two xors and the key schedule: 80).  Per
 # light draw (marginal and guided conditional searches, in-texel offsets, two
-# sincospi, the direction and its density: 50); per BSDF draw (lobe choice,
-# cosine or visible-normal warp, world frame, normalisation, two atan2 for
-# the texel and its density: 100).  Per evaluated direction: the balance heuristic and the BSDF (half vector, D,
+# sincospi, the direction and its density: 50).  Per BSDF draw (the second
+# Philox block: 80; lobe choice, cosine or visible-normal warp, world frame,
+# normalisation, two atan2 for the texel and its density: 100).  Per
+# evaluated direction: the balance heuristic and the BSDF (half vector, D,
 # both Smith Lambdas, G2, Schlick F, three densities: 60) and the
 # derivatives (D and Lambda in alpha, S in alpha, n.v, n.l and n.h, the
 # normal gradient in the tangent frame, kd/m/r terms, the probe coefficient
 # and its scatter: 85) = 145.
-ADJ_OPS_PHILOX = 160
+ADJ_OPS_PHILOX = 80
 ADJ_OPS_LIGHT = 50
-ADJ_OPS_BSDF = 100
+ADJ_OPS_BSDF = 180
 ADJ_OPS_PER_EVAL = 145
 
 
-def adjoint_units(hb, stats, w):
-    """The adjoint's units of work.  With tau = 1 a sample whose ray was
-    blocked adds nothing, and the kernel skips it before drawing it (its hit
-    bit is set); a sample pair with both rays blocked skips its Philox
-    blocks.  Counted from the step's hit bits ([words][N] u32, bit 2s the
-    light sample of sample s, bit 2s + 1 its BSDF sample).  Otherwise every
-    sample of a valid pixel is drawn and every traced direction evaluated."""
+def adjoint_units(hb, live, stats, w):
+    """The adjoint's units of work, counted from the step's hit bits and
+    live bits ([words][N] u32 each, bit 2s the light sample of sample s,
+    bit 2s + 1 its BSDF sample).  Given the live bits, the adjoint draws and
+    differentiates the live samples -- with tau = 1 only those not blocked
+    (a blocked one adds nothing) -- and a sample pair draws its first Philox
+    block once.  Without tracing every sample of a valid pixel is drawn."""
     import numpy as np
     pairs = stats["valid_pixels"] * w.spp
-    if w.tau != 1.0:
+    if w.tau == 0.0 or live is None:
         return {"pairs_drawn": pairs, "light_draws": pairs, "bsdf_draws": pairs,
                 "evaluated_directions": stats["rays_traced"]}
-    bits = hb.cpu().numpy().view(np.uint32)
+    need = live.cpu().numpy().view(np.uint32)
+    if w.tau == 1.0:
+        need = need & ~hb.cpu().numpy().view(np.uint32)
     even = np.uint32(0x55555555)
-    light, bsdf = bits & even, (bits >> np.uint32(1)) & even
-    both = int(np.bitwise_count(light & bsdf).sum())
-    light_only = int(np.bitwise_count(light & ~bsdf).sum())
-    bsdf_only = int(np.bitwise_count(bsdf & ~light).sum())
-    drawn = pairs - both
-    return {"pairs_drawn": drawn, "light_draws": drawn - light_only, "bsdf_draws": drawn - bsdf_only,
-            "evaluated_directions": stats["rays_traced"] - stats["rays_hit"]}
+    light, bsdf = need & even, (need >> np.uint32(1)) & even
+    return {"pairs_drawn": int(np.bitwise_count(light | bsdf).sum()), "light_draws": int(np.bitwise_count(light).sum()),
+            "bsdf_draws": int(np.bitwise_count(bsdf).sum()), "evaluated_directions": int(np.bitwise_count(need).sum())}
 
 
 # per-unit VALU lane-operation counts of the traversal: slab test of one
@@ -370,11 +370,12 @@ def sampling_study(args, M, gb, timed, seeds=4):
     g_cs = torch.randn((3, n), device=gb.kd.device) * m / max(int(m.sum()), 1)
     bwd = {}
     for name, f in (("nearest", 0), ("bilinear", M.FLAG_BILINEAR)):
-        hb = M.shade_fwd(sc, envh, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps, flags=f)[2]
+        live = torch.empty((M.hit_words(w.spp), n), dtype=torch.int32, device=gb.kd.device)
+        hb = M.shade_fwd(sc, envh, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps, flags=f, live=live)[2]
         g_env = torch.zeros_like(envh.env)
         bo = tuple(torch.empty_like(g_cd) for _ in range(3))
         bwd[name] = timed(lambda: M.shade_bwd(sc, envh, gb, w.spp, g_cd, g_cs, hitbits=hb, seed=w.seed, tau=w.tau,
-                                              ray_eps=w.ray_eps, flags=f, g_env=g_env, out=bo),
+                                              ray_eps=w.ray_eps, flags=f, g_env=g_env, out=bo, live=live),
                           max(3, args.kernel_reps // 2))
     return {"spp": w.spp, "seeds": seeds, "techniques": res, "bwd_ms": bwd}
 

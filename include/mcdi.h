@@ -215,6 +215,16 @@ typedef struct {
     uint32_t* decisions;    /* device [N][spp][3] when MCDI_FLAG_DUMP ([N][spp][9] with
                                MCDI_FLAG_DUMP_DIRS: words 3-5 and 6-8 the light and BSDF
                                samples' world directions), else NULL */
+    uint32_t* live;         /* optional device [ceil(2 spp / 32)][N] u32 in the hit bits' layout
+                               (bit 2s + t of word (2s + t) / 32: technique t of sample s; t = 0
+                               light, 1 BSDF): the samples drawn with a density above the horizon,
+                               which the estimator evaluates.  mcdi_shade_fwd writes it (when
+                               tau != 0); mcdi_shade_bwd, given it with the same forward's hit
+                               bits, draws and differentiates only those samples instead of
+                               drawing every sample pair to find them -- the same gradients bit
+                               for bit, less work where most samples are blocked or below the
+                               horizon.  NULL: the forward keeps its own, the adjoint draws.
+                               Ignored when tau is 0 and by the other calls. */
 } mcdi_params;
 
 /* Device-side counters, accumulated (+=) by every call that receives them.

@@ -192,17 +192,19 @@ def read_stats(t):
             "box_lanes": v[9]}
 
 
-def _params(spp, seed, tau, ray_eps, flags, decisions):
+def _params(spp, seed, tau, ray_eps, flags, decisions, live=None):
     return L.Params(int(spp), int(flags), int(seed), float(tau), float(ray_eps),
-                    decisions.data_ptr() if decisions is not None else None)
+                    decisions.data_ptr() if decisions is not None else None,
+                    live.data_ptr() if live is not None else None)
 
 
 def shade_fwd(scene, env, gb, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0, hitbits=True, decisions=False,
-              stats=None, out=None, stream=None):
+              stats=None, out=None, stream=None, live=None):
     """Forward pass.  Returns (c_d [3,N], c_s [3,N], hitbits [words,N] or None,
     decisions [N,spp,3] or None).  decisions="dirs": records of 9 words
     [N,spp,9], the last six the light and BSDF samples' world directions
-    (float32 bits)."""
+    (float32 bits).  live: an int32 [words,N] tensor the forward fills with
+    the samples it evaluates, for shade_bwd (with tau != 0)."""
     n = gb.n
     dev = gb.pos.device
     if out is None:
@@ -216,8 +218,10 @@ def shade_fwd(scene, env, gb, spp, seed=0, tau=1.0, ray_eps=1e-3, flags=0, hitbi
         dirs = decisions == "dirs"
         dec = torch.empty((n, spp, 9 if dirs else 3), dtype=torch.int32, device=dev)
         flags |= FLAG_DUMP | (FLAG_DUMP_DIRS if dirs else 0)
+    if live is not None:
+        _need(live, torch.int32, (hit_words(spp), n), "live")
     gs = gb.struct()
-    prm = _params(spp, seed, tau, ray_eps, flags, dec)
+    prm = _params(spp, seed, tau, ray_eps, flags, dec, live)
     L.check(L.lib().mcdi_shade_fwd(scene.handle, env.handle, C.byref(gs), C.byref(prm), _ptr(c_d), _ptr(c_s),
                                    _ptr(hb), _ptr(stats), _stream(stream)))
     return c_d, c_s, hb, dec
@@ -240,9 +244,11 @@ def shade_fwd_frozen(scene, env_s, gb_s, env_e, gb_e, spp, seed=0, tau=1.0, ray_
 
 
 def shade_bwd(scene, env, gb, spp, g_cd, g_cs, hitbits=None, seed=0, tau=1.0, ray_eps=1e-3, flags=0,
-              g_env=None, stats=None, out=None, stream=None):
+              g_env=None, stats=None, out=None, stream=None, live=None):
     """Backward pass.  Returns (g_kd, g_korm, g_nrm, g_env); g_env is
-    accumulated into if given, else a zeroed [H,W,3] tensor is created."""
+    accumulated into if given, else a zeroed [H,W,3] tensor is created.
+    live: the forward's live samples (with its hit bits): the adjoint then
+    draws only those."""
     n = gb.n
     dev = gb.pos.device
     _need(g_cd, torch.float32, (3, n), "g_cd")
@@ -255,8 +261,10 @@ def shade_bwd(scene, env, gb, spp, g_cd, g_cs, hitbits=None, seed=0, tau=1.0, ra
         g_kd, g_korm, g_nrm = out
     if g_env is None:
         g_env = torch.zeros((env.H, env.W, 3), dtype=torch.float32, device=dev)
+    if live is not None:
+        _need(live, torch.int32, (hit_words(spp), n), "live")
     gs = gb.struct()
-    prm = _params(spp, seed, tau, ray_eps, flags, None)
+    prm = _params(spp, seed, tau, ray_eps, flags, None, live)
     L.check(L.lib().mcdi_shade_bwd(scene.handle, env.handle, C.byref(gs), C.byref(prm), _ptr(g_cd), _ptr(g_cs),
                                    _ptr(hitbits), _ptr(g_kd), _ptr(g_korm), _ptr(g_nrm), _ptr(g_env),
                                    _ptr(stats), _stream(stream)))

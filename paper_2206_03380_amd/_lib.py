@@ -44,7 +44,7 @@ class GBuffer(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("spp", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64), ("tau", C.c_float),
-                ("ray_eps", C.c_float), ("decisions", vp)]
+                ("ray_eps", C.c_float), ("decisions", vp), ("live", vp)]
 
 
 class ServerConfig(C.Structure):

@@ -44,13 +44,16 @@ class MCDIShade(torch.autograd.Function):
         c_s = torch.empty((3, n), dtype=torch.float32, device=dev)
         need_bits = tau != 0.0 and any(ctx.needs_input_grad[:4]) and bwd_seed is None
         hb = torch.empty((hit_words(spp), n), dtype=torch.int32, device=dev) if need_bits else None
+        # the live samples go with the hit bits: the adjoint draws only those
+        live = torch.empty_like(hb) if need_bits else None
         gs = gbuf.struct(kd=kd, korm=korm, nrm=nrm)
-        prm = _params(spp, seed, tau, ray_eps, flags, None)
+        prm = _params(spp, seed, tau, ray_eps, flags, None, live)
         L.check(L.lib().mcdi_shade_fwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(c_d),
                                        _ptr(c_s), _ptr(hb), None, _stream()))
         vis = verts is not None and edges is not None and edge_spp > 0
-        ctx.save_for_backward(kd, korm, nrm, hb if hb is not None else torch.empty(0, device=dev),
-                              verts if vis else torch.empty(0, device=dev))
+        empty = torch.empty(0, device=dev)
+        ctx.save_for_backward(kd, korm, nrm, hb if hb is not None else empty, live if live is not None else empty,
+                              verts if vis else empty)
         ctx.meta = (scene, env_tables, gbuf, spp, seed if bwd_seed is None else bwd_seed, tau, ray_eps,
                     hb is not None, flags & ~(L.FLAG_DUMP | L.FLAG_TIME_TRACE))
         ctx.vis = (edges, edge_spp, sharp_gain) if vis else None
@@ -60,7 +63,7 @@ class MCDIShade(torch.autograd.Function):
     def backward(ctx, g_cd, g_cs):
         from . import _ptr, _stream, _params
         import ctypes as C
-        kd, korm, nrm, hb, verts = ctx.saved_tensors
+        kd, korm, nrm, hb, live, verts = ctx.saved_tensors
         scene, env_tables, gbuf, spp, seed, tau, ray_eps, has_bits, flags = ctx.meta
         n = gbuf.n
         dev = kd.device
@@ -72,7 +75,7 @@ class MCDIShade(torch.autograd.Function):
         g_env = torch.zeros((env_tables.H, env_tables.W, 3), dtype=torch.float32, device=dev)
         if any(ctx.needs_input_grad[:4]):
             gs = gbuf.struct(kd=kd, korm=korm, nrm=nrm)
-            prm = _params(spp, seed, tau, ray_eps, flags, None)
+            prm = _params(spp, seed, tau, ray_eps, flags, None, live if has_bits else None)
             L.check(L.lib().mcdi_shade_bwd(scene.handle, env_tables.handle, C.byref(gs), C.byref(prm), _ptr(g_cd),
                                            _ptr(g_cs), _ptr(hb) if has_bits else None, _ptr(g_kd), _ptr(g_korm),
                                            _ptr(g_nrm), _ptr(g_env), None, _stream()))

@@ -431,9 +431,11 @@ static mcdi_status trace_pipeline(const char* who, mcdi_scene sc, ShadeArgs& a, 
     const size_t sz_cnt = al(sizeof(int32_t) * (size_t)blocks);
     const size_t sz_org = al(sizeof(float4) * (size_t)n);
     const size_t sz_bits = hitbits ? 0 : al(sizeof(uint32_t) * words * (size_t)n);
+    // live samples (with tracing): the shading then walks only those
+    const size_t sz_live = (a.tau != 0.0f && !a.live) ? al(sizeof(uint32_t) * words * (size_t)n) : 0;
     ws.alloc = &sc->alloc;
     ws.s = s;
-    ws.base = sc->alloc.get(sz_rays + 2 * sz_cnt + sz_org + sz_bits, s);
+    ws.base = sc->alloc.get(sz_rays + 2 * sz_cnt + sz_org + sz_bits + sz_live, s);
     if (!ws.base) return fail(MCDI_E_OOM, "%s: workspace allocation failed", who);
     char* p = (char*)ws.base;
     a.rays = sz_rays ? (float4*)p : nullptr;
@@ -445,6 +447,8 @@ static mcdi_status trace_pipeline(const char* who, mcdi_scene sc, ShadeArgs& a, 
     a.origins = (float4*)p;
     p += sz_org;
     uint32_t* bits = hitbits ? hitbits : (uint32_t*)p;
+    p += sz_bits;
+    if (sz_live) a.live = (uint32_t*)p;
     // the generator needs a ray region even when nothing is traced
     ShadeArgs g = a;
     if (!g.rays) g.tau = 0.0f;
@@ -473,6 +477,7 @@ mcdi_status mcdi_shade_fwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, co
     mcdi_status st = fill_common("mcdi_shade_fwd", sc, ev, g, p, a);
     if (st != MCDI_OK) return st;
     if (!c_d || !c_s) return fail(MCDI_E_INVALID, "mcdi_shade_fwd: NULL c_d/c_s");
+    if (p->tau != 0.0f) a.live = p->live;   // NULL: the workspace keeps them
     hipStream_t s = (hipStream_t)stream;
     a.c_d = c_d;
     a.c_s = c_s;
@@ -546,6 +551,7 @@ mcdi_status mcdi_shade_bwd(mcdi_scene sc, mcdi_env ev, const mcdi_gbuffer* g, co
     a.g_env = g_env;
     a.stats = stats;
     Workspace ws;
+    if (p->tau != 0.0f && hitbits) a.live = p->live;   // a re-trace keeps its own
     if (hitbits) {
         a.hitbits_in = hitbits;
     } else {

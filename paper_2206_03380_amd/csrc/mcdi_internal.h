@@ -122,6 +122,12 @@ struct ShadeArgs {
     const float* g_cd;
     const float* g_cs;
     const uint32_t* hitbits_in;
+    // live samples, [words][N] in the hit bits' layout: bit 2s + t set where
+    // technique t's sample s was drawn with a density and above the horizon
+    // (the samples the estimator evaluates).  Ray generation writes it when
+    // tracing; the shading passes, given it, walk only those samples.  NULL:
+    // not kept.
+    uint32_t* live;
     float* g_kd;
     float* g_korm;
     float* g_nrm;

@@ -13,6 +13,14 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+// Multiply-adds are fused only within one source expression, never across
+// statements, so a sample's arithmetic rounds the same way in every loop that
+// evaluates it (the staged forward's walk over live samples, the decision
+// dump's full walk, the serving kernel's lockstep walk) and their results
+// agree bit for bit.  (Set before the shared headers, whose inline functions
+// are compiled here; the triangle test turns contraction off itself.)
+#pragma clang fp contract(on)
+
 #include "device_common.h"
 #include "shade_common.h"
 
@@ -363,6 +371,7 @@ __device__ __forceinline__ void gen_tile(const ShadeArgs& A, int64_t tile, float
     const int lane = __lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t c_rays = 0, c_culled = 0;
+    uint32_t lw = 0u;   // live bits of the current word
     for (int s = 0; s < spp; ++s) {
         uint4 r0 = make_uint4(0, 0, 0, 0), r1 = r0;
         if (go) {
@@ -389,8 +398,13 @@ __device__ __forceinline__ void gen_tile(const ShadeArgs& A, int64_t tile, float
                 const int slot = 2 * s + tech;
                 const uint32_t tag = (uint32_t)threadIdx.x | ((uint32_t)slot << 8);
                 region[base + (int)__popcll(bal & lt)] = make_float4(S.w.x, S.w.y, S.w.z, __uint_as_float(tag));
+                lw |= 1u << (slot & 31);
                 ++c_rays;
             }
+        }
+        if (A.live && active && ((s & 15) == 15 || s == spp - 1)) {
+            A.live[(s >> 4) * N + pix] = lw;
+            lw = 0u;
         }
     }
     if (COUNT) {
@@ -861,69 +875,103 @@ __device__ __forceinline__ void shade_tile(const ShadeArgs& A, int64_t tile, con
     // spp.  The decision dump draws every sample and skips only the
     // evaluation.
     const bool skip_blocked = !DUMP && A.tau == 1.0f;
-    for (int s0 = 0; s0 < spp; s0 += 16) {
-        const uint32_t bits = A.hitbits_in[(s0 >> 4) * N + pix];   // pairs s0 .. s0 + 15
-        uint32_t todo = (spp - s0 >= 16) ? 0xFFFFu : (1u << (spp - s0)) - 1u;
-        if (skip_blocked && !LOCKSTEP) todo &= ~even_bits(bits & (bits >> 1));
-        while (todo) {
-            const int s = s0 + __ffs(todo) - 1;
-            todo &= todo - 1u;
-            if (LOCKSTEP && skip_blocked && ((bits >> ((2 * s) & 31)) & 3u) == 3u) continue;
-            const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
-            const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
-            uint32_t rec0 = kNone, rec1 = kNone;
-            uint32_t rec2 = kDecValid | (P.nov_pos ? kDecNovPos : 0u);
-            float3 dir[2] = {f3(__uint_as_float(kNanBits), 0.0f, 0.0f), f3(__uint_as_float(kNanBits), 0.0f, 0.0f)};
-            for (int tech = 0; tech < 2; ++tech) {
-                if (skip_blocked && ((bits >> ((2 * s + tech) & 31)) & 1u)) continue;
-                Sample S;
-                if (tech == 0) {
-                    if (!light_on) continue;
-                    const bool has = draw_light<BWD ? kDrawBwd : kDrawFwd>(A, P, s_marg, r0, S);
-                    rec0 = (uint32_t)S.texel;
-                    if (DUMP) dir[0] = S.w;
-                    if (!has) { rec2 |= kDecLCull; continue; }
-                } else {
-                    if (P.bsdf_w == 0.0f) continue;
-                    if (draw_bsdf(P, r0, r1, S)) rec2 |= kDecLobeCos;
-                    if (DUMP) dir[1] = S.w;
+    if (!DUMP && !FROZEN && !LOCKSTEP && A.live) {
+        // the live bits name the samples the estimator evaluates: a lane
+        // draws and evaluates only those (and with tau = 1 only those not
+        // blocked), pair by pair in the same increasing (sample, technique)
+        // order; the two samples of a pair share the first Philox block
+        for (int s0 = 0; s0 < spp; s0 += 16) {
+            const uint32_t bits = A.hitbits_in[(s0 >> 4) * N + pix];
+            uint32_t need = A.live[(s0 >> 4) * N + pix];
+            if (skip_blocked) need &= ~bits;
+            uint32_t todo = even_bits(need | (need >> 1));
+            while (todo) {
+                const int k = __ffs(todo) - 1;
+                todo &= todo - 1u;
+                const int s = s0 + k;
+                const uint32_t pair = need >> (2 * k), hit = bits >> (2 * k);
+                const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
+                if (pair & 1u) {
+                    Sample S;
+                    draw_light<BWD ? kDrawBwd : kDrawFwd>(A, P, s_marg, r0, S);
+                    const float Hv = (hit & 1u) ? 1.0f - A.tau : 1.0f;
+                    eval_sample<BWD, BIL>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
                 }
-                if (!(S.wl.z > 0.0f)) { rec2 |= tech ? kDecBCull : kDecLCull; continue; }
-                if (tech == 1) {
+                if (pair & 2u) {
+                    Sample S;
+                    const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
+                    draw_bsdf(P, r0, r1, S);
                     bsdf_texel<!BWD>(A, light_on, S);
-                    rec1 = (uint32_t)S.texel;
-                }
-                float Hv = 1.0f;
-                if (trace) {
-                    const int bitpos = 2 * s + tech;
-                    rec2 |= tech ? kDecBTraced : kDecLTraced;
-                    if ((bits >> (bitpos & 31)) & 1u) {
-                        Hv = 1.0f - A.tau;
-                        rec2 |= tech ? kDecBHit : kDecLHit;
-                    }
-                }
-                // H = 0: no incident radiance, whatever the probe holds there
-                if (Hv == 0.0f) continue;
-                if (FROZEN) {
-                    // the sample's direction in the evaluation frame (the
-                    // sampled local direction itself where the frame is the same)
-                    Sample Se = S;
-                    if (!(Pe.n.x == P.n.x && Pe.n.y == P.n.y && Pe.n.z == P.n.z))
-                        Se.wl = f3(dot(S.w, Pe.t), dot(S.w, Pe.b), dot(S.w, Pe.n));
-                    eval_sample<BWD, BIL, true>(A, Pe, Se, Hv, invspp, fa, ba, Ud, Us, s_hot, rs, mis_density(P, S));
-                } else {
+                    const float Hv = (hit & 2u) ? 1.0f - A.tau : 1.0f;
                     eval_sample<BWD, BIL>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
                 }
             }
-            if (DUMP) {
-                const int st = dump_stride(A);
-                uint32_t* d = A.decisions + ((size_t)pix * spp + s) * st;
-                d[0] = rec0; d[1] = rec1; d[2] = rec2;
-                if (st == 9) {
-                    for (int t = 0; t < 2; ++t) {
-                        d[3 + 3 * t] = __float_as_uint(dir[t].x);
-                        d[4 + 3 * t] = __float_as_uint(dir[t].y);
-                        d[5 + 3 * t] = __float_as_uint(dir[t].z);
+        }
+    } else {
+        for (int s0 = 0; s0 < spp; s0 += 16) {
+            const uint32_t bits = A.hitbits_in[(s0 >> 4) * N + pix];   // pairs s0 .. s0 + 15
+            uint32_t todo = (spp - s0 >= 16) ? 0xFFFFu : (1u << (spp - s0)) - 1u;
+            if (skip_blocked && !LOCKSTEP) todo &= ~even_bits(bits & (bits >> 1));
+            while (todo) {
+                const int s = s0 + __ffs(todo) - 1;
+                todo &= todo - 1u;
+                if (LOCKSTEP && skip_blocked && ((bits >> ((2 * s) & 31)) & 3u) == 3u) continue;
+                const uint4 r0 = philox10(make_uint4(piv, vid, (uint32_t)s, 0u), k0, k1);
+                const uint4 r1 = philox10(make_uint4(piv, vid, (uint32_t)s, 1u), k0, k1);
+                uint32_t rec0 = kNone, rec1 = kNone;
+                uint32_t rec2 = kDecValid | (P.nov_pos ? kDecNovPos : 0u);
+                float3 dir[2] = {f3(__uint_as_float(kNanBits), 0.0f, 0.0f), f3(__uint_as_float(kNanBits), 0.0f, 0.0f)};
+                for (int tech = 0; tech < 2; ++tech) {
+                    if (skip_blocked && ((bits >> ((2 * s + tech) & 31)) & 1u)) continue;
+                    Sample S;
+                    if (tech == 0) {
+                        if (!light_on) continue;
+                        const bool has = draw_light<BWD ? kDrawBwd : kDrawFwd>(A, P, s_marg, r0, S);
+                        rec0 = (uint32_t)S.texel;
+                        if (DUMP) dir[0] = S.w;
+                        if (!has) { rec2 |= kDecLCull; continue; }
+                    } else {
+                        if (P.bsdf_w == 0.0f) continue;
+                        if (draw_bsdf(P, r0, r1, S)) rec2 |= kDecLobeCos;
+                        if (DUMP) dir[1] = S.w;
+                    }
+                    if (!(S.wl.z > 0.0f)) { rec2 |= tech ? kDecBCull : kDecLCull; continue; }
+                    if (tech == 1) {
+                        bsdf_texel<!BWD>(A, light_on, S);
+                        rec1 = (uint32_t)S.texel;
+                    }
+                    float Hv = 1.0f;
+                    if (trace) {
+                        const int bitpos = 2 * s + tech;
+                        rec2 |= tech ? kDecBTraced : kDecLTraced;
+                        if ((bits >> (bitpos & 31)) & 1u) {
+                            Hv = 1.0f - A.tau;
+                            rec2 |= tech ? kDecBHit : kDecLHit;
+                        }
+                    }
+                    // H = 0: no incident radiance, whatever the probe holds there
+                    if (Hv == 0.0f) continue;
+                    if (FROZEN) {
+                        // the sample's direction in the evaluation frame (the
+                        // sampled local direction itself where the frame is the same)
+                        Sample Se = S;
+                        if (!(Pe.n.x == P.n.x && Pe.n.y == P.n.y && Pe.n.z == P.n.z))
+                            Se.wl = f3(dot(S.w, Pe.t), dot(S.w, Pe.b), dot(S.w, Pe.n));
+                        eval_sample<BWD, BIL, true>(A, Pe, Se, Hv, invspp, fa, ba, Ud, Us, s_hot, rs, mis_density(P, S));
+                    } else {
+                        eval_sample<BWD, BIL>(A, P, S, Hv, invspp, fa, ba, Ud, Us, s_hot, rs);
+                    }
+                }
+                if (DUMP) {
+                    const int st = dump_stride(A);
+                    uint32_t* d = A.decisions + ((size_t)pix * spp + s) * st;
+                    d[0] = rec0; d[1] = rec1; d[2] = rec2;
+                    if (st == 9) {
+                        for (int t = 0; t < 2; ++t) {
+                            d[3 + 3 * t] = __float_as_uint(dir[t].x);
+                            d[4 + 3 * t] = __float_as_uint(dir[t].y);
+                            d[5 + 3 * t] = __float_as_uint(dir[t].z);
+                        }
                     }
                 }
             }

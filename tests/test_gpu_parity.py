@@ -346,6 +346,35 @@ def test_fwd_skip_blocked_equals_dump(tau):
         assert np.array_equal(a[key], b[key]), key
 
 
+@pytest.mark.parametrize("tau", [1.0, 0.5])
+@pytest.mark.parametrize("bil", [False, True])
+def test_bwd_live_bits_equal(tau, bil):
+    """Given the forward's live samples (the ones it evaluates), the adjoint
+    draws and differentiates only those; its per-pixel gradients equal those
+    of the adjoint that draws every sample pair, bit for bit, and its probe
+    gradient agrees to the float-atomic order of the scatter."""
+    import torch
+    import paper_2206_03380_amd as M
+    w = make_workload("tiny")
+    w.tau = tau
+    flags = M.FLAG_BILINEAR if bil else 0
+    _, (scene, env, gb, _) = gpu_forward(w, dump=False, flags=flags)
+    live = torch.full((M.hit_words(w.spp), gb.n), -1, dtype=torch.int32, device="cuda")
+    c_d, c_s, hb, _ = M.shade_fwd(scene, env, gb, w.spp, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps, flags=flags,
+                                  live=live)
+    lv = to_np(live).view(np.uint32)
+    assert lv.any() and not (lv == 0xFFFFFFFF).all()
+    ud, us = upstream_grads(w)
+    tud, tus = torch.from_numpy(ud).cuda(), torch.from_numpy(us).cuda()
+    kw = dict(hitbits=hb, seed=w.seed, tau=w.tau, ray_eps=w.ray_eps, flags=flags)
+    a = M.shade_bwd(scene, env, gb, w.spp, tud, tus, **kw)
+    b = M.shade_bwd(scene, env, gb, w.spp, tud, tus, live=live, **kw)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(to_np(x), to_np(y))
+    ea, eb = to_np(a[3]), to_np(b[3])
+    assert np.allclose(ea, eb, rtol=1e-5, atol=1e-6 * np.abs(ea).max())
+
+
 def test_blocked_directions_carry_no_radiance():
     """With tau = 1 the receiver under the sphere sees probe texels that hold
     +inf only through the sphere: forward (with and without the decision
