@@ -183,7 +183,7 @@ class PerRequest:
         self.n_launches = 0
 
     def submit(self, req):
-        from . import shade_fwd, shade_bwd
+        from . import shade_fwd, shade_bwd, hit_words
         req.rid = self._rid
         self._rid += 1
         req.t_submit = time.perf_counter()
@@ -197,14 +197,17 @@ class PerRequest:
         for t in [gb.pos, gb.nrm, gb.kd, gb.korm, gb.mask, gb.eye] + ([req.g_cd, req.g_cs] if req.grad else []):
             t.record_stream(self.stream)
         with torch.cuda.stream(self.stream):
+            # the adjoint gets the forward's live samples with its hit bits
+            live = (torch.empty((hit_words(req.spp), req.gb.n), dtype=torch.int32, device=req.gb.pos.device)
+                    if req.grad and req.tau != 0.0 else None)
             req.c_d, req.c_s, hb, _ = shade_fwd(scene, env, req.gb, req.spp, seed=req.seed, tau=req.tau,
                                                 ray_eps=req.ray_eps, flags=req.flags, hitbits=req.grad,
-                                                stream=self.stream)
+                                                stream=self.stream, live=live)
             self.n_launches += 1
             if req.grad:
                 req.g_kd, req.g_korm, req.g_nrm, req.g_env = shade_bwd(
                     scene, env, req.gb, req.spp, req.g_cd, req.g_cs, hitbits=hb, seed=req.seed, tau=req.tau,
-                    ray_eps=req.ray_eps, flags=req.flags, stream=self.stream)
+                    ray_eps=req.ray_eps, flags=req.flags, stream=self.stream, live=live)
                 self.n_launches += 1
         ev = torch.cuda.Event()
         ev.record(self.stream)
