@@ -193,6 +193,7 @@ struct mcdi_env_s {
     int32_t G = 1;
     int32_t win = 0;
     float4* tex = nullptr;         // [H*W] (r, g, b, pdf)
+    uint8_t* dclass = nullptr;     // [(H*W + 3) / 4] density classes
 };
 
 extern "C" {
@@ -335,14 +336,16 @@ mcdi_status mcdi_build_env_cdf(const float* env_rgb, int32_t H, int32_t W, const
     ev->G = env_guide_cells(W, ev->win);
     ev->guide = (int32_t*)ev->alloc.get(sizeof(int32_t) * (size_t)H * (ev->G + 1), s);
     ev->tex = (float4*)ev->alloc.get(sizeof(float4) * (size_t)H * W, s);
+    ev->dclass = (uint8_t*)ev->alloc.get(((size_t)H * W + 3) / 4, s);
     if (!ev->cond || !ev->marg || !ev->pdf || !ev->rowsum || !ev->light || !ev->hot_slot || !ev->hot_texel ||
-        !ev->n_hot || !ev->guide || !ev->tex) {
+        !ev->n_hot || !ev->guide || !ev->tex || !ev->dclass) {
         mcdi_destroy_env(ev);
         return fail(MCDI_E_OOM, "mcdi_build_env_cdf: device allocation failed");
     }
     hipError_t e = launch_env_cdf(env_rgb, H, W, ev->cond, ev->marg, ev->pdf, ev->rowsum, ev->light, s);
     if (e == hipSuccess) e = launch_env_guide(ev->cond, H, W, ev->G, ev->guide, s);
     if (e == hipSuccess) e = launch_env_pack(env_rgb, ev->pdf, (int64_t)H * W, ev->tex, s);
+    if (e == hipSuccess) e = launch_env_dclass(ev->pdf, (int64_t)H * W, ev->dclass, s);
     if (e == hipSuccess) e = launch_env_hot(ev->pdf, H, W, ev->hot_slot, ev->hot_texel, ev->n_hot, s);
     if (e != hipSuccess) {
         mcdi_destroy_env(ev);
@@ -363,6 +366,7 @@ void mcdi_destroy_env(mcdi_env ev) {
     ev->alloc.put(ev->hot_texel, ev->stream);
     ev->alloc.put(ev->n_hot, ev->stream);
     ev->alloc.put(ev->guide, ev->stream);
+    ev->alloc.put(ev->dclass, ev->stream);
     ev->alloc.put(ev->tex, ev->stream);
     delete ev;
 }
@@ -400,7 +404,7 @@ static mcdi_status fill_common(const char* who, mcdi_scene sc, mcdi_env ev, cons
     std::memset(&a, 0, sizeof(a));
     a.scene = scene_view(sc);
     a.env = EnvView{ev->H, ev->W, ev->cond, ev->marg, ev->light, ev->hot_slot, ev->hot_texel, ev->n_hot, ev->guide,
-                    ev->G, ev->tex, ev->pdf, ev->win};
+                    ev->G, ev->tex, ev->pdf, ev->win, ev->dclass};
     a.g = GBufView{g->n_views, g->height, g->width, g->view_base, g->pos, g->nrm, g->kd, g->korm, g->mask, g->eye, n};
     a.spp = p->spp;
     a.flags = p->flags;

@@ -121,6 +121,26 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* env, const float
     if (k < n) tex[k] = make_float4(env[3 * k], env[3 * k + 1], env[3 * k + 2], pdf[k]);
 }
 
+// Two bits per texel for ray generation, which only asks whether a light
+// sample has a density: 0 none (pdf <= 0 or NaN: pdf / (2 pi^2 sin) is not
+// > 0), 1 pdf >= 2^-100 (then pdf / (2 pi^2 sin) > 0 for every sin in
+// (0, 1]: the quotient is at least 2^-100 / 19.8, or infinite), 2 a tiny
+// positive pdf, whose quotient may round to 0 (read the pdf).  A quarter of a
+// byte per texel stays in the L2 cache where the 4-byte densities do not.
+__global__ __launch_bounds__(256) void dclass_kernel(const float* pdf, int64_t n, uint8_t* dclass) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;   // byte k: texels 4k .. 4k + 3
+    if (4 * k >= n) return;
+    uint32_t b = 0;
+    for (int t = 0; t < 4; ++t) {
+        const int64_t x = 4 * k + t;
+        if (x >= n) break;
+        const float p = pdf[x];
+        const uint32_t c = !(p > 0.0f) ? 0u : (p >= 0x1p-100f ? 1u : 2u);
+        b |= c << (2 * t);
+    }
+    dclass[k] = (uint8_t)b;
+}
+
 __global__ __launch_bounds__(256) void mix_kernel(const float4* rgb, const float4* dens, int64_t n, float4* out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -140,15 +160,13 @@ hipError_t launch_env_pack(const float* env, const float* pdf, int64_t n, float4
     return hipGetLastError();
 }
 
-#ifndef MCDI_WIN_BYTES
-#define MCDI_WIN_BYTES (4 << 20)
-#endif
 // Whether light draws read a cell's candidates in one go (cdf_find_row): for
 // conditional tables larger than one XCD's L2 (4 MB), where a line read by
 // one binary-search probe is often gone by the next.  A table that stays in
 // the cache is searched faster by the binary search.
 int env_row_window(int H, int W) {
-    return (double)H * (W + 1) * sizeof(float) > (double)MCDI_WIN_BYTES ? 1 : 0;
+    constexpr double kL2Bytes = 4 << 20;
+    return (double)H * (W + 1) * sizeof(float) > kL2Bytes ? 1 : 0;
 }
 
 // Guide cells per row, at most 1024: about eight columns per cell for the
@@ -160,6 +178,12 @@ int env_guide_cells(int W, int win) {
     int G = 1;
     while (cols * G <= W && G < 1024) G *= 2;
     return G;
+}
+
+hipError_t launch_env_dclass(const float* pdf, int64_t n, uint8_t* dclass, hipStream_t s) {
+    const int64_t bytes = (n + 3) / 4;
+    hipLaunchKernelGGL(dclass_kernel, dim3((unsigned)((bytes + 255) / 256)), dim3(256), 0, s, pdf, n, dclass);
+    return hipGetLastError();
 }
 
 hipError_t launch_env_guide(const float* cond, int H, int W, int G, int32_t* guide, hipStream_t s) {

@@ -94,6 +94,7 @@ struct EnvView {
     const float4* tex;             // [H*W] (r, g, b, pdf): radiance and density in one line
     const float* pdf;              // [H*W] the density alone (tex.w), a quarter of tex's lines
     int32_t win;                   // 1: row searches read the cell's candidates in one go
+    const uint8_t* dclass;         // [(H*W + 3) / 4] density classes, 2 bits per texel
 };
 
 struct GBufView {
@@ -178,6 +179,8 @@ hipError_t launch_env_pack(const float* env, const float* pdf, int64_t n, float4
 // out[k] = (rgb[k].xyz, dens[k].w)
 hipError_t launch_env_mix(const float4* rgb, const float4* dens, int64_t n, float4* out, hipStream_t s);
 hipError_t launch_env_guide(const float* cond, int H, int W, int G, int32_t* guide, hipStream_t s);
+// density classes of the texels, 2 bits each, 4 to a byte (dclass_kernel)
+hipError_t launch_env_dclass(const float* pdf, int64_t n, uint8_t* dclass, hipStream_t s);
 hipError_t launch_env_hot(const float* pdf, int H, int W, int32_t* hot_slot, int32_t* hot_texel, int32_t* n_hot,
                           hipStream_t s);
 // forward = gen_rays -> trace_rays -> shade; hit bits are produced by the

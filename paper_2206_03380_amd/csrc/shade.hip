@@ -67,8 +67,9 @@ struct BwdAcc {
 // Light technique: piecewise-constant 2D distribution over the probe.
 // Returns false when the sample has no density (direction at a pole).
 // How each stage draws a light sample:
-//  kDrawGen  ray generation: the density alone, from the density table (a
-//            quarter of the radiance table's cache lines);
+//  kDrawGen  ray generation: whether the density is positive, from the
+//            texels' 2-bit density classes (the density table for tiny
+//            densities): the sample's density itself is not used there;
 //  kDrawFwd  forward shading: the texel's radiance and density, kept for the
 //            evaluation;
 //  kDrawBwd  adjoint: the density from the radiance table (the evaluation
@@ -104,9 +105,16 @@ __device__ __forceinline__ bool draw_light(const ShadeArgs& A, const Pixel& P, c
     sincospif(2.0f * u, &sp, &cp);
     S.w = f3(st * cp, ct, st * sp);
     S.texel = i * W + j;
-    if (MODE == kDrawFwd) S.tx = A.env.tex[S.texel];
-    else if (MODE == kDrawGen) S.tx.w = A.env.pdf[S.texel];
-    else S.tx.w = A.env.tex[S.texel].w;
+    if (MODE == kDrawFwd) {
+        S.tx = A.env.tex[S.texel];
+    } else if (MODE == kDrawGen) {
+        // generation only asks whether the density is positive: the
+        // texel's class answers it except for tiny densities (class 2)
+        const uint32_t cls = (A.env.dclass[S.texel >> 2] >> (2 * (S.texel & 3))) & 3u;
+        S.tx.w = cls == 2u ? A.env.pdf[S.texel] : (float)cls;
+    } else {
+        S.tx.w = A.env.tex[S.texel].w;
+    }
     S.pL = st > 0.0f ? S.tx.w / (2.0f * kPi * kPi * st) : 0.0f;
     S.wl = f3(dot(S.w, P.t), dot(S.w, P.b), dot(S.w, P.n));
     return S.pL > 0.0f;
