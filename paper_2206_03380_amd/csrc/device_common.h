@@ -331,8 +331,10 @@ __device__ __forceinline__ bool qbvh_anyhit(const Scene& sc, const Ray& r, int n
 
 // Any-hit traversal of the 4-wide hierarchy with a stack of pending
 // references (a one-ray form; the shading kernels keep their stacks in LDS).
-// A stack that would overflow sends the ray to the binary traversal from the
-// root, which gives the same answer.
+// Hit children are pushed in the node's visit order for the ray's octant and
+// the last pushed is taken next, so each split's farther child comes first,
+// as in the shading kernels' walk.  A stack that would overflow sends the ray
+// to the binary traversal from the root, which gives the same answer.
 template <bool COUNT = false>
 __device__ __forceinline__ bool wbvh_anyhit(const Scene& sc, const Ray& r, int n_total, uint32_t& n_box,
                                             uint32_t& n_tri) {
@@ -340,6 +342,8 @@ __device__ __forceinline__ bool wbvh_anyhit(const Scene& sc, const Ray& r, int n
     const uint4* g = reinterpret_cast<const uint4*>(sc.groups);
     const uint32_t n_groups = sc.group_bytes / 64u;
     const QRay q = make_qray(r, *sc.frame);
+    const uint32_t oct3 =
+        3u * ((r.inv.x < 0.0f ? 1u : 0u) | (r.inv.y < 0.0f ? 2u : 0u) | (r.inv.z < 0.0f ? 4u : 0u));
     uint32_t stack[kDepth];
     int sp = 0;
     uint32_t node = n_total > 0 ? 0u : kWideNone;
@@ -361,16 +365,19 @@ __device__ __forceinline__ bool wbvh_anyhit(const Scene& sc, const Ray& r, int n
             continue;
         }
         if (node >= n_groups) { node = kWideNone; continue; }   // never for a valid hierarchy
-        uint32_t next = kWideNone;
-        for (int k = 0; k < 4; ++k) {
+        const uint32_t f = (sc.gorder[node] >> oct3) & 7u;
+        // slot order: swap within the first pair, within the second, the pairs
+        for (int p = 0; p < 4; ++p) {
+            int k = p;
+            if (f & 4u) k ^= 2;
+            if ((k < 2 && (f & 1u)) || (k >= 2 && (f & 2u))) k ^= 1;
             const uint4 c = g[4 * (size_t)node + k];
             if (COUNT && c.w != kQLeaf) ++n_box;
             if (!qbox_hit(q, c)) continue;
-            if (next == kWideNone) next = c.w;
-            else if (sp < kDepth) stack[sp++] = c.w;
-            else return qbvh_anyhit<COUNT>(sc, r, n_total, n_box, n_tri);
+            if (sp >= kDepth) return qbvh_anyhit<COUNT>(sc, r, n_total, n_box, n_tri);
+            stack[sp++] = c.w;
         }
-        node = next;
+        node = kWideNone;   // the last pushed is popped next
     }
 }
 

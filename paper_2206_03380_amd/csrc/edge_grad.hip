@@ -392,7 +392,11 @@ __global__ __launch_bounds__(256) void edge_trace_kernel(EdgeArgs E) {
             if (!edge_term(E, E.queue[i], ne, ns, scale, bil, T)) continue;
             ++c_rays;
             uint32_t nb = 0, nt = 0;
-            if (n_total > 0 && bvh_anyhit(sc, make_ray(T.o, T.wo), n_total, nb, nt)) {
+            // the 4-wide walk where the builder chose it (deep scenes)
+            const Ray ray = make_ray(T.o, T.wo);
+            const bool blocked = n_total > 0 && (sc.info->wide ? wbvh_anyhit(sc, ray, n_total, nb, nt)
+                                                               : bvh_anyhit(sc, ray, n_total, nb, nt));
+            if (blocked) {
                 ++c_hits;
                 continue;
             }
