@@ -85,6 +85,11 @@ typedef struct {
  * filling geometry: long walks bound by memory latency), else the binary
  * one (surfaces: short cache-resident walks bound by instruction issue).
  * Either walk gives the same answers.
+ * Big triangles (a box whose longest side is at least 1/8 of the longest side
+ * of the triangle centroids' bounds: the walls around a scene, say) form the
+ * root's first subtree, one triangle per leaf, when the mesh also has smaller
+ * ones; both walks take that subtree first, so the shadow rays those big
+ * occluders stop end early.
  * A triangle with an index outside [0, n_verts) or a non-finite vertex is
  * replaced by a degenerate triangle that no ray hits (counted in
  * mcdi_scene_info).  n_tris = 0 gives a scene every ray misses.
@@ -113,6 +118,7 @@ typedef struct {
     int32_t n_groups;     /* 4-wide nodes */
     int32_t wide;         /* 1: shadow rays walk the 4-wide hierarchy, 0: the binary one */
     float depth_complexity; /* sum of the leaf boxes' surface areas over the root box's */
+    int32_t n_big;        /* big triangles (see mcdi_build_scene) */
 } mcdi_scene_info_t;
 
 /* Synchronises the scene's stream and reports build statistics. */

@@ -75,7 +75,8 @@ class Scene:
         i = L.SceneInfo()
         L.check(L.lib().mcdi_scene_info(self.handle, C.byref(i)))
         return {"n_tris": i.n_tris, "n_nodes": i.n_nodes, "max_depth": i.max_depth, "bad_tris": i.bad_tris,
-                "n_groups": i.n_groups, "wide": i.wide, "depth_complexity": i.depth_complexity}
+                "n_groups": i.n_groups, "wide": i.wide, "depth_complexity": i.depth_complexity,
+                "n_big": i.n_big}
 
     def nodes(self, stream=None):
         """The BVH as device tensors: nodes int32 [n_nodes, 8] (lo xyz and hi

@@ -78,7 +78,7 @@ class BilateralGuide(C.Structure):
 class SceneInfo(C.Structure):
     _fields_ = [("n_tris", C.c_int64), ("n_nodes", C.c_int32), ("max_depth", C.c_int32),
                 ("bad_tris", C.c_int32), ("n_groups", C.c_int32), ("wide", C.c_int32),
-                ("depth_complexity", C.c_float)]
+                ("depth_complexity", C.c_float), ("n_big", C.c_int32)]
 
 
 _lib = None

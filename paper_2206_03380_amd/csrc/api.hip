@@ -290,6 +290,7 @@ mcdi_status mcdi_scene_info(mcdi_scene sc, mcdi_scene_info_t* info) {
     info->n_groups = h.n_groups;
     info->wide = h.wide;
     info->depth_complexity = h.depth_complexity;
+    info->n_big = h.n_big;
     return ok();
 }
 

@@ -1,7 +1,8 @@
 // Device BVH construction for the shadow-ray mesh (rebuilt whenever the mesh
 // changes: the paper re-extracts its mesh every optimisation iteration).
 //
-// Linear BVH: 63-bit Morton codes of triangle centroids, a radix sort, the
+// Linear BVH: 63-bit Morton codes of triangle centroids (under a top bit that
+// puts the mesh's big triangles first, see morton()), a radix sort, the
 // binary radix tree of the sorted codes built in parallel (one lane per
 // internal node, Karras 2012), box fitting and the counts of the nodes that
 // survive collapsing subtrees of <= 4 triangles into leaves, and a final pass
@@ -119,24 +120,42 @@ __device__ __forceinline__ uint64_t spread3(uint64_t x) {
     return x;
 }
 
+// Key of a triangle: bit 63 clear for a big triangle (its box's longest side
+// at least 1/kBigTriDiv of the centroid bounds' longest side), set for the
+// others, above the 63-bit Morton code of its centroid.  A mesh with both
+// kinds splits at the root into the big triangles (first) and the rest: a
+// room's walls, say, stop most shadow rays leaving the geometry inside it,
+// and under the Morton order alone each wall triangle widens the box of every
+// node it shares with the small triangles around its centroid.  The big ones
+// are counted into info->n_big.
 __global__ __launch_bounds__(256) void morton(const float4* tmp, int64_t nt, const int* cb, uint64_t* keys,
-                                              uint32_t* vals) {
+                                              uint32_t* vals, DeviceSceneInfo* info) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nt) return;
-    const float4 a = tmp[3 * f], b = tmp[3 * f + 1], c = tmp[3 * f + 2];
-    const float p[3] = {(a.x + b.x + c.x) * (1.0f / 3.0f), (a.y + b.y + c.y) * (1.0f / 3.0f),
-                        (a.z + b.z + c.z) * (1.0f / 3.0f)};
-    uint64_t code = 0;
-    for (int k = 0; k < 3; ++k) {
-        const float lo = ord_val(cb[k]), hi = ord_val(cb[3 + k]);
-        const float ext = hi - lo;
-        float u = ext > 0.0f ? (p[k] - lo) / ext : 0.5f;
-        u = fminf(fmaxf(u, 0.0f), 1.0f);
-        const uint64_t q = (uint64_t)fminf(u * 2097152.0f, 2097151.0f);
-        code |= spread3(q) << (2 - k);
+    bool big = false;
+    if (f < nt) {
+        const float4 a = tmp[3 * f], b = tmp[3 * f + 1], c = tmp[3 * f + 2];
+        const float p[3] = {(a.x + b.x + c.x) * (1.0f / 3.0f), (a.y + b.y + c.y) * (1.0f / 3.0f),
+                            (a.z + b.z + c.z) * (1.0f / 3.0f)};
+        const float sx = fmaxf(a.x, fmaxf(b.x, c.x)) - fminf(a.x, fminf(b.x, c.x));
+        const float sy = fmaxf(a.y, fmaxf(b.y, c.y)) - fminf(a.y, fminf(b.y, c.y));
+        const float sz = fmaxf(a.z, fmaxf(b.z, c.z)) - fminf(a.z, fminf(b.z, c.z));
+        uint64_t code = 0;
+        float cext = 0.0f;
+        for (int k = 0; k < 3; ++k) {
+            const float lo = ord_val(cb[k]), hi = ord_val(cb[3 + k]);
+            const float ext = hi - lo;
+            cext = fmaxf(cext, ext);
+            float u = ext > 0.0f ? (p[k] - lo) / ext : 0.5f;
+            u = fminf(fmaxf(u, 0.0f), 1.0f);
+            const uint64_t q = (uint64_t)fminf(u * 2097152.0f, 2097151.0f);
+            code |= spread3(q) << (2 - k);
+        }
+        big = fmaxf(sx, fmaxf(sy, sz)) * kBigTriDiv >= cext;
+        keys[f] = big ? code : (code | (1ull << 63));
+        vals[f] = (uint32_t)f;
     }
-    keys[f] = code;
-    vals[f] = (uint32_t)f;
+    const uint64_t m = __ballot(big);
+    if ((threadIdx.x & 63) == 0 && m != 0) atomicAdd(&info->n_big, (int)__popcll(m));
 }
 
 struct Tree {
@@ -156,8 +175,17 @@ struct Tree {
     float4* pre;       // [2nt] box of the block's triangles up to k (inclusive)
     float4* suf;       // [2nt] box of the block's triangles from k to the block end
     float4* st;        // [levels][nb][2] sparse table of block boxes
+    const int32_t* nbig;   // the big triangles' count (sorted first)
     int nb, levels;
 };
+
+// Most triangles a leaf holds: kLeafMax, and kBigLeafMax inside the big
+// triangles' subtree (sorted range [0, n_big)) of a mesh that has both kinds.
+// Every node but the root lies entirely on one side of n_big.
+__device__ __forceinline__ int leaf_cap(const Tree& T, int nt, int last) {
+    const int nb = *T.nbig;
+    return (nb < nt && last < nb) ? kBigLeafMax : kLeafMax;
+}
 
 __device__ __forceinline__ int prefix_len(const uint64_t* keys, int nt, int a, int b) {
     if (b < 0 || b >= nt) return -1;
@@ -199,8 +227,10 @@ __global__ __launch_bounds__(256) void radix_tree(const uint64_t* keys, int nt, 
     // the split is at the first bit the range's codes differ in, bit 63 - dnode
     // (x, y, z interleaved from bit 62 down: bit b is x, y or z as b % 3 is 2,
     // 1 or 0); the left child holds the codes with a 0 there, the lower side;
-    // equal codes (split by index) take x
-    T.axis[i] = dnode < 64 ? 2 - (63 - dnode) % 3 : 0;
+    // equal codes (split by index) take x.  A split at bit 63 (the root of a
+    // mesh with big and small triangles) is 3: no axis, the left child (the
+    // big triangles) first for every ray
+    T.axis[i] = dnode == 0 ? 3 : dnode < 64 ? 2 - (63 - dnode) % 3 : 0;
     T.parent[L] = i;
     T.parent[R] = i;
     T.flag[i] = 0;
@@ -221,21 +251,22 @@ __device__ __forceinline__ void fit_node(int p, int nt, const Tree& T) {
     T.box[2 * p] = make_float4(fminf(al.x, bl.x), fminf(al.y, bl.y), fminf(al.z, bl.z), 0.0f);
     T.box[2 * p + 1] = make_float4(fmaxf(ah.x, bh.x), fmaxf(ah.y, bh.y), fmaxf(ah.z, bh.z), 0.0f);
     const int size = T.last[p] - T.first[p] + 1;
-    T.cnt[p] = size <= kLeafMax ? 1 : 1 + T.cnt[l] + T.cnt[r];
+    T.cnt[p] = size <= leaf_cap(T, nt, T.last[p]) ? 1 : 1 + T.cnt[l] + T.cnt[r];
 }
 
-// leaf marks: a node of <= kLeafMax triangles whose parent has more is a
+// leaf marks: a node of <= leaf_cap triangles whose parent has more is a
 // leaf of the collapsed tree (the root, when the whole mesh fits in one)
 __global__ __launch_bounds__(256) void mark_leaves(int nt, Tree T) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= 2 * nt - 1) return;
     const bool prim = x >= nt - 1;
     const int first = prim ? x - (nt - 1) : T.first[x];
-    const int size = prim ? 1 : T.last[x] - first + 1;
-    if (size > kLeafMax) return;
+    const int last = prim ? first : T.last[x];
+    const int size = last - first + 1;
+    if (size > leaf_cap(T, nt, last)) return;
     if (x != 0) {
         const int p = T.parent[x];
-        if (p < 0 || p >= nt - 1 || T.last[p] - T.first[p] + 1 <= kLeafMax) return;
+        if (p < 0 || p >= nt - 1 || T.last[p] - T.first[p] + 1 <= leaf_cap(T, nt, T.last[p])) return;
     }
     if (first >= 0 && first < nt) T.mark[first] = 1;
 }
@@ -444,7 +475,7 @@ __global__ __launch_bounds__(256) void emit(int nt, Tree T, Node* out, QNode* qo
     if (x != 0) {
         const int p = T.parent[x];
         if (p < 0 || p >= nt - 1) return;                       // not linked (never for a valid tree)
-        if (T.last[p] - T.first[p] + 1 <= kLeafMax) return;  // inside a collapsed leaf
+        if (T.last[p] - T.first[p] + 1 <= leaf_cap(T, nt, T.last[p])) return;  // inside a collapsed leaf
     }
     int idx = 0, depth = 0, cur = x;
     while (cur != 0 && depth < 4096) {
@@ -461,7 +492,7 @@ __global__ __launch_bounds__(256) void emit(int nt, Tree T, Node* out, QNode* qo
         payload = ((x - (nt - 1)) << 3) | 1;
     } else {
         const int size = T.last[x] - T.first[x] + 1;
-        if (size <= kLeafMax) payload = (T.first[x] << 3) | size;
+        if (size <= leaf_cap(T, nt, T.last[x])) payload = (T.first[x] << 3) | size;
     }
     const float4 lo = T.box[2 * x], hi = T.box[2 * x + 1];
     Node nd;
@@ -506,8 +537,9 @@ __global__ void reorder(const float4* tmp, const uint32_t* vals, int64_t nt, flo
 // ray direction (bit a set where the component on axis a is negative), three
 // bits -- swap slots 0 and 1, swap slots 2 and 3, swap the two pairs -- that
 // put each binary split's child farther along the ray after the nearer one in
-// slot order.  The walk pushes hit children in slot order and pops the last
-// pushed, so it descends into the farther child first.
+// slot order (the big triangles' child after the other at the split that
+// separates them).  The walk pushes hit children in slot order and pops the
+// last pushed, so it descends into the farther child first.
 __device__ __forceinline__ QNode empty_record() {
     QNode q;
     q.x = 0xFFFFFFFFu;   // lo.x = lo.y = 65535
@@ -515,6 +547,13 @@ __device__ __forceinline__ QNode empty_record() {
     q.z = 0u;            // hi.y = hi.z = 0
     q.w = kQLeaf;        // an empty leaf, should it ever be taken
     return q;
+}
+
+// 1 when a ray of octant o should take the split's left child first: the
+// left child lies farther along the ray on the split's axis, or holds the big
+// triangles (axis 3)
+__device__ __forceinline__ uint32_t left_first(int axis, int o) {
+    return axis == 3 ? 1u : (uint32_t)((o >> axis) & 1);
 }
 
 __device__ __forceinline__ QNode child_record(const Node* out, const QNode* qout, const int32_t* gidx, int x) {
@@ -553,9 +592,9 @@ __global__ __launch_bounds__(256) void wide_groups(const Node* out, const QNode*
         }
         const int top = naxis[x];
         for (int o = 0; o < 8; ++o) {
-            uint32_t f = ((o >> top) & 1) ? 4u : 0u;
-            if (sub_axis[0] >= 0 && ((o >> sub_axis[0]) & 1)) f |= 1u;
-            if (sub_axis[1] >= 0 && ((o >> sub_axis[1]) & 1)) f |= 2u;
+            uint32_t f = left_first(top, o) << 2;
+            if (sub_axis[0] >= 0) f |= left_first(sub_axis[0], o);
+            if (sub_axis[1] >= 0) f |= left_first(sub_axis[1], o) << 1;
             order |= f << (3 * o);
         }
     }
@@ -611,6 +650,7 @@ __global__ void init_info(DeviceSceneInfo* info) {
     info->n_groups = 0;
     info->wide = 0;
     info->wide_bad = 0;
+    info->n_big = 0;
     info->depth_complexity = 0.0f;
     info->leaf_area = 0.0;
 }
@@ -656,7 +696,7 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     size_t sort_bytes = 0;
     if (nt > 1) {
         hipError_t e = rocprim::radix_sort_pairs(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                                 (uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)nt, 0, 63, s);
+                                                 (uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)nt, 0, 64, s);
         if (e != hipSuccess) return e;
     }
     size_t scan_bytes = 0;
@@ -715,6 +755,7 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
     uint32_t* gorder = reinterpret_cast<uint32_t*>(groups_out + 4 * ntm);
     T.nb = nb;
     T.levels = levels;
+    T.nbig = &info->n_big;
     hipError_t err = hipSuccess;
     if (nt > 0) {
         hipLaunchKernelGGL(tri_prep, dim3(nblk(nt)), dim3(256), 0, s, verts, nv, tris, (int64_t)nt, tmp, part, info);
@@ -724,8 +765,8 @@ hipError_t build_bvh(const float* verts, int64_t nv, const int32_t* tris, int64_
         hipLaunchKernelGGL(tiny_scene, dim3(1), dim3(1), 0, s, tmp, nt, nodes_out, tris_out, qnodes_out, frame_out,
                            info, groups_out, gorder);
     } else {
-        hipLaunchKernelGGL(morton, dim3(nblk(nt)), dim3(256), 0, s, tmp, (int64_t)nt, cb, keys, vals);
-        err = rocprim::radix_sort_pairs(sort_tmp, sort_bytes, keys, keys2, vals, vals2, (size_t)nt, 0, 63, s);
+        hipLaunchKernelGGL(morton, dim3(nblk(nt)), dim3(256), 0, s, tmp, (int64_t)nt, cb, keys, vals, info);
+        err = rocprim::radix_sort_pairs(sort_tmp, sort_bytes, keys, keys2, vals, vals2, (size_t)nt, 0, 64, s);
         if (err == hipSuccess) {
             hipLaunchKernelGGL(fill_i32, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, T.parent, (int64_t)(2 * nt - 1), -1);
             hipLaunchKernelGGL(fill_i32, dim3(nblk(2 * nt - 1)), dim3(256), 0, s, T.cnt, (int64_t)(2 * nt - 1), 0);

@@ -20,6 +20,12 @@ struct alignas(16) Node {
 };
 
 constexpr int kLeafMax = 4;
+// Big triangles: a triangle whose box's longest side is at least 1/kBigTriDiv
+// of the longest side of the triangle centroids' bounds.  When a mesh has both
+// big and small ones, the big ones form the root's first subtree, in leaves of
+// at most kBigLeafMax.
+constexpr float kBigTriDiv = 8.0f;
+constexpr int kBigLeafMax = 1;
 constexpr int kHotMax = 1024;   // probe texels privatised in LDS by the adjoint
 constexpr int kBlock = 256;     // pixels per workgroup in the shading kernels
 
@@ -31,7 +37,7 @@ struct DeviceSceneInfo {
     int32_t wide;              // 1: shadow rays walk the wide hierarchy
     float depth_complexity;    // sum of leaf box areas / root box area
     int32_t wide_bad;          // a wide reference failed the builder's check
-    int32_t pad;
+    int32_t n_big;             // big triangles (the root's first subtree when 0 < n_big < n_tris)
     double leaf_area;          // the sum (accumulated by the builder)
 };
 

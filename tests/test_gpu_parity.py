@@ -176,6 +176,34 @@ def _check_bvh(nodes, tris_leaf, verts, faces, bad=0):
         assert np.array_equal(key(ref), key(got))
 
 
+def _big_tris(v, f):
+    """The builder's big triangles, in its own FP32 operations: the box's
+    longest side times 8 at least the longest side of the centroid bounds."""
+    t = v[f].astype(np.float32)                                # [nt, 3, 3]
+    cen = ((t[:, 0] + t[:, 1]) + t[:, 2]) * np.float32(1.0 / 3.0)
+    cext = (cen.max(0) - cen.min(0)).max()
+    side = (t.max(1) - t.min(1)).max(1)
+    return side * np.float32(8.0) >= cext
+
+
+def _check_big_subtree(nodes, tris_leaf, v, f, info):
+    """A mesh with big and small triangles: the root's first subtree holds
+    exactly the big ones, one per leaf."""
+    big = _big_tris(v, f)
+    assert info["n_big"] == int(big.sum())
+    if not 0 < big.sum() < len(f):
+        return
+    esc, pay = nodes[:, 3], nodes[:, 7]
+    assert pay[0] == 0
+    sub = np.arange(1, esc[1])
+    leaves = sub[pay[sub] != 0]
+    assert np.all((pay[leaves] & 7) == 1)
+    got = np.concatenate([tris_leaf[p >> 3:(p >> 3) + (p & 7), :, :3].reshape(-1, 9) for p in pay[leaves]])
+    ref = v[f[big]].reshape(-1, 9).astype(np.float32)
+    key = lambda a: a[np.lexsort(a.T[::-1])]  # noqa: E731
+    assert np.array_equal(key(ref), key(got))
+
+
 @pytest.mark.parametrize("case", ["soup255", "soup256", "soup257", "soup1000", "dup600", "sphere12", "sphere40",
                                   "lattice"])
 def test_bvh_structure(case):
@@ -205,7 +233,9 @@ def test_bvh_structure(case):
     torch.cuda.synchronize()
     nodes, tris = to_np(nodes), to_np(tris)
     assert info["n_nodes"] == len(nodes) and info["bad_tris"] == 0
+    _check_big_subtree(nodes, tris, v, f, info)
     if case == "lattice":
+        assert info["n_big"] == 36, info   # the room: floor, roof, four walls around their windows
         # full structure check on a million triangles is slow in Python: a
         # random subset of nodes for the local checks, coverage for all
         n, nt = len(nodes), len(f)
