@@ -529,7 +529,8 @@ __global__ void reorder(const float4* tmp, const uint32_t* vals, int64_t nt, flo
 // contributes (itself when it is a leaf, else its two children), slots 2-3
 // what the second contributes; a child record is the quantised box of that
 // binary node with w = its wide node's index (internal) or kQLeaf | payload
-// (leaf), and an unused slot holds an empty record (lo > hi: no ray hits it).
+// (leaf), and an unused slot holds an empty record (lo > hi: no ray hits it);
+// every record's w also carries kRefLive.
 // Wide nodes are numbered in the binary pre-order of their nodes (an
 // exclusive scan of the flags), so the wide hierarchy is in pre-order too.
 //
@@ -606,6 +607,7 @@ __global__ __launch_bounds__(256) void wide_groups(const Node* out, const QNode*
     for (int i = 0; i < 4; ++i) {
         const uint32_t w = g[i].w;
         if (!(w & kQLeaf) && ((int)w <= self || (int)w >= n_groups)) atomicOr(&info->wide_bad, 1);
+        g[i].w = w | kRefLive;
     }
 }
 
@@ -635,6 +637,7 @@ __global__ void tiny_scene(const float4* tmp, int nt, Node* out, float4* tris_ou
     info->max_depth = 0;
     groups[0] = nt == 0 ? empty_record() : qout[0];
     for (int k = 1; k < 4; ++k) groups[k] = empty_record();
+    for (int k = 0; k < 4; ++k) groups[k].w |= kRefLive;
     gorder[0] = 0u;
     info->n_groups = 1;
 }

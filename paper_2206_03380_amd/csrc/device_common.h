@@ -372,10 +372,10 @@ __device__ __forceinline__ bool wbvh_anyhit(const Scene& sc, const Ray& r, int n
             if (f & 4u) k ^= 2;
             if ((k < 2 && (f & 1u)) || (k >= 2 && (f & 2u))) k ^= 1;
             const uint4 c = g[4 * (size_t)node + k];
-            if (COUNT && c.w != kQLeaf) ++n_box;
+            if (COUNT && (c.w & ~kRefLive) != kQLeaf) ++n_box;
             if (!qbox_hit(q, c)) continue;
             if (sp >= kDepth) return qbvh_anyhit<COUNT>(sc, r, n_total, n_box, n_tri);
-            stack[sp++] = c.w;
+            stack[sp++] = c.w & ~kRefLive;
         }
         node = kWideNone;   // the last pushed is popped next
     }

@@ -58,6 +58,10 @@ struct QNode {
     uint32_t x, y, z, w;
 };
 constexpr uint32_t kQLeaf = 0x80000000u;
+// Set in every child reference of a wide node (references stay below 2^29):
+// a walk replaces the reference of a child whose box it missed by 0 and
+// pushes the rest, advancing its stack past each reference that has the bit.
+constexpr uint32_t kRefLive = 1u << 30;
 
 // Wide node of the shadow-ray traversal: four child records in QNode form
 // (64 bytes, one aligned segment), w = the child's wide-node index (internal)

@@ -676,7 +676,7 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                         const uint32_t payload = node & ~kQLeaf;
                         if (p0 == 0u) p0 = payload;
                         else p1 = payload;
-                        node = sp > 0 ? stk[--sp * kBlock] : kWideNone;
+                        node = sp > 0 ? (stk[--sp * kBlock] & ~kRefLive) : kWideNone;
                     } else {
                         // one wide node: four child records from one 64-byte
                         // segment, and its visit order for the ray's octant
@@ -686,13 +686,13 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                         for (int k = 0; k < 4; ++k)
                             c[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(grs, off + 16u * k, 0, 0));
                         const uint32_t f = (__builtin_amdgcn_raw_buffer_load_b32(ors, node * 4u, 0, 0) >> oct3) & 7u;
+                        // a missed child's reference becomes 0 (no kRefLive
+                        // bit: the push below does not keep it)
                         uint32_t w[4];
-                        bool h[4];
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            if (COUNT && c[k].w != kQLeaf) ++c_box;
-                            h[k] = qbox_hit(qray, c[k]);
-                            w[k] = c[k].w;
+                            if (COUNT && (c[k].w & ~kRefLive) != kQLeaf) ++c_box;
+                            w[k] = qbox_hit(qray, c[k]) ? c[k].w : 0u;
                         }
                         // farther child of each split after the nearer one
                         // (the pushed-last is popped first): within each pair,
@@ -700,10 +700,7 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                         const bool s0 = (f & 1u) != 0u, s1 = (f & 2u) != 0u, sT = (f & 4u) != 0u;
                         const uint32_t a0 = s0 ? w[1] : w[0], a1 = s0 ? w[0] : w[1];
                         const uint32_t a2 = s1 ? w[3] : w[2], a3 = s1 ? w[2] : w[3];
-                        const bool g0 = s0 ? h[1] : h[0], g1 = s0 ? h[0] : h[1];
-                        const bool g2 = s1 ? h[3] : h[2], g3 = s1 ? h[2] : h[3];
                         const uint32_t ws[4] = {sT ? a2 : a0, sT ? a3 : a1, sT ? a0 : a2, sT ? a1 : a3};
-                        const bool hs[4] = {sT ? g2 : g0, sT ? g3 : g1, sT ? g0 : g2, sT ? g1 : g3};
                         // every hit child is pushed: each record is stored at
                         // the first free row and the row is kept if the child
                         // was hit (rows up to kStack + 3 exist, so a visit
@@ -711,15 +708,15 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                         // overflow is checked once per visit); then the top is
                         // popped as the next node (a leaf reference moves to a
                         // pending slot at the next step)
-                        uint32_t* at = stk + sp * kBlock;
+                        int row = sp;
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            *at = ws[k];
-                            at += hs[k] ? kBlock : 0;
+                            stk[row * kBlock] = ws[k];
+                            row += (int)((ws[k] & kRefLive) >> 30);
                         }
-                        sp = (int)((at - stk) / kBlock);
+                        sp = row;
                         const bool over = sp > kStack;
-                        const uint32_t top = stk[(sp > 0 ? sp - 1 : 0) * kBlock];
+                        const uint32_t top = stk[(sp > 0 ? sp - 1 : 0) * kBlock] & ~kRefLive;
                         const uint32_t next = sp > 0 ? top : kWideNone;
                         sp = sp > 0 ? sp - 1 : 0;
                         node = next;
