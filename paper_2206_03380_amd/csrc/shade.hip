@@ -720,6 +720,15 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                         const uint32_t next = sp > 0 ? top : kWideNone;
                         sp = sp > 0 ? sp - 1 : 0;
                         node = next;
+                        if (!over && next != kWideNone && (next & kQLeaf)) {
+                            // a leaf reference on top goes to a pending slot
+                            // now (this visit started with the second free),
+                            // and the next entry is popped
+                            const uint32_t payload = next & ~kQLeaf;
+                            if (p0 == 0u) p0 = payload;
+                            else p1 = payload;
+                            node = sp > 0 ? (stk[--sp * kBlock] & ~kRefLive) : kWideNone;
+                        }
                         if (over) {
                             // the stack is full: walk the binary tree from the
                             // root instead (the same answer, more steps)
