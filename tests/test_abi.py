@@ -88,3 +88,32 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     tris = torch.zeros((1, 3), dtype=torch.int32)
     with pytest.raises(TypeError, match="CUDA"):
         M.Scene(verts, tris)
+
+
+def test_binding_structs_match_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (the header compiled by the host C compiler)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    from paper_2206_03380_amd import _lib as L
+    pairs = {"Allocator": "mcdi_allocator", "GBuffer": "mcdi_gbuffer", "Params": "mcdi_params",
+             "Stats": "mcdi_stats", "SceneInfo": "mcdi_scene_info_t", "BilateralGuide": "mcdi_bilateral_guide",
+             "ServerConfig": "mcdi_server_config", "Request": "mcdi_request", "ServerInfo": "mcdi_server_info_t"}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mcdi.h"', "int main(void) {"]
+    want = []
+    for py, c in pairs.items():
+        cls = getattr(L, py)
+        lines.append('printf("%%zu\\n", sizeof(%s));' % c)
+        want.append(ctypes.sizeof(cls))
+        for name, _ in cls._fields_:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (c, name))
+            want.append(getattr(cls, name).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == want
