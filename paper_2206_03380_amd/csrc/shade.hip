@@ -708,8 +708,7 @@ __device__ __forceinline__ void trace_tile_wide(const ShadeArgs& A, int64_t tile
                         // was hit (rows up to kStack + 3 exist, so a visit
                         // starting with a full stack stays in bounds; the
                         // overflow is checked once per visit); then the top is
-                        // popped as the next node (a leaf reference moves to a
-                        // pending slot at the next step)
+                        // popped as the next node
                         int row = sp;
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
