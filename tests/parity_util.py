@@ -170,3 +170,14 @@ def occluder_with_hidden_infinity(level=3, H=16, W=32, seed=31):
     env_inf = env.copy()
     env_inf[inside] = np.inf
     return v, f, p, n, env, env_inf
+
+
+def big_tris(v, f):
+    """The scene builder's big triangles, in its own FP32 operations: the
+    triangle box's longest side times 8 at least the longest side of the
+    bounds of the triangle centroids."""
+    t = v[f].astype(np.float32)                                # [nt, 3, 3]
+    cen = ((t[:, 0] + t[:, 1]) + t[:, 2]) * np.float32(1.0 / 3.0)
+    cext = (cen.max(0) - cen.min(0)).max()
+    side = (t.max(1) - t.min(1)).max(1)
+    return side * np.float32(8.0) >= cext

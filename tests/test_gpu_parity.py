@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from workloads import make_workload, upstream_grads, from_arrays
-from tests.parity_util import gpu_forward, compare, hitbits_per_pixel, to_np, check_dirs, TOL, REL_TOL, U
+from tests.parity_util import gpu_forward, compare, hitbits_per_pixel, to_np, check_dirs, big_tris, TOL, REL_TOL, U
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -176,20 +176,10 @@ def _check_bvh(nodes, tris_leaf, verts, faces, bad=0):
         assert np.array_equal(key(ref), key(got))
 
 
-def _big_tris(v, f):
-    """The builder's big triangles, in its own FP32 operations: the box's
-    longest side times 8 at least the longest side of the centroid bounds."""
-    t = v[f].astype(np.float32)                                # [nt, 3, 3]
-    cen = ((t[:, 0] + t[:, 1]) + t[:, 2]) * np.float32(1.0 / 3.0)
-    cext = (cen.max(0) - cen.min(0)).max()
-    side = (t.max(1) - t.min(1)).max(1)
-    return side * np.float32(8.0) >= cext
-
-
 def _check_big_subtree(nodes, tris_leaf, v, f, info):
     """A mesh with big and small triangles: the root's first subtree holds
     exactly the big ones, one per leaf."""
-    big = _big_tris(v, f)
+    big = big_tris(v, f)
     assert info["n_big"] == int(big.sum())
     if not 0 < big.sum() < len(f):
         return
