@@ -5,9 +5,9 @@
 // puts the mesh's big triangles first, see morton()), a radix sort, the
 // binary radix tree of the sorted codes built in parallel (one lane per
 // internal node, Karras 2012), box fitting and the counts of the nodes that
-// survive collapsing subtrees of <= 4 triangles into leaves, and a final pass
-// that writes every surviving node at its depth-first pre-order index with a
-// skip link, so traversal needs no stack.
+// survive collapsing subtrees of <= 4 triangles (1 among the big ones) into
+// leaves, and a final pass that writes every surviving node at its depth-first
+// pre-order index with a skip link, so traversal needs no stack.
 //
 // Fitting runs in two parts over blocks of 256 sorted triangles.  Nodes whose
 // triangles lie in one block are fitted bottom-up inside that block's
